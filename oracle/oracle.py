@@ -1,0 +1,297 @@
+"""ctypes front end of the plain serial FP64 CPU oracle (halo_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path.  It shares no code
+with the GPU library; the two meet only in the seeded catalogues of
+``paper_1110_4372_amd.synth``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "halo_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (plain C, FP64, no fused contractions)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Params(C.Structure):
+    _fields_ = [("box", C.c_double), ("b", C.c_double), ("f", C.c_double),
+                ("min_members", C.c_int32), ("max_levels", C.c_int32),
+                ("merge_q2", C.c_double), ("particle_mass", C.c_double),
+                ("G", C.c_double), ("rho_vir", C.c_double), ("softening", C.c_double),
+                ("core_frac", C.c_double), ("unbound_threshold", C.c_double)]
+
+
+_P = C.c_void_p
+
+NODE_FIELDS = [("parent", np.int32), ("level", np.int32), ("first_child", np.int32),
+               ("n_children", np.int32), ("count", np.uint32), ("canon", np.uint32),
+               ("fof", np.uint32), ("flags", np.uint32), ("cx", np.float64),
+               ("cy", np.float64), ("cz", np.float64), ("vx", np.float64),
+               ("vy", np.float64), ("vz", np.float64), ("sx2", np.float64),
+               ("sv2", np.float64), ("ell2", np.float32)]
+HALO_FIELDS = [("seed_node", np.int32), ("merged_into", np.int32), ("host", np.int32),
+               ("fof", np.uint32), ("n_assigned", np.uint32), ("xs", np.float64),
+               ("ys", np.float64), ("zs", np.float64), ("vxs", np.float64),
+               ("vys", np.float64), ("vzs", np.float64), ("sv2", np.float64),
+               ("vmax2", np.float64)]
+UNB_FIELDS = [("n_bound_own", np.uint32), ("n_s", np.uint32), ("n_bound_s", np.uint32),
+              ("valid", np.uint8), ("vbx", np.float64), ("vby", np.float64),
+              ("vbz", np.float64)]
+PROP_FIELDS = [("px", np.float64), ("py", np.float64), ("pz", np.float64),
+               ("vcx", np.float64), ("vcy", np.float64), ("vcz", np.float64),
+               ("vbx", np.float64), ("vby", np.float64), ("vbz", np.float64),
+               ("mvir", np.float64), ("rvir", np.float64), ("vmax", np.float64),
+               ("voff", np.float64), ("n_bound", np.uint32)]
+
+
+def _struct(fields):
+    return type("S", (C.Structure,), {"_fields_": [(n, _P) for n, _ in fields]})
+
+
+NodesS, HalosS, UnbS, PropsS = (_struct(NODE_FIELDS), _struct(HALO_FIELDS),
+                               _struct(UNB_FIELDS), _struct(PROP_FIELDS))
+
+
+def _alloc(fields, cap):
+    arrs = {n: np.zeros(max(cap, 1), dtype=t) for n, t in fields}
+    return arrs
+
+
+def _fill(S, fields, arrs):
+    s = S()
+    for n, _ in fields:
+        setattr(s, n, arrs[n].ctypes.data)
+    return s
+
+
+def _trim(arrs, k):
+    return {n: a[:k].copy() for n, a in arrs.items()}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        i64, i32 = C.c_int64, C.c_int
+        L.orc_fof3d.argtypes = [C.POINTER(Params), i64, i32, _P, _P, _P, _P]
+        L.orc_refine6d.argtypes = [C.POINTER(Params), i64, i32, _P, _P, _P, _P, _P, _P, _P,
+                                   i64, C.POINTER(NodesS), _P, C.POINTER(C.c_int64)]
+        L.orc_assign.argtypes = [C.POINTER(Params), i64, i32, _P, _P, _P, _P, _P, _P,
+                                 C.POINTER(NodesS), i64, _P, i64, C.POINTER(HalosS), _P,
+                                 C.POINTER(C.c_int64)]
+        L.orc_unbind.argtypes = [C.POINTER(Params), i64, i32, _P, _P, _P, _P, _P, _P,
+                                 C.POINTER(HalosS), i64, _P, _P, _P, _P, C.POINTER(UnbS)]
+        L.orc_props.argtypes = [C.POINTER(Params), i64, i32, _P, _P, _P, _P, _P, _P,
+                                C.POINTER(NodesS), i64, C.POINTER(HalosS), i64, _P, _P,
+                                C.POINTER(PropsS)]
+        L.orc_node_normalise.argtypes = [C.POINTER(Params), i64, i32, _P, _P, _P, _P, _P,
+                                         _P, _P, _P, _P]
+        L.orc_nn6d.argtypes = [i64, _P, _P]
+        L.orc_nn6d.restype = None
+        L.orc_ell2.argtypes = [i64, _P, C.c_double]
+        L.orc_ell2.restype = C.c_float
+        L.orc_fof6d.argtypes = [i64, _P, C.c_float, _P]
+        L.orc_fof6d.restype = None
+        L.orc_phi_points.argtypes = [C.POINTER(Params), i32, _P, _P, _P, _P, i64, _P, i64, _P]
+        L.orc_phi_points.restype = None
+        L.orc_position_shift.argtypes = [C.c_double]
+        L.orc_position_shift.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+@dataclasses.dataclass
+class Particles:
+    """Particle arrays in input order (positions float64 or float32)."""
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    vx: np.ndarray
+    vy: np.ndarray
+    vz: np.ndarray
+
+    @classmethod
+    def of(cls, cat):
+        return cls(cat.x, cat.y, cat.z, cat.vx, cat.vy, cat.vz)
+
+    @property
+    def n(self):
+        return int(self.x.shape[0])
+
+    @property
+    def f64(self):
+        return int(self.x.dtype == np.float64)
+
+    def ptrs(self, vel=True):
+        for a in (self.x, self.y, self.z) + ((self.vx, self.vy, self.vz) if vel else ()):
+            assert a.flags.c_contiguous
+        for a in (self.x, self.y, self.z):
+            assert a.dtype == self.x.dtype
+        if vel:
+            for a in (self.vx, self.vy, self.vz):
+                assert a.dtype == np.float32
+        arrs = (self.x, self.y, self.z) + ((self.vx, self.vy, self.vz) if vel else ())
+        return [a.ctypes.data for a in arrs]
+
+
+def make_params(box, particle_mass, softening, *, b=0.28, f=0.7, min_members=10,
+                max_levels=200, merge_q2=200.0, G=None, rho_vir=None, core_frac=0.1,
+                unbound_threshold=0.5) -> Params:
+    from paper_1110_4372_amd import synth
+    return Params(box, b, f, min_members, max_levels, merge_q2, particle_mass,
+                  synth.G_NEWTON if G is None else G,
+                  synth.RHO_VIR if rho_vir is None else rho_vir, softening, core_frac,
+                  unbound_threshold)
+
+
+def params_of(cat, **kw) -> Params:
+    return make_params(cat.box, cat.particle_mass, cat.softening, **kw)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def fof3d(p: Params, P: Particles) -> np.ndarray:
+    lab = np.zeros(P.n, dtype=np.uint32)
+    _check(lib().orc_fof3d(C.byref(p), P.n, P.f64, *P.ptrs(False), lab.ctypes.data), "fof3d")
+    return lab
+
+
+def refine6d(p: Params, P: Particles, label: np.ndarray):
+    label = np.ascontiguousarray(label, dtype=np.uint32)
+    cap = max(16, P.n // 4)
+    while True:
+        arrs = _alloc(NODE_FIELDS, cap)
+        S = _fill(NodesS, NODE_FIELDS, arrs)
+        deepest = np.zeros(P.n, dtype=np.int32)
+        nn = C.c_int64(0)
+        rc = lib().orc_refine6d(C.byref(p), P.n, P.f64, *P.ptrs(), label.ctypes.data, cap,
+                                C.byref(S), deepest.ctypes.data, C.byref(nn))
+        if rc == -4:
+            cap = nn.value
+            continue
+        _check(rc, "refine6d")
+        return _trim(arrs, nn.value), deepest
+
+
+def assign(p: Params, P: Particles, nodes: dict, deepest: np.ndarray):
+    nn = int(nodes["parent"].shape[0])
+    nodes = {k: np.ascontiguousarray(v) for k, v in nodes.items()}
+    NS = _fill(NodesS, NODE_FIELDS, nodes)
+    cap = max(1, int(np.sum(nodes["n_children"] == 0)))
+    arrs = _alloc(HALO_FIELDS, cap)
+    HS = _fill(HalosS, HALO_FIELDS, arrs)
+    halo_of = np.zeros(P.n, dtype=np.int32)
+    nh = C.c_int64(0)
+    deepest = np.ascontiguousarray(deepest, dtype=np.int32)
+    _check(lib().orc_assign(C.byref(p), P.n, P.f64, *P.ptrs(), C.byref(NS), nn,
+                            deepest.ctypes.data, cap, C.byref(HS), halo_of.ctypes.data,
+                            C.byref(nh)), "assign")
+    return _trim(arrs, nh.value), halo_of
+
+
+def unbind(p: Params, P: Particles, halos: dict, halo_of: np.ndarray):
+    nh = int(halos["seed_node"].shape[0])
+    halos = {k: np.ascontiguousarray(v) for k, v in halos.items()}
+    HS = _fill(HalosS, HALO_FIELDS, halos)
+    out = _alloc(UNB_FIELDS, nh)
+    US = _fill(UnbS, UNB_FIELDS, out)
+    bound = np.zeros(P.n, dtype=np.uint8)
+    phi = np.zeros(P.n, dtype=np.float64)
+    phia = np.zeros(P.n, dtype=np.float64)
+    halo_of = np.ascontiguousarray(halo_of, dtype=np.int32)
+    _check(lib().orc_unbind(C.byref(p), P.n, P.f64, *P.ptrs(), C.byref(HS), nh,
+                            halo_of.ctypes.data, bound.ctypes.data, phi.ctypes.data,
+                            phia.ctypes.data, C.byref(US)), "unbind")
+    return _trim(out, nh), bound, phi, phia
+
+
+def props(p: Params, P: Particles, nodes: dict, halos: dict, halo_of, bound):
+    nn = int(nodes["parent"].shape[0])
+    nh = int(halos["seed_node"].shape[0])
+    nodes = {k: np.ascontiguousarray(v) for k, v in nodes.items()}
+    halos = {k: np.ascontiguousarray(v) for k, v in halos.items()}
+    NS = _fill(NodesS, NODE_FIELDS, nodes)
+    HS = _fill(HalosS, HALO_FIELDS, halos)
+    out = _alloc(PROP_FIELDS, nh)
+    PS = _fill(PropsS, PROP_FIELDS, out)
+    halo_of = np.ascontiguousarray(halo_of, dtype=np.int32)
+    bound = np.ascontiguousarray(bound, dtype=np.uint8)
+    _check(lib().orc_props(C.byref(p), P.n, P.f64, *P.ptrs(), C.byref(NS), nn, C.byref(HS), nh,
+                           halo_of.ctypes.data, bound.ctypes.data, C.byref(PS)), "props")
+    return _trim(out, nh)
+
+
+def node_normalise(p: Params, P: Particles, members: np.ndarray):
+    members = np.ascontiguousarray(members, dtype=np.int64)
+    nm = int(members.shape[0])
+    xi = np.zeros((nm, 6), dtype=np.float32)
+    mom = np.zeros(8, dtype=np.float64)
+    _check(lib().orc_node_normalise(C.byref(p), nm, P.f64, *P.ptrs(), members.ctypes.data,
+                                    xi.ctypes.data, mom.ctypes.data), "normalise")
+    return xi, mom
+
+
+def nn6d(xi: np.ndarray) -> np.ndarray:
+    xi = np.ascontiguousarray(xi, dtype=np.float32)
+    d = np.zeros(xi.shape[0], dtype=np.float32)
+    lib().orc_nn6d(xi.shape[0], xi.ctypes.data, d.ctypes.data)
+    return d
+
+
+def ell2(dmin: np.ndarray, f: float = 0.7) -> float:
+    dmin = np.ascontiguousarray(dmin, dtype=np.float32)
+    return float(lib().orc_ell2(dmin.shape[0], dmin.ctypes.data, f))
+
+
+def fof6d(xi: np.ndarray, l2: float) -> np.ndarray:
+    xi = np.ascontiguousarray(xi, dtype=np.float32)
+    comp = np.zeros(xi.shape[0], dtype=np.int64)
+    lib().orc_fof6d(xi.shape[0], xi.ctypes.data, C.c_float(l2), comp.ctypes.data)
+    return comp
+
+
+def phi_points(p: Params, P: Particles, src: np.ndarray, tgt: np.ndarray) -> np.ndarray:
+    src = np.ascontiguousarray(src, dtype=np.int64)
+    tgt = np.ascontiguousarray(tgt, dtype=np.int64)
+    out = np.zeros(tgt.shape[0], dtype=np.float64)
+    lib().orc_phi_points(C.byref(p), P.f64, *P.ptrs(False), src.ctypes.data, src.shape[0],
+                         tgt.ctypes.data, tgt.shape[0], out.ctypes.data)
+    return out
+
+
+def position_shift(box: float) -> int:
+    return int(lib().orc_position_shift(box))
+
+
+def run_all(p: Params, P: Particles):
+    """The whole path on the CPU: fof3d -> refine6d -> assign -> unbind -> props."""
+    lab = fof3d(p, P)
+    nodes, deepest = refine6d(p, P, lab)
+    halos, halo_of = assign(p, P, nodes, deepest)
+    unb, bound, phi, phia = unbind(p, P, halos, halo_of)
+    pr = props(p, P, nodes, halos, halo_of, bound)
+    return dict(label=lab, nodes=nodes, deepest=deepest, halos=halos, halo_of=halo_of,
+                unbound=unb, bound=bound, phi=phi, phi_abs=phia, props=pr)
