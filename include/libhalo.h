@@ -1,0 +1,266 @@
+/*
+ * libhalo.h -- C ABI of the MI355X (gfx950) phase-space halo-finding path.
+ *
+ * The five stages follow the method of Behroozi, Wechsler & Wu (2013), "The
+ * ROCKSTAR phase-space temporal halo finder", Section 3 and Appendix B:
+ *
+ *   libhalo_fof3d     3D friends-of-friends groups             (Section 3.1)
+ *   libhalo_refine6d  recursive 6D phase-space FOF hierarchy   (Section 3.2, Eq. 1)
+ *   libhalo_assign    seeds, seed merging, particle assignment (Section 3.3, Eqs. 2-4)
+ *                     and host/subhalo relation                (Section 3.4)
+ *   libhalo_unbind    single-pass unbinding                    (Section 3.5.3, App. B)
+ *   libhalo_props     halo centre, SO mass/radius, vmax, core  (Sections 3.5.1-3.5.4)
+ *                     and bulk velocity, core-bulk offset
+ *
+ * Conventions shared by every entry point
+ *   - Particles are given in structure-of-arrays form in input order:
+ *     positions x, y, z as float32 or float64 (pos_dtype), in [0, box);
+ *     velocities vx, vy, vz as float32 (km/s).  Particle i is the i-th element.
+ *   - Every array argument is a DEVICE pointer owned by the caller, unless
+ *     documented as a host pointer (the n_* counts and the parameter block).
+ *     The library never frees caller memory; it owns only its workspace,
+ *     allocated on the context's device and released by libhalo_ctx_destroy.
+ *   - Work is enqueued on `stream` (a hipStream_t, NULL = default stream).  A
+ *     call returns after its host-visible counts are known, which needs a
+ *     few small synchronous read-backs on that stream; device outputs are
+ *     complete when the stream is.
+ *   - Errors: every call returns LIBHALO_OK (0) or a negative status; the
+ *     message is in libhalo_last_error(ctx).  On error the device outputs are
+ *     unspecified.  LIBHALO_ECAPACITY writes the required count into the
+ *     n_* host output so the caller can grow the buffer and call again.
+ *   - One context per stream at a time; a context is not thread safe.
+ *
+ * Floating point: 3D friendship uses FP64 minimum-image distances; group
+ * moments use positions (relative to the group's smallest-index particle) and
+ * velocities quantised to fixed point (2^-S Mpc/h with S = 40 -
+ * ceil(log2(box/2)), and 2^-24 km/s) and summed exactly in 128-bit integers,
+ * so results do not depend on summation order; 6D distances are FP32 on
+ * coordinates normalised in FP64 and rounded once.
+ */
+#ifndef LIBHALO_H
+#define LIBHALO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LIBHALO_OK = 0,
+  LIBHALO_EINVAL = -1,     /* bad argument, parameter or input value */
+  LIBHALO_ENOMEM = -2,     /* device allocation of the workspace failed */
+  LIBHALO_EHIP = -3,       /* a HIP runtime call failed */
+  LIBHALO_ECAPACITY = -4,  /* an output table is too small; n_* holds the need */
+  LIBHALO_EGEOMETRY = -5   /* a FOF group spans half the box or more */
+} libhalo_status;
+
+typedef enum { LIBHALO_F32 = 0, LIBHALO_F64 = 1 } libhalo_dtype;
+
+/* How the hierarchy and potential kernels are scheduled. */
+typedef enum {
+  LIBHALO_PLAIN = 0,   /* one launch sequence per node / halo */
+  LIBHALO_BATCHED = 1  /* all nodes of a level / all halos per launch */
+} libhalo_mode;
+
+/* Arithmetic of the unbinding potential. */
+typedef enum {
+  LIBHALO_PREC_FP64 = 0,  /* FP64 direct sum */
+  LIBHALO_PREC_MIXED = 1  /* FP32 halo-local tiles, compensated FP32 sums,
+                             FP64 recheck of energies near zero */
+} libhalo_prec;
+
+/* Method parameters (Table 2 and Section 3 of the paper for the defaults). */
+typedef struct {
+  double box;               /* periodic box side L (Mpc/h) */
+  double b;                 /* FOF linking parameter; ll = b L / N^(1/3) (0.28) */
+  double f;                 /* linked fraction for the 6D linking length (0.7) */
+  int32_t min_members;      /* smallest group / subgroup refined or kept (10) */
+  int32_t max_levels;       /* hierarchy depth limit (EINVAL beyond it) */
+  double merge_q2;          /* seed merge threshold on q^2 = (10 sqrt 2)^2 = 200 */
+  double particle_mass;     /* m (Msun/h) */
+  double G;                 /* gravitational constant, (Mpc/h)(km/s)^2/(Msun/h) */
+  double rho_vir;           /* virial density, 360 rho_m at z = 0 ((Msun/h)/(Mpc/h)^3) */
+  double softening;         /* Plummer softening eps of the potential (Mpc/h) */
+  double core_frac;         /* core radius as a fraction of R_vir (0.1) */
+  double unbound_threshold; /* minimum bound fraction of a valid halo (0.5) */
+  double e_recheck;         /* mixed precision: FP64 recheck when |E| <
+                               e_recheck (|K| + |phi|) (1e-4) */
+  int32_t mode;             /* libhalo_mode */
+  int32_t prec;             /* libhalo_prec */
+} libhalo_params;
+
+/* Node table (refine6d output), structure of arrays, capacity `cap` rows.
+ * Row order is breadth first: level by level; within a level, children of a
+ * node follow their parents' order and, among siblings, their smallest
+ * particle index.  Level-0 rows are the FOF groups of >= min_members. */
+typedef struct {
+  int32_t* parent;      /* parent row, -1 for a FOF group */
+  int32_t* level;       /* depth, 0 for a FOF group */
+  int32_t* first_child; /* first child row (children are contiguous), -1 if leaf */
+  int32_t* n_children;  /* number of subgroups with >= min_members */
+  uint32_t* count;      /* number of particles */
+  uint32_t* canon;      /* smallest particle index (node identity) */
+  uint32_t* fof;        /* FOF label of the group the node belongs to */
+  uint32_t* flags;      /* LIBHALO_NODE_* */
+  double *cx, *cy, *cz; /* centre (mean position), wrapped into [0, L) */
+  double *vx, *vy, *vz; /* mean velocity */
+  double* sx2;          /* position dispersion sigma_x^2 (3D, 1/n) */
+  double* sv2;          /* velocity dispersion sigma_v^2 (3D, 1/n) */
+  float* ell2;          /* squared 6D linking length, -1 if not computed */
+  int64_t cap;
+} libhalo_nodes;
+
+#define LIBHALO_NODE_LEAF 1u
+#define LIBHALO_NODE_DEGENERATE 2u /* sigma_x or sigma_v is zero */
+#define LIBHALO_NODE_WHOLE 4u      /* the only subgroup would be the node */
+
+/* Seed / halo table (assign output), one row per leaf node, in node order. */
+typedef struct {
+  int32_t* seed_node;   /* leaf node row of the seed */
+  int32_t* merged_into; /* itself if kept, else the kept seed it merged into */
+  int32_t* host;        /* host halo row (Section 3.4), -1 for a FOF's main halo */
+  uint32_t* fof;        /* FOF label */
+  uint32_t* n_assigned; /* particles assigned to the halo */
+  double *xs, *ys, *zs;    /* seed position (leaf mean) */
+  double *vxs, *vys, *vzs; /* seed velocity (leaf mean) */
+  double* sv2;          /* final velocity dispersion of the assigned particles */
+  double* vmax2;        /* final vmax^2 of the assigned particles about the seed */
+  int64_t cap;
+} libhalo_halos;
+
+/* Unbinding results per halo row. */
+typedef struct {
+  uint32_t* n_bound_own; /* bound particles among those assigned to the halo */
+  uint32_t* n_s;         /* |S(h)|: the halo's particles plus its subhalos' */
+  uint32_t* n_bound_s;   /* bound particles in S(h) */
+  uint8_t* valid;        /* n_bound_s >= unbound_threshold * n_s */
+  double *vbx, *vby, *vbz; /* bulk velocity of S(h) */
+} libhalo_unbound;
+
+/* Halo properties per halo row (zeros for merged seeds). */
+typedef struct {
+  double *px, *py, *pz;    /* centre */
+  double *vcx, *vcy, *vcz; /* core velocity (within core_frac R_vir) */
+  double *vbx, *vby, *vbz; /* bulk velocity (within R_vir) */
+  double *mvir, *rvir, *vmax, *voff;
+  uint32_t* n_bound;       /* bound particles of S(h) */
+} libhalo_props_out;
+
+typedef struct libhalo_ctx libhalo_ctx;
+
+/* Create a context on HIP device `device` with parameters *p (host).
+ * Validates the parameters (EINVAL).  Allocates nothing on the device. */
+int libhalo_ctx_create(const libhalo_params* p, int device, libhalo_ctx** out);
+/* Release the workspace and the context. */
+int libhalo_ctx_destroy(libhalo_ctx* ctx);
+/* Message of the last error on this context (static storage of the ctx). */
+const char* libhalo_last_error(const libhalo_ctx* ctx);
+/* Replace the parameters (EINVAL if invalid). */
+int libhalo_set_params(libhalo_ctx* ctx, const libhalo_params* p);
+/* Version string of the library. */
+const char* libhalo_version(void);
+
+/*
+ * 3D friends-of-friends (Section 3.1), standard definition: particles i and
+ * j are friends when their minimum-image separation is <= ll = b L / n^(1/3)
+ * (FP64); groups are connected components.  Exact: independent of order.
+ *   fof_label[n]  out: smallest particle index of i's group
+ *   perm[n]       out: first *n_members entries are the particles of groups
+ *                 with >= min_members, ordered by (label, index)
+ *   grp_first[grp_cap], grp_count[grp_cap]
+ *                 out: range of each such group in perm, groups by label
+ *   n_groups, n_members  host out
+ * Errors: EINVAL (n < 1, n >= 2^32 - 1, a position outside [0, L) or NaN),
+ * ECAPACITY (n_groups > grp_cap).
+ */
+int libhalo_fof3d(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
+                  const void* y, const void* z, uint32_t* fof_label, uint32_t* perm,
+                  uint32_t* grp_first, uint32_t* grp_count, int64_t grp_cap,
+                  int64_t* n_groups, int64_t* n_members, void* stream);
+
+/*
+ * Recursive phase-space FOF hierarchy (Section 3.2) of every FOF group given
+ * by (perm, grp_first, grp_count) as produced by libhalo_fof3d.  For each
+ * (sub)group: Eq. 1 metric (positions and velocities divided by the group's
+ * 3D dispersions), squared linking length ell^2 = the ceil(f n)-th smallest
+ * nearest-neighbour squared distance (so that a fraction >= f of the
+ * particles have a friend), 6D FOF at ell^2; components of >= min_members
+ * become subgroups, recursively.  A node with a zero dispersion, or whose
+ * only subgroup would hold all its particles, is a leaf.
+ *   nodes         out: node table (cap rows)
+ *   deepest[n]    out: deepest node row holding particle i, -1 if none
+ *   n_nodes       host out
+ * Errors: ECAPACITY (n_nodes > nodes->cap), EGEOMETRY (group extent >= L/2
+ * on an axis), EINVAL (depth beyond max_levels, |v| >= 2^16 km/s).
+ */
+int libhalo_refine6d(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
+                     const void* y, const void* z, const float* vx, const float* vy,
+                     const float* vz, const uint32_t* perm, const uint32_t* grp_first,
+                     const uint32_t* grp_count, int64_t n_groups, libhalo_nodes* nodes,
+                     int32_t* deepest, int64_t* n_nodes, void* stream);
+
+/*
+ * Seeds, merging, assignment and host/subhalo relation (Sections 3.3-3.4).
+ * One seed per leaf node.  Within a FOF group, seeds are visited by
+ * decreasing size (ties: lower row); a seed merges into the closest kept
+ * seed when |dx|^2/mu_x^2 + |dv|^2/mu_v^2 < merge_q2 (Eq. 2, mu = sigma /
+ * sqrt(n) of the visited, smaller seed).  Bottom-up over levels, the
+ * particles of a node outside all its subgroups go to its only seed, or to
+ * the seed minimising |dx|^2/r_dyn^2 + |dv|^2/sigma_v^2 (Eqs. 3-4; r_dyn =
+ * vmax / sqrt(4/3 pi G rho_vir); sigma_v and vmax from the particles already
+ * assigned to that seed; ties: lower row).  Within a FOF group each halo but
+ * the one with most particles becomes a sub of the closest halo (same metric)
+ * earlier in the order (n_assigned desc, row asc).
+ *   halos         out: seed / halo table (cap rows)
+ *   halo_of[n]    out: halo row of particle i, -1 outside refined groups
+ *   n_halos       host out (number of seeds = leaf nodes)
+ * Errors: ECAPACITY (n_halos > halos->cap), EINVAL.
+ */
+int libhalo_assign(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
+                   const void* y, const void* z, const float* vx, const float* vy,
+                   const float* vz, const libhalo_nodes* nodes, int64_t n_nodes,
+                   const int32_t* deepest, libhalo_halos* halos, int32_t* halo_of,
+                   int64_t* n_halos, void* stream);
+
+/*
+ * Single-pass unbinding (Section 3.5.3; exact direct sum in place of the
+ * paper's tree code of Appendix B).  For particle i assigned to halo h:
+ * phi_i = -G m sum_{j in S(h), j != i} (r_ij^2 + eps^2)^-1/2, S(h) = the
+ * particles of h and of all its subhalos; bound iff
+ * 1/2 |v_i - v_bulk(h)|^2 + phi_i < 0 with v_bulk(h) the mean velocity of
+ * S(h).  A halo is valid when n_bound_s >= unbound_threshold * n_s.
+ *   bound[n]      out: 1 if bound, 0 otherwise (0 outside halos)
+ *   phi[n]        out (may be NULL): potential, 0 outside halos
+ *   out           out: per-halo results
+ * Errors: EINVAL.
+ */
+int libhalo_unbind(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
+                   const void* y, const void* z, const float* vx, const float* vy,
+                   const float* vz, const libhalo_halos* halos, int64_t n_halos,
+                   const int32_t* halo_of, uint8_t* bound, double* phi,
+                   libhalo_unbound* out, void* stream);
+
+/*
+ * Halo properties from bound particles (Sections 3.5.1-3.5.4):
+ * centre = mean position of the node, on the chain from the halo's seed leaf
+ * up while the node holds no other halo's seed, minimising sigma_x / sqrt(n)
+ * (ties: deeper); B(h) = bound particles of S(h) by distance from the
+ * centre; virial SO mass M = k* m with k* the largest k such that every
+ * j <= k has 3 j m / (4 pi r_j^3) >= rho_vir, R_vir = (3 M / (4 pi
+ * rho_vir))^(1/3); vmax = max_{j <= k*} sqrt(G j m / max(r_j, eps)); bulk
+ * velocity = mean of the k* innermost; core velocity = mean within core_frac
+ * R_vir (the innermost particle if none); voff = |core - bulk|.
+ * Errors: EINVAL.
+ */
+int libhalo_props(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
+                  const void* y, const void* z, const float* vx, const float* vy,
+                  const float* vz, const libhalo_nodes* nodes, int64_t n_nodes,
+                  const libhalo_halos* halos, int64_t n_halos, const int32_t* halo_of,
+                  const uint8_t* bound, libhalo_props_out* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

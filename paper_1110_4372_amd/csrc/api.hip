@@ -1,0 +1,216 @@
+// C ABI of libhalo: context, parameter validation, error capture, dispatch.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+#include "fof3d.hpp"
+#include "stages.hpp"
+
+struct libhalo_ctx {
+  halo::Ctx c;
+};
+
+namespace halo {
+
+void Ctx::ensure_ws(size_t bytes) {
+  if (bytes <= ws.cap) return;
+  if (ws.base) {
+    HALO_HIP(hipDeviceSynchronize());
+    HALO_HIP(hipFree(ws.base));
+    ws.base = nullptr;
+    ws.cap = 0;
+  }
+  size_t want = bytes + bytes / 8;
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{LIBHALO_ENOMEM, "workspace allocation of " + std::to_string(want) +
+                                    " bytes failed"};
+  }
+  ws.base = static_cast<char*>(p);
+  ws.cap = want;
+}
+
+void Ctx::release() {
+  if (ws.base) (void)hipFree(ws.base);
+  if (d_err) (void)hipFree(d_err);
+  if (h_pinned) (void)hipHostFree(h_pinned);
+  ws.base = nullptr;
+  d_err = nullptr;
+  h_pinned = nullptr;
+}
+
+static std::string validate(const libhalo_params& p) {
+  if (!(p.box > 0.0) || !std::isfinite(p.box)) return "box must be positive";
+  if (!(p.b > 0.0)) return "b must be positive";
+  if (!(p.f > 0.0 && p.f <= 1.0)) return "f must lie in (0, 1]";
+  if (p.min_members < 2) return "min_members must be >= 2";
+  if (p.max_levels < 1 || p.max_levels > 4096) return "max_levels must lie in [1, 4096]";
+  if (!(p.merge_q2 >= 0.0)) return "merge_q2 must be >= 0";
+  if (!(p.particle_mass > 0.0)) return "particle_mass must be positive";
+  if (!(p.G > 0.0)) return "G must be positive";
+  if (!(p.rho_vir > 0.0)) return "rho_vir must be positive";
+  if (!(p.softening > 0.0)) return "softening must be positive";
+  if (!(p.core_frac > 0.0)) return "core_frac must be positive";
+  if (!(p.unbound_threshold >= 0.0 && p.unbound_threshold <= 1.0))
+    return "unbound_threshold must lie in [0, 1]";
+  if (!(p.e_recheck >= 0.0)) return "e_recheck must be >= 0";
+  if (p.mode != LIBHALO_PLAIN && p.mode != LIBHALO_BATCHED) return "unknown mode";
+  if (p.prec != LIBHALO_PREC_FP64 && p.prec != LIBHALO_PREC_MIXED) return "unknown prec";
+  return "";
+}
+
+}  // namespace halo
+
+template <class F>
+static int guarded(libhalo_ctx* ctx, F&& f) {
+  if (!ctx) return LIBHALO_EINVAL;
+  try {
+    HALO_HIP(hipSetDevice(ctx->c.device));
+    f(ctx->c);
+    ctx->c.err.clear();
+    return LIBHALO_OK;
+  } catch (const halo::Error& e) {
+    ctx->c.err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->c.err = "host allocation failed";
+    return LIBHALO_ENOMEM;
+  }
+}
+
+extern "C" {
+
+const char* libhalo_version(void) { return "libhalo 0.1 (gfx950)"; }
+
+int libhalo_ctx_create(const libhalo_params* p, int device, libhalo_ctx** out) {
+  if (!p || !out) return LIBHALO_EINVAL;
+  *out = nullptr;
+  if (!halo::validate(*p).empty()) return LIBHALO_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return LIBHALO_EINVAL;
+  libhalo_ctx* c = new (std::nothrow) libhalo_ctx();
+  if (!c) return LIBHALO_ENOMEM;
+  c->c.p = *p;
+  c->c.device = device;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipMalloc(&c->c.d_err, 256) != hipSuccess ||
+      hipHostMalloc(&c->c.h_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    c->c.release();
+    delete c;
+    return LIBHALO_EHIP;
+  }
+  *out = c;
+  return LIBHALO_OK;
+}
+
+int libhalo_ctx_destroy(libhalo_ctx* ctx) {
+  if (!ctx) return LIBHALO_EINVAL;
+  (void)hipSetDevice(ctx->c.device);
+  (void)hipDeviceSynchronize();
+  ctx->c.release();
+  delete ctx;
+  return LIBHALO_OK;
+}
+
+const char* libhalo_last_error(const libhalo_ctx* ctx) {
+  return ctx ? ctx->c.err.c_str() : "null context";
+}
+
+int libhalo_set_params(libhalo_ctx* ctx, const libhalo_params* p) {
+  if (!ctx || !p) return LIBHALO_EINVAL;
+  std::string m = halo::validate(*p);
+  if (!m.empty()) {
+    ctx->c.err = m;
+    return LIBHALO_EINVAL;
+  }
+  ctx->c.p = *p;
+  return LIBHALO_OK;
+}
+
+static bool dtype_ok(int d) { return d == LIBHALO_F32 || d == LIBHALO_F64; }
+
+int libhalo_fof3d(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, const void* y,
+                  const void* z, uint32_t* fof_label, uint32_t* perm, uint32_t* grp_first,
+                  uint32_t* grp_count, int64_t grp_cap, int64_t* n_groups,
+                  int64_t* n_members, void* stream) {
+  return guarded(ctx, [&](halo::Ctx& c) {
+    HALO_CHECK(n >= 1 && n < 0xFFFFFFFFll, LIBHALO_EINVAL, "n must lie in [1, 2^32-1)");
+    HALO_CHECK(dtype_ok(pos_dtype), LIBHALO_EINVAL, "pos_dtype must be F32 or F64");
+    HALO_CHECK(x && y && z && fof_label && perm && n_groups && n_members, LIBHALO_EINVAL,
+               "null pointer argument");
+    HALO_CHECK(grp_cap == 0 || (grp_first && grp_count), LIBHALO_EINVAL,
+               "null group table");
+    c.ensure_ws(halo::fof3d_workspace(c.p, n, pos_dtype));
+    halo::fof3d(c, n, pos_dtype, x, y, z, fof_label, perm, grp_first, grp_count, grp_cap,
+                n_groups, n_members, (hipStream_t)stream);
+  });
+}
+
+int libhalo_refine6d(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
+                     const void* y, const void* z, const float* vx, const float* vy,
+                     const float* vz, const uint32_t* perm, const uint32_t* grp_first,
+                     const uint32_t* grp_count, int64_t n_groups, libhalo_nodes* nodes,
+                     int32_t* deepest, int64_t* n_nodes, void* stream) {
+  return guarded(ctx, [&](halo::Ctx& c) {
+    HALO_CHECK(n >= 1 && n < 0xFFFFFFFFll, LIBHALO_EINVAL, "n must lie in [1, 2^32-1)");
+    HALO_CHECK(dtype_ok(pos_dtype), LIBHALO_EINVAL, "pos_dtype must be F32 or F64");
+    HALO_CHECK(x && y && z && vx && vy && vz && nodes && deepest && n_nodes, LIBHALO_EINVAL,
+               "null pointer argument");
+    HALO_CHECK(n_groups >= 0 && (n_groups == 0 || (perm && grp_first && grp_count)),
+               LIBHALO_EINVAL, "bad group table");
+    halo::refine6d(c, n, pos_dtype, x, y, z, vx, vy, vz, perm, grp_first, grp_count,
+                   n_groups, nodes, deepest, n_nodes, (hipStream_t)stream);
+  });
+}
+
+int libhalo_assign(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, const void* y,
+                   const void* z, const float* vx, const float* vy, const float* vz,
+                   const libhalo_nodes* nodes, int64_t n_nodes, const int32_t* deepest,
+                   libhalo_halos* halos, int32_t* halo_of, int64_t* n_halos, void* stream) {
+  return guarded(ctx, [&](halo::Ctx& c) {
+    HALO_CHECK(n >= 1 && n < 0xFFFFFFFFll, LIBHALO_EINVAL, "n must lie in [1, 2^32-1)");
+    HALO_CHECK(dtype_ok(pos_dtype), LIBHALO_EINVAL, "pos_dtype must be F32 or F64");
+    HALO_CHECK(x && y && z && vx && vy && vz && nodes && deepest && halos && halo_of &&
+                   n_halos,
+               LIBHALO_EINVAL, "null pointer argument");
+    HALO_CHECK(n_nodes >= 0, LIBHALO_EINVAL, "n_nodes must be >= 0");
+    halo::assign(c, n, pos_dtype, x, y, z, vx, vy, vz, nodes, n_nodes, deepest, halos,
+                 halo_of, n_halos, (hipStream_t)stream);
+  });
+}
+
+int libhalo_unbind(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, const void* y,
+                   const void* z, const float* vx, const float* vy, const float* vz,
+                   const libhalo_halos* halos, int64_t n_halos, const int32_t* halo_of,
+                   uint8_t* bound, double* phi, libhalo_unbound* out, void* stream) {
+  return guarded(ctx, [&](halo::Ctx& c) {
+    HALO_CHECK(n >= 1 && n < 0xFFFFFFFFll, LIBHALO_EINVAL, "n must lie in [1, 2^32-1)");
+    HALO_CHECK(dtype_ok(pos_dtype), LIBHALO_EINVAL, "pos_dtype must be F32 or F64");
+    HALO_CHECK(x && y && z && vx && vy && vz && halos && halo_of && bound && out,
+               LIBHALO_EINVAL, "null pointer argument");
+    HALO_CHECK(n_halos >= 0, LIBHALO_EINVAL, "n_halos must be >= 0");
+    halo::unbind(c, n, pos_dtype, x, y, z, vx, vy, vz, halos, n_halos, halo_of, bound, phi,
+                 out, (hipStream_t)stream);
+  });
+}
+
+int libhalo_props(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, const void* y,
+                  const void* z, const float* vx, const float* vy, const float* vz,
+                  const libhalo_nodes* nodes, int64_t n_nodes, const libhalo_halos* halos,
+                  int64_t n_halos, const int32_t* halo_of, const uint8_t* bound,
+                  libhalo_props_out* out, void* stream) {
+  return guarded(ctx, [&](halo::Ctx& c) {
+    HALO_CHECK(n >= 1 && n < 0xFFFFFFFFll, LIBHALO_EINVAL, "n must lie in [1, 2^32-1)");
+    HALO_CHECK(dtype_ok(pos_dtype), LIBHALO_EINVAL, "pos_dtype must be F32 or F64");
+    HALO_CHECK(x && y && z && vx && vy && vz && nodes && halos && halo_of && bound && out,
+               LIBHALO_EINVAL, "null pointer argument");
+    HALO_CHECK(n_nodes >= 0 && n_halos >= 0, LIBHALO_EINVAL, "negative table size");
+    halo::props(c, n, pos_dtype, x, y, z, vx, vy, vz, nodes, n_nodes, halos, n_halos, halo_of,
+                bound, out, (hipStream_t)stream);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+// Shared device helpers and the context of the libhalo HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "libhalo.h"
+
+namespace halo {
+
+constexpr int kWave = 64;
+constexpr int kVelShift = 24;  // velocity fixed point: 2^-24 km/s
+
+// ------------------------------------------------------------ errors -----
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define HALO_HIP(call)                                                        \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      throw ::halo::Error{LIBHALO_EHIP, std::string(#call) + ": " +           \
+                                            hipGetErrorString(e_)};           \
+  } while (0)
+
+#define HALO_CHECK(cond, code, msg)                       \
+  do {                                                    \
+    if (!(cond)) throw ::halo::Error{(code), (msg)};      \
+  } while (0)
+
+// Device error word bits, set by kernels, read back by the host.
+enum : uint32_t {
+  kErrPosRange = 1u,   // a position outside [0, L) or NaN
+  kErrGeometry = 2u,   // group extent >= L/2
+  kErrVelRange = 4u,   // |v| >= 2^16 km/s or NaN
+};
+
+// ------------------------------------------------------------ workspace --
+// Grow-only device arena.  Each entry point resets it and carves buffers.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  size_t high = 0;  // largest request seen
+  void reset() { off = 0; }
+  template <class T>
+  T* take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    if (off + bytes > cap) {
+      high = off + bytes > high ? off + bytes : high;
+      throw Error{LIBHALO_ENOMEM, "workspace exhausted"};  // caller grows and retries
+    }
+    T* p = reinterpret_cast<T*>(base + off);
+    off += bytes;
+    if (off > high) high = off;
+    return p;
+  }
+};
+
+struct Ctx {
+  libhalo_params p{};
+  int device = 0;
+  std::string err;
+  Arena ws;
+  uint32_t* d_err = nullptr;       // device error word
+  void* h_pinned = nullptr;        // small pinned host buffer for read-backs
+  hipStream_t stream = nullptr;
+  void ensure_ws(size_t bytes);
+  void release();
+  template <class T>
+  T* host_slot(int i) { return reinterpret_cast<T*>(static_cast<char*>(h_pinned) + 64 * i); }
+};
+
+// ------------------------------------------------------------ launch -----
+inline unsigned blocks_for(int64_t n, int threads) {
+  int64_t b = (n + threads - 1) / threads;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+// ------------------------------------------------------------ device math -
+__device__ __forceinline__ double min_image(double d, double box) {
+  double h = 0.5 * box;
+  if (d > h) return d - box;
+  if (d < -h) return d + box;
+  return d;
+}
+
+// |(a, b, c)|^2 evaluated as fma(c, c, fma(b, b, a * a)).
+__device__ __forceinline__ double sq3(double a, double b, double c) {
+  return __fma_rn(c, c, __fma_rn(b, b, a * a));
+}
+
+template <class T>
+__device__ __forceinline__ double ld_pos(const T* p, int64_t i) {
+  return (double)p[i];
+}
+
+// Signed 128-bit integer as two 64-bit words (value = hi * 2^64 + lo).
+struct I128 {
+  unsigned long long lo;
+  long long hi;
+};
+
+__device__ __forceinline__ I128 i128_from(long long v) {
+  I128 r;
+  r.lo = (unsigned long long)v;
+  r.hi = v < 0 ? -1ll : 0ll;
+  return r;
+}
+
+__device__ __forceinline__ I128 i128_add(I128 a, I128 b) {
+  I128 r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo ? 1 : 0);
+  return r;
+}
+
+__device__ __forceinline__ I128 i128_sqr(long long v) {
+  __int128 s = (__int128)v * (__int128)v;
+  I128 r;
+  r.lo = (unsigned long long)s;
+  r.hi = (long long)(s >> 64);
+  return r;
+}
+
+// Nearest double of a 128-bit integer by one fixed sequence of roundings:
+// fma((double)hi, 2^64, (double)lo).
+__device__ __forceinline__ double i128_to_f64(I128 v) {
+  return __fma_rn((double)v.hi, 18446744073709551616.0, (double)v.lo);
+}
+
+__device__ __forceinline__ I128 wave_sum_i128(I128 v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    I128 w;
+    w.lo = __shfl_xor(v.lo, o);
+    w.hi = __shfl_xor(v.hi, o);
+    v = i128_add(v, w);
+  }
+  return v;
+}
+
+// Exact 128-bit accumulation into global memory with two 64-bit atomics:
+// carries out of the low word are added to the high word.
+__device__ __forceinline__ void atomic_add_i128(I128* acc, I128 v) {
+  unsigned long long old = atomicAdd(&acc->lo, v.lo);
+  unsigned long long carry = (old + v.lo) < old ? 1ull : 0ull;
+  long long add_hi = v.hi + (long long)carry;
+  if (add_hi != 0) atomicAdd((unsigned long long*)&acc->hi, (unsigned long long)add_hi);
+}
+
+__device__ __forceinline__ long long quantise(double v, int shift) {
+  return (long long)rint(ldexp(v, shift));
+}
+
+// Order-preserving u64 image of a double (for atomic min/max).
+__device__ __forceinline__ unsigned long long f64_ord(double d) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(d);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double ord_f64(unsigned long long u) {
+  u = (u >> 63) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u;
+  return __longlong_as_double((long long)u);
+}
+
+// Canonical FP32 squared 6D distance: s = d0*d0, then fmaf of the other five
+// components in the order d1, d2, e0, e1, e2, with d = b - a.
+__device__ __forceinline__ float d2_6(float a0, float a1, float a2, float a3, float a4,
+                                      float a5, float b0, float b1, float b2, float b3,
+                                      float b4, float b5) {
+  float d0 = b0 - a0, d1 = b1 - a1, d2 = b2 - a2;
+  float e0 = b3 - a3, e1 = b4 - a4, e2 = b5 - a5;
+  float s = d0 * d0;
+  s = __fmaf_rn(d1, d1, s);
+  s = __fmaf_rn(d2, d2, s);
+  s = __fmaf_rn(e0, e0, s);
+  s = __fmaf_rn(e1, e1, s);
+  s = __fmaf_rn(e2, e2, s);
+  return s;
+}
+
+// ------------------------------------------------------------ union-find --
+// Parents always point to smaller indices, so a root is its set's minimum.
+__device__ __forceinline__ uint32_t uf_load(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void uf_store(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t uf_find(uint32_t* par, uint32_t x) {
+  uint32_t cur = uf_load(par + x);
+  if (cur == x) return x;
+  uint32_t prev = x, next;
+  while (cur > (next = uf_load(par + cur))) {
+    uf_store(par + prev, next);  // path halving; next is an ancestor of prev
+    prev = cur;
+    cur = next;
+  }
+  return cur;
+}
+
+// Join the sets of a and b; returns the root of the joined set.
+__device__ __forceinline__ uint32_t uf_union(uint32_t* par, uint32_t a, uint32_t b) {
+  uint32_t ra = uf_find(par, a), rb = uf_find(par, b);
+  while (ra != rb) {
+    if (ra < rb) {
+      uint32_t t = ra;
+      ra = rb;
+      rb = t;
+    }
+    // hook the larger root ra under rb
+    uint32_t old = atomicCAS(par + ra, ra, rb);
+    if (old == ra) return rb;
+    ra = uf_find(par, old);
+    rb = uf_find(par, rb);
+  }
+  return ra;
+}
+
+}  // namespace halo

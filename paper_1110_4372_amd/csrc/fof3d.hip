@@ -1,0 +1,369 @@
+// 3D friends-of-friends on a radix-sorted cell list (Section 3.1 of the paper,
+// standard FOF definition), for gfx950.
+//
+// Cells have side s <= ll / sqrt(3) (1 - 1e-6), so any two particles in one
+// cell are friends: every occupied cell is a clique and union-find runs over
+// cells, not particles.  Each occupied cell visits the half stencil of cells
+// within reach R = ceil(ll / s) and stops testing a cell pair at its first
+// friendly pair (or skips it when both cells already share a root).  The
+// result is the exact standard FOF partition, the dense cores costing about
+// one test per cell pair -- the role the paper's dense-particle shortcut
+// plays on the CPU, without its order-dependent superset.
+#include "fof3d.hpp"
+#include "primitives.hpp"
+
+namespace halo {
+
+namespace {
+
+struct Grid {
+  double box, hbox, ll2, inv_side;
+  int64_t nc;   // cells per axis
+  int reach;    // stencil reach in cells
+};
+
+template <class T>
+__global__ void k_cell_keys(const T* x, const T* y, const T* z, int64_t n, Grid g,
+                            unsigned long long* key, uint32_t* err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double p[3] = {(double)x[i], (double)y[i], (double)z[i]};
+  int64_t c[3];
+  bool bad = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!(p[a] >= 0.0 && p[a] < g.box)) bad = true;
+    int64_t ci = (int64_t)floor(p[a] * g.inv_side);
+    ci = ci < 0 ? 0 : (ci >= g.nc ? g.nc - 1 : ci);
+    c[a] = ci;
+  }
+  if (bad) atomicOr(err, kErrPosRange);
+  key[i] = (unsigned long long)((c[2] * g.nc + c[1]) * g.nc + c[0]);
+}
+
+template <class T>
+__global__ void k_gather3(const T* x, const T* y, const T* z, const uint32_t* perm, int64_t n,
+                          T* xs, T* ys, T* zs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t j = perm[i];
+  xs[i] = x[j];
+  ys[i] = y[j];
+  zs[i] = z[j];
+}
+
+// head[i] = 1 where the sorted key changes.
+__global__ void k_heads(const unsigned long long* key, int64_t n, uint32_t* head) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  head[i] = (i == 0 || key[i] != key[i - 1]) ? 1u : 0u;
+}
+
+// cell_of[i] = cell index of sorted particle i; cell table start / key.
+__global__ void k_cells(const unsigned long long* key, const uint32_t* hscan, int64_t n,
+                        uint32_t* cell_of, uint32_t* cell_start,
+                        unsigned long long* cell_key) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool h = (i == 0 || key[i] != key[i - 1]);
+  uint32_t c = hscan[i] + (h ? 0u : 0xFFFFFFFFu);  // inclusive scan - 1
+  cell_of[i] = c;
+  if (h) {
+    cell_start[c] = (uint32_t)i;
+    cell_key[c] = key[i];
+  }
+}
+
+// row_start[r] = first cell whose key is >= r * nc (rows are (cz, cy)).
+__global__ void k_rows(const unsigned long long* cell_key, int64_t ncell, int64_t nc,
+                       int64_t nrow, uint32_t* row_start) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > nrow) return;
+  unsigned long long target = (unsigned long long)(r * nc);
+  int64_t lo = 0, hi = ncell;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (cell_key[mid] < target)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  row_start[r] = (uint32_t)lo;
+}
+
+__device__ __forceinline__ int64_t find_cell(const unsigned long long* cell_key,
+                                             const uint32_t* row_start, int64_t row,
+                                             unsigned long long want) {
+  int64_t lo = row_start[row], hi = row_start[row + 1];
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    unsigned long long k = cell_key[mid];
+    if (k < want)
+      lo = mid + 1;
+    else if (k > want)
+      hi = mid;
+    else
+      return mid;
+  }
+  return -1;
+}
+
+// Link pass over the half stencil.  phase 0: offsets within one cell on every
+// axis; phase 1: the others.  One thread per occupied cell.
+template <class T>
+__global__ void k_link(const T* xs, const T* ys, const T* zs, const uint32_t* cell_start,
+                       const unsigned long long* cell_key, const uint32_t* row_start,
+                       int64_t ncell, int64_t n, Grid g, int phase, uint32_t* par) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int64_t nc = g.nc;
+  const unsigned long long kc = cell_key[c];
+  const int64_t cx = (int64_t)(kc % (unsigned long long)nc);
+  const int64_t cy = (int64_t)((kc / (unsigned long long)nc) % (unsigned long long)nc);
+  const int64_t cz = (int64_t)(kc / ((unsigned long long)nc * (unsigned long long)nc));
+  const uint32_t a0 = cell_start[c];
+  const uint32_t a1 = (c + 1 < ncell) ? cell_start[c + 1] : (uint32_t)n;
+  const int R = g.reach;
+  const double side = g.box / (double)nc;
+  for (int dz = 0; dz <= R; ++dz) {
+    for (int dy = (dz == 0 ? 0 : -R); dy <= R; ++dy) {
+      for (int dx = ((dz == 0 && dy == 0) ? 1 : -R); dx <= R; ++dx) {
+        int far = (dx > 1 || dx < -1 || dy > 1 || dy < -1 || dz > 1);
+        if (far != phase) continue;
+        // smallest possible separation of the two cells
+        double gx = (double)(dx < 0 ? -dx - 1 : (dx > 0 ? dx - 1 : 0));
+        double gy = (double)(dy < 0 ? -dy - 1 : (dy > 0 ? dy - 1 : 0));
+        double gz = (double)(dz > 0 ? dz - 1 : 0);
+        if ((gx * gx + gy * gy + gz * gz) * side * side > g.ll2 * (1.0 + 1e-9)) continue;
+        int64_t nx = cx + dx, ny = cy + dy, nz = cz + dz;
+        nx = nx < 0 ? nx + nc : (nx >= nc ? nx - nc : nx);
+        ny = ny < 0 ? ny + nc : (ny >= nc ? ny - nc : ny);
+        nz = nz < 0 ? nz + nc : (nz >= nc ? nz - nc : nz);
+        int64_t row = nz * nc + ny;
+        int64_t d = find_cell(cell_key, row_start, row,
+                              (unsigned long long)(row * nc + nx));
+        if (d < 0) continue;
+        if (uf_find(par, (uint32_t)c) == uf_find(par, (uint32_t)d)) continue;
+        const uint32_t b0 = cell_start[d];
+        const uint32_t b1 = (d + 1 < ncell) ? cell_start[d + 1] : (uint32_t)n;
+        bool linked = false;
+        for (uint32_t i = a0; i < a1 && !linked; ++i) {
+          double xi = (double)xs[i], yi = (double)ys[i], zi = (double)zs[i];
+          for (uint32_t j = b0; j < b1; ++j) {
+            double ex = min_image((double)xs[j] - xi, g.box);
+            double ey = min_image((double)ys[j] - yi, g.box);
+            double ez = min_image((double)zs[j] - zi, g.box);
+            if (sq3(ex, ey, ez) <= g.ll2) {
+              linked = true;
+              break;
+            }
+          }
+        }
+        if (linked) uf_union(par, (uint32_t)c, (uint32_t)d);
+      }
+    }
+  }
+}
+
+__global__ void k_compress(uint32_t* par, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  par[i] = uf_find(par, (uint32_t)i);
+}
+
+// minidx[root] = smallest input index in the component.
+__global__ void k_minidx(const uint32_t* cell_of, const uint32_t* perm, const uint32_t* par,
+                         int64_t n, uint32_t* minidx) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  atomicMin(minidx + par[cell_of[i]], perm[i]);
+}
+
+__global__ void k_labels(const uint32_t* cell_of, const uint32_t* perm, const uint32_t* par,
+                         const uint32_t* minidx, int64_t n, uint32_t* label,
+                         uint32_t* gsize) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t l = minidx[par[cell_of[i]]];
+  label[perm[i]] = l;
+  atomicAdd(gsize + l, 1u);
+}
+
+__global__ void k_member_flags(const uint32_t* label, const uint32_t* gsize, int64_t n,
+                               uint32_t mm, uint32_t* flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  flag[i] = gsize[label[i]] >= mm ? 1u : 0u;
+}
+
+__global__ void k_member_compact(const uint32_t* label, const uint32_t* gsize,
+                                 const uint32_t* pos, int64_t n, uint32_t mm, uint32_t* key,
+                                 uint32_t* val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t l = label[i];
+  if (gsize[l] >= mm) {
+    key[pos[i]] = l;
+    val[pos[i]] = (uint32_t)i;
+  }
+}
+
+__global__ void k_group_heads(const uint32_t* key, int64_t m, uint32_t* head) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  head[i] = (i == 0 || key[i] != key[i - 1]) ? 1u : 0u;
+}
+
+__global__ void k_group_table(const uint32_t* key, const uint32_t* hscan, int64_t m,
+                              const uint32_t* gsize, uint32_t* grp_first,
+                              uint32_t* grp_count, int64_t cap) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  if (i == 0 || key[i] != key[i - 1]) {
+    uint32_t g = hscan[i];
+    if ((int64_t)g < cap) {
+      grp_first[g] = (uint32_t)i;
+      grp_count[g] = gsize[key[i]];
+    }
+  }
+}
+
+__global__ void k_copy_u32(const uint32_t* a, uint32_t* b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+template <class T>
+void fof3d_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, uint32_t* label,
+                uint32_t* perm_out, uint32_t* grp_first, uint32_t* grp_count, int64_t grp_cap,
+                int64_t* n_groups, int64_t* n_members, hipStream_t s) {
+  const libhalo_params& P = ctx.p;
+  const double ll = P.b * P.box / cbrt((double)n);
+  const double smax = ll / sqrt(3.0) * (1.0 - 1e-6);
+  Grid g;
+  g.box = P.box;
+  g.hbox = 0.5 * P.box;
+  g.ll2 = ll * ll;
+  g.nc = (int64_t)ceil(P.box / smax);
+  const double side = P.box / (double)g.nc;
+  g.inv_side = (double)g.nc / P.box;
+  g.reach = (int)ceil(ll / side);
+  HALO_CHECK(g.nc >= 2 * g.reach + 1, LIBHALO_EINVAL,
+             "box too small for the linking length (fewer than 2R+1 cells per side)");
+  HALO_CHECK((double)g.nc * (double)g.nc * (double)g.nc < 1.8e19, LIBHALO_EINVAL,
+             "cell grid exceeds 64-bit keys");
+  const int64_t nrow = g.nc * g.nc;
+  HALO_CHECK(nrow < 0xFFFFFFFFll, LIBHALO_EINVAL, "cell rows exceed 32-bit table");
+
+  Arena& A = ctx.ws;
+  A.reset();
+  auto* key0 = A.take<unsigned long long>(n);
+  auto* key1 = A.take<unsigned long long>(n);
+  auto* v0 = A.take<uint32_t>(n);
+  auto* v1 = A.take<uint32_t>(n);
+  T* xs = A.take<T>(n);
+  T* ys = A.take<T>(n);
+  T* zs = A.take<T>(n);
+  auto* cell_of = A.take<uint32_t>(n);
+  auto* hscan = A.take<uint32_t>(n + 1);
+  auto* cell_start = A.take<uint32_t>(n);
+  auto* cell_key = A.take<unsigned long long>(n);
+  auto* row_start = A.take<uint32_t>(nrow + 1);
+  auto* par = A.take<uint32_t>(n);
+  auto* minidx = A.take<uint32_t>(n);
+  auto* gsize = A.take<uint32_t>(n);
+  auto* cnt = A.take<uint32_t>(8);
+  void* rtmp = A.take<char>(radix_tmp_bytes(n));
+  uint32_t* stmp = A.take<uint32_t>(scan_tmp_elems<uint32_t>(n + 1));
+
+  const int TB = 256;
+  const unsigned nb = blocks_for(n, TB);
+  HALO_HIP(hipMemsetAsync(ctx.d_err, 0, sizeof(uint32_t), s));
+  k_cell_keys<T><<<nb, TB, 0, s>>>(x, y, z, n, g, key0, ctx.d_err);
+  k_iota<<<nb, TB, 0, s>>>(v0, n);
+  int kb = bits_for((unsigned long long)(g.nc * g.nc * g.nc - 1));
+  bool flip = radix_sort_pairs<unsigned long long>(key0, v0, key1, v1, n, kb, rtmp, s);
+  unsigned long long* skey = flip ? key1 : key0;
+  uint32_t* sperm = flip ? v1 : v0;
+  k_gather3<T><<<nb, TB, 0, s>>>(x, y, z, sperm, n, xs, ys, zs);
+  k_heads<<<nb, TB, 0, s>>>(skey, n, hscan);
+  exclusive_scan<uint32_t>(hscan, hscan, n, cnt, stmp, s);
+  k_cells<<<nb, TB, 0, s>>>(skey, hscan, n, cell_of, cell_start, cell_key);
+  // number of occupied cells = cnt[0] (exclusive scan of heads, total)
+  uint32_t* h = ctx.host_slot<uint32_t>(0);
+  HALO_HIP(hipMemcpyAsync(h, cnt, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipMemcpyAsync(h + 1, ctx.d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipStreamSynchronize(s));
+  HALO_CHECK((h[1] & kErrPosRange) == 0, LIBHALO_EINVAL, "a position lies outside [0, box)");
+  const int64_t ncell = h[0];
+  k_rows<<<blocks_for(nrow + 1, TB), TB, 0, s>>>(cell_key, ncell, g.nc, nrow, row_start);
+  k_iota<<<blocks_for(ncell, TB), TB, 0, s>>>(par, ncell);
+  for (int phase = 0; phase < 2; ++phase) {
+    k_link<T><<<blocks_for(ncell, 128), 128, 0, s>>>(xs, ys, zs, cell_start, cell_key,
+                                                       row_start, ncell, n, g, phase, par);
+    k_compress<<<blocks_for(ncell, TB), TB, 0, s>>>(par, ncell);
+  }
+  k_fill_u32<<<nb, TB, 0, s>>>(minidx, ncell, 0xFFFFFFFFu);
+  k_fill_u32<<<nb, TB, 0, s>>>(gsize, n, 0u);
+  k_minidx<<<nb, TB, 0, s>>>(cell_of, sperm, par, n, minidx);
+  k_labels<<<nb, TB, 0, s>>>(cell_of, sperm, par, minidx, n, label, gsize);
+  // members of groups with >= min_members, in input order, keyed by label
+  const uint32_t mm = (uint32_t)P.min_members;
+  k_member_flags<<<nb, TB, 0, s>>>(label, gsize, n, mm, v0);
+  exclusive_scan<uint32_t>(v0, hscan, n, cnt + 1, stmp, s);
+  uint32_t* mkey0 = reinterpret_cast<uint32_t*>(key0);
+  uint32_t* mkey1 = reinterpret_cast<uint32_t*>(key1);
+  k_member_compact<<<nb, TB, 0, s>>>(label, gsize, hscan, n, mm, mkey0, v0);
+  HALO_HIP(hipMemcpyAsync(h + 2, cnt + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipStreamSynchronize(s));
+  const int64_t m = h[2];
+  bool f2 = radix_sort_pairs<uint32_t>(mkey0, v0, mkey1, v1, m, bits_for((uint64_t)n), rtmp, s);
+  uint32_t* gkey = f2 ? mkey1 : mkey0;
+  uint32_t* gval = f2 ? v1 : v0;
+  if (m > 0) {
+    k_copy_u32<<<blocks_for(m, TB), TB, 0, s>>>(gval, perm_out, m);
+    k_group_heads<<<blocks_for(m, TB), TB, 0, s>>>(gkey, m, hscan);
+    exclusive_scan<uint32_t>(hscan, hscan, m, cnt + 2, stmp, s);
+    k_group_table<<<blocks_for(m, TB), TB, 0, s>>>(gkey, hscan, m, gsize, grp_first,
+                                                  grp_count, grp_cap);
+    HALO_HIP(hipMemcpyAsync(h + 3, cnt + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  } else {
+    h[3] = 0;
+  }
+  HALO_HIP(hipStreamSynchronize(s));
+  *n_members = m;
+  *n_groups = h[3];
+  HALO_CHECK(*n_groups <= grp_cap, LIBHALO_ECAPACITY, "group table too small");
+}
+
+}  // namespace
+
+size_t fof3d_workspace(const libhalo_params& P, int64_t n, int pos_dtype) {
+  const double ll = P.b * P.box / cbrt((double)n);
+  const double smax = ll / sqrt(3.0) * (1.0 - 1e-6);
+  int64_t nc = (int64_t)ceil(P.box / smax);
+  size_t tsz = pos_dtype == LIBHALO_F64 ? 8 : 4;
+  size_t b = 0;
+  auto add = [&](size_t bytes) { b += (bytes + 255) & ~size_t(255); };
+  add(8 * n); add(8 * n); add(4 * n); add(4 * n);
+  add(tsz * n); add(tsz * n); add(tsz * n);
+  add(4 * n); add(4 * (n + 1)); add(4 * n); add(8 * n);
+  add(4 * ((size_t)nc * nc + 1));
+  add(4 * n); add(4 * n); add(4 * n); add(32);
+  add(radix_tmp_bytes(n));
+  add(4 * scan_tmp_elems<uint32_t>(n + 1));
+  return b + 4096;
+}
+
+void fof3d(Ctx& ctx, int64_t n, int pos_dtype, const void* x, const void* y, const void* z,
+           uint32_t* label, uint32_t* perm, uint32_t* grp_first, uint32_t* grp_count,
+           int64_t grp_cap, int64_t* n_groups, int64_t* n_members, hipStream_t s) {
+  if (pos_dtype == LIBHALO_F64)
+    fof3d_impl<double>(ctx, n, (const double*)x, (const double*)y, (const double*)z, label,
+                       perm, grp_first, grp_count, grp_cap, n_groups, n_members, s);
+  else
+    fof3d_impl<float>(ctx, n, (const float*)x, (const float*)y, (const float*)z, label, perm,
+                      grp_first, grp_count, grp_cap, n_groups, n_members, s);
+}
+
+}  // namespace halo

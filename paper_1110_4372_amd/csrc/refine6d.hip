@@ -1,0 +1,870 @@
+// Recursive phase-space FOF hierarchy (Section 3.2 of the paper) on gfx950,
+// level-synchronous: every kernel of a level covers all nodes of that level.
+//
+// Per level, for each node (a subgroup of particles, contiguous in the level
+// array, ordered by input index):
+//   1. moments: exact fixed-point sums (positions about the node's anchor --
+//      its smallest-index particle -- and velocities), 128-bit accumulators;
+//   2. normalised FP32 coordinates (Eq. 1 metric);
+//   3. nearest-neighbour squared distance of every particle (LDS-tiled
+//      all-pairs within the node);
+//   4. ell^2 = k-th smallest of them, k = ceil(f n): radix selection on the
+//      FP32 bit patterns (in LDS for nodes <= 4096, multi-block above);
+//   5. 6D FOF at ell^2: union-find over level positions with CAS hooking;
+//   6. children = components of >= min_members: a stable radix sort by child
+//      id builds the next level's array in (parent, smallest index) order.
+#include <algorithm>
+
+#include "primitives.hpp"
+#include "stages.hpp"
+
+namespace halo {
+
+namespace {
+
+constexpr int TB = 256;
+constexpr int kMomTile = 1024;       // particles per moment work item
+constexpr int kPairI = 256;          // i particles per pair work item
+constexpr int kPairJ = 2048;         // j particles per pair work item
+constexpr int kSelSmall = 4096;      // nodes up to this size select in LDS
+constexpr int kSelTile = 4096;       // elements per big-node select item
+constexpr unsigned kPersist = 4096;  // persistent grid of pair / moment kernels
+
+struct LevelNodes {
+  uint32_t* first;
+  uint32_t* count;
+  int32_t* parent;  // global row of the parent, -1 at level 0
+  uint32_t* fof;
+  uint32_t* canon;
+};
+
+struct NodeScratch {
+  I128* acc;                 // 8 per node: sum qx, qy, qz, q^2, sum wx, wy, wz, w^2
+  unsigned long long* ext;   // 6 per node: ordered min/max of u per axis (level 0)
+  double* prm;               // 12 per node: anchor xyz, ubar xyz, vbar xyz, isx, isv, active
+  uint32_t* kth;             // target rank (1-based)
+  float* ell2;
+  uint32_t* whole;
+  uint32_t* nch;
+  uint32_t* fch;
+  uint32_t* wmom;            // worklist offsets (K+1)
+  uint32_t* wpair;
+  uint32_t* big;             // big-node list for selection
+  uint32_t* wbig;
+  uint32_t* selp;            // prefix / remaining per big node
+  uint32_t* ghist;           // 256 per big node
+};
+
+__device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint32_t w) {
+  // last k with off[k] <= w (off non-decreasing, off[0] = 0)
+  uint32_t lo = 0, hi = K;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= w)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------ level 0 ------
+__global__ void k_level0(const uint32_t* perm, const uint32_t* grp_first,
+                         const uint32_t* grp_count, uint32_t G, uint32_t M, uint32_t* lidx,
+                         uint32_t* lnode) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  lidx[m] = perm[m];
+  // groups are contiguous and in order: last g with first[g] <= m
+  uint32_t lo = 0, hi = G;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (grp_first[mid] <= m)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  lnode[m] = lo;
+}
+
+__global__ void k_level0_nodes(const uint32_t* perm, const uint32_t* grp_first,
+                               const uint32_t* grp_count, uint32_t G, LevelNodes nd) {
+  uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  nd.first[g] = grp_first[g];
+  nd.count[g] = grp_count[g];
+  nd.parent[g] = -1;
+  uint32_t lab = perm[grp_first[g]];
+  nd.fof[g] = lab;
+  nd.canon[g] = lab;
+}
+
+// ------------------------------------------------------------ moments ------
+__global__ void k_mom_items(const uint32_t* count, uint32_t K, uint32_t* items) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < K) items[k] = (count[k] + kMomTile - 1) / kMomTile;
+}
+
+template <class T>
+__global__ void __launch_bounds__(TB)
+    k_mom_accum(const T* x, const T* y, const T* z, const float* vx, const float* vy,
+                const float* vz, const uint32_t* lidx, LevelNodes nd, uint32_t K,
+                const uint32_t* woff, uint32_t w_begin_node, uint32_t w_end_node, double box,
+                int sx, int level0, NodeScratch sc, uint32_t* err) {
+  __shared__ I128 red[TB / kWave][8];
+  const uint32_t w0 = woff[w_begin_node], w1 = woff[w_end_node];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (uint32_t w = w0 + blockIdx.x; w < w1; w += gridDim.x) {
+    const uint32_t k = seg_of(woff, K, w);
+    const uint32_t t = w - woff[k];
+    const uint32_t first = nd.first[k], cnt = nd.count[k];
+    const uint32_t a = lidx[first];
+    const double xa[3] = {(double)x[a], (double)y[a], (double)z[a]};
+    I128 s[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s[q] = i128_from(0);
+    double umin[3] = {0, 0, 0}, umax[3] = {0, 0, 0};
+    uint32_t bad = 0;
+    for (uint32_t e = t * kMomTile + threadIdx.x; e < cnt && e < (t + 1) * kMomTile;
+         e += TB) {
+      const uint32_t i = lidx[first + e];
+      const double p[3] = {(double)x[i], (double)y[i], (double)z[i]};
+      const float v[3] = {vx[i], vy[i], vz[i]};
+      long long q[3], wq[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double u = min_image(p[c] - xa[c], box);
+        umin[c] = fmin(umin[c], u);
+        umax[c] = fmax(umax[c], u);
+        q[c] = quantise(u, sx);
+        if (!(fabsf(v[c]) < 65536.0f)) bad = 1;
+        wq[c] = quantise((double)v[c], kVelShift);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s[c] = i128_add(s[c], i128_from(q[c]));
+        s[4 + c] = i128_add(s[4 + c], i128_from(wq[c]));
+      }
+      s[3] = i128_add(s[3], i128_add(i128_sqr(q[0]), i128_add(i128_sqr(q[1]), i128_sqr(q[2]))));
+      s[7] = i128_add(s[7],
+                      i128_add(i128_sqr(wq[0]), i128_add(i128_sqr(wq[1]), i128_sqr(wq[2]))));
+    }
+    if (bad) atomicOr(err, kErrVelRange);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s[q] = wave_sum_i128(s[q]);
+    if (level0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double mn = umin[c], mx = umax[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          mn = fmin(mn, __shfl_xor(mn, o));
+          mx = fmax(mx, __shfl_xor(mx, o));
+        }
+        if (lane == 0) {
+          atomicMin(sc.ext + 6 * k + c, f64_ord(mn));
+          atomicMax(sc.ext + 6 * k + 3 + c, f64_ord(mx));
+        }
+      }
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) red[wid][q] = s[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+      I128 tot = red[0][threadIdx.x];
+      for (int ww = 1; ww < TB / kWave; ++ww) tot = i128_add(tot, red[ww][threadIdx.x]);
+      atomic_add_i128(sc.acc + 8 * k + threadIdx.x, tot);
+    }
+    __syncthreads();
+  }
+}
+
+// Mean and 3D variance from exact sums (same evaluation order as the
+// definition in the header comment of libhalo.h).
+__device__ void finish_moments(const I128* s, double n, int shift, double mean[3],
+                               double* var) {
+  double mq[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) mq[c] = i128_to_f64(s[c]) / n;
+  double s2q = i128_to_f64(s[3]) / n;
+  double t = mq[0] * mq[0];
+  t = __fma_rn(mq[1], mq[1], t);
+  t = __fma_rn(mq[2], mq[2], t);
+  double vq = s2q - t;
+  if (!(vq > 0.0)) vq = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) mean[c] = ldexp(mq[c], -shift);
+  *var = ldexp(vq, -2 * shift);
+}
+
+template <class T>
+__global__ void k_mom_final(const T* x, const T* y, const T* z, const uint32_t* lidx,
+                            LevelNodes nd, uint32_t k0, uint32_t k1, double box, int sx,
+                            int level0, double f, NodeScratch sc, double* mom_out,
+                            uint32_t* err) {
+  uint32_t k = k0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= k1) return;
+  const double n = (double)nd.count[k];
+  const uint32_t a = lidx[nd.first[k]];
+  const double xa[3] = {(double)x[a], (double)y[a], (double)z[a]};
+  double ubar[3], vbar[3], sx2, sv2;
+  finish_moments(sc.acc + 8 * k, n, sx, ubar, &sx2);
+  finish_moments(sc.acc + 8 * k + 4, n, kVelShift, vbar, &sv2);
+  if (level0) {
+    for (int c = 0; c < 3; ++c)
+      if (ord_f64(sc.ext[6 * k + 3 + c]) - ord_f64(sc.ext[6 * k + c]) >= 0.5 * box)
+        atomicOr(err, kErrGeometry);
+  }
+  double* mo = mom_out + 8 * (size_t)k;
+  for (int c = 0; c < 3; ++c) {
+    double cc = xa[c] + ubar[c];
+    if (cc < 0.0)
+      cc += box;
+    else if (cc >= box)
+      cc -= box;
+    mo[c] = cc;
+    mo[3 + c] = vbar[c];
+  }
+  mo[6] = sx2;
+  mo[7] = sv2;
+  double* pr = sc.prm + 12 * (size_t)k;
+  bool active = (sx2 > 0.0) && (sv2 > 0.0);
+  for (int c = 0; c < 3; ++c) {
+    pr[c] = xa[c];
+    pr[3 + c] = ubar[c];
+    pr[6 + c] = vbar[c];
+  }
+  pr[9] = active ? 1.0 / sqrt(sx2) : 0.0;
+  pr[10] = active ? 1.0 / sqrt(sv2) : 0.0;
+  pr[11] = active ? 1.0 : 0.0;
+  uint32_t kk = (uint32_t)ceil(f * n);
+  if (kk < 1) kk = 1;
+  if (kk > nd.count[k]) kk = nd.count[k];
+  sc.kth[k] = kk;
+  sc.ell2[k] = -1.0f;
+  sc.whole[k] = 0;
+  sc.nch[k] = 0;
+  sc.fch[k] = 0xFFFFFFFFu;
+}
+
+// Normalised coordinates, written as six FP32 planes of stride S.
+template <class T>
+__global__ void k_norm6(const T* x, const T* y, const T* z, const float* vx, const float* vy,
+                        const float* vz, const uint32_t* lidx, const uint32_t* lnode,
+                        uint32_t m0, uint32_t m1, double box, NodeScratch sc, float* xi,
+                        size_t S) {
+  uint32_t m = m0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= m1) return;
+  const uint32_t k = lnode[m];
+  const double* pr = sc.prm + 12 * (size_t)k;
+  if (pr[11] == 0.0) return;
+  const uint32_t i = lidx[m];
+  const double p[3] = {(double)x[i], (double)y[i], (double)z[i]};
+  const float v[3] = {vx[i], vy[i], vz[i]};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double u = min_image(p[c] - pr[c], box);
+    xi[(size_t)c * S + m] = (float)((u - pr[3 + c]) * pr[9]);
+    xi[(size_t)(3 + c) * S + m] = (float)(((double)v[c] - pr[6 + c]) * pr[10]);
+  }
+}
+
+// ------------------------------------------------------------ pair kernels --
+__global__ void k_pair_items(const uint32_t* count, const double* prm, uint32_t K,
+                             uint32_t* items) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  uint32_t n = count[k];
+  bool active = prm[12 * (size_t)k + 11] != 0.0;
+  items[k] = active ? ((n + kPairI - 1) / kPairI) * ((n + kPairJ - 1) / kPairJ) : 0u;
+}
+
+// Nearest-neighbour squared distance: D[i] = min_{j != i in node} d2(i, j).
+__global__ void __launch_bounds__(TB)
+    k_nn(const float* xi, size_t S, LevelNodes nd, uint32_t K, const uint32_t* woff,
+         uint32_t kb, uint32_t ke, uint32_t* D) {
+  __shared__ float t[6][TB];
+  const uint32_t w0 = woff[kb], w1 = woff[ke];
+  for (uint32_t w = w0 + blockIdx.x; w < w1; w += gridDim.x) {
+    const uint32_t k = seg_of(woff, K, w);
+    const uint32_t r = w - woff[k];
+    const uint32_t first = nd.first[k], n = nd.count[k];
+    const uint32_t tj = (n + kPairJ - 1) / kPairJ;
+    const uint32_t it = r / tj, jc = r % tj;
+    const uint32_t li = it * kPairI + threadIdx.x;
+    const bool ok = li < n;
+    const uint32_t gi = first + (ok ? li : 0);
+    float a[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a[c] = xi[(size_t)c * S + gi];
+    float best = __int_as_float(0x7F800000);
+    const uint32_t j0 = jc * kPairJ;
+    const uint32_t j1 = min(n, j0 + kPairJ);
+    for (uint32_t jt = j0; jt < j1; jt += TB) {
+      __syncthreads();
+      const uint32_t lj = jt + threadIdx.x;
+      if (lj < j1) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) t[c][threadIdx.x] = xi[(size_t)c * S + first + lj];
+      }
+      __syncthreads();
+      const uint32_t nt = min((uint32_t)TB, j1 - jt);
+      for (uint32_t q = 0; q < nt; ++q) {
+        float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], t[0][q], t[1][q], t[2][q],
+                       t[3][q], t[4][q], t[5][q]);
+        if (jt + q != li && d < best) best = d;
+      }
+    }
+    if (ok) atomicMin(D + gi, __float_as_uint(best));
+    __syncthreads();
+  }
+}
+
+// 6D FOF at ell^2 over pairs j > i; both particles must have a friend.
+__global__ void __launch_bounds__(TB)
+    k_fof6(const float* xi, size_t S, LevelNodes nd, uint32_t K, const uint32_t* woff,
+           uint32_t kb, uint32_t ke, const uint32_t* D, const float* ell2, uint32_t* par) {
+  __shared__ float t[6][TB];
+  __shared__ uint32_t troot[TB];
+  const uint32_t w0 = woff[kb], w1 = woff[ke];
+  const float qnan = __int_as_float(0x7FC00000);
+  for (uint32_t w = w0 + blockIdx.x; w < w1; w += gridDim.x) {
+    const uint32_t k = seg_of(woff, K, w);
+    const uint32_t r = w - woff[k];
+    const uint32_t first = nd.first[k], n = nd.count[k];
+    const uint32_t tj = (n + kPairJ - 1) / kPairJ;
+    const uint32_t it = r / tj, jc = r % tj;
+    const uint32_t i0 = it * kPairI;
+    const uint32_t j0 = jc * kPairJ;
+    const uint32_t j1 = min(n, j0 + kPairJ);
+    if (j1 <= i0 + 1) continue;  // uniform over the block: no pair with j > i
+    const float l2 = ell2[k];
+    const uint32_t li = i0 + threadIdx.x;
+    const bool ok = li < n && __uint_as_float(D[first + (li < n ? li : 0)]) <= l2;
+    const uint32_t gi = first + (li < n ? li : 0);
+    float a[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a[c] = xi[(size_t)c * S + gi];
+    uint32_t ri = ok ? uf_find(par, gi) : 0xFFFFFFFFu;
+    for (uint32_t jt = j0; jt < j1; jt += TB) {
+      __syncthreads();
+      const uint32_t lj = jt + threadIdx.x;
+      if (lj < j1) {
+        const uint32_t gj = first + lj;
+        const bool lj_ok = __uint_as_float(D[gj]) <= l2;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) t[c][threadIdx.x] = lj_ok ? xi[(size_t)c * S + gj] : qnan;
+        troot[threadIdx.x] = lj_ok ? uf_find(par, gj) : 0xFFFFFFFFu;
+      }
+      __syncthreads();
+      if (ok) {
+        const uint32_t nt = min((uint32_t)TB, j1 - jt);
+        for (uint32_t q = 0; q < nt; ++q) {
+          if (jt + q <= li) continue;
+          float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], t[0][q], t[1][q], t[2][q],
+                         t[3][q], t[4][q], t[5][q]);
+          if (d <= l2 && troot[q] != ri) {
+            uf_union(par, gi, first + jt + q);
+            ri = uf_find(par, gi);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ selection ----
+// ell^2 of nodes with at most kSelSmall particles: radix select in LDS.
+__global__ void __launch_bounds__(TB)
+    k_select_small(const uint32_t* D, LevelNodes nd, uint32_t k0, uint32_t k1,
+                   NodeScratch sc) {
+  __shared__ uint32_t v[kSelSmall];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t s_pre, s_k;
+  const uint32_t k = k0 + blockIdx.x;
+  if (k >= k1) return;
+  const uint32_t n = nd.count[k];
+  if (n > kSelSmall || sc.prm[12 * (size_t)k + 11] == 0.0) return;
+  const uint32_t first = nd.first[k];
+  for (uint32_t e = threadIdx.x; e < n; e += TB) v[e] = D[first + e];
+  if (threadIdx.x == 0) {
+    s_pre = 0;
+    s_k = sc.kth[k];
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 24 - 8 * pass;
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t pre = s_pre;
+    for (uint32_t e = threadIdx.x; e < n; e += TB) {
+      uint32_t b = v[e];
+      if (pass == 0 || (b >> (shift + 8)) == (pre >> (shift + 8)))
+        atomicAdd(&hist[(b >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t run = 0, kk = s_k;
+      for (uint32_t d = 0; d < 256; ++d) {
+        if (run + hist[d] >= kk) {
+          s_pre = pre | (d << shift);
+          s_k = kk - run;
+          break;
+        }
+        run += hist[d];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sc.ell2[k] = __uint_as_float(s_pre);
+}
+
+__global__ void k_big_flags(LevelNodes nd, uint32_t K, NodeScratch sc, uint32_t* flag) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  flag[k] = (nd.count[k] > kSelSmall && sc.prm[12 * (size_t)k + 11] != 0.0) ? 1u : 0u;
+}
+
+__global__ void k_big_list(const uint32_t* flag, const uint32_t* pos, uint32_t K,
+                           LevelNodes nd, NodeScratch sc) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  if (flag[k]) {
+    uint32_t b = pos[k];
+    sc.big[b] = k;
+    sc.wbig[b] = (nd.count[k] + kSelTile - 1) / kSelTile;
+    sc.selp[2 * b] = 0;
+    sc.selp[2 * b + 1] = sc.kth[k];
+  }
+}
+
+__global__ void k_zero_hist(NodeScratch sc, const uint32_t* nbig) {
+  uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  for (; e < 256u * nbig[0]; e += gridDim.x * blockDim.x) sc.ghist[e] = 0;
+}
+
+__global__ void __launch_bounds__(TB)
+    k_select_big_hist(const uint32_t* D, LevelNodes nd, NodeScratch sc, const uint32_t* nbig,
+                      int pass) {
+  __shared__ uint32_t hist[256];
+  const uint32_t B = nbig[0];
+  const uint32_t W = sc.wbig[B];  // total items (exclusive scan total)
+  const int shift = 24 - 8 * pass;
+  for (uint32_t w = blockIdx.x; w < W; w += gridDim.x) {
+    const uint32_t b = seg_of(sc.wbig, B, w);
+    const uint32_t t = w - sc.wbig[b];
+    const uint32_t k = sc.big[b];
+    const uint32_t first = nd.first[k], n = nd.count[k];
+    const uint32_t pre = sc.selp[2 * b];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t e = t * kSelTile + threadIdx.x; e < n && e < (t + 1) * kSelTile; e += TB) {
+      uint32_t bits = D[first + e];
+      if (pass == 0 || (bits >> (shift + 8)) == (pre >> (shift + 8)))
+        atomicAdd(&hist[(bits >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (hist[threadIdx.x]) atomicAdd(sc.ghist + 256 * (size_t)b + threadIdx.x, hist[threadIdx.x]);
+    __syncthreads();
+  }
+}
+
+__global__ void k_select_big_resolve(NodeScratch sc, const uint32_t* nbig, int pass) {
+  const uint32_t B = nbig[0];
+  const int shift = 24 - 8 * pass;
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < B;
+       b += gridDim.x * blockDim.x) {
+    uint32_t* h = sc.ghist + 256 * (size_t)b;
+    uint32_t run = 0, kk = sc.selp[2 * b + 1], pre = sc.selp[2 * b];
+    for (uint32_t d = 0; d < 256; ++d) {
+      uint32_t c = h[d];
+      h[d] = 0;
+      if (kk != 0 && run + c >= kk) {
+        pre |= d << shift;
+        kk = kk - run;
+        sc.selp[2 * b] = pre;
+        sc.selp[2 * b + 1] = kk;
+        kk = 0;  // found; keep clearing
+      }
+      run += c;
+    }
+    if (pass == 3) sc.ell2[sc.big[b]] = __uint_as_float(sc.selp[2 * b]);
+  }
+}
+
+// ------------------------------------------------------------ children -----
+__global__ void k_comp_size(const uint32_t* par, const uint32_t* lnode, uint32_t M,
+                            NodeScratch sc, uint32_t* csize) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  if (sc.prm[12 * (size_t)lnode[m] + 11] == 0.0) return;
+  atomicAdd(csize + par[m], 1u);
+}
+
+__global__ void k_whole(const uint32_t* par, const uint32_t* lnode, const uint32_t* csize,
+                        uint32_t M, LevelNodes nd, NodeScratch sc) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const uint32_t k = lnode[m];
+  if (sc.prm[12 * (size_t)k + 11] == 0.0) return;
+  if (par[m] == m && csize[m] == nd.count[k]) sc.whole[k] = 1u;
+}
+
+__global__ void k_child_flags(const uint32_t* par, const uint32_t* lnode,
+                              const uint32_t* csize, uint32_t M, uint32_t mm, NodeScratch sc,
+                              uint32_t* cflag, uint32_t* head) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const uint32_t k = lnode[m];
+  bool child = sc.prm[12 * (size_t)k + 11] != 0.0 && sc.whole[k] == 0 && csize[par[m]] >= mm;
+  cflag[m] = child ? 1u : 0u;
+  head[m] = (child && par[m] == m) ? 1u : 0u;
+}
+
+__global__ void k_child_nodes(const uint32_t* par, const uint32_t* lnode,
+                              const uint32_t* csize, const uint32_t* lidx,
+                              const uint32_t* hrank, const uint32_t* head, uint32_t M,
+                              LevelNodes nd, int32_t base, NodeScratch sc, LevelNodes nx,
+                              uint32_t* cid) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M || !head[m]) return;
+  const uint32_t k = lnode[m];
+  const uint32_t c = hrank[m];
+  nx.count[c] = csize[m];
+  nx.canon[c] = lidx[m];
+  nx.parent[c] = base + (int32_t)k;
+  nx.fof[c] = nd.fof[k];
+  cid[m] = c;
+  atomicAdd(sc.nch + k, 1u);
+  atomicMin(sc.fch + k, c);
+}
+
+__global__ void k_child_keys(const uint32_t* par, const uint32_t* cflag, const uint32_t* crank,
+                             const uint32_t* cid, uint32_t M, uint32_t* key, uint32_t* val) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M || !cflag[m]) return;
+  const uint32_t p = crank[m];
+  key[p] = cid[par[m]];
+  val[p] = m;
+}
+
+__global__ void k_next_level(const uint32_t* skey, const uint32_t* sval, const uint32_t* lidx,
+                             uint32_t M2, uint32_t* lidx2, uint32_t* lnode2) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= M2) return;
+  lidx2[q] = lidx[sval[q]];
+  lnode2[q] = skey[q];
+}
+
+__global__ void k_next_first(const uint32_t* skey, uint32_t M2, uint32_t* first2) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= M2) return;
+  if (q == 0 || skey[q] != skey[q - 1]) first2[skey[q]] = q;
+}
+
+__global__ void k_deepest(const uint32_t* lidx, const uint32_t* lnode, uint32_t M,
+                          int32_t base, int32_t* deepest) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  deepest[lidx[m]] = base + (int32_t)lnode[m];
+}
+
+__global__ void k_node_out(LevelNodes nd, uint32_t K, int32_t base, int32_t level,
+                           int32_t next_base, const double* mom, NodeScratch sc,
+                           libhalo_nodes out) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int64_t row = (int64_t)base + k;
+  if (row >= out.cap) return;
+  const bool active = sc.prm[12 * (size_t)k + 11] != 0.0;
+  const uint32_t nch = sc.nch[k];
+  uint32_t flags = 0;
+  if (nch == 0) flags |= LIBHALO_NODE_LEAF;
+  if (!active) flags |= LIBHALO_NODE_DEGENERATE;
+  if (sc.whole[k]) flags |= LIBHALO_NODE_WHOLE;
+  out.parent[row] = nd.parent[k];
+  out.level[row] = level;
+  out.first_child[row] = nch ? next_base + (int32_t)sc.fch[k] : -1;
+  out.n_children[row] = (int32_t)nch;
+  out.count[row] = nd.count[k];
+  out.canon[row] = nd.canon[k];
+  out.fof[row] = nd.fof[k];
+  out.flags[row] = flags;
+  const double* mo = mom + 8 * (size_t)k;
+  out.cx[row] = mo[0];
+  out.cy[row] = mo[1];
+  out.cz[row] = mo[2];
+  out.vx[row] = mo[3];
+  out.vy[row] = mo[4];
+  out.vz[row] = mo[5];
+  out.sx2[row] = mo[6];
+  out.sv2[row] = mo[7];
+  out.ell2[row] = active ? sc.ell2[k] : -1.0f;
+}
+
+__global__ void k_compress(uint32_t* par, uint32_t M) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < M) par[m] = uf_find(par, m);
+}
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_zero_node_scratch(NodeScratch sc, uint32_t K) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  for (int q = 0; q < 8; ++q) sc.acc[8 * (size_t)k + q] = I128{0ull, 0ll};
+  for (int c = 0; c < 3; ++c) {
+    sc.ext[6 * (size_t)k + c] = ~0ull;
+    sc.ext[6 * (size_t)k + 3 + c] = 0ull;
+  }
+}
+
+// ------------------------------------------------------------ driver -------
+struct Rd {  // small read-back helper on the pinned host block
+  Ctx& c;
+  hipStream_t s;
+  uint32_t* h;
+  uint32_t get(const uint32_t* d, int slot = 0) {
+    HALO_HIP(hipMemcpyAsync(h + slot, d, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HALO_HIP(hipStreamSynchronize(s));
+    return h[slot];
+  }
+};
+
+template <class T>
+void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const float* vx,
+                 const float* vy, const float* vz, const uint32_t* perm,
+                 const uint32_t* grp_first, const uint32_t* grp_count, int64_t G,
+                 libhalo_nodes* out, int32_t* deepest, int64_t* n_nodes, hipStream_t s) {
+  const libhalo_params& P = ctx.p;
+  const double box = P.box;
+  int e2 = 0;
+  frexp(0.5 * box, &e2);
+  const int sx = 40 - e2;
+  const bool plain = P.mode == LIBHALO_PLAIN;
+  Rd rd{ctx, s, ctx.host_slot<uint32_t>(0)};
+
+  k_fill_i32<<<blocks_for(n, TB), TB, 0, s>>>(deepest, n, -1);
+  *n_nodes = 0;
+  if (G == 0) {
+    HALO_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  // number of members = first + count of the last group
+  HALO_HIP(hipMemcpyAsync(rd.h, grp_first + G - 1, 4, hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipMemcpyAsync(rd.h + 1, grp_count + G - 1, 4, hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipStreamSynchronize(s));
+  const uint32_t M = rd.h[0] + rd.h[1];
+  const uint32_t Kmax = std::max<uint32_t>((uint32_t)G, M / (uint32_t)P.min_members + 1);
+
+  // workspace
+  size_t need = 0;
+  auto add = [&](size_t b) { need += (b + 255) & ~size_t(255); };
+  for (int q = 0; q < 4; ++q) add(4ull * M);         // lidx, lnode x2
+  add(4ull * 6 * M);                                 // xi planes
+  for (int q = 0; q < 8; ++q) add(4ull * (M + 1));   // D, par, csize, cflag, head, crank, hrank, cid
+  for (int q = 0; q < 4; ++q) add(4ull * (M + 1));   // sort key/val x2
+  add(radix_tmp_bytes(M));
+  add(4 * scan_tmp_elems<uint32_t>(M + 1));
+  for (int q = 0; q < 2; ++q) add(5 * 4ull * (Kmax + 1));  // level node arrays x2
+  add(16ull * 8 * Kmax);   // acc
+  add(8ull * 6 * Kmax);    // ext
+  add(8ull * 12 * Kmax);   // prm
+  add(8ull * 8 * Kmax);    // mom
+  for (int q = 0; q < 9; ++q) add(4ull * (Kmax + 2));  // kth ell2 whole nch fch wmom wpair big wbig
+  add(8ull * (M / kSelSmall + 2));                    // selp
+  add(4ull * 256 * (M / kSelSmall + 2));              // ghist
+  add(64);
+  ctx.ensure_ws(need + 65536);
+  Arena& A = ctx.ws;
+  A.reset();
+  uint32_t* lidx = A.take<uint32_t>(M);
+  uint32_t* lnode = A.take<uint32_t>(M);
+  uint32_t* lidx2 = A.take<uint32_t>(M);
+  uint32_t* lnode2 = A.take<uint32_t>(M);
+  float* xi = A.take<float>(6ull * M);
+  uint32_t* D = A.take<uint32_t>(M + 1);
+  uint32_t* par = A.take<uint32_t>(M + 1);
+  uint32_t* csize = A.take<uint32_t>(M + 1);
+  uint32_t* cflag = A.take<uint32_t>(M + 1);
+  uint32_t* head = A.take<uint32_t>(M + 1);
+  uint32_t* crank = A.take<uint32_t>(M + 1);
+  uint32_t* hrank = A.take<uint32_t>(M + 1);
+  uint32_t* cid = A.take<uint32_t>(M + 1);
+  uint32_t* k0 = A.take<uint32_t>(M + 1);
+  uint32_t* v0 = A.take<uint32_t>(M + 1);
+  uint32_t* k1 = A.take<uint32_t>(M + 1);
+  uint32_t* v1 = A.take<uint32_t>(M + 1);
+  void* rtmp = A.take<char>(radix_tmp_bytes(M));
+  uint32_t* stmp = A.take<uint32_t>(scan_tmp_elems<uint32_t>(M + 1));
+  LevelNodes L[2];
+  for (int q = 0; q < 2; ++q) {
+    L[q].first = A.take<uint32_t>(Kmax + 1);
+    L[q].count = A.take<uint32_t>(Kmax + 1);
+    L[q].parent = A.take<int32_t>(Kmax + 1);
+    L[q].fof = A.take<uint32_t>(Kmax + 1);
+    L[q].canon = A.take<uint32_t>(Kmax + 1);
+  }
+  NodeScratch sc;
+  sc.acc = A.take<I128>(8ull * Kmax);
+  sc.ext = A.take<unsigned long long>(6ull * Kmax);
+  sc.prm = A.take<double>(12ull * Kmax);
+  double* mom = A.take<double>(8ull * Kmax);
+  sc.kth = A.take<uint32_t>(Kmax + 2);
+  sc.ell2 = A.take<float>(Kmax + 2);
+  sc.whole = A.take<uint32_t>(Kmax + 2);
+  sc.nch = A.take<uint32_t>(Kmax + 2);
+  sc.fch = A.take<uint32_t>(Kmax + 2);
+  sc.wmom = A.take<uint32_t>(Kmax + 2);
+  sc.wpair = A.take<uint32_t>(Kmax + 2);
+  sc.big = A.take<uint32_t>(Kmax + 2);
+  sc.wbig = A.take<uint32_t>(Kmax + 2);
+  sc.selp = A.take<uint32_t>(2ull * (M / kSelSmall + 2));
+  sc.ghist = A.take<uint32_t>(256ull * (M / kSelSmall + 2));
+  uint32_t* dcnt = A.take<uint32_t>(16);
+
+  HALO_HIP(hipMemsetAsync(ctx.d_err, 0, sizeof(uint32_t), s));
+  k_level0<<<blocks_for(M, TB), TB, 0, s>>>(perm, grp_first, grp_count, (uint32_t)G, M, lidx,
+                                            lnode);
+  k_level0_nodes<<<blocks_for(G, TB), TB, 0, s>>>(perm, grp_first, grp_count, (uint32_t)G,
+                                                  L[0]);
+  uint32_t K = (uint32_t)G, Mi = M;
+  int cur = 0;
+  int32_t base = 0;
+  std::vector<uint32_t> hcount;
+  for (int level = 0; K > 0; ++level) {
+    HALO_CHECK(level < P.max_levels, LIBHALO_EINVAL, "hierarchy deeper than max_levels");
+    LevelNodes nd = L[cur], nx = L[cur ^ 1];
+    const size_t S = Mi;  // plane stride of xi for this level
+    const int level0 = level == 0;
+    k_zero_node_scratch<<<blocks_for(K, TB), TB, 0, s>>>(sc, K);
+    k_mom_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, K, sc.wmom);
+    exclusive_scan<uint32_t>(sc.wmom, sc.wmom, K, sc.wmom + K, stmp, s);
+    if (plain) {
+      hcount.resize(K);
+      HALO_HIP(hipMemcpyAsync(hcount.data(), nd.count, 4ull * K, hipMemcpyDeviceToHost, s));
+      HALO_HIP(hipStreamSynchronize(s));
+    }
+    // 1. moments
+    if (plain) {
+      for (uint32_t k = 0; k < K; ++k) {
+        unsigned g = (hcount[k] + kMomTile - 1) / kMomTile;
+        k_mom_accum<T><<<g, TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, nd, K, sc.wmom, k, k + 1,
+                                        box, sx, level0, sc, ctx.d_err);
+        k_mom_final<T><<<1, 64, 0, s>>>(x, y, z, lidx, nd, k, k + 1, box, sx, level0, P.f, sc,
+                                        mom, ctx.d_err);
+      }
+    } else {
+      k_mom_accum<T><<<kPersist, TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, nd, K, sc.wmom, 0, K,
+                                             box, sx, level0, sc, ctx.d_err);
+      k_mom_final<T><<<blocks_for(K, 128), 128, 0, s>>>(x, y, z, lidx, nd, 0, K, box, sx,
+                                                        level0, P.f, sc, mom, ctx.d_err);
+    }
+    if (level0) {
+      uint32_t e = rd.get(ctx.d_err, 2);
+      HALO_CHECK((e & kErrGeometry) == 0, LIBHALO_EGEOMETRY,
+                 "a FOF group spans half the box or more");
+      HALO_CHECK((e & kErrVelRange) == 0, LIBHALO_EINVAL, "a velocity is >= 2^16 km/s or NaN");
+    }
+    // 2. normalised coordinates
+    k_norm6<T><<<blocks_for(Mi, TB), TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, lnode, 0, Mi, box,
+                                                 sc, xi, S);
+    // 3. nearest neighbours; 5. union-find parents
+    k_fill_u32<<<blocks_for(Mi, TB), TB, 0, s>>>(D, Mi, 0x7F800000u);
+    k_iota<<<blocks_for(Mi, TB), TB, 0, s>>>(par, Mi);
+    k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, K, sc.wpair);
+    exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
+    if (plain) {
+      for (uint32_t k = 0; k < K; ++k) {
+        uint32_t nn = hcount[k];
+        unsigned g = ((nn + kPairI - 1) / kPairI) * ((nn + kPairJ - 1) / kPairJ);
+        k_nn<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, D);
+        if (nn <= (uint32_t)kSelSmall) k_select_small<<<1, TB, 0, s>>>(D, nd, k, k + 1, sc);
+      }
+    } else {
+      k_nn<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, D);
+      k_select_small<<<K, TB, 0, s>>>(D, nd, 0, K, sc);
+    }
+    // 4. selection for big nodes (both forms: a handful of nodes)
+    k_big_flags<<<blocks_for(K, TB), TB, 0, s>>>(nd, K, sc, cflag);
+    exclusive_scan<uint32_t>(cflag, head, K, dcnt, stmp, s);
+    k_big_list<<<blocks_for(K, TB), TB, 0, s>>>(cflag, head, K, nd, sc);
+    {
+      uint32_t nbig = rd.get(dcnt, 3);
+      if (nbig > 0) {
+        exclusive_scan<uint32_t>(sc.wbig, sc.wbig, nbig, sc.wbig + nbig, stmp, s);
+        k_zero_hist<<<64, TB, 0, s>>>(sc, dcnt);
+        for (int pass = 0; pass < 4; ++pass) {
+          k_select_big_hist<<<kPersist, TB, 0, s>>>(D, nd, sc, dcnt, pass);
+          k_select_big_resolve<<<blocks_for(nbig, 64), 64, 0, s>>>(sc, dcnt, pass);
+        }
+      }
+    }
+    // 5. 6D FOF
+    if (plain) {
+      for (uint32_t k = 0; k < K; ++k) {
+        uint32_t nn = hcount[k];
+        unsigned g = ((nn + kPairI - 1) / kPairI) * ((nn + kPairJ - 1) / kPairJ);
+        k_fof6<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, D, sc.ell2, par);
+      }
+    } else {
+      k_fof6<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, D, sc.ell2, par);
+    }
+    k_compress<<<blocks_for(Mi, TB), TB, 0, s>>>(par, Mi);
+    // 6. children
+    k_fill_u32<<<blocks_for(Mi, TB), TB, 0, s>>>(csize, Mi, 0u);
+    k_comp_size<<<blocks_for(Mi, TB), TB, 0, s>>>(par, lnode, Mi, sc, csize);
+    k_whole<<<blocks_for(Mi, TB), TB, 0, s>>>(par, lnode, csize, Mi, nd, sc);
+    k_child_flags<<<blocks_for(Mi, TB), TB, 0, s>>>(par, lnode, csize, Mi,
+                                                    (uint32_t)P.min_members, sc, cflag, head);
+    exclusive_scan<uint32_t>(head, hrank, Mi, dcnt, stmp, s);
+    exclusive_scan<uint32_t>(cflag, crank, Mi, dcnt + 1, stmp, s);
+    HALO_HIP(hipMemcpyAsync(rd.h + 4, dcnt, 8, hipMemcpyDeviceToHost, s));
+    HALO_HIP(hipStreamSynchronize(s));
+    const uint32_t K2 = rd.h[4], M2 = rd.h[5];
+    const int32_t next_base = base + (int32_t)K;
+    if (K2 > 0) {
+      k_child_nodes<<<blocks_for(Mi, TB), TB, 0, s>>>(par, lnode, csize, lidx, hrank, head, Mi,
+                                                      nd, base, sc, nx, cid);
+      k_child_keys<<<blocks_for(Mi, TB), TB, 0, s>>>(par, cflag, crank, cid, Mi, k0, v0);
+      bool f = radix_sort_pairs<uint32_t>(k0, v0, k1, v1, M2, bits_for(K2), rtmp, s);
+      uint32_t* sk = f ? k1 : k0;
+      uint32_t* sv = f ? v1 : v0;
+      k_next_level<<<blocks_for(M2, TB), TB, 0, s>>>(sk, sv, lidx, M2, lidx2, lnode2);
+      k_next_first<<<blocks_for(M2, TB), TB, 0, s>>>(sk, M2, nx.first);
+    }
+    k_deepest<<<blocks_for(Mi, TB), TB, 0, s>>>(lidx, lnode, Mi, base, deepest);
+    k_node_out<<<blocks_for(K, TB), TB, 0, s>>>(nd, K, base, level, next_base, mom, sc, *out);
+    base = next_base;
+    K = K2;
+    Mi = M2;
+    std::swap(lidx, lidx2);
+    std::swap(lnode, lnode2);
+    cur ^= 1;
+  }
+  HALO_HIP(hipStreamSynchronize(s));
+  *n_nodes = base;
+  HALO_CHECK(base <= out->cap, LIBHALO_ECAPACITY, "node table too small");
+}
+
+}  // namespace
+
+void refine6d(Ctx& ctx, int64_t n, int pos_dtype, const void* x, const void* y, const void* z,
+              const float* vx, const float* vy, const float* vz, const uint32_t* perm,
+              const uint32_t* grp_first, const uint32_t* grp_count, int64_t n_groups,
+              libhalo_nodes* nodes, int32_t* deepest, int64_t* n_nodes, hipStream_t s) {
+  if (pos_dtype == LIBHALO_F64)
+    refine_impl<double>(ctx, n, (const double*)x, (const double*)y, (const double*)z, vx, vy,
+                        vz, perm, grp_first, grp_count, n_groups, nodes, deepest, n_nodes, s);
+  else
+    refine_impl<float>(ctx, n, (const float*)x, (const float*)y, (const float*)z, vx, vy, vz,
+                       perm, grp_first, grp_count, n_groups, nodes, deepest, n_nodes, s);
+}
+
+}  // namespace halo
