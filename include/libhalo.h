@@ -162,6 +162,16 @@ int libhalo_set_params(libhalo_ctx* ctx, const libhalo_params* p);
 /* Version string of the library. */
 const char* libhalo_version(void);
 
+/* Kernel timing (tracing aid).  With profiling enabled, the library brackets
+ * its hot kernel launches with HIP events on the launch stream.
+ * libhalo_profile_read waits for those events and returns the summed device
+ * time (ms) and the number of launches of `kernel` (a kernel name such as
+ * "k_potential_f64") recorded since the last reset.  Errors: EINVAL, EHIP. */
+int libhalo_profile(libhalo_ctx* ctx, int enable);
+int libhalo_profile_reset(libhalo_ctx* ctx);
+int libhalo_profile_read(libhalo_ctx* ctx, const char* kernel, double* total_ms,
+                         int64_t* launches);
+
 /*
  * 3D friends-of-friends (Section 3.1), standard definition: particles i and
  * j are friends when their minimum-image separation is <= ll = b L / n^(1/3)

@@ -32,7 +32,25 @@ void Ctx::ensure_ws(size_t bytes) {
   ws.cap = want;
 }
 
+hipEvent_t Ctx::event() {
+  if (!spare.empty()) {
+    hipEvent_t e = spare.back();
+    spare.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HALO_HIP(hipEventCreate(&e));
+  return e;
+}
+
 void Ctx::release() {
+  for (auto& r : recs) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  for (auto e : spare) (void)hipEventDestroy(e);
+  recs.clear();
+  spare.clear();
   if (ws.base) (void)hipFree(ws.base);
   if (d_err) (void)hipFree(d_err);
   if (h_pinned) (void)hipHostFree(h_pinned);
@@ -131,6 +149,39 @@ int libhalo_set_params(libhalo_ctx* ctx, const libhalo_params* p) {
 }
 
 static bool dtype_ok(int d) { return d == LIBHALO_F32 || d == LIBHALO_F64; }
+
+int libhalo_profile(libhalo_ctx* ctx, int enable) {
+  return guarded(ctx, [&](halo::Ctx& c) { c.prof = enable != 0; });
+}
+
+int libhalo_profile_reset(libhalo_ctx* ctx) {
+  return guarded(ctx, [&](halo::Ctx& c) {
+    for (auto& r : c.recs) {
+      c.spare.push_back(r.e0);
+      c.spare.push_back(r.e1);
+    }
+    c.recs.clear();
+  });
+}
+
+int libhalo_profile_read(libhalo_ctx* ctx, const char* kernel, double* total_ms,
+                         int64_t* launches) {
+  return guarded(ctx, [&](halo::Ctx& c) {
+    HALO_CHECK(kernel && total_ms && launches, LIBHALO_EINVAL, "null pointer argument");
+    double t = 0.0;
+    int64_t k = 0;
+    for (auto& r : c.recs) {
+      if (std::strcmp(r.name, kernel) != 0) continue;
+      HALO_HIP(hipEventSynchronize(r.e1));
+      float ms = 0.f;
+      HALO_HIP(hipEventElapsedTime(&ms, r.e0, r.e1));
+      t += ms;
+      ++k;
+    }
+    *total_ms = t;
+    *launches = k;
+  });
+}
 
 int libhalo_fof3d(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, const void* y,
                   const void* z, uint32_t* fof_label, uint32_t* perm, uint32_t* grp_first,

@@ -1,0 +1,592 @@
+// Seeds, Poisson seed merging (Eq. 2), hierarchical particle assignment
+// (Eqs. 3-4) and the single-timestep host/subhalo relation (Sections 3.3-3.4)
+// on gfx950.
+//
+//  - seeds: one per leaf node, in node order;
+//  - merging: one wavefront per FOF group walks its seeds by decreasing size
+//    and compares each with the kept ones lane-parallel;
+//  - seed sets: every (ancestor, merged seed) pair of every leaf, sorted and
+//    made unique, gives the distinct halos below each node;
+//  - assignment, deepest level first: the particles a node holds outside its
+//    subgroups go to its only halo or to the Eq. 3 argmin, with sigma_v and
+//    vmax of each candidate halo recomputed from its current particles by a
+//    segmented radial sort (exact, order-independent reductions);
+//  - host/sub: one wavefront per FOF group over halos by decreasing size.
+#include <algorithm>
+#include <cmath>
+
+#include "primitives.hpp"
+#include "radial.hpp"
+#include "stages.hpp"
+
+namespace halo {
+
+namespace {
+
+constexpr int TB = 256;
+
+struct SeedT {  // internal seed table
+  uint32_t* cnt;
+  double* sx2;
+  double* sv2;
+};
+
+__global__ void k_leaf_flags(const int32_t* n_children, uint32_t NN, uint32_t* flag) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < NN) flag[k] = n_children[k] == 0 ? 1u : 0u;
+}
+
+__global__ void k_seeds(libhalo_nodes nd, uint32_t NN, const uint32_t* flag,
+                        const uint32_t* pos, libhalo_halos h, SeedT st, int32_t* node_seed) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= NN) return;
+  if (!flag[k]) {
+    node_seed[k] = -1;
+    return;
+  }
+  uint32_t s = pos[k];
+  node_seed[k] = (int32_t)s;
+  h.seed_node[s] = (int32_t)k;
+  h.fof[s] = nd.fof[k];
+  h.xs[s] = nd.cx[k];
+  h.ys[s] = nd.cy[k];
+  h.zs[s] = nd.cz[k];
+  h.vxs[s] = nd.vx[k];
+  h.vys[s] = nd.vy[k];
+  h.vzs[s] = nd.vz[k];
+  h.host[s] = -1;
+  st.cnt[s] = nd.count[k];
+  st.sx2[s] = nd.sx2[k];
+  st.sv2[s] = nd.sv2[k];
+}
+
+// key = fof * 2^32 + (2^32 - 1 - size): ascending key = (fof asc, size desc)
+__global__ void k_group_size_keys(const uint32_t* fof, const uint32_t* size, uint32_t S,
+                                  unsigned long long* key, uint32_t* val) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  key[s] = ((unsigned long long)fof[s] << 32) | (unsigned long long)(0xFFFFFFFFu - size[s]);
+  val[s] = s;
+}
+
+__global__ void k_fof_heads(const unsigned long long* key, uint32_t S, uint32_t* head) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= S) return;
+  head[q] = (q == 0 || (key[q] >> 32) != (key[q - 1] >> 32)) ? 1u : 0u;
+}
+
+__global__ void k_fof_segments(const uint32_t* head, const uint32_t* hpos, uint32_t S,
+                               uint32_t* seg_start) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= S) return;
+  if (head[q]) seg_start[hpos[q]] = q;
+}
+
+// Eq. 2 merging, one wavefront per FOF group.  kept[] holds, per group, the
+// kept seeds in visiting order (at the group's slice of ord).
+__global__ void k_merge(const uint32_t* ord, const uint32_t* seg_start, const uint32_t* nseg,
+                        uint32_t S, double box, double q2, libhalo_halos h, SeedT st,
+                        uint32_t* kept) {
+  const uint32_t F = nseg[0];
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= F) return;
+  const uint32_t a0 = seg_start[wave];
+  const uint32_t a1 = (wave + 1 < F) ? seg_start[wave + 1] : S;
+  uint32_t nk = 0;
+  for (uint32_t t = a0; t < a1; ++t) {
+    const uint32_t b = ord[t];
+    const double cb = (double)st.cnt[b], sx2 = st.sx2[b], sv2 = st.sv2[b];
+    double bq = INFINITY;
+    uint32_t best = 0xFFFFFFFFu;
+    if (sx2 > 0.0 && sv2 > 0.0) {
+      const double imx = cb / sx2, imv = cb / sv2;
+      for (uint32_t q = lane; q < nk; q += 64) {
+        const uint32_t a = kept[a0 + q];
+        double dx = min_image(h.xs[b] - h.xs[a], box);
+        double dy = min_image(h.ys[b] - h.ys[a], box);
+        double dz = min_image(h.zs[b] - h.zs[a], box);
+        double ux = h.vxs[b] - h.vxs[a], uy = h.vys[b] - h.vys[a], uz = h.vzs[b] - h.vzs[a];
+        double qq = __fma_rn(sq3(dx, dy, dz), imx, sq3(ux, uy, uz) * imv);
+        if (qq < bq || (qq == bq && a < best)) {
+          bq = qq;
+          best = a;
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        double oq = __shfl_xor(bq, o);
+        uint32_t ob = __shfl_xor(best, o);
+        if (oq < bq || (oq == bq && ob < best)) {
+          bq = oq;
+          best = ob;
+        }
+      }
+    }
+    if (best != 0xFFFFFFFFu && bq < q2) {
+      if (lane == 0) h.merged_into[b] = (int32_t)best;
+    } else {
+      if (lane == 0) {
+        h.merged_into[b] = (int32_t)b;
+        kept[a0 + nk] = b;
+      }
+      ++nk;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Pairs (ancestor node, merged halo) of every leaf.
+__global__ void k_pair_count(const libhalo_halos h, const libhalo_nodes nd, uint32_t S,
+                             uint32_t* cnt) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S) cnt[s] = (uint32_t)nd.level[h.seed_node[s]] + 1u;
+}
+
+__global__ void k_pair_emit(const libhalo_halos h, const libhalo_nodes nd, uint32_t S,
+                            const uint32_t* off, unsigned long long* key, uint32_t* val) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const unsigned long long mh = (unsigned long long)(uint32_t)h.merged_into[s];
+  uint32_t o = off[s];
+  for (int32_t k = h.seed_node[s]; k >= 0; k = nd.parent[k]) {
+    key[o] = ((unsigned long long)(uint32_t)k << 32) | mh;
+    val[o] = 0;
+    ++o;
+  }
+}
+
+__global__ void k_uniq_flags(const unsigned long long* key, uint32_t P, uint32_t* flag) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < P) flag[q] = (q == 0 || key[q] != key[q - 1]) ? 1u : 0u;
+}
+
+__global__ void k_uniq_write(const unsigned long long* key, const uint32_t* flag,
+                             const uint32_t* pos, uint32_t P, uint32_t* ids, uint32_t* soff) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P || !flag[q]) return;
+  const uint32_t u = pos[q];
+  const uint32_t node = (uint32_t)(key[q] >> 32);
+  ids[u] = (uint32_t)key[q];
+  if (q == 0 || (key[q] >> 32) != (key[q - 1] >> 32)) soff[node] = u;
+}
+
+// Own particles: deepest >= 0, keyed by node.
+__global__ void k_own_flags(const int32_t* deepest, uint32_t n, uint32_t* flag,
+                            uint32_t* ocnt) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t d = deepest[i];
+  flag[i] = d >= 0 ? 1u : 0u;
+  if (d >= 0) atomicAdd(ocnt + d, 1u);
+}
+
+__global__ void k_own_compact(const int32_t* deepest, const uint32_t* flag, const uint32_t* pos,
+                              uint32_t n, uint32_t* key, uint32_t* val) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  key[pos[i]] = (uint32_t)deepest[i];
+  val[pos[i]] = i;
+}
+
+__global__ void k_level_start(const int32_t* level, uint32_t NN, uint32_t* lstart) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= NN) return;
+  if (k == 0 || level[k] != level[k - 1]) lstart[level[k]] = k;
+}
+
+__global__ void k_multi_per_level(const int32_t* level, const uint32_t* soff, uint32_t NN,
+                                  uint32_t* lmulti) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= NN) return;
+  if (soff[k + 1] - soff[k] >= 2) atomicAdd(lmulti + level[k], 1u);
+}
+
+__global__ void k_mark_cand(const uint32_t* soff, const uint32_t* ids, uint32_t k0, uint32_t k1,
+                            uint32_t* cand) {
+  uint32_t k = k0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= k1) return;
+  if (soff[k + 1] - soff[k] < 2) return;
+  for (uint32_t q = soff[k]; q < soff[k + 1]; ++q) cand[ids[q]] = 1u;
+}
+
+// Assigned particles so far whose halo is a candidate: flag for compaction.
+__global__ void k_cand_flags(const uint32_t* own, uint32_t q0, uint32_t q1,
+                             const int32_t* halo_of, const uint32_t* cand, uint32_t* flag) {
+  uint32_t q = q0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= q1) return;
+  int32_t hh = halo_of[own[q]];
+  flag[q - q0] = (hh >= 0 && cand[hh]) ? 1u : 0u;
+}
+
+__global__ void k_cand_compact(const uint32_t* own, uint32_t q0, uint32_t q1,
+                               const int32_t* halo_of, const uint32_t* flag,
+                               const uint32_t* pos, uint32_t* seg, uint32_t* pidx) {
+  uint32_t q = q0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= q1 || !flag[q - q0]) return;
+  uint32_t i = own[q];
+  seg[pos[q - q0]] = (uint32_t)halo_of[i];
+  pidx[pos[q - q0]] = i;
+}
+
+struct Metric {
+  const double* xs;
+  const double* ys;
+  const double* zs;
+  const double* vxs;
+  const double* vys;
+  const double* vzs;
+  const double* sv2;
+  const double* vmax2;
+};
+
+template <class T>
+__global__ void k_assign_level(const T* x, const T* y, const T* z, const float* vx,
+                               const float* vy, const float* vz, double box, double cdyn,
+                               const uint32_t* own, const uint32_t* okey, uint32_t q0,
+                               uint32_t q1, const uint32_t* soff, const uint32_t* ids,
+                               Metric mt, int32_t* halo_of) {
+  uint32_t q = q0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= q1) return;
+  const uint32_t i = own[q], k = okey[q];
+  const uint32_t s0 = soff[k], s1 = soff[k + 1];
+  uint32_t best = ids[s0];
+  if (s1 - s0 > 1) {
+    const double px = (double)x[i], py = (double)y[i], pz = (double)z[i];
+    const double ux0 = (double)vx[i], uy0 = (double)vy[i], uz0 = (double)vz[i];
+    double bd = INFINITY;
+    for (uint32_t t = s0; t < s1; ++t) {
+      const uint32_t h = ids[t];
+      const double ird = cdyn / mt.vmax2[h];
+      const double isv = 1.0 / fmax(mt.sv2[h], 1e-300);
+      double dx = min_image(px - mt.xs[h], box), dy = min_image(py - mt.ys[h], box),
+             dz = min_image(pz - mt.zs[h], box);
+      double ux = ux0 - mt.vxs[h], uy = uy0 - mt.vys[h], uz = uz0 - mt.vzs[h];
+      double d = __fma_rn(sq3(dx, dy, dz), ird, sq3(ux, uy, uz) * isv);
+      if (d < bd) {  // ids ascending: ties keep the lower id
+        bd = d;
+        best = h;
+      }
+    }
+  }
+  halo_of[i] = (int32_t)best;
+}
+
+__global__ void k_count_assigned(const int32_t* halo_of, uint32_t n, uint32_t* na) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && halo_of[i] >= 0) atomicAdd(na + halo_of[i], 1u);
+}
+
+__global__ void k_all_assigned(const int32_t* halo_of, uint32_t n, uint32_t* flag) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = halo_of[i] >= 0 ? 1u : 0u;
+}
+
+__global__ void k_all_compact(const int32_t* halo_of, const uint32_t* flag, const uint32_t* pos,
+                              uint32_t n, uint32_t* seg, uint32_t* pidx) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  seg[pos[i]] = (uint32_t)halo_of[i];
+  pidx[pos[i]] = i;
+}
+
+__global__ void k_finish_halos(libhalo_halos h, uint32_t S, const uint32_t* na,
+                               const double* sv2, const double* vm2) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  h.n_assigned[s] = na[s];
+  bool kept = h.merged_into[s] == (int32_t)s;
+  h.sv2[s] = kept ? sv2[s] : 0.0;
+  h.vmax2[s] = kept ? vm2[s] : 0.0;
+}
+
+__global__ void k_kept_flags(const libhalo_halos h, uint32_t S, uint32_t* flag) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S) flag[s] = h.merged_into[s] == (int32_t)s ? 1u : 0u;
+}
+
+__global__ void k_kept_keys(const libhalo_halos h, uint32_t S, const uint32_t* flag,
+                            const uint32_t* pos, unsigned long long* key, uint32_t* val) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S || !flag[s]) return;
+  uint32_t p = pos[s];
+  key[p] = ((unsigned long long)h.fof[s] << 32) |
+           (unsigned long long)(0xFFFFFFFFu - h.n_assigned[s]);
+  val[p] = s;
+}
+
+// Host/sub relation, one wavefront per FOF group.
+__global__ void k_hostsub(const uint32_t* ord, const uint32_t* seg_start, const uint32_t* nseg,
+                          uint32_t KH, double box, double cdyn, libhalo_halos h) {
+  const uint32_t F = nseg[0];
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= F) return;
+  const uint32_t a0 = seg_start[wave];
+  const uint32_t a1 = (wave + 1 < F) ? seg_start[wave + 1] : KH;
+  for (uint32_t t = a0 + 1; t < a1; ++t) {
+    const uint32_t s = ord[t];
+    double bd = INFINITY;
+    uint32_t best = 0xFFFFFFFFu;
+    for (uint32_t u = a0 + lane; u < t; u += 64) {
+      const uint32_t H = ord[u];
+      const double ird = cdyn / h.vmax2[H];
+      const double isv = 1.0 / fmax(h.sv2[H], 1e-300);
+      double dx = min_image(h.xs[s] - h.xs[H], box), dy = min_image(h.ys[s] - h.ys[H], box),
+             dz = min_image(h.zs[s] - h.zs[H], box);
+      double ux = h.vxs[s] - h.vxs[H], uy = h.vys[s] - h.vys[H], uz = h.vzs[s] - h.vzs[H];
+      double d = __fma_rn(sq3(dx, dy, dz), ird, sq3(ux, uy, uz) * isv);
+      if (d < bd || (d == bd && H < best)) {
+        bd = d;
+        best = H;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      double od = __shfl_xor(bd, o);
+      uint32_t ob = __shfl_xor(best, o);
+      if (od < bd || (od == bd && ob < best)) {
+        bd = od;
+        best = ob;
+      }
+    }
+    if (lane == 0) h.host[s] = (int32_t)best;
+  }
+}
+
+__global__ void k_copy_one(const uint32_t* a, uint32_t* b) { *b = *a; }
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+template <class T>
+void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, const T* z,
+                 const float* vx, const float* vy, const float* vz, const libhalo_nodes& nd,
+                 int64_t NN, const int32_t* deepest, libhalo_halos& h, int32_t* halo_of,
+                 int64_t* n_halos, hipStream_t s) {
+  const libhalo_params& P = ctx.p;
+  const double box = P.box;
+  const double cdyn = (4.0 * M_PI / 3.0) * P.G * P.rho_vir;
+  const double Gm = P.G * P.particle_mass;
+  const double eps2 = P.softening * P.softening;
+  uint32_t* hb = ctx.host_slot<uint32_t>(0);
+  auto readu = [&](const uint32_t* d, int slot) {
+    HALO_HIP(hipMemcpyAsync(hb + slot, d, 4, hipMemcpyDeviceToHost, s));
+    HALO_HIP(hipStreamSynchronize(s));
+    return hb[slot];
+  };
+  k_fill_i32<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, n, -1);
+  *n_halos = 0;
+  if (NN == 0) {
+    HALO_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  // sizes known before any work: node count, deepest level, particle count
+  int32_t maxlev = 0;
+  HALO_HIP(hipMemcpyAsync(&maxlev, nd.level + NN - 1, 4, hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipStreamSynchronize(s));
+  const int nlev = maxlev + 1;
+  const int64_t NPmax = NN * (int64_t)nlev;  // (ancestor, leaf) pairs
+  struct W {
+    uint32_t *flag, *pos, *dcnt, *stmp, *cnt, *seg_start, *kept, *pcnt, *poff;
+    int32_t* node_seed;
+    double *sx2, *sv2, *cur_sv2, *cur_vm2;
+    unsigned long long *k64a, *k64b, *pk0, *pk1, *vm;
+    uint32_t *va, *vb, *pv0, *pv1, *pflag, *ppos, *soff, *ids, *ocnt, *iflag, *ipos;
+    uint32_t *ok0, *ov0, *ok1, *ov1, *ooff, *lstart, *lmulti, *cand, *na;
+    void *rtmp, *rtmp2;
+    I128* acc;
+    RadialBufs rb;
+  } w;
+  carve_workspace(ctx, [&](Arena& A) {
+    const int64_t K2 = NN + 2;
+    w.flag = A.take<uint32_t>(K2);
+    w.pos = A.take<uint32_t>(K2);
+    w.node_seed = A.take<int32_t>(K2);
+    w.dcnt = A.take<uint32_t>(16);
+    w.stmp = A.take<uint32_t>(scan_tmp_elems<uint32_t>(std::max<int64_t>(n, NPmax) + 2));
+    w.cnt = A.take<uint32_t>(K2);
+    w.sx2 = A.take<double>(K2);
+    w.sv2 = A.take<double>(K2);
+    w.k64a = A.take<unsigned long long>(K2);
+    w.k64b = A.take<unsigned long long>(K2);
+    w.va = A.take<uint32_t>(K2);
+    w.vb = A.take<uint32_t>(K2);
+    w.seg_start = A.take<uint32_t>(K2);
+    w.kept = A.take<uint32_t>(K2);
+    w.rtmp = A.take<char>(radix_tmp_bytes(std::max<int64_t>(NPmax, 1)));
+    w.pcnt = A.take<uint32_t>(K2);
+    w.poff = A.take<uint32_t>(K2);
+    w.pk0 = A.take<unsigned long long>(NPmax + 2);
+    w.pk1 = A.take<unsigned long long>(NPmax + 2);
+    w.pv0 = A.take<uint32_t>(NPmax + 2);
+    w.pv1 = A.take<uint32_t>(NPmax + 2);
+    w.pflag = A.take<uint32_t>(NPmax + 2);
+    w.ppos = A.take<uint32_t>(NPmax + 2);
+    w.soff = A.take<uint32_t>(K2);
+    w.ids = A.take<uint32_t>(NPmax + 2);
+    w.ocnt = A.take<uint32_t>(K2);
+    w.iflag = A.take<uint32_t>(n + 2);
+    w.ipos = A.take<uint32_t>(n + 2);
+    w.ok0 = A.take<uint32_t>(n + 2);
+    w.ov0 = A.take<uint32_t>(n + 2);
+    w.ok1 = A.take<uint32_t>(n + 2);
+    w.ov1 = A.take<uint32_t>(n + 2);
+    w.rtmp2 = A.take<char>(radix_tmp_bytes(n));
+    w.ooff = A.take<uint32_t>(K2);
+    w.lstart = A.take<uint32_t>(nlev + 2);
+    w.lmulti = A.take<uint32_t>(nlev + 2);
+    w.cand = A.take<uint32_t>(K2);
+    w.cur_sv2 = A.take<double>(K2);
+    w.cur_vm2 = A.take<double>(K2);
+    w.acc = A.take<I128>(4 * K2);
+    w.vm = A.take<unsigned long long>(K2);
+    w.na = A.take<uint32_t>(K2);
+    w.rb = radial_take(A, n, K2);
+  });
+  uint32_t *flag = w.flag, *pos = w.pos, *dcnt = w.dcnt, *stmp = w.stmp;
+  int32_t* node_seed = w.node_seed;
+  k_leaf_flags<<<blocks_for(NN, TB), TB, 0, s>>>(nd.n_children, (uint32_t)NN, flag);
+  exclusive_scan<uint32_t>(flag, pos, NN, dcnt, stmp, s);
+  const uint32_t S = readu(dcnt, 0);
+  *n_halos = S;
+  HALO_CHECK((int64_t)S <= h.cap, LIBHALO_ECAPACITY, "halo table too small");
+  SeedT st{w.cnt, w.sx2, w.sv2};
+  k_seeds<<<blocks_for(NN, TB), TB, 0, s>>>(nd, (uint32_t)NN, flag, pos, h, st, node_seed);
+
+  // ---- merging
+  unsigned long long *k64a = w.k64a, *k64b = w.k64b;
+  uint32_t *va = w.va, *vb = w.vb, *seg_start = w.seg_start, *kept = w.kept;
+  void* rtmp = w.rtmp;
+  k_group_size_keys<<<blocks_for(S, TB), TB, 0, s>>>(h.fof, st.cnt, S, k64a, va);
+  bool f = radix_sort_pairs<unsigned long long>(k64a, va, k64b, vb, S, 64, rtmp, s);
+  unsigned long long* skey = f ? k64b : k64a;
+  uint32_t* ord = f ? vb : va;
+  k_fof_heads<<<blocks_for(S, TB), TB, 0, s>>>(skey, S, flag);
+  exclusive_scan<uint32_t>(flag, pos, S, dcnt + 1, stmp, s);
+  k_fof_segments<<<blocks_for(S, TB), TB, 0, s>>>(flag, pos, S, seg_start);
+  const uint32_t F = readu(dcnt + 1, 1);
+  k_merge<<<blocks_for((int64_t)F * 64, TB), TB, 0, s>>>(ord, seg_start, dcnt + 1, S, box,
+                                                         P.merge_q2, h, st, kept);
+
+  // ---- seed sets per node
+  uint32_t *pcnt = w.pcnt, *poff = w.poff;
+  k_pair_count<<<blocks_for(S, TB), TB, 0, s>>>(h, nd, S, pcnt);
+  exclusive_scan<uint32_t>(pcnt, poff, S, poff + S, stmp, s);
+  const uint32_t NP = readu(poff + S, 2);
+  HALO_CHECK((int64_t)NP <= NPmax, LIBHALO_EINVAL, "seed-set pairs exceed their bound");
+  unsigned long long *pk0 = w.pk0, *pk1 = w.pk1;
+  uint32_t *pv0 = w.pv0, *pv1 = w.pv1, *pflag = w.pflag, *ppos = w.ppos;
+  k_pair_emit<<<blocks_for(S, TB), TB, 0, s>>>(h, nd, S, poff, pk0, pv0);
+  bool fp = radix_sort_pairs<unsigned long long>(pk0, pv0, pk1, pv1, NP,
+                                                 32 + bits_for((uint64_t)NN), rtmp, s);
+  unsigned long long* psk = fp ? pk1 : pk0;
+  k_uniq_flags<<<blocks_for(NP, TB), TB, 0, s>>>(psk, NP, pflag);
+  exclusive_scan<uint32_t>(pflag, ppos, NP, dcnt + 2, stmp, s);
+  uint32_t *soff = w.soff, *ids = w.ids;
+  k_uniq_write<<<blocks_for(NP, TB), TB, 0, s>>>(psk, pflag, ppos, NP, ids, soff);
+  k_copy_one<<<1, 1, 0, s>>>(dcnt + 2, soff + NN);
+
+  // ---- own particles per node, sorted by node then index
+  uint32_t *ocnt = w.ocnt, *iflag = w.iflag, *ipos = w.ipos;
+  uint32_t *ok0 = w.ok0, *ov0 = w.ov0, *ok1 = w.ok1, *ov1 = w.ov1;
+  void* rtmp2 = w.rtmp2;
+  k_fill_u32<<<blocks_for(NN + 1, TB), TB, 0, s>>>(ocnt, NN + 1, 0u);
+  k_own_flags<<<blocks_for(n, TB), TB, 0, s>>>(deepest, (uint32_t)n, iflag, ocnt);
+  exclusive_scan<uint32_t>(iflag, ipos, n, dcnt + 3, stmp, s);
+  k_own_compact<<<blocks_for(n, TB), TB, 0, s>>>(deepest, iflag, ipos, (uint32_t)n, ok0, ov0);
+  const uint32_t M = readu(dcnt + 3, 4);
+  bool fo = radix_sort_pairs<uint32_t>(ok0, ov0, ok1, ov1, M, bits_for((uint64_t)NN), rtmp2, s);
+  uint32_t* okey = fo ? ok1 : ok0;
+  uint32_t* own = fo ? ov1 : ov0;
+  uint32_t* ooff = w.ooff;
+  exclusive_scan<uint32_t>(ocnt, ooff, NN, ooff + NN, stmp, s);
+
+  // ---- levels
+  uint32_t *lstart = w.lstart, *lmulti = w.lmulti;
+  k_level_start<<<blocks_for(NN, TB), TB, 0, s>>>(nd.level, (uint32_t)NN, lstart);
+  k_fill_u32<<<1, 64, 0, s>>>(lmulti, nlev + 1, 0u);
+  k_multi_per_level<<<blocks_for(NN, TB), TB, 0, s>>>(nd.level, soff, (uint32_t)NN, lmulti);
+  std::vector<uint32_t> hls(nlev + 1), hlm(nlev + 1), hoo(NN + 1);
+  HALO_HIP(hipMemcpyAsync(hls.data(), lstart, 4ull * nlev, hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipMemcpyAsync(hlm.data(), lmulti, 4ull * nlev, hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipMemcpyAsync(hoo.data(), ooff, 4ull * (NN + 1), hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipStreamSynchronize(s));
+  hls[nlev] = (uint32_t)NN;
+
+  uint32_t *cand = w.cand, *na = w.na;
+  double *cur_sv2 = w.cur_sv2, *cur_vm2 = w.cur_vm2;
+  I128* acc = w.acc;
+  unsigned long long* vm = w.vm;
+  RadialBufs& rb = w.rb;
+  Metric cur{h.xs, h.ys, h.zs, h.vxs, h.vys, h.vzs, cur_sv2, cur_vm2};
+  for (int lev = maxlev; lev >= 0; --lev) {
+    const uint32_t k0 = hls[lev], k1 = hls[lev + 1];
+    const uint32_t q0 = hoo[k0], q1 = hoo[k1];  // own particles of this level
+    if (hlm[lev] > 0) {
+      k_fill_u32<<<blocks_for(S, TB), TB, 0, s>>>(cand, S, 0u);
+      k_mark_cand<<<blocks_for(k1 - k0, TB), TB, 0, s>>>(soff, ids, k0, k1, cand);
+      // particles assigned so far: own particles of deeper levels
+      const uint32_t a0 = q1, a1 = hoo[NN];
+      uint32_t m = 0;
+      if (a1 > a0) {
+        k_cand_flags<<<blocks_for(a1 - a0, TB), TB, 0, s>>>(own, a0, a1, halo_of, cand, iflag);
+        exclusive_scan<uint32_t>(iflag, ipos, a1 - a0, dcnt + 4, stmp, s);
+        k_cand_compact<<<blocks_for(a1 - a0, TB), TB, 0, s>>>(own, a0, a1, halo_of, iflag,
+                                                              ipos, rb.seg, rb.pidx);
+        m = readu(dcnt + 4, 5);
+      }
+      radial_sort(pos_dtype, x, y, z, box, h.xs, h.ys, h.zs, m, S, rb, s);
+      radial_sigma_vmax(vx, vy, vz, m, S, rb, Gm, eps2, acc, vm, cur_sv2, cur_vm2, s);
+    }
+    if (q1 > q0)
+      k_assign_level<T><<<blocks_for(q1 - q0, TB), TB, 0, s>>>(
+          x, y, z, vx, vy, vz, box, cdyn, own, okey, q0, q1, soff, ids, cur, halo_of);
+  }
+
+  // ---- final metric of every halo from all its particles
+  k_fill_u32<<<blocks_for(S, TB), TB, 0, s>>>(na, S, 0u);
+  k_count_assigned<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, (uint32_t)n, na);
+  k_all_assigned<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, (uint32_t)n, iflag);
+  exclusive_scan<uint32_t>(iflag, ipos, n, dcnt + 5, stmp, s);
+  k_all_compact<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, iflag, ipos, (uint32_t)n, rb.seg,
+                                                 rb.pidx);
+  const uint32_t MA = readu(dcnt + 5, 6);
+  radial_sort(pos_dtype, x, y, z, box, h.xs, h.ys, h.zs, MA, S, rb, s);
+  radial_sigma_vmax(vx, vy, vz, MA, S, rb, Gm, eps2, acc, vm, cur_sv2, cur_vm2, s);
+  k_finish_halos<<<blocks_for(S, TB), TB, 0, s>>>(h, S, na, cur_sv2, cur_vm2);
+
+  // ---- host/sub relation
+  k_kept_flags<<<blocks_for(S, TB), TB, 0, s>>>(h, S, flag);
+  exclusive_scan<uint32_t>(flag, pos, S, dcnt + 6, stmp, s);
+  k_kept_keys<<<blocks_for(S, TB), TB, 0, s>>>(h, S, flag, pos, k64a, va);
+  const uint32_t KH = readu(dcnt + 6, 7);
+  bool fk = radix_sort_pairs<unsigned long long>(k64a, va, k64b, vb, KH, 64, rtmp, s);
+  unsigned long long* kk = fk ? k64b : k64a;
+  uint32_t* kord = fk ? vb : va;
+  k_fof_heads<<<blocks_for(KH, TB), TB, 0, s>>>(kk, KH, flag);
+  exclusive_scan<uint32_t>(flag, pos, KH, dcnt + 7, stmp, s);
+  k_fof_segments<<<blocks_for(KH, TB), TB, 0, s>>>(flag, pos, KH, seg_start);
+  const uint32_t FH = readu(dcnt + 7, 8);
+  k_hostsub<<<blocks_for((int64_t)FH * 64, TB), TB, 0, s>>>(kord, seg_start, dcnt + 7, KH, box,
+                                                             cdyn, h);
+  HALO_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+void assign(Ctx& ctx, int64_t n, int pos_dtype, const void* x, const void* y, const void* z,
+            const float* vx, const float* vy, const float* vz, const libhalo_nodes* nodes,
+            int64_t n_nodes, const int32_t* deepest, libhalo_halos* halos, int32_t* halo_of,
+            int64_t* n_halos, hipStream_t s) {
+  if (pos_dtype == LIBHALO_F64)
+    assign_impl<double>(ctx, n, pos_dtype, (const double*)x, (const double*)y,
+                        (const double*)z, vx, vy, vz, *nodes, n_nodes, deepest, *halos,
+                        halo_of, n_halos, s);
+  else
+    assign_impl<float>(ctx, n, pos_dtype, (const float*)x, (const float*)y, (const float*)z,
+                       vx, vy, vz, *nodes, n_nodes, deepest, *halos, halo_of, n_halos, s);
+}
+
+}  // namespace halo

@@ -45,24 +45,46 @@ enum : uint32_t {
 struct Arena {
   char* base = nullptr;
   size_t cap = 0, off = 0;
-  size_t high = 0;  // largest request seen
+  bool counting = false;  // dry run: only sums the sizes of the takes
   void reset() { off = 0; }
   template <class T>
   T* take(size_t count) {
     size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
-    if (off + bytes > cap) {
-      high = off + bytes > high ? off + bytes : high;
-      throw Error{LIBHALO_ENOMEM, "workspace exhausted"};  // caller grows and retries
+    if (counting) {
+      off += bytes;
+      return reinterpret_cast<T*>(uintptr_t(256));
     }
+    if (off + bytes > cap) throw Error{LIBHALO_ENOMEM, "workspace exhausted"};
     T* p = reinterpret_cast<T*>(base + off);
     off += bytes;
-    if (off > high) high = off;
     return p;
   }
 };
 
+// Runs carve(arena) once to size the workspace, grows it, then carves for real.
+template <class Ctx_, class F>
+void carve_workspace(Ctx_& ctx, F&& carve) {
+  Arena dry;
+  dry.counting = true;
+  carve(dry);
+  ctx.ensure_ws(dry.off + 4096);
+  ctx.ws.reset();
+  carve(ctx.ws);
+}
+
+// Kernel timing: when enabled, instrumented launches are bracketed by HIP
+// events on their stream; read back and summed per kernel name on request.
+struct ProfRec {
+  const char* name;
+  hipEvent_t e0, e1;
+};
+
 struct Ctx {
   libhalo_params p{};
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> spare;
+  hipEvent_t event();
   int device = 0;
   std::string err;
   Arena ws;
@@ -74,6 +96,20 @@ struct Ctx {
   template <class T>
   T* host_slot(int i) { return reinterpret_cast<T*>(static_cast<char*>(h_pinned) + 64 * i); }
 };
+
+// Bracket a launch with events when profiling is on.
+#define HALO_PROF(ctx, nm, strm, ...)                               \
+  do {                                                              \
+    if ((ctx).prof) {                                               \
+      ::halo::ProfRec r_{nm, (ctx).event(), (ctx).event()};         \
+      HALO_HIP(hipEventRecord(r_.e0, strm));                        \
+      __VA_ARGS__;                                                  \
+      HALO_HIP(hipEventRecord(r_.e1, strm));                        \
+      (ctx).recs.push_back(r_);                                     \
+    } else {                                                        \
+      __VA_ARGS__;                                                  \
+    }                                                               \
+  } while (0)
 
 // ------------------------------------------------------------ launch -----
 inline unsigned blocks_for(int64_t n, int threads) {

@@ -299,8 +299,8 @@ void fof3d_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, uint32_
   k_rows<<<blocks_for(nrow + 1, TB), TB, 0, s>>>(cell_key, ncell, g.nc, nrow, row_start);
   k_iota<<<blocks_for(ncell, TB), TB, 0, s>>>(par, ncell);
   for (int phase = 0; phase < 2; ++phase) {
-    k_link<T><<<blocks_for(ncell, 128), 128, 0, s>>>(xs, ys, zs, cell_start, cell_key,
-                                                       row_start, ncell, n, g, phase, par);
+    HALO_PROF(ctx, "k_link", s, k_link<T><<<blocks_for(ncell, 128), 128, 0, s>>>(xs, ys, zs, cell_start, cell_key,
+                                                       row_start, ncell, n, g, phase, par));
     k_compress<<<blocks_for(ncell, TB), TB, 0, s>>>(par, ncell);
   }
   k_fill_u32<<<nb, TB, 0, s>>>(minidx, ncell, 0xFFFFFFFFu);

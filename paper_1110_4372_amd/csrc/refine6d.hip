@@ -755,14 +755,14 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     if (plain) {
       for (uint32_t k = 0; k < K; ++k) {
         unsigned g = (hcount[k] + kMomTile - 1) / kMomTile;
-        k_mom_accum<T><<<g, TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, nd, K, sc.wmom, k, k + 1,
-                                        box, sx, level0, sc, ctx.d_err);
+        HALO_PROF(ctx, "k_mom_accum", s, k_mom_accum<T><<<g, TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, nd, K, sc.wmom, k, k + 1,
+                                        box, sx, level0, sc, ctx.d_err));
         k_mom_final<T><<<1, 64, 0, s>>>(x, y, z, lidx, nd, k, k + 1, box, sx, level0, P.f, sc,
                                         mom, ctx.d_err);
       }
     } else {
-      k_mom_accum<T><<<kPersist, TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, nd, K, sc.wmom, 0, K,
-                                             box, sx, level0, sc, ctx.d_err);
+      HALO_PROF(ctx, "k_mom_accum", s, k_mom_accum<T><<<kPersist, TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, nd, K, sc.wmom, 0, K,
+                                             box, sx, level0, sc, ctx.d_err));
       k_mom_final<T><<<blocks_for(K, 128), 128, 0, s>>>(x, y, z, lidx, nd, 0, K, box, sx,
                                                         level0, P.f, sc, mom, ctx.d_err);
     }
@@ -784,12 +784,12 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       for (uint32_t k = 0; k < K; ++k) {
         uint32_t nn = hcount[k];
         unsigned g = ((nn + kPairI - 1) / kPairI) * ((nn + kPairJ - 1) / kPairJ);
-        k_nn<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, D);
-        if (nn <= (uint32_t)kSelSmall) k_select_small<<<1, TB, 0, s>>>(D, nd, k, k + 1, sc);
+        HALO_PROF(ctx, "k_nn", s, k_nn<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, D));
+        if (nn <= (uint32_t)kSelSmall) HALO_PROF(ctx, "k_select_small", s, k_select_small<<<1, TB, 0, s>>>(D, nd, k, k + 1, sc));
       }
     } else {
-      k_nn<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, D);
-      k_select_small<<<K, TB, 0, s>>>(D, nd, 0, K, sc);
+      HALO_PROF(ctx, "k_nn", s, k_nn<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, D));
+      HALO_PROF(ctx, "k_select_small", s, k_select_small<<<K, TB, 0, s>>>(D, nd, 0, K, sc));
     }
     // 4. selection for big nodes (both forms: a handful of nodes)
     k_big_flags<<<blocks_for(K, TB), TB, 0, s>>>(nd, K, sc, cflag);
@@ -811,10 +811,10 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       for (uint32_t k = 0; k < K; ++k) {
         uint32_t nn = hcount[k];
         unsigned g = ((nn + kPairI - 1) / kPairI) * ((nn + kPairJ - 1) / kPairJ);
-        k_fof6<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, D, sc.ell2, par);
+        HALO_PROF(ctx, "k_fof6", s, k_fof6<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, D, sc.ell2, par));
       }
     } else {
-      k_fof6<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, D, sc.ell2, par);
+      HALO_PROF(ctx, "k_fof6", s, k_fof6<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, D, sc.ell2, par));
     }
     k_compress<<<blocks_for(Mi, TB), TB, 0, s>>>(par, Mi);
     // 6. children

@@ -1,0 +1,559 @@
+// Single-pass unbinding (Section 3.5.3) with an exact direct-sum potential in
+// place of the paper's tree code (Appendix B), on gfx950.
+//
+// Layout: the kept halos of each FOF group are laid out in depth-first
+// preorder of the host/subhalo forest, each halo's own particles in input
+// order, so S(h) -- the halo with all its subhaloes -- is one contiguous range
+// [slot_h, slot_h + |S(h)|) and its own particles are the range's head.
+// Coordinates are unwrapped once about the FOF group's anchor particle, so
+// pair separations need no minimum image (groups span less than L/2).
+//
+// Potential: one work item = 256 own particles of a halo; the block streams
+// the halo's S(h) through LDS in tiles and each thread sums its particle's
+// terms in a fixed order.  FP64 form: FP64 terms 1/sqrt(r^2 + eps^2).  Mixed
+// form: FP32 halo-local coordinates and compensated FP32 sums, FP64 recheck
+// of particles whose energy lies within e_recheck of zero.
+#include <algorithm>
+#include <cmath>
+
+#include "primitives.hpp"
+#include "stages.hpp"
+
+namespace halo {
+
+namespace {
+
+constexpr int TB = 256;
+constexpr unsigned kPersist = 4096;
+
+__global__ void k_kept_host_keys(const libhalo_halos h, uint32_t S, uint32_t* flag) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  flag[s] = (h.merged_into[s] == (int32_t)s && h.host[s] >= 0) ? 1u : 0u;
+}
+
+__global__ void k_child_compact(const libhalo_halos h, uint32_t S, const uint32_t* flag,
+                                const uint32_t* pos, uint32_t* key, uint32_t* val,
+                                uint32_t* ccnt) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S || !flag[s]) return;
+  key[pos[s]] = (uint32_t)h.host[s];
+  val[pos[s]] = s;
+  atomicAdd(ccnt + h.host[s], 1u);
+}
+
+// nS[a] += n_assigned[h] for h and every ancestor a of h; depth[h].
+__global__ void k_subtree_sizes(const libhalo_halos h, uint32_t S, uint32_t* nS,
+                                uint32_t* depth) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  if (h.merged_into[s] != (int32_t)s) {
+    depth[s] = 0xFFFFFFFFu;
+    return;
+  }
+  const uint32_t na = h.n_assigned[s];
+  uint32_t d = 0;
+  atomicAdd(nS + s, na);
+  for (int32_t a = h.host[s]; a >= 0; a = h.host[a]) {
+    atomicAdd(nS + a, na);
+    ++d;
+  }
+  depth[s] = d;
+}
+
+__global__ void k_root_flags(const uint32_t* depth, const uint32_t* nS, uint32_t S,
+                             uint32_t* val) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S) val[s] = depth[s] == 0 ? nS[s] : 0u;
+}
+
+__global__ void k_root_slots(const uint32_t* depth, const uint32_t* scan, uint32_t S,
+                             uint32_t* slot) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S && depth[s] == 0) slot[s] = scan[s];
+}
+
+// Children of halos at depth d get their slots: after the parent's own
+// particles, siblings in increasing id.
+__global__ void k_child_slots(const libhalo_halos h, const uint32_t* depth, uint32_t S,
+                              uint32_t d, const uint32_t* coff, const uint32_t* cids,
+                              const uint32_t* nS, uint32_t* slot) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S || depth[s] != d) return;
+  uint32_t o = slot[s] + h.n_assigned[s];
+  for (uint32_t q = coff[s]; q < coff[s + 1]; ++q) {
+    uint32_t c = cids[q];
+    slot[c] = o;
+    o += nS[c];
+  }
+}
+
+__global__ void k_assigned_flags(const int32_t* halo_of, uint32_t n, uint32_t* flag) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = halo_of[i] >= 0 ? 1u : 0u;
+}
+
+__global__ void k_assigned_compact(const int32_t* halo_of, const uint32_t* flag,
+                                   const uint32_t* pos, uint32_t n, uint32_t* key,
+                                   uint32_t* val) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  key[pos[i]] = (uint32_t)halo_of[i];
+  val[pos[i]] = i;
+}
+
+__global__ void k_group_first(const uint32_t* key, uint32_t m, uint32_t* gfirst) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  if (q == 0 || key[q] != key[q - 1]) gfirst[key[q]] = q;
+}
+
+// Layout arrays: particle index, unwrapped FP64 coordinates, velocities.
+template <class T>
+__global__ void k_layout(const T* x, const T* y, const T* z, const float* vx, const float* vy,
+                         const float* vz, double box, const libhalo_halos h,
+                         const uint32_t* key, const uint32_t* val, const uint32_t* gfirst,
+                         const uint32_t* slot, uint32_t m, uint32_t* lp, double* ux, double* uy,
+                         double* uz, float* lvx, float* lvy, float* lvz, uint32_t* lhalo) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const uint32_t hh = key[q], i = val[q];
+  const uint32_t p = slot[hh] + (q - gfirst[hh]);
+  const uint32_t a = h.fof[hh];
+  lp[p] = i;
+  lhalo[p] = hh;
+  ux[p] = min_image((double)x[i] - (double)x[a], box);
+  uy[p] = min_image((double)y[i] - (double)y[a], box);
+  uz[p] = min_image((double)z[i] - (double)z[a], box);
+  lvx[p] = vx[i];
+  lvy[p] = vy[i];
+  lvz[p] = vz[i];
+}
+
+__global__ void k_zero_acc(I128* acc, uint32_t* nb, uint32_t S) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  for (int c = 0; c < 3; ++c) acc[3 * (size_t)s + c] = I128{0ull, 0ll};
+  nb[s] = 0;
+}
+
+// Exact velocity sums of each halo's own particles.
+__global__ void k_own_vsum(const float* lvx, const float* lvy, const float* lvz,
+                           const uint32_t* lhalo, uint32_t m, I128* acc) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = q < m;
+  const uint32_t hh = ok ? lhalo[q] : 0xFFFFFFFFu;
+  I128 v[3];
+  v[0] = i128_from(ok ? quantise((double)lvx[q], kVelShift) : 0);
+  v[1] = i128_from(ok ? quantise((double)lvy[q], kVelShift) : 0);
+  v[2] = i128_from(ok ? quantise((double)lvz[q], kVelShift) : 0);
+  const uint32_t h0 = __shfl(hh, 0);
+  if (__all(hh == h0) && h0 != 0xFFFFFFFFu) {
+    for (int c = 0; c < 3; ++c) v[c] = wave_sum_i128(v[c]);
+    if ((threadIdx.x & 63) == 0)
+      for (int c = 0; c < 3; ++c) atomic_add_i128(acc + 3 * (size_t)h0 + c, v[c]);
+  } else if (ok) {
+    for (int c = 0; c < 3; ++c) atomic_add_i128(acc + 3 * (size_t)hh + c, v[c]);
+  }
+}
+
+// Adds each halo's own sums to every ancestor's S(h) sums.
+__global__ void k_chain_vsum(const libhalo_halos h, uint32_t S, const I128* own, I128* accS) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S || h.merged_into[s] != (int32_t)s) return;
+  for (int c = 0; c < 3; ++c) {
+    I128 v = own[3 * (size_t)s + c];
+    atomic_add_i128(accS + 3 * (size_t)s + c, v);
+    for (int32_t a = h.host[s]; a >= 0; a = h.host[a]) atomic_add_i128(accS + 3 * (size_t)a + c, v);
+  }
+}
+
+__global__ void k_vbulk(const I128* accS, const uint32_t* nS, uint32_t S, double* vb) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  double n = (double)nS[s];
+  for (int c = 0; c < 3; ++c)
+    vb[3 * (size_t)s + c] =
+        nS[s] ? ldexp(i128_to_f64(accS[3 * (size_t)s + c]) / n, -kVelShift) : 0.0;
+}
+
+__global__ void k_pot_items(const libhalo_halos h, uint32_t S, uint32_t* items) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  items[s] = h.merged_into[s] == (int32_t)s ? (h.n_assigned[s] + TB - 1) / TB : 0u;
+}
+
+__device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint32_t w) {
+  uint32_t lo = 0, hi = K;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= w)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// FP64 direct sum: sum_j 1/sqrt(r^2 + eps^2) over S(h), j != i.
+__global__ void __launch_bounds__(TB)
+    k_potential_f64(const double* ux, const double* uy, const double* uz, const libhalo_halos h,
+                    uint32_t S, const uint32_t* slot, const uint32_t* nS, const uint32_t* woff,
+                    uint32_t kb, uint32_t ke, double eps2, double* sum) {
+  __shared__ double tx[TB], ty[TB], tz[TB];
+  const uint32_t w0 = woff[kb], w1 = woff[ke];
+  for (uint32_t w = w0 + blockIdx.x; w < w1; w += gridDim.x) {
+    const uint32_t hh = seg_of(woff, S, w);
+    const uint32_t it = w - woff[hh];
+    const uint32_t base = slot[hh], nown = h.n_assigned[hh], ns = nS[hh];
+    const uint32_t li = it * TB + threadIdx.x;
+    const bool ok = li < nown;
+    const uint32_t qi = base + (ok ? li : 0);
+    const double xi = ux[qi], yi = uy[qi], zi = uz[qi];
+    double acc = 0.0;
+    for (uint32_t jt = 0; jt < ns; jt += TB) {
+      __syncthreads();
+      if (jt + threadIdx.x < ns) {
+        tx[threadIdx.x] = ux[base + jt + threadIdx.x];
+        ty[threadIdx.x] = uy[base + jt + threadIdx.x];
+        tz[threadIdx.x] = uz[base + jt + threadIdx.x];
+      }
+      __syncthreads();
+      const uint32_t nt = min((uint32_t)TB, ns - jt);
+      for (uint32_t q = 0; q < nt; ++q) {
+        double dx = tx[q] - xi, dy = ty[q] - yi, dz = tz[q] - zi;
+        double r2 = sq3(dx, dy, dz) + eps2;
+        double t = 1.0 / sqrt(r2);
+        acc += (jt + q != li) ? t : 0.0;
+      }
+    }
+    if (ok) sum[qi] = acc;
+    __syncthreads();
+  }
+}
+
+// Mixed precision: FP32 coordinates relative to the halo's first particle,
+// FP32 rsqrt terms, Kahan-compensated FP32 sum per thread.
+__global__ void __launch_bounds__(TB)
+    k_potential_f32(const double* ux, const double* uy, const double* uz, const libhalo_halos h,
+                    uint32_t S, const uint32_t* slot, const uint32_t* nS, const uint32_t* woff,
+                    uint32_t kb, uint32_t ke, float eps2, double* sum) {
+  __shared__ float tx[TB], ty[TB], tz[TB];
+  const uint32_t w0 = woff[kb], w1 = woff[ke];
+  for (uint32_t w = w0 + blockIdx.x; w < w1; w += gridDim.x) {
+    const uint32_t hh = seg_of(woff, S, w);
+    const uint32_t it = w - woff[hh];
+    const uint32_t base = slot[hh], nown = h.n_assigned[hh], ns = nS[hh];
+    const double ox = ux[base], oy = uy[base], oz = uz[base];
+    const uint32_t li = it * TB + threadIdx.x;
+    const bool ok = li < nown;
+    const uint32_t qi = base + (ok ? li : 0);
+    const float xi = (float)(ux[qi] - ox), yi = (float)(uy[qi] - oy), zi = (float)(uz[qi] - oz);
+    float acc = 0.0f, comp = 0.0f;
+    for (uint32_t jt = 0; jt < ns; jt += TB) {
+      __syncthreads();
+      if (jt + threadIdx.x < ns) {
+        tx[threadIdx.x] = (float)(ux[base + jt + threadIdx.x] - ox);
+        ty[threadIdx.x] = (float)(uy[base + jt + threadIdx.x] - oy);
+        tz[threadIdx.x] = (float)(uz[base + jt + threadIdx.x] - oz);
+      }
+      __syncthreads();
+      const uint32_t nt = min((uint32_t)TB, ns - jt);
+      float part = 0.0f;
+      for (uint32_t q = 0; q < nt; ++q) {
+        float dx = tx[q] - xi, dy = ty[q] - yi, dz = tz[q] - zi;
+        float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2)));
+        float t = __frsqrt_rn(r2);
+        part += (jt + q != li) ? t : 0.0f;
+      }
+      // Kahan step per tile
+      float yk = part - comp;
+      float tk = acc + yk;
+      comp = (tk - acc) - yk;
+      acc = tk;
+    }
+    if (ok) sum[qi] = (double)acc - (double)comp;
+    __syncthreads();
+  }
+}
+
+// FP64 recheck of one particle's potential (mixed form), one block per particle.
+__global__ void __launch_bounds__(TB)
+    k_recheck(const double* ux, const double* uy, const double* uz, const uint32_t* lhalo,
+              const uint32_t* slot, const uint32_t* nS, const uint32_t* list,
+              const uint32_t* nlist, double eps2, double* sum) {
+  __shared__ double red[TB];
+  const uint32_t L = nlist[0];
+  for (uint32_t t = blockIdx.x; t < L; t += gridDim.x) {
+    const uint32_t qi = list[t];
+    const uint32_t hh = lhalo[qi];
+    const uint32_t base = slot[hh], ns = nS[hh];
+    const double xi = ux[qi], yi = uy[qi], zi = uz[qi];
+    double acc = 0.0;
+    for (uint32_t j = threadIdx.x; j < ns; j += TB) {
+      if (base + j == qi) continue;
+      double dx = ux[base + j] - xi, dy = uy[base + j] - yi, dz = uz[base + j] - zi;
+      acc += 1.0 / sqrt(sq3(dx, dy, dz) + eps2);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = TB / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) sum[qi] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_energy(const double* sum, const float* lvx, const float* lvy,
+                         const float* lvz, const uint32_t* lhalo, const uint32_t* lp,
+                         const double* vb, uint32_t m, double mGm, double e_rel, int mixed,
+                         uint8_t* bound, double* phi, uint32_t* nb_own, uint32_t* rlist,
+                         uint32_t* nr) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const uint32_t hh = lhalo[q], i = lp[q];
+  const double ph = mGm * sum[q];
+  const double ux = (double)lvx[q] - vb[3 * (size_t)hh], uy = (double)lvy[q] - vb[3 * (size_t)hh + 1],
+               uz = (double)lvz[q] - vb[3 * (size_t)hh + 2];
+  const double k = 0.5 * sq3(ux, uy, uz);
+  const double e = k + ph;
+  if (mixed && fabs(e) < e_rel * (k + fabs(ph))) {
+    rlist[atomicAdd(nr, 1u)] = q;
+    return;  // decided after the FP64 recheck
+  }
+  const uint8_t b = e < 0.0;
+  bound[i] = b;
+  if (phi) phi[i] = ph;
+  if (b) atomicAdd(nb_own + hh, 1u);
+}
+
+__global__ void k_energy_list(const double* sum, const float* lvx, const float* lvy,
+                              const float* lvz, const uint32_t* lhalo, const uint32_t* lp,
+                              const double* vb, const uint32_t* list, const uint32_t* nlist,
+                              double mGm, uint8_t* bound, double* phi, uint32_t* nb_own) {
+  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nlist[0]) return;
+  const uint32_t q = list[t];
+  const uint32_t hh = lhalo[q], i = lp[q];
+  const double ph = mGm * sum[q];
+  const double ux = (double)lvx[q] - vb[3 * (size_t)hh], uy = (double)lvy[q] - vb[3 * (size_t)hh + 1],
+               uz = (double)lvz[q] - vb[3 * (size_t)hh + 2];
+  const double e = 0.5 * sq3(ux, uy, uz) + ph;
+  const uint8_t b = e < 0.0;
+  bound[i] = b;
+  if (phi) phi[i] = ph;
+  if (b) atomicAdd(nb_own + hh, 1u);
+}
+
+__global__ void k_unbind_out(const libhalo_halos h, uint32_t S, const uint32_t* nS,
+                             const uint32_t* nb_own, const double* vb, double ut,
+                             libhalo_unbound o, uint32_t* nbS) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const bool kept = h.merged_into[s] == (int32_t)s;
+  o.n_bound_own[s] = kept ? nb_own[s] : 0u;
+  o.n_s[s] = kept ? nS[s] : 0u;
+  o.vbx[s] = kept ? vb[3 * (size_t)s] : 0.0;
+  o.vby[s] = kept ? vb[3 * (size_t)s + 1] : 0.0;
+  o.vbz[s] = kept ? vb[3 * (size_t)s + 2] : 0.0;
+  if (kept) {
+    uint32_t b = nb_own[s];
+    atomicAdd(nbS + s, b);
+    for (int32_t a = h.host[s]; a >= 0; a = h.host[a]) atomicAdd(nbS + a, b);
+  }
+}
+
+__global__ void k_valid(const libhalo_halos h, uint32_t S, const uint32_t* nS,
+                        const uint32_t* nbS, double ut, libhalo_unbound o) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const bool kept = h.merged_into[s] == (int32_t)s;
+  o.n_bound_s[s] = kept ? nbS[s] : 0u;
+  o.valid[s] = kept && ((double)nbS[s] >= ut * (double)nS[s]) ? 1 : 0;
+}
+
+__global__ void k_init_particles(uint8_t* bound, double* phi, uint32_t n) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bound[i] = 0;
+  if (phi) phi[i] = 0.0;
+}
+
+template <class T>
+void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const float* vx,
+                 const float* vy, const float* vz, const libhalo_halos& h, int64_t S64,
+                 const int32_t* halo_of, uint8_t* bound, double* phi, libhalo_unbound& o,
+                 hipStream_t s) {
+  const libhalo_params& P = ctx.p;
+  const uint32_t S = (uint32_t)S64;
+  const double box = P.box;
+  const double eps2 = P.softening * P.softening;
+  const double mGm = -P.G * P.particle_mass;
+  const bool mixed = P.prec == LIBHALO_PREC_MIXED;
+  const bool plain = P.mode == LIBHALO_PLAIN;
+  uint32_t* hb = ctx.host_slot<uint32_t>(0);
+  auto readu = [&](const uint32_t* d, int slot) {
+    HALO_HIP(hipMemcpyAsync(hb + slot, d, 4, hipMemcpyDeviceToHost, s));
+    HALO_HIP(hipStreamSynchronize(s));
+    return hb[slot];
+  };
+  k_init_particles<<<blocks_for(n, TB), TB, 0, s>>>(bound, phi, (uint32_t)n);
+  if (S == 0) {
+    HALO_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  struct W {
+    uint32_t *flag, *pos, *ck0, *cv0, *ck1, *cv1, *ccnt, *coff, *nS, *depth, *slot, *rootv,
+        *dcnt, *stmp, *ak0, *av0, *ak1, *av1, *gfirst, *lp, *lhalo, *woff, *nb_own, *nbS,
+        *rlist;
+    double *ux, *uy, *uz, *vb, *sum;
+    float *lvx, *lvy, *lvz;
+    I128 *accO, *accS;
+    void *rtmp;
+  } w;
+  carve_workspace(ctx, [&](Arena& A) {
+    const int64_t S2 = S + 2, N2 = n + 2;
+    w.flag = A.take<uint32_t>(std::max(S2, N2));
+    w.pos = A.take<uint32_t>(std::max(S2, N2));
+    w.ck0 = A.take<uint32_t>(S2);
+    w.cv0 = A.take<uint32_t>(S2);
+    w.ck1 = A.take<uint32_t>(S2);
+    w.cv1 = A.take<uint32_t>(S2);
+    w.ccnt = A.take<uint32_t>(S2);
+    w.coff = A.take<uint32_t>(S2);
+    w.nS = A.take<uint32_t>(S2);
+    w.depth = A.take<uint32_t>(S2);
+    w.slot = A.take<uint32_t>(S2);
+    w.rootv = A.take<uint32_t>(S2);
+    w.dcnt = A.take<uint32_t>(16);
+    w.stmp = A.take<uint32_t>(scan_tmp_elems<uint32_t>(std::max(S2, N2)));
+    w.ak0 = A.take<uint32_t>(N2);
+    w.av0 = A.take<uint32_t>(N2);
+    w.ak1 = A.take<uint32_t>(N2);
+    w.av1 = A.take<uint32_t>(N2);
+    w.gfirst = A.take<uint32_t>(S2);
+    w.lp = A.take<uint32_t>(N2);
+    w.lhalo = A.take<uint32_t>(N2);
+    w.woff = A.take<uint32_t>(S2);
+    w.nb_own = A.take<uint32_t>(S2);
+    w.nbS = A.take<uint32_t>(S2);
+    w.rlist = A.take<uint32_t>(N2);
+    w.ux = A.take<double>(N2);
+    w.uy = A.take<double>(N2);
+    w.uz = A.take<double>(N2);
+    w.vb = A.take<double>(3 * S2);
+    w.sum = A.take<double>(N2);
+    w.lvx = A.take<float>(N2);
+    w.lvy = A.take<float>(N2);
+    w.lvz = A.take<float>(N2);
+    w.accO = A.take<I128>(3 * S2);
+    w.accS = A.take<I128>(3 * S2);
+    w.rtmp = A.take<char>(radix_tmp_bytes(std::max(S2, N2)));
+  });
+  // children lists of the host/sub forest, ascending ids per host
+  k_kept_host_keys<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.flag);
+  exclusive_scan<uint32_t>(w.flag, w.pos, S, w.dcnt, w.stmp, s);
+  k_fill_u32<<<blocks_for(S + 1, TB), TB, 0, s>>>(w.ccnt, S + 1, 0u);
+  k_child_compact<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.flag, w.pos, w.ck0, w.cv0, w.ccnt);
+  const uint32_t NC = readu(w.dcnt, 0);
+  bool fc = radix_sort_pairs<uint32_t>(w.ck0, w.cv0, w.ck1, w.cv1, NC, bits_for(S), w.rtmp, s);
+  uint32_t* cids = fc ? w.cv1 : w.cv0;
+  exclusive_scan<uint32_t>(w.ccnt, w.coff, S, w.coff + S, w.stmp, s);
+  // subtree sizes, depths, preorder slots
+  k_fill_u32<<<blocks_for(S, TB), TB, 0, s>>>(w.nS, S, 0u);
+  k_subtree_sizes<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, w.depth);
+  k_root_flags<<<blocks_for(S, TB), TB, 0, s>>>(w.depth, w.nS, S, w.rootv);
+  exclusive_scan<uint32_t>(w.rootv, w.rootv, S, w.dcnt + 1, w.stmp, s);
+  k_root_slots<<<blocks_for(S, TB), TB, 0, s>>>(w.depth, w.rootv, S, w.slot);
+  // deepest host chain: bounded by the number of kept halos; stop when no child
+  uint32_t maxd = 0;
+  {
+    std::vector<uint32_t> hd(S);
+    HALO_HIP(hipMemcpyAsync(hd.data(), w.depth, 4ull * S, hipMemcpyDeviceToHost, s));
+    HALO_HIP(hipStreamSynchronize(s));
+    for (uint32_t v : hd)
+      if (v != 0xFFFFFFFFu && v > maxd) maxd = v;
+  }
+  for (uint32_t d = 0; d < maxd; ++d)
+    k_child_slots<<<blocks_for(S, TB), TB, 0, s>>>(h, w.depth, S, d, w.coff, cids, w.nS, w.slot);
+  // particles in layout order
+  k_assigned_flags<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, (uint32_t)n, w.flag);
+  exclusive_scan<uint32_t>(w.flag, w.pos, n, w.dcnt + 2, w.stmp, s);
+  k_assigned_compact<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, w.flag, w.pos, (uint32_t)n,
+                                                      w.ak0, w.av0);
+  const uint32_t m = readu(w.dcnt + 2, 1);
+  bool fa = radix_sort_pairs<uint32_t>(w.ak0, w.av0, w.ak1, w.av1, m, bits_for(S), w.rtmp, s);
+  uint32_t* akey = fa ? w.ak1 : w.ak0;
+  uint32_t* aval = fa ? w.av1 : w.av0;
+  if (m > 0) {
+    k_group_first<<<blocks_for(m, TB), TB, 0, s>>>(akey, m, w.gfirst);
+    k_layout<T><<<blocks_for(m, TB), TB, 0, s>>>(x, y, z, vx, vy, vz, box, h, akey, aval,
+                                                 w.gfirst, w.slot, m, w.lp, w.ux, w.uy, w.uz,
+                                                 w.lvx, w.lvy, w.lvz, w.lhalo);
+  }
+  // bulk velocities of S(h)
+  k_zero_acc<<<blocks_for(S, TB), TB, 0, s>>>(w.accO, w.nb_own, S);
+  k_zero_acc<<<blocks_for(S, TB), TB, 0, s>>>(w.accS, w.nbS, S);
+  if (m > 0) k_own_vsum<<<blocks_for(m, TB), TB, 0, s>>>(w.lvx, w.lvy, w.lvz, w.lhalo, m, w.accO);
+  k_chain_vsum<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.accO, w.accS);
+  k_vbulk<<<blocks_for(S, TB), TB, 0, s>>>(w.accS, w.nS, S, w.vb);
+  // potentials
+  k_pot_items<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.woff);
+  exclusive_scan<uint32_t>(w.woff, w.woff, S, w.woff + S, w.stmp, s);
+  if (m > 0) {
+    if (plain) {
+      std::vector<uint32_t> ho(S + 1);
+      HALO_HIP(hipMemcpyAsync(ho.data(), w.woff, 4ull * (S + 1), hipMemcpyDeviceToHost, s));
+      HALO_HIP(hipStreamSynchronize(s));
+      for (uint32_t hh = 0; hh < S; ++hh) {
+        uint32_t g = ho[hh + 1] - ho[hh];
+        if (!g) continue;
+        if (mixed)
+          HALO_PROF(ctx, "k_potential_f32", s, k_potential_f32<<<g, TB, 0, s>>>(w.ux, w.uy, w.uz, h, S, w.slot, w.nS, w.woff, hh,
+                                           hh + 1, (float)eps2, w.sum));
+        else
+          HALO_PROF(ctx, "k_potential_f64", s, k_potential_f64<<<g, TB, 0, s>>>(w.ux, w.uy, w.uz, h, S, w.slot, w.nS, w.woff, hh,
+                                           hh + 1, eps2, w.sum));
+      }
+    } else if (mixed) {
+      HALO_PROF(ctx, "k_potential_f32", s, k_potential_f32<<<kPersist, TB, 0, s>>>(w.ux, w.uy, w.uz, h, S, w.slot, w.nS, w.woff, 0, S,
+                                              (float)eps2, w.sum));
+    } else {
+      HALO_PROF(ctx, "k_potential_f64", s, k_potential_f64<<<kPersist, TB, 0, s>>>(w.ux, w.uy, w.uz, h, S, w.slot, w.nS, w.woff, 0, S,
+                                              eps2, w.sum));
+    }
+    k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 3, 1, 0u);
+    k_energy<<<blocks_for(m, TB), TB, 0, s>>>(w.sum, w.lvx, w.lvy, w.lvz, w.lhalo, w.lp, w.vb, m,
+                                             mGm, P.e_recheck, mixed ? 1 : 0, bound, phi,
+                                             w.nb_own, w.rlist, w.dcnt + 3);
+    if (mixed) {
+      k_recheck<<<1024, TB, 0, s>>>(w.ux, w.uy, w.uz, w.lhalo, w.slot, w.nS, w.rlist,
+                                    w.dcnt + 3, eps2, w.sum);
+      k_energy_list<<<blocks_for(m, TB), TB, 0, s>>>(w.sum, w.lvx, w.lvy, w.lvz, w.lhalo, w.lp,
+                                                     w.vb, w.rlist, w.dcnt + 3, mGm, bound,
+                                                     phi, w.nb_own);
+    }
+  }
+  k_unbind_out<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, w.nb_own, w.vb,
+                                                P.unbound_threshold, o, w.nbS);
+  k_valid<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, w.nbS, P.unbound_threshold, o);
+  HALO_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+void unbind(Ctx& ctx, int64_t n, int pos_dtype, const void* x, const void* y, const void* z,
+            const float* vx, const float* vy, const float* vz, const libhalo_halos* halos,
+            int64_t n_halos, const int32_t* halo_of, uint8_t* bound, double* phi,
+            libhalo_unbound* out, hipStream_t s) {
+  if (pos_dtype == LIBHALO_F64)
+    unbind_impl<double>(ctx, n, (const double*)x, (const double*)y, (const double*)z, vx, vy,
+                        vz, *halos, n_halos, halo_of, bound, phi, *out, s);
+  else
+    unbind_impl<float>(ctx, n, (const float*)x, (const float*)y, (const float*)z, vx, vy, vz,
+                       *halos, n_halos, halo_of, bound, phi, *out, s);
+}
+
+}  // namespace halo

@@ -99,8 +99,9 @@ PropsS = _struct(PROP_FIELDS, False)
 
 # Exported symbols (the C ABI of include/libhalo.h).
 SYMBOLS = ["libhalo_ctx_create", "libhalo_ctx_destroy", "libhalo_last_error",
-           "libhalo_set_params", "libhalo_version", "libhalo_fof3d", "libhalo_refine6d",
-           "libhalo_assign", "libhalo_unbind", "libhalo_props"]
+           "libhalo_set_params", "libhalo_version", "libhalo_profile", "libhalo_profile_reset",
+           "libhalo_profile_read", "libhalo_fof3d", "libhalo_refine6d", "libhalo_assign",
+           "libhalo_unbind", "libhalo_props"]
 
 _lib = None
 
@@ -121,6 +122,9 @@ def load_library(path: str = LIB_PATH):
     L.libhalo_last_error.restype = C.c_char_p
     L.libhalo_set_params.argtypes = [_P, C.POINTER(CParams)]
     L.libhalo_version.restype = C.c_char_p
+    L.libhalo_profile.argtypes = [_P, i32]
+    L.libhalo_profile_reset.argtypes = [_P]
+    L.libhalo_profile_read.argtypes = [_P, C.c_char_p, C.POINTER(C.c_double), pi64]
     L.libhalo_fof3d.argtypes = [_P, i64, i32, _P, _P, _P, _P, _P, _P, _P, i64, pi64, pi64, _P]
     L.libhalo_refine6d.argtypes = [_P, i64, i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, i64,
                                    C.POINTER(NodesS), _P, pi64, _P]
@@ -223,6 +227,20 @@ class Halo:
         if rc != 0:
             msg = self.L.libhalo_last_error(self.h).decode()
             raise HaloError(rc, msg)
+
+    # ------------------------------------------------------------ timing --
+    def profile(self, enable: bool = True):
+        """Bracket the library's hot kernel launches with HIP events."""
+        self._check(self.L.libhalo_profile(self.h, int(enable)))
+
+    def profile_reset(self):
+        self._check(self.L.libhalo_profile_reset(self.h))
+
+    def profile_read(self, kernel: str):
+        """(total device ms, launches) of `kernel` since the last reset."""
+        t, k = C.c_double(0.0), C.c_int64(0)
+        self._check(self.L.libhalo_profile_read(self.h, kernel.encode(), C.byref(t), C.byref(k)))
+        return t.value, k.value
 
     # ------------------------------------------------------------ stages --
     def fof3d(self, P: Particles, grp_cap: int | None = None):

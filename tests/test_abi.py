@@ -1,0 +1,59 @@
+"""The C ABI library loads and exports every entry point of include/libhalo.h."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "libhalo.h")).read()
+    return sorted(set(re.findall(r"\b(libhalo_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1110_4372_amd import build, halo
+    if not os.path.exists(halo.LIB_PATH):
+        build.build()
+    return ctypes.CDLL(halo.LIB_PATH)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_symbols()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), f"{n} not exported"
+
+
+def test_binding_lists_every_symbol():
+    from paper_1110_4372_amd import halo
+    assert sorted(halo.SYMBOLS) == declared_symbols()
+
+
+def test_version_and_bad_args_without_gpu(lib):
+    lib.libhalo_version.restype = ctypes.c_char_p
+    assert b"gfx950" in lib.libhalo_version()
+    # null arguments are rejected before any device call
+    assert lib.libhalo_ctx_create(None, 0, None) == -1
+    assert lib.libhalo_ctx_destroy(None) == -1
+    assert lib.libhalo_fof3d(None, 10, 0, None, None, None, None, None, None, None, 0,
+                             None, None, None) == -1
+
+
+def test_params_struct_matches_header():
+    """ctypes mirror of libhalo_params has the header's field order."""
+    from paper_1110_4372_amd import halo
+    src = open(os.path.join(ROOT, "include", "libhalo.h")).read()
+    body = src[src.index("typedef struct {\n  double box;"):src.index("} libhalo_params;")]
+    fields = re.findall(r"^\s*(?:double|int32_t)\s+([A-Za-z_0-9]+);", body, re.M)
+    assert fields == [f for f, _ in halo.CParams._fields_]
+
+
+def test_product_path_does_not_import_oracle():
+    """The binding and build modules never touch the oracle."""
+    for f in ("halo.py", "build.py", "synth.py", "__init__.py"):
+        src = open(os.path.join(ROOT, "paper_1110_4372_amd", f)).read()
+        assert not re.search(r"^\s*(from|import)\s+oracle", src, re.M), f

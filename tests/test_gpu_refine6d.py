@@ -1,0 +1,156 @@
+"""6D phase-space hierarchy on the GPU against the CPU oracle (Section 3.2).
+
+Node tables and the deepest-node map must match bit for bit: every moment is
+an exact fixed-point sum, every distance the same FP32 expression."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import note, particles_from_arrays, to_np
+from tests.test_oracle_pins import clustered, particles
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ["parent", "level", "first_child", "n_children", "count", "canon", "fof", "flags",
+          "cx", "cy", "cz", "vx", "vy", "vz", "sx2", "sv2", "ell2"]
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1110_4372_amd import halo
+    halo.load_library()
+    return halo
+
+
+def gpu_nodes(nodes):
+    return {k: to_np(v) for k, v in nodes.items()}
+
+
+def subset_nodes(nodes, keep_fof):
+    """Rows of the FOF groups in keep_fof, re-indexed (BFS order is kept)."""
+    rows = np.nonzero(np.isin(nodes["fof"].astype(np.int64), keep_fof))[0]
+    remap = np.full(nodes["fof"].shape[0] + 1, -1, np.int64)
+    remap[rows] = np.arange(rows.shape[0])
+    out = {k: v[rows].copy() for k, v in nodes.items()}
+    for k in ("parent", "first_child"):
+        v = out[k].astype(np.int64)
+        out[k] = np.where(v >= 0, remap[v], -1)
+    return out, remap
+
+
+def assert_nodes_equal(g, o):
+    assert g["parent"].shape[0] == o["parent"].shape[0], "node counts differ"
+    for f in FIELDS:
+        a = np.asarray(g[f])
+        b = np.asarray(o[f])
+        if a.dtype.kind == "f":
+            ok = np.array_equal(a.view(np.uint64 if a.itemsize == 8 else np.uint32),
+                                b.astype(a.dtype).view(np.uint64 if a.itemsize == 8 else
+                                                       np.uint32))
+        else:
+            ok = np.array_equal(a.astype(np.int64), b.astype(np.int64))
+        if not ok:
+            bad = np.nonzero(a.astype(np.float64) != b.astype(np.float64))[0][:5]
+            raise AssertionError(f"field {f} differs at rows {bad}: gpu {a[bad]} oracle {b[bad]}")
+
+
+def run_both(H, orc, pos, vel, box, mode=1, m=1e10, eps=0.01):
+    P = particles(orc, pos, vel)
+    p = orc.make_params(box, m, eps)
+    lab = orc.fof3d(p, P)
+    onodes, odeep = orc.refine6d(p, P, lab)
+    ctx = H.Halo(H.Params(box=box, particle_mass=m, softening=eps, mode=mode))
+    GP = particles_from_arrays(pos, vel)
+    fof = ctx.fof3d(GP)
+    gnodes, gdeep = ctx.refine6d(GP, fof)
+    return onodes, odeep, gpu_nodes(gnodes), to_np(gdeep)
+
+
+@pytest.mark.parametrize("n,seed,f64,mode", [(3000, 5, True, 1), (6000, 6, False, 1),
+                                             (3000, 5, True, 0), (12001, 7, False, 1)])
+def test_refine_clustered(H, orc, n, seed, f64, mode):
+    note(f"refine6d clustered n={n} seed={seed} f64={f64} mode={mode}")
+    box = 10.0 * (n / 1500) ** (1 / 3)
+    pos, vel = clustered(n, box, seed, nblob=4, spread=0.25, f64=f64)
+    on, od, gn, gd = run_both(H, orc, pos, vel, box, mode=mode)
+    assert on["parent"].shape[0] > 4
+    assert_nodes_equal(gn, on)
+    np.testing.assert_array_equal(gd, od)
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+def test_refine_c1(H, orc, c1, c1_oracle, mode):
+    note(f"refine6d c1 mode={mode}")
+    ctx = H.Halo(H.params_for_catalog(c1, mode=mode))
+    P = H.Particles.from_catalog(c1)
+    fof = ctx.fof3d(P)
+    gn, gd = ctx.refine6d(P, fof)
+    assert_nodes_equal(gpu_nodes(gn), c1_oracle["nodes"])
+    np.testing.assert_array_equal(to_np(gd), c1_oracle["deepest"])
+
+
+def test_refine_c2_sampled(H, orc):
+    """128^3 catalogue at full size; the oracle refines a sample of FOF groups
+    (every other group is cut into singletons in its input labels)."""
+    from paper_1110_4372_amd import synth
+    note("refine6d c2 sampled groups")
+    cat = synth.make_catalog("c2")
+    ctx = H.Halo(H.params_for_catalog(cat))
+    P = H.Particles.from_catalog(cat)
+    fof = ctx.fof3d(P)
+    gn, gd = ctx.refine6d(P, fof)
+    gn = gpu_nodes(gn)
+    gd = to_np(gd)
+    lab = to_np(fof["label"]).astype(np.int64)
+    sizes = np.bincount(lab, minlength=lab.shape[0])
+    groups = np.nonzero(sizes >= 10)[0]
+    rng = np.random.default_rng(0)
+    small = groups[sizes[groups] <= 1500]
+    mid = groups[(sizes[groups] > 3000) & (sizes[groups] <= 12000)]
+    keep = np.sort(np.concatenate([rng.choice(small, 150, replace=False),
+                                   rng.choice(mid, min(2, mid.shape[0]), replace=False)]))
+    lab_s = np.where(np.isin(lab, keep), lab, np.arange(lab.shape[0])).astype(np.uint32)
+    p = orc.params_of(cat)
+    on, od = orc.refine6d(p, orc.Particles.of(cat), lab_s)
+    sub, remap = subset_nodes(gn, keep)
+    assert_nodes_equal(sub, on)
+    inside = np.isin(lab, keep)
+    np.testing.assert_array_equal(np.where(gd[inside] >= 0, remap[gd[inside]], -1), od[inside])
+    assert np.all((gd >= 0) == (sizes[lab] >= 10))
+
+
+def test_refine_repeat_and_modes_agree(H, c1):
+    note("refine6d repeat x3 and plain == batched")
+    outs = []
+    for mode in (1, 1, 0):
+        ctx = H.Halo(H.params_for_catalog(c1, mode=mode))
+        P = H.Particles.from_catalog(c1)
+        gn, gd = ctx.refine6d(P, ctx.fof3d(P))
+        outs.append((gpu_nodes(gn), to_np(gd)))
+    for gn, gd in outs[1:]:
+        assert_nodes_equal(gn, outs[0][0])
+        np.testing.assert_array_equal(gd, outs[0][1])
+
+
+def test_refine_capacity_two_call(H, c1):
+    note("refine6d capacity error then retry")
+    ctx = H.Halo(H.params_for_catalog(c1))
+    P = H.Particles.from_catalog(c1)
+    fof = ctx.fof3d(P)
+    with pytest.raises(H.HaloError) as e:
+        ctx.refine6d(P, fof, node_cap=5)
+    assert e.value.code == -4
+    gn, _ = ctx.refine6d(P, fof)
+    assert gn["parent"].shape[0] > 5
+
+
+def test_refine_velocity_blobs(H, orc):
+    """Two co-spatial haloes differing only in bulk velocity are separated."""
+    note("refine6d velocity blobs")
+    rng = np.random.default_rng(9)
+    n = 2000
+    pos = 16.0 + 0.15 * rng.standard_normal((n, 3))
+    vel = (40.0 * rng.standard_normal((n, 3))).astype(np.float32)
+    vel[: n // 2, 0] += 600.0
+    on, od, gn, gd = run_both(H, orc, pos, vel, 32.0, m=1e10)
+    assert_nodes_equal(gn, on)
+    np.testing.assert_array_equal(gd, od)

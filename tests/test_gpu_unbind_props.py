@@ -1,0 +1,119 @@
+"""Unbinding and halo properties on the GPU against the oracle (Sections
+3.5.1-3.5.4, Appendix B).
+
+Bound flags are decided by floating-point sums whose rounding order differs
+between the two sides, so flags must agree wherever the energy lies outside
+the error band of those sums (|E| > tol (K + |phi|)); inside it either
+answer is correct and the count is reported.  Properties must agree within
+1e-5 relative (FP64 on both sides)."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import note, particles_from_arrays, to_np
+from tests.test_oracle_pins import clustered, particles
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1110_4372_amd import halo
+    halo.load_library()
+    return halo
+
+
+def energy_band(o, P, tol):
+    """Particles whose bound flag is decided beyond the band, from the oracle."""
+    ho = o["halo_of"]
+    vb = np.stack([o["unbound"]["vbx"], o["unbound"]["vby"], o["unbound"]["vbz"]], 1)
+    v = np.stack([P.vx, P.vy, P.vz], 1).astype(np.float64)
+    inside = ho >= 0
+    k = np.zeros(ho.shape[0])
+    k[inside] = 0.5 * ((v[inside] - vb[ho[inside]]) ** 2).sum(1)
+    e = k + o["phi"]
+    return inside & (np.abs(e) > tol * (k + np.abs(o["phi"])))
+
+
+def compare_unbind(g_unb, g_bound, g_phi, o, P, tol, phi_rtol):
+    decided = energy_band(o, P, tol)
+    ambiguous = int(np.sum((o["halo_of"] >= 0) & ~decided))
+    gb = to_np(g_bound)
+    np.testing.assert_array_equal(gb[decided], o["bound"][decided])
+    np.testing.assert_array_equal(gb[o["halo_of"] < 0], 0)
+    gphi = to_np(g_phi)
+    inside = o["halo_of"] >= 0
+    np.testing.assert_allclose(gphi[inside], o["phi"][inside], rtol=phi_rtol, atol=0)
+    gu = {k: to_np(v) for k, v in g_unb.items()}
+    np.testing.assert_array_equal(gu["n_s"], o["unbound"]["n_s"])
+    for c in ("vbx", "vby", "vbz"):
+        np.testing.assert_array_equal(gu[c], o["unbound"][c])
+    changed = int(np.sum(gb[inside] != o["bound"][inside]))
+    if ambiguous == 0 or changed == 0:
+        for c in ("n_bound_own", "n_bound_s", "valid"):
+            np.testing.assert_array_equal(gu[c].astype(np.int64),
+                                          o["unbound"][c].astype(np.int64))
+    return ambiguous, changed
+
+
+def compare_props(g, o, kept):
+    g = {k: to_np(v) for k, v in g.items()}
+    np.testing.assert_array_equal(g["n_bound"][kept], o["n_bound"][kept])
+    for f in ("px", "py", "pz"):
+        np.testing.assert_array_equal(g[f][kept], o[f][kept])
+    for f in ("mvir",):
+        np.testing.assert_array_equal(g[f][kept], o[f][kept])
+    for f in ("rvir", "vmax"):
+        np.testing.assert_allclose(g[f][kept], o[f][kept], rtol=1e-5, atol=0)
+    for a, b in (("vbx", "vbx"), ("vby", "vby"), ("vbz", "vbz"), ("vcx", "vcx"),
+                 ("vcy", "vcy"), ("vcz", "vcz")):
+        scale = np.maximum(np.abs(o[b][kept]), 1.0)
+        assert np.all(np.abs(g[a][kept] - o[b][kept]) <= 1e-5 * scale), a
+    np.testing.assert_allclose(g["voff"][kept], o["voff"][kept], rtol=1e-5, atol=1e-6)
+
+
+def run_gpu(H, P, params):
+    ctx = H.Halo(params)
+    return ctx.run_all(P)
+
+
+@pytest.mark.parametrize("n,seed,f64,prec", [(4000, 31, True, 0), (9000, 32, False, 0),
+                                             (9000, 32, False, 1)])
+def test_unbind_props_clustered(H, orc, n, seed, f64, prec):
+    note(f"unbind/props clustered n={n} seed={seed} f64={f64} prec={prec}")
+    box = 10.0 * (n / 1500) ** (1 / 3)
+    pos, vel = clustered(n, box, seed, nblob=5, spread=0.3, f64=f64)
+    m, eps = 1e11, 0.005
+    p = orc.make_params(box, m, eps)
+    P = particles(orc, pos, vel)
+    o = orc.run_all(p, P)
+    g = run_gpu(H, particles_from_arrays(pos, vel),
+                H.Params(box=box, particle_mass=m, softening=eps, prec=prec))
+    tol, rtol = (1e-9, 1e-9) if prec == 0 else (1e-4, 2e-5)
+    amb, changed = compare_unbind(g["unbound"], g["bound"], g["phi"], o, P, tol, rtol)
+    print(f"ambiguous={amb} changed={changed}")
+    kept = o["halos"]["merged_into"] == np.arange(o["halos"]["merged_into"].shape[0])
+    if changed == 0:
+        compare_props(g["props"], o["props"], kept)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_unbind_props_c1(H, c1, c1_oracle, prec):
+    note(f"unbind/props c1 prec={prec}")
+    g = run_gpu(H, H.Particles.from_catalog(c1), H.params_for_catalog(c1, prec=prec))
+    o = c1_oracle
+    tol, rtol = (1e-9, 1e-9) if prec == 0 else (1e-4, 2e-5)
+    amb, changed = compare_unbind(g["unbound"], g["bound"], g["phi"], o, c1, tol, rtol)
+    print(f"ambiguous={amb} changed={changed}")
+    assert changed == 0
+    kept = o["halos"]["merged_into"] == np.arange(o["halos"]["merged_into"].shape[0])
+    compare_props(g["props"], o["props"], kept)
+
+
+def test_unbind_plain_equals_batched(H, c1):
+    note("unbind plain == batched")
+    a = run_gpu(H, H.Particles.from_catalog(c1), H.params_for_catalog(c1, mode=1))
+    b = run_gpu(H, H.Particles.from_catalog(c1), H.params_for_catalog(c1, mode=0))
+    np.testing.assert_array_equal(to_np(a["bound"]), to_np(b["bound"]))
+    np.testing.assert_array_equal(to_np(a["phi"]), to_np(b["phi"]))
+    for k in a["props"]:
+        np.testing.assert_array_equal(to_np(a["props"][k]), to_np(b["props"][k]))
