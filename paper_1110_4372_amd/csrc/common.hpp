@@ -240,6 +240,18 @@ __device__ __forceinline__ uint32_t uf_find(uint32_t* par, uint32_t x) {
   return cur;
 }
 
+// Root of x without touching the forest.  Compression kernels must use this:
+// a path-halving find running in another thread could otherwise overwrite a
+// pointer just set to the root with a lower ancestor.
+__device__ __forceinline__ uint32_t uf_root(const uint32_t* par, uint32_t x) {
+  uint32_t p = uf_load(par + x);
+  while (p != x) {
+    x = p;
+    p = uf_load(par + x);
+  }
+  return x;
+}
+
 // Join the sets of a and b; returns the root of the joined set.
 __device__ __forceinline__ uint32_t uf_union(uint32_t* par, uint32_t a, uint32_t b) {
   uint32_t ra = uf_find(par, a), rb = uf_find(par, b);

@@ -165,10 +165,12 @@ __global__ void k_link(const T* xs, const T* ys, const T* zs, const uint32_t* ce
   }
 }
 
+// Every parent becomes its root.  Roots do not change during this pass (no
+// unions), so each thread may store the root it reads.
 __global__ void k_compress(uint32_t* par, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  par[i] = uf_find(par, (uint32_t)i);
+  uf_store(par + i, uf_root(par, (uint32_t)i));
 }
 
 // minidx[root] = smallest input index in the component.

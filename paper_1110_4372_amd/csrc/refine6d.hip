@@ -605,9 +605,10 @@ __global__ void k_node_out(LevelNodes nd, uint32_t K, int32_t base, int32_t leve
   out.ell2[row] = active ? sc.ell2[k] : -1.0f;
 }
 
+// Every parent becomes its root (read-only walks; see uf_root).
 __global__ void k_compress(uint32_t* par, uint32_t M) {
   uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m < M) par[m] = uf_find(par, m);
+  if (m < M) uf_store(par + m, uf_root(par, m));
 }
 
 __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {

@@ -119,11 +119,14 @@ def test_refine_c2_sampled(H, orc):
 
 
 def test_refine_repeat_and_modes_agree(H, c1):
-    note("refine6d repeat x3 and plain == batched")
+    """Repeated runs in both forms give bit-identical hierarchies.  Regression
+    test of the compression race: a path-halving find concurrent with the
+    compression pass could leave a parent pointing below its root."""
+    note("refine6d repeat x8 and plain == batched")
     outs = []
-    for mode in (1, 1, 0):
+    P = H.Particles.from_catalog(c1)
+    for mode in (1, 0, 1, 0, 1, 0, 1, 0):
         ctx = H.Halo(H.params_for_catalog(c1, mode=mode))
-        P = H.Particles.from_catalog(c1)
         gn, gd = ctx.refine6d(P, ctx.fof3d(P))
         outs.append((gpu_nodes(gn), to_np(gd)))
     for gn, gd in outs[1:]:
