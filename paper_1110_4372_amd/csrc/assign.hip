@@ -174,11 +174,10 @@ __global__ void k_uniq_write(const unsigned long long* key, const uint32_t* flag
 // Own particles: deepest >= 0, keyed by node.
 __global__ void k_own_flags(const int32_t* deepest, uint32_t n, uint32_t* flag,
                             uint32_t* ocnt) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int32_t d = deepest[i];
-  flag[i] = d >= 0 ? 1u : 0u;
-  if (d >= 0) atomicAdd(ocnt + d, 1u);
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t d = i < n ? deepest[i] : -1;
+  if (i < n) flag[i] = d >= 0 ? 1u : 0u;
+  agg_add_u32(ocnt, d >= 0 ? (uint32_t)d : 0u, 1u, d >= 0);
 }
 
 __global__ void k_own_compact(const int32_t* deepest, const uint32_t* flag, const uint32_t* pos,
@@ -273,8 +272,9 @@ __global__ void k_assign_level(const T* x, const T* y, const T* z, const float* 
 }
 
 __global__ void k_count_assigned(const int32_t* halo_of, uint32_t n, uint32_t* na) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && halo_of[i] >= 0) atomicAdd(na + halo_of[i], 1u);
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t h = i < n ? halo_of[i] : -1;
+  agg_add_u32(na, h >= 0 ? (uint32_t)h : 0u, 1u, h >= 0);
 }
 
 __global__ void k_all_assigned(const int32_t* halo_of, uint32_t n, uint32_t* flag) {

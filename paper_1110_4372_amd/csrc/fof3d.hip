@@ -173,22 +173,33 @@ __global__ void k_compress(uint32_t* par, int64_t n) {
   uf_store(par + i, uf_root(par, (uint32_t)i));
 }
 
-// minidx[root] = smallest input index in the component.
-__global__ void k_minidx(const uint32_t* cell_of, const uint32_t* perm, const uint32_t* par,
-                         int64_t n, uint32_t* minidx) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  atomicMin(minidx + par[cell_of[i]], perm[i]);
+// minidx[root] = smallest input index in the component, one atomic per cell.
+__global__ void k_cell_min(const uint32_t* cell_start, int64_t ncell, int64_t n,
+                           const uint32_t* perm, const uint32_t* par, uint32_t* minidx) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const uint32_t a0 = cell_start[c];
+  const uint32_t a1 = (c + 1 < ncell) ? cell_start[c + 1] : (uint32_t)n;
+  uint32_t mn = 0xFFFFFFFFu;
+  for (uint32_t i = a0; i < a1; ++i) mn = min(mn, perm[i]);
+  atomicMin(minidx + par[c], mn);
+}
+
+// Group sizes by label, one atomic per cell.
+__global__ void k_cell_sizes(const uint32_t* cell_start, int64_t ncell, int64_t n,
+                             const uint32_t* par, const uint32_t* minidx, uint32_t* gsize) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const uint32_t a0 = cell_start[c];
+  const uint32_t a1 = (c + 1 < ncell) ? cell_start[c + 1] : (uint32_t)n;
+  atomicAdd(gsize + minidx[par[c]], a1 - a0);
 }
 
 __global__ void k_labels(const uint32_t* cell_of, const uint32_t* perm, const uint32_t* par,
-                         const uint32_t* minidx, int64_t n, uint32_t* label,
-                         uint32_t* gsize) {
+                         const uint32_t* minidx, int64_t n, uint32_t* label) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  uint32_t l = minidx[par[cell_of[i]]];
-  label[perm[i]] = l;
-  atomicAdd(gsize + l, 1u);
+  label[perm[i]] = minidx[par[cell_of[i]]];
 }
 
 __global__ void k_member_flags(const uint32_t* label, const uint32_t* gsize, int64_t n,
@@ -307,8 +318,9 @@ void fof3d_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, uint32_
   }
   k_fill_u32<<<nb, TB, 0, s>>>(minidx, ncell, 0xFFFFFFFFu);
   k_fill_u32<<<nb, TB, 0, s>>>(gsize, n, 0u);
-  k_minidx<<<nb, TB, 0, s>>>(cell_of, sperm, par, n, minidx);
-  k_labels<<<nb, TB, 0, s>>>(cell_of, sperm, par, minidx, n, label, gsize);
+  k_cell_min<<<blocks_for(ncell, TB), TB, 0, s>>>(cell_start, ncell, n, sperm, par, minidx);
+  k_cell_sizes<<<blocks_for(ncell, TB), TB, 0, s>>>(cell_start, ncell, n, par, minidx, gsize);
+  k_labels<<<nb, TB, 0, s>>>(cell_of, sperm, par, minidx, n, label);
   // members of groups with >= min_members, in input order, keyed by label
   const uint32_t mm = (uint32_t)P.min_members;
   k_member_flags<<<nb, TB, 0, s>>>(label, gsize, n, mm, v0);

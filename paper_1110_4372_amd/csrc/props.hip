@@ -129,23 +129,46 @@ __global__ void k_so_accum(const float* vx, const float* vy, const float* vz,
                            const uint32_t* start, uint32_t m, const uint32_t* kstar,
                            const double* rc2, double eps2, I128* acc, unsigned long long* vm,
                            uint32_t* ncore) {
-  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  const uint32_t hh = s_seg[q], i = s_pidx[q];
-  const uint32_t j = q - start[hh] + 1;
-  const double r2 = s_r2[q];
-  long long w[3] = {quantise((double)vx[i], kVelShift), quantise((double)vy[i], kVelShift),
-                    quantise((double)vz[i], kVelShift)};
-  if (j <= kstar[hh]) {
-    double jj = (double)j;
-    double t = (jj * jj) / fmax(r2, eps2);
-    atomicMax(vm + hh, (unsigned long long)__double_as_longlong(t));
-    for (int c = 0; c < 3; ++c) atomic_add_i128(acc + 6 * (size_t)hh + c, i128_from(w[c]));
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = q < m;
+  uint32_t hh = 0xFFFFFFFFu;
+  I128 v[6];
+  for (int c = 0; c < 6; ++c) v[c] = i128_from(0);
+  double t = 0.0;
+  bool in_core = false;
+  if (ok) {
+    hh = s_seg[q];
+    const uint32_t i = s_pidx[q];
+    const uint32_t j = q - start[hh] + 1;
+    const double r2 = s_r2[q];
+    const long long w[3] = {quantise((double)vx[i], kVelShift),
+                            quantise((double)vy[i], kVelShift),
+                            quantise((double)vz[i], kVelShift)};
+    if (j <= kstar[hh]) {
+      const double jj = (double)j;
+      t = (jj * jj) / fmax(r2, eps2);
+      for (int c = 0; c < 3; ++c) v[c] = i128_from(w[c]);
+    }
+    if (r2 < rc2[hh]) {
+      in_core = true;
+      for (int c = 0; c < 3; ++c) v[3 + c] = i128_from(w[c]);
+    }
   }
-  if (r2 < rc2[hh]) {
-    for (int c = 0; c < 3; ++c) atomic_add_i128(acc + 6 * (size_t)hh + 3 + c, i128_from(w[c]));
-    atomicAdd(ncore + hh, 1u);
+  const uint32_t h0 = __shfl(hh, 0);
+  if (__all(hh == h0) && h0 != 0xFFFFFFFFu) {
+    double tm = t;
+    for (int o = 32; o > 0; o >>= 1) tm = fmax(tm, __shfl_xor(tm, o));
+    for (int c = 0; c < 6; ++c) v[c] = wave_sum_i128(v[c]);
+    if ((threadIdx.x & 63) == 0) {
+      for (int c = 0; c < 6; ++c) atomic_add_i128(acc + 6 * (size_t)h0 + c, v[c]);
+      if (tm > 0.0) atomicMax(vm + h0, (unsigned long long)__double_as_longlong(tm));
+    }
+  } else if (ok) {
+    for (int c = 0; c < 6; ++c)
+      if (v[c].lo != 0 || v[c].hi != 0) atomic_add_i128(acc + 6 * (size_t)hh + c, v[c]);
+    if (t > 0.0) atomicMax(vm + hh, (unsigned long long)__double_as_longlong(t));
   }
+  agg_add_u32(ncore, ok ? hh : 0u, 1u, in_core);
 }
 
 __global__ void k_prop_out(const libhalo_halos h, uint32_t S, const uint32_t* start,

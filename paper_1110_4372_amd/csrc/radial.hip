@@ -12,17 +12,21 @@ __global__ void k_r2(const T* x, const T* y, const T* z, double box, const doubl
                      const double* cy, const double* cz, const uint32_t* seg,
                      const uint32_t* pidx, uint32_t m, double* r2, unsigned long long* key,
                      uint32_t* val, uint32_t* cnt) {
-  uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m) return;
-  const uint32_t h = seg[e], i = pidx[e];
-  double dx = min_image((double)x[i] - cx[h], box);
-  double dy = min_image((double)y[i] - cy[h], box);
-  double dz = min_image((double)z[i] - cz[h], box);
-  double d = sq3(dx, dy, dz);
-  r2[e] = d;
-  key[e] = (unsigned long long)__double_as_longlong(d);
-  val[e] = e;
-  atomicAdd(cnt + h, 1u);
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = e < m;
+  uint32_t h = 0;
+  if (ok) {
+    h = seg[e];
+    const uint32_t i = pidx[e];
+    double dx = min_image((double)x[i] - cx[h], box);
+    double dy = min_image((double)y[i] - cy[h], box);
+    double dz = min_image((double)z[i] - cz[h], box);
+    double d = sq3(dx, dy, dz);
+    r2[e] = d;
+    key[e] = (unsigned long long)__double_as_longlong(d);
+    val[e] = e;
+  }
+  agg_add_u32(cnt, h, 1u, ok);
 }
 
 __global__ void k_seg_keys(const uint32_t* seg, const uint32_t* perm, uint32_t m,

@@ -498,10 +498,9 @@ __global__ void k_select_big_resolve(NodeScratch sc, const uint32_t* nbig, int p
 // ------------------------------------------------------------ children -----
 __global__ void k_comp_size(const uint32_t* par, const uint32_t* lnode, uint32_t M,
                             NodeScratch sc, uint32_t* csize) {
-  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
-  if (sc.prm[12 * (size_t)lnode[m] + 11] == 0.0) return;
-  atomicAdd(csize + par[m], 1u);
+  const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = m < M && sc.prm[12 * (size_t)lnode[m < M ? m : 0] + 11] != 0.0;
+  agg_add_u32(csize, ok ? par[m] : 0u, 1u, ok);
 }
 
 __global__ void k_whole(const uint32_t* par, const uint32_t* lnode, const uint32_t* csize,

@@ -195,7 +195,8 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint
   return lo;
 }
 
-// FP64 direct sum: sum_j 1/sqrt(r^2 + eps^2) over S(h), j != i.
+// FP64 direct sum: sum_j 1/sqrt(r^2 + eps^2) over S(h), j != i.  Terms use the
+// hardware rsqrt estimate refined by two Newton steps (FP64-accurate).
 __global__ void __launch_bounds__(TB)
     k_potential_f64(const double* ux, const double* uy, const double* uz, const libhalo_halos h,
                     uint32_t S, const uint32_t* slot, const uint32_t* nS, const uint32_t* woff,
@@ -210,7 +211,7 @@ __global__ void __launch_bounds__(TB)
     const bool ok = li < nown;
     const uint32_t qi = base + (ok ? li : 0);
     const double xi = ux[qi], yi = uy[qi], zi = uz[qi];
-    double acc = 0.0;
+    double acc0 = 0.0, acc1 = 0.0;
     for (uint32_t jt = 0; jt < ns; jt += TB) {
       __syncthreads();
       if (jt + threadIdx.x < ns) {
@@ -220,14 +221,25 @@ __global__ void __launch_bounds__(TB)
       }
       __syncthreads();
       const uint32_t nt = min((uint32_t)TB, ns - jt);
-      for (uint32_t q = 0; q < nt; ++q) {
-        double dx = tx[q] - xi, dy = ty[q] - yi, dz = tz[q] - zi;
-        double r2 = sq3(dx, dy, dz) + eps2;
-        double t = 1.0 / sqrt(r2);
-        acc += (jt + q != li) ? t : 0.0;
+      const uint32_t self = li - jt;  // tile index of i itself (may be out of range)
+      uint32_t q = 0;
+      for (; q + 2 <= nt; q += 2) {
+        double dx0 = tx[q] - xi, dy0 = ty[q] - yi, dz0 = tz[q] - zi;
+        double dx1 = tx[q + 1] - xi, dy1 = ty[q + 1] - yi, dz1 = tz[q + 1] - zi;
+        double r0 = __fma_rn(dz0, dz0, __fma_rn(dy0, dy0, __fma_rn(dx0, dx0, eps2)));
+        double r1 = __fma_rn(dz1, dz1, __fma_rn(dy1, dy1, __fma_rn(dx1, dx1, eps2)));
+        double t0 = rsqrt_f64(r0), t1 = rsqrt_f64(r1);
+        acc0 += (q != self) ? t0 : 0.0;
+        acc1 += (q + 1 != self) ? t1 : 0.0;
+      }
+      if (q < nt) {
+        double dx0 = tx[q] - xi, dy0 = ty[q] - yi, dz0 = tz[q] - zi;
+        double r0 = __fma_rn(dz0, dz0, __fma_rn(dy0, dy0, __fma_rn(dx0, dx0, eps2)));
+        double t0 = rsqrt_f64(r0);
+        acc0 += (q != self) ? t0 : 0.0;
       }
     }
-    if (ok) sum[qi] = acc;
+    if (ok) sum[qi] = acc0 + acc1;
     __syncthreads();
   }
 }
@@ -259,13 +271,24 @@ __global__ void __launch_bounds__(TB)
       }
       __syncthreads();
       const uint32_t nt = min((uint32_t)TB, ns - jt);
-      float part = 0.0f;
-      for (uint32_t q = 0; q < nt; ++q) {
-        float dx = tx[q] - xi, dy = ty[q] - yi, dz = tz[q] - zi;
-        float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2)));
-        float t = __frsqrt_rn(r2);
-        part += (jt + q != li) ? t : 0.0f;
+      const uint32_t self = li - jt;
+      float p0 = 0.0f, p1 = 0.0f;
+      uint32_t q = 0;
+      for (; q + 2 <= nt; q += 2) {
+        float dx0 = tx[q] - xi, dy0 = ty[q] - yi, dz0 = tz[q] - zi;
+        float dx1 = tx[q + 1] - xi, dy1 = ty[q + 1] - yi, dz1 = tz[q + 1] - zi;
+        float r0 = __fmaf_rn(dz0, dz0, __fmaf_rn(dy0, dy0, __fmaf_rn(dx0, dx0, eps2)));
+        float r1 = __fmaf_rn(dz1, dz1, __fmaf_rn(dy1, dy1, __fmaf_rn(dx1, dx1, eps2)));
+        float t0 = __builtin_amdgcn_rsqf(r0), t1 = __builtin_amdgcn_rsqf(r1);
+        p0 += (q != self) ? t0 : 0.0f;
+        p1 += (q + 1 != self) ? t1 : 0.0f;
       }
+      if (q < nt) {
+        float dx0 = tx[q] - xi, dy0 = ty[q] - yi, dz0 = tz[q] - zi;
+        float r0 = __fmaf_rn(dz0, dz0, __fmaf_rn(dy0, dy0, __fmaf_rn(dx0, dx0, eps2)));
+        p0 += (q != self) ? __builtin_amdgcn_rsqf(r0) : 0.0f;
+      }
+      const float part = p0 + p1;
       // Kahan step per tile
       float yk = part - comp;
       float tk = acc + yk;
@@ -311,22 +334,28 @@ __global__ void k_energy(const double* sum, const float* lvx, const float* lvy,
                          const double* vb, uint32_t m, double mGm, double e_rel, int mixed,
                          uint8_t* bound, double* phi, uint32_t* nb_own, uint32_t* rlist,
                          uint32_t* nr) {
-  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  const uint32_t hh = lhalo[q], i = lp[q];
-  const double ph = mGm * sum[q];
-  const double ux = (double)lvx[q] - vb[3 * (size_t)hh], uy = (double)lvy[q] - vb[3 * (size_t)hh + 1],
-               uz = (double)lvz[q] - vb[3 * (size_t)hh + 2];
-  const double k = 0.5 * sq3(ux, uy, uz);
-  const double e = k + ph;
-  if (mixed && fabs(e) < e_rel * (k + fabs(ph))) {
-    rlist[atomicAdd(nr, 1u)] = q;
-    return;  // decided after the FP64 recheck
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = q < m;
+  uint32_t hh = 0;
+  bool b = false;
+  if (ok) {
+    hh = lhalo[q];
+    const uint32_t i = lp[q];
+    const double ph = mGm * sum[q];
+    const double ux = (double)lvx[q] - vb[3 * (size_t)hh],
+                 uy = (double)lvy[q] - vb[3 * (size_t)hh + 1],
+                 uz = (double)lvz[q] - vb[3 * (size_t)hh + 2];
+    const double k = 0.5 * sq3(ux, uy, uz);
+    const double e = k + ph;
+    if (mixed && fabs(e) < e_rel * (k + fabs(ph))) {
+      rlist[atomicAdd(nr, 1u)] = q;  // decided after the FP64 recheck
+    } else {
+      b = e < 0.0;
+      bound[i] = b;
+      if (phi) phi[i] = ph;
+    }
   }
-  const uint8_t b = e < 0.0;
-  bound[i] = b;
-  if (phi) phi[i] = ph;
-  if (b) atomicAdd(nb_own + hh, 1u);
+  agg_add_u32(nb_own, hh, 1u, b);
 }
 
 __global__ void k_energy_list(const double* sum, const float* lvx, const float* lvy,
