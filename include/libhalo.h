@@ -89,6 +89,10 @@ typedef struct {
                                e_recheck (|K| + |phi|) (1e-4) */
   int32_t mode;             /* libhalo_mode */
   int32_t prec;             /* libhalo_prec */
+  int32_t grid_min;         /* nodes with more particles use the exact grid
+                               neighbour search instead of all pairs; 0 = 8192,
+                               else >= 64 (results are identical either way) */
+  int32_t reserved;         /* must be 0 */
 } libhalo_params;
 
 /* Node table (refine6d output), structure of arrays, capacity `cap` rows.

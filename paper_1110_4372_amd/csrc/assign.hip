@@ -172,12 +172,24 @@ __global__ void k_uniq_write(const unsigned long long* key, const uint32_t* flag
 }
 
 // Own particles: deepest >= 0, keyed by node.
-__global__ void k_own_flags(const int32_t* deepest, uint32_t n, uint32_t* flag,
-                            uint32_t* ocnt) {
+__global__ void k_own_flags(const int32_t* deepest, uint32_t n, uint32_t* flag) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t d = i < n ? deepest[i] : -1;
-  if (i < n) flag[i] = d >= 0 ? 1u : 0u;
-  agg_add_u32(ocnt, d >= 0 ? (uint32_t)d : 0u, 1u, d >= 0);
+  if (i < n) flag[i] = deepest[i] >= 0 ? 1u : 0u;
+}
+
+// off[k] = first position of node k in the node-sorted own list (lower bound).
+__global__ void k_own_offsets(const uint32_t* okey, uint32_t M, uint32_t NN, uint32_t* off) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > NN) return;
+  uint32_t lo = 0, hi = M;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (okey[mid] < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  off[k] = lo;
 }
 
 __global__ void k_own_compact(const int32_t* deepest, const uint32_t* flag, const uint32_t* pos,
@@ -271,12 +283,6 @@ __global__ void k_assign_level(const T* x, const T* y, const T* z, const float* 
   halo_of[i] = (int32_t)best;
 }
 
-__global__ void k_count_assigned(const int32_t* halo_of, uint32_t n, uint32_t* na) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t h = i < n ? halo_of[i] : -1;
-  agg_add_u32(na, h >= 0 ? (uint32_t)h : 0u, 1u, h >= 0);
-}
-
 __global__ void k_all_assigned(const int32_t* halo_of, uint32_t n, uint32_t* flag) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) flag[i] = halo_of[i] >= 0 ? 1u : 0u;
@@ -290,11 +296,11 @@ __global__ void k_all_compact(const int32_t* halo_of, const uint32_t* flag, cons
   pidx[pos[i]] = i;
 }
 
-__global__ void k_finish_halos(libhalo_halos h, uint32_t S, const uint32_t* na,
+__global__ void k_finish_halos(libhalo_halos h, uint32_t S, const uint32_t* start,
                                const double* sv2, const double* vm2) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;
-  h.n_assigned[s] = na[s];
+  h.n_assigned[s] = start[s + 1] - start[s];
   bool kept = h.merged_into[s] == (int32_t)s;
   h.sv2[s] = kept ? sv2[s] : 0.0;
   h.vmax2[s] = kept ? vm2[s] : 0.0;
@@ -492,8 +498,7 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
   uint32_t *ocnt = w.ocnt, *iflag = w.iflag, *ipos = w.ipos;
   uint32_t *ok0 = w.ok0, *ov0 = w.ov0, *ok1 = w.ok1, *ov1 = w.ov1;
   void* rtmp2 = w.rtmp2;
-  k_fill_u32<<<blocks_for(NN + 1, TB), TB, 0, s>>>(ocnt, NN + 1, 0u);
-  k_own_flags<<<blocks_for(n, TB), TB, 0, s>>>(deepest, (uint32_t)n, iflag, ocnt);
+  k_own_flags<<<blocks_for(n, TB), TB, 0, s>>>(deepest, (uint32_t)n, iflag);
   exclusive_scan<uint32_t>(iflag, ipos, n, dcnt + 3, stmp, s);
   k_own_compact<<<blocks_for(n, TB), TB, 0, s>>>(deepest, iflag, ipos, (uint32_t)n, ok0, ov0);
   const uint32_t M = readu(dcnt + 3, 4);
@@ -501,7 +506,7 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
   uint32_t* okey = fo ? ok1 : ok0;
   uint32_t* own = fo ? ov1 : ov0;
   uint32_t* ooff = w.ooff;
-  exclusive_scan<uint32_t>(ocnt, ooff, NN, ooff + NN, stmp, s);
+  k_own_offsets<<<blocks_for(NN + 1, TB), TB, 0, s>>>(okey, M, (uint32_t)NN, ooff);
 
   // ---- levels
   uint32_t *lstart = w.lstart, *lmulti = w.lmulti;
@@ -546,8 +551,6 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
   }
 
   // ---- final metric of every halo from all its particles
-  k_fill_u32<<<blocks_for(S, TB), TB, 0, s>>>(na, S, 0u);
-  k_count_assigned<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, (uint32_t)n, na);
   k_all_assigned<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, (uint32_t)n, iflag);
   exclusive_scan<uint32_t>(iflag, ipos, n, dcnt + 5, stmp, s);
   k_all_compact<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, iflag, ipos, (uint32_t)n, rb.seg,
@@ -555,7 +558,7 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
   const uint32_t MA = readu(dcnt + 5, 6);
   radial_sort(pos_dtype, x, y, z, box, h.xs, h.ys, h.zs, MA, S, rb, s);
   radial_sigma_vmax(vx, vy, vz, MA, S, rb, Gm, eps2, acc, vm, cur_sv2, cur_vm2, s);
-  k_finish_halos<<<blocks_for(S, TB), TB, 0, s>>>(h, S, na, cur_sv2, cur_vm2);
+  k_finish_halos<<<blocks_for(S, TB), TB, 0, s>>>(h, S, rb.start, cur_sv2, cur_vm2);
 
   // ---- host/sub relation
   k_kept_flags<<<blocks_for(S, TB), TB, 0, s>>>(h, S, flag);

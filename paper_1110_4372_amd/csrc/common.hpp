@@ -219,14 +219,31 @@ __device__ __forceinline__ float d2_6(float a0, float a1, float a2, float a3, fl
   return s;
 }
 
-// 1/sqrt(x) in FP64: hardware estimate refined by two Newton steps
-// y <- y (3/2 - (x/2) y^2), each step doubling the correct bits.
+// 1/sqrt(x) in FP64: the hardware estimate (relative error ~2^-23) refined
+// by one Newton step y <- y (3/2 - (x/2) y^2), which squares the error
+// (~2^-46, below the rounding of the potential sums it feeds).
 __device__ __forceinline__ double rsqrt_f64(double x) {
   double y = __builtin_amdgcn_rsq(x);
   const double h = 0.5 * x;
   y = y * __fma_rn(-h * y, y, 1.5);
-  y = y * __fma_rn(-h * y, y, 1.5);
   return y;
+}
+
+// Wave-aggregated atomic min at base[key] (same contract as agg_add_u32).
+__device__ __forceinline__ void agg_min_u32(uint32_t* base, uint32_t key, uint32_t val,
+                                            bool active) {
+  unsigned long long pending = __ballot(active);
+  const int lane = threadIdx.x & 63;
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const uint32_t k = __shfl(key, leader);
+    const unsigned long long same = __ballot(active && key == k) & pending;
+    uint32_t v = (same >> lane) & 1ull ? val : 0xFFFFFFFFu;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor(v, o));
+    if (lane == leader) atomicMin(base + k, v);
+    pending &= ~same;
+  }
 }
 
 // Wave-aggregated atomic add of `val` at base[key]: lanes sharing a key send

@@ -173,26 +173,35 @@ __global__ void k_compress(uint32_t* par, int64_t n) {
   uf_store(par + i, uf_root(par, (uint32_t)i));
 }
 
-// minidx[root] = smallest input index in the component, one atomic per cell.
+// minidx[root] = smallest input index in the component: per-cell minimum,
+// then one wave-aggregated atomic per cell (neighbouring cells share roots).
 __global__ void k_cell_min(const uint32_t* cell_start, int64_t ncell, int64_t n,
                            const uint32_t* perm, const uint32_t* par, uint32_t* minidx) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  const uint32_t a0 = cell_start[c];
-  const uint32_t a1 = (c + 1 < ncell) ? cell_start[c + 1] : (uint32_t)n;
-  uint32_t mn = 0xFFFFFFFFu;
-  for (uint32_t i = a0; i < a1; ++i) mn = min(mn, perm[i]);
-  atomicMin(minidx + par[c], mn);
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = c < ncell;
+  uint32_t mn = 0xFFFFFFFFu, root = 0;
+  if (ok) {
+    const uint32_t a0 = cell_start[c];
+    const uint32_t a1 = (c + 1 < ncell) ? cell_start[c + 1] : (uint32_t)n;
+    for (uint32_t i = a0; i < a1; ++i) mn = min(mn, perm[i]);
+    root = par[c];
+  }
+  agg_min_u32(minidx, root, mn, ok);
 }
 
-// Group sizes by label, one atomic per cell.
+// Group sizes by label, one wave-aggregated atomic per cell.
 __global__ void k_cell_sizes(const uint32_t* cell_start, int64_t ncell, int64_t n,
                              const uint32_t* par, const uint32_t* minidx, uint32_t* gsize) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  const uint32_t a0 = cell_start[c];
-  const uint32_t a1 = (c + 1 < ncell) ? cell_start[c + 1] : (uint32_t)n;
-  atomicAdd(gsize + minidx[par[c]], a1 - a0);
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = c < ncell;
+  uint32_t cnt = 0, lab = 0;
+  if (ok) {
+    const uint32_t a0 = cell_start[c];
+    const uint32_t a1 = (c + 1 < ncell) ? cell_start[c + 1] : (uint32_t)n;
+    cnt = a1 - a0;
+    lab = minidx[par[c]];
+  }
+  agg_add_u32(gsize, lab, cnt, ok);
 }
 
 __global__ void k_labels(const uint32_t* cell_of, const uint32_t* perm, const uint32_t* par,

@@ -16,57 +16,13 @@
 #include <algorithm>
 
 #include "primitives.hpp"
+#include "refine_common.hpp"
 #include "stages.hpp"
 
 namespace halo {
 
 namespace {
-
-constexpr int TB = 256;
-constexpr int kMomTile = 1024;       // particles per moment work item
-constexpr int kPairI = 256;          // i particles per pair work item
-constexpr int kPairJ = 2048;         // j particles per pair work item
-constexpr int kSelSmall = 4096;      // nodes up to this size select in LDS
-constexpr int kSelTile = 4096;       // elements per big-node select item
-constexpr unsigned kPersist = 4096;  // persistent grid of pair / moment kernels
-
-struct LevelNodes {
-  uint32_t* first;
-  uint32_t* count;
-  int32_t* parent;  // global row of the parent, -1 at level 0
-  uint32_t* fof;
-  uint32_t* canon;
-};
-
-struct NodeScratch {
-  I128* acc;                 // 8 per node: sum qx, qy, qz, q^2, sum wx, wy, wz, w^2
-  unsigned long long* ext;   // 6 per node: ordered min/max of u per axis (level 0)
-  double* prm;               // 12 per node: anchor xyz, ubar xyz, vbar xyz, isx, isv, active
-  uint32_t* kth;             // target rank (1-based)
-  float* ell2;
-  uint32_t* whole;
-  uint32_t* nch;
-  uint32_t* fch;
-  uint32_t* wmom;            // worklist offsets (K+1)
-  uint32_t* wpair;
-  uint32_t* big;             // big-node list for selection
-  uint32_t* wbig;
-  uint32_t* selp;            // prefix / remaining per big node
-  uint32_t* ghist;           // 256 per big node
-};
-
-__device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint32_t w) {
-  // last k with off[k] <= w (off non-decreasing, off[0] = 0)
-  uint32_t lo = 0, hi = K;
-  while (hi - lo > 1) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (off[mid] <= w)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
+using namespace refine;
 
 // ------------------------------------------------------------ level 0 ------
 __global__ void k_level0(const uint32_t* perm, const uint32_t* grp_first,
@@ -272,13 +228,17 @@ __global__ void k_norm6(const T* x, const T* y, const T* z, const float* vx, con
 }
 
 // ------------------------------------------------------------ pair kernels --
-__global__ void k_pair_items(const uint32_t* count, const double* prm, uint32_t K,
-                             uint32_t* items) {
+// Pair work items of the nodes selected by `which`: 0 = all-pairs nodes,
+// 1 = nodes whose grid search fell back, 2 = every node not on the grid.
+__global__ void k_pair_items(const uint32_t* count, const double* prm, const uint32_t* gstate,
+                             uint32_t K, int which, uint32_t* items) {
   uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   uint32_t n = count[k];
   bool active = prm[12 * (size_t)k + 11] != 0.0;
-  items[k] = active ? ((n + kPairI - 1) / kPairI) * ((n + kPairJ - 1) / kPairJ) : 0u;
+  uint32_t g = gstate[k];
+  bool sel = which == 0 ? g == 0u : (which == 1 ? g == 2u : g != 1u);
+  items[k] = (active && sel) ? ((n + kPairI - 1) / kPairI) * ((n + kPairJ - 1) / kPairJ) : 0u;
 }
 
 // Nearest-neighbour squared distance: D[i] = min_{j != i in node} d2(i, j).
@@ -368,6 +328,97 @@ __global__ void __launch_bounds__(TB)
           if (d <= l2 && troot[q] != ri) {
             uf_union(par, gi, first + jt + q);
             ri = uf_find(par, gi);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Particles that can link (D <= ell^2) of the all-pairs nodes, compacted in
+// level order so that each node's linkable particles stay contiguous.
+__global__ void k_link_flags(const uint32_t* lnode, const uint32_t* D, uint32_t M,
+                             NodeScratch sc, uint32_t* flag) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const uint32_t k = lnode[m];
+  flag[m] = (sc.prm[12 * (size_t)k + 11] != 0.0 && sc.gstate[k] != 1u &&
+             __uint_as_float(D[m]) <= sc.ell2[k])
+                ? 1u
+                : 0u;
+}
+
+__global__ void k_link_gather(const float* xi, size_t S, const uint32_t* flag,
+                              const uint32_t* pos, uint32_t M, float* cxi, uint32_t* lpos) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M || !flag[m]) return;
+  const uint32_t c = pos[m];
+  lpos[c] = m;
+#pragma unroll
+  for (int p = 0; p < 6; ++p) cxi[(size_t)p * S + c] = xi[(size_t)p * S + m];
+}
+
+__global__ void k_link_nodes(LevelNodes nd, const uint32_t* pos, uint32_t K, LevelNodes cn) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const uint32_t a = pos[nd.first[k]], b = pos[nd.first[k] + nd.count[k]];
+  cn.first[k] = a;
+  cn.count[k] = b - a;
+}
+
+__global__ void k_link_items(const uint32_t* ccount, uint32_t K, uint32_t* items) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const uint32_t n = ccount[k];
+  items[k] = ((n + kPairI - 1) / kPairI) * ((n + kPairJ - 1) / kPairJ);
+}
+
+// 6D FOF at ell^2 over the compacted linkable particles, pairs j > i.
+__global__ void __launch_bounds__(TB)
+    k_fof6c(const float* cxi, size_t S, LevelNodes cn, const uint32_t* lpos, uint32_t K,
+            const uint32_t* woff, uint32_t kb, uint32_t ke, const float* ell2, uint32_t* par) {
+  __shared__ float t[6][TB];
+  __shared__ uint32_t troot[TB];
+  const uint32_t w0 = woff[kb], w1 = woff[ke];
+  for (uint32_t w = w0 + blockIdx.x; w < w1; w += gridDim.x) {
+    const uint32_t k = seg_of(woff, K, w);
+    const uint32_t r = w - woff[k];
+    const uint32_t first = cn.first[k], n = cn.count[k];
+    const uint32_t tj = (n + kPairJ - 1) / kPairJ;
+    const uint32_t it = r / tj, jc = r % tj;
+    const uint32_t i0 = it * kPairI;
+    const uint32_t j0 = jc * kPairJ;
+    const uint32_t j1 = min(n, j0 + kPairJ);
+    if (j1 <= i0 + 1) continue;  // uniform over the block: no pair with j > i
+    const float l2 = ell2[k];
+    const uint32_t li = i0 + threadIdx.x;
+    const bool ok = li < n;
+    const uint32_t gi = first + (ok ? li : 0);
+    const uint32_t mi = lpos[gi];
+    float a[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a[c] = cxi[(size_t)c * S + gi];
+    uint32_t ri = ok ? uf_find(par, mi) : 0xFFFFFFFFu;
+    for (uint32_t jt = j0; jt < j1; jt += TB) {
+      __syncthreads();
+      const uint32_t lj = jt + threadIdx.x;
+      if (lj < j1) {
+        const uint32_t gj = first + lj;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) t[c][threadIdx.x] = cxi[(size_t)c * S + gj];
+        troot[threadIdx.x] = uf_find(par, lpos[gj]);
+      }
+      __syncthreads();
+      if (ok) {
+        const uint32_t nt = min((uint32_t)TB, j1 - jt);
+        uint32_t q = li >= jt ? li - jt + 1 : 0u;  // only j > i
+        for (; q < nt; ++q) {
+          float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], t[0][q], t[1][q], t[2][q],
+                         t[3][q], t[4][q], t[5][q]);
+          if (d <= l2 && troot[q] != ri) {
+            uf_union(par, mi, lpos[first + jt + q]);
+            ri = uf_find(par, mi);
           }
         }
       }
@@ -663,71 +714,66 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
   const uint32_t M = rd.h[0] + rd.h[1];
   const uint32_t Kmax = std::max<uint32_t>((uint32_t)G, M / (uint32_t)P.min_members + 1);
 
-  // workspace
-  size_t need = 0;
-  auto add = [&](size_t b) { need += (b + 255) & ~size_t(255); };
-  for (int q = 0; q < 4; ++q) add(4ull * M);         // lidx, lnode x2
-  add(4ull * 6 * M);                                 // xi planes
-  for (int q = 0; q < 8; ++q) add(4ull * (M + 1));   // D, par, csize, cflag, head, crank, hrank, cid
-  for (int q = 0; q < 4; ++q) add(4ull * (M + 1));   // sort key/val x2
-  add(radix_tmp_bytes(M));
-  add(4 * scan_tmp_elems<uint32_t>(M + 1));
-  for (int q = 0; q < 2; ++q) add(5 * 4ull * (Kmax + 1));  // level node arrays x2
-  add(16ull * 8 * Kmax);   // acc
-  add(8ull * 6 * Kmax);    // ext
-  add(8ull * 12 * Kmax);   // prm
-  add(8ull * 8 * Kmax);    // mom
-  for (int q = 0; q < 9; ++q) add(4ull * (Kmax + 2));  // kth ell2 whole nch fch wmom wpair big wbig
-  add(8ull * (M / kSelSmall + 2));                    // selp
-  add(4ull * 256 * (M / kSelSmall + 2));              // ghist
-  add(64);
-  ctx.ensure_ws(need + 65536);
-  Arena& A = ctx.ws;
-  A.reset();
-  uint32_t* lidx = A.take<uint32_t>(M);
-  uint32_t* lnode = A.take<uint32_t>(M);
-  uint32_t* lidx2 = A.take<uint32_t>(M);
-  uint32_t* lnode2 = A.take<uint32_t>(M);
-  float* xi = A.take<float>(6ull * M);
-  uint32_t* D = A.take<uint32_t>(M + 1);
-  uint32_t* par = A.take<uint32_t>(M + 1);
-  uint32_t* csize = A.take<uint32_t>(M + 1);
-  uint32_t* cflag = A.take<uint32_t>(M + 1);
-  uint32_t* head = A.take<uint32_t>(M + 1);
-  uint32_t* crank = A.take<uint32_t>(M + 1);
-  uint32_t* hrank = A.take<uint32_t>(M + 1);
-  uint32_t* cid = A.take<uint32_t>(M + 1);
-  uint32_t* k0 = A.take<uint32_t>(M + 1);
-  uint32_t* v0 = A.take<uint32_t>(M + 1);
-  uint32_t* k1 = A.take<uint32_t>(M + 1);
-  uint32_t* v1 = A.take<uint32_t>(M + 1);
-  void* rtmp = A.take<char>(radix_tmp_bytes(M));
-  uint32_t* stmp = A.take<uint32_t>(scan_tmp_elems<uint32_t>(M + 1));
+  // workspace (sized by a dry run of the same carving)
+  uint32_t *lidx, *lnode, *lidx2, *lnode2, *D, *par, *csize, *cflag, *head, *crank, *hrank,
+      *cid, *k0, *v0, *k1, *v1, *stmp, *dcnt, *lpos;
+  float *xi, *cxi;
+  LevelNodes cnodes;
+  void* rtmp;
+  double* mom;
   LevelNodes L[2];
-  for (int q = 0; q < 2; ++q) {
-    L[q].first = A.take<uint32_t>(Kmax + 1);
-    L[q].count = A.take<uint32_t>(Kmax + 1);
-    L[q].parent = A.take<int32_t>(Kmax + 1);
-    L[q].fof = A.take<uint32_t>(Kmax + 1);
-    L[q].canon = A.take<uint32_t>(Kmax + 1);
-  }
   NodeScratch sc;
-  sc.acc = A.take<I128>(8ull * Kmax);
-  sc.ext = A.take<unsigned long long>(6ull * Kmax);
-  sc.prm = A.take<double>(12ull * Kmax);
-  double* mom = A.take<double>(8ull * Kmax);
-  sc.kth = A.take<uint32_t>(Kmax + 2);
-  sc.ell2 = A.take<float>(Kmax + 2);
-  sc.whole = A.take<uint32_t>(Kmax + 2);
-  sc.nch = A.take<uint32_t>(Kmax + 2);
-  sc.fch = A.take<uint32_t>(Kmax + 2);
-  sc.wmom = A.take<uint32_t>(Kmax + 2);
-  sc.wpair = A.take<uint32_t>(Kmax + 2);
-  sc.big = A.take<uint32_t>(Kmax + 2);
-  sc.wbig = A.take<uint32_t>(Kmax + 2);
-  sc.selp = A.take<uint32_t>(2ull * (M / kSelSmall + 2));
-  sc.ghist = A.take<uint32_t>(256ull * (M / kSelSmall + 2));
-  uint32_t* dcnt = A.take<uint32_t>(16);
+  GridBufs gb;
+  carve_workspace(ctx, [&](Arena& A) {
+    lidx = A.take<uint32_t>(M);
+    lnode = A.take<uint32_t>(M);
+    lidx2 = A.take<uint32_t>(M);
+    lnode2 = A.take<uint32_t>(M);
+    xi = A.take<float>(6ull * M);
+    cxi = A.take<float>(6ull * M);
+    lpos = A.take<uint32_t>(M + 1);
+    cnodes.first = A.take<uint32_t>(Kmax + 1);
+    cnodes.count = A.take<uint32_t>(Kmax + 1);
+    D = A.take<uint32_t>(M + 1);
+    par = A.take<uint32_t>(M + 1);
+    csize = A.take<uint32_t>(M + 1);
+    cflag = A.take<uint32_t>(M + 1);
+    head = A.take<uint32_t>(M + 1);
+    crank = A.take<uint32_t>(M + 1);
+    hrank = A.take<uint32_t>(M + 1);
+    cid = A.take<uint32_t>(M + 1);
+    k0 = A.take<uint32_t>(M + 1);
+    v0 = A.take<uint32_t>(M + 1);
+    k1 = A.take<uint32_t>(M + 1);
+    v1 = A.take<uint32_t>(M + 1);
+    rtmp = A.take<char>(radix_tmp_bytes(M));
+    stmp = A.take<uint32_t>(scan_tmp_elems<uint32_t>(M + 1));
+    for (int q = 0; q < 2; ++q) {
+      L[q].first = A.take<uint32_t>(Kmax + 1);
+      L[q].count = A.take<uint32_t>(Kmax + 1);
+      L[q].parent = A.take<int32_t>(Kmax + 1);
+      L[q].fof = A.take<uint32_t>(Kmax + 1);
+      L[q].canon = A.take<uint32_t>(Kmax + 1);
+    }
+    sc.gstate = A.take<uint32_t>(Kmax + 2);
+    sc.acc = A.take<I128>(8ull * Kmax);
+    sc.ext = A.take<unsigned long long>(6ull * Kmax);
+    sc.prm = A.take<double>(12ull * Kmax);
+    mom = A.take<double>(8ull * Kmax);
+    sc.kth = A.take<uint32_t>(Kmax + 2);
+    sc.ell2 = A.take<float>(Kmax + 2);
+    sc.whole = A.take<uint32_t>(Kmax + 2);
+    sc.nch = A.take<uint32_t>(Kmax + 2);
+    sc.fch = A.take<uint32_t>(Kmax + 2);
+    sc.wmom = A.take<uint32_t>(Kmax + 2);
+    sc.wpair = A.take<uint32_t>(Kmax + 2);
+    sc.big = A.take<uint32_t>(Kmax + 2);
+    sc.wbig = A.take<uint32_t>(Kmax + 2);
+    sc.selp = A.take<uint32_t>(2ull * (M / kSelSmall + 2));
+    sc.ghist = A.take<uint32_t>(256ull * (M / kSelSmall + 2));
+    dcnt = A.take<uint32_t>(16);
+    grid_take(A, gb, M, Kmax);
+  });
 
   HALO_HIP(hipMemsetAsync(ctx.d_err, 0, sizeof(uint32_t), s));
   k_level0<<<blocks_for(M, TB), TB, 0, s>>>(perm, grp_first, grp_count, (uint32_t)G, M, lidx,
@@ -775,27 +821,32 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     // 2. normalised coordinates
     k_norm6<T><<<blocks_for(Mi, TB), TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, lnode, 0, Mi, box,
                                                  sc, xi, S);
-    // 3. nearest neighbours; 5. union-find parents
+    // 3. nearest neighbours: grid search for large nodes, all-pairs for the rest
     k_fill_u32<<<blocks_for(Mi, TB), TB, 0, s>>>(D, Mi, 0x7F800000u);
     k_iota<<<blocks_for(Mi, TB), TB, 0, s>>>(par, Mi);
-    k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, K, sc.wpair);
+    HALO_PROF(ctx, "grid_build", s,
+              grid_build(gb, xi, S, nd, K, lnode, Mi, M, sc, P.f, rd.h + 8, s, D,
+                         P.grid_min > 0 ? (uint32_t)P.grid_min : kGridMin));
+    k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, 0, sc.wpair);
     exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
     if (plain) {
       for (uint32_t k = 0; k < K; ++k) {
         uint32_t nn = hcount[k];
         unsigned g = ((nn + kPairI - 1) / kPairI) * ((nn + kPairJ - 1) / kPairJ);
         HALO_PROF(ctx, "k_nn", s, k_nn<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, D));
-        if (nn <= (uint32_t)kSelSmall) HALO_PROF(ctx, "k_select_small", s, k_select_small<<<1, TB, 0, s>>>(D, nd, k, k + 1, sc));
+        if (nn <= (uint32_t)kSelSmall)
+          HALO_PROF(ctx, "k_select_small", s,
+                    k_select_small<<<1, TB, 0, s>>>(D, nd, k, k + 1, sc));
       }
     } else {
       HALO_PROF(ctx, "k_nn", s, k_nn<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, D));
       HALO_PROF(ctx, "k_select_small", s, k_select_small<<<K, TB, 0, s>>>(D, nd, 0, K, sc));
     }
     // 4. selection for big nodes (both forms: a handful of nodes)
-    k_big_flags<<<blocks_for(K, TB), TB, 0, s>>>(nd, K, sc, cflag);
-    exclusive_scan<uint32_t>(cflag, head, K, dcnt, stmp, s);
-    k_big_list<<<blocks_for(K, TB), TB, 0, s>>>(cflag, head, K, nd, sc);
-    {
+    auto select_big = [&]() {
+      k_big_flags<<<blocks_for(K, TB), TB, 0, s>>>(nd, K, sc, cflag);
+      exclusive_scan<uint32_t>(cflag, head, K, dcnt, stmp, s);
+      k_big_list<<<blocks_for(K, TB), TB, 0, s>>>(cflag, head, K, nd, sc);
       uint32_t nbig = rd.get(dcnt, 3);
       if (nbig > 0) {
         exclusive_scan<uint32_t>(sc.wbig, sc.wbig, nbig, sc.wbig + nbig, stmp, s);
@@ -805,17 +856,32 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
           k_select_big_resolve<<<blocks_for(nbig, 64), 64, 0, s>>>(sc, dcnt, pass);
         }
       }
+    };
+    select_big();
+    // grid nodes whose ell^2 exceeds their search radius: all-pairs again
+    if (grid_check(gb, sc, lnode, Mi, D, rd.h + 8, s) > 0) {
+      k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, 1, sc.wpair);
+      exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
+      HALO_PROF(ctx, "k_nn", s, k_nn<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, D));
+      select_big();
     }
-    // 5. 6D FOF
+    // 5. 6D FOF: all-pairs nodes over their compacted linkable particles
+    k_link_flags<<<blocks_for(Mi, TB), TB, 0, s>>>(lnode, D, Mi, sc, cflag);
+    exclusive_scan<uint32_t>(cflag, crank, Mi, crank + Mi, stmp, s);
+    k_link_gather<<<blocks_for(Mi, TB), TB, 0, s>>>(xi, S, cflag, crank, Mi, cxi, lpos);
+    k_link_nodes<<<blocks_for(K, TB), TB, 0, s>>>(nd, crank, K, cnodes);
+    k_link_items<<<blocks_for(K, TB), TB, 0, s>>>(cnodes.count, K, sc.wpair);
+    exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
     if (plain) {
       for (uint32_t k = 0; k < K; ++k) {
         uint32_t nn = hcount[k];
         unsigned g = ((nn + kPairI - 1) / kPairI) * ((nn + kPairJ - 1) / kPairJ);
-        HALO_PROF(ctx, "k_fof6", s, k_fof6<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, D, sc.ell2, par));
+        HALO_PROF(ctx, "k_fof6", s, k_fof6c<<<g, TB, 0, s>>>(cxi, S, cnodes, lpos, K, sc.wpair, k, k + 1, sc.ell2, par));
       }
     } else {
-      HALO_PROF(ctx, "k_fof6", s, k_fof6<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, D, sc.ell2, par));
+      HALO_PROF(ctx, "k_fof6", s, k_fof6c<<<kPersist, TB, 0, s>>>(cxi, S, cnodes, lpos, K, sc.wpair, 0, K, sc.ell2, par));
     }
+    HALO_PROF(ctx, "grid_fof", s, grid_fof(gb, sc, D, par, s));
     k_compress<<<blocks_for(Mi, TB), TB, 0, s>>>(par, Mi);
     // 6. children
     k_fill_u32<<<blocks_for(Mi, TB), TB, 0, s>>>(csize, Mi, 0u);

@@ -1,0 +1,86 @@
+// Level-synchronous hierarchy state shared by the refinement kernels.
+#pragma once
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace halo {
+namespace refine {
+
+constexpr int TB = 256;
+constexpr int kMomTile = 1024;       // particles per moment work item
+constexpr int kPairI = 256;          // i particles per pair work item
+constexpr int kPairJ = 2048;         // j particles per pair work item
+constexpr int kSelSmall = 4096;      // nodes up to this size select in LDS
+constexpr int kSelTile = 4096;       // elements per big-node select item
+constexpr unsigned kPersist = 4096;  // persistent grid of pair / moment kernels
+
+struct LevelNodes {
+  uint32_t* first;
+  uint32_t* count;
+  int32_t* parent;  // global row of the parent, -1 at level 0
+  uint32_t* fof;
+  uint32_t* canon;
+};
+
+struct NodeScratch {
+  uint32_t* gstate;          // 0 all-pairs, 1 grid search, 2 grid fell back to all-pairs
+  I128* acc;                 // 8 per node: sum qx, qy, qz, q^2, sum wx, wy, wz, w^2
+  unsigned long long* ext;   // 6 per node: ordered min/max of u per axis (level 0)
+  double* prm;               // 12 per node: anchor xyz, ubar xyz, vbar xyz, isx, isv, active
+  uint32_t* kth;             // target rank (1-based)
+  float* ell2;
+  uint32_t* whole;
+  uint32_t* nch;
+  uint32_t* fch;
+  uint32_t* wmom;            // worklist offsets (K+1)
+  uint32_t* wpair;
+  uint32_t* big;             // big-node list for selection
+  uint32_t* wbig;
+  uint32_t* selp;            // prefix / remaining per big node
+  uint32_t* ghist;           // 256 per big node
+};
+
+__device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint32_t w) {
+  // last k with off[k] <= w (off non-decreasing, off[0] = 0)
+  uint32_t lo = 0, hi = K;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= w)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+
+// ---- exact fixed-radius tile search for large nodes (grid6d.hip) ----
+constexpr uint32_t kGridMin = 131072; // default: nodes above this size use the tile search
+constexpr uint32_t kGridFloor = 64;   // smallest accepted threshold
+constexpr int kSamples = 512;         // sample size of the radius estimate
+
+struct GridBufs {
+  uint32_t *nb_rank, *gnode, *ncell, *cellbase, *pstart, *gcount, *gtile_node;
+  float *samp, *r2, *tbox;
+  uint32_t *flag, *pos, *v0, *v1, *gm, *cnt, *stmp;
+  unsigned long long *k0, *k1;
+  float* gx;  // six planes of stride MB, sorted order
+  void* rtmp;
+  uint32_t MB = 0, NB = 0, NT = 0;
+};
+
+void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax);
+// Classifies the level's nodes (sc.gstate), builds the grid of the large ones
+// and writes their nearest-neighbour distances into D.  Returns their number.
+uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint32_t K,
+                    const uint32_t* lnode, uint32_t Mi, uint32_t M, NodeScratch sc, double f,
+                    uint32_t* hb, hipStream_t s, uint32_t* D, uint32_t gmin);
+// After the selection: nodes whose ell^2 exceeds their search radius get
+// gstate 2 and their D reset; returns how many.
+uint32_t grid_check(GridBufs& g, NodeScratch sc, const uint32_t* lnode, uint32_t Mi,
+                    uint32_t* D, uint32_t* hb, hipStream_t s);
+void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par, hipStream_t s);
+
+}  // namespace refine
+}  // namespace halo

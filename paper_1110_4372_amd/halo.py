@@ -34,7 +34,8 @@ class CParams(C.Structure):
                 ("merge_q2", C.c_double), ("particle_mass", C.c_double), ("G", C.c_double),
                 ("rho_vir", C.c_double), ("softening", C.c_double), ("core_frac", C.c_double),
                 ("unbound_threshold", C.c_double), ("e_recheck", C.c_double),
-                ("mode", C.c_int32), ("prec", C.c_int32)]
+                ("mode", C.c_int32), ("prec", C.c_int32), ("grid_min", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 @dataclasses.dataclass
@@ -54,12 +55,13 @@ class Params:
     e_recheck: float = 1e-4
     mode: int = BATCHED
     prec: int = PREC_FP64
+    grid_min: int = 0
 
     def c(self) -> CParams:
         return CParams(self.box, self.b, self.f, self.min_members, self.max_levels,
                        self.merge_q2, self.particle_mass, self.G, self.rho_vir,
                        self.softening, self.core_frac, self.unbound_threshold,
-                       self.e_recheck, self.mode, self.prec)
+                       self.e_recheck, self.mode, self.prec, self.grid_min, 0)
 
 
 NODE_FIELDS = [("parent", torch.int32), ("level", torch.int32), ("first_child", torch.int32),

@@ -53,34 +53,42 @@ def assert_nodes_equal(g, o):
             raise AssertionError(f"field {f} differs at rows {bad}: gpu {a[bad]} oracle {b[bad]}")
 
 
-def run_both(H, orc, pos, vel, box, mode=1, m=1e10, eps=0.01):
+def run_both(H, orc, pos, vel, box, mode=1, m=1e10, eps=0.01, grid_min=0):
     P = particles(orc, pos, vel)
     p = orc.make_params(box, m, eps)
     lab = orc.fof3d(p, P)
     onodes, odeep = orc.refine6d(p, P, lab)
-    ctx = H.Halo(H.Params(box=box, particle_mass=m, softening=eps, mode=mode))
+    ctx = H.Halo(H.Params(box=box, particle_mass=m, softening=eps, mode=mode,
+                          grid_min=grid_min))
     GP = particles_from_arrays(pos, vel)
     fof = ctx.fof3d(GP)
     gnodes, gdeep = ctx.refine6d(GP, fof)
     return onodes, odeep, gpu_nodes(gnodes), to_np(gdeep)
 
 
-@pytest.mark.parametrize("n,seed,f64,mode", [(3000, 5, True, 1), (6000, 6, False, 1),
-                                             (3000, 5, True, 0), (12001, 7, False, 1)])
-def test_refine_clustered(H, orc, n, seed, f64, mode):
-    note(f"refine6d clustered n={n} seed={seed} f64={f64} mode={mode}")
+@pytest.mark.parametrize("n,seed,f64,mode,grid_min", [(3000, 5, True, 1, 0),
+                                                      (6000, 6, False, 1, 0),
+                                                      (3000, 5, True, 0, 0),
+                                                      (12001, 7, False, 1, 0),
+                                                      (12001, 7, False, 1, 64),
+                                                      (20000, 8, False, 1, 0)])
+def test_refine_clustered(H, orc, n, seed, f64, mode, grid_min):
+    note(f"refine6d clustered n={n} seed={seed} f64={f64} mode={mode} grid_min={grid_min}")
     box = 10.0 * (n / 1500) ** (1 / 3)
-    pos, vel = clustered(n, box, seed, nblob=4, spread=0.25, f64=f64)
-    on, od, gn, gd = run_both(H, orc, pos, vel, box, mode=mode)
+    nblob = 2 if n >= 20000 else 4
+    pos, vel = clustered(n, box, seed, nblob=nblob, spread=0.25, f64=f64)
+    on, od, gn, gd = run_both(H, orc, pos, vel, box, mode=mode, grid_min=grid_min)
     assert on["parent"].shape[0] > 4
     assert_nodes_equal(gn, on)
     np.testing.assert_array_equal(gd, od)
 
 
-@pytest.mark.parametrize("mode", [1, 0])
-def test_refine_c1(H, orc, c1, c1_oracle, mode):
-    note(f"refine6d c1 mode={mode}")
-    ctx = H.Halo(H.params_for_catalog(c1, mode=mode))
+@pytest.mark.parametrize("mode,grid_min", [(1, 0), (0, 0), (1, 64), (1, 1000)])
+def test_refine_c1(H, orc, c1, c1_oracle, mode, grid_min):
+    """grid_min = 64 sends every node above 64 particles through the exact grid
+    neighbour search; the node table must not change."""
+    note(f"refine6d c1 mode={mode} grid_min={grid_min}")
+    ctx = H.Halo(H.params_for_catalog(c1, mode=mode, grid_min=grid_min))
     P = H.Particles.from_catalog(c1)
     fof = ctx.fof3d(P)
     gn, gd = ctx.refine6d(P, fof)
@@ -125,8 +133,8 @@ def test_refine_repeat_and_modes_agree(H, c1):
     note("refine6d repeat x8 and plain == batched")
     outs = []
     P = H.Particles.from_catalog(c1)
-    for mode in (1, 0, 1, 0, 1, 0, 1, 0):
-        ctx = H.Halo(H.params_for_catalog(c1, mode=mode))
+    for mode, gm in ((1, 0), (0, 0), (1, 64), (0, 64), (1, 0), (0, 0), (1, 64), (0, 0)):
+        ctx = H.Halo(H.params_for_catalog(c1, mode=mode, grid_min=gm))
         gn, gd = ctx.refine6d(P, ctx.fof3d(P))
         outs.append((gpu_nodes(gn), to_np(gd)))
     for gn, gd in outs[1:]:
