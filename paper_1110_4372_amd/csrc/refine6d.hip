@@ -228,111 +228,114 @@ __global__ void k_norm6(const T* x, const T* y, const T* z, const float* vx, con
 }
 
 // ------------------------------------------------------------ pair kernels --
-// Pair work items of the nodes selected by `which`: 0 = all-pairs nodes,
-// 1 = nodes whose grid search fell back, 2 = every node not on the grid.
+// Nearest-neighbour work unit: 64 particles of a node (one wavefront, lane =
+// particle) against one j-chunk of the node.  The chunk is at least kNNJ
+// particles, a multiple of 64, and grows with the node so a node has at most
+// 64 chunks.
+__host__ __device__ __forceinline__ uint32_t nn_chunk(uint32_t n) {
+  uint32_t c = (n + 63u) / 64u;
+  c = (c + 63u) & ~63u;
+  return c > (uint32_t)kNNJ ? c : (uint32_t)kNNJ;
+}
+
+__host__ __device__ __forceinline__ uint32_t nn_units(uint32_t n) {
+  const uint32_t J = nn_chunk(n);
+  return ((n + 63u) / 64u) * ((n + J - 1) / J);
+}
+
+// Units of the nodes selected by `which`: 0 = all-pairs nodes, 1 = nodes whose
+// grid search fell back.
 __global__ void k_pair_items(const uint32_t* count, const double* prm, const uint32_t* gstate,
                              uint32_t K, int which, uint32_t* items) {
   uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
-  uint32_t n = count[k];
-  bool active = prm[12 * (size_t)k + 11] != 0.0;
-  uint32_t g = gstate[k];
-  bool sel = which == 0 ? g == 0u : (which == 1 ? g == 2u : g != 1u);
-  items[k] = (active && sel) ? ((n + kPairI - 1) / kPairI) * ((n + kPairJ - 1) / kPairJ) : 0u;
+  const uint32_t n = count[k];
+  const bool active = prm[12 * (size_t)k + 11] != 0.0;
+  const uint32_t g = gstate[k];
+  const bool sel = which == 0 ? g == 0u : g == 2u;
+  items[k] = (active && sel) ? nn_units(n) : 0u;
 }
 
-// Nearest-neighbour squared distance: D[i] = min_{j != i in node} d2(i, j).
-__global__ void __launch_bounds__(TB)
-    k_nn(const float* xi, size_t S, LevelNodes nd, uint32_t K, const uint32_t* woff,
-         uint32_t kb, uint32_t ke, uint32_t* D) {
-  __shared__ float t[6][TB];
-  const uint32_t w0 = woff[kb], w1 = woff[ke];
-  for (uint32_t w = w0 + blockIdx.x; w < w1; w += gridDim.x) {
-    const uint32_t k = seg_of(woff, K, w);
-    const uint32_t r = w - woff[k];
-    const uint32_t first = nd.first[k], n = nd.count[k];
-    const uint32_t tj = (n + kPairJ - 1) / kPairJ;
-    const uint32_t it = r / tj, jc = r % tj;
-    const uint32_t li = it * kPairI + threadIdx.x;
-    const bool ok = li < n;
-    const uint32_t gi = first + (ok ? li : 0);
-    float a[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) a[c] = xi[(size_t)c * S + gi];
-    float best = __int_as_float(0x7F800000);
-    const uint32_t j0 = jc * kPairJ;
-    const uint32_t j1 = min(n, j0 + kPairJ);
-    for (uint32_t jt = j0; jt < j1; jt += TB) {
-      __syncthreads();
-      const uint32_t lj = jt + threadIdx.x;
-      if (lj < j1) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) t[c][threadIdx.x] = xi[(size_t)c * S + first + lj];
-      }
-      __syncthreads();
-      const uint32_t nt = min((uint32_t)TB, j1 - jt);
-      for (uint32_t q = 0; q < nt; ++q) {
-        float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], t[0][q], t[1][q], t[2][q],
-                       t[3][q], t[4][q], t[5][q]);
-        if (jt + q != li && d < best) best = d;
-      }
-    }
-    if (ok) atomicMin(D + gi, __float_as_uint(best));
-    __syncthreads();
+// Next unit of this wavefront (whole wave active): from the shared counter or
+// by striding over the grid; readfirstlane makes the value wave-uniform for
+// the compiler, which keeps unit bounds and j loads scalar.
+__device__ __forceinline__ uint32_t wave_next_unit(uint32_t* ctr, uint32_t u0, uint32_t t) {
+  uint32_t v;
+  if (ctr) {
+    v = 0;
+    if ((threadIdx.x & 63u) == 0) v = atomicAdd(ctr, 1u);
+  } else {
+    const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
+    v = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) + t * nw;
   }
+  return u0 + __builtin_amdgcn_readfirstlane(v);
 }
 
-// 6D FOF at ell^2 over pairs j > i; both particles must have a friend.
+// min over j in [j0, j1) of d2(i, j); the six j coordinates are wave-uniform
+// scalar loads.  kSelf: skip j == self.
+template <bool kSelf>
+__device__ __forceinline__ float nn_span(const float* __restrict__ xi, size_t S, uint32_t j0,
+                                         uint32_t j1, uint32_t self, const float* a,
+                                         float best) {
+  uint32_t j = j0;
+  for (; j + 8 <= j1; j += 8) {
+    float b[6][8];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const float* __restrict__ p = xi + (size_t)c * S + j;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b[c][u] = p[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], b[0][u], b[1][u], b[2][u],
+                           b[3][u], b[4][u], b[5][u]);
+      if (kSelf)
+        best = (j + u != self) ? fminf(best, d) : best;
+      else
+        best = fminf(best, d);
+    }
+  }
+  for (; j < j1; ++j) {
+    const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], xi[j], xi[S + j], xi[2 * S + j],
+                         xi[3 * S + j], xi[4 * S + j], xi[5 * S + j]);
+    if (!kSelf || j != self) best = fminf(best, d);
+  }
+  return best;
+}
+
+// Nearest-neighbour squared distance: D[i] = min_{j != i in node} d2(i, j),
+// over the units [woff[kb], woff[ke]).  Each unit folds its minimum into D
+// with an atomic min on the FP32 bits (non-negative floats order as integers).
 __global__ void __launch_bounds__(TB)
-    k_fof6(const float* xi, size_t S, LevelNodes nd, uint32_t K, const uint32_t* woff,
-           uint32_t kb, uint32_t ke, const uint32_t* D, const float* ell2, uint32_t* par) {
-  __shared__ float t[6][TB];
-  __shared__ uint32_t troot[TB];
-  const uint32_t w0 = woff[kb], w1 = woff[ke];
-  const float qnan = __int_as_float(0x7FC00000);
-  for (uint32_t w = w0 + blockIdx.x; w < w1; w += gridDim.x) {
-    const uint32_t k = seg_of(woff, K, w);
-    const uint32_t r = w - woff[k];
+    k_nn(const float* __restrict__ xi, size_t S, LevelNodes nd, uint32_t K,
+         const uint32_t* __restrict__ woff, uint32_t kb, uint32_t ke, uint32_t* ctr,
+         uint32_t* D) {
+  const uint32_t u0 = woff[kb], u1 = woff[ke];
+  for (uint32_t t = 0;; ++t) {
+    const uint32_t u = wave_next_unit(ctr, u0, t);
+    if (u >= u1) break;
+    const uint32_t k = seg_of(woff, K, u);
+    const uint32_t local = u - woff[k];
     const uint32_t first = nd.first[k], n = nd.count[k];
-    const uint32_t tj = (n + kPairJ - 1) / kPairJ;
-    const uint32_t it = r / tj, jc = r % tj;
-    const uint32_t i0 = it * kPairI;
-    const uint32_t j0 = jc * kPairJ;
-    const uint32_t j1 = min(n, j0 + kPairJ);
-    if (j1 <= i0 + 1) continue;  // uniform over the block: no pair with j > i
-    const float l2 = ell2[k];
-    const uint32_t li = i0 + threadIdx.x;
-    const bool ok = li < n && __uint_as_float(D[first + (li < n ? li : 0)]) <= l2;
-    const uint32_t gi = first + (li < n ? li : 0);
+    const uint32_t J = nn_chunk(n);
+    const uint32_t ni = (n + 63u) / 64u;
+    const uint32_t c = local / ni, it = local - c * ni;
+    const uint32_t li = it * 64u + (threadIdx.x & 63u);
+    const bool ok = li < n;
+    const uint32_t gi = first + (ok ? li : 0u);
     float a[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) a[c] = xi[(size_t)c * S + gi];
-    uint32_t ri = ok ? uf_find(par, gi) : 0xFFFFFFFFu;
-    for (uint32_t jt = j0; jt < j1; jt += TB) {
-      __syncthreads();
-      const uint32_t lj = jt + threadIdx.x;
-      if (lj < j1) {
-        const uint32_t gj = first + lj;
-        const bool lj_ok = __uint_as_float(D[gj]) <= l2;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) t[c][threadIdx.x] = lj_ok ? xi[(size_t)c * S + gj] : qnan;
-        troot[threadIdx.x] = lj_ok ? uf_find(par, gj) : 0xFFFFFFFFu;
-      }
-      __syncthreads();
-      if (ok) {
-        const uint32_t nt = min((uint32_t)TB, j1 - jt);
-        for (uint32_t q = 0; q < nt; ++q) {
-          if (jt + q <= li) continue;
-          float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], t[0][q], t[1][q], t[2][q],
-                         t[3][q], t[4][q], t[5][q]);
-          if (d <= l2 && troot[q] != ri) {
-            uf_union(par, gi, first + jt + q);
-            ri = uf_find(par, gi);
-          }
-        }
-      }
-    }
-    __syncthreads();
+    for (int q = 0; q < 6; ++q) a[q] = xi[(size_t)q * S + gi];
+    const uint32_t j0 = c * J, j1 = min(j0 + J, n);
+    // the wave's own particles [s0, s1) lie wholly inside or outside the chunk
+    uint32_t s0 = it * 64u, s1 = min(s0 + 64u, n);
+    if (s0 < j0 || s0 >= j1) s0 = s1 = j1;
+    float best = __int_as_float(0x7F800000);
+    best = nn_span<false>(xi, S, first + j0, first + s0, 0u, a, best);
+    best = nn_span<true>(xi, S, first + s0, first + s1, first + li, a, best);
+    best = nn_span<false>(xi, S, first + s1, first + j1, 0u, a, best);
+    if (ok) atomicMin(D + gi, __float_as_uint(best));
   }
 }
 
@@ -832,14 +835,17 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     if (plain) {
       for (uint32_t k = 0; k < K; ++k) {
         uint32_t nn = hcount[k];
-        unsigned g = ((nn + kPairI - 1) / kPairI) * ((nn + kPairJ - 1) / kPairJ);
-        HALO_PROF(ctx, "k_nn", s, k_nn<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, D));
+        const unsigned g = blocks_for(nn_units(nn), TB / 64);
+        HALO_PROF(ctx, "k_nn", s,
+                  k_nn<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, nullptr, D));
         if (nn <= (uint32_t)kSelSmall)
           HALO_PROF(ctx, "k_select_small", s,
                     k_select_small<<<1, TB, 0, s>>>(D, nd, k, k + 1, sc));
       }
     } else {
-      HALO_PROF(ctx, "k_nn", s, k_nn<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, D));
+      k_fill_u32<<<1, 64, 0, s>>>(dcnt + 8, 1, 0u);
+      HALO_PROF(ctx, "k_nn", s,
+                k_nn<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, D));
       HALO_PROF(ctx, "k_select_small", s, k_select_small<<<K, TB, 0, s>>>(D, nd, 0, K, sc));
     }
     // 4. selection for big nodes (both forms: a handful of nodes)
@@ -862,7 +868,9 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     if (grid_check(gb, sc, lnode, Mi, D, rd.h + 8, s) > 0) {
       k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, 1, sc.wpair);
       exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
-      HALO_PROF(ctx, "k_nn", s, k_nn<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, D));
+      k_fill_u32<<<1, 64, 0, s>>>(dcnt + 8, 1, 0u);
+      HALO_PROF(ctx, "k_nn", s,
+                k_nn<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, D));
       select_big();
     }
     // 5. 6D FOF: all-pairs nodes over their compacted linkable particles

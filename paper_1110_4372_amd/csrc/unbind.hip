@@ -177,12 +177,6 @@ __global__ void k_vbulk(const I128* accS, const uint32_t* nS, uint32_t S, double
         nS[s] ? ldexp(i128_to_f64(accS[3 * (size_t)s + c]) / n, -kVelShift) : 0.0;
 }
 
-__global__ void k_pot_items(const libhalo_halos h, uint32_t S, uint32_t* items) {
-  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  items[s] = h.merged_into[s] == (int32_t)s ? (h.n_assigned[s] + TB - 1) / TB : 0u;
-}
-
 __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint32_t w) {
   uint32_t lo = 0, hi = K;
   while (hi - lo > 1) {
@@ -195,109 +189,269 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint
   return lo;
 }
 
-// FP64 direct sum: sum_j 1/sqrt(r^2 + eps^2) over S(h), j != i.  Terms use the
-// hardware rsqrt estimate refined by two Newton steps (FP64-accurate).
-__global__ void __launch_bounds__(TB)
-    k_potential_f64(const double* ux, const double* uy, const double* uz, const libhalo_halos h,
-                    uint32_t S, const uint32_t* slot, const uint32_t* nS, const uint32_t* woff,
-                    uint32_t kb, uint32_t ke, double eps2, double* sum) {
-  __shared__ double tx[TB], ty[TB], tz[TB];
-  const uint32_t w0 = woff[kb], w1 = woff[ke];
-  for (uint32_t w = w0 + blockIdx.x; w < w1; w += gridDim.x) {
-    const uint32_t hh = seg_of(woff, S, w);
-    const uint32_t it = w - woff[hh];
-    const uint32_t base = slot[hh], nown = h.n_assigned[hh], ns = nS[hh];
-    const uint32_t li = it * TB + threadIdx.x;
-    const bool ok = li < nown;
-    const uint32_t qi = base + (ok ? li : 0);
-    const double xi = ux[qi], yi = uy[qi], zi = uz[qi];
-    double acc0 = 0.0, acc1 = 0.0;
-    for (uint32_t jt = 0; jt < ns; jt += TB) {
-      __syncthreads();
-      if (jt + threadIdx.x < ns) {
-        tx[threadIdx.x] = ux[base + jt + threadIdx.x];
-        ty[threadIdx.x] = uy[base + jt + threadIdx.x];
-        tz[threadIdx.x] = uz[base + jt + threadIdx.x];
-      }
-      __syncthreads();
-      const uint32_t nt = min((uint32_t)TB, ns - jt);
-      const uint32_t self = li - jt;  // tile index of i itself (may be out of range)
-      uint32_t q = 0;
-      for (; q + 2 <= nt; q += 2) {
-        double dx0 = tx[q] - xi, dy0 = ty[q] - yi, dz0 = tz[q] - zi;
-        double dx1 = tx[q + 1] - xi, dy1 = ty[q + 1] - yi, dz1 = tz[q + 1] - zi;
-        double r0 = __fma_rn(dz0, dz0, __fma_rn(dy0, dy0, __fma_rn(dx0, dx0, eps2)));
-        double r1 = __fma_rn(dz1, dz1, __fma_rn(dy1, dy1, __fma_rn(dx1, dx1, eps2)));
-        double t0 = rsqrt_f64(r0), t1 = rsqrt_f64(r1);
-        acc0 += (q != self) ? t0 : 0.0;
-        acc1 += (q + 1 != self) ? t1 : 0.0;
-      }
-      if (q < nt) {
-        double dx0 = tx[q] - xi, dy0 = ty[q] - yi, dz0 = tz[q] - zi;
-        double r0 = __fma_rn(dz0, dz0, __fma_rn(dy0, dy0, __fma_rn(dx0, dx0, eps2)));
-        double t0 = rsqrt_f64(r0);
-        acc0 += (q != self) ? t0 : 0.0;
-      }
+// ------------------------------------------------------------ potentials --
+// Work unit: 64 own particles (one wavefront, lane = particle) of a halo
+// against one j-chunk of its S(h).  The chunk is at least kPotJ particles and
+// grows with |S(h)| so a halo has at most 64 chunks.  Each unit writes one
+// partial sum per particle; the partials of a particle are added in chunk
+// order afterwards, so the result does not depend on which wave ran which unit.
+constexpr uint32_t kPotJ = 2048;
+
+__host__ __device__ __forceinline__ uint32_t pot_chunk(uint32_t ns) {
+  uint32_t c = (ns + 63u) / 64u;
+  c = (c + 63u) & ~63u;
+  return c > kPotJ ? c : kPotJ;
+}
+
+// Per kept halo: unit and partial counts; the sort key orders units by cost,
+// largest first (a unit costs ~ 64 * min(|S(h)|, chunk) terms).
+__global__ void k_pot_counts(const libhalo_halos h, uint32_t S, const uint32_t* nS,
+                             uint32_t* ucnt, unsigned long long* pcnt, uint32_t* key,
+                             uint32_t* val) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const uint32_t nown = h.n_assigned[s], ns = nS[s];
+  const bool on = h.merged_into[s] == (int32_t)s && nown > 0;
+  const uint32_t J = pot_chunk(ns);
+  const uint32_t nc = (ns + J - 1) / J;
+  ucnt[s] = on ? ((nown + 63u) / 64u) * nc : 0u;
+  pcnt[s] = on ? (unsigned long long)nown * nc : 0ull;
+  key[s] = on ? ~min(ns, J) : 0xFFFFFFFFu;
+  val[s] = s;
+}
+
+__global__ void k_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t n,
+                             uint32_t* dst) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = src[idx[k]];
+}
+
+struct PotUnit {
+  uint32_t hh, base, nown, ns, i, j0, j1, s0, s1, c;
+};
+
+// Decodes unit u: the units of halo order[k] are [uoff[k], uoff[k+1]),
+// chunk-major so that concurrent waves share a j-chunk.
+__device__ __forceinline__ PotUnit pot_unit(const libhalo_halos& h, const uint32_t* order,
+                                            const uint32_t* uoff, uint32_t K,
+                                            const uint32_t* slot, const uint32_t* nS,
+                                            uint32_t u) {
+  PotUnit r;
+  const uint32_t k = seg_of(uoff, K, u);
+  r.hh = order[k];
+  const uint32_t local = u - uoff[k];
+  r.nown = h.n_assigned[r.hh];
+  r.ns = nS[r.hh];
+  r.base = slot[r.hh];
+  const uint32_t J = pot_chunk(r.ns);
+  const uint32_t ni = (r.nown + 63u) / 64u;
+  r.c = local / ni;
+  const uint32_t it = local - r.c * ni;
+  r.i = it * 64u + (threadIdx.x & 63u);
+  r.j0 = r.c * J;
+  r.j1 = min(r.j0 + J, r.ns);
+  // the wave's own particles [s0, s1) lie wholly inside the chunk or wholly
+  // outside it, since the chunk length is a multiple of 64
+  r.s0 = it * 64u;
+  r.s1 = min(r.s0 + 64u, r.ns);
+  if (r.s0 < r.j0 || r.s0 >= r.j1) r.s0 = r.s1 = r.j1;
+  return r;
+}
+
+// Next unit of this wavefront: from the shared counter (dynamic) or by
+// striding over the grid (static).  Called with the whole wave active, so
+// readfirstlane reads lane 0 and marks the result wave-uniform for the
+// compiler (which then keeps the unit's bounds and j loads scalar).
+__device__ __forceinline__ uint32_t pot_next(uint32_t* ctr, uint32_t u0, uint32_t t) {
+  uint32_t v;
+  if (ctr) {
+    v = 0;
+    if ((threadIdx.x & 63u) == 0) v = atomicAdd(ctr, 1u);
+  } else {
+    const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
+    v = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) + t * nw;
+  }
+  return u0 + __builtin_amdgcn_readfirstlane(v);
+}
+
+// FP64 terms 1/sqrt(r^2 + eps^2) for j in [j0, j1) of the layout.  The j
+// coordinates are wave-uniform and come in through scalar loads as operands of
+// the vector ops.  y0 = hardware rsqrt estimate (about 2^-24 relative); one
+// Newton step gives y0 + y0 e / 2 with e = 1 - r y0^2, so the terms are kept
+// as A = sum y0 and C = sum y0 e and combined as A + C / 2.
+// kSelf: skip j == self (only the span holding the wave's own particles).
+template <bool kSelf>
+__device__ __forceinline__ void pot_span_f64(const double* __restrict__ ux,
+                                             const double* __restrict__ uy,
+                                             const double* __restrict__ uz, uint32_t j0,
+                                             uint32_t j1, uint32_t self, double xi, double yi,
+                                             double zi, double eps2, double* A, double* C) {
+  uint32_t j = j0;
+  for (; j + 8 <= j1; j += 8) {
+    const double* __restrict__ px = ux + j;
+    const double* __restrict__ py = uy + j;
+    const double* __restrict__ pz = uz + j;
+    double bx[8], by[8], bz[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      bx[u] = px[u];
+      by[u] = py[u];
+      bz[u] = pz[u];
     }
-    if (ok) sum[qi] = acc0 + acc1;
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double dx = bx[u] - xi, dy = by[u] - yi, dz = bz[u] - zi;
+      const double r = __fma_rn(dz, dz, __fma_rn(dy, dy, __fma_rn(dx, dx, eps2)));
+      double y = __builtin_amdgcn_rsq(r);
+      const double e = __fma_rn(-(r * y), y, 1.0);
+      if (kSelf) y = (j + u != self) ? y : 0.0;
+      A[u & 3] += y;
+      C[u & 3] = __fma_rn(y, e, C[u & 3]);
+    }
+  }
+  for (; j < j1; ++j) {
+    const double dx = ux[j] - xi, dy = uy[j] - yi, dz = uz[j] - zi;
+    const double r = __fma_rn(dz, dz, __fma_rn(dy, dy, __fma_rn(dx, dx, eps2)));
+    double y = __builtin_amdgcn_rsq(r);
+    const double e = __fma_rn(-(r * y), y, 1.0);
+    if (kSelf) y = (j != self) ? y : 0.0;
+    A[0] += y;
+    C[0] = __fma_rn(y, e, C[0]);
   }
 }
 
-// Mixed precision: FP32 coordinates relative to the halo's first particle,
-// FP32 rsqrt terms, Kahan-compensated FP32 sum per thread.
+// FP64 form: one partial sum over a j-chunk per own particle and unit.
 __global__ void __launch_bounds__(TB)
-    k_potential_f32(const double* ux, const double* uy, const double* uz, const libhalo_halos h,
-                    uint32_t S, const uint32_t* slot, const uint32_t* nS, const uint32_t* woff,
-                    uint32_t kb, uint32_t ke, float eps2, double* sum) {
-  __shared__ float tx[TB], ty[TB], tz[TB];
-  const uint32_t w0 = woff[kb], w1 = woff[ke];
-  for (uint32_t w = w0 + blockIdx.x; w < w1; w += gridDim.x) {
-    const uint32_t hh = seg_of(woff, S, w);
-    const uint32_t it = w - woff[hh];
-    const uint32_t base = slot[hh], nown = h.n_assigned[hh], ns = nS[hh];
-    const double ox = ux[base], oy = uy[base], oz = uz[base];
-    const uint32_t li = it * TB + threadIdx.x;
-    const bool ok = li < nown;
-    const uint32_t qi = base + (ok ? li : 0);
-    const float xi = (float)(ux[qi] - ox), yi = (float)(uy[qi] - oy), zi = (float)(uz[qi] - oz);
-    float acc = 0.0f, comp = 0.0f;
-    for (uint32_t jt = 0; jt < ns; jt += TB) {
-      __syncthreads();
-      if (jt + threadIdx.x < ns) {
-        tx[threadIdx.x] = (float)(ux[base + jt + threadIdx.x] - ox);
-        ty[threadIdx.x] = (float)(uy[base + jt + threadIdx.x] - oy);
-        tz[threadIdx.x] = (float)(uz[base + jt + threadIdx.x] - oz);
-      }
-      __syncthreads();
-      const uint32_t nt = min((uint32_t)TB, ns - jt);
-      const uint32_t self = li - jt;
-      float p0 = 0.0f, p1 = 0.0f;
-      uint32_t q = 0;
-      for (; q + 2 <= nt; q += 2) {
-        float dx0 = tx[q] - xi, dy0 = ty[q] - yi, dz0 = tz[q] - zi;
-        float dx1 = tx[q + 1] - xi, dy1 = ty[q + 1] - yi, dz1 = tz[q + 1] - zi;
-        float r0 = __fmaf_rn(dz0, dz0, __fmaf_rn(dy0, dy0, __fmaf_rn(dx0, dx0, eps2)));
-        float r1 = __fmaf_rn(dz1, dz1, __fmaf_rn(dy1, dy1, __fmaf_rn(dx1, dx1, eps2)));
-        float t0 = __builtin_amdgcn_rsqf(r0), t1 = __builtin_amdgcn_rsqf(r1);
-        p0 += (q != self) ? t0 : 0.0f;
-        p1 += (q + 1 != self) ? t1 : 0.0f;
-      }
-      if (q < nt) {
-        float dx0 = tx[q] - xi, dy0 = ty[q] - yi, dz0 = tz[q] - zi;
-        float r0 = __fmaf_rn(dz0, dz0, __fmaf_rn(dy0, dy0, __fmaf_rn(dx0, dx0, eps2)));
-        p0 += (q != self) ? __builtin_amdgcn_rsqf(r0) : 0.0f;
-      }
-      const float part = p0 + p1;
-      // Kahan step per tile
-      float yk = part - comp;
-      float tk = acc + yk;
-      comp = (tk - acc) - yk;
-      acc = tk;
-    }
-    if (ok) sum[qi] = (double)acc - (double)comp;
-    __syncthreads();
+    k_potential_f64(const double* __restrict__ ux, const double* __restrict__ uy,
+                    const double* __restrict__ uz, const libhalo_halos h,
+                    const uint32_t* __restrict__ order, const uint32_t* __restrict__ uoff,
+                    uint32_t K, const uint32_t* __restrict__ slot,
+                    const uint32_t* __restrict__ nS, const unsigned long long* __restrict__ poff,
+                    uint32_t u0, uint32_t u1, uint32_t* ctr, double eps2,
+                    double* __restrict__ part) {
+  for (uint32_t t = 0;; ++t) {
+    const uint32_t u = pot_next(ctr, u0, t);
+    if (u >= u1) break;
+    const PotUnit w = pot_unit(h, order, uoff, K, slot, nS, u);
+    const bool ok = w.i < w.nown;
+    const uint32_t qi = w.base + (ok ? w.i : 0u);
+    const double xi = ux[qi], yi = uy[qi], zi = uz[qi];
+    double A[4] = {0.0, 0.0, 0.0, 0.0}, C[4] = {0.0, 0.0, 0.0, 0.0};
+    const uint32_t b = w.base;
+    pot_span_f64<false>(ux, uy, uz, b + w.j0, b + w.s0, 0u, xi, yi, zi, eps2, A, C);
+    pot_span_f64<true>(ux, uy, uz, b + w.s0, b + w.s1, b + w.i, xi, yi, zi, eps2, A, C);
+    pot_span_f64<false>(ux, uy, uz, b + w.s1, b + w.j1, 0u, xi, yi, zi, eps2, A, C);
+    const double a = (A[0] + A[1]) + (A[2] + A[3]);
+    const double c = (C[0] + C[1]) + (C[2] + C[3]);
+    if (ok) part[poff[w.hh] + (unsigned long long)w.c * w.nown + w.i] = __fma_rn(0.5, c, a);
   }
+}
+
+// FP32 terms for j in [j0, j1): relative FP32 coordinates, hardware FP32
+// rsqrt, four partial sums folded every 64 terms into a compensated sum.
+template <bool kSelf>
+__device__ __forceinline__ void pot_span_f32(const float* __restrict__ fx,
+                                             const float* __restrict__ fy,
+                                             const float* __restrict__ fz, uint32_t j0,
+                                             uint32_t j1, uint32_t self, float xi, float yi,
+                                             float zi, float eps2, float& acc, float& comp) {
+  uint32_t j = j0;
+  while (j < j1) {
+    const uint32_t je = min(j + 64u, j1);
+    float p[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (; j + 8 <= je; j += 8) {
+      const float* __restrict__ px = fx + j;
+      const float* __restrict__ py = fy + j;
+      const float* __restrict__ pz = fz + j;
+      float bx[8], by[8], bz[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        bx[u] = px[u];
+        by[u] = py[u];
+        bz[u] = pz[u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float dx = bx[u] - xi, dy = by[u] - yi, dz = bz[u] - zi;
+        const float r = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2)));
+        float y = __builtin_amdgcn_rsqf(r);
+        if (kSelf) y = (j + u != self) ? y : 0.0f;
+        p[u & 3] += y;
+      }
+    }
+    for (; j < je; ++j) {
+      const float dx = fx[j] - xi, dy = fy[j] - yi, dz = fz[j] - zi;
+      const float r = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2)));
+      float y = __builtin_amdgcn_rsqf(r);
+      if (kSelf) y = (j != self) ? y : 0.0f;
+      p[0] += y;
+    }
+    const float s = (p[0] + p[1]) + (p[2] + p[3]);
+    const float yk = s - comp;
+    const float tk = acc + yk;
+    comp = (tk - acc) - yk;
+    acc = tk;
+  }
+}
+
+// Mixed form: FP32 coordinates relative to the first particle of the
+// outermost host of the halo's tree (one origin per contiguous tree range).
+__global__ void k_rel_f32(const double* ux, const double* uy, const double* uz,
+                          const libhalo_halos h, const uint32_t* slot, const uint32_t* lhalo,
+                          uint32_t m, float* fx, float* fy, float* fz) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  int32_t r = (int32_t)lhalo[q];
+  while (h.host[r] >= 0) r = h.host[r];
+  const uint32_t o = slot[r];
+  fx[q] = (float)(ux[q] - ux[o]);
+  fy[q] = (float)(uy[q] - uy[o]);
+  fz[q] = (float)(uz[q] - uz[o]);
+}
+
+__global__ void __launch_bounds__(TB)
+    k_potential_f32(const float* __restrict__ fx, const float* __restrict__ fy,
+                    const float* __restrict__ fz, const libhalo_halos h,
+                    const uint32_t* __restrict__ order, const uint32_t* __restrict__ uoff,
+                    uint32_t K, const uint32_t* __restrict__ slot,
+                    const uint32_t* __restrict__ nS, const unsigned long long* __restrict__ poff,
+                    uint32_t u0, uint32_t u1, uint32_t* ctr, float eps2,
+                    double* __restrict__ part) {
+  for (uint32_t t = 0;; ++t) {
+    const uint32_t u = pot_next(ctr, u0, t);
+    if (u >= u1) break;
+    const PotUnit w = pot_unit(h, order, uoff, K, slot, nS, u);
+    const bool ok = w.i < w.nown;
+    const uint32_t qi = w.base + (ok ? w.i : 0u);
+    const float xi = fx[qi], yi = fy[qi], zi = fz[qi];
+    float acc = 0.0f, comp = 0.0f;
+    const uint32_t b = w.base;
+    pot_span_f32<false>(fx, fy, fz, b + w.j0, b + w.s0, 0u, xi, yi, zi, eps2, acc, comp);
+    pot_span_f32<true>(fx, fy, fz, b + w.s0, b + w.s1, b + w.i, xi, yi, zi, eps2, acc, comp);
+    pot_span_f32<false>(fx, fy, fz, b + w.s1, b + w.j1, 0u, xi, yi, zi, eps2, acc, comp);
+    if (ok)
+      part[poff[w.hh] + (unsigned long long)w.c * w.nown + w.i] = (double)acc - (double)comp;
+  }
+}
+
+// sum[q] = the particle's chunk partials added in chunk order.
+__global__ void k_pot_reduce(const libhalo_halos h, const uint32_t* lhalo, const uint32_t* slot,
+                             const uint32_t* nS, const unsigned long long* poff,
+                             const double* part, uint32_t m, double* sum) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const uint32_t hh = lhalo[q];
+  if (h.merged_into[hh] != (int32_t)hh) {
+    sum[q] = 0.0;
+    return;
+  }
+  const uint32_t i = q - slot[hh], nown = h.n_assigned[hh], ns = nS[hh];
+  const uint32_t J = pot_chunk(ns);
+  const uint32_t nc = (ns + J - 1) / J;
+  const double* p = part + poff[hh] + i;
+  double s = p[0];
+  for (uint32_t c = 1; c < nc; ++c) s += p[(size_t)c * nown];
+  sum[q] = s;
 }
 
 // FP64 recheck of one particle's potential (mixed form), one block per particle.
@@ -435,10 +589,11 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
   }
   struct W {
     uint32_t *flag, *pos, *ck0, *cv0, *ck1, *cv1, *ccnt, *coff, *nS, *depth, *slot, *rootv,
-        *dcnt, *stmp, *ak0, *av0, *ak1, *av1, *gfirst, *lp, *lhalo, *woff, *nb_own, *nbS,
-        *rlist;
+        *dcnt, *stmp, *ak0, *av0, *ak1, *av1, *gfirst, *lp, *lhalo, *nb_own, *nbS, *rlist,
+        *ucnt, *uoff, *pk0, *pv0, *pk1, *pv1;
+    unsigned long long *pcnt, *poff, *stmp64;
     double *ux, *uy, *uz, *vb, *sum;
-    float *lvx, *lvy, *lvz;
+    float *lvx, *lvy, *lvz, *fx, *fy, *fz;
     I128 *accO, *accS;
     void *rtmp;
   } w;
@@ -465,7 +620,15 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     w.gfirst = A.take<uint32_t>(S2);
     w.lp = A.take<uint32_t>(N2);
     w.lhalo = A.take<uint32_t>(N2);
-    w.woff = A.take<uint32_t>(S2);
+    w.ucnt = A.take<uint32_t>(S2);
+    w.uoff = A.take<uint32_t>(S2);
+    w.pk0 = A.take<uint32_t>(S2);
+    w.pv0 = A.take<uint32_t>(S2);
+    w.pk1 = A.take<uint32_t>(S2);
+    w.pv1 = A.take<uint32_t>(S2);
+    w.pcnt = A.take<unsigned long long>(S2);
+    w.poff = A.take<unsigned long long>(S2);
+    w.stmp64 = A.take<unsigned long long>(scan_tmp_elems<unsigned long long>(S2));
     w.nb_own = A.take<uint32_t>(S2);
     w.nbS = A.take<uint32_t>(S2);
     w.rlist = A.take<uint32_t>(N2);
@@ -477,6 +640,9 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     w.lvx = A.take<float>(N2);
     w.lvy = A.take<float>(N2);
     w.lvz = A.take<float>(N2);
+    w.fx = mixed ? A.take<float>(N2) : nullptr;
+    w.fy = mixed ? A.take<float>(N2) : nullptr;
+    w.fz = mixed ? A.take<float>(N2) : nullptr;
     w.accO = A.take<I128>(3 * S2);
     w.accS = A.take<I128>(3 * S2);
     w.rtmp = A.take<char>(radix_tmp_bytes(std::max(S2, N2)));
@@ -528,31 +694,53 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
   if (m > 0) k_own_vsum<<<blocks_for(m, TB), TB, 0, s>>>(w.lvx, w.lvy, w.lvz, w.lhalo, m, w.accO);
   k_chain_vsum<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.accO, w.accS);
   k_vbulk<<<blocks_for(S, TB), TB, 0, s>>>(w.accS, w.nS, S, w.vb);
-  // potentials
-  k_pot_items<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.woff);
-  exclusive_scan<uint32_t>(w.woff, w.woff, S, w.woff + S, w.stmp, s);
+  // potentials: work units ordered largest first, one partial per particle
+  // and j-chunk, partials added in chunk order
+  k_pot_counts<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, w.ucnt, w.pcnt, w.pk0, w.pv0);
+  const bool fo = radix_sort_pairs<uint32_t>(w.pk0, w.pv0, w.pk1, w.pv1, S, 32, w.rtmp, s);
+  const uint32_t* order = fo ? w.pv1 : w.pv0;
+  k_gather_u32<<<blocks_for(S, TB), TB, 0, s>>>(w.ucnt, order, S, w.uoff);
+  exclusive_scan<uint32_t>(w.uoff, w.uoff, S, w.uoff + S, w.stmp, s);
+  exclusive_scan<unsigned long long>(w.pcnt, w.poff, S, w.poff + S, w.stmp64, s);
+  unsigned long long* hb64 = ctx.host_slot<unsigned long long>(1);
+  HALO_HIP(hipMemcpyAsync(hb64, w.poff + S, 8, hipMemcpyDeviceToHost, s));
+  const uint32_t U = readu(w.uoff + S, 2);
+  const unsigned long long NP = *hb64;
   if (m > 0) {
+    double* part = static_cast<double*>(ctx.ensure_aux(8ull * (NP ? NP : 1ull)));
+    if (mixed)
+      k_rel_f32<<<blocks_for(m, TB), TB, 0, s>>>(w.ux, w.uy, w.uz, h, w.slot, w.lhalo, m, w.fx,
+                                                 w.fy, w.fz);
+    auto launch = [&](uint32_t u0, uint32_t u1, uint32_t* ctr, unsigned grid) {
+      if (mixed)
+        HALO_PROF(ctx, "k_potential_f32", s,
+                  k_potential_f32<<<grid, TB, 0, s>>>(w.fx, w.fy, w.fz, h, order, w.uoff, S,
+                                                      w.slot, w.nS, w.poff, u0, u1, ctr,
+                                                      (float)eps2, part));
+      else
+        HALO_PROF(ctx, "k_potential_f64", s,
+                  k_potential_f64<<<grid, TB, 0, s>>>(w.ux, w.uy, w.uz, h, order, w.uoff, S,
+                                                      w.slot, w.nS, w.poff, u0, u1, ctr, eps2,
+                                                      part));
+    };
     if (plain) {
-      std::vector<uint32_t> ho(S + 1);
-      HALO_HIP(hipMemcpyAsync(ho.data(), w.woff, 4ull * (S + 1), hipMemcpyDeviceToHost, s));
+      // one launch per halo, in halo order, each over that halo's units
+      std::vector<uint32_t> ho(S + 1), ord(S);
+      HALO_HIP(hipMemcpyAsync(ho.data(), w.uoff, 4ull * (S + 1), hipMemcpyDeviceToHost, s));
+      HALO_HIP(hipMemcpyAsync(ord.data(), order, 4ull * S, hipMemcpyDeviceToHost, s));
       HALO_HIP(hipStreamSynchronize(s));
+      std::vector<uint32_t> pos(S);
+      for (uint32_t k = 0; k < S; ++k) pos[ord[k]] = k;
       for (uint32_t hh = 0; hh < S; ++hh) {
-        uint32_t g = ho[hh + 1] - ho[hh];
-        if (!g) continue;
-        if (mixed)
-          HALO_PROF(ctx, "k_potential_f32", s, k_potential_f32<<<g, TB, 0, s>>>(w.ux, w.uy, w.uz, h, S, w.slot, w.nS, w.woff, hh,
-                                           hh + 1, (float)eps2, w.sum));
-        else
-          HALO_PROF(ctx, "k_potential_f64", s, k_potential_f64<<<g, TB, 0, s>>>(w.ux, w.uy, w.uz, h, S, w.slot, w.nS, w.woff, hh,
-                                           hh + 1, eps2, w.sum));
+        const uint32_t k = pos[hh], nu = ho[k + 1] - ho[k];
+        if (nu) launch(ho[k], ho[k + 1], nullptr, blocks_for(nu, TB / 64));
       }
-    } else if (mixed) {
-      HALO_PROF(ctx, "k_potential_f32", s, k_potential_f32<<<kPersist, TB, 0, s>>>(w.ux, w.uy, w.uz, h, S, w.slot, w.nS, w.woff, 0, S,
-                                              (float)eps2, w.sum));
-    } else {
-      HALO_PROF(ctx, "k_potential_f64", s, k_potential_f64<<<kPersist, TB, 0, s>>>(w.ux, w.uy, w.uz, h, S, w.slot, w.nS, w.woff, 0, S,
-                                              eps2, w.sum));
+    } else if (U > 0) {
+      k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 4, 1, 0u);
+      launch(0, U, w.dcnt + 4, kPersist);
     }
+    k_pot_reduce<<<blocks_for(m, TB), TB, 0, s>>>(h, w.lhalo, w.slot, w.nS, w.poff, part, m,
+                                                  w.sum);
     k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 3, 1, 0u);
     k_energy<<<blocks_for(m, TB), TB, 0, s>>>(w.sum, w.lvx, w.lvy, w.lvz, w.lhalo, w.lp, w.vb, m,
                                              mGm, P.e_recheck, mixed ? 1 : 0, bound, phi,
