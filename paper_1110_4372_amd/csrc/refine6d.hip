@@ -377,56 +377,110 @@ __global__ void k_link_items(const uint32_t* ccount, uint32_t K, uint32_t* items
   items[k] = ((n + kPairI - 1) / kPairI) * ((n + kPairJ - 1) / kPairJ);
 }
 
-// 6D FOF at ell^2 over the compacted linkable particles, pairs j > i.
+// One block of at most 64 j (node-local [jb, je)) against the wave's particles:
+// bit q of the lane's mask marks j = jb + q as a friend of particle li.  rootv
+// holds roots of the block's particles found when its tile was staged; a lane
+// joins its set with a friend only when that root differs from its own (a
+// skipped pair had equal roots at some point, and sets only merge).
+// kDiag: the block holding the wave's own particles, where only j > i counts.
+template <bool kDiag>
+__device__ __forceinline__ void fof_block(const float* __restrict__ cxi, size_t S,
+                                          uint32_t first, uint32_t jb, uint32_t je,
+                                          uint32_t li, bool ok, const float* a, float l2,
+                                          const uint32_t* __restrict__ lpos, uint32_t mi,
+                                          uint32_t& ri, uint32_t* par, const uint32_t* rootv) {
+  unsigned long long fm = 0ull;
+  uint32_t j = jb;
+  for (; j + 8 <= je; j += 8) {
+    float b[6][8];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const float* __restrict__ p = cxi + (size_t)c * S + first + j;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b[c][u] = p[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], b[0][u], b[1][u], b[2][u],
+                           b[3][u], b[4][u], b[5][u]);
+      const bool f = ok && d <= l2 && (!kDiag || j + u > li);
+      fm |= f ? (1ull << (j - jb + u)) : 0ull;
+    }
+  }
+  for (; j < je; ++j) {
+    const uint32_t g = first + j;
+    const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], cxi[g], cxi[S + g],
+                         cxi[2 * S + g], cxi[3 * S + g], cxi[4 * S + g], cxi[5 * S + g]);
+    const bool f = ok && d <= l2 && (!kDiag || j > li);
+    fm |= f ? (1ull << (j - jb)) : 0ull;
+  }
+  while (fm) {
+    const uint32_t q = (uint32_t)__builtin_ctzll(fm);
+    fm &= fm - 1ull;
+    if (rootv[q] != ri) ri = uf_union(par, mi, lpos[first + jb + q]);
+  }
+}
+
+// 6D FOF at ell^2 over the compacted linkable particles of all-pairs nodes,
+// pairs j > i.  Work item: kPairI particles of a node (a block, one per
+// thread) against a kPairJ chunk, taken in tiles of TB: the block finds the
+// roots of a tile's particles (one per thread, into LDS), then each wave
+// streams the tile's coordinates as scalar loads in blocks of 64.
 __global__ void __launch_bounds__(TB)
-    k_fof6c(const float* cxi, size_t S, LevelNodes cn, const uint32_t* lpos, uint32_t K,
-            const uint32_t* woff, uint32_t kb, uint32_t ke, const float* ell2, uint32_t* par) {
-  __shared__ float t[6][TB];
+    k_fof6(const float* __restrict__ cxi, size_t S, LevelNodes cn,
+           const uint32_t* __restrict__ lpos, uint32_t K, const uint32_t* __restrict__ woff,
+           uint32_t kb, uint32_t ke, uint32_t* ctr, const float* __restrict__ ell2,
+           uint32_t* par) {
   __shared__ uint32_t troot[TB];
-  const uint32_t w0 = woff[kb], w1 = woff[ke];
-  for (uint32_t w = w0 + blockIdx.x; w < w1; w += gridDim.x) {
-    const uint32_t k = seg_of(woff, K, w);
-    const uint32_t r = w - woff[k];
+  __shared__ uint32_t su;
+  const uint32_t u0 = woff[kb], u1 = woff[ke];
+  for (uint32_t t = 0;; ++t) {
+    uint32_t v;
+    if (ctr) {
+      __syncthreads();
+      if (threadIdx.x == 0) su = atomicAdd(ctr, 1u);
+      __syncthreads();
+      v = su;
+    } else {
+      v = blockIdx.x + t * gridDim.x;
+    }
+    const uint32_t u = u0 + __builtin_amdgcn_readfirstlane(v);
+    if (u >= u1) break;
+    const uint32_t k = seg_of(woff, K, u);
+    const uint32_t r = u - woff[k];
     const uint32_t first = cn.first[k], n = cn.count[k];
     const uint32_t tj = (n + kPairJ - 1) / kPairJ;
-    const uint32_t it = r / tj, jc = r % tj;
+    const uint32_t it = r / tj, jc = r - it * tj;
     const uint32_t i0 = it * kPairI;
-    const uint32_t j0 = jc * kPairJ;
-    const uint32_t j1 = min(n, j0 + kPairJ);
-    if (j1 <= i0 + 1) continue;  // uniform over the block: no pair with j > i
-    const float l2 = ell2[k];
+    const uint32_t j0 = jc * kPairJ, j1 = min(n, j0 + kPairJ);
+    if (j1 <= i0 + 1) continue;  // block-uniform: no pair with j > i
     const uint32_t li = i0 + threadIdx.x;
     const bool ok = li < n;
-    const uint32_t gi = first + (ok ? li : 0);
+    const uint32_t gi = first + (ok ? li : 0u);
     const uint32_t mi = lpos[gi];
+    uint32_t ri = mi;
+    const float l2 = ell2[k];
     float a[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) a[c] = cxi[(size_t)c * S + gi];
-    uint32_t ri = ok ? uf_find(par, mi) : 0xFFFFFFFFu;
-    for (uint32_t jt = j0; jt < j1; jt += TB) {
+    for (int q = 0; q < 6; ++q) a[q] = cxi[(size_t)q * S + gi];
+    const uint32_t w0 = i0 + (threadIdx.x & ~63u);  // the wave's first particle
+    for (uint32_t jt = max(j0, i0); jt < j1; jt += TB) {
       __syncthreads();
       const uint32_t lj = jt + threadIdx.x;
-      if (lj < j1) {
-        const uint32_t gj = first + lj;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) t[c][threadIdx.x] = cxi[(size_t)c * S + gj];
-        troot[threadIdx.x] = uf_find(par, lpos[gj]);
-      }
+      troot[threadIdx.x] = lj < j1 ? uf_find(par, lpos[first + lj]) : 0xFFFFFFFFu;
       __syncthreads();
-      if (ok) {
-        const uint32_t nt = min((uint32_t)TB, j1 - jt);
-        uint32_t q = li >= jt ? li - jt + 1 : 0u;  // only j > i
-        for (; q < nt; ++q) {
-          float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], t[0][q], t[1][q], t[2][q],
-                         t[3][q], t[4][q], t[5][q]);
-          if (d <= l2 && troot[q] != ri) {
-            uf_union(par, mi, lpos[first + jt + q]);
-            ri = uf_find(par, mi);
-          }
-        }
+      const uint32_t te = min(jt + TB, j1);
+      for (uint32_t jb = jt; jb < te; jb += 64u) {
+        if (jb < w0) continue;  // every j of the block is below the wave's i
+        const uint32_t je = min(jb + 64u, te);
+        if (jb == w0)
+          fof_block<true>(cxi, S, first, jb, je, li, ok, a, l2, lpos, mi, ri, par,
+                          troot + (jb - jt));
+        else
+          fof_block<false>(cxi, S, first, jb, je, li, ok, a, l2, lpos, mi, ri, par,
+                           troot + (jb - jt));
       }
     }
-    __syncthreads();
   }
 }
 
@@ -882,12 +936,17 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
     if (plain) {
       for (uint32_t k = 0; k < K; ++k) {
-        uint32_t nn = hcount[k];
-        unsigned g = ((nn + kPairI - 1) / kPairI) * ((nn + kPairJ - 1) / kPairJ);
-        HALO_PROF(ctx, "k_fof6", s, k_fof6c<<<g, TB, 0, s>>>(cxi, S, cnodes, lpos, K, sc.wpair, k, k + 1, sc.ell2, par));
+        const uint32_t nn = hcount[k];
+        const unsigned g = ((nn + kPairI - 1) / kPairI) * ((nn + kPairJ - 1) / kPairJ);
+        HALO_PROF(ctx, "k_fof6", s,
+                  k_fof6<<<g, TB, 0, s>>>(cxi, S, cnodes, lpos, K, sc.wpair, k, k + 1, nullptr,
+                                          sc.ell2, par));
       }
     } else {
-      HALO_PROF(ctx, "k_fof6", s, k_fof6c<<<kPersist, TB, 0, s>>>(cxi, S, cnodes, lpos, K, sc.wpair, 0, K, sc.ell2, par));
+      k_fill_u32<<<1, 64, 0, s>>>(dcnt + 8, 1, 0u);
+      HALO_PROF(ctx, "k_fof6", s,
+                k_fof6<<<kPersist, TB, 0, s>>>(cxi, S, cnodes, lpos, K, sc.wpair, 0, K,
+                                               dcnt + 8, sc.ell2, par));
     }
     HALO_PROF(ctx, "grid_fof", s, grid_fof(gb, sc, D, par, s));
     k_compress<<<blocks_for(Mi, TB), TB, 0, s>>>(par, Mi);

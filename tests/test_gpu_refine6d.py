@@ -165,3 +165,24 @@ def test_refine_velocity_blobs(H, orc):
     on, od, gn, gd = run_both(H, orc, pos, vel, 32.0, m=1e10)
     assert_nodes_equal(gn, on)
     np.testing.assert_array_equal(gd, od)
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+def test_refine_duplicate_clumps(H, orc, mode):
+    """Two clumps of 250 particles with identical phase-space coordinates in a
+    2000-particle halo: every pair inside a clump is a 6D friend at distance 0
+    (dense friend masks in every block of the pair pass), and the clump nodes
+    come out degenerate (zero dispersion)."""
+    note(f"refine6d duplicate clumps mode={mode}")
+    rng = np.random.default_rng(21)
+    n, c = 2000, 250
+    pos = 16.0 + 0.15 * rng.standard_normal((n, 3))
+    vel = (40.0 * rng.standard_normal((n, 3))).astype(np.float32)
+    pos[:c] = (16.05, 16.0, 16.0)
+    vel[:c] = (60.0, 0.0, 0.0)
+    pos[c:2 * c] = (15.95, 16.0, 16.0)
+    vel[c:2 * c] = (-60.0, 0.0, 0.0)
+    on, od, gn, gd = run_both(H, orc, pos, vel, 32.0, m=1e10, mode=mode)
+    assert np.any((on["flags"] & 2) != 0), "expected degenerate nodes"
+    assert_nodes_equal(gn, on)
+    np.testing.assert_array_equal(gd, od)
