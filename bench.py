@@ -74,7 +74,8 @@ def pair_work(ctx, P, out):
     cnt = nodes["count"].cpu().numpy().astype(np.float64)
     flags = nodes["flags"].cpu().numpy()
     active = (flags & 2) == 0
-    nn_pairs = float(np.sum(cnt[active] ** 2))
+    # distinct pairs per node: the nearest-neighbour pass evaluates each once
+    nn_pairs = float(np.sum(cnt[active] * (cnt[active] - 1.0) / 2.0))
     h = {k: v.cpu().numpy() for k, v in halos.items()}
     ns = unb["n_s"].cpu().numpy().astype(np.float64)
     kept = h["merged_into"] == np.arange(h["merged_into"].shape[0])
@@ -148,8 +149,9 @@ def main():
     pot_name = "k_potential_f64" if prec == H.PREC_FP64 else "k_potential_f32"
     t_pot, l_pot = kern[pot_name]
     t_nn, l_nn = kern["k_nn"]
-    # per pair: potential 12 FLOP (3 sub, r^2 with 1 mul + 2 fma, + eps^2, sqrt,
-    # div, accumulate); nearest neighbour 17 FLOP (6 sub, 1 mul, 5 fma)
+    # per term: potential 12 FLOP (3 sub, r^2 with 1 mul + 2 fma, + eps^2, sqrt,
+    # div, accumulate) over ordered (own, S(h)) pairs; nearest neighbour 17 FLOP
+    # (6 sub, 1 mul, 5 fma) per distinct pair of a node
     cands = {
         pot_name: (t_pot, l_pot, pot_pairs * 12.0,
                    FP64_PEAK_TFLOPS if prec == H.PREC_FP64 else FP32_PEAK_TFLOPS),

@@ -234,6 +234,78 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
   return y;
 }
 
+// Per-segment accumulation over segment-sorted elements, one element per
+// thread, whole block active: NC exact sums at acc[NC * h + c], a max of
+// non-negative doubles at vm[h] (as bits) and an optional count at cnt[h].
+// A wave whose elements share one segment reduces them into LDS; thread 0
+// then merges runs of equal segment across the block's NW waves, so a large
+// segment costs one set of atomics per block.  A wave spanning several
+// segments adds per element.  h = 0xFFFFFFFF marks an absent element.
+template <int NC, int NW>
+struct SegMerge {
+  uint32_t h[NW];
+  I128 v[NW][NC];
+  double t[NW];
+  uint32_t c[NW];
+};
+
+template <int NC, int NW>
+__device__ __forceinline__ void seg_merge_add(SegMerge<NC, NW>& L, uint32_t h, I128* v,
+                                              double t, uint32_t c, I128* acc,
+                                              unsigned long long* vm, uint32_t* cnt) {
+  const uint32_t none = 0xFFFFFFFFu;
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t h0 = __builtin_amdgcn_readfirstlane(h);
+  if (__all(h == h0) && h0 != none) {
+    for (int o = 32; o > 0; o >>= 1) {
+      t = fmax(t, __shfl_xor(t, o));
+      c += __shfl_xor(c, o);
+    }
+    for (int k = 0; k < NC; ++k) v[k] = wave_sum_i128(v[k]);
+    if ((threadIdx.x & 63) == 0) {
+      L.h[wave] = h0;
+      for (int k = 0; k < NC; ++k) L.v[wave][k] = v[k];
+      L.t[wave] = t;
+      L.c[wave] = c;
+    }
+  } else {
+    if ((threadIdx.x & 63) == 0) L.h[wave] = none;
+    if (h != none) {
+      for (int k = 0; k < NC; ++k)
+        if (v[k].lo != 0 || v[k].hi != 0) atomic_add_i128(acc + NC * (size_t)h + k, v[k]);
+      if (t > 0.0) atomicMax(vm + h, (unsigned long long)__double_as_longlong(t));
+      if (cnt && c) atomicAdd(cnt + h, c);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t cur = none, sc = 0;
+    I128 s[NC];
+    double sm = 0.0;
+    for (int w = 0; w <= NW; ++w) {
+      const uint32_t hw = w < NW ? L.h[w] : none;
+      if (hw != none && hw == cur) {
+        for (int k = 0; k < NC; ++k) s[k] = i128_add(s[k], L.v[w][k]);
+        sm = fmax(sm, L.t[w]);
+        sc += L.c[w];
+        continue;
+      }
+      if (cur != none) {
+        for (int k = 0; k < NC; ++k)
+          if (s[k].lo != 0 || s[k].hi != 0) atomic_add_i128(acc + NC * (size_t)cur + k, s[k]);
+        if (sm > 0.0) atomicMax(vm + cur, (unsigned long long)__double_as_longlong(sm));
+        if (cnt && sc) atomicAdd(cnt + cur, sc);
+      }
+      cur = hw;
+      if (hw != none) {
+        for (int k = 0; k < NC; ++k) s[k] = L.v[w][k];
+        sm = L.t[w];
+        sc = L.c[w];
+      }
+    }
+  }
+}
+
 // Wave-aggregated atomic min at base[key] (same contract as agg_add_u32).
 __device__ __forceinline__ void agg_min_u32(uint32_t* base, uint32_t key, uint32_t val,
                                             bool active) {

@@ -124,18 +124,21 @@ __global__ void k_so_radius(const uint32_t* kfail, const uint32_t* start, uint32
   rc2[s] = rc * rc;
 }
 
-__global__ void k_so_accum(const float* vx, const float* vy, const float* vz,
-                           const uint32_t* s_seg, const uint32_t* s_pidx, const double* s_r2,
-                           const uint32_t* start, uint32_t m, const uint32_t* kstar,
-                           const double* rc2, double eps2, I128* acc, unsigned long long* vm,
-                           uint32_t* ncore) {
+constexpr int kSoTB = 1024;
+
+__global__ void __launch_bounds__(kSoTB)
+    k_so_accum(const float* vx, const float* vy, const float* vz, const uint32_t* s_seg,
+               const uint32_t* s_pidx, const double* s_r2, const uint32_t* start, uint32_t m,
+               const uint32_t* kstar, const double* rc2, double eps2, I128* acc,
+               unsigned long long* vm, uint32_t* ncore) {
+  __shared__ SegMerge<6, kSoTB / 64> L;
   const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = q < m;
   uint32_t hh = 0xFFFFFFFFu;
   I128 v[6];
   for (int c = 0; c < 6; ++c) v[c] = i128_from(0);
   double t = 0.0;
-  bool in_core = false;
+  uint32_t in_core = 0;
   if (ok) {
     hh = s_seg[q];
     const uint32_t i = s_pidx[q];
@@ -150,25 +153,11 @@ __global__ void k_so_accum(const float* vx, const float* vy, const float* vz,
       for (int c = 0; c < 3; ++c) v[c] = i128_from(w[c]);
     }
     if (r2 < rc2[hh]) {
-      in_core = true;
+      in_core = 1;
       for (int c = 0; c < 3; ++c) v[3 + c] = i128_from(w[c]);
     }
   }
-  const uint32_t h0 = __shfl(hh, 0);
-  if (__all(hh == h0) && h0 != 0xFFFFFFFFu) {
-    double tm = t;
-    for (int o = 32; o > 0; o >>= 1) tm = fmax(tm, __shfl_xor(tm, o));
-    for (int c = 0; c < 6; ++c) v[c] = wave_sum_i128(v[c]);
-    if ((threadIdx.x & 63) == 0) {
-      for (int c = 0; c < 6; ++c) atomic_add_i128(acc + 6 * (size_t)h0 + c, v[c]);
-      if (tm > 0.0) atomicMax(vm + h0, (unsigned long long)__double_as_longlong(tm));
-    }
-  } else if (ok) {
-    for (int c = 0; c < 6; ++c)
-      if (v[c].lo != 0 || v[c].hi != 0) atomic_add_i128(acc + 6 * (size_t)hh + c, v[c]);
-    if (t > 0.0) atomicMax(vm + hh, (unsigned long long)__double_as_longlong(t));
-  }
-  agg_add_u32(ncore, ok ? hh : 0u, 1u, in_core);
+  seg_merge_add<6, kSoTB / 64>(L, hh, v, t, in_core, acc, vm, ncore);
 }
 
 __global__ void k_prop_out(const libhalo_halos h, uint32_t S, const uint32_t* start,
@@ -292,7 +281,7 @@ void props(Ctx& ctx, int64_t n, int pos_dtype, const void* x, const void* y, con
   k_so_radius<<<blocks_for(S, TB), TB, 0, s>>>(w.kfail, rb.start, S, C, P.core_frac, w.kstar,
                                                w.rvir, w.rc2);
   if (m > 0)
-    k_so_accum<<<blocks_for(m, TB), TB, 0, s>>>(vx, vy, vz, rb.s_seg, rb.s_pidx, rb.s_r2,
+    k_so_accum<<<blocks_for(m, kSoTB), kSoTB, 0, s>>>(vx, vy, vz, rb.s_seg, rb.s_pidx, rb.s_r2,
                                                 rb.start, m, w.kstar, w.rc2, eps2, w.acc, w.vm,
                                                 w.ncore);
   k_prop_out<<<blocks_for(S, TB), TB, 0, s>>>(h, S, rb.start, rb.s_pidx, vx, vy, vz, w.kstar,

@@ -11,22 +11,33 @@ template <class T>
 __global__ void k_r2(const T* x, const T* y, const T* z, double box, const double* cx,
                      const double* cy, const double* cz, const uint32_t* seg,
                      const uint32_t* pidx, uint32_t m, double* r2, unsigned long long* key,
-                     uint32_t* val, uint32_t* cnt) {
+                     uint32_t* val) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = e < m;
-  uint32_t h = 0;
-  if (ok) {
-    h = seg[e];
-    const uint32_t i = pidx[e];
-    double dx = min_image((double)x[i] - cx[h], box);
-    double dy = min_image((double)y[i] - cy[h], box);
-    double dz = min_image((double)z[i] - cz[h], box);
-    double d = sq3(dx, dy, dz);
-    r2[e] = d;
-    key[e] = (unsigned long long)__double_as_longlong(d);
-    val[e] = e;
+  if (e >= m) return;
+  const uint32_t h = seg[e];
+  const uint32_t i = pidx[e];
+  double dx = min_image((double)x[i] - cx[h], box);
+  double dy = min_image((double)y[i] - cy[h], box);
+  double dz = min_image((double)z[i] - cz[h], box);
+  double d = sq3(dx, dy, dz);
+  r2[e] = d;
+  key[e] = (unsigned long long)__double_as_longlong(d);
+  val[e] = e;
+}
+
+// start[s] = first position of segment s in the segment-sorted keys.
+__global__ void k_seg_starts(const uint32_t* skey, uint32_t m, uint32_t nseg, uint32_t* start) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > nseg) return;
+  uint32_t lo = 0, hi = m;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (skey[mid] < s)
+      lo = mid + 1;
+    else
+      hi = mid;
   }
-  agg_add_u32(cnt, h, 1u, ok);
+  start[s] = lo;
 }
 
 __global__ void k_seg_keys(const uint32_t* seg, const uint32_t* perm, uint32_t m,
@@ -53,11 +64,17 @@ __global__ void k_zero_sv(I128* acc, unsigned long long* vm, uint32_t nseg) {
   vm[h] = 0ull;
 }
 
-__global__ void k_sigma_vmax_accum(const float* vx, const float* vy, const float* vz,
-                                   const uint32_t* s_seg, const uint32_t* s_pidx,
-                                   const double* s_r2, const uint32_t* start, uint32_t m,
-                                   double eps2, I128* acc, unsigned long long* vm) {
-  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int kSvTB = 256;  // block of the accumulation (4 waves)
+
+// Exact velocity sums and max of k^2 / max(r^2, eps^2) per segment over the
+// sorted elements, one element per thread.
+__global__ void __launch_bounds__(kSvTB)
+    k_sigma_vmax_accum(const float* vx, const float* vy, const float* vz,
+                       const uint32_t* s_seg, const uint32_t* s_pidx, const double* s_r2,
+                       const uint32_t* start, uint32_t m, double eps2, I128* acc,
+                       unsigned long long* vm) {
+  __shared__ SegMerge<4, kSvTB / 64> L;
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = q < m;
   const uint32_t h = ok ? s_seg[q] : 0xFFFFFFFFu;
   long long w[3] = {0, 0, 0};
@@ -67,27 +84,13 @@ __global__ void k_sigma_vmax_accum(const float* vx, const float* vy, const float
     w[0] = quantise((double)vx[i], kVelShift);
     w[1] = quantise((double)vy[i], kVelShift);
     w[2] = quantise((double)vz[i], kVelShift);
-    double kk = (double)(q - start[h] + 1);
+    const double kk = (double)(q - start[h] + 1);
     t = (kk * kk) / fmax(s_r2[q], eps2);
   }
   I128 v[4];
   for (int c = 0; c < 3; ++c) v[c] = i128_from(w[c]);
   v[3] = i128_add(i128_sqr(w[0]), i128_add(i128_sqr(w[1]), i128_sqr(w[2])));
-  // one segment for the whole wave: reduce first
-  const uint32_t h0 = __shfl(h, 0);
-  const bool uniform = __all(h == h0) && h0 != 0xFFFFFFFFu;
-  if (uniform) {
-    double tm = t;
-    for (int o = 32; o > 0; o >>= 1) tm = fmax(tm, __shfl_xor(tm, o));
-    for (int c = 0; c < 4; ++c) v[c] = wave_sum_i128(v[c]);
-    if ((threadIdx.x & 63) == 0) {
-      for (int c = 0; c < 4; ++c) atomic_add_i128(acc + 4 * (size_t)h0 + c, v[c]);
-      atomicMax(vm + h0, (unsigned long long)__double_as_longlong(tm));
-    }
-  } else if (ok) {
-    for (int c = 0; c < 4; ++c) atomic_add_i128(acc + 4 * (size_t)h + c, v[c]);
-    atomicMax(vm + h, (unsigned long long)__double_as_longlong(t));
-  }
+  seg_merge_add<4, kSvTB / 64>(L, h, v, t, 0u, acc, vm, nullptr);
 }
 
 __global__ void k_sigma_vmax_final(const I128* acc, const unsigned long long* vm,
@@ -126,7 +129,6 @@ size_t radial_bytes(int64_t m, int64_t nseg) {
   add(8 * m); add(8 * m);                 // k64
   add(4 * m); add(4 * m); add(4 * m); add(4 * m);
   add(8 * m);                             // r2
-  add(4 * (nseg + 2));                    // cnt
   add(radix_tmp_bytes(m));
   add(4 * scan_tmp_elems<uint32_t>(m + nseg + 2));
   return b;
@@ -147,7 +149,6 @@ RadialBufs radial_take(Arena& A, int64_t m, int64_t nseg) {
   b.k32a = A.take<uint32_t>(m);
   b.k32b = A.take<uint32_t>(m);
   b.r2 = A.take<double>(m);
-  b.cnt = A.take<uint32_t>(nseg + 2);
   b.rtmp = A.take<char>(radix_tmp_bytes(m));
   b.stmp = A.take<uint32_t>(scan_tmp_elems<uint32_t>(m + nseg + 2));
   return b;
@@ -156,22 +157,21 @@ RadialBufs radial_take(Arena& A, int64_t m, int64_t nseg) {
 void radial_sort(int pos_dtype, const void* x, const void* y, const void* z, double box,
                  const double* cx, const double* cy, const double* cz, int64_t m,
                  int64_t nseg, RadialBufs& b, hipStream_t s) {
-  k_fill_u32<<<blocks_for(nseg + 1, TB), TB, 0, s>>>(b.cnt, nseg + 1, 0u);
-  if (m > 0) {
-    if (pos_dtype == LIBHALO_F64)
-      k_r2<double><<<blocks_for(m, TB), TB, 0, s>>>((const double*)x, (const double*)y,
-                                                    (const double*)z, box, cx, cy, cz, b.seg,
-                                                    b.pidx, (uint32_t)m, b.r2, b.k64a, b.va,
-                                                    b.cnt);
-    else
-      k_r2<float><<<blocks_for(m, TB), TB, 0, s>>>((const float*)x, (const float*)y,
-                                                   (const float*)z, box, cx, cy, cz, b.seg,
-                                                   b.pidx, (uint32_t)m, b.r2, b.k64a, b.va,
-                                                   b.cnt);
+  if (m == 0) {
+    k_fill_u32<<<blocks_for(nseg + 1, TB), TB, 0, s>>>(b.start, nseg + 1, 0u);
+    return;
   }
-  exclusive_scan<uint32_t>(b.cnt, b.start, nseg + 1, nullptr, b.stmp, s);
-  if (m == 0) return;
-  // by r^2 (non-negative doubles order as their bit patterns), then stably by segment
+  if (pos_dtype == LIBHALO_F64)
+    k_r2<double><<<blocks_for(m, TB), TB, 0, s>>>((const double*)x, (const double*)y,
+                                                  (const double*)z, box, cx, cy, cz, b.seg,
+                                                  b.pidx, (uint32_t)m, b.r2, b.k64a, b.va);
+  else
+    k_r2<float><<<blocks_for(m, TB), TB, 0, s>>>((const float*)x, (const float*)y,
+                                                 (const float*)z, box, cx, cy, cz, b.seg,
+                                                 b.pidx, (uint32_t)m, b.r2, b.k64a, b.va);
+  // by r^2 (non-negative doubles order as their bit patterns), then stably by
+  // segment; ties in r^2 keep the input order, which the callers give in
+  // ascending particle index within a segment
   bool f1 = radix_sort_pairs<unsigned long long>(b.k64a, b.va, b.k64b, b.vb, m, 63, b.rtmp, s);
   uint32_t* p1 = f1 ? b.vb : b.va;
   uint32_t* p1o = f1 ? b.va : b.vb;
@@ -180,6 +180,9 @@ void radial_sort(int pos_dtype, const void* x, const void* y, const void* z, dou
                                        bits_for((uint64_t)(nseg > 0 ? nseg - 1 : 0)), b.rtmp,
                                        s);
   uint32_t* perm = f2 ? p1o : p1;
+  uint32_t* skey = f2 ? b.k32b : b.k32a;
+  k_seg_starts<<<blocks_for(nseg + 1, TB), TB, 0, s>>>(skey, (uint32_t)m, (uint32_t)nseg,
+                                                       b.start);
   k_radial_out<<<blocks_for(m, TB), TB, 0, s>>>(perm, b.seg, b.pidx, b.r2, (uint32_t)m,
                                                 b.s_seg, b.s_pidx, b.s_r2);
 }
@@ -190,8 +193,8 @@ void radial_sigma_vmax(const float* vx, const float* vy, const float* vz, int64_
   if (nseg <= 0) return;
   k_zero_sv<<<blocks_for(nseg, TB), TB, 0, s>>>(acc, vm, (uint32_t)nseg);
   if (m > 0)
-    k_sigma_vmax_accum<<<blocks_for(m, TB), TB, 0, s>>>(vx, vy, vz, b.s_seg, b.s_pidx, b.s_r2,
-                                                        b.start, (uint32_t)m, eps2, acc, vm);
+    k_sigma_vmax_accum<<<blocks_for(m, kSvTB), kSvTB, 0, s>>>(
+        vx, vy, vz, b.s_seg, b.s_pidx, b.s_r2, b.start, (uint32_t)m, eps2, acc, vm);
   k_sigma_vmax_final<<<blocks_for(nseg, TB), TB, 0, s>>>(acc, vm, b.start, (uint32_t)nseg, Gm,
                                                          sv2, vmax2);
 }

@@ -23,7 +23,6 @@ struct RadialBufs {
   uint32_t* k32a;
   uint32_t* k32b;
   double* r2;
-  uint32_t* cnt;
   void* rtmp;
   uint32_t* stmp;
 };

@@ -228,19 +228,18 @@ __global__ void k_norm6(const T* x, const T* y, const T* z, const float* vx, con
 }
 
 // ------------------------------------------------------------ pair kernels --
-// Nearest-neighbour work unit: 64 particles of a node (one wavefront, lane =
-// particle) against one j-chunk of the node.  The chunk is at least kNNJ
-// particles, a multiple of 64, and grows with the node so a node has at most
-// 64 chunks.
+// Nearest-neighbour work unit: 256 particles of a node (a block, four waves
+// of 64) against one j-chunk.  The chunk is a multiple of 256 particles, at
+// least 1024 and at most kSymJMax, so a chunk's j-minima fit in LDS.
 __host__ __device__ __forceinline__ uint32_t nn_chunk(uint32_t n) {
   uint32_t c = (n + 63u) / 64u;
-  c = (c + 63u) & ~63u;
-  return c > (uint32_t)kNNJ ? c : (uint32_t)kNNJ;
+  c = (c + 255u) & ~255u;
+  return c < (uint32_t)kNNJ ? (uint32_t)kNNJ : (c > kSymJMax ? kSymJMax : c);
 }
 
 __host__ __device__ __forceinline__ uint32_t nn_units(uint32_t n) {
   const uint32_t J = nn_chunk(n);
-  return ((n + 63u) / 64u) * ((n + J - 1) / J);
+  return ((n + 255u) / 256u) * ((n + J - 1) / J);
 }
 
 // Units of the nodes selected by `which`: 0 = all-pairs nodes, 1 = nodes whose
@@ -254,21 +253,6 @@ __global__ void k_pair_items(const uint32_t* count, const double* prm, const uin
   const uint32_t g = gstate[k];
   const bool sel = which == 0 ? g == 0u : g == 2u;
   items[k] = (active && sel) ? nn_units(n) : 0u;
-}
-
-// Next unit of this wavefront (whole wave active): from the shared counter or
-// by striding over the grid; readfirstlane makes the value wave-uniform for
-// the compiler, which keeps unit bounds and j loads scalar.
-__device__ __forceinline__ uint32_t wave_next_unit(uint32_t* ctr, uint32_t u0, uint32_t t) {
-  uint32_t v;
-  if (ctr) {
-    v = 0;
-    if ((threadIdx.x & 63u) == 0) v = atomicAdd(ctr, 1u);
-  } else {
-    const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
-    v = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) + t * nw;
-  }
-  return u0 + __builtin_amdgcn_readfirstlane(v);
 }
 
 // min over j in [j0, j1) of d2(i, j); the six j coordinates are wave-uniform
@@ -304,38 +288,166 @@ __device__ __forceinline__ float nn_span(const float* __restrict__ xi, size_t S,
   return best;
 }
 
+// Lane exchanges for the cross-lane minima (whole wave active).  The minima
+// work on FP32 bit patterns as unsigned integers: every value is a
+// non-negative float or +inf, whose bits order like the values.
+__device__ __forceinline__ uint32_t lane_xor1(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t lane_xor2(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t lane_xor4(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x101F);
+}
+__device__ __forceinline__ uint32_t lane_xor8(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t lane_xor16(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);
+}
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t x) {
+  const int l = (int)(threadIdx.x & 63u);
+  return (uint32_t)__builtin_amdgcn_ds_bpermute((l ^ 32) << 2, (int)x);
+}
+
+// Minimum over the wave's 64 lanes of each of d[0..7] (FP32 bits), transposed:
+// lane l returns the minimum of d[u] with u = 4 b0 + 2 b1 + b2 (b0..b2 the low
+// bits of l).  Each halving step keeps the half of the values selected by one
+// lane bit and takes the partner's copy of the same half.
+__device__ __forceinline__ uint32_t wave_min8(const uint32_t* d) {
+  const uint32_t l = threadIdx.x & 63u;
+  const bool b0 = l & 1u, b1 = l & 2u, b2 = l & 4u;
+  uint32_t r1[4], r2[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t keep = b0 ? d[4 + k] : d[k];
+    const uint32_t send = b0 ? d[k] : d[4 + k];
+    r1[k] = min(keep, lane_xor1(send));
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const uint32_t keep = b1 ? r1[2 + k] : r1[k];
+    const uint32_t send = b1 ? r1[k] : r1[2 + k];
+    r2[k] = min(keep, lane_xor2(send));
+  }
+  const uint32_t keep = b2 ? r2[1] : r2[0];
+  const uint32_t send = b2 ? r2[0] : r2[1];
+  uint32_t r = min(keep, lane_xor4(send));
+  r = min(r, lane_xor8(r));
+  r = min(r, lane_xor16(r));
+  r = min(r, lane_xor32(r));
+  return r;
+}
+
+__device__ __forceinline__ uint32_t wave_min1(uint32_t r) {
+  r = min(r, lane_xor1(r));
+  r = min(r, lane_xor2(r));
+  r = min(r, lane_xor4(r));
+  r = min(r, lane_xor8(r));
+  r = min(r, lane_xor16(r));
+  r = min(r, lane_xor32(r));
+  return r;
+}
+
+// Pairs of the wave's particles with j in [j0, j1) (all j above every i of
+// the wave), each pair evaluated once: the lane keeps its own minimum, and the
+// minimum over the wave for each j goes to jmin[j - jc] (LDS, as FP32 bits).
+// Lanes without a particle carry coordinates of 1e30, so their d2 is +inf.
+__device__ __forceinline__ float nn_sym_span(const float* __restrict__ xi, size_t S,
+                                             uint32_t first, uint32_t j0, uint32_t j1,
+                                             uint32_t jc, const float* a, float best,
+                                             uint32_t* jmin) {
+  const uint32_t l = threadIdx.x & 63u;
+  const uint32_t ul = ((l & 1u) << 2) | (l & 2u) | ((l >> 2) & 1u);
+  uint32_t j = j0;
+  for (; j + 8 <= j1; j += 8) {
+    float b[6][8];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const float* __restrict__ p = xi + (size_t)c * S + first + j;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b[c][u] = p[u];
+    }
+    uint32_t d[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float e = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], b[0][u], b[1][u], b[2][u],
+                           b[3][u], b[4][u], b[5][u]);
+      best = fminf(best, e);
+      d[u] = __float_as_uint(e);
+    }
+    const uint32_t r = wave_min8(d);
+    if (l < 8u) atomicMin(jmin + (j - jc + ul), r);
+  }
+  for (; j < j1; ++j) {
+    const uint32_t g = first + j;
+    const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], xi[g], xi[S + g], xi[2 * S + g],
+                         xi[3 * S + g], xi[4 * S + g], xi[5 * S + g]);
+    best = fminf(best, d);
+    const uint32_t r = wave_min1(__float_as_uint(d));
+    if (l == 0u) atomicMin(jmin + (j - jc), r);
+  }
+  return best;
+}
+
 // Nearest-neighbour squared distance: D[i] = min_{j != i in node} d2(i, j),
-// over the units [woff[kb], woff[ke]).  Each unit folds its minimum into D
-// with an atomic min on the FP32 bits (non-negative floats order as integers).
+// over the units [woff[kb], woff[ke]).  Each unordered pair of 64-particle
+// tiles is evaluated once, by the wave owning the lower tile; the tile itself
+// is evaluated in full.  Minima are folded into D with atomic min on the FP32
+// bits (non-negative floats order as integers), skipped when D is already
+// lower.
 __global__ void __launch_bounds__(TB)
     k_nn(const float* __restrict__ xi, size_t S, LevelNodes nd, uint32_t K,
          const uint32_t* __restrict__ woff, uint32_t kb, uint32_t ke, uint32_t* ctr,
          uint32_t* D) {
+  __shared__ uint32_t jmin[kSymJMax];
+  __shared__ uint32_t su;
+  const uint32_t inf = 0x7F800000u;
   const uint32_t u0 = woff[kb], u1 = woff[ke];
   for (uint32_t t = 0;; ++t) {
-    const uint32_t u = wave_next_unit(ctr, u0, t);
+    uint32_t v;
+    if (ctr) {
+      __syncthreads();
+      if (threadIdx.x == 0) su = atomicAdd(ctr, 1u);
+      __syncthreads();
+      v = su;
+    } else {
+      v = blockIdx.x + t * gridDim.x;
+    }
+    const uint32_t u = u0 + __builtin_amdgcn_readfirstlane(v);
     if (u >= u1) break;
     const uint32_t k = seg_of(woff, K, u);
     const uint32_t local = u - woff[k];
     const uint32_t first = nd.first[k], n = nd.count[k];
     const uint32_t J = nn_chunk(n);
-    const uint32_t ni = (n + 63u) / 64u;
-    const uint32_t c = local / ni, it = local - c * ni;
-    const uint32_t li = it * 64u + (threadIdx.x & 63u);
+    const uint32_t nb = (n + 255u) / 256u;
+    const uint32_t c = local / nb, b = local - c * nb;
+    const uint32_t j0 = c * J, j1 = min(j0 + J, n);
+    if (j1 <= b * 256u) continue;  // chunk below the block's particles (block-uniform)
+    // the wave's tile (readfirstlane: uniform to the compiler, so spans stay scalar)
+    const uint32_t t0 = __builtin_amdgcn_readfirstlane(b * 256u + (threadIdx.x & ~63u));
+    const uint32_t li = t0 + (threadIdx.x & 63u);
     const bool ok = li < n;
     const uint32_t gi = first + (ok ? li : 0u);
     float a[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) a[q] = xi[(size_t)q * S + gi];
-    const uint32_t j0 = c * J, j1 = min(j0 + J, n);
-    // the wave's own particles [s0, s1) lie wholly inside or outside the chunk
-    uint32_t s0 = it * 64u, s1 = min(s0 + 64u, n);
-    if (s0 < j0 || s0 >= j1) s0 = s1 = j1;
-    float best = __int_as_float(0x7F800000);
-    best = nn_span<false>(xi, S, first + j0, first + s0, 0u, a, best);
-    best = nn_span<true>(xi, S, first + s0, first + s1, first + li, a, best);
-    best = nn_span<false>(xi, S, first + s1, first + j1, 0u, a, best);
-    if (ok) atomicMin(D + gi, __float_as_uint(best));
+    for (int q = 0; q < 6; ++q) a[q] = ok ? xi[(size_t)q * S + gi] : 1e30f;
+    for (uint32_t q = threadIdx.x; q < j1 - j0; q += TB) jmin[q] = inf;
+    __syncthreads();
+    float best = __int_as_float(inf);
+    if (t0 < n) {
+      if (t0 >= j0 && t0 < j1)
+        best = nn_span<true>(xi, S, first + t0, first + min(t0 + 64u, n), first + li, a, best);
+      const uint32_t js = max(j0, t0 + 64u);
+      if (js < j1) best = nn_sym_span(xi, S, first, js, j1, j0, a, best, jmin);
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < j1 - j0; q += TB) {
+      const uint32_t m = jmin[q];
+      if (m < D[first + j0 + q]) atomicMin(D + first + j0 + q, m);
+    }
+    if (ok && __float_as_uint(best) < D[gi]) atomicMin(D + gi, __float_as_uint(best));
   }
 }
 
@@ -889,7 +1001,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     if (plain) {
       for (uint32_t k = 0; k < K; ++k) {
         uint32_t nn = hcount[k];
-        const unsigned g = blocks_for(nn_units(nn), TB / 64);
+        const unsigned g = nn_units(nn);
         HALO_PROF(ctx, "k_nn", s,
                   k_nn<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, nullptr, D));
         if (nn <= (uint32_t)kSelSmall)
