@@ -96,6 +96,24 @@ def test_unbind_props_clustered(H, orc, n, seed, f64, prec):
         compare_props(g["props"], o["props"], kept)
 
 
+def test_unbind_small_softening(H, orc):
+    """Softening 2e-4, well below the haloes' extent: close pairs dominate the
+    potential sums and neighbouring terms span many decades; same comparison as
+    the other FP64 cases."""
+    n, seed = 4000, 34
+    note(f"unbind small softening n={n} seed={seed}")
+    box = 10.0 * (n / 1500) ** (1 / 3)
+    pos, vel = clustered(n, box, seed, nblob=5, spread=0.3, f64=True)
+    m, eps = 1e11, 2e-4
+    p = orc.make_params(box, m, eps)
+    P = particles(orc, pos, vel)
+    o = orc.run_all(p, P)
+    g = run_gpu(H, particles_from_arrays(pos, vel),
+                H.Params(box=box, particle_mass=m, softening=eps, prec=0))
+    amb, changed = compare_unbind(g["unbound"], g["bound"], g["phi"], o, P, 1e-9, 1e-9)
+    print(f"ambiguous={amb} changed={changed}")
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_unbind_props_c1(H, c1, c1_oracle, prec):
     note(f"unbind/props c1 prec={prec}")
