@@ -597,6 +597,43 @@ __global__ void __launch_bounds__(TB)
 }
 
 // ------------------------------------------------------------ selection ----
+// Radix-select step over a 256-bin histogram, one wave: lane l holds bins
+// 4l..4l+3 in c[].  Finds the bin d where the running count first reaches kk
+// (kk >= 1) and returns it with kk minus the count before d, in every lane;
+// d = 256 when the histogram holds fewer than kk values.
+__device__ __forceinline__ void wave_select_bin(const uint32_t* c, uint32_t kk, uint32_t& d,
+                                                uint32_t& rest) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t s = c[0] + c[1] + c[2] + c[3];
+  uint32_t inc = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o);
+    if ((int)lane >= o) inc += t;
+  }
+  const uint32_t exc = inc - s;
+  const unsigned long long hit = __ballot(kk > exc && kk <= inc);
+  uint32_t dd = 256u, rr = kk;
+  if (hit) {
+    const int L = __ffsll((long long)hit) - 1;
+    if ((int)lane == L) {
+      uint32_t run = exc;
+      for (int q = 0; q < 4; ++q) {
+        if (run + c[q] >= kk) {
+          dd = 4u * lane + q;
+          rr = kk - run;
+          break;
+        }
+        run += c[q];
+      }
+    }
+    dd = __shfl(dd, L);
+    rr = __shfl(rr, L);
+  }
+  d = dd;
+  rest = rr;
+}
+
 // ell^2 of nodes with at most kSelSmall particles: radix select in LDS.
 __global__ void __launch_bounds__(TB)
     k_select_small(const uint32_t* D, LevelNodes nd, uint32_t k0, uint32_t k1,
@@ -626,15 +663,14 @@ __global__ void __launch_bounds__(TB)
         atomicAdd(&hist[(b >> shift) & 255u], 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t run = 0, kk = s_k;
-      for (uint32_t d = 0; d < 256; ++d) {
-        if (run + hist[d] >= kk) {
-          s_pre = pre | (d << shift);
-          s_k = kk - run;
-          break;
-        }
-        run += hist[d];
+    if (threadIdx.x < 64) {
+      uint32_t c[4];
+      for (int q = 0; q < 4; ++q) c[q] = hist[4 * threadIdx.x + q];
+      uint32_t d, rest;
+      wave_select_bin(c, s_k, d, rest);
+      if (threadIdx.x == 0 && d < 256u) {
+        s_pre = pre | (d << shift);
+        s_k = rest;
       }
     }
     __syncthreads();
@@ -692,26 +728,32 @@ __global__ void __launch_bounds__(TB)
   }
 }
 
+// One wave per big node: reads and clears its histogram, then narrows the
+// prefix and the rank to the selected bin.
 __global__ void k_select_big_resolve(NodeScratch sc, const uint32_t* nbig, int pass) {
   const uint32_t B = nbig[0];
   const int shift = 24 - 8 * pass;
-  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < B;
-       b += gridDim.x * blockDim.x) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t b = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < B; b += nw) {
     uint32_t* h = sc.ghist + 256 * (size_t)b;
-    uint32_t run = 0, kk = sc.selp[2 * b + 1], pre = sc.selp[2 * b];
-    for (uint32_t d = 0; d < 256; ++d) {
-      uint32_t c = h[d];
-      h[d] = 0;
-      if (kk != 0 && run + c >= kk) {
-        pre |= d << shift;
-        kk = kk - run;
-        sc.selp[2 * b] = pre;
-        sc.selp[2 * b + 1] = kk;
-        kk = 0;  // found; keep clearing
-      }
-      run += c;
+    uint32_t c[4];
+    for (int q = 0; q < 4; ++q) {
+      c[q] = h[4 * lane + q];
+      h[4 * lane + q] = 0;
     }
-    if (pass == 3) sc.ell2[sc.big[b]] = __uint_as_float(sc.selp[2 * b]);
+    const uint32_t kk = sc.selp[2 * b + 1];
+    uint32_t pre = sc.selp[2 * b];
+    uint32_t d = 256u, rest = kk;
+    if (kk != 0) wave_select_bin(c, kk, d, rest);
+    if (d < 256u) pre |= d << shift;
+    if (lane == 0) {
+      if (d < 256u) {
+        sc.selp[2 * b] = pre;
+        sc.selp[2 * b + 1] = rest;
+      }
+      if (pass == 3) sc.ell2[sc.big[b]] = __uint_as_float(pre);
+    }
   }
 }
 
@@ -1025,7 +1067,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
         k_zero_hist<<<64, TB, 0, s>>>(sc, dcnt);
         for (int pass = 0; pass < 4; ++pass) {
           k_select_big_hist<<<kPersist, TB, 0, s>>>(D, nd, sc, dcnt, pass);
-          k_select_big_resolve<<<blocks_for(nbig, 64), 64, 0, s>>>(sc, dcnt, pass);
+          k_select_big_resolve<<<blocks_for(nbig, TB / 64), TB, 0, s>>>(sc, dcnt, pass);
         }
       }
     };
