@@ -511,13 +511,15 @@ __device__ __forceinline__ void fof_block(const float* __restrict__ cxi, size_t 
 #pragma unroll
       for (int u = 0; u < 8; ++u) b[c][u] = p[u];
     }
+    uint32_t m8 = 0;  // bit u: j + u is a friend (built from u = 7 down to 0)
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 7; u >= 0; --u) {
       const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], b[0][u], b[1][u], b[2][u],
                            b[3][u], b[4][u], b[5][u]);
       const bool f = ok && d <= l2 && (!kDiag || j + u > li);
-      fm |= f ? (1ull << (j - jb + u)) : 0ull;
+      m8 = 2u * m8 + (f ? 1u : 0u);
     }
+    fm |= (unsigned long long)m8 << (j - jb);
   }
   for (; j < je; ++j) {
     const uint32_t g = first + j;
