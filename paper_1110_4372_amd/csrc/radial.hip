@@ -10,7 +10,7 @@ constexpr int TB = 256;
 template <class T>
 __global__ void k_r2(const T* x, const T* y, const T* z, double box, const double* cx,
                      const double* cy, const double* cz, const uint32_t* seg,
-                     const uint32_t* pidx, uint32_t m, double* r2, unsigned long long* key,
+                     const uint32_t* pidx, uint32_t m, double* r2, uint32_t* key,
                      uint32_t* val) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m) return;
@@ -21,7 +21,9 @@ __global__ void k_r2(const T* x, const T* y, const T* z, double box, const doubl
   double dz = min_image((double)z[i] - cz[h], box);
   double d = sq3(dx, dy, dz);
   r2[e] = d;
-  key[e] = (unsigned long long)__double_as_longlong(d);
+  // FP32 rounding is monotone, so this key orders like r^2 up to runs of
+  // equal keys, which k_radial_fix puts in exact order
+  key[e] = __float_as_uint((float)d);
   val[e] = e;
 }
 
@@ -48,13 +50,43 @@ __global__ void k_seg_keys(const uint32_t* seg, const uint32_t* perm, uint32_t m
 
 __global__ void k_radial_out(const uint32_t* perm, const uint32_t* seg, const uint32_t* pidx,
                              const double* r2, uint32_t m, uint32_t* s_seg, uint32_t* s_pidx,
-                             double* s_r2) {
+                             double* s_r2, uint32_t* s_e) {
   uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m) return;
   uint32_t e = perm[q];
   s_seg[q] = seg[e];
   s_pidx[q] = pidx[e];
   s_r2[q] = r2[e];
+  s_e[q] = e;
+}
+
+// Elements sorted by (segment, FP32-rounded r^2), equal keys in input order:
+// the first element of each run of equal keys sorts its run by (exact r^2,
+// input position), which gives the order of a stable sort on the exact r^2.
+// Runs are rare and short; a run of identical values is already in order.
+__global__ void k_radial_fix(const uint32_t* s_seg, uint32_t* s_pidx, double* s_r2,
+                             uint32_t* s_e, uint32_t m) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const uint32_t h = s_seg[q];
+  const float f = (float)s_r2[q];
+  if (q > 0 && s_seg[q - 1] == h && (float)s_r2[q - 1] == f) return;  // not a run head
+  uint32_t end = q + 1;
+  while (end < m && s_seg[end] == h && (float)s_r2[end] == f) ++end;
+  for (uint32_t a = q + 1; a < end; ++a) {
+    const double r = s_r2[a];
+    const uint32_t pe = s_e[a], pp = s_pidx[a];
+    uint32_t b = a;
+    while (b > q && (s_r2[b - 1] > r || (s_r2[b - 1] == r && s_e[b - 1] > pe))) {
+      s_r2[b] = s_r2[b - 1];
+      s_e[b] = s_e[b - 1];
+      s_pidx[b] = s_pidx[b - 1];
+      --b;
+    }
+    s_r2[b] = r;
+    s_e[b] = pe;
+    s_pidx[b] = pp;
+  }
 }
 
 __global__ void k_zero_sv(I128* acc, unsigned long long* vm, uint32_t nseg) {
@@ -126,7 +158,7 @@ size_t radial_bytes(int64_t m, int64_t nseg) {
   add(4 * m); add(4 * m);                 // seg, pidx
   add(4 * m); add(4 * m); add(8 * m);     // sorted
   add(4 * (nseg + 2));                    // start
-  add(8 * m); add(8 * m);                 // k64
+  add(4 * m);                             // s_e
   add(4 * m); add(4 * m); add(4 * m); add(4 * m);
   add(8 * m);                             // r2
   add(radix_tmp_bytes(m));
@@ -142,8 +174,7 @@ RadialBufs radial_take(Arena& A, int64_t m, int64_t nseg) {
   b.s_pidx = A.take<uint32_t>(m);
   b.s_r2 = A.take<double>(m);
   b.start = A.take<uint32_t>(nseg + 2);
-  b.k64a = A.take<unsigned long long>(m);
-  b.k64b = A.take<unsigned long long>(m);
+  b.s_e = A.take<uint32_t>(m);
   b.va = A.take<uint32_t>(m);
   b.vb = A.take<uint32_t>(m);
   b.k32a = A.take<uint32_t>(m);
@@ -164,15 +195,14 @@ void radial_sort(int pos_dtype, const void* x, const void* y, const void* z, dou
   if (pos_dtype == LIBHALO_F64)
     k_r2<double><<<blocks_for(m, TB), TB, 0, s>>>((const double*)x, (const double*)y,
                                                   (const double*)z, box, cx, cy, cz, b.seg,
-                                                  b.pidx, (uint32_t)m, b.r2, b.k64a, b.va);
+                                                  b.pidx, (uint32_t)m, b.r2, b.k32a, b.va);
   else
     k_r2<float><<<blocks_for(m, TB), TB, 0, s>>>((const float*)x, (const float*)y,
                                                  (const float*)z, box, cx, cy, cz, b.seg,
-                                                 b.pidx, (uint32_t)m, b.r2, b.k64a, b.va);
-  // by r^2 (non-negative doubles order as their bit patterns), then stably by
-  // segment; ties in r^2 keep the input order, which the callers give in
-  // ascending particle index within a segment
-  bool f1 = radix_sort_pairs<unsigned long long>(b.k64a, b.va, b.k64b, b.vb, m, 63, b.rtmp, s);
+                                                 b.pidx, (uint32_t)m, b.r2, b.k32a, b.va);
+  // by FP32-rounded r^2 (non-negative floats order as their bit patterns), then
+  // stably by segment; equal keys keep the input order until k_radial_fix
+  bool f1 = radix_sort_pairs<uint32_t>(b.k32a, b.va, b.k32b, b.vb, m, 32, b.rtmp, s);
   uint32_t* p1 = f1 ? b.vb : b.va;
   uint32_t* p1o = f1 ? b.va : b.vb;
   k_seg_keys<<<blocks_for(m, TB), TB, 0, s>>>(b.seg, p1, (uint32_t)m, b.k32a);
@@ -184,7 +214,9 @@ void radial_sort(int pos_dtype, const void* x, const void* y, const void* z, dou
   k_seg_starts<<<blocks_for(nseg + 1, TB), TB, 0, s>>>(skey, (uint32_t)m, (uint32_t)nseg,
                                                        b.start);
   k_radial_out<<<blocks_for(m, TB), TB, 0, s>>>(perm, b.seg, b.pidx, b.r2, (uint32_t)m,
-                                                b.s_seg, b.s_pidx, b.s_r2);
+                                                b.s_seg, b.s_pidx, b.s_r2, b.s_e);
+  k_radial_fix<<<blocks_for(m, TB), TB, 0, s>>>(b.s_seg, b.s_pidx, b.s_r2, b.s_e,
+                                                (uint32_t)m);
 }
 
 void radial_sigma_vmax(const float* vx, const float* vy, const float* vz, int64_t m,

@@ -16,8 +16,7 @@ struct RadialBufs {
   double* s_r2;
   uint32_t* start;  // nseg + 1
   // scratch
-  unsigned long long* k64a;
-  unsigned long long* k64b;
+  uint32_t* s_e;  // input position of each sorted element
   uint32_t* va;
   uint32_t* vb;
   uint32_t* k32a;
