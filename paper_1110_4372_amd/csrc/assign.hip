@@ -82,8 +82,12 @@ __global__ void k_fof_segments(const uint32_t* head, const uint32_t* hpos, uint3
   if (head[q]) seg_start[hpos[q]] = q;
 }
 
-// Eq. 2 merging, one wavefront per FOF group.  kept[] holds, per group, the
-// kept seeds in visiting order (at the group's slice of ord).
+// Eq. 2 merging, one wavefront per FOF group of at most kMergeWave seeds.
+// kept[] holds, per group, the kept seeds in visiting order (at the group's
+// slice of ord).
+constexpr uint32_t kMergeWave = 512;
+constexpr int kMergeTB = 1024;
+constexpr uint32_t kMergeLds = 1024;  // kept seeds held in LDS by k_merge_big
 __global__ void k_merge(const uint32_t* ord, const uint32_t* seg_start, const uint32_t* nseg,
                         uint32_t S, double box, double q2, libhalo_halos h, SeedT st,
                         uint32_t* kept) {
@@ -93,6 +97,7 @@ __global__ void k_merge(const uint32_t* ord, const uint32_t* seg_start, const ui
   if (wave >= F) return;
   const uint32_t a0 = seg_start[wave];
   const uint32_t a1 = (wave + 1 < F) ? seg_start[wave + 1] : S;
+  if (a1 - a0 > kMergeWave) return;  // k_merge_big
   uint32_t nk = 0;
   for (uint32_t t = a0; t < a1; ++t) {
     const uint32_t b = ord[t];
@@ -133,6 +138,119 @@ __global__ void k_merge(const uint32_t* ord, const uint32_t* seg_start, const ui
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Eq. 2 merging of the groups with more than kMergeWave seeds, one block
+// per group: the same sequential visit as k_merge, with the kept seeds'
+// positions and velocities in LDS (beyond kMergeLds read from the halo table)
+// and a block-wide argmin per visited seed (ties to the lower id).
+__global__ void __launch_bounds__(kMergeTB)
+    k_merge_big(const uint32_t* ord, const uint32_t* seg_start, const uint32_t* nseg,
+                uint32_t S, double box, double q2, libhalo_halos h, SeedT st,
+                uint32_t* kept) {
+  constexpr int NW = kMergeTB / 64;
+  __shared__ double kx[kMergeLds], ky[kMergeLds], kz[kMergeLds];
+  __shared__ double kvx[kMergeLds], kvy[kMergeLds], kvz[kMergeLds];
+  __shared__ uint32_t kid[kMergeLds];
+  __shared__ double wq[NW];
+  __shared__ uint32_t wb[NW];
+  __shared__ uint32_t s_big[kMergeTB];
+  __shared__ uint32_t s_nbig;
+  const uint32_t F = nseg[0];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (uint32_t g0 = blockIdx.x * kMergeTB; g0 < F; g0 += gridDim.x * kMergeTB) {
+    // the big groups among groups g0 .. g0 + kMergeTB - 1
+    if (threadIdx.x == 0) s_nbig = 0;
+    __syncthreads();
+    {
+      const uint32_t g = g0 + threadIdx.x;
+      if (g < F) {
+        const uint32_t a1 = (g + 1 < F) ? seg_start[g + 1] : S;
+        if (a1 - seg_start[g] > kMergeWave) s_big[atomicAdd(&s_nbig, 1u)] = g;
+      }
+    }
+    __syncthreads();
+    const uint32_t nbig = s_nbig;
+    for (uint32_t gi = 0; gi < nbig; ++gi) {
+      const uint32_t g = s_big[gi];
+      const uint32_t a0 = seg_start[g];
+      const uint32_t a1 = (g + 1 < F) ? seg_start[g + 1] : S;
+      uint32_t nk = 0;
+      for (uint32_t t = a0; t < a1; ++t) {
+        const uint32_t b = ord[t];
+        const double cb = (double)st.cnt[b], sx2 = st.sx2[b], sv2 = st.sv2[b];
+        const double xb = h.xs[b], yb = h.ys[b], zb = h.zs[b];
+        const double vxb = h.vxs[b], vyb = h.vys[b], vzb = h.vzs[b];
+        double bq = INFINITY;
+        uint32_t best = 0xFFFFFFFFu;
+        const bool can = sx2 > 0.0 && sv2 > 0.0;
+        if (can) {
+          const double imx = cb / sx2, imv = cb / sv2;
+          for (uint32_t q = threadIdx.x; q < nk; q += kMergeTB) {
+            uint32_t a;
+            double ax, ay, az, avx, avy, avz;
+            if (q < kMergeLds) {
+              a = kid[q];
+              ax = kx[q]; ay = ky[q]; az = kz[q];
+              avx = kvx[q]; avy = kvy[q]; avz = kvz[q];
+            } else {
+              a = kept[a0 + q];
+              ax = h.xs[a]; ay = h.ys[a]; az = h.zs[a];
+              avx = h.vxs[a]; avy = h.vys[a]; avz = h.vzs[a];
+            }
+            double dx = min_image(xb - ax, box);
+            double dy = min_image(yb - ay, box);
+            double dz = min_image(zb - az, box);
+            double ux = vxb - avx, uy = vyb - avy, uz = vzb - avz;
+            double qq = __fma_rn(sq3(dx, dy, dz), imx, sq3(ux, uy, uz) * imv);
+            if (qq < bq || (qq == bq && a < best)) {
+              bq = qq;
+              best = a;
+            }
+          }
+          for (int o = 32; o > 0; o >>= 1) {
+            double oq = __shfl_xor(bq, o);
+            uint32_t ob = __shfl_xor(best, o);
+            if (oq < bq || (oq == bq && ob < best)) {
+              bq = oq;
+              best = ob;
+            }
+          }
+          if (lane == 0) {
+            wq[wid] = bq;
+            wb[wid] = best;
+          }
+        }
+        __syncthreads();
+        if (can) {
+          bq = wq[0];
+          best = wb[0];
+          for (int w = 1; w < NW; ++w)
+            if (wq[w] < bq || (wq[w] == bq && wb[w] < best)) {
+              bq = wq[w];
+              best = wb[w];
+            }
+        }
+        const bool merge = best != 0xFFFFFFFFu && bq < q2;
+        if (threadIdx.x == 0) {
+          if (merge) {
+            h.merged_into[b] = (int32_t)best;
+          } else {
+            h.merged_into[b] = (int32_t)b;
+            kept[a0 + nk] = b;
+            if (nk < kMergeLds) {
+              kid[nk] = b;
+              kx[nk] = xb; ky[nk] = yb; kz[nk] = zb;
+              kvx[nk] = vxb; kvy[nk] = vyb; kvz[nk] = vzb;
+            }
+          }
+        }
+        if (!merge) ++nk;
+        __syncthreads();
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -322,15 +440,25 @@ __global__ void k_kept_keys(const libhalo_halos h, uint32_t S, const uint32_t* f
 }
 
 // Host/sub relation, one wavefront per FOF group.
+// Host of each halo (Section 3.4): argmin of the Eq. 3 distance over the
+// larger halos of its FOF group (earlier in ord), in the candidate host's
+// metric; one wavefront per halo, its group located by binary search.
 __global__ void k_hostsub(const uint32_t* ord, const uint32_t* seg_start, const uint32_t* nseg,
                           uint32_t KH, double box, double cdyn, libhalo_halos h) {
   const uint32_t F = nseg[0];
-  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (wave >= F) return;
-  const uint32_t a0 = seg_start[wave];
-  const uint32_t a1 = (wave + 1 < F) ? seg_start[wave + 1] : KH;
-  for (uint32_t t = a0 + 1; t < a1; ++t) {
+  const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < KH; t += nw) {
+    uint32_t lo = 0, hi = F;  // last group start <= t
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (seg_start[mid] <= t)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const uint32_t a0 = seg_start[lo];
+    if (t == a0) continue;  // the group's largest halo has no host
     const uint32_t s = ord[t];
     double bd = INFINITY;
     uint32_t best = 0xFFFFFFFFu;
@@ -475,6 +603,8 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
   const uint32_t F = readu(dcnt + 1, 1);
   k_merge<<<blocks_for((int64_t)F * 64, TB), TB, 0, s>>>(ord, seg_start, dcnt + 1, S, box,
                                                          P.merge_q2, h, st, kept);
+  k_merge_big<<<std::min<int64_t>(blocks_for(F, kMergeTB), 256), kMergeTB, 0, s>>>(
+      ord, seg_start, dcnt + 1, S, box, P.merge_q2, h, st, kept);
 
   // ---- seed sets per node
   uint32_t *pcnt = w.pcnt, *poff = w.poff;
@@ -572,7 +702,7 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
   exclusive_scan<uint32_t>(flag, pos, KH, dcnt + 7, stmp, s);
   k_fof_segments<<<blocks_for(KH, TB), TB, 0, s>>>(flag, pos, KH, seg_start);
   const uint32_t FH = readu(dcnt + 7, 8);
-  k_hostsub<<<blocks_for((int64_t)FH * 64, TB), TB, 0, s>>>(kord, seg_start, dcnt + 7, KH, box,
+  k_hostsub<<<blocks_for((int64_t)KH * 64, TB), TB, 0, s>>>(kord, seg_start, dcnt + 7, KH, box,
                                                              cdyn, h);
   HALO_HIP(hipStreamSynchronize(s));
 }

@@ -111,3 +111,36 @@ def test_assign_repeat(H, c1):
     b = gpu_pipeline(H, H.Particles.from_catalog(c1), H.params_for_catalog(c1))
     assert_halos_equal(a[3], b[3])
     np.testing.assert_array_equal(a[4], b[4])
+
+
+def clump_lattice(seed=41, side=9, per=30, box=20.0):
+    """side^3 tight clumps of `per` particles on a lattice finer than the
+    linking length (one FOF group), each with its own bulk velocity, so each
+    clump becomes a seed of that group."""
+    rng = np.random.default_rng(seed)
+    g = np.arange(side) * 0.2
+    cx, cy, cz = np.meshgrid(g, g, g, indexing="ij")
+    c = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], 1) + 8.0
+    k = c.shape[0]
+    pos = np.repeat(c, per, 0) + 0.01 * rng.standard_normal((k * per, 3))
+    bulk = 300.0 * rng.standard_normal((k, 3))
+    vel = (np.repeat(bulk, per, 0) + 5.0 * rng.standard_normal((k * per, 3))).astype(np.float32)
+    return pos, vel, box
+
+
+def test_assign_many_seeds_one_group(H, orc):
+    """One FOF group with more than 512 seeds: merging runs in the block-per-
+    group form, and the host/subhalo relation covers hundreds of halos in one
+    group."""
+    note("assign many seeds in one group")
+    pos, vel, box = clump_lattice()
+    p = orc.make_params(box, 1e10, 0.01)
+    P = particles(orc, pos, vel)
+    o = orc.run_all(p, P)
+    fof = np.asarray(o["halos"]["fof"])
+    assert np.unique(fof).shape[0] == 1 and fof.shape[0] > 512
+    assert np.any(np.asarray(o["halos"]["merged_into"]) != np.arange(fof.shape[0]))
+    _, _, _, gh, gho = gpu_pipeline(H, particles_from_arrays(pos, vel),
+                                    H.Params(box=box, particle_mass=1e10, softening=0.01))
+    assert_halos_equal(gh, o["halos"])
+    np.testing.assert_array_equal(gho, o["halo_of"])
