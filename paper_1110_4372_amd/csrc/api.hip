@@ -32,25 +32,6 @@ void Ctx::ensure_ws(size_t bytes) {
   ws.cap = want;
 }
 
-void* Ctx::ensure_aux(size_t bytes) {
-  if (bytes <= aux_cap) return aux;
-  if (aux) {
-    HALO_HIP(hipDeviceSynchronize());
-    HALO_HIP(hipFree(aux));
-    aux = nullptr;
-    aux_cap = 0;
-  }
-  size_t want = bytes + bytes / 8 + 4096;
-  if (hipMalloc(&aux, want) != hipSuccess) {
-    (void)hipGetLastError();
-    aux = nullptr;
-    throw Error{LIBHALO_ENOMEM, "auxiliary allocation of " + std::to_string(want) +
-                                    " bytes failed"};
-  }
-  aux_cap = want;
-  return aux;
-}
-
 hipEvent_t Ctx::event() {
   if (!spare.empty()) {
     hipEvent_t e = spare.back();
@@ -71,9 +52,6 @@ void Ctx::release() {
   recs.clear();
   spare.clear();
   if (ws.base) (void)hipFree(ws.base);
-  if (aux) (void)hipFree(aux);
-  aux = nullptr;
-  aux_cap = 0;
   if (d_err) (void)hipFree(d_err);
   if (h_pinned) (void)hipHostFree(h_pinned);
   ws.base = nullptr;

@@ -88,15 +88,10 @@ struct Ctx {
   int device = 0;
   std::string err;
   Arena ws;
-  // second device buffer for scratch whose size is known only after part of a
-  // stage has run (grows like ws, never moves the main workspace)
-  void* aux = nullptr;
-  size_t aux_cap = 0;
   uint32_t* d_err = nullptr;       // device error word
   void* h_pinned = nullptr;        // small pinned host buffer for read-backs
   hipStream_t stream = nullptr;
   void ensure_ws(size_t bytes);
-  void* ensure_aux(size_t bytes);
   void release();
   template <class T>
   T* host_slot(int i) { return reinterpret_cast<T*>(static_cast<char*>(h_pinned) + 64 * i); }

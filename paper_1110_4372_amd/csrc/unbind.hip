@@ -192,10 +192,20 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint
 // ------------------------------------------------------------ potentials --
 // Work unit: 64 own particles (one wavefront, lane = particle) of a halo
 // against one j-chunk of its S(h).  The chunk is at least kPotJ particles and
-// grows with |S(h)| so a halo has at most 64 chunks.  Each unit writes one
-// partial sum per particle; the partials of a particle are added in chunk
-// order afterwards, so the result does not depend on which wave ran which unit.
+// grows with |S(h)| so a halo has at most 64 chunks.  Each unit adds its
+// partial sum per particle into a 128-bit fixed-point accumulator (64
+// fractional bits) with integer atomics: integer addition is associative, so
+// the result does not depend on which wave ran which unit or in what order.
 constexpr uint32_t kPotJ = 2048;
+
+// v >= 0 (a sum of positive terms, far below 2^63) in units of 2^-64.
+__device__ __forceinline__ I128 pot_fixed(double v) {
+  const double ip = floor(v);
+  I128 r;
+  r.hi = (long long)ip;
+  r.lo = (unsigned long long)((v - ip) * 18446744073709551616.0);
+  return r;
+}
 
 __host__ __device__ __forceinline__ uint32_t pot_chunk(uint32_t ns) {
   uint32_t c = (ns + 63u) / 64u;
@@ -203,11 +213,10 @@ __host__ __device__ __forceinline__ uint32_t pot_chunk(uint32_t ns) {
   return c > kPotJ ? c : kPotJ;
 }
 
-// Per kept halo: unit and partial counts; the sort key orders units by cost,
+// Per kept halo: the unit count; the sort key orders units by cost,
 // largest first (a unit costs ~ 64 * min(|S(h)|, chunk) terms).
 __global__ void k_pot_counts(const libhalo_halos h, uint32_t S, const uint32_t* nS,
-                             uint32_t* ucnt, unsigned long long* pcnt, uint32_t* key,
-                             uint32_t* val) {
+                             uint32_t* ucnt, uint32_t* key, uint32_t* val) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;
   const uint32_t nown = h.n_assigned[s], ns = nS[s];
@@ -215,7 +224,6 @@ __global__ void k_pot_counts(const libhalo_halos h, uint32_t S, const uint32_t* 
   const uint32_t J = pot_chunk(ns);
   const uint32_t nc = (ns + J - 1) / J;
   ucnt[s] = on ? ((nown + 63u) / 64u) * nc : 0u;
-  pcnt[s] = on ? (unsigned long long)nown * nc : 0ull;
   key[s] = on ? ~min(ns, J) : 0xFFFFFFFFu;
   val[s] = s;
 }
@@ -326,9 +334,8 @@ __global__ void __launch_bounds__(TB)
                     const double* __restrict__ uz, const libhalo_halos h,
                     const uint32_t* __restrict__ order, const uint32_t* __restrict__ uoff,
                     uint32_t K, const uint32_t* __restrict__ slot,
-                    const uint32_t* __restrict__ nS, const unsigned long long* __restrict__ poff,
-                    uint32_t u0, uint32_t u1, uint32_t* ctr, double eps2,
-                    double* __restrict__ part) {
+                    const uint32_t* __restrict__ nS, uint32_t u0, uint32_t u1, uint32_t* ctr,
+                    double eps2, I128* __restrict__ acc) {
   for (uint32_t t = 0;; ++t) {
     const uint32_t u = pot_next(ctr, u0, t);
     if (u >= u1) break;
@@ -343,7 +350,7 @@ __global__ void __launch_bounds__(TB)
     pot_span_f64<false>(ux, uy, uz, b + w.s1, b + w.j1, 0u, xi, yi, zi, eps2, A, C);
     const double a = (A[0] + A[1]) + (A[2] + A[3]);
     const double c = (C[0] + C[1]) + (C[2] + C[3]);
-    if (ok) part[poff[w.hh] + (unsigned long long)w.c * w.nown + w.i] = __fma_rn(0.5, c, a);
+    if (ok) atomic_add_i128(acc + qi, pot_fixed(__fma_rn(0.5, c, a)));
   }
 }
 
@@ -414,9 +421,8 @@ __global__ void __launch_bounds__(TB)
                     const float* __restrict__ fz, const libhalo_halos h,
                     const uint32_t* __restrict__ order, const uint32_t* __restrict__ uoff,
                     uint32_t K, const uint32_t* __restrict__ slot,
-                    const uint32_t* __restrict__ nS, const unsigned long long* __restrict__ poff,
-                    uint32_t u0, uint32_t u1, uint32_t* ctr, float eps2,
-                    double* __restrict__ part) {
+                    const uint32_t* __restrict__ nS, uint32_t u0, uint32_t u1, uint32_t* ctr,
+                    float eps2, I128* __restrict__ out) {
   for (uint32_t t = 0;; ++t) {
     const uint32_t u = pot_next(ctr, u0, t);
     if (u >= u1) break;
@@ -429,29 +435,19 @@ __global__ void __launch_bounds__(TB)
     pot_span_f32<false>(fx, fy, fz, b + w.j0, b + w.s0, 0u, xi, yi, zi, eps2, acc, comp);
     pot_span_f32<true>(fx, fy, fz, b + w.s0, b + w.s1, b + w.i, xi, yi, zi, eps2, acc, comp);
     pot_span_f32<false>(fx, fy, fz, b + w.s1, b + w.j1, 0u, xi, yi, zi, eps2, acc, comp);
-    if (ok)
-      part[poff[w.hh] + (unsigned long long)w.c * w.nown + w.i] = (double)acc - (double)comp;
+    if (ok) atomic_add_i128(out + qi, pot_fixed((double)acc - (double)comp));
   }
 }
 
-// sum[q] = the particle's chunk partials added in chunk order.
-__global__ void k_pot_reduce(const libhalo_halos h, const uint32_t* lhalo, const uint32_t* slot,
-                             const uint32_t* nS, const unsigned long long* poff,
-                             const double* part, uint32_t m, double* sum) {
+__global__ void k_zero_i128(I128* a, uint32_t m) {
   uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  const uint32_t hh = lhalo[q];
-  if (h.merged_into[hh] != (int32_t)hh) {
-    sum[q] = 0.0;
-    return;
-  }
-  const uint32_t i = q - slot[hh], nown = h.n_assigned[hh], ns = nS[hh];
-  const uint32_t J = pot_chunk(ns);
-  const uint32_t nc = (ns + J - 1) / J;
-  const double* p = part + poff[hh] + i;
-  double s = p[0];
-  for (uint32_t c = 1; c < nc; ++c) s += p[(size_t)c * nown];
-  sum[q] = s;
+  if (q < m) a[q] = I128{0ull, 0ll};
+}
+
+// sum[q] = the particle's fixed-point potential sum as FP64.
+__global__ void k_pot_finish(const I128* acc, uint32_t m, double* sum) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) sum[q] = ldexp(i128_to_f64(acc[q]), -64);
 }
 
 // FP64 recheck of one particle's potential (mixed form), one block per particle.
@@ -591,10 +587,9 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     uint32_t *flag, *pos, *ck0, *cv0, *ck1, *cv1, *ccnt, *coff, *nS, *depth, *slot, *rootv,
         *dcnt, *stmp, *ak0, *av0, *ak1, *av1, *gfirst, *lp, *lhalo, *nb_own, *nbS, *rlist,
         *ucnt, *uoff, *pk0, *pv0, *pk1, *pv1;
-    unsigned long long *pcnt, *poff, *stmp64;
     double *ux, *uy, *uz, *vb, *sum;
     float *lvx, *lvy, *lvz, *fx, *fy, *fz;
-    I128 *accO, *accS;
+    I128 *accO, *accS, *pacc;
     void *rtmp;
   } w;
   carve_workspace(ctx, [&](Arena& A) {
@@ -626,9 +621,6 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     w.pv0 = A.take<uint32_t>(S2);
     w.pk1 = A.take<uint32_t>(S2);
     w.pv1 = A.take<uint32_t>(S2);
-    w.pcnt = A.take<unsigned long long>(S2);
-    w.poff = A.take<unsigned long long>(S2);
-    w.stmp64 = A.take<unsigned long long>(scan_tmp_elems<unsigned long long>(S2));
     w.nb_own = A.take<uint32_t>(S2);
     w.nbS = A.take<uint32_t>(S2);
     w.rlist = A.take<uint32_t>(N2);
@@ -645,6 +637,7 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     w.fz = mixed ? A.take<float>(N2) : nullptr;
     w.accO = A.take<I128>(3 * S2);
     w.accS = A.take<I128>(3 * S2);
+    w.pacc = A.take<I128>(N2);
     w.rtmp = A.take<char>(radix_tmp_bytes(std::max(S2, N2)));
   });
   // children lists of the host/sub forest, ascending ids per host
@@ -696,18 +689,14 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
   k_vbulk<<<blocks_for(S, TB), TB, 0, s>>>(w.accS, w.nS, S, w.vb);
   // potentials: work units ordered largest first, one partial per particle
   // and j-chunk, partials added in chunk order
-  k_pot_counts<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, w.ucnt, w.pcnt, w.pk0, w.pv0);
+  k_pot_counts<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, w.ucnt, w.pk0, w.pv0);
   const bool fo = radix_sort_pairs<uint32_t>(w.pk0, w.pv0, w.pk1, w.pv1, S, 32, w.rtmp, s);
   const uint32_t* order = fo ? w.pv1 : w.pv0;
   k_gather_u32<<<blocks_for(S, TB), TB, 0, s>>>(w.ucnt, order, S, w.uoff);
   exclusive_scan<uint32_t>(w.uoff, w.uoff, S, w.uoff + S, w.stmp, s);
-  exclusive_scan<unsigned long long>(w.pcnt, w.poff, S, w.poff + S, w.stmp64, s);
-  unsigned long long* hb64 = ctx.host_slot<unsigned long long>(1);
-  HALO_HIP(hipMemcpyAsync(hb64, w.poff + S, 8, hipMemcpyDeviceToHost, s));
   const uint32_t U = readu(w.uoff + S, 2);
-  const unsigned long long NP = *hb64;
   if (m > 0) {
-    double* part = static_cast<double*>(ctx.ensure_aux(8ull * (NP ? NP : 1ull)));
+    k_zero_i128<<<blocks_for(m, TB), TB, 0, s>>>(w.pacc, m);
     if (mixed)
       k_rel_f32<<<blocks_for(m, TB), TB, 0, s>>>(w.ux, w.uy, w.uz, h, w.slot, w.lhalo, m, w.fx,
                                                  w.fy, w.fz);
@@ -715,13 +704,12 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       if (mixed)
         HALO_PROF(ctx, "k_potential_f32", s,
                   k_potential_f32<<<grid, TB, 0, s>>>(w.fx, w.fy, w.fz, h, order, w.uoff, S,
-                                                      w.slot, w.nS, w.poff, u0, u1, ctr,
-                                                      (float)eps2, part));
+                                                      w.slot, w.nS, u0, u1, ctr, (float)eps2,
+                                                      w.pacc));
       else
         HALO_PROF(ctx, "k_potential_f64", s,
                   k_potential_f64<<<grid, TB, 0, s>>>(w.ux, w.uy, w.uz, h, order, w.uoff, S,
-                                                      w.slot, w.nS, w.poff, u0, u1, ctr, eps2,
-                                                      part));
+                                                      w.slot, w.nS, u0, u1, ctr, eps2, w.pacc));
     };
     if (plain) {
       // one launch per halo, in halo order, each over that halo's units
@@ -739,8 +727,7 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 4, 1, 0u);
       launch(0, U, w.dcnt + 4, kPersist);
     }
-    k_pot_reduce<<<blocks_for(m, TB), TB, 0, s>>>(h, w.lhalo, w.slot, w.nS, w.poff, part, m,
-                                                  w.sum);
+    k_pot_finish<<<blocks_for(m, TB), TB, 0, s>>>(w.pacc, m, w.sum);
     k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 3, 1, 0u);
     k_energy<<<blocks_for(m, TB), TB, 0, s>>>(w.sum, w.lvx, w.lvy, w.lvz, w.lhalo, w.lp, w.vb, m,
                                              mGm, P.e_recheck, mixed ? 1 : 0, bound, phi,

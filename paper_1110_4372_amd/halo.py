@@ -177,7 +177,7 @@ class Particles:
     @classmethod
     def from_catalog(cls, cat, device="cuda"):
         def t(a):
-            return torch.from_numpy(a).to(device)
+            return a if isinstance(a, torch.Tensor) else torch.from_numpy(a).to(device)
         return cls(t(cat.x), t(cat.y), t(cat.z), t(cat.vx), t(cat.vy), t(cat.vz))
 
     @property

@@ -305,3 +305,133 @@ def nfw_halo(n: int, conc: float, mass: float, seed: int = 0,
         sigma = math.sqrt(G_NEWTON * mass / (2.0 * rvir))
     vel = np.asarray(bulk, float) + sigma * rng.standard_normal((n, 3))
     return np.mod(pos, box), vel.astype(np.float32), rvir
+
+
+@dataclasses.dataclass
+class DeviceCatalog:
+    """A catalogue whose particle arrays live on the GPU (torch tensors)."""
+    spec_name: str
+    box: float
+    n: int
+    x: "object"
+    y: "object"
+    z: "object"
+    vx: "object"
+    vy: "object"
+    vz: "object"
+    particle_mass: float
+    softening: float
+    halos: dict
+
+
+def make_catalog_device(name: str, seed: int = 0, device: str = "cuda",
+                        chunk: int = 1 << 25) -> DeviceCatalog:
+    """The power-law catalogues (c2, c3, c5) drawn with the same recipe as
+    ``make_catalog``, with the particles sampled on the GPU in chunks of haloes.
+
+    The halo and subhalo tables come from numpy's generator seeded by ``seed``
+    exactly as in ``make_catalog``; particle positions, velocities, the
+    background and the final shuffle come from torch's generator on ``device``
+    seeded by ``seed``, so the realisation differs from ``make_catalog``'s while
+    every distribution is the same.  NFW radii solve f(x) = p by bisection in
+    FP64 instead of through the Lambert W function.
+    """
+    import torch
+
+    spec = SPECS[name]
+    if spec.kind != "powerlaw" or spec.cluster_n:
+        raise NotImplementedError("device generator covers the power-law catalogues")
+    rng = np.random.default_rng(seed)
+    n_total, box = spec.n, spec.box
+    mp = particle_mass(n_total, box)
+
+    sizes = _draw_host_sizes(rng, spec)
+    n_host = sizes.shape[0]
+    sub_host = np.nonzero(sizes >= spec.sub_min_host)[0]
+    sub_sizes = np.floor(spec.sub_frac * sizes[sub_host]).astype(np.int64)
+    host_mass = sizes * mp
+    host_rvir = virial_radius(host_mass)
+    host_c = 5.0 + 5.0 * rng.random(n_host)
+    host_sig = np.sqrt(G_NEWTON * host_mass / (2.0 * host_rvir))
+    host_ctr = rng.random((n_host, 3)) * box
+    host_bulk = 300.0 * rng.standard_normal((n_host, 3))
+    own = sizes.copy()
+    np.subtract.at(own, sub_host, sub_sizes)
+    sub_mass = sub_sizes * mp
+    sub_rvir = virial_radius(np.maximum(sub_mass, mp))
+    sub_c = 5.0 + 5.0 * rng.random(sub_host.shape[0])
+    sub_sig = np.sqrt(G_NEWTON * np.maximum(sub_mass, mp) / (2.0 * sub_rvir))
+    sub_r = _nfw_radii(rng, host_c[sub_host], host_rvir[sub_host], 0.1, 1.0)
+    sub_ctr = host_ctr[sub_host] + sub_r[:, None] * _iso_dirs(rng, sub_host.shape[0])
+    sub_bulk = host_bulk[sub_host] + host_sig[sub_host, None] * rng.standard_normal(
+        (sub_host.shape[0], 3))
+
+    all_sizes = np.concatenate([own, sub_sizes])
+    tables = [np.concatenate([host_ctr, sub_ctr]), np.concatenate([host_bulk, sub_bulk]),
+              np.concatenate([host_c, sub_c]), np.concatenate([host_rvir, sub_rvir]),
+              np.concatenate([host_sig, sub_sig])]
+    dev = torch.device(device)
+    ctr_t, bulk_t, c_t, rv_t, sig_t = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                                       for a in tables)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    f64 = torch.float64
+    P = torch.empty((3, n_total), dtype=torch.float32, device=dev)
+    V = torch.empty((3, n_total), dtype=torch.float32, device=dev)
+
+    def uni(k):
+        return torch.rand(k, generator=gen, device=dev, dtype=f64)
+
+    def nfw_f(x):
+        return torch.log1p(x) - x / (1.0 + x)
+
+    cum = np.concatenate([[0], np.cumsum(all_sizes)])
+    off, h0, nh = 0, 0, all_sizes.shape[0]
+    while h0 < nh:
+        h1 = int(np.searchsorted(cum, cum[h0] + chunk, side="right")) - 1
+        h1 = max(h1, h0 + 1)
+        h1 = min(h1, nh)
+        cnt = torch.from_numpy(all_sizes[h0:h1]).to(dev)
+        hid = torch.repeat_interleave(torch.arange(h0, h1, device=dev), cnt)
+        k = int(hid.shape[0])
+        c = c_t[hid]
+        p = uni(k) * nfw_f(c)
+        lo = torch.zeros(k, dtype=f64, device=dev)
+        hi = c.clone()
+        for _ in range(60):  # f(x) = p on [0, c]; f increases monotonically
+            mid = 0.5 * (lo + hi)
+            below = nfw_f(mid) < p
+            lo = torch.where(below, mid, lo)
+            hi = torch.where(below, hi, mid)
+        r = 0.5 * (lo + hi) * (rv_t[hid] / c)
+        del lo, hi, p, c
+        mu = 2.0 * uni(k) - 1.0
+        phi = (2.0 * math.pi) * uni(k)
+        s = torch.sqrt(torch.clamp(1.0 - mu * mu, min=0.0))
+        d = (s * torch.cos(phi), s * torch.sin(phi), mu)
+        for a in range(3):
+            P[a, off:off + k] = (ctr_t[hid, a] + r * d[a]).float()
+            V[a, off:off + k] = (bulk_t[hid, a] + sig_t[hid] * torch.randn(
+                k, generator=gen, device=dev, dtype=f64)).float()
+        off += k
+        h0 = h1
+        del hid, r, mu, phi, s, d
+    n_bg = n_total - off
+    if n_bg < 0:
+        raise ValueError("halo particles exceed the particle budget")
+    for a in range(3):
+        P[a, off:] = (uni(n_bg) * box).float()
+        V[a, off:] = (100.0 * torch.randn(n_bg, generator=gen, device=dev, dtype=f64)).float()
+    perm = torch.randperm(n_total, generator=gen, device=dev)
+    cols = []
+    for a in range(3):
+        col = torch.remainder(P[a][perm].double(), box).float()
+        col[col >= box] = 0.0
+        cols.append(col.contiguous())
+    del P
+    vcols = [V[a][perm].contiguous() for a in range(3)]
+    del V, perm
+    halos = dict(host_sizes=sizes, host_centres=host_ctr, host_bulk=host_bulk,
+                 host_rvir=host_rvir, host_c=host_c, sub_host=sub_host, sub_sizes=sub_sizes)
+    return DeviceCatalog(spec.name, box, n_total, cols[0], cols[1], cols[2], vcols[0],
+                         vcols[1], vcols[2], mp, default_softening(n_total, box), halos)
