@@ -48,25 +48,42 @@ def measured_traffic(kernel):
     return rec["bytes"]
 
 
-def one_step(ctx, P):
+STAGES = ("fof3d", "refine6d", "assign", "unbind", "props")
+
+
+def one_step(ctx, P, ev=None):
+    """The five calls; ev (6 HIP events on the launch stream) brackets them."""
+    rec = (lambda i: ev[i].record()) if ev else (lambda i: None)
+    rec(0)
     fof = ctx.fof3d(P)
+    rec(1)
     nodes, deepest = ctx.refine6d(P, fof)
+    rec(2)
     halos, halo_of = ctx.assign(P, nodes, deepest)
+    rec(3)
     unb, bound, phi = ctx.unbind(P, halos, halo_of, want_phi=False)
-    pr = ctx.props(P, nodes, halos, halo_of, bound)
+    rec(4)
+    ctx.props(P, nodes, halos, halo_of, bound)
+    rec(5)
     return fof, nodes, halos, halo_of, unb
 
 
 def timed(ctx, P, steps, warmup):
+    """Mean wall time per step over `steps` after `warmup`, and the mean device
+    time of each call (HIP events, read after the timed region)."""
     import torch
     for _ in range(warmup):
         one_step(ctx, P)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        out = one_step(ctx, P)
+    for k in range(steps):
+        out = one_step(ctx, P, evs[k])
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps, out
+    sec = (time.perf_counter() - t0) / steps
+    stage = {STAGES[i]: sum(e[i].elapsed_time(e[i + 1]) for e in evs) / steps
+             for i in range(5)}
+    return sec, out, stage
 
 
 def pair_work(ctx, P, out):
@@ -88,22 +105,31 @@ def pair_work(ctx, P, out):
 def cpu_baseline(cat, budget_s: float = 20.0):
     """The CPU oracle (serial FP64 C) on a sub-volume of the catalogue: the
     particles of the corner cube [0, L/k)^3, treated as a periodic box of side
-    L/k (the same linking length), k chosen so the run takes ~budget_s."""
+    L/k (the same linking length), k chosen so the run takes ~budget_s (at
+    least 4, and large enough that the cube holds ~65k particles)."""
     import numpy as np
     from oracle import oracle as O
     from paper_1110_4372_amd import synth
     O.build(force=False)
-    for frac in (4, 3, 2):
+
+    def host(a):
+        return a.cpu().numpy() if hasattr(a, "cpu") else a
+
+    k0 = max(4, int(round((cat.n / 65536.0) ** (1.0 / 3.0))))
+    fracs = list(range(k0, max(1, k0 // 3), -1))
+    for frac in fracs:
         side = cat.box / frac
         sel = (cat.x < side) & (cat.y < side) & (cat.z < side)
-        sub = synth.Catalog(cat.spec_name, side, int(sel.sum()), *(np.ascontiguousarray(a[sel])
-                            for a in (cat.x, cat.y, cat.z, cat.vx, cat.vy, cat.vz)),
-                            cat.particle_mass, cat.softening, cat.truth[sel], {})
+        cols = [np.ascontiguousarray(host(a[sel])) for a in (cat.x, cat.y, cat.z, cat.vx,
+                                                            cat.vy, cat.vz)]
+        nsel = int(cols[0].shape[0])
+        sub = synth.Catalog(cat.spec_name, side, nsel, *cols, cat.particle_mass,
+                            cat.softening, np.full(nsel, -1, np.int64), {})
         p = O.params_of(sub)
         t0 = time.perf_counter()
         O.run_all(p, O.Particles.of(sub))
         dt = time.perf_counter() - t0
-        if dt > budget_s / 4 or frac == 2:
+        if dt > budget_s / 4 or frac == fracs[-1]:
             return dict(value=sub.n / dt, unit="particles/s", cores=1, kind="oracle",
                         sample=f"corner sub-box of side L/{frac} ({sub.n} particles) of the "
                                f"same catalogue, full path fof3d..props, serial C, "
@@ -122,6 +148,12 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration)")
+    ap.add_argument("--grid-min", type=int, default=0,
+                    help="nodes above this many particles use the 6D tile search "
+                         "(0: the library default)")
+    ap.add_argument("--gen", default="host", choices=["host", "device"],
+                    help="catalogue generator: numpy (host) or torch on the GPU (device; "
+                         "power-law configs, for the 512^3 and 1024^3 catalogues)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -132,11 +164,14 @@ def main():
     from paper_1110_4372_amd import halo as H
     from paper_1110_4372_amd import synth
 
-    cat = synth.make_catalog(args.config, seed=0)
+    if args.gen == "device":
+        cat = synth.make_catalog_device(args.config, seed=0)
+    else:
+        cat = synth.make_catalog(args.config, seed=0)
     P = H.Particles.from_catalog(cat)
     prec = H.PREC_FP64 if args.prec == "fp64" else H.PREC_MIXED
-    ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec))
-    sec, out = timed(ctx, P, args.steps, args.warmup)
+    ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=args.grid_min))
+    sec, out, stage = timed(ctx, P, args.steps, args.warmup)
 
     # dominant kernels, timed with HIP events on the library's launch stream
     ctx.profile(True)
@@ -169,8 +204,9 @@ def main():
 
     plain = None
     if not args.no_plain:
-        ctxp = H.Halo(H.params_for_catalog(cat, mode=H.PLAIN, prec=prec))
-        sp, _ = timed(ctxp, P, 1, 1)
+        ctxp = H.Halo(H.params_for_catalog(cat, mode=H.PLAIN, prec=prec,
+                                           grid_min=args.grid_min))
+        sp, _, _ = timed(ctxp, P, 1, 1)
         plain = {"value": cat.n / sp, "ms_per_step": sp * 1e3}
 
     if args.copy_probe:
@@ -187,10 +223,12 @@ def main():
         "dtype": "f64+f32" if prec == H.PREC_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {cat.n} particles, box {cat.box} Mpc/h, "
-                               "power-law NFW hosts + subhaloes + 40% uniform, seed 0",
+                               "power-law NFW hosts + subhaloes + 40% uniform, seed 0"
+                               + (" (GPU-drawn)" if args.gen == "device" else ""),
                    "form": "batched", "potential": args.prec,
                    "n_groups": int(out[0]["n_groups"]), "n_nodes": int(out[1]["parent"].shape[0]),
                    "n_halos": int(out[2]["seed_node"].shape[0])},
+        "stage_ms": stage,
         "plain": plain,
         "roofline": roofline,
         "cpu_baseline": cpu,

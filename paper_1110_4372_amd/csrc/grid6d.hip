@@ -90,7 +90,8 @@ __global__ void __launch_bounds__(TB) k_grid_params(GridBufs g, uint32_t NB, dou
   if (b >= NB) return;
   for (int e = threadIdx.x; e < kSamples; e += TB) v[e] = g.samp[(size_t)b * kSamples + e];
   __syncthreads();
-  int kq = (int)ceil(f * (double)kSamples);
+  // rank margin of ~2 standard deviations of the sample quantile's rank
+  int kq = (int)ceil((f + kSampleMargin) * (double)kSamples);
   kq = kq < 1 ? 1 : (kq > kSamples ? kSamples : kq);
   for (int e = threadIdx.x; e < kSamples; e += TB) {
     int rank = 0;
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(TB) k_grid_params(GridBufs g, uint32_t NB, dou
     if (rank == kq - 1) pick = x;
   }
   __syncthreads();
-  if (threadIdx.x == 0) g.r2[b] = fmaxf(2.0f * pick, 1e-30f);
+  if (threadIdx.x == 0) g.r2[b] = fmaxf(kRadiusFactor * pick, 1e-30f);
 }
 
 __global__ void k_grid_flags(const uint32_t* lnode, uint32_t M, GridBufs g, uint32_t* flag) {
@@ -237,31 +238,23 @@ __global__ void __launch_bounds__(kTile)
         const uint32_t jtile = jc + bit;
         const uint32_t q0 = ps + (jtile - tb0) * kTile;
         const uint32_t q1 = min(pe, q0 + kTile);
-        __syncthreads();
-        if (q0 + lane < q1) {
-          const uint32_t qj = q0 + lane;
-          for (int c = 0; c < 6; ++c) t[c][lane] = X[(size_t)c * MB + qj];
-          if (MODE == 1) {
+        if (MODE == 1) {  // the FOF pass stages the tile and its roots
+          __syncthreads();
+          if (q0 + lane < q1) {
+            const uint32_t qj = q0 + lane;
+            for (int c = 0; c < 6; ++c) t[c][lane] = X[(size_t)c * MB + qj];
             const uint32_t mj = g.gm[qj];
             troot[lane] = __uint_as_float(D[mj]) <= l2 ? uf_find(par, mj) : 0xFFFFFFFEu;
           }
+          __syncthreads();
         }
-        __syncthreads();
         const uint32_t nj = q1 - q0;
         if (MODE == 0) {
-          if (jtile == it) {
-            for (uint32_t q = 0; q < nj; ++q) {
-              float d = d2_6(a0, a1, a2, a3, a4, a5, t[0][q], t[1][q], t[2][q], t[3][q], t[4][q],
-                             t[5][q]);
-              if (q != (uint32_t)lane) best = fminf(best, d);
-            }
-          } else {
-            for (uint32_t q = 0; q < nj; ++q) {
-              float d = d2_6(a0, a1, a2, a3, a4, a5, t[0][q], t[1][q], t[2][q], t[3][q], t[4][q],
-                             t[5][q]);
-              best = fminf(best, d);
-            }
-          }
+          const float av[6] = {a0, a1, a2, a3, a4, a5};
+          if (jtile == it)
+            best = nn_span<true>(X, MB, q0, q1, qi, av, best);
+          else
+            best = nn_span<false>(X, MB, q0, q1, 0u, av, best);
         } else if (active) {
           const uint32_t qstart = (jtile == it) ? (uint32_t)lane + 1 : 0u;
           for (uint32_t q = qstart; q < nj; ++q) {

@@ -255,38 +255,6 @@ __global__ void k_pair_items(const uint32_t* count, const double* prm, const uin
   items[k] = (active && sel) ? nn_units(n) : 0u;
 }
 
-// min over j in [j0, j1) of d2(i, j); the six j coordinates are wave-uniform
-// scalar loads.  kSelf: skip j == self.
-template <bool kSelf>
-__device__ __forceinline__ float nn_span(const float* __restrict__ xi, size_t S, uint32_t j0,
-                                         uint32_t j1, uint32_t self, const float* a,
-                                         float best) {
-  uint32_t j = j0;
-  for (; j + 8 <= j1; j += 8) {
-    float b[6][8];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const float* __restrict__ p = xi + (size_t)c * S + j;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) b[c][u] = p[u];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], b[0][u], b[1][u], b[2][u],
-                           b[3][u], b[4][u], b[5][u]);
-      if (kSelf)
-        best = (j + u != self) ? fminf(best, d) : best;
-      else
-        best = fminf(best, d);
-    }
-  }
-  for (; j < j1; ++j) {
-    const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], xi[j], xi[S + j], xi[2 * S + j],
-                         xi[3 * S + j], xi[4 * S + j], xi[5 * S + j]);
-    if (!kSelf || j != self) best = fminf(best, d);
-  }
-  return best;
-}
 
 // Lane exchanges for the cross-lane minima (whole wave active).  The minima
 // work on FP32 bit patterns as unsigned integers: every value is a

@@ -68,14 +68,14 @@ def test_assign_c1(H, c1, c1_oracle):
     assert kept.sum() >= 10 and (~kept).sum() >= 1
 
 
-def test_assign_c2_sampled(H, orc):
-    """128^3 catalogue; the oracle runs refine + assign on sampled FOF groups."""
-    from paper_1110_4372_amd import synth
+def test_assign_c2_sampled(H, orc, c2, c2_fof_oracle):
+    """128^3 catalogue; the oracle runs refine + assign on sampled FOF groups
+    (its own FOF labels, every other group cut into singletons)."""
     note("assign c2 sampled")
-    cat = synth.make_catalog("c2")
+    cat = c2
     fof, gn, gd, gh, gho = gpu_pipeline(H, H.Particles.from_catalog(cat),
                                         H.params_for_catalog(cat))
-    lab = to_np(fof["label"]).astype(np.int64)
+    lab = np.asarray(c2_fof_oracle).astype(np.int64)
     sizes = np.bincount(lab, minlength=lab.shape[0])
     groups = np.nonzero(sizes >= 10)[0]
     rng = np.random.default_rng(1)

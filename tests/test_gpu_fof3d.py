@@ -56,15 +56,12 @@ def test_fof3d_c1(H, orc, c1):
     _check_groups(want, got)
 
 
-def test_fof3d_c2_full(H, orc):
+def test_fof3d_c2_full(H, c2, c2_fof_oracle):
     """128^3 in a 100 Mpc/h box (float32 positions), full comparison."""
-    from paper_1110_4372_amd import synth
     note("fof3d c2 128^3")
-    cat = synth.make_catalog("c2")
-    want = orc.fof3d(orc.params_of(cat), orc.Particles.of(cat))
-    ctx = H.Halo(H.params_for_catalog(cat))
-    got = ctx.fof3d(H.Particles.from_catalog(cat))
-    _check_groups(want, got)
+    ctx = H.Halo(H.params_for_catalog(c2))
+    got = ctx.fof3d(H.Particles.from_catalog(c2))
+    _check_groups(c2_fof_oracle, got)
 
 
 def test_fof3d_lattice_edge(H, orc):

@@ -96,19 +96,18 @@ def test_refine_c1(H, orc, c1, c1_oracle, mode, grid_min):
     np.testing.assert_array_equal(to_np(gd), c1_oracle["deepest"])
 
 
-def test_refine_c2_sampled(H, orc):
+def test_refine_c2_sampled(H, orc, c2, c2_fof_oracle):
     """128^3 catalogue at full size; the oracle refines a sample of FOF groups
-    (every other group is cut into singletons in its input labels)."""
-    from paper_1110_4372_amd import synth
+    (its own FOF labels, every other group cut into singletons)."""
     note("refine6d c2 sampled groups")
-    cat = synth.make_catalog("c2")
+    cat = c2
     ctx = H.Halo(H.params_for_catalog(cat))
     P = H.Particles.from_catalog(cat)
     fof = ctx.fof3d(P)
     gn, gd = ctx.refine6d(P, fof)
     gn = gpu_nodes(gn)
     gd = to_np(gd)
-    lab = to_np(fof["label"]).astype(np.int64)
+    lab = np.asarray(c2_fof_oracle).astype(np.int64)
     sizes = np.bincount(lab, minlength=lab.shape[0])
     groups = np.nonzero(sizes >= 10)[0]
     rng = np.random.default_rng(0)
