@@ -1,0 +1,169 @@
+"""The 512^3 catalogue at full size (134M particles, drawn on the GPU), checked
+against the oracle on sampled FOF groups.
+
+FOF membership is local: a group whose members all lie more than ll inside a
+sub-cube of the box is the same group when FOF runs on the sub-cube's
+particles alone.  The oracle runs the whole path on the particles of a few
+random sub-cubes (the box and the linking length of the full catalogue), and
+the GPU's output for the interior groups -- labels, node table, deepest node,
+halo table, halo_of and bound flags -- must match it exactly, as at the
+smaller sizes."""
+import numpy as np
+import pytest
+import torch
+
+from tests.gpu_util import note, to_np
+from tests.test_gpu_assign import assert_halos_equal
+from tests.test_gpu_refine6d import assert_nodes_equal, gpu_nodes, subset_nodes
+from tests.test_gpu_unbind_props import energy_band
+
+pytestmark = pytest.mark.gpu
+
+CUBE = 30.0  # Mpc/h; ~17k particles of the 512^3 catalogue on average
+MAX_SUB = 60000
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1110_4372_amd import halo
+    halo.load_library()
+    return halo
+
+
+def _subset_halos(hal, keep_fof, node_remap):
+    """Rows of the haloes of the FOF groups in keep_fof, re-indexed."""
+    rows = np.nonzero(np.isin(hal["fof"].astype(np.int64), keep_fof))[0]
+    remap = np.full(hal["fof"].shape[0] + 1, -1, np.int64)
+    remap[rows] = np.arange(rows.shape[0])
+    out = {k: np.asarray(v)[rows].copy() for k, v in hal.items()}
+    out["seed_node"] = node_remap[out["seed_node"].astype(np.int64)]
+    for k in ("merged_into", "host"):
+        v = out[k].astype(np.int64)
+        out[k] = np.where(v >= 0, remap[v], -1)
+    return out, remap
+
+
+def test_c3_full_size_subcubes(H, orc):
+    from paper_1110_4372_amd import synth
+    note("c3 full size, oracle on sub-cubes")
+    cat = synth.make_catalog_device("c3", seed=0)
+    P = H.Particles.from_catalog(cat)
+    ctx = H.Halo(H.params_for_catalog(cat))
+    fof = ctx.fof3d(P)
+    nodes, deep = ctx.refine6d(P, fof)
+    halos, hof = ctx.assign(P, nodes, deep)
+    unb, bound, _ = ctx.unbind(P, halos, hof, want_phi=False)
+    torch.cuda.synchronize()
+    glab = to_np(fof["label"]).astype(np.int64)
+    gn = gpu_nodes(nodes)
+    gdeep = to_np(deep).astype(np.int64)
+    gh = {k: to_np(v) for k, v in halos.items()}
+    ghof = to_np(hof).astype(np.int64)
+    gbound = to_np(bound)
+    gsize = np.bincount(glab, minlength=glab.shape[0])
+
+    N, L = cat.n, cat.box
+    ll = 0.28 * L / N ** (1.0 / 3.0)
+    rng = np.random.default_rng(7)
+    checked_groups = checked_nodes = checked_halos = 0
+    for corner in rng.random((6, 3)) * (L - CUBE):
+        lo, hi = corner, corner + CUBE
+        inside = torch.ones(N, dtype=torch.bool, device=P.x.device)
+        for a, t in enumerate((P.x, P.y, P.z)):
+            inside &= (t >= float(lo[a])) & (t < float(hi[a]))
+        idx = to_np(torch.nonzero(inside).flatten()).astype(np.int64)
+        pos = np.stack([to_np(t[idx]) for t in (P.x, P.y, P.z)], 1)
+        vel = np.stack([to_np(t[idx]) for t in (P.vx, P.vy, P.vz)], 1)
+        n_sub = idx.shape[0]
+        print(f"cube at {np.round(lo, 1)}: {n_sub} particles", flush=True)
+        if n_sub > MAX_SUB:
+            continue  # part of a very large halo: the serial oracle would take minutes
+        # the oracle derives ll = b L / n^(1/3) from the particles it is given
+        p = orc.make_params(L, cat.particle_mass, cat.softening,
+                            b=0.28 * (n_sub / N) ** (1.0 / 3.0))
+        Po = orc.Particles(*(np.ascontiguousarray(pos[:, a]) for a in range(3)),
+                           *(np.ascontiguousarray(vel[:, a]) for a in range(3)))
+        o = orc.run_all(p, Po)
+        olab = o["label"].astype(np.int64)
+        sizes = np.bincount(olab, minlength=n_sub)
+        p64 = pos.astype(np.float64)
+        far = np.all((p64 >= lo + ll) & (p64 < hi - ll), axis=1)
+        groups = np.nonzero(sizes >= 10)[0]
+        interior = groups[np.array([far[olab == g].all() for g in groups], bool)] \
+            if groups.shape[0] else groups
+        if interior.shape[0] == 0:
+            continue
+        mem = np.isin(olab, interior)
+        # FOF: same members, label = smallest input index
+        np.testing.assert_array_equal(glab[idx[mem]], idx[olab[mem]])
+        keep = idx[interior]
+        np.testing.assert_array_equal(gsize[keep], sizes[interior])
+        # hierarchy of the interior groups
+        gsub, gremap = subset_nodes(gn, keep)
+        osub, oremap = subset_nodes(o["nodes"], interior)
+        for f in ("canon", "fof"):
+            osub[f] = idx[osub[f].astype(np.int64)]
+        assert_nodes_equal(gsub, osub)
+        np.testing.assert_array_equal(gremap[gdeep[idx[mem]]],
+                                      oremap[o["deepest"].astype(np.int64)[mem]])
+        # haloes and memberships
+        ghs, ghre = _subset_halos(gh, keep, gremap)
+        oh = {k: np.asarray(v) for k, v in o["halos"].items()}
+        ohs, ohre = _subset_halos(oh, interior, oremap)
+        ohs["fof"] = idx[ohs["fof"].astype(np.int64)]
+        assert_halos_equal(ghs, ohs)
+        gm = ghof[idx[mem]]
+        om = o["halo_of"].astype(np.int64)[mem]
+        np.testing.assert_array_equal(np.where(gm >= 0, ghre[gm], -1),
+                                      np.where(om >= 0, ohre[om], -1))
+        # bound flags wherever the energy lies outside the FP64 error band
+        decided = energy_band(o, Po, 1e-9) & mem
+        np.testing.assert_array_equal(gbound[idx[decided]], o["bound"][decided])
+        checked_groups += interior.shape[0]
+        checked_nodes += osub["parent"].shape[0]
+        checked_halos += ohs["seed_node"].shape[0]
+    print(f"checked {checked_groups} groups, {checked_nodes} nodes, {checked_halos} halos")
+    assert checked_groups >= 20 and checked_halos >= 20
+
+
+def test_c4_mixed_matches_fp64(H):
+    """256^3 plus a 5e6-particle cluster at full size: the mixed-precision form
+    (FP32 potential tiles, FP64 recheck of energies within 1e-4 of zero) against
+    the FP64 form.  Stages before unbinding do not depend on the precision and
+    must match bit for bit; a bound flag may differ only where the FP64 energy
+    lies within the FP64 error band of zero; phi agrees to 2e-5 and, where no
+    flag differs, the properties are identical."""
+    from paper_1110_4372_amd import synth
+    note("c4 full size, mixed vs fp64")
+    cat = synth.make_catalog("c4", seed=0)
+    P = H.Particles.from_catalog(cat)
+    out = {}
+    for prec in (H.PREC_FP64, H.PREC_MIXED):
+        ctx = H.Halo(H.params_for_catalog(cat, prec=prec))
+        r = ctx.run_all(P)
+        torch.cuda.synchronize()
+        out[prec] = r
+    a, b = out[H.PREC_FP64], out[H.PREC_MIXED]
+    for k in ("label",):
+        np.testing.assert_array_equal(to_np(a["fof"][k]), to_np(b["fof"][k]))
+    for k in a["halos"]:
+        np.testing.assert_array_equal(to_np(a["halos"][k]), to_np(b["halos"][k]))
+    np.testing.assert_array_equal(to_np(a["halo_of"]), to_np(b["halo_of"]))
+    hof = to_np(a["halo_of"]).astype(np.int64)
+    inside = hof >= 0
+    pa, pb = to_np(a["phi"]), to_np(b["phi"])
+    np.testing.assert_allclose(pb[inside], pa[inside], rtol=2e-5, atol=0)
+    ua = {k: to_np(v) for k, v in a["unbound"].items()}
+    vb = np.stack([ua["vbx"], ua["vby"], ua["vbz"]], 1)
+    v = np.stack([to_np(P.vx), to_np(P.vy), to_np(P.vz)], 1).astype(np.float64)
+    kin = np.zeros(hof.shape[0])
+    kin[inside] = 0.5 * ((v[inside] - vb[hof[inside]]) ** 2).sum(1)
+    e = kin + pa
+    ba, bb = to_np(a["bound"]), to_np(b["bound"])
+    changed = np.nonzero(ba != bb)[0]
+    print(f"assigned {int(inside.sum())}, changed flags {changed.shape[0]}, "
+          f"max phi rel err {np.max(np.abs(pb[inside] - pa[inside]) / np.abs(pa[inside])):.2e}")
+    assert np.all(np.abs(e[changed]) <= 1e-9 * (kin[changed] + np.abs(pa[changed])))
+    if changed.shape[0] == 0:
+        for k in a["props"]:
+            np.testing.assert_array_equal(to_np(a["props"][k]), to_np(b["props"][k]))
