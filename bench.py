@@ -28,10 +28,10 @@ FP32_PEAK_TFLOPS = 157.3
 # copy of known size).  Reported only while the kernel's source file is the
 # one that was measured.
 MEASURED_TRAFFIC = {
-    "k_potential_f64": {"bytes": 455.8e6, "src": "paper_1110_4372_amd/csrc/unbind.hip",
-                        "sha1": "0a5accbc10392df64405921019c1a163a89cadfd"},
-    "k_nn": {"bytes": 87.7e6, "src": "paper_1110_4372_amd/csrc/refine6d.hip",
-             "sha1": "e70eda1a58385e9a24a396f7dd3fa70ad35122e2"},
+    "k_potential_f64": {"bytes": 398.0e6, "src": "paper_1110_4372_amd/csrc/unbind.hip",
+                        "sha1": "7120e0588906f3aa8b8ba66abaf5bd5211a9446e"},
+    "k_nn": {"bytes": 87.9e6, "src": "paper_1110_4372_amd/csrc/refine6d.hip",
+             "sha1": "75e766d3892624fc45855265e4510abc93cce3c2"},
 }
 
 
@@ -87,19 +87,88 @@ def timed(ctx, P, steps, warmup):
 
 
 def pair_work(ctx, P, out):
-    """Algorithmic units of the dominant kernels of one step."""
+    """Algorithmic FLOPs of the dominant kernels of one step.
+
+    Nearest neighbour: each distinct pair of a node once, 17 FLOP (6 sub, 1 mul,
+    5 fma).  Potential: a term 1/sqrt(r^2 + eps^2) is 12 FLOP (3 sub, r^2 as
+    1 mul + 2 fma, + eps^2, rsqrt counted as sqrt + div, accumulate); a pair of
+    two own particles of a halo is one term added to both particles' sums
+    (13 FLOP), a pair of an own particle and a subhalo particle of S(h) one
+    term added to the own particle's sum (12 FLOP)."""
     import numpy as np
     fof, nodes, halos, halo_of, unb = out
     cnt = nodes["count"].cpu().numpy().astype(np.float64)
     flags = nodes["flags"].cpu().numpy()
     active = (flags & 2) == 0
-    # distinct pairs per node: the nearest-neighbour pass evaluates each once
-    nn_pairs = float(np.sum(cnt[active] * (cnt[active] - 1.0) / 2.0))
+    nn_flops = 17.0 * float(np.sum(cnt[active] * (cnt[active] - 1.0) / 2.0))
     h = {k: v.cpu().numpy() for k, v in halos.items()}
     ns = unb["n_s"].cpu().numpy().astype(np.float64)
     kept = h["merged_into"] == np.arange(h["merged_into"].shape[0])
-    pot_pairs = float(np.sum(h["n_assigned"][kept].astype(np.float64) * ns[kept]))
-    return nn_pairs, pot_pairs
+    nown = h["n_assigned"][kept].astype(np.float64)
+    nsk = ns[kept]
+    pot_flops = float(np.sum(13.0 * nown * (nown - 1.0) / 2.0 + 12.0 * nown * (nsk - nown)))
+    return nn_flops, pot_flops
+
+
+# Algorithmic HBM bytes of each pass (what the pass must move, not what it
+# re-reads), from the per-particle figures of the method's data flow:
+#   fof3d   cell keys 24 + ~5 sort passes x 24 + gather 24 + union-find and
+#           labels 32 + label sort 4 x 16 + group gather 64  -> 340 B/particle
+#   refine6d per particle visit of a node: moments 24 + normalised 6D write 24
+#           + pair-pass reads 24 + child compaction 52        -> 124 B/visit
+#   assign  per visit: read 24 + write 4; per assigned particle a radial sort
+#           and scan of 64 B
+#   unbind  per assigned particle: gather pos/vel 24 + halo_of 4, layout write
+#           44, key sort 64, energy pass 24                   -> 160 B
+#   props   per assigned particle: radial sort and scans       -> 64 B
+PASS_BOUND = {"fof3d": "hbm", "refine6d": "alu (6D pair kernels)", "assign": "hbm",
+              "unbind": "alu (potential)", "props": "hbm"}
+
+
+def pass_report(n, out, stage):
+    import numpy as np
+    visits = float(out[1]["count"].double().sum().item())
+    nas = float((out[3] >= 0).sum().item())
+    nbytes = {"fof3d": 340.0 * n, "refine6d": 124.0 * visits,
+              "assign": 28.0 * visits + 64.0 * nas, "unbind": 160.0 * nas, "props": 64.0 * nas}
+    rep = {}
+    for k in STAGES:
+        ms = stage[k]
+        gbs = nbytes[k] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        rep[k] = {"ms": ms, "bytes": nbytes[k], "GB/s": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                  "bound": PASS_BOUND[k]}
+    return rep
+
+
+def precision_report(H, cat, P, grid_min):
+    """The mixed form against the FP64 form, both on the GPU: the count of
+    changed bound flags and halo validity, and the largest relative error of
+    phi and of each property."""
+    import numpy as np
+    res = {}
+    for prec in (H.PREC_FP64, H.PREC_MIXED):
+        ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=grid_min))
+        res[prec] = ctx.run_all(P)
+    a, b = res[H.PREC_FP64], res[H.PREC_MIXED]
+    hof = a["halo_of"].cpu().numpy()
+    ins = hof >= 0
+    pa, pb = a["phi"].cpu().numpy()[ins], b["phi"].cpu().numpy()[ins]
+    rep = {"assigned": int(ins.sum()),
+           "changed_bound": int((a["bound"] != b["bound"]).sum().item()),
+           "changed_valid": int((a["unbound"]["valid"] != b["unbound"]["valid"]).sum().item()),
+           "phi_max_rel_err": float(np.max(np.abs(pb - pa) / np.abs(pa))) if pa.size else 0.0}
+    va = a["unbound"]["valid"].cpu().numpy().astype(bool)
+    vb = b["unbound"]["valid"].cpu().numpy().astype(bool)
+    both = va & vb
+    errs = {}
+    for k in ("px", "py", "pz", "vcx", "vcy", "vcz", "vbx", "vby", "vbz", "mvir", "rvir",
+              "vmax", "voff"):
+        xa = a["props"][k].cpu().numpy()[both]
+        xb = b["props"][k].cpu().numpy()[both]
+        den = np.maximum(np.abs(xa), 1e-300)
+        errs[k] = float(np.max(np.abs(xb - xa) / den)) if xa.size else 0.0
+    rep["props_max_rel_err"] = errs
+    return rep
 
 
 def cpu_baseline(cat, budget_s: float = 20.0):
@@ -145,6 +214,8 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the other precision form and the mixed-vs-FP64 comparison")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration)")
@@ -182,17 +253,14 @@ def main():
                                              "k_potential_f32", "k_link", "k_mom_accum",
                                              "k_select_small")}
     ctx.profile(False)
-    nn_pairs, pot_pairs = pair_work(ctx, P, out)
+    nn_flops, pot_flops = pair_work(ctx, P, out)
     pot_name = "k_potential_f64" if prec == H.PREC_FP64 else "k_potential_f32"
     t_pot, l_pot = kern[pot_name]
     t_nn, l_nn = kern["k_nn"]
-    # per term: potential 12 FLOP (3 sub, r^2 with 1 mul + 2 fma, + eps^2, sqrt,
-    # div, accumulate) over ordered (own, S(h)) pairs; nearest neighbour 17 FLOP
-    # (6 sub, 1 mul, 5 fma) per distinct pair of a node
     cands = {
-        pot_name: (t_pot, l_pot, pot_pairs * 12.0,
+        pot_name: (t_pot, l_pot, pot_flops,
                    FP64_PEAK_TFLOPS if prec == H.PREC_FP64 else FP32_PEAK_TFLOPS),
-        "k_nn": (t_nn, l_nn, nn_pairs * 17.0, FP32_PEAK_TFLOPS),
+        "k_nn": (t_nn, l_nn, nn_flops, FP32_PEAK_TFLOPS),
     }
     dom = max(cands, key=lambda k: cands[k][0])
     t_ms, launches, flops, peak = cands[dom]
@@ -202,12 +270,31 @@ def main():
                 "launches": launches, "avg_launch_ms": t_ms / max(launches, 1),
                 "per_step_ms": {k: v[0] for k, v in kern.items()}}
 
+    # the four forms: batched and plain, FP64 and mixed potential, per pass
+    names = {H.PREC_FP64: "fp64", H.PREC_MIXED: "mixed"}
+    forms = {f"batched_{names[prec]}": {"value": cat.n / sec, "ms_per_step": sec * 1e3,
+                                          "stage_ms": stage}}
+    other = H.PREC_MIXED if prec == H.PREC_FP64 else H.PREC_FP64
+    if not args.no_forms:
+        ctxo = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=other,
+                                           grid_min=args.grid_min))
+        so, _, sto = timed(ctxo, P, args.steps, 1)
+        forms[f"batched_{names[other]}"] = {"value": cat.n / so, "ms_per_step": so * 1e3,
+                                             "stage_ms": sto}
+        del ctxo
     plain = None
     if not args.no_plain:
-        ctxp = H.Halo(H.params_for_catalog(cat, mode=H.PLAIN, prec=prec,
-                                           grid_min=args.grid_min))
-        sp, _, _ = timed(ctxp, P, 1, 1)
-        plain = {"value": cat.n / sp, "ms_per_step": sp * 1e3}
+        for pr in ((prec,) if args.no_forms else (prec, other)):
+            ctxp = H.Halo(H.params_for_catalog(cat, mode=H.PLAIN, prec=pr,
+                                               grid_min=args.grid_min))
+            sp, _, stp = timed(ctxp, P, 1, 1)
+            forms[f"plain_{names[pr]}"] = {"value": cat.n / sp, "ms_per_step": sp * 1e3,
+                                            "stage_ms": stp}
+            if pr == prec:
+                plain = {"value": cat.n / sp, "ms_per_step": sp * 1e3}
+            del ctxp
+    precision = None if args.no_forms else precision_report(H, cat, P, args.grid_min)
+    passes = pass_report(cat.n, out, stage)
 
     if args.copy_probe:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -229,7 +316,10 @@ def main():
                    "n_groups": int(out[0]["n_groups"]), "n_nodes": int(out[1]["parent"].shape[0]),
                    "n_halos": int(out[2]["seed_node"].shape[0])},
         "stage_ms": stage,
+        "passes": passes,
         "plain": plain,
+        "forms": forms,
+        "precision": precision,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

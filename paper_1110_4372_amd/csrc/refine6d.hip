@@ -15,6 +15,7 @@
 //      id builds the next level's array in (parent, smallest index) order.
 #include <algorithm>
 
+#include "lanes.hpp"
 #include "primitives.hpp"
 #include "refine_common.hpp"
 #include "stages.hpp"
@@ -256,29 +257,8 @@ __global__ void k_pair_items(const uint32_t* count, const double* prm, const uin
 }
 
 
-// Lane exchanges for the cross-lane minima (whole wave active).  The minima
-// work on FP32 bit patterns as unsigned integers: every value is a
-// non-negative float or +inf, whose bits order like the values.
-__device__ __forceinline__ uint32_t lane_xor1(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
-}
-__device__ __forceinline__ uint32_t lane_xor2(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);
-}
-__device__ __forceinline__ uint32_t lane_xor4(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x101F);
-}
-__device__ __forceinline__ uint32_t lane_xor8(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false);
-}
-__device__ __forceinline__ uint32_t lane_xor16(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);
-}
-__device__ __forceinline__ uint32_t lane_xor32(uint32_t x) {
-  const int l = (int)(threadIdx.x & 63u);
-  return (uint32_t)__builtin_amdgcn_ds_bpermute((l ^ 32) << 2, (int)x);
-}
-
+// The cross-lane minima work on FP32 bit patterns as unsigned integers: every
+// value is a non-negative float or +inf, whose bits order like the values.
 // Minimum over the wave's 64 lanes of each of d[0..7] (FP32 bits), transposed:
 // lane l returns the minimum of d[u] with u = 4 b0 + 2 b1 + b2 (b0..b2 the low
 // bits of l).  Each halving step keeps the half of the values selected by one

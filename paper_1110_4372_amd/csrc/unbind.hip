@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "lanes.hpp"
 #include "primitives.hpp"
 #include "stages.hpp"
 
@@ -190,41 +191,55 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint
 }
 
 // ------------------------------------------------------------ potentials --
-// Work unit: 64 own particles (one wavefront, lane = particle) of a halo
-// against one j-chunk of its S(h).  The chunk is at least kPotJ particles and
-// grows with |S(h)| so a halo has at most 64 chunks.  Each unit adds its
-// partial sum per particle into a 128-bit fixed-point accumulator (64
-// fractional bits) with integer atomics: integer addition is associative, so
-// the result does not depend on which wave ran which unit or in what order.
-constexpr uint32_t kPotJ = 2048;
+// Work unit: kPotI own particles of a halo (a block of four wavefronts; each
+// lane holds kPotK particles i = t0 + lane + 64 k of its wave's tile of
+// kPotTile) against one j-chunk of kPotJ particles of its S(h).  S(h) starts
+// with the halo's own particles, followed by its subhaloes' S.  A pair of two
+// own particles is evaluated once: the wave owning the lower tile adds the
+// term to its particle's sum and, summed over the wave's kPotTile particles,
+// to the other particle's sum, which collects in LDS for the unit.  The wave's
+// own tile and the subhalo particles are evaluated from the i side only.
+//
+// Every partial sum goes into a 128-bit fixed-point accumulator (value x 2^32,
+// integer atomics): integer addition is associative, so the result does not
+// depend on which block ran which unit, or when.
+constexpr uint32_t kPotK = 4;
+constexpr uint32_t kPotTile = 64 * kPotK;  // particles per wave
+constexpr uint32_t kPotI = 4 * kPotTile;   // particles per unit
+constexpr uint32_t kPotJ = 2048;           // a multiple of kPotTile
+constexpr int kPotFrac = 32;               // fractional bits of the accumulators
+constexpr double kFar = 1e150;             // coordinate of a lane slot without a particle
 
-// v >= 0 (a sum of positive terms, far below 2^63) in units of 2^-64.
+// round(v 2^32) for v >= 0 (below 2^63) as a 128-bit integer; every step is
+// exact: s is an integer, and its 2^64 and 2^32 words are split off by floor
+// and fma.
 __device__ __forceinline__ I128 pot_fixed(double v) {
-  const double ip = floor(v);
+  const double s = rint(ldexp(v, kPotFrac));
+  const double h = floor(s * 0x1p-64);
+  const double m = __fma_rn(-h, 0x1p64, s);
+  const double mh = floor(m * 0x1p-32);
+  const double ml = __fma_rn(-mh, 0x1p32, m);
   I128 r;
-  r.hi = (long long)ip;
-  r.lo = (unsigned long long)((v - ip) * 18446744073709551616.0);
+  r.lo = ((unsigned long long)(uint32_t)mh << 32) | (uint32_t)ml;
+  r.hi = (long long)(int32_t)h;
   return r;
 }
 
-__host__ __device__ __forceinline__ uint32_t pot_chunk(uint32_t ns) {
-  uint32_t c = (ns + 63u) / 64u;
-  c = (c + 63u) & ~63u;
-  return c > kPotJ ? c : kPotJ;
+__host__ __device__ __forceinline__ uint32_t pot_units(uint32_t nown, uint32_t ns) {
+  return ((nown + kPotI - 1u) / kPotI) * ((ns + kPotJ - 1u) / kPotJ);
 }
 
-// Per kept halo: the unit count; the sort key orders units by cost,
-// largest first (a unit costs ~ 64 * min(|S(h)|, chunk) terms).
+// Per kept halo: the unit count, and a sort key ordering halos by their cost
+// (~ nown |S(h)|), largest first.
 __global__ void k_pot_counts(const libhalo_halos h, uint32_t S, const uint32_t* nS,
                              uint32_t* ucnt, uint32_t* key, uint32_t* val) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;
   const uint32_t nown = h.n_assigned[s], ns = nS[s];
   const bool on = h.merged_into[s] == (int32_t)s && nown > 0;
-  const uint32_t J = pot_chunk(ns);
-  const uint32_t nc = (ns + J - 1) / J;
-  ucnt[s] = on ? ((nown + 63u) / 64u) * nc : 0u;
-  key[s] = on ? ~min(ns, J) : 0xFFFFFFFFu;
+  const unsigned long long cost = ((unsigned long long)nown * ns) >> 16;
+  ucnt[s] = on ? pot_units(nown, ns) : 0u;
+  key[s] = on ? ~(uint32_t)min(cost, 0xFFFFFFFEull) : 0xFFFFFFFFu;
   val[s] = s;
 }
 
@@ -235,71 +250,201 @@ __global__ void k_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t 
 }
 
 struct PotUnit {
-  uint32_t hh, base, nown, ns, i, j0, j1, s0, s1, c;
+  uint32_t base, nown, ns, b, j0, j1;
 };
 
 // Decodes unit u: the units of halo order[k] are [uoff[k], uoff[k+1]),
-// chunk-major so that concurrent waves share a j-chunk.
+// chunk-major so that concurrent blocks share a j-chunk.
 __device__ __forceinline__ PotUnit pot_unit(const libhalo_halos& h, const uint32_t* order,
                                             const uint32_t* uoff, uint32_t K,
                                             const uint32_t* slot, const uint32_t* nS,
                                             uint32_t u) {
   PotUnit r;
   const uint32_t k = seg_of(uoff, K, u);
-  r.hh = order[k];
+  const uint32_t hh = order[k];
   const uint32_t local = u - uoff[k];
-  r.nown = h.n_assigned[r.hh];
-  r.ns = nS[r.hh];
-  r.base = slot[r.hh];
-  const uint32_t J = pot_chunk(r.ns);
-  const uint32_t ni = (r.nown + 63u) / 64u;
-  r.c = local / ni;
-  const uint32_t it = local - r.c * ni;
-  r.i = it * 64u + (threadIdx.x & 63u);
-  r.j0 = r.c * J;
-  r.j1 = min(r.j0 + J, r.ns);
-  // the wave's own particles [s0, s1) lie wholly inside the chunk or wholly
-  // outside it, since the chunk length is a multiple of 64
-  r.s0 = it * 64u;
-  r.s1 = min(r.s0 + 64u, r.ns);
-  if (r.s0 < r.j0 || r.s0 >= r.j1) r.s0 = r.s1 = r.j1;
+  r.nown = h.n_assigned[hh];
+  r.ns = nS[hh];
+  r.base = slot[hh];
+  const uint32_t nb = (r.nown + kPotI - 1u) / kPotI;
+  const uint32_t c = local / nb;
+  r.b = local - c * nb;
+  r.j0 = c * kPotJ;
+  r.j1 = min(r.j0 + kPotJ, r.ns);
   return r;
 }
 
-// Next unit of this wavefront: from the shared counter (dynamic) or by
-// striding over the grid (static).  Called with the whole wave active, so
-// readfirstlane reads lane 0 and marks the result wave-uniform for the
-// compiler (which then keeps the unit's bounds and j loads scalar).
-__device__ __forceinline__ uint32_t pot_next(uint32_t* ctr, uint32_t u0, uint32_t t) {
+// Next unit of this block: from the shared counter (dynamic) or by striding
+// over the grid (static).  readfirstlane marks the result wave-uniform for the
+// compiler, which then keeps the unit's bounds and the j loads scalar.
+__device__ __forceinline__ uint32_t pot_next(uint32_t* ctr, uint32_t u0, uint32_t t,
+                                             uint32_t* su) {
+  __syncthreads();  // the previous unit's LDS sums are flushed
   uint32_t v;
   if (ctr) {
-    v = 0;
-    if ((threadIdx.x & 63u) == 0) v = atomicAdd(ctr, 1u);
+    if (threadIdx.x == 0) *su = atomicAdd(ctr, 1u);
+    __syncthreads();
+    v = *su;
   } else {
-    const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
-    v = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) + t * nw;
+    v = blockIdx.x + t * gridDim.x;
   }
   return u0 + __builtin_amdgcn_readfirstlane(v);
 }
 
-// FP64 terms 1/sqrt(r^2 + eps^2) for j in [j0, j1) of the layout.  The j
-// coordinates are wave-uniform and come in through scalar loads as operands of
-// the vector ops.  y0 = hardware rsqrt estimate (about 2^-24 relative); one
-// Newton step gives y0 + y0 e / 2 with e = 1 - r y0^2, so the terms are kept
-// as A = sum y0 and C = sum y0 e and combined as A + C / 2.
-// kSelf: skip j == self (only the span holding the wave's own particles).
+// jacc[q] += v (fixed point, LDS; lo and hi words in separate arrays).
+__device__ __forceinline__ void lds_add_fixed(unsigned long long* jlo, unsigned long long* jhi,
+                                              uint32_t q, double v) {
+  const I128 f = pot_fixed(v);
+  const unsigned long long old = atomicAdd(jlo + q, f.lo);
+  const long long add_hi = f.hi + ((old + f.lo) < old ? 1ll : 0ll);
+  if (add_hi != 0) atomicAdd(jhi + q, (unsigned long long)add_hi);
+}
+
+// Sum over the wave's 64 lanes of each of d[0..7], transposed: lane l returns
+// the sum of d[u] with u = 4 b0 + 2 b1 + b2 (b0..b2 the low bits of l).  Each
+// halving step keeps the half of the values selected by one lane bit and adds
+// the partner's copy of the same half; the tree is fixed, so the result is
+// deterministic.
+template <class F, F (*X1)(F), F (*X2)(F), F (*X4)(F), F (*X8)(F), F (*X16)(F), F (*X32)(F)>
+__device__ __forceinline__ F wave_sum8(const F* d) {
+  const uint32_t l = threadIdx.x & 63u;
+  const bool b0 = l & 1u, b1 = l & 2u, b2 = l & 4u;
+  F r1[4], r2[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const F keep = b0 ? d[4 + k] : d[k];
+    const F send = b0 ? d[k] : d[4 + k];
+    r1[k] = keep + X1(send);
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const F keep = b1 ? r1[2 + k] : r1[k];
+    const F send = b1 ? r1[k] : r1[2 + k];
+    r2[k] = keep + X2(send);
+  }
+  const F keep = b2 ? r2[1] : r2[0];
+  const F send = b2 ? r2[0] : r2[1];
+  F r = keep + X4(send);
+  r = r + X8(r);
+  r = r + X16(r);
+  r = r + X32(r);
+  return r;
+}
+
+template <class F, F (*X1)(F), F (*X2)(F), F (*X4)(F), F (*X8)(F), F (*X16)(F), F (*X32)(F)>
+__device__ __forceinline__ F wave_sum1(F r) {
+  r = r + X1(r);
+  r = r + X2(r);
+  r = r + X4(r);
+  r = r + X8(r);
+  r = r + X16(r);
+  r = r + X32(r);
+  return r;
+}
+
+#define HALO_XORS(F, f)                                                                   \
+  F, lane_xor_##f<lane_xor1>, lane_xor_##f<lane_xor2>, lane_xor_##f<lane_xor4>,         \
+      lane_xor_##f<lane_xor8>, lane_xor_##f<lane_xor16>, lane_xor_##f<lane_xor32>
+
+__device__ __forceinline__ uint32_t lane_perm8() {
+  const uint32_t l = threadIdx.x & 63u;
+  return ((l & 1u) << 2) | (l & 2u) | ((l >> 2) & 1u);
+}
+
+// The unit's LDS j sums into the particles' accumulators.
+__device__ __forceinline__ void pot_flush(const unsigned long long* jlo,
+                                          const unsigned long long* jhi, uint32_t n,
+                                          I128* __restrict__ acc) {
+  for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) {
+    const I128 v{jlo[q], (long long)jhi[q]};
+    if (v.lo != 0 || v.hi != 0) atomic_add_i128(acc + q, v);
+  }
+}
+
+__device__ __forceinline__ void pot_clear(unsigned long long* jlo, unsigned long long* jhi,
+                                          uint32_t n) {
+  for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) {
+    jlo[q] = 0ull;
+    jhi[q] = 0ull;
+  }
+}
+
+// FP64 term 1/sqrt(r^2 + eps^2) of particle (x, y, z) and j.  y0 = hardware
+// rsqrt estimate (about 2^-24 relative); one Newton step gives y0 + y0 e / 2
+// with e = 1 - r y0^2.
+__device__ __forceinline__ void pot_term_f64(double bx, double by, double bz, double x,
+                                             double y, double z, double eps2, double& y0,
+                                             double& e) {
+  const double dx = bx - x, dy = by - y, dz = bz - z;
+  const double r = __fma_rn(dz, dz, __fma_rn(dy, dy, __fma_rn(dx, dx, eps2)));
+  y0 = __builtin_amdgcn_rsq(r);
+  e = __fma_rn(-(r * y0), y0, 1.0);
+}
+
+// FP64 terms for j in [j0, j1) of the layout, i side only, kept as
+// A = sum y0 and C = sum y0 e (combined as A + C / 2).  The j coordinates are
+// wave-uniform and come in through scalar loads as operands of the vector ops.
+// kSelf: skip j == the slot's own particle (the span holding the wave's tile).
 template <bool kSelf>
 __device__ __forceinline__ void pot_span_f64(const double* __restrict__ ux,
                                              const double* __restrict__ uy,
                                              const double* __restrict__ uz, uint32_t j0,
-                                             uint32_t j1, uint32_t self, double xi, double yi,
-                                             double zi, double eps2, double* A, double* C) {
+                                             uint32_t j1, const uint32_t* self, const double* x,
+                                             const double* y, const double* z, double eps2,
+                                             double* A, double* C) {
   uint32_t j = j0;
-  for (; j + 8 <= j1; j += 8) {
+  for (; j + 4 <= j1; j += 4) {
+    double bx[4], by[4], bz[4];
     const double* __restrict__ px = ux + j;
     const double* __restrict__ py = uy + j;
     const double* __restrict__ pz = uz + j;
-    double bx[8], by[8], bz[8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      bx[u] = px[u];
+      by[u] = py[u];
+      bz[u] = pz[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (uint32_t k = 0; k < kPotK; ++k) {
+        double y0, e;
+        pot_term_f64(bx[u], by[u], bz[u], x[k], y[k], z[k], eps2, y0, e);
+        if (kSelf) y0 = (j + u != self[k]) ? y0 : 0.0;
+        A[k] += y0;
+        C[k] = __fma_rn(y0, e, C[k]);
+      }
+  }
+  for (; j < j1; ++j)
+#pragma unroll
+    for (uint32_t k = 0; k < kPotK; ++k) {
+      double y0, e;
+      pot_term_f64(ux[j], uy[j], uz[j], x[k], y[k], z[k], eps2, y0, e);
+      if (kSelf) y0 = (j != self[k]) ? y0 : 0.0;
+      A[k] += y0;
+      C[k] = __fma_rn(y0, e, C[k]);
+    }
+}
+
+// FP64 terms of the pairs (slot, j) for own j in [j0, j1), all above the
+// wave's tile, each evaluated once: the Newton-corrected term goes to the
+// slot's A and, summed over the wave's slots, to jacc[j - jc].  Slots without
+// a particle sit at kFar, where the term is ~1e-150: below half an ulp of any
+// real term (>= 1 / the group's extent), so it changes no sum.
+__device__ __forceinline__ void pot_sym_f64(const double* __restrict__ ux,
+                                            const double* __restrict__ uy,
+                                            const double* __restrict__ uz, uint32_t j0,
+                                            uint32_t j1, uint32_t jc, const double* x,
+                                            const double* y, const double* z, double eps2,
+                                            double* A, unsigned long long* jlo,
+                                            unsigned long long* jhi) {
+  const uint32_t l = threadIdx.x & 63u, ul = lane_perm8();
+  uint32_t j = j0;
+  for (; j + 8 <= j1; j += 8) {
+    double bx[8], by[8], bz[8], tj[8];
+    const double* __restrict__ px = ux + j;
+    const double* __restrict__ py = uy + j;
+    const double* __restrict__ pz = uz + j;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       bx[u] = px[u];
@@ -308,27 +453,34 @@ __device__ __forceinline__ void pot_span_f64(const double* __restrict__ ux,
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const double dx = bx[u] - xi, dy = by[u] - yi, dz = bz[u] - zi;
-      const double r = __fma_rn(dz, dz, __fma_rn(dy, dy, __fma_rn(dx, dx, eps2)));
-      double y = __builtin_amdgcn_rsq(r);
-      const double e = __fma_rn(-(r * y), y, 1.0);
-      if (kSelf) y = (j + u != self) ? y : 0.0;
-      A[u & 3] += y;
-      C[u & 3] = __fma_rn(y, e, C[u & 3]);
+#pragma unroll
+      for (uint32_t k = 0; k < kPotK; ++k) {
+        double y0, e;
+        pot_term_f64(bx[u], by[u], bz[u], x[k], y[k], z[k], eps2, y0, e);
+        const double t = __fma_rn(0.5 * y0, e, y0);
+        A[k] += t;
+        tj[u] = k == 0 ? t : tj[u] + t;
+      }
     }
+    const double s = wave_sum8<HALO_XORS(double, f64)>(tj);
+    if (l < 8u) lds_add_fixed(jlo, jhi, j - jc + ul, s);
   }
   for (; j < j1; ++j) {
-    const double dx = ux[j] - xi, dy = uy[j] - yi, dz = uz[j] - zi;
-    const double r = __fma_rn(dz, dz, __fma_rn(dy, dy, __fma_rn(dx, dx, eps2)));
-    double y = __builtin_amdgcn_rsq(r);
-    const double e = __fma_rn(-(r * y), y, 1.0);
-    if (kSelf) y = (j != self) ? y : 0.0;
-    A[0] += y;
-    C[0] = __fma_rn(y, e, C[0]);
+    double tj = 0.0;
+#pragma unroll
+    for (uint32_t k = 0; k < kPotK; ++k) {
+      double y0, e;
+      pot_term_f64(ux[j], uy[j], uz[j], x[k], y[k], z[k], eps2, y0, e);
+      const double t = __fma_rn(0.5 * y0, e, y0);
+      A[k] += t;
+      tj = k == 0 ? t : tj + t;
+    }
+    const double s = wave_sum1<HALO_XORS(double, f64)>(tj);
+    if (l == 0u) lds_add_fixed(jlo, jhi, j - jc, s);
   }
 }
 
-// FP64 form: one partial sum over a j-chunk per own particle and unit.
+// FP64 form.
 __global__ void __launch_bounds__(TB)
     k_potential_f64(const double* __restrict__ ux, const double* __restrict__ uy,
                     const double* __restrict__ uz, const libhalo_halos h,
@@ -336,41 +488,93 @@ __global__ void __launch_bounds__(TB)
                     uint32_t K, const uint32_t* __restrict__ slot,
                     const uint32_t* __restrict__ nS, uint32_t u0, uint32_t u1, uint32_t* ctr,
                     double eps2, I128* __restrict__ acc) {
+  __shared__ unsigned long long jlo[kPotJ], jhi[kPotJ];
+  __shared__ uint32_t su;
   for (uint32_t t = 0;; ++t) {
-    const uint32_t u = pot_next(ctr, u0, t);
+    const uint32_t u = pot_next(ctr, u0, t, &su);
     if (u >= u1) break;
     const PotUnit w = pot_unit(h, order, uoff, K, slot, nS, u);
-    const bool ok = w.i < w.nown;
-    const uint32_t qi = w.base + (ok ? w.i : 0u);
-    const double xi = ux[qi], yi = uy[qi], zi = uz[qi];
-    double A[4] = {0.0, 0.0, 0.0, 0.0}, C[4] = {0.0, 0.0, 0.0, 0.0};
-    const uint32_t b = w.base;
-    pot_span_f64<false>(ux, uy, uz, b + w.j0, b + w.s0, 0u, xi, yi, zi, eps2, A, C);
-    pot_span_f64<true>(ux, uy, uz, b + w.s0, b + w.s1, b + w.i, xi, yi, zi, eps2, A, C);
-    pot_span_f64<false>(ux, uy, uz, b + w.s1, b + w.j1, 0u, xi, yi, zi, eps2, A, C);
-    const double a = (A[0] + A[1]) + (A[2] + A[3]);
-    const double c = (C[0] + C[1]) + (C[2] + C[3]);
-    if (ok) atomic_add_i128(acc + qi, pot_fixed(__fma_rn(0.5, c, a)));
+    const uint32_t ib = w.b * kPotI;
+    const uint32_t je = min(w.j1, w.nown);  // end of the chunk's own part
+    if (w.j1 <= ib && w.j1 <= w.nown) continue;  // pairs taken from the other side
+    const uint32_t nj = je > w.j0 ? je - w.j0 : 0u;
+    pot_clear(jlo, jhi, nj);
+    __syncthreads();
+    const uint32_t t0 =
+        __builtin_amdgcn_readfirstlane(ib + (threadIdx.x >> 6) * kPotTile);
+    if (t0 < w.nown) {
+      const uint32_t b = w.base;
+      uint32_t qi[kPotK];
+      double x[kPotK], y[kPotK], z[kPotK], A[kPotK], C[kPotK];
+#pragma unroll
+      for (uint32_t k = 0; k < kPotK; ++k) {
+        const uint32_t li = t0 + (threadIdx.x & 63u) + 64u * k;
+        const bool ok = li < w.nown;
+        const uint32_t q = b + (ok ? li : 0u);  // an in-range load either way
+        qi[k] = ok ? q : 0xFFFFFFFFu;
+        x[k] = ok ? ux[q] : kFar;
+        y[k] = ok ? uy[q] : kFar;
+        z[k] = ok ? uz[q] : kFar;
+        A[k] = 0.0;
+        C[k] = 0.0;
+      }
+      if (t0 >= w.j0 && t0 < w.j1)
+        pot_span_f64<true>(ux, uy, uz, b + t0, b + min(t0 + kPotTile, w.nown), qi, x, y, z,
+                           eps2, A, C);
+      const uint32_t js = max(w.j0, t0 + kPotTile);
+      if (js < je)
+        pot_sym_f64(ux, uy, uz, b + js, b + je, b + w.j0, x, y, z, eps2, A, jlo, jhi);
+      const uint32_t ss = max(w.j0, w.nown);
+      if (ss < w.j1)
+        pot_span_f64<false>(ux, uy, uz, b + ss, b + w.j1, qi, x, y, z, eps2, A, C);
+#pragma unroll
+      for (uint32_t k = 0; k < kPotK; ++k) {
+        const double v = __fma_rn(0.5, C[k], A[k]);
+        if (qi[k] != 0xFFFFFFFFu && v > 0.0) atomic_add_i128(acc + qi[k], pot_fixed(v));
+      }
+    }
+    __syncthreads();
+    pot_flush(jlo, jhi, nj, acc + w.base + w.j0);
   }
 }
 
-// FP32 terms for j in [j0, j1): relative FP32 coordinates, hardware FP32
-// rsqrt, four partial sums folded every 64 terms into a compensated sum.
+// FP32 form: coordinates relative to the tree's origin, hardware FP32 rsqrt;
+// the i-side terms of each slot go into a partial sum folded every 64 j into
+// a compensated sum.
+struct Comp32 {
+  float acc = 0.0f, comp = 0.0f;
+  __device__ __forceinline__ void add(float s) {
+    const float yk = s - comp;
+    const float tk = acc + yk;
+    comp = (tk - acc) - yk;
+    acc = tk;
+  }
+};
+
+__device__ __forceinline__ float pot_term_f32(float bx, float by, float bz, float x, float y,
+                                              float z, float eps2) {
+  const float dx = bx - x, dy = by - y, dz = bz - z;
+  return __builtin_amdgcn_rsqf(__fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2))));
+}
+
 template <bool kSelf>
 __device__ __forceinline__ void pot_span_f32(const float* __restrict__ fx,
                                              const float* __restrict__ fy,
                                              const float* __restrict__ fz, uint32_t j0,
-                                             uint32_t j1, uint32_t self, float xi, float yi,
-                                             float zi, float eps2, float& acc, float& comp) {
+                                             uint32_t j1, const uint32_t* self, const float* x,
+                                             const float* y, const float* z, float eps2,
+                                             Comp32* A) {
   uint32_t j = j0;
   while (j < j1) {
     const uint32_t je = min(j + 64u, j1);
-    float p[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float p[kPotK];
+#pragma unroll
+    for (uint32_t k = 0; k < kPotK; ++k) p[k] = 0.0f;
     for (; j + 8 <= je; j += 8) {
+      float bx[8], by[8], bz[8];
       const float* __restrict__ px = fx + j;
       const float* __restrict__ py = fy + j;
       const float* __restrict__ pz = fz + j;
-      float bx[8], by[8], bz[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         bx[u] = px[u];
@@ -378,26 +582,80 @@ __device__ __forceinline__ void pot_span_f32(const float* __restrict__ fx,
         bz[u] = pz[u];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const float dx = bx[u] - xi, dy = by[u] - yi, dz = bz[u] - zi;
-        const float r = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2)));
-        float y = __builtin_amdgcn_rsqf(r);
-        if (kSelf) y = (j + u != self) ? y : 0.0f;
-        p[u & 3] += y;
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (uint32_t k = 0; k < kPotK; ++k) {
+          float t = pot_term_f32(bx[u], by[u], bz[u], x[k], y[k], z[k], eps2);
+          if (kSelf) t = (j + u != self[k]) ? t : 0.0f;
+          p[k] += t;
+        }
+    }
+    for (; j < je; ++j)
+#pragma unroll
+      for (uint32_t k = 0; k < kPotK; ++k) {
+        float t = pot_term_f32(fx[j], fy[j], fz[j], x[k], y[k], z[k], eps2);
+        if (kSelf) t = (j != self[k]) ? t : 0.0f;
+        p[k] += t;
       }
+#pragma unroll
+    for (uint32_t k = 0; k < kPotK; ++k) A[k].add(p[k]);
+  }
+}
+
+// FP32 terms of the pairs (slot, j) for own j in [j0, j1) above the wave's
+// tile, each evaluated once: i side as in pot_span_f32, j side summed over the
+// wave's slots in FP32 (a fixed tree) and added to jacc[j - jc] in fixed
+// point.  Slots without a particle sit at 1e18, where the term (~6e-19) is
+// below half an ulp of any real term.
+__device__ __forceinline__ void pot_sym_f32(const float* __restrict__ fx,
+                                            const float* __restrict__ fy,
+                                            const float* __restrict__ fz, uint32_t j0,
+                                            uint32_t j1, uint32_t jc, const float* x,
+                                            const float* y, const float* z, float eps2,
+                                            Comp32* A, unsigned long long* jlo,
+                                            unsigned long long* jhi) {
+  const uint32_t l = threadIdx.x & 63u, ul = lane_perm8();
+  uint32_t j = j0;
+  while (j < j1) {
+    const uint32_t je = min(j + 64u, j1);
+    float p[kPotK];
+#pragma unroll
+    for (uint32_t k = 0; k < kPotK; ++k) p[k] = 0.0f;
+    for (; j + 8 <= je; j += 8) {
+      float bx[8], by[8], bz[8], tj[8];
+      const float* __restrict__ px = fx + j;
+      const float* __restrict__ py = fy + j;
+      const float* __restrict__ pz = fz + j;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        bx[u] = px[u];
+        by[u] = py[u];
+        bz[u] = pz[u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (uint32_t k = 0; k < kPotK; ++k) {
+          const float t = pot_term_f32(bx[u], by[u], bz[u], x[k], y[k], z[k], eps2);
+          p[k] += t;
+          tj[u] = k == 0 ? t : tj[u] + t;
+        }
+      const float s = wave_sum8<HALO_XORS(float, f32)>(tj);
+      if (l < 8u) lds_add_fixed(jlo, jhi, j - jc + ul, (double)s);
     }
     for (; j < je; ++j) {
-      const float dx = fx[j] - xi, dy = fy[j] - yi, dz = fz[j] - zi;
-      const float r = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2)));
-      float y = __builtin_amdgcn_rsqf(r);
-      if (kSelf) y = (j != self) ? y : 0.0f;
-      p[0] += y;
+      float tj = 0.0f;
+#pragma unroll
+      for (uint32_t k = 0; k < kPotK; ++k) {
+        const float t = pot_term_f32(fx[j], fy[j], fz[j], x[k], y[k], z[k], eps2);
+        p[k] += t;
+        tj = k == 0 ? t : tj + t;
+      }
+      const float s = wave_sum1<HALO_XORS(float, f32)>(tj);
+      if (l == 0u) lds_add_fixed(jlo, jhi, j - jc, (double)s);
     }
-    const float s = (p[0] + p[1]) + (p[2] + p[3]);
-    const float yk = s - comp;
-    const float tk = acc + yk;
-    comp = (tk - acc) - yk;
-    acc = tk;
+#pragma unroll
+    for (uint32_t k = 0; k < kPotK; ++k) A[k].add(p[k]);
   }
 }
 
@@ -416,26 +674,57 @@ __global__ void k_rel_f32(const double* ux, const double* uy, const double* uz,
   fz[q] = (float)(uz[q] - uz[o]);
 }
 
-__global__ void __launch_bounds__(TB)
+__global__ void __launch_bounds__(TB, 4)
     k_potential_f32(const float* __restrict__ fx, const float* __restrict__ fy,
                     const float* __restrict__ fz, const libhalo_halos h,
                     const uint32_t* __restrict__ order, const uint32_t* __restrict__ uoff,
                     uint32_t K, const uint32_t* __restrict__ slot,
                     const uint32_t* __restrict__ nS, uint32_t u0, uint32_t u1, uint32_t* ctr,
-                    float eps2, I128* __restrict__ out) {
+                    float eps2, I128* __restrict__ acc) {
+  __shared__ unsigned long long jlo[kPotJ], jhi[kPotJ];
+  __shared__ uint32_t su;
   for (uint32_t t = 0;; ++t) {
-    const uint32_t u = pot_next(ctr, u0, t);
+    const uint32_t u = pot_next(ctr, u0, t, &su);
     if (u >= u1) break;
     const PotUnit w = pot_unit(h, order, uoff, K, slot, nS, u);
-    const bool ok = w.i < w.nown;
-    const uint32_t qi = w.base + (ok ? w.i : 0u);
-    const float xi = fx[qi], yi = fy[qi], zi = fz[qi];
-    float acc = 0.0f, comp = 0.0f;
-    const uint32_t b = w.base;
-    pot_span_f32<false>(fx, fy, fz, b + w.j0, b + w.s0, 0u, xi, yi, zi, eps2, acc, comp);
-    pot_span_f32<true>(fx, fy, fz, b + w.s0, b + w.s1, b + w.i, xi, yi, zi, eps2, acc, comp);
-    pot_span_f32<false>(fx, fy, fz, b + w.s1, b + w.j1, 0u, xi, yi, zi, eps2, acc, comp);
-    if (ok) atomic_add_i128(out + qi, pot_fixed((double)acc - (double)comp));
+    const uint32_t ib = w.b * kPotI;
+    const uint32_t je = min(w.j1, w.nown);
+    if (w.j1 <= ib && w.j1 <= w.nown) continue;
+    const uint32_t nj = je > w.j0 ? je - w.j0 : 0u;
+    pot_clear(jlo, jhi, nj);
+    __syncthreads();
+    const uint32_t t0 =
+        __builtin_amdgcn_readfirstlane(ib + (threadIdx.x >> 6) * kPotTile);
+    if (t0 < w.nown) {
+      const uint32_t b = w.base;
+      uint32_t qi[kPotK];
+      float x[kPotK], y[kPotK], z[kPotK];
+      Comp32 A[kPotK];
+#pragma unroll
+      for (uint32_t k = 0; k < kPotK; ++k) {
+        const uint32_t li = t0 + (threadIdx.x & 63u) + 64u * k;
+        const bool ok = li < w.nown;
+        const uint32_t q = b + (ok ? li : 0u);
+        qi[k] = ok ? q : 0xFFFFFFFFu;
+        x[k] = ok ? fx[q] : 1e18f;
+        y[k] = ok ? fy[q] : 1e18f;
+        z[k] = ok ? fz[q] : 1e18f;
+      }
+      if (t0 >= w.j0 && t0 < w.j1)
+        pot_span_f32<true>(fx, fy, fz, b + t0, b + min(t0 + kPotTile, w.nown), qi, x, y, z,
+                           eps2, A);
+      const uint32_t js = max(w.j0, t0 + kPotTile);
+      if (js < je) pot_sym_f32(fx, fy, fz, b + js, b + je, b + w.j0, x, y, z, eps2, A, jlo, jhi);
+      const uint32_t ss = max(w.j0, w.nown);
+      if (ss < w.j1) pot_span_f32<false>(fx, fy, fz, b + ss, b + w.j1, qi, x, y, z, eps2, A);
+#pragma unroll
+      for (uint32_t k = 0; k < kPotK; ++k) {
+        const double v = (double)A[k].acc - (double)A[k].comp;
+        if (qi[k] != 0xFFFFFFFFu && v > 0.0) atomic_add_i128(acc + qi[k], pot_fixed(v));
+      }
+    }
+    __syncthreads();
+    pot_flush(jlo, jhi, nj, acc + w.base + w.j0);
   }
 }
 
@@ -447,7 +736,7 @@ __global__ void k_zero_i128(I128* a, uint32_t m) {
 // sum[q] = the particle's fixed-point potential sum as FP64.
 __global__ void k_pot_finish(const I128* acc, uint32_t m, double* sum) {
   uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < m) sum[q] = ldexp(i128_to_f64(acc[q]), -64);
+  if (q < m) sum[q] = ldexp(i128_to_f64(acc[q]), -kPotFrac);
 }
 
 // FP64 recheck of one particle's potential (mixed form), one block per particle.
@@ -721,7 +1010,7 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       for (uint32_t k = 0; k < S; ++k) pos[ord[k]] = k;
       for (uint32_t hh = 0; hh < S; ++hh) {
         const uint32_t k = pos[hh], nu = ho[k + 1] - ho[k];
-        if (nu) launch(ho[k], ho[k + 1], nullptr, blocks_for(nu, TB / 64));
+        if (nu) launch(ho[k], ho[k + 1], nullptr, nu);
       }
     } else if (U > 0) {
       k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 4, 1, 0u);
