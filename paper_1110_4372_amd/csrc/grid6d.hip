@@ -185,6 +185,20 @@ __device__ __forceinline__ float box_gap2(const float* a, const float* b) {
   return s;
 }
 
+// Squared gap between a point and a tile's box, in the component order and
+// FP32 operations of d2_6: each step is monotone and the per-axis gap is at
+// most |b_c - a_c| for every b in the box, so the result never exceeds d2_6
+// of the point and any particle of the tile.  The box is wave-uniform.
+__device__ __forceinline__ float point_gap2(const float* a, const float* __restrict__ box) {
+  float s = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const float gap = fmaxf(0.0f, fmaxf(box[c] - a[c], a[c] - box[6 + c]));
+    s = c == 0 ? gap * gap : __fmaf_rn(gap, gap, s);
+  }
+  return s;
+}
+
 // Block-sparse pass of one target tile per wavefront.  mode 0: nearest
 // neighbour within the node; mode 1: 6D FOF unions at ell^2.
 template <int MODE>
@@ -225,17 +239,33 @@ __global__ void __launch_bounds__(kTile)
     __builtin_amdgcn_wave_barrier();
     __syncthreads();
     float best = __int_as_float(0x7F800000);
-    // FOF considers each unordered pair once: j tiles from the target on
+    const float av[6] = {a0, a1, a2, a3, a4, a5};
+    if (MODE == 0) {
+      // the own tile first: a close first minimum for the per-lane pruning
+      const uint32_t q0 = p0, q1 = p1;
+      best = nn_span<true>(X, MB, q0, q1, qi, av, best);
+    }
+    // j tiles by chunks of 64, starting at the chunk holding the target (near
+    // it on the Morton curve); FOF considers each unordered pair once, so its
+    // j tiles start at the target
     const uint32_t jt0 = MODE == 1 ? it : tb0;
-    for (uint32_t jc = jt0; jc < tb1; jc += kTile) {
+    const uint32_t nch = (tb1 - jt0 + kTile - 1) / kTile;
+    const uint32_t c0 = MODE == 1 ? 0u : (it - tb0) / kTile;
+    for (uint32_t cc = 0; cc < nch; ++cc) {
+      const uint32_t ch = c0 + cc < nch ? c0 + cc : c0 + cc - nch;
+      const uint32_t jc = jt0 + ch * kTile;
       const uint32_t jt = jc + lane;
       bool cand = false;
-      if (jt < tb1) cand = box_gap2(ibox, g.tbox + 12 * (size_t)jt) <= radius2;
+      if (jt < tb1 && (MODE == 1 || jt != it))
+        cand = box_gap2(ibox, g.tbox + 12 * (size_t)jt) <= radius2;
       unsigned long long mask = __ballot(cand);
       while (mask) {
         const int bit = __ffsll((long long)mask) - 1;
         mask &= mask - 1;
-        const uint32_t jtile = jc + bit;
+        const uint32_t jtile = __builtin_amdgcn_readfirstlane(jc + bit);
+        // skip the tile unless some lane could gain from it
+        const float gp = point_gap2(av, g.tbox + 12 * (size_t)jtile);
+        if (MODE == 0 ? !__any(ok && gp < best) : !__any(active && gp <= l2)) continue;
         const uint32_t q0 = ps + (jtile - tb0) * kTile;
         const uint32_t q1 = min(pe, q0 + kTile);
         if (MODE == 1) {  // the FOF pass stages the tile and its roots
@@ -250,11 +280,7 @@ __global__ void __launch_bounds__(kTile)
         }
         const uint32_t nj = q1 - q0;
         if (MODE == 0) {
-          const float av[6] = {a0, a1, a2, a3, a4, a5};
-          if (jtile == it)
-            best = nn_span<true>(X, MB, q0, q1, qi, av, best);
-          else
-            best = nn_span<false>(X, MB, q0, q1, 0u, av, best);
+          best = nn_span<false>(X, MB, q0, q1, 0u, av, best);
         } else if (active) {
           const uint32_t qstart = (jtile == it) ? (uint32_t)lane + 1 : 0u;
           for (uint32_t q = qstart; q < nj; ++q) {
