@@ -53,7 +53,13 @@ STAGES = ("fof3d", "refine6d", "assign", "unbind", "props")
 
 def one_step(ctx, P, ev=None):
     """The five calls; ev (6 HIP events on the launch stream) brackets them."""
-    rec = (lambda i: ev[i].record()) if ev else (lambda i: None)
+    def rec(i):
+        if ev:
+            ev[i].record()
+        if PROGRESS and i > 0:
+            import torch
+            torch.cuda.synchronize()
+            progress(f"  {STAGES[i - 1]} done")
     rec(0)
     fof = ctx.fof3d(P)
     rec(1)
@@ -68,17 +74,34 @@ def one_step(ctx, P, ev=None):
     return fof, nodes, halos, halo_of, unb
 
 
+PROGRESS = False
+
+
+def progress(msg):
+    """A line on stderr after each long step (--progress): large catalogues take
+    minutes per step."""
+    if PROGRESS:
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def timed(ctx, P, steps, warmup):
     """Mean wall time per step over `steps` after `warmup`, and the mean device
-    time of each call (HIP events, read after the timed region)."""
+    time of each call (HIP events, read after the timed region).  With
+    --progress each step is synchronised to report it."""
     import torch
-    for _ in range(warmup):
+    for k in range(warmup):
         one_step(ctx, P)
+        if PROGRESS:
+            torch.cuda.synchronize()
+            progress(f"warm-up step {k + 1}/{warmup} done")
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         out = one_step(ctx, P, evs[k])
+        if PROGRESS:
+            torch.cuda.synchronize()
+            progress(f"timed step {k + 1}/{steps} done")
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
     stage = {STAGES[i]: sum(e[i].elapsed_time(e[i + 1]) for e in evs) / steps
@@ -214,6 +237,8 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--progress", action="store_true",
+                    help="report each step and stage on stderr (synchronises after each)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other precision form and the mixed-vs-FP64 comparison")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
@@ -226,6 +251,8 @@ def main():
                     help="catalogue generator: numpy (host) or torch on the GPU (device; "
                          "power-law configs, for the 512^3 and 1024^3 catalogues)")
     args = ap.parse_args()
+    global PROGRESS
+    PROGRESS = args.progress
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "decomposition is a design, not part of this build", file=sys.stderr)
@@ -240,6 +267,7 @@ def main():
     else:
         cat = synth.make_catalog(args.config, seed=0)
     P = H.Particles.from_catalog(cat)
+    progress(f"catalogue {args.config}: {cat.n} particles")
     prec = H.PREC_FP64 if args.prec == "fp64" else H.PREC_MIXED
     ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=args.grid_min))
     sec, out, stage = timed(ctx, P, args.steps, args.warmup)
@@ -249,6 +277,7 @@ def main():
     ctx.profile_reset()
     one_step(ctx, P)
     torch.cuda.synchronize()
+    progress("kernel-timed step done")
     kern = {k: ctx.profile_read(k) for k in ("k_nn", "k_fof6", "k_potential_f64",
                                              "k_potential_f32", "k_link", "k_mom_accum",
                                              "k_select_small")}
