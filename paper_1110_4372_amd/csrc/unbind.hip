@@ -369,29 +369,29 @@ __device__ __forceinline__ void pot_clear(unsigned long long* jlo, unsigned long
   }
 }
 
-// FP64 term 1/sqrt(r^2 + eps^2) of particle (x, y, z) and j.  y0 = hardware
-// rsqrt estimate (about 2^-24 relative); one Newton step gives y0 + y0 e / 2
-// with e = 1 - r y0^2.
-__device__ __forceinline__ void pot_term_f64(double bx, double by, double bz, double x,
-                                             double y, double z, double eps2, double& y0,
-                                             double& e) {
+// Twice the FP64 term 1/sqrt(r^2 + eps^2) of particle (x, y, z) and j: with
+// y0 the hardware rsqrt estimate (about 2^-24 relative), one Newton step
+// gives y0 (3 - r y0^2) / 2; the kernels add y0 (3 - r y0^2) (a mul, an fma
+// and a mul) and halve the sums, exactly, when they convert them.
+__device__ __forceinline__ double pot_term2_f64(double bx, double by, double bz, double x,
+                                                double y, double z, double eps2) {
   const double dx = bx - x, dy = by - y, dz = bz - z;
   const double r = __fma_rn(dz, dz, __fma_rn(dy, dy, __fma_rn(dx, dx, eps2)));
-  y0 = __builtin_amdgcn_rsq(r);
-  e = __fma_rn(-(r * y0), y0, 1.0);
+  const double y0 = __builtin_amdgcn_rsq(r);
+  return __fma_rn(-(r * y0), y0, 3.0) * y0;
 }
 
-// FP64 terms for j in [j0, j1) of the layout, i side only, kept as
-// A = sum y0 and C = sum y0 e (combined as A + C / 2).  The j coordinates are
-// wave-uniform and come in through scalar loads as operands of the vector ops.
-// kSelf: skip j == the slot's own particle (the span holding the wave's tile).
+// FP64 terms (doubled) for j in [j0, j1) of the layout, i side only.  The j
+// coordinates are wave-uniform and come in through scalar loads as operands of
+// the vector ops.  kSelf: skip j == the slot's own particle (the span holding
+// the wave's tile).
 template <bool kSelf>
 __device__ __forceinline__ void pot_span_f64(const double* __restrict__ ux,
                                              const double* __restrict__ uy,
                                              const double* __restrict__ uz, uint32_t j0,
                                              uint32_t j1, const uint32_t* self, const double* x,
                                              const double* y, const double* z, double eps2,
-                                             double* A, double* C) {
+                                             double* A) {
   uint32_t j = j0;
   for (; j + 4 <= j1; j += 4) {
     double bx[4], by[4], bz[4];
@@ -408,28 +408,22 @@ __device__ __forceinline__ void pot_span_f64(const double* __restrict__ ux,
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (uint32_t k = 0; k < kPotK; ++k) {
-        double y0, e;
-        pot_term_f64(bx[u], by[u], bz[u], x[k], y[k], z[k], eps2, y0, e);
-        if (kSelf) y0 = (j + u != self[k]) ? y0 : 0.0;
-        A[k] += y0;
-        C[k] = __fma_rn(y0, e, C[k]);
+        const double t = pot_term2_f64(bx[u], by[u], bz[u], x[k], y[k], z[k], eps2);
+        A[k] += (!kSelf || j + u != self[k]) ? t : 0.0;
       }
   }
   for (; j < j1; ++j)
 #pragma unroll
     for (uint32_t k = 0; k < kPotK; ++k) {
-      double y0, e;
-      pot_term_f64(ux[j], uy[j], uz[j], x[k], y[k], z[k], eps2, y0, e);
-      if (kSelf) y0 = (j != self[k]) ? y0 : 0.0;
-      A[k] += y0;
-      C[k] = __fma_rn(y0, e, C[k]);
+      const double t = pot_term2_f64(ux[j], uy[j], uz[j], x[k], y[k], z[k], eps2);
+      A[k] += (!kSelf || j != self[k]) ? t : 0.0;
     }
 }
 
-// FP64 terms of the pairs (slot, j) for own j in [j0, j1), all above the
-// wave's tile, each evaluated once: the Newton-corrected term goes to the
-// slot's A and, summed over the wave's slots, to jacc[j - jc].  Slots without
-// a particle sit at kFar, where the term is ~1e-150: below half an ulp of any
+// FP64 terms (doubled) of the pairs (slot, j) for own j in [j0, j1), all
+// above the wave's tile, each evaluated once: the term goes to the slot's A
+// and, summed over the wave's slots, to jacc[j - jc].  Slots without a
+// particle sit at kFar, where the term is ~1e-150: below half an ulp of any
 // real term (>= 1 / the group's extent), so it changes no sum.
 __device__ __forceinline__ void pot_sym_f64(const double* __restrict__ ux,
                                             const double* __restrict__ uy,
@@ -455,33 +449,29 @@ __device__ __forceinline__ void pot_sym_f64(const double* __restrict__ ux,
     for (int u = 0; u < 8; ++u) {
 #pragma unroll
       for (uint32_t k = 0; k < kPotK; ++k) {
-        double y0, e;
-        pot_term_f64(bx[u], by[u], bz[u], x[k], y[k], z[k], eps2, y0, e);
-        const double t = __fma_rn(0.5 * y0, e, y0);
+        const double t = pot_term2_f64(bx[u], by[u], bz[u], x[k], y[k], z[k], eps2);
         A[k] += t;
         tj[u] = k == 0 ? t : tj[u] + t;
       }
     }
     const double s = wave_sum8<HALO_XORS(double, f64)>(tj);
-    if (l < 8u) lds_add_fixed(jlo, jhi, j - jc + ul, s);
+    if (l < 8u) lds_add_fixed(jlo, jhi, j - jc + ul, 0.5 * s);
   }
   for (; j < j1; ++j) {
     double tj = 0.0;
 #pragma unroll
     for (uint32_t k = 0; k < kPotK; ++k) {
-      double y0, e;
-      pot_term_f64(ux[j], uy[j], uz[j], x[k], y[k], z[k], eps2, y0, e);
-      const double t = __fma_rn(0.5 * y0, e, y0);
+      const double t = pot_term2_f64(ux[j], uy[j], uz[j], x[k], y[k], z[k], eps2);
       A[k] += t;
       tj = k == 0 ? t : tj + t;
     }
     const double s = wave_sum1<HALO_XORS(double, f64)>(tj);
-    if (l == 0u) lds_add_fixed(jlo, jhi, j - jc, s);
+    if (l == 0u) lds_add_fixed(jlo, jhi, j - jc, 0.5 * s);
   }
 }
 
 // FP64 form.
-__global__ void __launch_bounds__(TB)
+__global__ void __launch_bounds__(TB, 4)
     k_potential_f64(const double* __restrict__ ux, const double* __restrict__ uy,
                     const double* __restrict__ uz, const libhalo_halos h,
                     const uint32_t* __restrict__ order, const uint32_t* __restrict__ uoff,
@@ -505,7 +495,7 @@ __global__ void __launch_bounds__(TB)
     if (t0 < w.nown) {
       const uint32_t b = w.base;
       uint32_t qi[kPotK];
-      double x[kPotK], y[kPotK], z[kPotK], A[kPotK], C[kPotK];
+      double x[kPotK], y[kPotK], z[kPotK], A[kPotK];
 #pragma unroll
       for (uint32_t k = 0; k < kPotK; ++k) {
         const uint32_t li = t0 + (threadIdx.x & 63u) + 64u * k;
@@ -516,20 +506,19 @@ __global__ void __launch_bounds__(TB)
         y[k] = ok ? uy[q] : kFar;
         z[k] = ok ? uz[q] : kFar;
         A[k] = 0.0;
-        C[k] = 0.0;
       }
       if (t0 >= w.j0 && t0 < w.j1)
         pot_span_f64<true>(ux, uy, uz, b + t0, b + min(t0 + kPotTile, w.nown), qi, x, y, z,
-                           eps2, A, C);
+                           eps2, A);
       const uint32_t js = max(w.j0, t0 + kPotTile);
       if (js < je)
         pot_sym_f64(ux, uy, uz, b + js, b + je, b + w.j0, x, y, z, eps2, A, jlo, jhi);
       const uint32_t ss = max(w.j0, w.nown);
       if (ss < w.j1)
-        pot_span_f64<false>(ux, uy, uz, b + ss, b + w.j1, qi, x, y, z, eps2, A, C);
+        pot_span_f64<false>(ux, uy, uz, b + ss, b + w.j1, qi, x, y, z, eps2, A);
 #pragma unroll
       for (uint32_t k = 0; k < kPotK; ++k) {
-        const double v = __fma_rn(0.5, C[k], A[k]);
+        const double v = 0.5 * A[k];
         if (qi[k] != 0xFFFFFFFFu && v > 0.0) atomic_add_i128(acc + qi[k], pot_fixed(v));
       }
     }
