@@ -949,6 +949,10 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     HALO_CHECK(level < P.max_levels, LIBHALO_EINVAL, "hierarchy deeper than max_levels");
     LevelNodes nd = L[cur], nx = L[cur ^ 1];
     const size_t S = Mi;  // plane stride of xi for this level
+    // persistent grids sized to the level: units are fetched from a counter, so
+    // any grid is correct, and a deep level's few units need no 4096 blocks
+    const unsigned pgrid = (unsigned)std::min<uint64_t>(
+        kPersist, std::max<uint64_t>(256, 4 * (((uint64_t)Mi + 255) / 256)));
     const int level0 = level == 0;
     k_zero_node_scratch<<<blocks_for(K, TB), TB, 0, s>>>(sc, K);
     k_mom_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, K, sc.wmom);
@@ -968,7 +972,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
                                         mom, ctx.d_err);
       }
     } else {
-      HALO_PROF(ctx, "k_mom_accum", s, k_mom_accum<T><<<kPersist, TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, nd, K, sc.wmom, 0, K,
+      HALO_PROF(ctx, "k_mom_accum", s, k_mom_accum<T><<<pgrid, TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, nd, K, sc.wmom, 0, K,
                                              box, sx, level0, sc, ctx.d_err));
       k_mom_final<T><<<blocks_for(K, 128), 128, 0, s>>>(x, y, z, lidx, nd, 0, K, box, sx,
                                                         level0, P.f, sc, mom, ctx.d_err);
@@ -1003,7 +1007,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     } else {
       k_fill_u32<<<1, 64, 0, s>>>(dcnt + 8, 1, 0u);
       HALO_PROF(ctx, "k_nn", s,
-                k_nn<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, D));
+                k_nn<<<pgrid, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, D));
       HALO_PROF(ctx, "k_select_small", s, k_select_small<<<K, TB, 0, s>>>(D, nd, 0, K, sc));
     }
     // 4. selection for big nodes (both forms: a handful of nodes)
@@ -1016,7 +1020,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
         exclusive_scan<uint32_t>(sc.wbig, sc.wbig, nbig, sc.wbig + nbig, stmp, s);
         k_zero_hist<<<64, TB, 0, s>>>(sc, dcnt);
         for (int pass = 0; pass < 4; ++pass) {
-          k_select_big_hist<<<kPersist, TB, 0, s>>>(D, nd, sc, dcnt, pass);
+          k_select_big_hist<<<pgrid, TB, 0, s>>>(D, nd, sc, dcnt, pass);
           k_select_big_resolve<<<blocks_for(nbig, TB / 64), TB, 0, s>>>(sc, dcnt, pass);
         }
       }
@@ -1028,7 +1032,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
       k_fill_u32<<<1, 64, 0, s>>>(dcnt + 8, 1, 0u);
       HALO_PROF(ctx, "k_nn", s,
-                k_nn<<<kPersist, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, D));
+                k_nn<<<pgrid, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, D));
       select_big();
     }
     // 5. 6D FOF: all-pairs nodes over their compacted linkable particles
@@ -1049,7 +1053,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     } else {
       k_fill_u32<<<1, 64, 0, s>>>(dcnt + 8, 1, 0u);
       HALO_PROF(ctx, "k_fof6", s,
-                k_fof6<<<kPersist, TB, 0, s>>>(cxi, S, cnodes, lpos, K, sc.wpair, 0, K,
+                k_fof6<<<pgrid, TB, 0, s>>>(cxi, S, cnodes, lpos, K, sc.wpair, 0, K,
                                                dcnt + 8, sc.ell2, par));
     }
     HALO_PROF(ctx, "grid_fof", s, grid_fof(gb, sc, D, par, s));

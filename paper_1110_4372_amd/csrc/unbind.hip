@@ -1003,7 +1003,7 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       }
     } else if (U > 0) {
       k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 4, 1, 0u);
-      launch(0, U, w.dcnt + 4, kPersist);
+      launch(0, U, w.dcnt + 4, std::min<uint32_t>(kPersist, U));
     }
     k_pot_finish<<<blocks_for(m, TB), TB, 0, s>>>(w.pacc, m, w.sum);
     k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 3, 1, 0u);
