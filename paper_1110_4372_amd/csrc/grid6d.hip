@@ -9,11 +9,13 @@
 //   2. the node's particles are ordered along a 6D Morton curve (8 bits per
 //      coordinate over [-A, A], clamped) and cut into tiles of 64; each tile
 //      gets its 6D bounding box;
-//   3. one wavefront per target tile tests the boxes of all tiles of the node
-//      (64 at a time, one per lane) and streams every tile whose box lies
-//      within R of its own box through LDS, computing the canonical FP32 d^2
-//      of all 64 x 64 pairs.  Every pair closer than R lies in such a tile
-//      pair, so D_i is exact whenever D_i <= R^2 and exceeds R^2 otherwise;
+//   3. one wavefront per target tile tests the boxes of super-tiles (64
+//      consecutive tiles, 64 super-tiles at a time, one per lane), then the
+//      tiles of each super-tile within R, and evaluates every tile whose box
+//      lies within R of its own box: the canonical FP32 d^2 of its pairs,
+//      unless no lane's particle is close enough to the tile's box to gain
+//      from it.  Every pair closer than R lies in such a tile pair, so D_i is
+//      exact whenever D_i <= R^2 and exceeds R^2 otherwise;
 //   4. after the selection of ell^2 (the k-th smallest D) the node's result is
 //      exact iff ell^2 <= R^2; a node failing the check is redone all-pairs;
 //   5. 6D FOF at ell^2 uses the same tiles, pruned at ell.
@@ -175,6 +177,29 @@ __global__ void k_tile_boxes(GridBufs g, uint32_t MB, uint32_t NT) {
   }
 }
 
+// Box of each super-tile: the union of the boxes of tiles [64 g, 64 g + 64),
+// one wavefront per super-tile.  A super-tile may hold tiles of two nodes; its
+// box then bounds both, which only weakens the pruning.
+__global__ void k_super_boxes(GridBufs g, uint32_t NT, uint32_t NS) {
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t lane = threadIdx.x & 63u;
+  if (wave >= NS) return;
+  const uint32_t t = wave * 64u + lane;
+  const bool ok = t < NT;
+  const uint32_t tt = ok ? t : wave * 64u;
+  for (int c = 0; c < 6; ++c) {
+    float mn = g.tbox[12 * (size_t)tt + c], mx = g.tbox[12 * (size_t)tt + 6 + c];
+    for (int o = 32; o > 0; o >>= 1) {
+      mn = fminf(mn, __shfl_xor(mn, o));
+      mx = fmaxf(mx, __shfl_xor(mx, o));
+    }
+    if (lane == 0) {
+      g.sbox[12 * (size_t)wave + c] = mn;
+      g.sbox[12 * (size_t)wave + 6 + c] = mx;
+    }
+  }
+}
+
 __device__ __forceinline__ float box_gap2(const float* a, const float* b) {
   float s = 0.0f;
 #pragma unroll
@@ -245,52 +270,68 @@ __global__ void __launch_bounds__(kTile)
       const uint32_t q0 = p0, q1 = p1;
       best = nn_span<true>(X, MB, q0, q1, qi, av, best);
     }
-    // j tiles by chunks of 64, starting at the chunk holding the target (near
-    // it on the Morton curve); FOF considers each unordered pair once, so its
-    // j tiles start at the target
+    // j tiles through super-tiles of 64, 64 super-tiles at a time; the NN pass
+    // starts at the super-tile holding the target (near it on the Morton
+    // curve); FOF considers each unordered pair once, so its j tiles start at
+    // the target
     const uint32_t jt0 = MODE == 1 ? it : tb0;
-    const uint32_t nch = (tb1 - jt0 + kTile - 1) / kTile;
-    const uint32_t c0 = MODE == 1 ? 0u : (it - tb0) / kTile;
-    for (uint32_t cc = 0; cc < nch; ++cc) {
-      const uint32_t ch = c0 + cc < nch ? c0 + cc : c0 + cc - nch;
-      const uint32_t jc = jt0 + ch * kTile;
-      const uint32_t jt = jc + lane;
-      bool cand = false;
-      if (jt < tb1 && (MODE == 1 || jt != it))
-        cand = box_gap2(ibox, g.tbox + 12 * (size_t)jt) <= radius2;
-      unsigned long long mask = __ballot(cand);
-      while (mask) {
-        const int bit = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        const uint32_t jtile = __builtin_amdgcn_readfirstlane(jc + bit);
-        // skip the tile unless some lane could gain from it
-        const float gp = point_gap2(av, g.tbox + 12 * (size_t)jtile);
-        if (MODE == 0 ? !__any(ok && gp < best) : !__any(active && gp <= l2)) continue;
-        const uint32_t q0 = ps + (jtile - tb0) * kTile;
-        const uint32_t q1 = min(pe, q0 + kTile);
-        if (MODE == 1) {  // the FOF pass stages the tile and its roots
-          __syncthreads();
-          if (q0 + lane < q1) {
-            const uint32_t qj = q0 + lane;
-            for (int c = 0; c < 6; ++c) t[c][lane] = X[(size_t)c * MB + qj];
-            const uint32_t mj = g.gm[qj];
-            troot[lane] = __uint_as_float(D[mj]) <= l2 ? uf_find(par, mj) : 0xFFFFFFFEu;
-          }
-          __syncthreads();
-        }
-        const uint32_t nj = q1 - q0;
-        if (MODE == 0) {
-          best = nn_span<false>(X, MB, q0, q1, 0u, av, best);
-        } else if (active) {
-          const uint32_t qstart = (jtile == it) ? (uint32_t)lane + 1 : 0u;
-          for (uint32_t q = qstart; q < nj; ++q) {
-            if (troot[q] == 0xFFFFFFFEu || troot[q] == ri) continue;
-            float d = d2_6(a0, a1, a2, a3, a4, a5, t[0][q], t[1][q], t[2][q], t[3][q], t[4][q],
-                           t[5][q]);
-            if (d <= l2) {
-              uf_union(par, mi, g.gm[q0 + q]);
-              ri = uf_find(par, mi);
+    const uint32_t s0 = jt0 >> 6, ns = ((tb1 - 1) >> 6) - s0 + 1;
+    const uint32_t rot = MODE == 1 ? 0u : (it >> 6) - s0;
+    for (uint32_t sb = 0; sb < ns; sb += kTile) {
+      const uint32_t sl = sb + lane;
+      bool scand = false;
+      if (sl < ns) {
+        const uint32_t sg = s0 + (sl + rot < ns ? sl + rot : sl + rot - ns);
+        scand = box_gap2(ibox, g.sbox + 12 * (size_t)sg) <= radius2;
+      }
+      unsigned long long smask = __ballot(scand);
+      while (smask) {
+        const int sbit = __ffsll((long long)smask) - 1;
+        smask &= smask - 1;
+        const uint32_t sl2 = sb + sbit;
+        const uint32_t sg = __builtin_amdgcn_readfirstlane(
+            s0 + (sl2 + rot < ns ? sl2 + rot : sl2 + rot - ns));
+        const uint32_t ta = max(sg * 64u, jt0), tz = min(sg * 64u + 64u, tb1);
+        const uint32_t jt = ta + lane;
+        bool cand = false;
+        if (jt < tz && (MODE == 1 || jt != it))
+          cand = box_gap2(ibox, g.tbox + 12 * (size_t)jt) <= radius2;
+        unsigned long long mask = __ballot(cand);
+        while (mask) {
+          const int bit = __ffsll((long long)mask) - 1;
+          mask &= mask - 1;
+          const uint32_t jtile = __builtin_amdgcn_readfirstlane(ta + bit);
+          // skip the tile unless some lane could gain from it
+          const float gp = point_gap2(av, g.tbox + 12 * (size_t)jtile);
+          if (MODE == 0 ? !__any(ok && gp < best) : !__any(active && gp <= l2)) continue;
+          const uint32_t q0 = ps + (jtile - tb0) * kTile;
+          const uint32_t q1 = min(pe, q0 + kTile);
+          if (MODE == 1) {  // the FOF pass stages the tile and its roots
+            __syncthreads();
+            if (q0 + lane < q1) {
+              const uint32_t qj = q0 + lane;
+              for (int c = 0; c < 6; ++c) t[c][lane] = X[(size_t)c * MB + qj];
+              const uint32_t mj = g.gm[qj];
+              troot[lane] = __uint_as_float(D[mj]) <= l2 ? uf_find(par, mj) : 0xFFFFFFFEu;
             }
+            __syncthreads();
+            if (active) {
+              // a j already in the lane's set (equal roots at some point; sets
+              // only merge) needs no distance
+              const uint32_t nj = q1 - q0;
+              const uint32_t qstart = (jtile == it) ? (uint32_t)lane + 1 : 0u;
+              for (uint32_t q = qstart; q < nj; ++q) {
+                if (troot[q] == 0xFFFFFFFEu || troot[q] == ri) continue;
+                const float d = d2_6(a0, a1, a2, a3, a4, a5, t[0][q], t[1][q], t[2][q],
+                                     t[3][q], t[4][q], t[5][q]);
+                if (d <= l2) {
+                  uf_union(par, mi, g.gm[q0 + q]);
+                  ri = uf_find(par, mi);
+                }
+              }
+            }
+          } else {
+            best = nn_span<false>(X, MB, q0, q1, 0u, av, best);
           }
         }
       }
@@ -347,6 +388,7 @@ void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax) {
   g.gcount = A.take<uint32_t>(NBmax + 1);
   g.gtile_node = A.take<uint32_t>(NTmax);
   g.tbox = A.take<float>(12ull * NTmax);
+  g.sbox = A.take<float>(12ull * (NTmax / 64 + 2));
   g.flag = A.take<uint32_t>((size_t)M + 2);
   g.pos = A.take<uint32_t>((size_t)M + 2);
   g.k0 = A.take<unsigned long long>((size_t)M + 2);
@@ -396,6 +438,8 @@ uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint3
   k_grid_gather<<<blocks_for(MB, TB), TB, 0, s>>>(sv, xi, S, MB, g);
   k_tile_setup<<<blocks_for(NB, TB), TB, 0, s>>>(nd, g, NB);
   k_tile_boxes<<<blocks_for((int64_t)NT * 64, TB), TB, 0, s>>>(g, MB, NT);
+  const uint32_t NS = (NT + 63) / 64;
+  k_super_boxes<<<blocks_for((int64_t)NS * 64, TB), TB, 0, s>>>(g, NT, NS);
   k_tile_pass<0><<<std::min<uint32_t>(NT, 16384), kTile, 0, s>>>(g, MB, NT, sc, D, nullptr);
   return NB;
 }

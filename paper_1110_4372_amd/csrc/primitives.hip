@@ -52,16 +52,17 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const T* in, int64
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// Scans a tile of kScanTile elements; adds offset part[blockIdx.x] if part.
-template <class T>
-__global__ void __launch_bounds__(kScanThreads) k_scan_down(const T* in, T* out, int64_t n,
-                                                            const T* part, T* total) {
-  __shared__ T lds[kScanThreads / kWave + 1];
-  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  T v[kScanItems];
+// Scans a tile of NT x ITEMS elements per block; adds offset part[blockIdx.x]
+// if part.
+template <class T, int NT = kScanThreads, int ITEMS = kScanItems>
+__global__ void __launch_bounds__(NT) k_scan_down(const T* in, T* out, int64_t n,
+                                                  const T* part, T* total) {
+  __shared__ T lds[NT / kWave + 1];
+  int64_t base = (int64_t)blockIdx.x * (NT * ITEMS) + (int64_t)threadIdx.x * ITEMS;
+  T v[ITEMS];
   T s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     v[i] = (base + i < n) ? in[base + i] : T(0);
     s += v[i];
   }
@@ -69,12 +70,17 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(const T* in, T* out,
   T run = block_exclusive_scan(s, &tot, lds);
   if (part) run += part[blockIdx.x];
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     if (base + i < n) out[base + i] = run;
     run += v[i];
   }
   if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) *total = run;
 }
+
+// One block of 1024 threads scans up to kScanOneBlock elements in one launch.
+constexpr int kScanOneThreads = 1024;
+constexpr int kScanOneItems = 16;
+constexpr int64_t kScanOneBlock = (int64_t)kScanOneThreads * kScanOneItems;
 
 }  // namespace
 
@@ -96,6 +102,11 @@ void exclusive_scan(const T* in, T* out, int64_t n, T* total, T* tmp, hipStream_
   }
   if (n <= kScanTile) {
     k_scan_down<T><<<1, kScanThreads, 0, s>>>(in, out, n, nullptr, total);
+    return;
+  }
+  if (n <= kScanOneBlock) {
+    k_scan_down<T, kScanOneThreads, kScanOneItems>
+        <<<1, kScanOneThreads, 0, s>>>(in, out, n, nullptr, total);
     return;
   }
   int64_t nb = (n + kScanTile - 1) / kScanTile;

@@ -72,6 +72,7 @@ constexpr float kRadiusFactor = 2.0f;
 struct GridBufs {
   uint32_t *nb_rank, *gnode, *ncell, *cellbase, *pstart, *gcount, *gtile_node;
   float *samp, *r2, *tbox;
+  float* sbox;  // 12 per super-tile of 64 tiles: the union of their boxes
   uint32_t *flag, *pos, *v0, *v1, *gm, *cnt, *stmp;
   unsigned long long *k0, *k1;
   float* gx;  // six planes of stride MB, sorted order
