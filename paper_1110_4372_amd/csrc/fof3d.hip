@@ -108,8 +108,49 @@ __device__ __forceinline__ int64_t find_cell(const unsigned long long* cell_key,
   return -1;
 }
 
+// First cell of [lo, hi) whose key is >= want (keys ascend within a row).
+__device__ __forceinline__ uint32_t lower_cell(const unsigned long long* cell_key, uint32_t lo,
+                                               uint32_t hi, unsigned long long want) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (cell_key[mid] < want)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Links cell c with occupied cell d (key kd) at offset (dx, dy, dz) when they
+// do not share a root yet and hold a friendly pair: the cells' particles are
+// tested until the first pair within ll.
+template <class T>
+__device__ __forceinline__ void link_pair(const T* xs, const T* ys, const T* zs,
+                                          const uint32_t* cell_start, int64_t ncell, int64_t n,
+                                          const Grid& g, uint32_t c, uint32_t a0, uint32_t a1,
+                                          uint32_t d, uint32_t* par) {
+  if (uf_find(par, c) == uf_find(par, d)) return;
+  const uint32_t b0 = cell_start[d];
+  const uint32_t b1 = (d + 1 < ncell) ? cell_start[d + 1] : (uint32_t)n;
+  for (uint32_t i = a0; i < a1; ++i) {
+    const double xi = (double)xs[i], yi = (double)ys[i], zi = (double)zs[i];
+    for (uint32_t j = b0; j < b1; ++j) {
+      const double ex = min_image((double)xs[j] - xi, g.box);
+      const double ey = min_image((double)ys[j] - yi, g.box);
+      const double ez = min_image((double)zs[j] - zi, g.box);
+      if (sq3(ex, ey, ez) <= g.ll2) {
+        uf_union(par, c, d);
+        return;
+      }
+    }
+  }
+}
+
 // Link pass over the half stencil.  phase 0: offsets within one cell on every
-// axis; phase 1: the others.  One thread per occupied cell.
+// axis; phase 1: the others.  One thread per occupied cell.  The stencil is
+// visited row by row (rows are (cz, cy)): an empty row costs its two bounds,
+// and the occupied cells of the x range [cx - R, cx + R] (periodic, so up to
+// two intervals) are found by one search.
 template <class T>
 __global__ void k_link(const T* xs, const T* ys, const T* zs, const uint32_t* cell_start,
                        const unsigned long long* cell_key, const uint32_t* row_start,
@@ -127,39 +168,46 @@ __global__ void k_link(const T* xs, const T* ys, const T* zs, const uint32_t* ce
   const double side = g.box / (double)nc;
   for (int dz = 0; dz <= R; ++dz) {
     for (int dy = (dz == 0 ? 0 : -R); dy <= R; ++dy) {
-      for (int dx = ((dz == 0 && dy == 0) ? 1 : -R); dx <= R; ++dx) {
-        int far = (dx > 1 || dx < -1 || dy > 1 || dy < -1 || dz > 1);
-        if (far != phase) continue;
-        // smallest possible separation of the two cells
-        double gx = (double)(dx < 0 ? -dx - 1 : (dx > 0 ? dx - 1 : 0));
-        double gy = (double)(dy < 0 ? -dy - 1 : (dy > 0 ? dy - 1 : 0));
-        double gz = (double)(dz > 0 ? dz - 1 : 0);
-        if ((gx * gx + gy * gy + gz * gz) * side * side > g.ll2 * (1.0 + 1e-9)) continue;
-        int64_t nx = cx + dx, ny = cy + dy, nz = cz + dz;
-        nx = nx < 0 ? nx + nc : (nx >= nc ? nx - nc : nx);
-        ny = ny < 0 ? ny + nc : (ny >= nc ? ny - nc : ny);
-        nz = nz < 0 ? nz + nc : (nz >= nc ? nz - nc : nz);
-        int64_t row = nz * nc + ny;
-        int64_t d = find_cell(cell_key, row_start, row,
-                              (unsigned long long)(row * nc + nx));
-        if (d < 0) continue;
-        if (uf_find(par, (uint32_t)c) == uf_find(par, (uint32_t)d)) continue;
-        const uint32_t b0 = cell_start[d];
-        const uint32_t b1 = (d + 1 < ncell) ? cell_start[d + 1] : (uint32_t)n;
-        bool linked = false;
-        for (uint32_t i = a0; i < a1 && !linked; ++i) {
-          double xi = (double)xs[i], yi = (double)ys[i], zi = (double)zs[i];
-          for (uint32_t j = b0; j < b1; ++j) {
-            double ex = min_image((double)xs[j] - xi, g.box);
-            double ey = min_image((double)ys[j] - yi, g.box);
-            double ez = min_image((double)zs[j] - zi, g.box);
-            if (sq3(ex, ey, ez) <= g.ll2) {
-              linked = true;
-              break;
-            }
-          }
+      const int xlo = (dz == 0 && dy == 0) ? 1 : -R;
+      // phase 0 holds only |dx|, |dy|, dz <= 1
+      if (phase == 0 && (dz > 1 || dy > 1 || dy < -1)) continue;
+      int64_t ny = cy + dy, nz = cz + dz;
+      ny = ny < 0 ? ny + nc : (ny >= nc ? ny - nc : ny);
+      nz = nz < 0 ? nz + nc : (nz >= nc ? nz - nc : nz);
+      const int64_t row = nz * nc + ny;
+      const uint32_t r0 = row_start[row], r1 = row_start[row + 1];
+      if (r0 == r1) continue;
+      const unsigned long long rbase = (unsigned long long)row * (unsigned long long)nc;
+      // x range [cx + xlo, cx + R] as up to two intervals of [0, nc)
+      int64_t u0 = cx + xlo, u1 = cx + R;
+      int64_t iv[2][2];
+      int nv = 0;
+      if (u0 < 0) {
+        iv[nv][0] = u0 + nc; iv[nv][1] = nc - 1; ++nv;
+        u0 = 0;
+      }
+      if (u1 >= nc) {
+        iv[nv][0] = 0; iv[nv][1] = u1 - nc; ++nv;
+        u1 = nc - 1;
+      }
+      iv[nv][0] = u0; iv[nv][1] = u1; ++nv;
+      for (int q = 0; q < nv; ++q) {
+        uint32_t p = lower_cell(cell_key, r0, r1, rbase + (unsigned long long)iv[q][0]);
+        for (; p < r1; ++p) {
+          const unsigned long long kd = cell_key[p];
+          const int64_t x = (int64_t)(kd - rbase);
+          if (x > iv[q][1]) break;
+          int64_t dx = x - cx;
+          dx = dx > R ? dx - nc : (dx < -R ? dx + nc : dx);
+          const int far = (dx > 1 || dx < -1 || dy > 1 || dy < -1 || dz > 1);
+          if (far != phase) continue;
+          // smallest possible separation of the two cells
+          const double gx = (double)(dx < 0 ? -dx - 1 : (dx > 0 ? dx - 1 : 0));
+          const double gy = (double)(dy < 0 ? -dy - 1 : (dy > 0 ? dy - 1 : 0));
+          const double gz = (double)(dz > 0 ? dz - 1 : 0);
+          if ((gx * gx + gy * gy + gz * gz) * side * side > g.ll2 * (1.0 + 1e-9)) continue;
+          link_pair(xs, ys, zs, cell_start, ncell, n, g, (uint32_t)c, a0, a1, p, par);
         }
-        if (linked) uf_union(par, (uint32_t)c, (uint32_t)d);
       }
     }
   }
