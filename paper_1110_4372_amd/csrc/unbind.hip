@@ -300,37 +300,7 @@ __device__ __forceinline__ void lds_add_fixed(unsigned long long* jlo, unsigned 
   if (add_hi != 0) atomicAdd(jhi + q, (unsigned long long)add_hi);
 }
 
-// Sum over the wave's 64 lanes of each of d[0..7], transposed: lane l returns
-// the sum of d[u] with u = 4 b0 + 2 b1 + b2 (b0..b2 the low bits of l).  Each
-// halving step keeps the half of the values selected by one lane bit and adds
-// the partner's copy of the same half; the tree is fixed, so the result is
-// deterministic.
-template <class F, F (*X1)(F), F (*X2)(F), F (*X4)(F), F (*X8)(F), F (*X16)(F), F (*X32)(F)>
-__device__ __forceinline__ F wave_sum8(const F* d) {
-  const uint32_t l = threadIdx.x & 63u;
-  const bool b0 = l & 1u, b1 = l & 2u, b2 = l & 4u;
-  F r1[4], r2[2];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const F keep = b0 ? d[4 + k] : d[k];
-    const F send = b0 ? d[k] : d[4 + k];
-    r1[k] = keep + X1(send);
-  }
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const F keep = b1 ? r1[2 + k] : r1[k];
-    const F send = b1 ? r1[k] : r1[2 + k];
-    r2[k] = keep + X2(send);
-  }
-  const F keep = b2 ? r2[1] : r2[0];
-  const F send = b2 ? r2[0] : r2[1];
-  F r = keep + X4(send);
-  r = r + X8(r);
-  r = r + X16(r);
-  r = r + X32(r);
-  return r;
-}
-
+// Sum over the wave's 64 lanes, in every lane (a fixed tree).
 template <class F, F (*X1)(F), F (*X2)(F), F (*X4)(F), F (*X8)(F), F (*X16)(F), F (*X32)(F)>
 __device__ __forceinline__ F wave_sum1(F r) {
   r = r + X1(r);
@@ -342,14 +312,82 @@ __device__ __forceinline__ F wave_sum1(F r) {
   return r;
 }
 
+// Sum over the wave's 64 lanes of each of d[0..7], transposed, with lane-half
+// swaps: v_permlane32_swap exchanges the upper half of one register with the
+// lower half of another, so adding the two results sums lanes l and l ^ 32 of
+// one value in the lower half and of the other value in the upper half (no
+// selects); v_permlane16_swap does the same for l ^ 16 within each half, a
+// keep/send exchange for l ^ 8 halves the values once more, and three
+// exchanges sum the lanes l ^ 1, l ^ 2, l ^ 4.  Lane l with l & 7 == 0 returns
+// the sum of d[u] with u = 4 b3 + 2 b4 + b5 (b3..b5 bits 3..5 of l).  The tree
+// is fixed, so the result is deterministic.
+__device__ __forceinline__ void swap_halves32(uint32_t& x, uint32_t& y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+__device__ __forceinline__ void swap_halves16(uint32_t& x, uint32_t& y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+template <void (*SW)(uint32_t&, uint32_t&)>
+__device__ __forceinline__ double swap_add_f64(double x, double y) {
+  unsigned long long ux = (unsigned long long)__double_as_longlong(x);
+  unsigned long long uy = (unsigned long long)__double_as_longlong(y);
+  uint32_t xl = (uint32_t)ux, xh = (uint32_t)(ux >> 32), yl = (uint32_t)uy,
+           yh = (uint32_t)(uy >> 32);
+  SW(xl, yl);
+  SW(xh, yh);
+  const double a = __longlong_as_double((long long)(((unsigned long long)xh << 32) | xl));
+  const double b = __longlong_as_double((long long)(((unsigned long long)yh << 32) | yl));
+  return a + b;
+}
+template <void (*SW)(uint32_t&, uint32_t&)>
+__device__ __forceinline__ float swap_add_f32(float x, float y) {
+  uint32_t ux = __float_as_uint(x), uy = __float_as_uint(y);
+  SW(ux, uy);
+  return __uint_as_float(ux) + __uint_as_float(uy);
+}
+
+__device__ __forceinline__ double wave_sum8_f64(const double* d) {
+  const bool b3 = threadIdx.x & 8u;
+  double s[4], t[2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) s[m] = swap_add_f64<swap_halves32>(d[2 * m], d[2 * m + 1]);
+  t[0] = swap_add_f64<swap_halves16>(s[0], s[1]);
+  t[1] = swap_add_f64<swap_halves16>(s[2], s[3]);
+  double r = (b3 ? t[1] : t[0]) + lane_xor_f64<lane_xor8>(b3 ? t[0] : t[1]);
+  r = r + lane_xor_f64<lane_xor1>(r);
+  r = r + lane_xor_f64<lane_xor2>(r);
+  r = r + lane_xor_f64<lane_xor4>(r);
+  return r;
+}
+
+__device__ __forceinline__ float wave_sum8_f32(const float* d) {
+  const bool b3 = threadIdx.x & 8u;
+  float s[4], t[2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) s[m] = swap_add_f32<swap_halves32>(d[2 * m], d[2 * m + 1]);
+  t[0] = swap_add_f32<swap_halves16>(s[0], s[1]);
+  t[1] = swap_add_f32<swap_halves16>(s[2], s[3]);
+  float r = (b3 ? t[1] : t[0]) + lane_xor_f32<lane_xor8>(b3 ? t[0] : t[1]);
+  r = r + lane_xor_f32<lane_xor1>(r);
+  r = r + lane_xor_f32<lane_xor2>(r);
+  r = r + lane_xor_f32<lane_xor4>(r);
+  return r;
+}
+
+// The value index whose wave sum lane l holds after wave_sum8_f64/f32.
+__device__ __forceinline__ uint32_t sum8_index() {
+  const uint32_t l = threadIdx.x & 63u;
+  return (((l >> 3) & 1u) << 2) | (((l >> 4) & 1u) << 1) | ((l >> 5) & 1u);
+}
+
 #define HALO_XORS(F, f)                                                                   \
   F, lane_xor_##f<lane_xor1>, lane_xor_##f<lane_xor2>, lane_xor_##f<lane_xor4>,         \
       lane_xor_##f<lane_xor8>, lane_xor_##f<lane_xor16>, lane_xor_##f<lane_xor32>
 
-__device__ __forceinline__ uint32_t lane_perm8() {
-  const uint32_t l = threadIdx.x & 63u;
-  return ((l & 1u) << 2) | (l & 2u) | ((l >> 2) & 1u);
-}
 
 // The unit's LDS j sums into the particles' accumulators.
 __device__ __forceinline__ void pot_flush(const unsigned long long* jlo,
@@ -369,16 +407,18 @@ __device__ __forceinline__ void pot_clear(unsigned long long* jlo, unsigned long
   }
 }
 
-// Twice the FP64 term 1/sqrt(r^2 + eps^2) of particle (x, y, z) and j: with
-// y0 the hardware rsqrt estimate (about 2^-24 relative), one Newton step
-// gives y0 (3 - r y0^2) / 2; the kernels add y0 (3 - r y0^2) (a mul, an fma
-// and a mul) and halve the sums, exactly, when they convert them.
-__device__ __forceinline__ double pot_term2_f64(double bx, double by, double bz, double x,
-                                                double y, double z, double eps2) {
+// Twice the FP64 term 1/sqrt(r^2 + eps^2) of particle (x, y, z) and j is
+// c y0: with y0 the hardware rsqrt estimate (about 2^-24 relative), one Newton
+// step gives y0 (3 - r y0^2) / 2, so c = 3 - r y0^2 (a mul and an fma).  The
+// kernels add c y0 with an fma and halve the sums, exactly, when they convert
+// them.
+__device__ __forceinline__ void pot_term2_f64(double bx, double by, double bz, double x,
+                                              double y, double z, double eps2, double& c,
+                                              double& y0) {
   const double dx = bx - x, dy = by - y, dz = bz - z;
   const double r = __fma_rn(dz, dz, __fma_rn(dy, dy, __fma_rn(dx, dx, eps2)));
-  const double y0 = __builtin_amdgcn_rsq(r);
-  return __fma_rn(-(r * y0), y0, 3.0) * y0;
+  y0 = __builtin_amdgcn_rsq(r);
+  c = __fma_rn(-(r * y0), y0, 3.0);
 }
 
 // FP64 terms (doubled) for j in [j0, j1) of the layout, i side only.  The j
@@ -408,15 +448,17 @@ __device__ __forceinline__ void pot_span_f64(const double* __restrict__ ux,
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (uint32_t k = 0; k < kPotK; ++k) {
-        const double t = pot_term2_f64(bx[u], by[u], bz[u], x[k], y[k], z[k], eps2);
-        A[k] += (!kSelf || j + u != self[k]) ? t : 0.0;
+        double c, y0;
+        pot_term2_f64(bx[u], by[u], bz[u], x[k], y[k], z[k], eps2, c, y0);
+        A[k] = __fma_rn(c, (!kSelf || j + u != self[k]) ? y0 : 0.0, A[k]);
       }
   }
   for (; j < j1; ++j)
 #pragma unroll
     for (uint32_t k = 0; k < kPotK; ++k) {
-      const double t = pot_term2_f64(ux[j], uy[j], uz[j], x[k], y[k], z[k], eps2);
-      A[k] += (!kSelf || j != self[k]) ? t : 0.0;
+      double c, y0;
+      pot_term2_f64(ux[j], uy[j], uz[j], x[k], y[k], z[k], eps2, c, y0);
+      A[k] = __fma_rn(c, (!kSelf || j != self[k]) ? y0 : 0.0, A[k]);
     }
 }
 
@@ -432,7 +474,7 @@ __device__ __forceinline__ void pot_sym_f64(const double* __restrict__ ux,
                                             const double* y, const double* z, double eps2,
                                             double* A, unsigned long long* jlo,
                                             unsigned long long* jhi) {
-  const uint32_t l = threadIdx.x & 63u, ul = lane_perm8();
+  const uint32_t l = threadIdx.x & 63u, ul = sum8_index();
   uint32_t j = j0;
   for (; j + 8 <= j1; j += 8) {
     double bx[8], by[8], bz[8], tj[8];
@@ -449,19 +491,23 @@ __device__ __forceinline__ void pot_sym_f64(const double* __restrict__ ux,
     for (int u = 0; u < 8; ++u) {
 #pragma unroll
       for (uint32_t k = 0; k < kPotK; ++k) {
-        const double t = pot_term2_f64(bx[u], by[u], bz[u], x[k], y[k], z[k], eps2);
+        double c, y0;
+        pot_term2_f64(bx[u], by[u], bz[u], x[k], y[k], z[k], eps2, c, y0);
+        const double t = c * y0;  // one live value per pair (fmas of c and y0 spill here)
         A[k] += t;
         tj[u] = k == 0 ? t : tj[u] + t;
       }
     }
-    const double s = wave_sum8<HALO_XORS(double, f64)>(tj);
-    if (l < 8u) lds_add_fixed(jlo, jhi, j - jc + ul, 0.5 * s);
+    const double s = wave_sum8_f64(tj);
+    if ((l & 7u) == 0u) lds_add_fixed(jlo, jhi, j - jc + ul, 0.5 * s);
   }
   for (; j < j1; ++j) {
     double tj = 0.0;
 #pragma unroll
     for (uint32_t k = 0; k < kPotK; ++k) {
-      const double t = pot_term2_f64(ux[j], uy[j], uz[j], x[k], y[k], z[k], eps2);
+      double c, y0;
+      pot_term2_f64(ux[j], uy[j], uz[j], x[k], y[k], z[k], eps2, c, y0);
+      const double t = c * y0;
       A[k] += t;
       tj = k == 0 ? t : tj + t;
     }
@@ -603,7 +649,7 @@ __device__ __forceinline__ void pot_sym_f32(const float* __restrict__ fx,
                                             const float* y, const float* z, float eps2,
                                             Comp32* A, unsigned long long* jlo,
                                             unsigned long long* jhi) {
-  const uint32_t l = threadIdx.x & 63u, ul = lane_perm8();
+  const uint32_t l = threadIdx.x & 63u, ul = sum8_index();
   uint32_t j = j0;
   while (j < j1) {
     const uint32_t je = min(j + 64u, j1);
@@ -629,8 +675,8 @@ __device__ __forceinline__ void pot_sym_f32(const float* __restrict__ fx,
           p[k] += t;
           tj[u] = k == 0 ? t : tj[u] + t;
         }
-      const float s = wave_sum8<HALO_XORS(float, f32)>(tj);
-      if (l < 8u) lds_add_fixed(jlo, jhi, j - jc + ul, (double)s);
+      const float s = wave_sum8_f32(tj);
+      if ((l & 7u) == 0u) lds_add_fixed(jlo, jhi, j - jc + ul, (double)s);
     }
     for (; j < je; ++j) {
       float tj = 0.0f;
