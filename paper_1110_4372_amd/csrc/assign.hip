@@ -254,6 +254,114 @@ __global__ void __launch_bounds__(kMergeTB)
   }
 }
 
+// Eq. 2 merging of the groups with more than kMergeWave seeds, in parallel
+// over all their seeds: the visit in k_merge_big decides seed b (position t of
+// its group's slice of ord) from the kept seeds before it, and merges b into
+// the argmin a of q(a, b) when that is below q2.  Only earlier seeds with
+// q(a, b) < q2 can matter, so they are listed for every b first (the same FP64
+// expression as the visit), and one thread per group then resolves its seeds
+// in order, visiting only those with a candidate: b stays kept unless some
+// candidate is still kept, and merges into the kept candidate of least q
+// (ties to the lower id).
+template <bool kWrite>
+__global__ void k_merge_cand(const uint32_t* ord, const uint32_t* head, const uint32_t* hpos,
+                             const uint32_t* seg_start, const uint32_t* nseg, uint32_t S,
+                             double box, double q2, libhalo_halos h, SeedT st, uint32_t* ccnt,
+                             const uint32_t* cstart, uint32_t* cpos, double* cq) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= S) return;
+  const uint32_t F = nseg[0];
+  const uint32_t g = hpos[t] + head[t] - 1u;
+  const uint32_t a0 = seg_start[g], a1 = (g + 1 < F) ? seg_start[g + 1] : S;
+  uint32_t c = 0, w = kWrite ? cstart[t] : 0u;
+  if (a1 - a0 > kMergeWave) {
+    const uint32_t b = ord[t];
+    const double cb = (double)st.cnt[b], sx2 = st.sx2[b], sv2 = st.sv2[b];
+    if (sx2 > 0.0 && sv2 > 0.0) {
+      const double imx = cb / sx2, imv = cb / sv2;
+      const double xb = h.xs[b], yb = h.ys[b], zb = h.zs[b];
+      const double vxb = h.vxs[b], vyb = h.vys[b], vzb = h.vzs[b];
+      for (uint32_t pa = a0; pa < t; ++pa) {
+        const uint32_t a = ord[pa];
+        const double dx = min_image(xb - h.xs[a], box);
+        const double dy = min_image(yb - h.ys[a], box);
+        const double dz = min_image(zb - h.zs[a], box);
+        const double ux = vxb - h.vxs[a], uy = vyb - h.vys[a], uz = vzb - h.vzs[a];
+        const double qq = __fma_rn(sq3(dx, dy, dz), imx, sq3(ux, uy, uz) * imv);
+        if (qq < q2) {
+          if (kWrite) {
+            cpos[w] = pa;
+            cq[w] = qq;
+            ++w;
+          } else {
+            ++c;
+          }
+        }
+      }
+    }
+  }
+  if (!kWrite) ccnt[t] = c;
+}
+
+// Seeds of big groups start kept; those with candidates are listed in order.
+__global__ void k_merge_big_init(const uint32_t* ord, const uint32_t* head, const uint32_t* hpos,
+                                 const uint32_t* seg_start, const uint32_t* nseg, uint32_t S,
+                                 const uint32_t* ccnt, libhalo_halos h, uint8_t* status,
+                                 uint32_t* hflag) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= S) return;
+  const uint32_t F = nseg[0];
+  const uint32_t g = hpos[t] + head[t] - 1u;
+  const uint32_t a0 = seg_start[g], a1 = (g + 1 < F) ? seg_start[g + 1] : S;
+  const bool big = a1 - a0 > kMergeWave;
+  if (big) {
+    const uint32_t b = ord[t];
+    h.merged_into[b] = (int32_t)b;
+    status[t] = 1;
+  }
+  hflag[t] = (big && ccnt[t] > 0) ? 1u : 0u;
+}
+
+__global__ void k_merge_list(const uint32_t* hflag, const uint32_t* lpos, uint32_t S,
+                             uint32_t* list) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < S && hflag[t]) list[lpos[t]] = t;
+}
+
+// One thread per group: its seeds with candidates, in visiting order.  A
+// thread reads only statuses it wrote itself or that were set before the
+// kernel.
+__global__ void k_merge_resolve(const uint32_t* ord, const uint32_t* seg_start,
+                                const uint32_t* nseg, uint32_t S, const uint32_t* lpos,
+                                const uint32_t* list, const uint32_t* cstart,
+                                const uint32_t* cpos, const double* cq, libhalo_halos h,
+                                uint8_t* status) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t F = nseg[0];
+  if (g >= F) return;
+  const uint32_t a0 = seg_start[g], a1 = (g + 1 < F) ? seg_start[g + 1] : S;
+  if (a1 - a0 <= kMergeWave) return;
+  for (uint32_t e = lpos[a0]; e < lpos[a1]; ++e) {
+    const uint32_t t = list[e];
+    double bq = INFINITY;
+    uint32_t best = 0xFFFFFFFFu;
+    for (uint32_t k = cstart[t]; k < cstart[t + 1]; ++k) {
+      const uint32_t pa = cpos[k];
+      if (!status[pa]) continue;
+      const uint32_t a = ord[pa];
+      const double q = cq[k];
+      if (q < bq || (q == bq && a < best)) {
+        bq = q;
+        best = a;
+      }
+    }
+    if (best != 0xFFFFFFFFu) {
+      h.merged_into[ord[t]] = (int32_t)best;
+      status[t] = 0;
+    }
+  }
+}
+
 // Pairs (ancestor node, merged halo) of every leaf.
 __global__ void k_pair_count(const libhalo_halos h, const libhalo_nodes nd, uint32_t S,
                              uint32_t* cnt) {
@@ -365,13 +473,23 @@ struct Metric {
   const double* vxs;
   const double* vys;
   const double* vzs;
-  const double* sv2;
-  const double* vmax2;
+  const double* ird;  // cdyn / v_max^2 = 1 / r_dyn^2 of the seed's current particles
+  const double* isv;  // 1 / sigma_v^2 (floored at 1e-300)
 };
+
+// The Eq. 3 weights of every seed from its current sigma_v^2 and v_max^2,
+// once per level (the same expressions the per-particle loop would evaluate).
+__global__ void k_metric_weights(const double* sv2, const double* vm2, uint32_t S, double cdyn,
+                                 double* ird, double* isv) {
+  uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= S) return;
+  ird[h] = cdyn / vm2[h];
+  isv[h] = 1.0 / fmax(sv2[h], 1e-300);
+}
 
 template <class T>
 __global__ void k_assign_level(const T* x, const T* y, const T* z, const float* vx,
-                               const float* vy, const float* vz, double box, double cdyn,
+                               const float* vy, const float* vz, double box,
                                const uint32_t* own, const uint32_t* okey, uint32_t q0,
                                uint32_t q1, const uint32_t* soff, const uint32_t* ids,
                                Metric mt, int32_t* halo_of) {
@@ -386,8 +504,7 @@ __global__ void k_assign_level(const T* x, const T* y, const T* z, const float* 
     double bd = INFINITY;
     for (uint32_t t = s0; t < s1; ++t) {
       const uint32_t h = ids[t];
-      const double ird = cdyn / mt.vmax2[h];
-      const double isv = 1.0 / fmax(mt.sv2[h], 1e-300);
+      const double ird = mt.ird[h], isv = mt.isv[h];
       double dx = min_image(px - mt.xs[h], box), dy = min_image(py - mt.ys[h], box),
              dz = min_image(pz - mt.zs[h], box);
       double ux = ux0 - mt.vxs[h], uy = uy0 - mt.vys[h], uz = uz0 - mt.vzs[h];
@@ -525,10 +642,14 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
   struct W {
     uint32_t *flag, *pos, *dcnt, *stmp, *cnt, *seg_start, *kept, *pcnt, *poff;
     int32_t* node_seed;
-    double *sx2, *sv2, *cur_sv2, *cur_vm2;
+    double *sx2, *sv2, *cur_sv2, *cur_vm2, *ird, *isv;
     unsigned long long *k64a, *k64b, *pk0, *pk1, *vm;
     uint32_t *va, *vb, *pv0, *pv1, *pflag, *ppos, *soff, *ids, *ocnt, *iflag, *ipos;
     uint32_t *ok0, *ov0, *ok1, *ov1, *ooff, *lstart, *lmulti, *cand, *na;
+    uint32_t *mc_cnt, *mc_start, *mc_flag, *mc_lpos, *mc_list, *mc_pos;
+    double* mc_q;
+    uint8_t* mc_status;
+    int64_t mc_cap;
     void *rtmp, *rtmp2;
     I128* acc;
     RadialBufs rb;
@@ -549,6 +670,15 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
     w.vb = A.take<uint32_t>(K2);
     w.seg_start = A.take<uint32_t>(K2);
     w.kept = A.take<uint32_t>(K2);
+    w.mc_cnt = A.take<uint32_t>(K2);
+    w.mc_start = A.take<uint32_t>(K2 + 1);
+    w.mc_flag = A.take<uint32_t>(K2);
+    w.mc_lpos = A.take<uint32_t>(K2 + 1);
+    w.mc_list = A.take<uint32_t>(K2);
+    w.mc_status = A.take<uint8_t>(K2);
+    w.mc_cap = 8 * K2 + 4096;  // candidate pairs; more falls back to the visit
+    w.mc_pos = A.take<uint32_t>(w.mc_cap);
+    w.mc_q = A.take<double>(w.mc_cap);
     w.rtmp = A.take<char>(radix_tmp_bytes(std::max<int64_t>(NPmax, 1)));
     w.pcnt = A.take<uint32_t>(K2);
     w.poff = A.take<uint32_t>(K2);
@@ -574,6 +704,8 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
     w.cand = A.take<uint32_t>(K2);
     w.cur_sv2 = A.take<double>(K2);
     w.cur_vm2 = A.take<double>(K2);
+    w.ird = A.take<double>(K2);
+    w.isv = A.take<double>(K2);
     w.acc = A.take<I128>(4 * K2);
     w.vm = A.take<unsigned long long>(K2);
     w.na = A.take<uint32_t>(K2);
@@ -603,8 +735,29 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
   const uint32_t F = readu(dcnt + 1, 1);
   k_merge<<<blocks_for((int64_t)F * 64, TB), TB, 0, s>>>(ord, seg_start, dcnt + 1, S, box,
                                                          P.merge_q2, h, st, kept);
-  k_merge_big<<<std::min<int64_t>(blocks_for(F, kMergeTB), 256), kMergeTB, 0, s>>>(
-      ord, seg_start, dcnt + 1, S, box, P.merge_q2, h, st, kept);
+  {
+    // big groups: candidate lists in parallel, then an in-order resolution
+    k_merge_cand<false><<<blocks_for(S, TB), TB, 0, s>>>(ord, flag, pos, seg_start, dcnt + 1, S,
+                                                         box, P.merge_q2, h, st, w.mc_cnt,
+                                                         nullptr, nullptr, nullptr);
+    exclusive_scan<uint32_t>(w.mc_cnt, w.mc_start, S, w.mc_start + S, stmp, s);
+    const uint32_t NC = readu(w.mc_start + S, 8);
+    if ((int64_t)NC <= w.mc_cap) {
+      k_merge_cand<true><<<blocks_for(S, TB), TB, 0, s>>>(ord, flag, pos, seg_start, dcnt + 1,
+                                                          S, box, P.merge_q2, h, st, nullptr,
+                                                          w.mc_start, w.mc_pos, w.mc_q);
+      k_merge_big_init<<<blocks_for(S, TB), TB, 0, s>>>(ord, flag, pos, seg_start, dcnt + 1, S,
+                                                        w.mc_cnt, h, w.mc_status, w.mc_flag);
+      exclusive_scan<uint32_t>(w.mc_flag, w.mc_lpos, S, w.mc_lpos + S, stmp, s);
+      k_merge_list<<<blocks_for(S, TB), TB, 0, s>>>(w.mc_flag, w.mc_lpos, S, w.mc_list);
+      k_merge_resolve<<<blocks_for(F, TB), TB, 0, s>>>(ord, seg_start, dcnt + 1, S, w.mc_lpos,
+                                                       w.mc_list, w.mc_start, w.mc_pos,
+                                                       w.mc_q, h, w.mc_status);
+    } else {
+      k_merge_big<<<std::min<int64_t>(blocks_for(F, kMergeTB), 256), kMergeTB, 0, s>>>(
+          ord, seg_start, dcnt + 1, S, box, P.merge_q2, h, st, kept);
+    }
+  }
 
   // ---- seed sets per node
   uint32_t *pcnt = w.pcnt, *poff = w.poff;
@@ -655,7 +808,7 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
   I128* acc = w.acc;
   unsigned long long* vm = w.vm;
   RadialBufs& rb = w.rb;
-  Metric cur{h.xs, h.ys, h.zs, h.vxs, h.vys, h.vzs, cur_sv2, cur_vm2};
+  Metric cur{h.xs, h.ys, h.zs, h.vxs, h.vys, h.vzs, w.ird, w.isv};
   for (int lev = maxlev; lev >= 0; --lev) {
     const uint32_t k0 = hls[lev], k1 = hls[lev + 1];
     const uint32_t q0 = hoo[k0], q1 = hoo[k1];  // own particles of this level
@@ -674,10 +827,12 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
       }
       radial_sort(pos_dtype, x, y, z, box, h.xs, h.ys, h.zs, m, S, rb, s);
       radial_sigma_vmax(vx, vy, vz, m, S, rb, Gm, eps2, acc, vm, cur_sv2, cur_vm2, s);
+      k_metric_weights<<<blocks_for(S, TB), TB, 0, s>>>(cur_sv2, cur_vm2, S, cdyn, w.ird,
+                                                        w.isv);
     }
     if (q1 > q0)
       k_assign_level<T><<<blocks_for(q1 - q0, TB), TB, 0, s>>>(
-          x, y, z, vx, vy, vz, box, cdyn, own, okey, q0, q1, soff, ids, cur, halo_of);
+          x, y, z, vx, vy, vz, box, own, okey, q0, q1, soff, ids, cur, halo_of);
   }
 
   // ---- final metric of every halo from all its particles

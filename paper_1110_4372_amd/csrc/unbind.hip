@@ -321,16 +321,6 @@ __device__ __forceinline__ F wave_sum1(F r) {
 // exchanges sum the lanes l ^ 1, l ^ 2, l ^ 4.  Lane l with l & 7 == 0 returns
 // the sum of d[u] with u = 4 b3 + 2 b4 + b5 (b3..b5 bits 3..5 of l).  The tree
 // is fixed, so the result is deterministic.
-__device__ __forceinline__ void swap_halves32(uint32_t& x, uint32_t& y) {
-  const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
-  x = r[0];
-  y = r[1];
-}
-__device__ __forceinline__ void swap_halves16(uint32_t& x, uint32_t& y) {
-  const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
-  x = r[0];
-  y = r[1];
-}
 template <void (*SW)(uint32_t&, uint32_t&)>
 __device__ __forceinline__ double swap_add_f64(double x, double y) {
   unsigned long long ux = (unsigned long long)__double_as_longlong(x);
@@ -376,12 +366,6 @@ __device__ __forceinline__ float wave_sum8_f32(const float* d) {
   r = r + lane_xor_f32<lane_xor2>(r);
   r = r + lane_xor_f32<lane_xor4>(r);
   return r;
-}
-
-// The value index whose wave sum lane l holds after wave_sum8_f64/f32.
-__device__ __forceinline__ uint32_t sum8_index() {
-  const uint32_t l = threadIdx.x & 63u;
-  return (((l >> 3) & 1u) << 2) | (((l >> 4) & 1u) << 1) | ((l >> 5) & 1u);
 }
 
 #define HALO_XORS(F, f)                                                                   \
@@ -474,7 +458,7 @@ __device__ __forceinline__ void pot_sym_f64(const double* __restrict__ ux,
                                             const double* y, const double* z, double eps2,
                                             double* A, unsigned long long* jlo,
                                             unsigned long long* jhi) {
-  const uint32_t l = threadIdx.x & 63u, ul = sum8_index();
+  const uint32_t l = threadIdx.x & 63u, ul = swap8_index();
   uint32_t j = j0;
   for (; j + 8 <= j1; j += 8) {
     double bx[8], by[8], bz[8], tj[8];
@@ -649,7 +633,7 @@ __device__ __forceinline__ void pot_sym_f32(const float* __restrict__ fx,
                                             const float* y, const float* z, float eps2,
                                             Comp32* A, unsigned long long* jlo,
                                             unsigned long long* jhi) {
-  const uint32_t l = threadIdx.x & 63u, ul = sum8_index();
+  const uint32_t l = threadIdx.x & 63u, ul = swap8_index();
   uint32_t j = j0;
   while (j < j1) {
     const uint32_t je = min(j + 64u, j1);
