@@ -530,11 +530,17 @@ __global__ void __launch_bounds__(TB)
       __syncthreads();
       const uint32_t lj = jt + threadIdx.x;
       troot[threadIdx.x] = lj < j1 ? uf_find(par, lpos[first + lj]) : 0xFFFFFFFFu;
+      if (ok) ri = uf_find(par, mi);  // a current root: more blocks can be skipped
       __syncthreads();
       const uint32_t te = min(jt + TB, j1);
       for (uint32_t jb = jt; jb < te; jb += 64u) {
         if (jb < w0) continue;  // every j of the block is below the wave's i
         const uint32_t je = min(jb + 64u, te);
+        // a block whose particles all share the root of all the wave's
+        // particles holds no pair that can join two sets
+        const uint32_t r0 = __builtin_amdgcn_readfirstlane(ri);
+        const uint32_t q = jb + (threadIdx.x & 63u);
+        if (__all((!ok || ri == r0) && (q >= je || troot[q - jt] == r0))) continue;
         if (jb == w0)
           fof_block<true>(cxi, S, first, jb, je, li, ok, a, l2, lpos, mi, ri, par,
                           troot + (jb - jt));
