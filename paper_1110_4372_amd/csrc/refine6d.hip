@@ -231,29 +231,31 @@ __global__ void k_norm6(const T* x, const T* y, const T* z, const float* vx, con
 // ------------------------------------------------------------ pair kernels --
 // Nearest-neighbour work unit: 256 particles of a node (a block, four waves
 // of 64) against one j-chunk.  The chunk is a multiple of 256 particles, at
-// least 1024 and at most kSymJMax, so a chunk's j-minima fit in LDS.
-__host__ __device__ __forceinline__ uint32_t nn_chunk(uint32_t n) {
+// least jmin (kNNJ, or kNNJSmall on a small level, where more and shorter
+// units spread its few nodes over more of the chip) and at most kSymJMax, so a
+// chunk's j-minima fit in LDS.
+__host__ __device__ __forceinline__ uint32_t nn_chunk(uint32_t n, uint32_t jmin) {
   uint32_t c = (n + 63u) / 64u;
   c = (c + 255u) & ~255u;
-  return c < (uint32_t)kNNJ ? (uint32_t)kNNJ : (c > kSymJMax ? kSymJMax : c);
+  return c < jmin ? jmin : (c > kSymJMax ? kSymJMax : c);
 }
 
-__host__ __device__ __forceinline__ uint32_t nn_units(uint32_t n) {
-  const uint32_t J = nn_chunk(n);
+__host__ __device__ __forceinline__ uint32_t nn_units(uint32_t n, uint32_t jmin) {
+  const uint32_t J = nn_chunk(n, jmin);
   return ((n + 255u) / 256u) * ((n + J - 1) / J);
 }
 
 // Units of the nodes selected by `which`: 0 = all-pairs nodes, 1 = nodes whose
 // grid search fell back.
 __global__ void k_pair_items(const uint32_t* count, const double* prm, const uint32_t* gstate,
-                             uint32_t K, int which, uint32_t* items) {
+                             uint32_t K, int which, uint32_t jmin, uint32_t* items) {
   uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   const uint32_t n = count[k];
   const bool active = prm[12 * (size_t)k + 11] != 0.0;
   const uint32_t g = gstate[k];
   const bool sel = which == 0 ? g == 0u : g == 2u;
-  items[k] = (active && sel) ? nn_units(n) : 0u;
+  items[k] = (active && sel) ? nn_units(n, jmin) : 0u;
 }
 
 
@@ -348,7 +350,7 @@ __device__ __forceinline__ float nn_sym_span(const float* __restrict__ xi, size_
 __global__ void __launch_bounds__(TB)
     k_nn(const float* __restrict__ xi, size_t S, LevelNodes nd, uint32_t K,
          const uint32_t* __restrict__ woff, uint32_t kb, uint32_t ke, uint32_t* ctr,
-         uint32_t* D) {
+         uint32_t chmin, uint32_t* D) {
   __shared__ uint32_t jmin[kSymJMax];
   __shared__ uint32_t su;
   const uint32_t inf = 0x7F800000u;
@@ -368,7 +370,7 @@ __global__ void __launch_bounds__(TB)
     const uint32_t k = seg_of(woff, K, u);
     const uint32_t local = u - woff[k];
     const uint32_t first = nd.first[k], n = nd.count[k];
-    const uint32_t J = nn_chunk(n);
+    const uint32_t J = nn_chunk(n, chmin);
     const uint32_t nb = (n + 255u) / 256u;
     const uint32_t c = local / nb, b = local - c * nb;
     const uint32_t j0 = c * J, j1 = min(j0 + J, n);
@@ -430,11 +432,11 @@ __global__ void k_link_nodes(LevelNodes nd, const uint32_t* pos, uint32_t K, Lev
   cn.count[k] = b - a;
 }
 
-__global__ void k_link_items(const uint32_t* ccount, uint32_t K, uint32_t* items) {
+__global__ void k_link_items(const uint32_t* ccount, uint32_t K, uint32_t pj, uint32_t* items) {
   uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   const uint32_t n = ccount[k];
-  items[k] = ((n + kPairI - 1) / kPairI) * ((n + kPairJ - 1) / kPairJ);
+  items[k] = ((n + kPairI - 1) / kPairI) * ((n + pj - 1) / pj);
 }
 
 // One block of at most 64 j (node-local [jb, je)) against the wave's particles:
@@ -492,7 +494,7 @@ __global__ void __launch_bounds__(TB)
     k_fof6(const float* __restrict__ cxi, size_t S, LevelNodes cn,
            const uint32_t* __restrict__ lpos, uint32_t K, const uint32_t* __restrict__ woff,
            uint32_t kb, uint32_t ke, uint32_t* ctr, const float* __restrict__ ell2,
-           uint32_t* par) {
+           uint32_t pj, uint32_t* par) {
   __shared__ uint32_t troot[TB];
   __shared__ uint32_t su;
   const uint32_t u0 = woff[kb], u1 = woff[ke];
@@ -511,10 +513,10 @@ __global__ void __launch_bounds__(TB)
     const uint32_t k = seg_of(woff, K, u);
     const uint32_t r = u - woff[k];
     const uint32_t first = cn.first[k], n = cn.count[k];
-    const uint32_t tj = (n + kPairJ - 1) / kPairJ;
+    const uint32_t tj = (n + pj - 1) / pj;
     const uint32_t it = r / tj, jc = r - it * tj;
     const uint32_t i0 = it * kPairI;
-    const uint32_t j0 = jc * kPairJ, j1 = min(n, j0 + kPairJ);
+    const uint32_t j0 = jc * pj, j1 = min(n, j0 + pj);
     if (j1 <= i0 + 1) continue;  // block-uniform: no pair with j > i
     const uint32_t li = i0 + threadIdx.x;
     const bool ok = li < n;
@@ -959,6 +961,10 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     // any grid is correct, and a deep level's few units need no 4096 blocks
     const unsigned pgrid = (unsigned)std::min<uint64_t>(
         kPersist, std::max<uint64_t>(256, 4 * (((uint64_t)Mi + 255) / 256)));
+    // pair-unit chunks: shorter on small levels
+    const bool small_level = Mi < kSmallLevel;
+    const uint32_t nnj = small_level ? kNNJSmall : (uint32_t)kNNJ;
+    const uint32_t pj = small_level ? kPairJSmall : (uint32_t)kPairJ;
     const int level0 = level == 0;
     k_zero_node_scratch<<<blocks_for(K, TB), TB, 0, s>>>(sc, K);
     k_mom_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, K, sc.wmom);
@@ -998,14 +1004,15 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     HALO_PROF(ctx, "grid_build", s,
               grid_build(gb, xi, S, nd, K, lnode, Mi, M, sc, P.f, rd.h + 8, s, D,
                          P.grid_min > 0 ? (uint32_t)P.grid_min : kGridMin));
-    k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, 0, sc.wpair);
+    k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, 0, nnj,
+                                                   sc.wpair);
     exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
     if (plain) {
       for (uint32_t k = 0; k < K; ++k) {
         uint32_t nn = hcount[k];
-        const unsigned g = nn_units(nn);
+        const unsigned g = nn_units(nn, nnj);
         HALO_PROF(ctx, "k_nn", s,
-                  k_nn<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, nullptr, D));
+                  k_nn<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, nullptr, nnj, D));
         if (nn <= (uint32_t)kSelSmall)
           HALO_PROF(ctx, "k_select_small", s,
                     k_select_small<<<1, TB, 0, s>>>(D, nd, k, k + 1, sc));
@@ -1013,7 +1020,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     } else {
       k_fill_u32<<<1, 64, 0, s>>>(dcnt + 8, 1, 0u);
       HALO_PROF(ctx, "k_nn", s,
-                k_nn<<<pgrid, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, D));
+                k_nn<<<pgrid, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, nnj, D));
       HALO_PROF(ctx, "k_select_small", s, k_select_small<<<K, TB, 0, s>>>(D, nd, 0, K, sc));
     }
     // 4. selection for big nodes (both forms: a handful of nodes)
@@ -1034,11 +1041,12 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     select_big();
     // grid nodes whose ell^2 exceeds their search radius: all-pairs again
     if (grid_check(gb, sc, lnode, Mi, D, rd.h + 8, s) > 0) {
-      k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, 1, sc.wpair);
+      k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, 1, nnj,
+                                                     sc.wpair);
       exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
       k_fill_u32<<<1, 64, 0, s>>>(dcnt + 8, 1, 0u);
       HALO_PROF(ctx, "k_nn", s,
-                k_nn<<<pgrid, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, D));
+                k_nn<<<pgrid, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, nnj, D));
       select_big();
     }
     // 5. 6D FOF: all-pairs nodes over their compacted linkable particles
@@ -1046,21 +1054,21 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     exclusive_scan<uint32_t>(cflag, crank, Mi, crank + Mi, stmp, s);
     k_link_gather<<<blocks_for(Mi, TB), TB, 0, s>>>(xi, S, cflag, crank, Mi, cxi, lpos);
     k_link_nodes<<<blocks_for(K, TB), TB, 0, s>>>(nd, crank, K, cnodes);
-    k_link_items<<<blocks_for(K, TB), TB, 0, s>>>(cnodes.count, K, sc.wpair);
+    k_link_items<<<blocks_for(K, TB), TB, 0, s>>>(cnodes.count, K, pj, sc.wpair);
     exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
     if (plain) {
       for (uint32_t k = 0; k < K; ++k) {
         const uint32_t nn = hcount[k];
-        const unsigned g = ((nn + kPairI - 1) / kPairI) * ((nn + kPairJ - 1) / kPairJ);
+        const unsigned g = ((nn + kPairI - 1) / kPairI) * ((nn + pj - 1) / pj);
         HALO_PROF(ctx, "k_fof6", s,
                   k_fof6<<<g, TB, 0, s>>>(cxi, S, cnodes, lpos, K, sc.wpair, k, k + 1, nullptr,
-                                          sc.ell2, par));
+                                          sc.ell2, pj, par));
       }
     } else {
       k_fill_u32<<<1, 64, 0, s>>>(dcnt + 8, 1, 0u);
       HALO_PROF(ctx, "k_fof6", s,
                 k_fof6<<<pgrid, TB, 0, s>>>(cxi, S, cnodes, lpos, K, sc.wpair, 0, K,
-                                               dcnt + 8, sc.ell2, par));
+                                               dcnt + 8, sc.ell2, pj, par));
     }
     HALO_PROF(ctx, "grid_fof", s, grid_fof(gb, sc, D, par, s));
     k_compress<<<blocks_for(Mi, TB), TB, 0, s>>>(par, Mi);

@@ -12,6 +12,9 @@ constexpr int kMomTile = 1024;       // particles per moment work item
 constexpr int kPairI = 256;          // i particles per pair work item
 constexpr int kPairJ = 2048;         // j particles per pair work item
 constexpr int kNNJ = 1024;           // minimum j-chunk of a nearest-neighbour unit
+constexpr uint32_t kSmallLevel = 262144;  // levels below this many particles use
+constexpr uint32_t kNNJSmall = 256;       //   these shorter chunks
+constexpr uint32_t kPairJSmall = 512;
 constexpr uint32_t kSymJMax = 4096;  // maximum j-chunk (its minima sit in LDS)
 constexpr int kSelSmall = 4096;      // nodes up to this size select in LDS
 constexpr int kSelTile = 4096;       // elements per big-node select item
