@@ -91,23 +91,6 @@ __global__ void k_rows(const unsigned long long* cell_key, int64_t ncell, int64_
   row_start[r] = (uint32_t)lo;
 }
 
-__device__ __forceinline__ int64_t find_cell(const unsigned long long* cell_key,
-                                             const uint32_t* row_start, int64_t row,
-                                             unsigned long long want) {
-  int64_t lo = row_start[row], hi = row_start[row + 1];
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    unsigned long long k = cell_key[mid];
-    if (k < want)
-      lo = mid + 1;
-    else if (k > want)
-      hi = mid;
-    else
-      return mid;
-  }
-  return -1;
-}
-
 // First cell of [lo, hi) whose key is >= want (keys ascend within a row).
 __device__ __forceinline__ uint32_t lower_cell(const unsigned long long* cell_key, uint32_t lo,
                                                uint32_t hi, unsigned long long want) {

@@ -97,7 +97,7 @@ size_t scan_tmp_elems(int64_t n) {
 template <class T>
 void exclusive_scan(const T* in, T* out, int64_t n, T* total, T* tmp, hipStream_t s) {
   if (n <= 0) {
-    if (total) hipMemsetAsync(total, 0, sizeof(T), s);
+    if (total) (void)hipMemsetAsync(total, 0, sizeof(T), s);
     return;
   }
   if (n <= kScanTile) {
