@@ -408,6 +408,10 @@ uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint3
   g.NB = 0;
   g.MB = 0;
   g.NT = 0;
+  if (Mi <= gmin) {  // no node of the level can exceed the threshold: no read-back needed
+    k_fill_u32<<<blocks_for(K, TB), TB, 0, s>>>(sc.gstate, K, 0u);
+    return 0;
+  }
   k_grid_classify<<<blocks_for(K, TB), TB, 0, s>>>(nd, K, sc, gmin, g.flag);
   exclusive_scan<uint32_t>(g.flag, g.pos, K, g.cnt, g.stmp, s);
   k_grid_list<<<blocks_for(K, TB), TB, 0, s>>>(g.flag, g.pos, K, nd, g);

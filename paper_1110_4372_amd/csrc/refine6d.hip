@@ -1038,7 +1038,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
         }
       }
     };
-    select_big();
+    if (Mi > (uint32_t)kSelSmall) select_big();  // else no node is above kSelSmall
     // grid nodes whose ell^2 exceeds their search radius: all-pairs again
     if (grid_check(gb, sc, lnode, Mi, D, rd.h + 8, s) > 0) {
       k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, 1, nnj,
