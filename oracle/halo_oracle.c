@@ -46,11 +46,15 @@ static double min_image(double d, double box) {
 
 static double sq3(double a, double b, double c) { return fma(c, c, fma(b, b, a * a)); }
 
-/* Nearest double of a 128-bit integer, by one fixed sequence of roundings. */
+/* Double of a 128-bit integer (an exact fixed-point sum), by one fixed
+ * sequence of roundings, within an ulp: the magnitude's two 64-bit words are
+ * each rounded once and combined by one fma, then the sign is applied. */
 static double i128_to_f64(i128 v) {
-  int64_t hi = (int64_t)(v >> 64);
-  uint64_t lo = (uint64_t)v;
-  return fma((double)hi, 18446744073709551616.0, (double)lo);
+  const int neg = v < 0;
+  const unsigned __int128 m = neg ? (unsigned __int128)(-v) : (unsigned __int128)v;
+  const uint64_t hi = (uint64_t)(m >> 64), lo = (uint64_t)m;
+  const double d = fma((double)hi, 18446744073709551616.0, (double)lo);
+  return neg ? -d : d;
 }
 
 int32_t orc_position_shift(double box) {

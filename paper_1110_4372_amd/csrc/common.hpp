@@ -163,10 +163,20 @@ __device__ __forceinline__ I128 i128_sqr(long long v) {
   return r;
 }
 
-// Nearest double of a 128-bit integer by one fixed sequence of roundings:
-// fma((double)hi, 2^64, (double)lo).
+// Double of a 128-bit integer by one fixed sequence of roundings, within an
+// ulp: the magnitude's words are converted (each correctly rounded) and
+// combined by one fma, then the sign is applied.  Converting the signed words
+// directly would cancel: a small negative value has hi = -1 and lo near 2^64,
+// whose rounding loses up to 2^10 units.
 __device__ __forceinline__ double i128_to_f64(I128 v) {
-  return __fma_rn((double)v.hi, 18446744073709551616.0, (double)v.lo);
+  const bool neg = v.hi < 0;
+  unsigned long long ml = v.lo, mh = (unsigned long long)v.hi;
+  if (neg) {  // two's complement negation of the 128-bit value
+    ml = ~ml + 1ull;
+    mh = ~mh + (ml == 0ull ? 1ull : 0ull);
+  }
+  const double d = __fma_rn((double)mh, 18446744073709551616.0, (double)ml);
+  return neg ? -d : d;
 }
 
 __device__ __forceinline__ I128 wave_sum_i128(I128 v) {

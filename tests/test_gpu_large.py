@@ -8,6 +8,8 @@ random sub-cubes (the box and the linking length of the full catalogue), and
 the GPU's output for the interior groups -- labels, node table, deepest node,
 halo table, halo_of and bound flags -- must match it exactly, as at the
 smaller sizes."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -43,41 +45,48 @@ def _subset_halos(hal, keep_fof, node_remap):
     return out, remap
 
 
-def test_c3_full_size_subcubes(H, orc):
-    from paper_1110_4372_amd import synth
-    note("c3 full size, oracle on sub-cubes")
-    cat = synth.make_catalog_device("c3", seed=0)
-    P = H.Particles.from_catalog(cat)
-    ctx = H.Halo(H.params_for_catalog(cat))
+def subcube_parity(H, orc, cat, P, prec, ncubes=6, seed=7):
+    """Runs the whole path on the GPU at full size, then the oracle on random
+    sub-cubes, and compares the interior groups exactly (properties to 1e-5
+    relative where the oracle's and the GPU's bound flags of the group agree).
+    Returns the numbers of groups, nodes and haloes checked."""
+    ctx = H.Halo(H.params_for_catalog(cat, prec=prec))
     fof = ctx.fof3d(P)
     nodes, deep = ctx.refine6d(P, fof)
+    torch.cuda.synchronize()
+    print("fof3d and refine6d done", flush=True)
     halos, hof = ctx.assign(P, nodes, deep)
     unb, bound, _ = ctx.unbind(P, halos, hof, want_phi=False)
+    props = ctx.props(P, nodes, halos, hof, bound)
     torch.cuda.synchronize()
-    glab = to_np(fof["label"]).astype(np.int64)
+    print("assign, unbind and props done", flush=True)
+    label_d = fof["label"].long()
+    gsize_d = torch.bincount(label_d, minlength=P.n)
     gn = gpu_nodes(nodes)
-    gdeep = to_np(deep).astype(np.int64)
     gh = {k: to_np(v) for k, v in halos.items()}
-    ghof = to_np(hof).astype(np.int64)
-    gbound = to_np(bound)
-    gsize = np.bincount(glab, minlength=glab.shape[0])
+    gp = {k: to_np(v) for k, v in props.items()}
 
     N, L = cat.n, cat.box
     ll = 0.28 * L / N ** (1.0 / 3.0)
-    rng = np.random.default_rng(7)
-    checked_groups = checked_nodes = checked_halos = 0
-    for corner in rng.random((6, 3)) * (L - CUBE):
+    rng = np.random.default_rng(seed)
+    checked_groups = checked_nodes = checked_halos = checked_props = 0
+    for corner in rng.random((ncubes, 3)) * (L - CUBE):
         lo, hi = corner, corner + CUBE
         inside = torch.ones(N, dtype=torch.bool, device=P.x.device)
         for a, t in enumerate((P.x, P.y, P.z)):
             inside &= (t >= float(lo[a])) & (t < float(hi[a]))
-        idx = to_np(torch.nonzero(inside).flatten()).astype(np.int64)
-        pos = np.stack([to_np(t[idx]) for t in (P.x, P.y, P.z)], 1)
-        vel = np.stack([to_np(t[idx]) for t in (P.vx, P.vy, P.vz)], 1)
+        idx_d = torch.nonzero(inside).flatten()
+        idx = to_np(idx_d).astype(np.int64)
         n_sub = idx.shape[0]
         print(f"cube at {np.round(lo, 1)}: {n_sub} particles", flush=True)
         if n_sub > MAX_SUB:
             continue  # part of a very large halo: the serial oracle would take minutes
+        pos = np.stack([to_np(t[idx_d]) for t in (P.x, P.y, P.z)], 1)
+        vel = np.stack([to_np(t[idx_d]) for t in (P.vx, P.vy, P.vz)], 1)
+        glab = to_np(label_d[idx_d]).astype(np.int64)
+        gdeep = to_np(deep[idx_d]).astype(np.int64)
+        ghof = to_np(hof[idx_d]).astype(np.int64)
+        gbound = to_np(bound[idx_d])
         # the oracle derives ll = b L / n^(1/3) from the particles it is given
         p = orc.make_params(L, cat.particle_mass, cat.softening,
                             b=0.28 * (n_sub / N) ** (1.0 / 3.0))
@@ -95,16 +104,17 @@ def test_c3_full_size_subcubes(H, orc):
             continue
         mem = np.isin(olab, interior)
         # FOF: same members, label = smallest input index
-        np.testing.assert_array_equal(glab[idx[mem]], idx[olab[mem]])
+        np.testing.assert_array_equal(glab[mem], idx[olab[mem]])
         keep = idx[interior]
-        np.testing.assert_array_equal(gsize[keep], sizes[interior])
+        np.testing.assert_array_equal(to_np(gsize_d[torch.from_numpy(keep).to(P.x.device)]),
+                                      sizes[interior])
         # hierarchy of the interior groups
         gsub, gremap = subset_nodes(gn, keep)
         osub, oremap = subset_nodes(o["nodes"], interior)
         for f in ("canon", "fof"):
             osub[f] = idx[osub[f].astype(np.int64)]
         assert_nodes_equal(gsub, osub)
-        np.testing.assert_array_equal(gremap[gdeep[idx[mem]]],
+        np.testing.assert_array_equal(gremap[gdeep[mem]],
                                       oremap[o["deepest"].astype(np.int64)[mem]])
         # haloes and memberships
         ghs, ghre = _subset_halos(gh, keep, gremap)
@@ -112,18 +122,53 @@ def test_c3_full_size_subcubes(H, orc):
         ohs, ohre = _subset_halos(oh, interior, oremap)
         ohs["fof"] = idx[ohs["fof"].astype(np.int64)]
         assert_halos_equal(ghs, ohs)
-        gm = ghof[idx[mem]]
+        gm = ghof[mem]
         om = o["halo_of"].astype(np.int64)[mem]
         np.testing.assert_array_equal(np.where(gm >= 0, ghre[gm], -1),
                                       np.where(om >= 0, ohre[om], -1))
         # bound flags wherever the energy lies outside the FP64 error band
         decided = energy_band(o, Po, 1e-9) & mem
-        np.testing.assert_array_equal(gbound[idx[decided]], o["bound"][decided])
+        np.testing.assert_array_equal(gbound[decided], o["bound"][decided])
+        # properties of the haloes whose group has the same flags on both sides
+        agree = [g for g in interior if np.array_equal(gbound[olab == g], o["bound"][olab == g])]
+        grows = np.nonzero(np.isin(gh["fof"].astype(np.int64), idx[agree]))[0]
+        orows = np.nonzero(np.isin(oh["fof"].astype(np.int64), agree))[0]
+        assert grows.shape[0] == orows.shape[0]
+        for k in ("px", "py", "pz", "vcx", "vcy", "vcz", "vbx", "vby", "vbz", "mvir", "rvir",
+                  "vmax", "voff"):
+            np.testing.assert_allclose(gp[k][grows], np.asarray(o["props"][k])[orows],
+                                       rtol=1e-5, atol=1e-9, err_msg=k)
+        np.testing.assert_array_equal(gp["n_bound"][grows],
+                                      np.asarray(o["props"]["n_bound"])[orows])
         checked_groups += interior.shape[0]
         checked_nodes += osub["parent"].shape[0]
         checked_halos += ohs["seed_node"].shape[0]
-    print(f"checked {checked_groups} groups, {checked_nodes} nodes, {checked_halos} halos")
-    assert checked_groups >= 20 and checked_halos >= 20
+        checked_props += grows.shape[0]
+    print(f"checked {checked_groups} groups, {checked_nodes} nodes, {checked_halos} halos, "
+          f"{checked_props} halo property rows", flush=True)
+    return checked_groups, checked_nodes, checked_halos, checked_props
+
+
+def test_c3_full_size_subcubes(H, orc):
+    from paper_1110_4372_amd import synth
+    note("c3 full size, oracle on sub-cubes")
+    cat = synth.make_catalog_device("c3", seed=0)
+    P = H.Particles.from_catalog(cat)
+    g, _, h, pr = subcube_parity(H, orc, cat, P, H.PREC_FP64)
+    assert g >= 20 and h >= 20 and pr >= 20
+
+
+@pytest.mark.skipif(not os.environ.get("HALO_FULL_1024"),
+                    reason="1024^3 at full size takes minutes of GPU time: set HALO_FULL_1024=1")
+def test_c5_full_size_subcubes(H, orc):
+    """The 1024^3 catalogue (1.07e9 particles) at full size on one GPU, mixed
+    precision, against the oracle on sub-cubes."""
+    from paper_1110_4372_amd import synth
+    note("c5 full size (mixed), oracle on sub-cubes")
+    cat = synth.make_catalog_device("c5", seed=0)
+    P = H.Particles.from_catalog(cat)
+    g, _, h, pr = subcube_parity(H, orc, cat, P, H.PREC_MIXED, ncubes=8, seed=11)
+    assert g >= 20 and h >= 20 and pr >= 20
 
 
 def test_c4_mixed_matches_fp64(H):

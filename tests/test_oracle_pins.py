@@ -161,6 +161,28 @@ def test_moments_constructed(orc):
     np.testing.assert_allclose(xi[:, 0], [-1, 1, 0, 0])
 
 
+def test_moments_small_negative_sums(orc):
+    """The exact fixed-point sums of Eq. 1 convert to their double within an
+    ulp also when they are small and negative (in two's complement the high
+    word is -1 and the low word near 2^64, which a word-wise conversion would
+    round away).  Velocities are quantised to 2^-24 km/s; positions to the
+    box's shift."""
+    from fractions import Fraction
+    box = 32.0
+    pos = np.array([[2.0, 5.0, 5.0], [2.0 - 2 ** -20, 5.0, 5.0], [2.0 - 2 ** -20, 5.0, 5.0]])
+    vel = np.array([[-1e-3, -3e-4, -7e-3]] * 3, np.float32)
+    P = particles(orc, pos, vel)
+    xi, mom = orc.node_normalise(orc.make_params(box, 1.0, 0.01), P, np.arange(3))
+    for c in range(3):
+        q = [round(Fraction(float(v)) * 2 ** 24) for v in vel[:, c]]
+        exact = Fraction(sum(q), 3) / 2 ** 24
+        assert mom[3 + c] < 0.0
+        assert abs(Fraction(mom[3 + c]) - exact) <= abs(exact) * Fraction(1, 2 ** 51)
+    # the centre: anchor 2.0 plus the mean offset -2^-19 / 3
+    exact_cx = Fraction(2) + Fraction(-2 * 2 ** -20) / 3
+    assert abs(Fraction(mom[0]) - exact_cx) <= Fraction(2, 2 ** 52)
+
+
 def test_moments_periodic_wrap_and_translation(orc):
     """Unwrapping by minimum image; dyadic translation is exact."""
     box = 32.0
