@@ -45,7 +45,7 @@ def _subset_halos(hal, keep_fof, node_remap):
     return out, remap
 
 
-def subcube_parity(H, orc, cat, P, prec, ncubes=6, seed=7):
+def subcube_parity(H, orc, cat, P, prec, ncubes=6, seed=7, cube=CUBE):
     """Runs the whole path on the GPU at full size, then the oracle on random
     sub-cubes, and compares the interior groups exactly (properties to 1e-5
     relative where the oracle's and the GPU's bound flags of the group agree).
@@ -70,8 +70,8 @@ def subcube_parity(H, orc, cat, P, prec, ncubes=6, seed=7):
     ll = 0.28 * L / N ** (1.0 / 3.0)
     rng = np.random.default_rng(seed)
     checked_groups = checked_nodes = checked_halos = checked_props = 0
-    for corner in rng.random((ncubes, 3)) * (L - CUBE):
-        lo, hi = corner, corner + CUBE
+    for corner in rng.random((ncubes, 3)) * (L - cube):
+        lo, hi = corner, corner + cube
         inside = torch.ones(N, dtype=torch.bool, device=P.x.device)
         for a, t in enumerate((P.x, P.y, P.z)):
             inside &= (t >= float(lo[a])) & (t < float(hi[a]))
@@ -155,6 +155,18 @@ def test_c3_full_size_subcubes(H, orc):
     cat = synth.make_catalog_device("c3", seed=0)
     P = H.Particles.from_catalog(cat)
     g, _, h, pr = subcube_parity(H, orc, cat, P, H.PREC_FP64)
+    assert g >= 20 and h >= 20 and pr >= 20
+
+
+def test_c4_full_size_subcubes(H, orc):
+    """256^3 plus the 5e6-particle cluster at full size, mixed precision, against
+    the oracle on sub-cubes of 20 Mpc/h (the catalogue is twice as dense as the
+    512^3 one; cubes cutting the cluster exceed the oracle's size limit)."""
+    from paper_1110_4372_amd import synth
+    note("c4 full size (mixed), oracle on sub-cubes")
+    cat = synth.make_catalog("c4", seed=0)
+    P = H.Particles.from_catalog(cat)
+    g, _, h, pr = subcube_parity(H, orc, cat, P, H.PREC_MIXED, ncubes=6, seed=5, cube=20.0)
     assert g >= 20 and h >= 20 and pr >= 20
 
 
