@@ -1278,3 +1278,198 @@ int orc_props(const orc_params* p, int64_t n, int pos_f64, const void* x, const 
   free(node_seed);
   return ORC_OK;
 }
+
+/* ------------------------------------------------ additional properties -- */
+
+/*
+ * Spherical-overdensity count (Section 3.5.2): the largest k such that every
+ * j <= k of the radially sorted particles encloses a mean density
+ * 3 j m / (4 pi r_j^3) of at least the threshold, tested as r_j^6 <= (j C)^2
+ * with C = 3 m / (4 pi rho_threshold).  Pinned: constructed radii with a
+ * known crossing; the virial threshold reproduces orc_props' M_vir.
+ */
+int64_t orc_so_count(int64_t nb, const double* r2, double C) {
+  int64_t k = 0;
+  for (int64_t j = 0; j < nb; ++j) {
+    double r6 = r2[j] * r2[j] * r2[j];
+    double jc = (double)(j + 1) * C;
+    if (r6 <= jc * jc)
+      k = j + 1;
+    else
+      break;
+  }
+  return k;
+}
+
+static void neumaier(double* s, double* c, double term) {
+  double u = *s + term;
+  if (fabs(*s) >= fabs(term))
+    *c += (*s - u) + term;
+  else
+    *c += (term - u) + *s;
+  *s = u;
+}
+
+/*
+ * Sums over one halo's set V (Section 3.5.4), positions dx relative to the
+ * halo centre and velocities v (km/s), in plain FP64 with Neumaier
+ * compensation:
+ *   0-2   sum of dx                      (centre of mass: X_off)
+ *   3-5   sum of dx x (v - v_bulk)       (angular momentum J / m)
+ *   6     sum of |v - v_bulk|^2          (kinetic energy 2T / m)
+ *   7     sum over pairs i < j of 1/sqrt(|dx_i - dx_j|^2 + eps^2)
+ *                                        (potential energy -U / (G m^2),
+ *                                         Plummer softening as in unbinding)
+ *   8-13  sums of dx_a dx_b over the own particles (own[i] != 0), in the
+ *         order xx, yy, zz, xy, xz, yz   (the mass distribution tensor of
+ *                                         Eq. 11 times the count)
+ *   14    number of own particles
+ * Pinned: rigid rotation (J and T in closed form), a regular tetrahedron
+ * and a brute-force pair sum by another route (U), a rotated axis-aligned
+ * point set (tensor), a shifted set (centre of mass).
+ */
+void orc_halo_sums(int64_t k, const double* dx, const double* dy, const double* dz,
+                   const double* vx, const double* vy, const double* vz, const uint8_t* own,
+                   const double* vb, double eps2, double* o) {
+  double s[ORC_EXTRA_NSUM], c[ORC_EXTRA_NSUM];
+  for (int q = 0; q < ORC_EXTRA_NSUM; ++q) s[q] = c[q] = 0.0;
+  for (int64_t i = 0; i < k; ++i) {
+    double rx = dx[i], ry = dy[i], rz = dz[i];
+    double ux = vx[i] - vb[0], uy = vy[i] - vb[1], uz = vz[i] - vb[2];
+    neumaier(&s[0], &c[0], rx);
+    neumaier(&s[1], &c[1], ry);
+    neumaier(&s[2], &c[2], rz);
+    neumaier(&s[3], &c[3], ry * uz - rz * uy);
+    neumaier(&s[4], &c[4], rz * ux - rx * uz);
+    neumaier(&s[5], &c[5], rx * uy - ry * ux);
+    neumaier(&s[6], &c[6], ux * ux + uy * uy + uz * uz);
+    for (int64_t j = i + 1; j < k; ++j) {
+      double ex = dx[j] - rx, ey = dy[j] - ry, ez = dz[j] - rz;
+      neumaier(&s[7], &c[7], 1.0 / sqrt(ex * ex + ey * ey + ez * ez + eps2));
+    }
+    if (own[i]) {
+      neumaier(&s[8], &c[8], rx * rx);
+      neumaier(&s[9], &c[9], ry * ry);
+      neumaier(&s[10], &c[10], rz * rz);
+      neumaier(&s[11], &c[11], rx * ry);
+      neumaier(&s[12], &c[12], rx * rz);
+      neumaier(&s[13], &c[13], ry * rz);
+      s[14] += 1.0;
+    }
+  }
+  for (int q = 0; q < ORC_EXTRA_NSUM; ++q) o[q] = s[q] + c[q];
+}
+
+/*
+ * The sums of orc_halo_sums for every kept halo, over the set V(h) = the
+ * bound particles of S(h) inside the virial radius, that is the k* innermost
+ * by distance from the halo centre (the particles that define M_vir; the
+ * paper computes J, the energies and T/|U| from the bound particles within
+ * the halo radius -- reading: S(h), as for the mass), with the centre and
+ * the bulk velocity of orc_props.  Own particles (halo_of == h) give the
+ * shape tensor: the paper excludes substructure there.  k_so: the SO count
+ * of each extra threshold so_rho[t] (Section 3.5.2), over the same radial
+ * order of the bound particles of S(h).  Merged seeds get zeros.
+ */
+int orc_props_extra(const orc_params* p, int64_t n, int pos_f64, const void* x, const void* y,
+                    const void* z, const float* vx, const float* vy, const float* vz,
+                    const orc_halos* h, int64_t ns, const int32_t* halo_of,
+                    const uint8_t* bound, const orc_props_out* pr, int32_t n_so,
+                    const double* so_rho, orc_extra_sums* o) {
+  if (n_so < 0 || (n_so > 0 && !so_rho)) return ORC_EINVAL;
+  for (int32_t t = 0; t < n_so; ++t)
+    if (!(so_rho[t] > 0.0)) return ORC_EINVAL;
+  int64_t* hoff = (int64_t*)calloc((size_t)ns + 1, sizeof(int64_t));
+  for (int64_t i = 0; i < n; ++i)
+    if (halo_of[i] >= 0) hoff[halo_of[i] + 1]++;
+  for (int64_t s = 0; s < ns; ++s) hoff[s + 1] += hoff[s];
+  int64_t* hmem = (int64_t*)malloc(sizeof(int64_t) * (size_t)(hoff[ns] ? hoff[ns] : 1));
+  {
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ns ? ns : 1));
+    for (int64_t s = 0; s < ns; ++s) fill[s] = hoff[s];
+    for (int64_t i = 0; i < n; ++i)
+      if (halo_of[i] >= 0) hmem[fill[halo_of[i]]++] = i;
+    free(fill);
+  }
+  const double m = p->particle_mass;
+  const double Cvir = (3.0 * m) / (4.0 * M_PI * p->rho_vir);
+  const double e2 = p->softening * p->softening;
+  ivec S = {0, 0, NULL}, stk = {0, 0, NULL};
+  halo_tree tree;
+  build_halo_tree(ns, h->host, &tree);
+  int rc = ORC_OK;
+  for (int64_t s = 0; s < ns; ++s) {
+    double sums[ORC_EXTRA_NSUM];
+    for (int q = 0; q < ORC_EXTRA_NSUM; ++q) sums[q] = 0.0;
+    int64_t kstar = 0;
+    for (int32_t t = 0; t < n_so; ++t) o->k_so[(size_t)t * (size_t)ns + (size_t)s] = 0;
+    if (h->merged_into[s] == s) {
+      const double c[3] = {pr->px[s], pr->py[s], pr->pz[s]};
+      const double vb[3] = {pr->vbx[s], pr->vby[s], pr->vbz[s]};
+      subtree_members(&tree, hoff, hmem, s, &S, &stk);
+      rad_t* r = (rad_t*)malloc(sizeof(rad_t) * (size_t)(S.n ? S.n : 1));
+      int64_t nb = 0;
+      for (int64_t q = 0; q < S.n; ++q) {
+        int64_t i = S.v[q];
+        if (!bound[i]) continue;
+        double dx = min_image(pos_at(x, pos_f64, i) - c[0], p->box);
+        double dy = min_image(pos_at(y, pos_f64, i) - c[1], p->box);
+        double dz = min_image(pos_at(z, pos_f64, i) - c[2], p->box);
+        r[nb].r2 = sq3(dx, dy, dz);
+        r[nb].idx = i;
+        nb++;
+      }
+      qsort(r, (size_t)nb, sizeof(rad_t), cmp_rad);
+      double* r2 = (double*)malloc(sizeof(double) * (size_t)(nb ? nb : 1));
+      for (int64_t j = 0; j < nb; ++j) r2[j] = r[j].r2;
+      kstar = orc_so_count(nb, r2, Cvir);
+      if ((double)kstar * m != pr->mvir[s]) rc = ORC_EINVAL; /* not orc_props' M_vir */
+      for (int32_t t = 0; t < n_so; ++t) {
+        double Ct = (3.0 * m) / (4.0 * M_PI * so_rho[t]);
+        o->k_so[(size_t)t * (size_t)ns + (size_t)s] = (uint32_t)orc_so_count(nb, r2, Ct);
+      }
+      int64_t kk = kstar ? kstar : 1;
+      double* d = (double*)malloc(sizeof(double) * 6 * (size_t)kk);
+      uint8_t* own = (uint8_t*)malloc((size_t)kk);
+      for (int64_t j = 0; j < kstar; ++j) {
+        int64_t i = r[j].idx;
+        d[j] = min_image(pos_at(x, pos_f64, i) - c[0], p->box);
+        d[kk + j] = min_image(pos_at(y, pos_f64, i) - c[1], p->box);
+        d[2 * kk + j] = min_image(pos_at(z, pos_f64, i) - c[2], p->box);
+        d[3 * kk + j] = (double)vx[i];
+        d[4 * kk + j] = (double)vy[i];
+        d[5 * kk + j] = (double)vz[i];
+        own[j] = halo_of[i] == s;
+      }
+      orc_halo_sums(kstar, d, d + kk, d + 2 * kk, d + 3 * kk, d + 4 * kk, d + 5 * kk, own, vb,
+                    e2, sums);
+      free(d);
+      free(own);
+      free(r2);
+      free(r);
+    }
+    o->sx[s] = sums[0];
+    o->sy[s] = sums[1];
+    o->sz[s] = sums[2];
+    o->jx[s] = sums[3];
+    o->jy[s] = sums[4];
+    o->jz[s] = sums[5];
+    o->t2[s] = sums[6];
+    o->uinv[s] = sums[7];
+    o->mxx[s] = sums[8];
+    o->myy[s] = sums[9];
+    o->mzz[s] = sums[10];
+    o->mxy[s] = sums[11];
+    o->mxz[s] = sums[12];
+    o->myz[s] = sums[13];
+    o->n_own[s] = (uint32_t)sums[14];
+    o->k[s] = (uint32_t)kstar;
+  }
+  free(S.v);
+  free(stk.v);
+  free(tree.off);
+  free(tree.ids);
+  free(hoff);
+  free(hmem);
+  return rc;
+}

@@ -14,6 +14,10 @@
  *                 (Section 3.5.3, Appendix B)
  *   orc_props     centre, virial SO mass and radius, vmax, core and bulk
  *                 velocity, core-bulk offset (Sections 3.5.1-3.5.4)
+ *   orc_props_extra  the sums behind the additional properties of Sections
+ *                 3.5.2 and 3.5.4 (further SO thresholds, centre-of-mass
+ *                 offset, angular momentum, energies, shape tensor); the
+ *                 properties themselves are derived from them in oracle.py
  *
  * All pointers are host pointers owned by the caller.  Return 0 on success,
  * a negative code on error (ORC_E*).
@@ -72,6 +76,19 @@ typedef struct {            /* halo properties */
   uint32_t *n_bound;
 } orc_props_out;
 
+typedef struct {            /* sums behind the additional properties, per halo */
+  double *sx, *sy, *sz;     /* sum of x - centre over the set V(h) */
+  double *jx, *jy, *jz;     /* sum of (x - centre) x (v - v_bulk) over V(h) */
+  double *t2;               /* sum of |v - v_bulk|^2 over V(h) */
+  double *uinv;             /* sum over pairs of V(h) of 1/sqrt(r^2 + eps^2) */
+  double *mxx, *myy, *mzz, *mxy, *mxz, *myz; /* sum of (x - centre)_a (x - centre)_b,
+                                                own particles of V(h) */
+  uint32_t *k, *n_own;      /* |V(h)|, own particles in V(h) */
+  uint32_t *k_so;           /* SO count per extra threshold, [n_so * n_halos] */
+} orc_extra_sums;
+
+#define ORC_EXTRA_NSUM 15
+
 #define ORC_NODE_LEAF 1u
 #define ORC_NODE_DEGENERATE 2u  /* zero position or velocity dispersion */
 #define ORC_NODE_WHOLE 4u       /* the only child would equal the node */
@@ -102,7 +119,17 @@ int orc_props(const orc_params* p, int64_t n, int pos_f64, const void* x,
               const orc_halos* halos, int64_t n_halos, const int32_t* halo_of,
               const uint8_t* bound, orc_props_out* out);
 
+int orc_props_extra(const orc_params* p, int64_t n, int pos_f64, const void* x,
+                    const void* y, const void* z, const float* vx, const float* vy,
+                    const float* vz, const orc_halos* halos, int64_t n_halos,
+                    const int32_t* halo_of, const uint8_t* bound, const orc_props_out* props,
+                    int32_t n_so, const double* so_rho, orc_extra_sums* out);
+
 /* Exposed single steps, for the pins. */
+void orc_halo_sums(int64_t k, const double* dx, const double* dy, const double* dz,
+                   const double* vx, const double* vy, const double* vz, const uint8_t* own,
+                   const double* vbulk, double eps2, double* sums15);
+int64_t orc_so_count(int64_t nb, const double* r2_sorted, double C);
 int orc_node_normalise(const orc_params* p, int64_t n_members, int pos_f64,
                        const void* x, const void* y, const void* z,
                        const float* vx, const float* vy, const float* vz,

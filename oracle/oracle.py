@@ -62,12 +62,21 @@ PROP_FIELDS = [("px", np.float64), ("py", np.float64), ("pz", np.float64),
                ("voff", np.float64), ("n_bound", np.uint32)]
 
 
+EXTRA_FIELDS = [("sx", np.float64), ("sy", np.float64), ("sz", np.float64),
+                ("jx", np.float64), ("jy", np.float64), ("jz", np.float64),
+                ("t2", np.float64), ("uinv", np.float64), ("mxx", np.float64),
+                ("myy", np.float64), ("mzz", np.float64), ("mxy", np.float64),
+                ("mxz", np.float64), ("myz", np.float64), ("k", np.uint32),
+                ("n_own", np.uint32), ("k_so", np.uint32)]
+
+
 def _struct(fields):
     return type("S", (C.Structure,), {"_fields_": [(n, _P) for n, _ in fields]})
 
 
-NodesS, HalosS, UnbS, PropsS = (_struct(NODE_FIELDS), _struct(HALO_FIELDS),
-                               _struct(UNB_FIELDS), _struct(PROP_FIELDS))
+NodesS, HalosS, UnbS, PropsS, ExtraS = (_struct(NODE_FIELDS), _struct(HALO_FIELDS),
+                                       _struct(UNB_FIELDS), _struct(PROP_FIELDS),
+                                       _struct(EXTRA_FIELDS))
 
 
 def _alloc(fields, cap):
@@ -104,6 +113,13 @@ def lib():
         L.orc_props.argtypes = [C.POINTER(Params), i64, i32, _P, _P, _P, _P, _P, _P,
                                 C.POINTER(NodesS), i64, C.POINTER(HalosS), i64, _P, _P,
                                 C.POINTER(PropsS)]
+        L.orc_props_extra.argtypes = [C.POINTER(Params), i64, i32, _P, _P, _P, _P, _P, _P,
+                                      C.POINTER(HalosS), i64, _P, _P, C.POINTER(PropsS), i32,
+                                      _P, C.POINTER(ExtraS)]
+        L.orc_halo_sums.argtypes = [i64, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double, _P]
+        L.orc_halo_sums.restype = None
+        L.orc_so_count.argtypes = [i64, _P, C.c_double]
+        L.orc_so_count.restype = C.c_int64
         L.orc_node_normalise.argtypes = [C.POINTER(Params), i64, i32, _P, _P, _P, _P, _P,
                                          _P, _P, _P, _P]
         L.orc_nn6d.argtypes = [i64, _P, _P]
@@ -242,6 +258,154 @@ def props(p: Params, P: Particles, nodes: dict, halos: dict, halo_of, bound):
     _check(lib().orc_props(C.byref(p), P.n, P.f64, *P.ptrs(), C.byref(NS), nn, C.byref(HS), nh,
                            halo_of.ctypes.data, bound.ctypes.data, C.byref(PS)), "props")
     return _trim(out, nh)
+
+
+def props_extra_sums(p: Params, P: Particles, halos: dict, halo_of, bound, pr: dict,
+                     so_rho=()):
+    """orc_props_extra: the per-halo sums behind the additional properties."""
+    nh = int(halos["seed_node"].shape[0])
+    halos = {k: np.ascontiguousarray(v) for k, v in halos.items()}
+    HS = _fill(HalosS, HALO_FIELDS, halos)
+    prc = {k: np.ascontiguousarray(v) for k, v in pr.items()}
+    PS = _fill(PropsS, PROP_FIELDS, prc)
+    so = np.ascontiguousarray(np.asarray(so_rho, dtype=np.float64).reshape(-1))
+    n_so = int(so.shape[0])
+    out = {n: np.zeros(max(nh, 1), dtype=t) for n, t in EXTRA_FIELDS if n != "k_so"}
+    out["k_so"] = np.zeros(max(nh * n_so, 1), dtype=np.uint32)
+    ES = _fill(ExtraS, EXTRA_FIELDS, out)
+    halo_of = np.ascontiguousarray(halo_of, dtype=np.int32)
+    bound = np.ascontiguousarray(bound, dtype=np.uint8)
+    _check(lib().orc_props_extra(C.byref(p), P.n, P.f64, *P.ptrs(), C.byref(HS), nh,
+                                 halo_of.ctypes.data, bound.ctypes.data, C.byref(PS), n_so,
+                                 so.ctypes.data if n_so else None, C.byref(ES)), "props_extra")
+    res = {k: v[:nh].copy() for k, v in out.items() if k != "k_so"}
+    res["k_so"] = out["k_so"][:nh * n_so].reshape(n_so, nh).copy()
+    return res
+
+
+def halo_sums(dx, dy, dz, vx, vy, vz, own, vbulk, eps2):
+    """orc_halo_sums on one explicit set (15 sums; see halo_oracle.c)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (dx, dy, dz, vx, vy, vz)]
+    own = np.ascontiguousarray(own, dtype=np.uint8)
+    vb = np.ascontiguousarray(vbulk, dtype=np.float64)
+    out = np.zeros(15, dtype=np.float64)
+    lib().orc_halo_sums(arrs[0].shape[0], *[a.ctypes.data for a in arrs], own.ctypes.data,
+                        vb.ctypes.data, float(eps2), out.ctypes.data)
+    return out
+
+
+def so_count(r2_sorted, C_thr: float) -> int:
+    r2 = np.ascontiguousarray(r2_sorted, dtype=np.float64)
+    return int(lib().orc_so_count(r2.shape[0], r2.ctypes.data, float(C_thr)))
+
+
+# Section 3.5.4, Eq. 5-6: radius of the NFW circular-velocity maximum in units
+# of R_s, rounded as the paper prints it.  The concentration is sought on the
+# branch c >= KLYPIN_X (R_max inside R_vir) and clamped to [KLYPIN_X,
+# KLYPIN_CMAX] (reading: the paper gives no range).
+KLYPIN_X = 2.1626
+KLYPIN_CMAX = 1.0e4
+
+
+def nfw_f(x):
+    """f(x) = ln(1 + x) - x / (1 + x) (Eq. 8)."""
+    return np.log1p(x) - x / (1.0 + x)
+
+
+def klypin_concentration(vmax: float, mvir: float, rvir: float, G: float) -> float:
+    """Eq. 7: c / f(c) = vmax^2 R_vir / (G M_vir) * X / f(X), X = KLYPIN_X,
+    inverted numerically (Brent's method); 0 for a halo without mass."""
+    from scipy.optimize import brentq
+    if not (mvir > 0.0 and rvir > 0.0 and vmax > 0.0):
+        return 0.0
+    rhs = vmax * vmax * rvir / (G * mvir) * KLYPIN_X / nfw_f(KLYPIN_X)
+
+    def g(c):
+        return c / nfw_f(c) - rhs
+
+    if g(KLYPIN_X) >= 0.0:
+        return KLYPIN_X
+    if g(KLYPIN_CMAX) <= 0.0:
+        return KLYPIN_CMAX
+    return float(brentq(g, KLYPIN_X, KLYPIN_CMAX, xtol=1e-14, rtol=1e-15, maxiter=1000))
+
+
+def spin_parameters(Jmag, T, U, M, R, G):
+    """Eq. 9 (Peebles): lambda = J sqrt(|E|) / (G M^2.5), E = T + U; Eq. 10
+    (Bullock): lambda_B = J / sqrt(2 G M^3 R).  Zero for M = 0."""
+    Jmag, T, U, M, R = (np.asarray(a, dtype=np.float64) for a in (Jmag, T, U, M, R))
+    ok = M > 0.0
+    Ms = np.where(ok, M, 1.0)
+    Rs = np.where(R > 0.0, R, 1.0)
+    lam = np.where(ok, Jmag * np.sqrt(np.abs(T + U)) / (G * Ms ** 2.5), 0.0)
+    lamb = np.where(ok & (R > 0.0), Jmag / np.sqrt(2.0 * G * Ms ** 3 * Rs), 0.0)
+    return lam, lamb
+
+
+def shape_from_tensor(mxx, myy, mzz, mxy, mxz, myz, n):
+    """Eq. 11: M_ab = (1/N) sum x_a x_b; its eigenvalues sorted a^2 >= b^2 >=
+    c^2 give b/a, c/a and the major axis vector A = a e_1, signed so that its
+    largest-magnitude component is positive.  Zeros when N = 0 or a = 0."""
+    if n <= 0:
+        return 0.0, 0.0, np.zeros(3)
+    M = np.array([[mxx, mxy, mxz], [mxy, myy, myz], [mxz, myz, mzz]], dtype=np.float64) / n
+    w, V = np.linalg.eigh(M)
+    w = np.maximum(w[::-1], 0.0)
+    V = V[:, ::-1]
+    if w[0] <= 0.0:
+        return 0.0, 0.0, np.zeros(3)
+    e = V[:, 0]
+    if e[int(np.argmax(np.abs(e)))] < 0.0:
+        e = -e
+    return float(np.sqrt(w[1] / w[0])), float(np.sqrt(w[2] / w[0])), np.sqrt(w[0]) * e
+
+
+def props_extra(p: Params, P: Particles, halos: dict, halo_of, bound, pr: dict, so_rho=()):
+    """The additional halo properties of Sections 3.5.2 and 3.5.4 from the
+    oracle's own centre, bulk velocity, M_vir, R_vir and v_max:
+      xoff        |centre of mass of V(h) - centre|
+      jx, jy, jz  angular momentum m sum (x - c) x (v - v_bulk) over V(h)
+      kin, pot    T = m/2 sum |v - v_bulk|^2 and U = -G m^2 sum_pairs
+                  1/sqrt(r^2 + eps^2) over V(h); t_u = T / |U| (0 if U = 0)
+      spin, spin_bullock  Eq. 9 and Eq. 10
+      c_klypin, rs_klypin Eq. 7-8, R_s = R_vir / c
+      b_to_a, c_to_a, ax, ay, az, n_shape  Eq. 11 over the own particles
+      m_so, r_so  [n_so, n_halos] SO mass and radius at each threshold
+    V(h) is the set that defines M_vir (the k* innermost bound particles of
+    S(h))."""
+    s = props_extra_sums(p, P, halos, halo_of, bound, pr, so_rho)
+    m, G = p.particle_mass, p.G
+    nh = int(halos["seed_node"].shape[0])
+    k = s["k"].astype(np.float64)
+    kk = np.maximum(k, 1.0)
+    com = np.stack([s["sx"], s["sy"], s["sz"]], 1) / kk[:, None]
+    out = {"xoff": np.where(k > 0, np.linalg.norm(com, axis=1), 0.0)}
+    J = m * np.stack([s["jx"], s["jy"], s["jz"]], 1)
+    out["jx"], out["jy"], out["jz"] = J[:, 0], J[:, 1], J[:, 2]
+    T = 0.5 * m * s["t2"]
+    U = -G * m * m * s["uinv"]
+    out["kin"], out["pot"] = T, U
+    out["t_u"] = np.where(U != 0.0, T / np.where(U != 0.0, np.abs(U), 1.0), 0.0)
+    out["spin"], out["spin_bullock"] = spin_parameters(np.linalg.norm(J, axis=1), T, U,
+                                                       pr["mvir"], pr["rvir"], G)
+    c = np.array([klypin_concentration(float(pr["vmax"][h]), float(pr["mvir"][h]),
+                                       float(pr["rvir"][h]), G) for h in range(nh)])
+    out["c_klypin"] = c
+    out["rs_klypin"] = np.where(c > 0, pr["rvir"] / np.where(c > 0, c, 1.0), 0.0)
+    ba, ca, A = np.zeros(nh), np.zeros(nh), np.zeros((nh, 3))
+    for h in range(nh):
+        ba[h], ca[h], A[h] = shape_from_tensor(s["mxx"][h], s["myy"][h], s["mzz"][h],
+                                               s["mxy"][h], s["mxz"][h], s["myz"][h],
+                                               int(s["n_own"][h]))
+    out["b_to_a"], out["c_to_a"] = ba, ca
+    out["ax"], out["ay"], out["az"] = A[:, 0], A[:, 1], A[:, 2]
+    out["n_shape"] = s["n_own"].copy()
+    so = np.asarray(so_rho, dtype=np.float64).reshape(-1)
+    ks = s["k_so"].astype(np.float64)
+    out["m_so"] = ks * m
+    out["r_so"] = np.cbrt(ks * (3.0 * m) / (4.0 * np.pi * so[:, None])) if so.size else ks
+    out["k"] = s["k"]
+    return out
 
 
 def node_normalise(p: Params, P: Particles, members: np.ndarray):
