@@ -11,6 +11,9 @@
  *   libhalo_unbind    single-pass unbinding                    (Section 3.5.3, App. B)
  *   libhalo_props     halo centre, SO mass/radius, vmax, core  (Sections 3.5.1-3.5.4)
  *                     and bulk velocity, core-bulk offset
+ *   libhalo_props_extra  libhalo_props plus further SO masses,  (Sections 3.5.2, 3.5.4,
+ *                     X_off, spins, T/|U|, Klypin concentration   Eqs. 5-11)
+ *                     and shape
  *
  * Conventions shared by every entry point
  *   - Particles are given in structure-of-arrays form in input order:
@@ -152,6 +155,25 @@ typedef struct {
   uint32_t* n_bound;       /* bound particles of S(h) */
 } libhalo_props_out;
 
+/* Additional halo properties per halo row (zeros for merged seeds), over
+ * V(h) = the bound particles of S(h) inside R_vir (the k* innermost, the set
+ * that defines M_vir), about the libhalo_props centre and bulk velocity. */
+#define LIBHALO_MAX_SO 8
+typedef struct {
+  double* xoff;            /* |centre of mass of V(h) - centre| */
+  double *jx, *jy, *jz;    /* angular momentum m sum (x - c) x (v - v_bulk) */
+  double *kin, *pot;       /* T = m/2 sum |v - v_bulk|^2; U = -G m^2 sum over
+                              pairs of 1/sqrt(r^2 + softening^2) */
+  double* t_u;             /* T / |U| (0 when U = 0) */
+  double *spin, *spin_bullock; /* Eq. 9 and Eq. 10 */
+  double *c_klypin, *rs_klypin; /* Eq. 7-8 concentration and R_vir / c */
+  double *b_to_a, *c_to_a; /* Eq. 11 axis ratios, own particles of V(h) */
+  double *ax, *ay, *az;    /* major axis a e_1, largest component positive */
+  uint32_t* n_shape;       /* own particles of V(h) */
+  double *m_so, *r_so;     /* [n_so * cap], threshold-major */
+  int64_t cap;             /* rows of each array above (m_so, r_so: n_so * cap) */
+} libhalo_props_extra_out;
+
 typedef struct libhalo_ctx libhalo_ctx;
 
 /* Create a context on HIP device `device` with parameters *p (host).
@@ -273,6 +295,32 @@ int libhalo_props(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
                   const float* vz, const libhalo_nodes* nodes, int64_t n_nodes,
                   const libhalo_halos* halos, int64_t n_halos, const int32_t* halo_of,
                   const uint8_t* bound, libhalo_props_out* out, void* stream);
+
+/*
+ * libhalo_props plus the additional properties of Sections 3.5.2 and 3.5.4
+ * (writes *out exactly as libhalo_props does, and *ext):
+ *  - m_so / r_so: SO mass and radius at each of n_so further thresholds
+ *    so_rho[t] (host array, same units as rho_vir, each > 0), by the same
+ *    first-downcrossing rule as M_vir over the bound particles of S(h);
+ *  - xoff: distance from the centre to the centre of mass of V(h);
+ *  - angular momentum, T, U and T/|U| of V(h) with the Plummer softening of
+ *    unbinding; spin (Eq. 9, E = T + U, M = M_vir) and spin_bullock (Eq. 10);
+ *  - c_klypin: root c >= 2.1626 of Eq. 7, clamped to [2.1626, 1e4] (2.1626
+ *    when v_max^2 R_vir / (G M_vir) lies below the branch), rs_klypin =
+ *    R_vir / c;
+ *  - the Eq. 11 tensor (1/N) sum x_a x_b over the halo's own particles in
+ *    V(h) (substructure excluded), positions about the centre: b/a, c/a from
+ *    its sorted eigenvalues a^2 >= b^2 >= c^2 and the major axis vector.
+ * The potential energy costs sum_h |V(h)|^2 / 2 pair terms (FP64, fixed-point
+ * sums independent of scheduling).  Errors: EINVAL (n_so outside
+ * [0, LIBHALO_MAX_SO], a threshold <= 0, null pointers, ext->cap < n_halos).
+ */
+int libhalo_props_extra(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
+                        const void* y, const void* z, const float* vx, const float* vy,
+                        const float* vz, const libhalo_nodes* nodes, int64_t n_nodes,
+                        const libhalo_halos* halos, int64_t n_halos, const int32_t* halo_of,
+                        const uint8_t* bound, libhalo_props_out* out, int n_so,
+                        const double* so_rho, libhalo_props_extra_out* ext, void* stream);
 
 #ifdef __cplusplus
 }

@@ -5,6 +5,7 @@
 
 #include "common.hpp"
 #include "fof3d.hpp"
+#include "extra.hpp"
 #include "stages.hpp"
 
 struct libhalo_ctx {
@@ -263,6 +264,40 @@ int libhalo_props(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, con
     HALO_CHECK(n_nodes >= 0 && n_halos >= 0, LIBHALO_EINVAL, "negative table size");
     halo::props(c, n, pos_dtype, x, y, z, vx, vy, vz, nodes, n_nodes, halos, n_halos, halo_of,
                 bound, out, (hipStream_t)stream);
+  });
+}
+
+int libhalo_props_extra(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
+                        const void* y, const void* z, const float* vx, const float* vy,
+                        const float* vz, const libhalo_nodes* nodes, int64_t n_nodes,
+                        const libhalo_halos* halos, int64_t n_halos, const int32_t* halo_of,
+                        const uint8_t* bound, libhalo_props_out* out, int n_so,
+                        const double* so_rho, libhalo_props_extra_out* ext, void* stream) {
+  return guarded(ctx, [&](halo::Ctx& c) {
+    HALO_CHECK(n >= 1 && n < 0xFFFFFFFFll, LIBHALO_EINVAL, "n must lie in [1, 2^32-1)");
+    HALO_CHECK(dtype_ok(pos_dtype), LIBHALO_EINVAL, "pos_dtype must be F32 or F64");
+    HALO_CHECK(x && y && z && vx && vy && vz && nodes && halos && halo_of && bound && out && ext,
+               LIBHALO_EINVAL, "null pointer argument");
+    HALO_CHECK(n_nodes >= 0 && n_halos >= 0, LIBHALO_EINVAL, "negative table size");
+    HALO_CHECK(n_so >= 0 && n_so <= LIBHALO_MAX_SO, LIBHALO_EINVAL,
+               "n_so must lie in [0, LIBHALO_MAX_SO]");
+    HALO_CHECK(n_so == 0 || so_rho, LIBHALO_EINVAL, "so_rho is null");
+    HALO_CHECK(ext->cap >= n_halos, LIBHALO_EINVAL, "ext->cap is below n_halos");
+    halo::ExtraArgs ea;
+    ea.n_so = n_so;
+    ea.ext = ext;
+    for (int t = 0; t < n_so; ++t) {
+      HALO_CHECK(so_rho[t] > 0.0 && std::isfinite(so_rho[t]), LIBHALO_EINVAL,
+                 "SO thresholds must be positive and finite");
+      ea.rho[t] = so_rho[t];
+    }
+    HALO_CHECK(ext->xoff && ext->jx && ext->jy && ext->jz && ext->kin && ext->pot && ext->t_u &&
+                   ext->spin && ext->spin_bullock && ext->c_klypin && ext->rs_klypin &&
+                   ext->b_to_a && ext->c_to_a && ext->ax && ext->ay && ext->az &&
+                   ext->n_shape && (n_so == 0 || (ext->m_so && ext->r_so)),
+               LIBHALO_EINVAL, "null output array in ext");
+    halo::props(c, n, pos_dtype, x, y, z, vx, vy, vz, nodes, n_nodes, halos, n_halos, halo_of,
+                bound, out, (hipStream_t)stream, &ea);
   });
 }
 

@@ -9,6 +9,7 @@
 // fixed-point sums).
 #include <cmath>
 
+#include "extra.hpp"
 #include "primitives.hpp"
 #include "radial.hpp"
 #include "stages.hpp"
@@ -214,7 +215,7 @@ void props(Ctx& ctx, int64_t n, int pos_dtype, const void* x, const void* y, con
            const float* vx, const float* vy, const float* vz, const libhalo_nodes* nodes,
            int64_t n_nodes, const libhalo_halos* halos, int64_t n_halos,
            const int32_t* halo_of, const uint8_t* bound, libhalo_props_out* out,
-           hipStream_t s) {
+           hipStream_t s, const ExtraArgs* extra) {
   const libhalo_params& P = ctx.p;
   const libhalo_nodes& nd = *nodes;
   const libhalo_halos& h = *halos;
@@ -247,6 +248,7 @@ void props(Ctx& ctx, int64_t n, int pos_dtype, const void* x, const void* y, con
   HALO_HIP(hipStreamSynchronize(s));
   const uint32_t m = hb[0];
   RadialBufs rb;
+  ExtraBufs eb{};
   carve_workspace(ctx, [&](Arena& A) {
     w.mn = A.take<uint32_t>(NN + 2);
     w.mx = A.take<uint32_t>(NN + 2);
@@ -265,6 +267,7 @@ void props(Ctx& ctx, int64_t n, int pos_dtype, const void* x, const void* y, con
     w.acc = A.take<I128>(6ull * (S + 2));
     w.vm = A.take<unsigned long long>(S + 2);
     rb = radial_take(A, std::max<uint32_t>(m, 1), S + 2);
+    if (extra) eb = extra_take(A, S, m, extra->n_so);
   });
   // the second carve may have moved the workspace: redo the pair offsets
   k_chain_count<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, bound, h, (uint32_t)n, w.cnt);
@@ -287,6 +290,9 @@ void props(Ctx& ctx, int64_t n, int pos_dtype, const void* x, const void* y, con
   k_prop_out<<<blocks_for(S, TB), TB, 0, s>>>(h, S, rb.start, rb.s_pidx, vx, vy, vz, w.kstar,
                                               w.rvir, w.acc, w.vm, w.ncore, w.cx, w.cy, w.cz,
                                               P.particle_mass, Gm, *out);
+  if (extra)
+    props_extra_run(ctx, *extra, eb, pos_dtype, x, y, z, vx, vy, vz, halo_of, h, S, rb, m,
+                    w.kstar, *out, s);
   HALO_HIP(hipStreamSynchronize(s));
 }
 

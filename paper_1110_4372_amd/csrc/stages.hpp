@@ -3,6 +3,7 @@
 #include "common.hpp"
 
 namespace halo {
+struct ExtraArgs;
 void refine6d(Ctx& ctx, int64_t n, int pos_dtype, const void* x, const void* y, const void* z,
               const float* vx, const float* vy, const float* vz, const uint32_t* perm,
               const uint32_t* grp_first, const uint32_t* grp_count, int64_t n_groups,
@@ -19,5 +20,5 @@ void props(Ctx& ctx, int64_t n, int pos_dtype, const void* x, const void* y, con
            const float* vx, const float* vy, const float* vz, const libhalo_nodes* nodes,
            int64_t n_nodes, const libhalo_halos* halos, int64_t n_halos,
            const int32_t* halo_of, const uint8_t* bound, libhalo_props_out* out,
-           hipStream_t s);
+           hipStream_t s, const ExtraArgs* extra = nullptr);
 }  // namespace halo

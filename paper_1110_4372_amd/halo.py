@@ -84,6 +84,15 @@ PROP_FIELDS = [("px", torch.float64), ("py", torch.float64), ("pz", torch.float6
                ("mvir", torch.float64), ("rvir", torch.float64), ("vmax", torch.float64),
                ("voff", torch.float64), ("n_bound", torch.int32)]
 
+EXTRA_FIELDS = [("xoff", torch.float64), ("jx", torch.float64), ("jy", torch.float64),
+                ("jz", torch.float64), ("kin", torch.float64), ("pot", torch.float64),
+                ("t_u", torch.float64), ("spin", torch.float64), ("spin_bullock", torch.float64),
+                ("c_klypin", torch.float64), ("rs_klypin", torch.float64),
+                ("b_to_a", torch.float64), ("c_to_a", torch.float64), ("ax", torch.float64),
+                ("ay", torch.float64), ("az", torch.float64), ("n_shape", torch.int32),
+                ("m_so", torch.float64), ("r_so", torch.float64)]
+MAX_SO = 8
+
 _P = C.c_void_p
 
 
@@ -98,12 +107,13 @@ NodesS = _struct(NODE_FIELDS, True)
 HalosS = _struct(HALO_FIELDS, True)
 UnbS = _struct(UNB_FIELDS, False)
 PropsS = _struct(PROP_FIELDS, False)
+ExtraS = _struct(EXTRA_FIELDS, True)
 
 # Exported symbols (the C ABI of include/libhalo.h).
 SYMBOLS = ["libhalo_ctx_create", "libhalo_ctx_destroy", "libhalo_last_error",
            "libhalo_set_params", "libhalo_version", "libhalo_profile", "libhalo_profile_reset",
            "libhalo_profile_read", "libhalo_fof3d", "libhalo_refine6d", "libhalo_assign",
-           "libhalo_unbind", "libhalo_props"]
+           "libhalo_unbind", "libhalo_props", "libhalo_props_extra"]
 
 _lib = None
 
@@ -136,6 +146,9 @@ def load_library(path: str = LIB_PATH):
                                  _P, _P, _P, C.POINTER(UnbS), _P]
     L.libhalo_props.argtypes = [_P, i64, i32, _P, _P, _P, _P, _P, _P, C.POINTER(NodesS), i64,
                                 C.POINTER(HalosS), i64, _P, _P, C.POINTER(PropsS), _P]
+    L.libhalo_props_extra.argtypes = [_P, i64, i32, _P, _P, _P, _P, _P, _P, C.POINTER(NodesS),
+                                      i64, C.POINTER(HalosS), i64, _P, _P, C.POINTER(PropsS),
+                                      i32, _P, C.POINTER(ExtraS), _P]
     _lib = L
     return L
 
@@ -320,6 +333,33 @@ class Halo:
                                          C.byref(HS), nh, _ptr(halo_of), _ptr(bound),
                                          C.byref(PS), _stream()))
         return {n: t[:nh] for n, t in out.items()}
+
+    def props_extra(self, P: Particles, nodes: dict, halos: dict, halo_of, bound, so_rho=()):
+        """libhalo_props_extra: (basic properties, additional properties); m_so
+        and r_so have shape [len(so_rho), n_halos]."""
+        dev = self.device
+        nn = int(nodes["parent"].shape[0])
+        nh = int(halos["seed_node"].shape[0])
+        so = [float(r) for r in so_rho]
+        if len(so) > MAX_SO:
+            raise ValueError(f"at most {MAX_SO} SO thresholds")
+        NS = _cstruct(NodesS, NODE_FIELDS, nodes, nn)
+        HS = _cstruct(HalosS, HALO_FIELDS, halos, nh)
+        out = _table(PROP_FIELDS, nh, dev)
+        PS = _cstruct(PropsS, PROP_FIELDS, out)
+        cap = max(nh, 1)
+        ext = {n: torch.zeros(cap * max(len(so), 1) if n in ("m_so", "r_so") else cap,
+                              dtype=t, device=dev) for n, t in EXTRA_FIELDS}
+        ES = _cstruct(ExtraS, EXTRA_FIELDS, ext, cap)
+        rho_arr = (C.c_double * max(len(so), 1))(*so)
+        rho = C.cast(rho_arr, C.c_void_p) if so else None
+        self._check(self.L.libhalo_props_extra(
+            self.h, P.n, P.dtype_code, *P.args(), C.byref(NS), nn, C.byref(HS), nh,
+            _ptr(halo_of), _ptr(bound), C.byref(PS), len(so), rho, C.byref(ES), _stream()))
+        res = {n: t[:nh] for n, t in ext.items() if n not in ("m_so", "r_so")}
+        for n in ("m_so", "r_so"):
+            res[n] = ext[n][:cap * len(so)].view(len(so), cap)[:, :nh]
+        return {n: t[:nh] for n, t in out.items()}, res
 
     def run_all(self, P: Particles):
         """One pass of the whole path: fof3d -> refine6d -> assign -> unbind -> props."""
