@@ -28,10 +28,10 @@ FP32_PEAK_TFLOPS = 157.3
 # copy of known size).  Reported only while the kernel's source file is the
 # one that was measured.
 MEASURED_TRAFFIC = {
-    "k_potential_f64": {"bytes": 434.6e6, "src": "paper_1110_4372_amd/csrc/unbind.hip",
+    "k_potential_f64": {"bytes": 433.7e6, "src": "paper_1110_4372_amd/csrc/unbind.hip",
                         "sha1": "d64e9ce3e8b362de98520fe8c3bb5db1d91fda64"},
     "k_nn": {"bytes": 88.7e6, "src": "paper_1110_4372_amd/csrc/refine6d.hip",
-             "sha1": "69780a2941bf542785f2ff7b9c9c5965ccafb6de"},
+             "sha1": "007d8b882e35dcb6f5a54744e9ab110099299008"},
 }
 
 
@@ -71,7 +71,7 @@ def one_step(ctx, P, ev=None):
     rec(4)
     ctx.props(P, nodes, halos, halo_of, bound)
     rec(5)
-    return fof, nodes, halos, halo_of, unb
+    return fof, nodes, halos, halo_of, unb, bound
 
 
 PROGRESS = False
@@ -119,7 +119,7 @@ def pair_work(ctx, P, out):
     (13 FLOP), a pair of an own particle and a subhalo particle of S(h) one
     term added to the own particle's sum (12 FLOP)."""
     import numpy as np
-    fof, nodes, halos, halo_of, unb = out
+    fof, nodes, halos, halo_of, unb = out[:5]
     cnt = nodes["count"].cpu().numpy().astype(np.float64)
     flags = nodes["flags"].cpu().numpy()
     active = (flags & 2) == 0
@@ -131,6 +131,45 @@ def pair_work(ctx, P, out):
     nsk = ns[kept]
     pot_flops = float(np.sum(13.0 * nown * (nown - 1.0) / 2.0 + 12.0 * nown * (nsk - nown)))
     return nn_flops, pot_flops
+
+
+RHO_CRIT = 2.77536627e11
+
+
+def extras_report(ctx, P, out, particle_mass, rho_vir):
+    """libhalo_props_extra on the step's output, outside the timed step: the
+    call's device time (it recomputes the basic properties too), and its pair
+    kernel, the potential energy of V(h) (the k* innermost bound particles of
+    S(h)), against the FP64 VALU peak: each pair of V(h) is one term
+    1/sqrt(r^2 + eps^2) added once, 13 FLOP as the potential's own pairs."""
+    import numpy as np
+    import torch
+    fof, nodes, halos, halo_of, unb, bound = out
+    so = [rho_vir, 200.0 * RHO_CRIT, 500.0 * RHO_CRIT]
+    ctx.props_extra(P, nodes, halos, halo_of, bound, so)  # workspace and code objects
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    pr, ex = ctx.props_extra(P, nodes, halos, halo_of, bound, so)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ctx.profile(True)
+    ctx.profile_reset()
+    ctx.props_extra(P, nodes, halos, halo_of, bound, so)
+    torch.cuda.synchronize()
+    t_pe, l_pe = ctx.profile_read("k_pair_energy")
+    ctx.profile(False)
+    h = {k: v.cpu().numpy() for k, v in halos.items()}
+    kept = h["merged_into"] == np.arange(h["merged_into"].shape[0])
+    k = np.rint(pr["mvir"].cpu().numpy()[kept] / particle_mass)
+    pairs = float(np.sum(k * (k - 1.0) / 2.0))
+    ach = 13.0 * pairs / (t_pe * 1e-3) / 1e12 if t_pe > 0 else 0.0
+    return {"call_ms": ms, "pair_kernel": "k_pair_energy", "pair_ms": t_pe,
+            "pair_launches": l_pe, "pairs": pairs, "achieved_tflops": ach,
+            "peak_tflops": FP64_PEAK_TFLOPS, "frac": ach / FP64_PEAK_TFLOPS,
+            "so_thresholds": so,
+            "largest_halo_k": float(k.max()) if k.size else 0.0}
 
 
 # Algorithmic HBM bytes of each pass (what the pass must move, not what it
@@ -242,6 +281,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other precision form and the mixed-vs-FP64 comparison")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip timing libhalo_props_extra (not part of the step)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration)")
     ap.add_argument("--grid-min", type=int, default=0,
@@ -323,6 +364,10 @@ def main():
                 plain = {"value": cat.n / sp, "ms_per_step": sp * 1e3}
             del ctxp
     precision = None if args.no_forms else precision_report(H, cat, P, args.grid_min)
+    extras = None if args.no_extras else extras_report(ctx, P, out, cat.particle_mass,
+                                                       H.params_for_catalog(cat).rho_vir)
+    if extras is not None:
+        progress("additional properties timed")
     passes = pass_report(cat.n, out, stage)
 
     if args.copy_probe:
@@ -349,6 +394,7 @@ def main():
         "plain": plain,
         "forms": forms,
         "precision": precision,
+        "extras": extras,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

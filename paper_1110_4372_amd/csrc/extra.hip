@@ -97,19 +97,20 @@ __global__ void k_extra_init(I128* acc, I128* accU, uint32_t* nown, uint32_t* kf
 }
 
 // First j (1-based) of each halo's sorted bound list whose enclosed density
-// falls below threshold t: r_j^6 > (j C_t)^2.
+// falls below threshold t: r_j^6 > (j C_t)^2.  Elements of one halo are
+// contiguous, so a wave sends one atomic per halo and threshold.
 __global__ void k_so_fail_multi(const uint32_t* s_seg, const double* s_r2,
                                 const uint32_t* start, uint32_t m, uint32_t S,
                                 SoThresholds th, uint32_t* kfail) {
   const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  const uint32_t hh = s_seg[q];
-  const uint32_t j = q - start[hh] + 1;
-  const double r2 = s_r2[q];
+  const bool ok = q < m;
+  const uint32_t hh = ok ? s_seg[q] : 0u;
+  const uint32_t j = ok ? q - start[hh] + 1 : 0u;
+  const double r2 = ok ? s_r2[q] : 0.0;
   const double r6 = r2 * r2 * r2;
   for (int t = 0; t < th.n; ++t) {
     const double jc = (double)j * th.C[t];
-    if (!(r6 <= jc * jc)) atomicMin(kfail + (size_t)t * S + hh, j);
+    agg_min_u32(kfail + (size_t)t * S, hh, j, ok && !(r6 <= jc * jc));
   }
 }
 

@@ -99,17 +99,18 @@ __global__ void k_prop_init(uint32_t* kfail, I128* acc, unsigned long long* vm, 
 }
 
 // First j (1-based) whose enclosed density 3 j m / (4 pi r_j^3) falls below
-// rho_vir, tested as r_j^6 > (j C)^2 with C = 3 m / (4 pi rho_vir).
+// rho_vir, tested as r_j^6 > (j C)^2 with C = 3 m / (4 pi rho_vir).  A halo's
+// elements are contiguous: one atomic per wave and halo.
 __global__ void k_so_fail(const uint32_t* s_seg, const double* s_r2, const uint32_t* start,
                           uint32_t m, double C, uint32_t* kfail) {
-  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  const uint32_t hh = s_seg[q];
-  const uint32_t j = q - start[hh] + 1;
-  const double r2 = s_r2[q];
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = q < m;
+  const uint32_t hh = ok ? s_seg[q] : 0u;
+  const uint32_t j = ok ? q - start[hh] + 1 : 0u;
+  const double r2 = ok ? s_r2[q] : 0.0;
   const double r6 = r2 * r2 * r2;
   const double jc = (double)j * C;
-  if (!(r6 <= jc * jc)) atomicMin(kfail + hh, j);
+  agg_min_u32(kfail, hh, j, ok && !(r6 <= jc * jc));
 }
 
 __global__ void k_so_radius(const uint32_t* kfail, const uint32_t* start, uint32_t S, double C,

@@ -7,7 +7,7 @@ particles alone.  The oracle runs the whole path on the particles of a few
 random sub-cubes (the box and the linking length of the full catalogue), and
 the GPU's output for the interior groups -- labels, node table, deepest node,
 halo table, halo_of and bound flags -- must match it exactly, as at the
-smaller sizes."""
+smaller sizes; the basic and additional halo properties within 1e-5."""
 import os
 
 import numpy as np
@@ -16,6 +16,7 @@ import torch
 
 from tests.gpu_util import note, to_np
 from tests.test_gpu_assign import assert_halos_equal
+from tests.test_gpu_props_extra import compare_extra_rows
 from tests.test_gpu_refine6d import assert_nodes_equal, gpu_nodes, subset_nodes
 from tests.test_gpu_unbind_props import energy_band
 
@@ -23,6 +24,9 @@ pytestmark = pytest.mark.gpu
 
 CUBE = 30.0  # Mpc/h; ~17k particles of the 512^3 catalogue on average
 MAX_SUB = 60000
+# virial, 200 and 500 times critical, and half the virial density
+SO_THRESHOLDS = [360.0 * 0.27 * 2.77536627e11, 200.0 * 2.77536627e11, 500.0 * 2.77536627e11,
+                 0.5 * 360.0 * 0.27 * 2.77536627e11]
 
 
 @pytest.fixture(scope="module")
@@ -57,14 +61,15 @@ def subcube_parity(H, orc, cat, P, prec, ncubes=6, seed=7, cube=CUBE):
     print("fof3d and refine6d done", flush=True)
     halos, hof = ctx.assign(P, nodes, deep)
     unb, bound, _ = ctx.unbind(P, halos, hof, want_phi=False)
-    props = ctx.props(P, nodes, halos, hof, bound)
+    props, extra = ctx.props_extra(P, nodes, halos, hof, bound, SO_THRESHOLDS)
     torch.cuda.synchronize()
-    print("assign, unbind and props done", flush=True)
+    print("assign, unbind and props (with the additional ones) done", flush=True)
     label_d = fof["label"].long()
     gsize_d = torch.bincount(label_d, minlength=P.n)
     gn = gpu_nodes(nodes)
     gh = {k: to_np(v) for k, v in halos.items()}
     gp = {k: to_np(v) for k, v in props.items()}
+    gx = {k: to_np(v) for k, v in extra.items()}
 
     N, L = cat.n, cat.box
     ll = 0.28 * L / N ** (1.0 / 3.0)
@@ -140,6 +145,13 @@ def subcube_parity(H, orc, cat, P, prec, ncubes=6, seed=7, cube=CUBE):
                                        rtol=1e-5, atol=1e-9, err_msg=k)
         np.testing.assert_array_equal(gp["n_bound"][grows],
                                       np.asarray(o["props"]["n_bound"])[orows])
+        oex = orc.props_extra(p, Po, o["halos"], o["halo_of"], o["bound"], o["props"],
+                              SO_THRESHOLDS)
+        compare_extra_rows(
+            {k: (v[:, grows] if k in ("m_so", "r_so") else v[grows]) for k, v in gx.items()},
+            {k: (v[:, orows] if k in ("m_so", "r_so") else v[orows]) for k, v in oex.items()
+             if k != "k"},
+            np.asarray(o["props"]["mvir"])[orows], np.asarray(o["props"]["rvir"])[orows])
         checked_groups += interior.shape[0]
         checked_nodes += osub["parent"].shape[0]
         checked_halos += ohs["seed_node"].shape[0]

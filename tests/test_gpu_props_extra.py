@@ -31,37 +31,42 @@ def thresholds(rho_vir):
     return [rho_vir, 200.0 * RHO_CRIT, 500.0 * RHO_CRIT, 0.5 * rho_vir]
 
 
+def compare_extra_rows(g, oex, mvir, rvir):
+    """g, oex: additional properties of the same halos in the same order (numpy;
+    m_so and r_so [n_so, rows]); mvir, rvir: the oracle's basic properties."""
+    np.testing.assert_array_equal(g["n_shape"].astype(np.int64), oex["n_shape"].astype(np.int64))
+    np.testing.assert_array_equal(g["m_so"], oex["m_so"])
+    np.testing.assert_array_equal(g["m_so"][0], mvir)
+    np.testing.assert_allclose(g["r_so"], oex["r_so"], rtol=1e-12, atol=0)
+    for f in ("kin", "pot", "t_u", "spin", "spin_bullock", "c_klypin", "rs_klypin"):
+        np.testing.assert_allclose(g[f], oex[f], rtol=1e-5, atol=0, err_msg=f)
+    assert np.all(np.abs(g["xoff"] - oex["xoff"]) <= 1e-5 * oex["xoff"] + 1e-9 * rvir), "xoff"
+    Jo = np.stack([oex["jx"], oex["jy"], oex["jz"]], 1)
+    Jg = np.stack([g["jx"], g["jy"], g["jz"]], 1)
+    if Jo.size:
+        Jscale = np.linalg.norm(Jo, axis=1)[:, None]
+        assert np.all(np.abs(Jg - Jo) <= 1e-5 * Jscale + 1e-12 * np.abs(Jo).max()), "J"
+    # eigenvalues carry an absolute rounding of ~1e-16 a^2 on either side, so
+    # the ratios are compared squared (sqrt would turn 1e-16 into 1e-8 at 0)
+    for f in ("b_to_a", "c_to_a"):
+        np.testing.assert_allclose(g[f] ** 2, oex[f] ** 2, rtol=1e-5, atol=1e-12, err_msg=f)
+    Ao = np.stack([oex["ax"], oex["ay"], oex["az"]], 1)
+    Ag = np.stack([g["ax"], g["ay"], g["az"]], 1)
+    distinct = (1.0 - oex["b_to_a"] ** 2) > 1e-4
+    na, ng = np.linalg.norm(Ao, axis=1), np.linalg.norm(Ag, axis=1)
+    np.testing.assert_allclose(ng, na, rtol=1e-5, atol=1e-12)
+    dots = np.abs(np.einsum("ij,ij->i", Ag, Ao))
+    assert np.all(dots[distinct] >= (1.0 - 1e-6) * (na * ng)[distinct]), "major axis"
+
+
 def compare_extra(g_pr, g_ex, o, oex, kept):
     gp = {k: to_np(v) for k, v in g_pr.items()}
     g = {k: to_np(v) for k, v in g_ex.items()}
     # the basic properties come out as libhalo_props has them
     np.testing.assert_array_equal(gp["mvir"][kept], o["props"]["mvir"][kept])
-    np.testing.assert_array_equal(g["n_shape"][kept].astype(np.int64),
-                                  oex["n_shape"][kept].astype(np.int64))
-    np.testing.assert_array_equal(g["m_so"][:, kept], oex["m_so"][:, kept])
-    np.testing.assert_array_equal(g["m_so"][0][kept], o["props"]["mvir"][kept])
-    np.testing.assert_allclose(g["r_so"][:, kept], oex["r_so"][:, kept], rtol=1e-12, atol=0)
-    for f in ("kin", "pot", "t_u", "spin", "spin_bullock", "c_klypin", "rs_klypin"):
-        np.testing.assert_allclose(g[f][kept], oex[f][kept], rtol=1e-5, atol=0, err_msg=f)
-    rv = o["props"]["rvir"][kept]
-    assert np.all(np.abs(g["xoff"][kept] - oex["xoff"][kept])
-                  <= 1e-5 * oex["xoff"][kept] + 1e-9 * rv), "xoff"
-    Jo = np.stack([oex["jx"], oex["jy"], oex["jz"]], 1)[kept]
-    Jg = np.stack([g["jx"], g["jy"], g["jz"]], 1)[kept]
-    Jscale = np.linalg.norm(Jo, axis=1)[:, None]
-    assert np.all(np.abs(Jg - Jo) <= 1e-5 * Jscale + 1e-12 * np.abs(Jo).max()), "J"
-    # eigenvalues carry an absolute rounding of ~1e-16 a^2 on either side, so
-    # the ratios are compared squared (sqrt would turn 1e-16 into 1e-8 at 0)
-    for f in ("b_to_a", "c_to_a"):
-        np.testing.assert_allclose(g[f][kept] ** 2, oex[f][kept] ** 2, rtol=1e-5, atol=1e-12,
-                                   err_msg=f)
-    Ao = np.stack([oex["ax"], oex["ay"], oex["az"]], 1)[kept]
-    Ag = np.stack([g["ax"], g["ay"], g["az"]], 1)[kept]
-    distinct = (1.0 - oex["b_to_a"][kept] ** 2) > 1e-4
-    na, ng = np.linalg.norm(Ao, axis=1), np.linalg.norm(Ag, axis=1)
-    np.testing.assert_allclose(ng, na, rtol=1e-5, atol=1e-12)
-    dots = np.abs(np.einsum("ij,ij->i", Ag, Ao))
-    assert np.all(dots[distinct] >= (1.0 - 1e-6) * (na * ng)[distinct]), "major axis"
+    rows = lambda d: {k: (v[:, kept] if k in ("m_so", "r_so") else v[kept])  # noqa: E731
+                      for k, v in d.items() if k != "k"}
+    compare_extra_rows(rows(g), rows(oex), o["props"]["mvir"][kept], o["props"]["rvir"][kept])
     # merged seeds carry zeros
     merged = ~kept
     for f in ("kin", "pot", "spin", "c_klypin", "b_to_a"):
