@@ -1035,12 +1035,24 @@ void orc_phi_points(const orc_params* p, int pos_f64, const void* x, const void*
 
 /*
  * Single-pass unbinding (Section 3.5.3): a particle assigned to h is bound
- * when 1/2 |v - v_bulk,h|^2 + phi < 0, phi from all particles of S(h) (h with
- * its subhalos, the mass convention of Section 3.4) and v_bulk,h the mean
+ * when 1/2 |v - v_bulk|^2 + phi < 0, phi from all particles of S(h) (h with
+ * its subhalos, the mass convention of Section 3.4) and v_bulk the mean
  * velocity of S(h) (exact fixed-point sums).  A halo is valid when the bound
  * fraction of S(h) is at least unbound_threshold.  The potential is the exact
  * direct sum in place of the paper's Barnes-Hut tree (Appendix B).
  * phi_abs[i] = |phi_i| is returned for the error band of a comparison.
+ *
+ * Major mergers (Section 3.5.3, parameter MP of Table 2; off when
+ * major_merger = 0): the particles of a subhalo h whose merger ratio with its
+ * host, |S(h)| / |S(host)| (masses with substructure, as in Section 3.4), is
+ * at least MP take their potential from the merging system S(t), where t is
+ * reached from h by following host links while each link is such a major
+ * merger (reading: the system is the outermost halo joined by major
+ * mergers).  The paper changes only the potential, so the kinetic term keeps
+ * h's own v_bulk (reading), and a particle can only gain boundness.  Pinned:
+ * MP = 0 and MP > 1 leave every output unchanged; with MP no flag turns
+ * unbound and no potential gets shallower; a two-clump case against a
+ * brute-force numpy evaluation.
  */
 int orc_unbind(const orc_params* p, int64_t n, int pos_f64, const void* x, const void* y,
                const void* z, const float* vx, const float* vy, const float* vz,
@@ -1073,6 +1085,7 @@ int orc_unbind(const orc_params* p, int64_t n, int pos_f64, const void* x, const
     out->valid[s] = 0;
     out->vbx[s] = out->vby[s] = out->vbz[s] = 0.0;
   }
+  /* |S(h)| and the bulk velocity of S(h) of every kept halo */
   for (int64_t s = 0; s < ns; ++s) {
     if (h->merged_into[s] != s) continue;
     subtree_members(&tree, hoff, hmem, s, &S, &stk);
@@ -1089,6 +1102,17 @@ int orc_unbind(const orc_params* p, int64_t n, int pos_f64, const void* x, const
     out->vby[s] = vb[1];
     out->vbz[s] = vb[2];
     out->n_s[s] = (uint32_t)S.n;
+  }
+  for (int64_t s = 0; s < ns; ++s) {
+    if (h->merged_into[s] != s) continue;
+    /* the system whose potential decides h's particles */
+    int64_t t = s;
+    if (p->major_merger > 0.0)
+      while (h->host[t] >= 0 &&
+             (double)out->n_s[t] >= p->major_merger * (double)out->n_s[h->host[t]])
+        t = h->host[t];
+    subtree_members(&tree, hoff, hmem, t, &S, &stk);
+    const double vb[3] = {out->vbx[s], out->vby[s], out->vbz[s]};
     int64_t nown = hoff[s + 1] - hoff[s];
     double* ph = (double*)malloc(sizeof(double) * (size_t)(nown ? nown : 1));
     orc_phi_points(p, pos_f64, x, y, z, S.v, S.n, hmem + hoff[s], nown, ph);

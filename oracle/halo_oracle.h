@@ -49,6 +49,8 @@ typedef struct {
   double softening;         /* Plummer softening eps */
   double core_frac;         /* core radius as a fraction of R_vir (0.1) */
   double unbound_threshold; /* minimum bound fraction of a valid halo (0.5) */
+  double major_merger;      /* MP: a subhalo with |S(h)| >= MP |S(host)| is unbound in
+                               the merging system's potential; 0 = off */
 } orc_params;
 
 typedef struct {            /* node table, structure of arrays, capacity cap */

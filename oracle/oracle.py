@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("min_members", C.c_int32), ("max_levels", C.c_int32),
                 ("merge_q2", C.c_double), ("particle_mass", C.c_double),
                 ("G", C.c_double), ("rho_vir", C.c_double), ("softening", C.c_double),
-                ("core_frac", C.c_double), ("unbound_threshold", C.c_double)]
+                ("core_frac", C.c_double), ("unbound_threshold", C.c_double),
+                ("major_merger", C.c_double)]
 
 
 _P = C.c_void_p
@@ -172,12 +173,12 @@ class Particles:
 
 def make_params(box, particle_mass, softening, *, b=0.28, f=0.7, min_members=10,
                 max_levels=200, merge_q2=200.0, G=None, rho_vir=None, core_frac=0.1,
-                unbound_threshold=0.5) -> Params:
+                unbound_threshold=0.5, major_merger=0.0) -> Params:
     from paper_1110_4372_amd import synth
     return Params(box, b, f, min_members, max_levels, merge_q2, particle_mass,
                   synth.G_NEWTON if G is None else G,
                   synth.RHO_VIR if rho_vir is None else rho_vir, softening, core_frac,
-                  unbound_threshold)
+                  unbound_threshold, major_merger)
 
 
 def params_of(cat, **kw) -> Params:
