@@ -233,6 +233,47 @@ def precision_report(H, cat, P, grid_min):
     return rep
 
 
+def merger_report(H, cat, P, grid_min, prec, mp=0.3):
+    """The major-merger form (major_merger = MP of Table 2) against the
+    single-halo pass, outside the timed steps: the unbind call's device time
+    in both, the merger term's kernel, the number of merging subhaloes and
+    the bound flags gained (the merger form can only add flags)."""
+    import numpy as np
+    import torch
+    out = {}
+    for m in (0.0, mp):
+        ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=grid_min,
+                                          major_merger=m))
+        fof = ctx.fof3d(P)
+        nodes, deep = ctx.refine6d(P, fof)
+        halos, hof = ctx.assign(P, nodes, deep)
+        ctx.unbind(P, halos, hof, want_phi=False)  # warm-up
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        unb, bound, _ = ctx.unbind(P, halos, hof, want_phi=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ext = ctx.profile_read("k_potential_ext_f64")
+        ctx.profile(False)
+        h = {k: v.cpu().numpy() for k, v in halos.items()}
+        ns = unb["n_s"].cpu().numpy()
+        kept = np.nonzero(h["merged_into"] == np.arange(h["merged_into"].shape[0]))[0]
+        major = [s for s in kept if h["host"][s] >= 0 and m > 0 and ns[s] >= m * ns[h["host"][s]]]
+        out[m] = dict(ms=e0.elapsed_time(e1), ext_ms=ext[0], bound=bound.clone(),
+                      majors=len(major),
+                      major_particles=int(sum(int(h["n_assigned"][s]) for s in major)))
+    a, b = out[0.0], out[mp]
+    return {"major_merger": mp, "merging_subhaloes": b["majors"],
+            "their_particles": b["major_particles"],
+            "unbind_ms_single": a["ms"], "unbind_ms_merger": b["ms"],
+            "merger_kernel": "k_potential_ext_f64", "merger_kernel_ms": b["ext_ms"],
+            "flags_gained": int((b["bound"].int() - a["bound"].int()).clamp(min=0).sum().item()),
+            "flags_lost": int((a["bound"].int() - b["bound"].int()).clamp(min=0).sum().item())}
+
+
 def cpu_baseline(cat, budget_s: float = 20.0):
     """The CPU oracle (serial FP64 C) on a sub-volume of the catalogue: the
     particles of the corner cube [0, L/k)^3, treated as a periodic box of side
@@ -281,6 +322,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other precision form and the mixed-vs-FP64 comparison")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-merger", action="store_true",
+                    help="skip timing the major-merger unbinding (not part of the step)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip timing libhalo_props_extra (not part of the step)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -368,6 +411,9 @@ def main():
                                                        H.params_for_catalog(cat).rho_vir)
     if extras is not None:
         progress("additional properties timed")
+    merger = None if args.no_merger else merger_report(H, cat, P, args.grid_min, prec)
+    if merger is not None:
+        progress("major-merger form timed")
     passes = pass_report(cat.n, out, stage)
 
     if args.copy_probe:
@@ -395,6 +441,7 @@ def main():
         "forms": forms,
         "precision": precision,
         "extras": extras,
+        "merger": merger,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -96,6 +96,10 @@ typedef struct {
                                neighbour search instead of all pairs; 0 = 8192,
                                else >= 64 (results are identical either way) */
   int32_t reserved;         /* must be 0 */
+  double major_merger;      /* MP (Section 3.5.3, Table 2): the particles of a subhalo
+                               with |S(h)| >= MP |S(host)| take their potential from the
+                               merging system (the outermost halo reached through such
+                               host links); 0 = off, the single-halo pass (paper: 0.3) */
 } libhalo_params;
 
 /* Node table (refine6d output), structure of arrays, capacity `cap` rows.

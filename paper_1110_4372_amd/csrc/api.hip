@@ -74,6 +74,8 @@ static std::string validate(const libhalo_params& p) {
   if (!(p.core_frac > 0.0)) return "core_frac must be positive";
   if (!(p.unbound_threshold >= 0.0 && p.unbound_threshold <= 1.0))
     return "unbound_threshold must lie in [0, 1]";
+  if (!(p.major_merger >= 0.0 && std::isfinite(p.major_merger)))
+    return "major_merger must be finite and >= 0";
   if (!(p.e_recheck >= 0.0)) return "e_recheck must be >= 0";
   if (p.mode != LIBHALO_PLAIN && p.mode != LIBHALO_BATCHED) return "unknown mode";
   if (p.prec != LIBHALO_PREC_FP64 && p.prec != LIBHALO_PREC_MIXED) return "unknown prec";

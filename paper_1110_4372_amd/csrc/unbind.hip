@@ -747,6 +747,82 @@ __global__ void __launch_bounds__(TB, 4)
   }
 }
 
+// Major mergers (Section 3.5.3): the halo whose S decides the potential of
+// h's particles, following host links while |S(h)| >= mp |S(host)| (the
+// identity when mp <= 0 and for merged seeds).
+__global__ void k_merge_target(const libhalo_halos h, uint32_t S, const uint32_t* nS, double mp,
+                               uint32_t* tgt) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  int32_t t = (int32_t)s;
+  if (mp > 0.0 && h.merged_into[s] == (int32_t)s)
+    while (h.host[t] >= 0 && (double)nS[t] >= mp * (double)nS[h.host[t]]) t = h.host[t];
+  tgt[s] = (uint32_t)t;
+}
+
+// Units of the merger term: h's own particles (kPotI per unit) against the
+// particles of S(target) outside S(h) (kPotJ per unit); entry S stays 0.
+__global__ void k_ext_counts(const libhalo_halos h, uint32_t S, const uint32_t* tgt,
+                             const uint32_t* nS, uint32_t* ucnt) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > S) return;
+  uint32_t u = 0;
+  if (s < S && tgt[s] != s) {
+    const uint32_t nown = h.n_assigned[s], e = nS[tgt[s]] - nS[s];
+    u = ((nown + kPotI - 1u) / kPotI) * ((e + kPotJ - 1u) / kPotJ);
+  }
+  ucnt[s] = u;
+}
+
+// The merger term, FP64, i side only: S(target) lies in the layout as one
+// range holding S(h) as a sub-range, so the external particles are the two
+// ranges around it.  Terms go to the particles' fixed-point sums next to the
+// ones of S(h); the sum does not depend on which unit ran when.
+__global__ void __launch_bounds__(TB, 4)
+    k_potential_ext_f64(const double* __restrict__ ux, const double* __restrict__ uy,
+                        const double* __restrict__ uz, const libhalo_halos h,
+                        const uint32_t* __restrict__ tgt, const uint32_t* __restrict__ slot,
+                        const uint32_t* __restrict__ nS, const uint32_t* __restrict__ uoff,
+                        uint32_t S, double eps2, I128* __restrict__ acc) {
+  const uint32_t total = uoff[S];
+  for (uint32_t u0 = blockIdx.x; u0 < total; u0 += gridDim.x) {
+    const uint32_t u = __builtin_amdgcn_readfirstlane(u0);
+    const uint32_t hh = seg_of(uoff, S, u);
+    const uint32_t nown = h.n_assigned[hh], t = tgt[hh];
+    const uint32_t b = slot[hh], bt = slot[t];
+    const uint32_t e = nS[t] - nS[hh], pre = b - bt;
+    const uint32_t nb = (nown + kPotI - 1u) / kPotI;
+    const uint32_t local = u - uoff[hh];
+    const uint32_t c = local / nb;
+    const uint32_t t0 =
+        __builtin_amdgcn_readfirstlane((local - c * nb) * kPotI + (threadIdx.x >> 6) * kPotTile);
+    if (t0 >= nown) continue;  // wave-uniform
+    const uint32_t e0 = c * kPotJ, e1 = min(e0 + kPotJ, e);
+    uint32_t qi[kPotK];
+    double x[kPotK], y[kPotK], z[kPotK], A[kPotK];
+#pragma unroll
+    for (uint32_t k = 0; k < kPotK; ++k) {
+      const uint32_t li = t0 + (threadIdx.x & 63u) + 64u * k;
+      const bool ok = li < nown;
+      const uint32_t q = b + (ok ? li : 0u);
+      qi[k] = ok ? q : 0xFFFFFFFFu;
+      x[k] = ok ? ux[q] : kFar;
+      y[k] = ok ? uy[q] : kFar;
+      z[k] = ok ? uz[q] : kFar;
+      A[k] = 0.0;
+    }
+    if (e0 < min(e1, pre)) pot_span_f64<false>(ux, uy, uz, bt + e0, bt + min(e1, pre), qi, x, y, z, eps2, A);
+    if (max(e0, pre) < e1)
+      pot_span_f64<false>(ux, uy, uz, bt + nS[hh] + max(e0, pre), bt + nS[hh] + e1, qi, x, y,
+                          z, eps2, A);
+#pragma unroll
+    for (uint32_t k = 0; k < kPotK; ++k) {
+      const double v = 0.5 * A[k];
+      if (qi[k] != 0xFFFFFFFFu && v > 0.0) atomic_add_i128(acc + qi[k], pot_fixed(v));
+    }
+  }
+}
+
 __global__ void k_zero_i128(I128* a, uint32_t m) {
   uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q < m) a[q] = I128{0ull, 0ll};
@@ -758,16 +834,17 @@ __global__ void k_pot_finish(const I128* acc, uint32_t m, double* sum) {
   if (q < m) sum[q] = ldexp(i128_to_f64(acc[q]), -kPotFrac);
 }
 
-// FP64 recheck of one particle's potential (mixed form), one block per particle.
+// FP64 recheck of one particle's potential (mixed form), one block per particle,
+// over S(h) or, for a major merger, S of the merging system.
 __global__ void __launch_bounds__(TB)
     k_recheck(const double* ux, const double* uy, const double* uz, const uint32_t* lhalo,
-              const uint32_t* slot, const uint32_t* nS, const uint32_t* list,
-              const uint32_t* nlist, double eps2, double* sum) {
+              const uint32_t* tgt, const uint32_t* slot, const uint32_t* nS,
+              const uint32_t* list, const uint32_t* nlist, double eps2, double* sum) {
   __shared__ double red[TB];
   const uint32_t L = nlist[0];
   for (uint32_t t = blockIdx.x; t < L; t += gridDim.x) {
     const uint32_t qi = list[t];
-    const uint32_t hh = lhalo[qi];
+    const uint32_t hh = tgt[lhalo[qi]];  // S(h), or the merging system's S
     const uint32_t base = slot[hh], ns = nS[hh];
     const double xi = ux[qi], yi = uy[qi], zi = uz[qi];
     double acc = 0.0;
@@ -894,7 +971,7 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
   struct W {
     uint32_t *flag, *pos, *ck0, *cv0, *ck1, *cv1, *ccnt, *coff, *nS, *depth, *slot, *rootv,
         *dcnt, *stmp, *ak0, *av0, *ak1, *av1, *gfirst, *lp, *lhalo, *nb_own, *nbS, *rlist,
-        *ucnt, *uoff, *pk0, *pv0, *pk1, *pv1;
+        *ucnt, *uoff, *pk0, *pv0, *pk1, *pv1, *tgt, *ecnt, *eoff;
     double *ux, *uy, *uz, *vb, *sum;
     float *lvx, *lvy, *lvz, *fx, *fy, *fz;
     I128 *accO, *accS, *pacc;
@@ -931,6 +1008,9 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     w.pv1 = A.take<uint32_t>(S2);
     w.nb_own = A.take<uint32_t>(S2);
     w.nbS = A.take<uint32_t>(S2);
+    w.tgt = A.take<uint32_t>(S2);
+    w.ecnt = A.take<uint32_t>(S2);
+    w.eoff = A.take<uint32_t>(S2);
     w.rlist = A.take<uint32_t>(N2);
     w.ux = A.take<double>(N2);
     w.uy = A.take<double>(N2);
@@ -995,6 +1075,7 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
   if (m > 0) k_own_vsum<<<blocks_for(m, TB), TB, 0, s>>>(w.lvx, w.lvy, w.lvz, w.lhalo, m, w.accO);
   k_chain_vsum<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.accO, w.accS);
   k_vbulk<<<blocks_for(S, TB), TB, 0, s>>>(w.accS, w.nS, S, w.vb);
+  k_merge_target<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, P.major_merger, w.tgt);
   // potentials: work units ordered largest first, one partial per particle
   // and j-chunk, partials added in chunk order
   k_pot_counts<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, w.ucnt, w.pk0, w.pv0);
@@ -1035,13 +1116,20 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 4, 1, 0u);
       launch(0, U, w.dcnt + 4, std::min<uint32_t>(kPersist, U));
     }
+    if (P.major_merger > 0.0) {
+      k_ext_counts<<<blocks_for(S + 1, TB), TB, 0, s>>>(h, S, w.tgt, w.nS, w.ecnt);
+      exclusive_scan<uint32_t>(w.ecnt, w.eoff, S + 1, w.dcnt + 5, w.stmp, s);
+      HALO_PROF(ctx, "k_potential_ext_f64", s,
+                k_potential_ext_f64<<<kPersist, TB, 0, s>>>(w.ux, w.uy, w.uz, h, w.tgt, w.slot,
+                                                             w.nS, w.eoff, S, eps2, w.pacc));
+    }
     k_pot_finish<<<blocks_for(m, TB), TB, 0, s>>>(w.pacc, m, w.sum);
     k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 3, 1, 0u);
     k_energy<<<blocks_for(m, TB), TB, 0, s>>>(w.sum, w.lvx, w.lvy, w.lvz, w.lhalo, w.lp, w.vb, m,
                                              mGm, P.e_recheck, mixed ? 1 : 0, bound, phi,
                                              w.nb_own, w.rlist, w.dcnt + 3);
     if (mixed) {
-      k_recheck<<<1024, TB, 0, s>>>(w.ux, w.uy, w.uz, w.lhalo, w.slot, w.nS, w.rlist,
+      k_recheck<<<1024, TB, 0, s>>>(w.ux, w.uy, w.uz, w.lhalo, w.tgt, w.slot, w.nS, w.rlist,
                                     w.dcnt + 3, eps2, w.sum);
       k_energy_list<<<blocks_for(m, TB), TB, 0, s>>>(w.sum, w.lvx, w.lvy, w.lvz, w.lhalo, w.lp,
                                                      w.vb, w.rlist, w.dcnt + 3, mGm, bound,
