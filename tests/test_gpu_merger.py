@@ -81,3 +81,14 @@ def test_merger_c1(H, orc, c1, prec):
 def test_merger_bad_parameter(H, c1):
     with pytest.raises(H.HaloError):
         H.Halo(H.params_for_catalog(c1, major_merger=-0.1))
+
+
+def test_merger_plain_equals_batched(H):
+    """The merger term's fixed-point sums do not depend on the launch form."""
+    note("major merger plain == batched")
+    pos, vel = merger(5)
+    P = particles_from_arrays(pos, vel)
+    outs = [H.Halo(H.Params(box=BOX, particle_mass=M_PART, softening=EPS, mode=mode,
+                            major_merger=0.3)).run_all(P) for mode in (1, 0)]
+    np.testing.assert_array_equal(to_np(outs[0]["phi"]), to_np(outs[1]["phi"]))
+    np.testing.assert_array_equal(to_np(outs[0]["bound"]), to_np(outs[1]["bound"]))

@@ -169,3 +169,19 @@ def test_props_extra_argument_errors(H, c1):
     _, ex = ctx.props_extra(P, g["nodes"], g["halos"], g["halo_of"], g["bound"], [])
     assert tuple(ex["m_so"].shape) == (0, int(g["halos"]["seed_node"].shape[0]))
     assert float(to_np(ex["kin"]).max()) > 0.0
+
+
+def test_props_extra_deterministic(H, c1):
+    """Fixed-point sums: repeated calls, and the plain and batched forms of the
+    path before them, give the same bits."""
+    note("props_extra determinism c1")
+    P = H.Particles.from_catalog(c1)
+    res = []
+    for mode in (1, 1, 0):
+        ctx = H.Halo(H.params_for_catalog(c1, mode=mode))
+        g = ctx.run_all(P)
+        res.append(ctx.props_extra(P, g["nodes"], g["halos"], g["halo_of"], g["bound"],
+                                   [1e13, 3e13])[1])
+    for r in res[1:]:
+        for k in res[0]:
+            np.testing.assert_array_equal(to_np(r[k]), to_np(res[0][k]), err_msg=k)
