@@ -67,7 +67,8 @@ def subcube_parity(H, orc, cat, P, prec, ncubes=6, seed=7, cube=CUBE, extras=Tru
     else:
         props, extra = ctx.props(P, nodes, halos, hof, bound), None
     torch.cuda.synchronize()
-    print("assign, unbind and props (with the additional ones) done", flush=True)
+    print("assign, unbind and props done" + (" (with the additional ones)" if extras else ""),
+          flush=True)
     label_d = fof["label"].long()
     gsize_d = torch.bincount(label_d, minlength=P.n)
     gn = gpu_nodes(nodes)
