@@ -330,7 +330,9 @@ def main():
                     help="also run one 256 MiB device copy (counter calibration)")
     ap.add_argument("--grid-min", type=int, default=0,
                     help="nodes above this many particles use the 6D tile search "
-                         "(0: the library default)")
+                         "(0: the library default, or the autotuner's pick with --autotune)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the grid_min candidates before the run and use the fastest")
     ap.add_argument("--gen", default="host", choices=["host", "device"],
                     help="catalogue generator: numpy (host) or torch on the GPU (device; "
                          "power-law configs, for the 512^3 and 1024^3 catalogues)")
@@ -353,6 +355,16 @@ def main():
     P = H.Particles.from_catalog(cat)
     progress(f"catalogue {args.config}: {cat.n} particles")
     prec = H.PREC_FP64 if args.prec == "fp64" else H.PREC_MIXED
+    tuned = None
+    if args.grid_min == 0 and args.autotune:
+        # the framework's own tuning step, before (and outside) the timed steps:
+        # refine6d timed at each candidate size bin; results do not depend on it
+        from paper_1110_4372_amd import autotune
+        best, t = autotune.tune_grid_min(
+            H, H.params_for_catalog(cat, mode=H.BATCHED, prec=prec), P, repeats=2)
+        args.grid_min = int(best)
+        tuned = {"grid_min": int(best), "refine_ms": {str(k): v for k, v in t.items()}}
+        progress(f"autotuned grid_min = {best}")
     ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=args.grid_min))
     sec, out, stage = timed(ctx, P, args.steps, args.warmup)
 
@@ -433,6 +445,7 @@ def main():
                                "power-law NFW hosts + subhaloes + 40% uniform, seed 0"
                                + (" (GPU-drawn)" if args.gen == "device" else ""),
                    "form": "batched", "potential": args.prec,
+                   "grid_min": args.grid_min, "autotune": tuned,
                    "n_groups": int(out[0]["n_groups"]), "n_nodes": int(out[1]["parent"].shape[0]),
                    "n_halos": int(out[2]["seed_node"].shape[0])},
         "stage_ms": stage,
