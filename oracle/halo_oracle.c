@@ -384,6 +384,58 @@ float orc_ell2(int64_t n, const float* dmin, double f) {
   return r;
 }
 
+/*
+ * SplitMix64 (Steele, Lea & Flood 2014): the output for counter x.  It draws
+ * the random subset of Section 3.2 from the particle's input index.
+ */
+static uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/*
+ * Subset membership for the linking length of a node of n > m particles
+ * (Section 3.2: in large groups the nearest neighbours are found for a random
+ * subset of 10^4 only).  Reading: each particle is drawn independently with
+ * probability m / n, decided exactly as splitmix64(index) * n < m * 2^64
+ * (128-bit integers), so the subset's expected size is m.
+ */
+int orc_in_subset(uint64_t index, int64_t n, int64_t m) {
+  if (m <= 0 || n <= m) return 1;
+  unsigned __int128 lhs = (unsigned __int128)splitmix64(index) * (unsigned __int128)n;
+  unsigned __int128 rhs = (unsigned __int128)m << 64;
+  return lhs < rhs;
+}
+
+/*
+ * Linking length from a subset: the nearest-neighbour distance (against every
+ * particle of the node) of each subset member, and ell^2 = the k-th smallest
+ * of those, k = ceil(f n_sub) (orc_ell2).  An empty subset (possible only
+ * by chance) falls back to every particle.
+ */
+static float ell2_subset(int64_t n, const float* xi6, const int64_t* mem, int32_t m, double f) {
+  int64_t ns = 0;
+  for (int64_t i = 0; i < n; ++i) ns += orc_in_subset((uint64_t)mem[i], n, m);
+  if (ns == 0) ns = n, m = 0;
+  float* d = (float*)malloc(sizeof(float) * (size_t)ns);
+  int64_t q = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!orc_in_subset((uint64_t)mem[i], n, m)) continue;
+    float best = INFINITY;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      float dd = d2_6d(xi6 + 6 * i, xi6 + 6 * j);
+      if (dd < best) best = dd;
+    }
+    d[q++] = best;
+  }
+  float r = orc_ell2(ns, d, f);
+  free(d);
+  return r;
+}
+
 /* 6D FOF at ell^2: comp[i] = smallest local index of i's component. */
 void orc_fof6d(int64_t n, const float* xi6, float ell2, int64_t* comp) {
   for (int64_t i = 0; i < n; ++i) comp[i] = i;
@@ -529,11 +581,16 @@ int orc_refine6d(const orc_params* p, int64_t n, int pos_f64, const void* x,
         free(xi);
         continue;
       }
-      float* dmin = (float*)malloc(sizeof(float) * (size_t)nm);
-      orc_nn6d(nm, xi, dmin);
-      float l2 = orc_ell2(nm, dmin, p->f);
+      float l2;
+      if (p->ell_subset > 0 && nm > p->ell_subset) {
+        l2 = ell2_subset(nm, xi, mem, p->ell_subset, p->f);
+      } else {
+        float* dmin = (float*)malloc(sizeof(float) * (size_t)nm);
+        orc_nn6d(nm, xi, dmin);
+        l2 = orc_ell2(nm, dmin, p->f);
+        free(dmin);
+      }
       nv.ell2[k] = l2;
-      free(dmin);
       int64_t* comp = (int64_t*)malloc(sizeof(int64_t) * (size_t)nm);
       int64_t* csz = (int64_t*)calloc((size_t)nm, sizeof(int64_t));
       orc_fof6d(nm, xi, l2, comp);

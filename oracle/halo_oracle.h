@@ -49,6 +49,9 @@ typedef struct {
   double softening;         /* Plummer softening eps */
   double core_frac;         /* core radius as a fraction of R_vir (0.1) */
   double unbound_threshold; /* minimum bound fraction of a valid halo (0.5) */
+  int32_t ell_subset;       /* 0: l from every particle's nearest neighbour; else nodes
+                               of more particles take it from a hashed subset of about
+                               this many (the paper's 10^4) */
   double major_merger;      /* MP: a subhalo with |S(h)| >= MP |S(host)| is unbound in
                                the merging system's potential; 0 = off */
 } orc_params;
@@ -143,6 +146,7 @@ void orc_phi_points(const orc_params* p, int pos_f64, const void* x, const void*
                     const void* z, const int64_t* src, int64_t nsrc, const int64_t* tgt,
                     int64_t ntgt, double* phi);
 int32_t orc_position_shift(double box);
+int orc_in_subset(uint64_t index, int64_t n, int64_t m);
 
 #ifdef __cplusplus
 }

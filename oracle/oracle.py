@@ -37,7 +37,7 @@ class Params(C.Structure):
                 ("merge_q2", C.c_double), ("particle_mass", C.c_double),
                 ("G", C.c_double), ("rho_vir", C.c_double), ("softening", C.c_double),
                 ("core_frac", C.c_double), ("unbound_threshold", C.c_double),
-                ("major_merger", C.c_double)]
+                ("ell_subset", C.c_int32), ("major_merger", C.c_double)]
 
 
 _P = C.c_void_p
@@ -131,6 +131,8 @@ def lib():
         L.orc_fof6d.restype = None
         L.orc_phi_points.argtypes = [C.POINTER(Params), i32, _P, _P, _P, _P, i64, _P, i64, _P]
         L.orc_phi_points.restype = None
+        L.orc_in_subset.argtypes = [C.c_uint64, C.c_int64, C.c_int64]
+        L.orc_in_subset.restype = C.c_int
         L.orc_position_shift.argtypes = [C.c_double]
         L.orc_position_shift.restype = C.c_int32
         _lib = L
@@ -173,12 +175,12 @@ class Particles:
 
 def make_params(box, particle_mass, softening, *, b=0.28, f=0.7, min_members=10,
                 max_levels=200, merge_q2=200.0, G=None, rho_vir=None, core_frac=0.1,
-                unbound_threshold=0.5, major_merger=0.0) -> Params:
+                unbound_threshold=0.5, major_merger=0.0, ell_subset=0) -> Params:
     from paper_1110_4372_amd import synth
     return Params(box, b, f, min_members, max_levels, merge_q2, particle_mass,
                   synth.G_NEWTON if G is None else G,
                   synth.RHO_VIR if rho_vir is None else rho_vir, softening, core_frac,
-                  unbound_threshold, major_merger)
+                  unbound_threshold, ell_subset, major_merger)
 
 
 def params_of(cat, **kw) -> Params:
