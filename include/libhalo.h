@@ -95,7 +95,10 @@ typedef struct {
   int32_t grid_min;         /* nodes with more particles use the exact grid
                                neighbour search instead of all pairs; 0 = 8192,
                                else >= 64 (results are identical either way) */
-  int32_t reserved;         /* must be 0 */
+  int32_t ell_subset;       /* 0: ell from every particle's nearest neighbour (exact);
+                               m > 0: nodes of more than m particles take it from a
+                               subset drawn with probability m / n per particle
+                               (SplitMix64 of the input index; Section 3.2, paper: 10^4) */
   double major_merger;      /* MP (Section 3.5.3, Table 2): the particles of a subhalo
                                with |S(h)| >= MP |S(host)| take their potential from the
                                merging system (the outermost halo reached through such

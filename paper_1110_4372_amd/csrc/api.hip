@@ -80,7 +80,7 @@ static std::string validate(const libhalo_params& p) {
   if (p.mode != LIBHALO_PLAIN && p.mode != LIBHALO_BATCHED) return "unknown mode";
   if (p.prec != LIBHALO_PREC_FP64 && p.prec != LIBHALO_PREC_MIXED) return "unknown prec";
   if (p.grid_min != 0 && p.grid_min < 64) return "grid_min must be 0 or >= 64";
-  if (p.reserved != 0) return "reserved must be 0";
+  if (p.ell_subset < 0) return "ell_subset must be >= 0";
   return "";
 }
 

@@ -636,6 +636,61 @@ __global__ void __launch_bounds__(TB)
   if (threadIdx.x == 0) sc.ell2[k] = __uint_as_float(s_pre);
 }
 
+// ------------------------------------------------------- subset ell ----
+// Section 3.2: in large groups the nearest neighbours are found for a random
+// subset only.  A particle of a node of n > m particles belongs to the subset
+// when SplitMix64 (Steele, Lea & Flood 2014) of its input index times n is
+// below m 2^64 (exact 128-bit comparison): probability m / n, expected size m.
+// Its nearest-neighbour distance is the exact one against the whole node, so
+// D stays exact for every particle (the 6D FOF pass prunes with it); only the
+// selection of ell^2 reads the subset.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+  unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ bool in_subset(uint32_t index, uint32_t n, uint32_t m) {
+  if (n <= m) return true;
+  const unsigned __int128 l = (unsigned __int128)splitmix64(index) * n;
+  return l < ((unsigned __int128)m << 64);
+}
+
+// nsub[k] = subset size of each node above m (zero-initialised).
+__global__ void k_subset_count(const uint32_t* lidx, const uint32_t* lnode, LevelNodes nd,
+                               uint32_t Mi, uint32_t m, uint32_t* nsub) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = q < Mi;
+  const uint32_t k = ok ? lnode[q] : 0u;
+  const uint32_t n = ok ? nd.count[k] : 0u;
+  agg_add_u32(nsub, k, 1u, ok && n > m && in_subset(lidx[q], n, m));
+}
+
+// Dsel = D on the subset, +inf elsewhere; a node whose draw came out empty
+// keeps every particle.
+__global__ void k_subset_sel(const uint32_t* lidx, const uint32_t* lnode, LevelNodes nd,
+                             uint32_t Mi, uint32_t m, const uint32_t* nsub, const uint32_t* D,
+                             uint32_t* Dsel) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Mi) return;
+  const uint32_t k = lnode[q], n = nd.count[k];
+  const bool keep = n <= m || nsub[k] == 0u || in_subset(lidx[q], n, m);
+  Dsel[q] = keep ? D[q] : 0x7F800000u;
+}
+
+// Rank of ell^2 within the subset: ceil(f n_sub), clamped to [1, n_sub].
+__global__ void k_subset_kth(LevelNodes nd, uint32_t K, uint32_t m, double f,
+                             const uint32_t* nsub, NodeScratch sc) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K || nd.count[k] <= m || nsub[k] == 0u) return;
+  const uint32_t ns = nsub[k];
+  uint32_t kk = (uint32_t)ceil(f * ns);
+  if (kk < 1) kk = 1;
+  if (kk > ns) kk = ns;
+  sc.kth[k] = kk;
+}
+
 __global__ void k_big_flags(LevelNodes nd, uint32_t K, NodeScratch sc, uint32_t* flag) {
   uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
@@ -885,7 +940,8 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
 
   // workspace (sized by a dry run of the same carving)
   uint32_t *lidx, *lnode, *lidx2, *lnode2, *D, *par, *csize, *cflag, *head, *crank, *hrank,
-      *cid, *k0, *v0, *k1, *v1, *stmp, *dcnt, *lpos;
+      *cid, *k0, *v0, *k1, *v1, *stmp, *dcnt, *lpos, *Dsel = nullptr, *nsub = nullptr;
+  const uint32_t msub = (uint32_t)P.ell_subset;  // 0: exact ell
   float *xi, *cxi;
   LevelNodes cnodes;
   void* rtmp;
@@ -904,6 +960,10 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     cnodes.first = A.take<uint32_t>(Kmax + 1);
     cnodes.count = A.take<uint32_t>(Kmax + 1);
     D = A.take<uint32_t>(M + 1);
+    if (msub > 0) {
+      Dsel = A.take<uint32_t>(M + 1);
+      nsub = A.take<uint32_t>(Kmax + 1);
+    }
     par = A.take<uint32_t>(M + 1);
     csize = A.take<uint32_t>(M + 1);
     cflag = A.take<uint32_t>(M + 1);
@@ -1013,7 +1073,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
         const unsigned g = nn_units(nn, nnj);
         HALO_PROF(ctx, "k_nn", s,
                   k_nn<<<g, TB, 0, s>>>(xi, S, nd, K, sc.wpair, k, k + 1, nullptr, nnj, D));
-        if (nn <= (uint32_t)kSelSmall)
+        if (msub == 0 && nn <= (uint32_t)kSelSmall)
           HALO_PROF(ctx, "k_select_small", s,
                     k_select_small<<<1, TB, 0, s>>>(D, nd, k, k + 1, sc));
       }
@@ -1021,7 +1081,17 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       k_fill_u32<<<1, 64, 0, s>>>(dcnt + 8, 1, 0u);
       HALO_PROF(ctx, "k_nn", s,
                 k_nn<<<pgrid, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, nnj, D));
-      HALO_PROF(ctx, "k_select_small", s, k_select_small<<<K, TB, 0, s>>>(D, nd, 0, K, sc));
+      if (msub == 0)
+        HALO_PROF(ctx, "k_select_small", s, k_select_small<<<K, TB, 0, s>>>(D, nd, 0, K, sc));
+    }
+    // subset form of ell (Section 3.2): select over the subset's distances
+    const uint32_t* Dsl = msub > 0 ? Dsel : D;
+    if (msub > 0) {
+      k_fill_u32<<<blocks_for(K, TB), TB, 0, s>>>(nsub, K, 0u);
+      k_subset_count<<<blocks_for(Mi, TB), TB, 0, s>>>(lidx, lnode, nd, Mi, msub, nsub);
+      k_subset_sel<<<blocks_for(Mi, TB), TB, 0, s>>>(lidx, lnode, nd, Mi, msub, nsub, D, Dsel);
+      k_subset_kth<<<blocks_for(K, TB), TB, 0, s>>>(nd, K, msub, P.f, nsub, sc);
+      HALO_PROF(ctx, "k_select_small", s, k_select_small<<<K, TB, 0, s>>>(Dsel, nd, 0, K, sc));
     }
     // 4. selection for big nodes (both forms: a handful of nodes)
     auto select_big = [&]() {
@@ -1033,7 +1103,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
         exclusive_scan<uint32_t>(sc.wbig, sc.wbig, nbig, sc.wbig + nbig, stmp, s);
         k_zero_hist<<<64, TB, 0, s>>>(sc, dcnt);
         for (int pass = 0; pass < 4; ++pass) {
-          k_select_big_hist<<<pgrid, TB, 0, s>>>(D, nd, sc, dcnt, pass);
+          k_select_big_hist<<<pgrid, TB, 0, s>>>(Dsl, nd, sc, dcnt, pass);
           k_select_big_resolve<<<blocks_for(nbig, TB / 64), TB, 0, s>>>(sc, dcnt, pass);
         }
       }
@@ -1047,6 +1117,9 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       k_fill_u32<<<1, 64, 0, s>>>(dcnt + 8, 1, 0u);
       HALO_PROF(ctx, "k_nn", s,
                 k_nn<<<pgrid, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, nnj, D));
+      if (msub > 0)
+        k_subset_sel<<<blocks_for(Mi, TB), TB, 0, s>>>(lidx, lnode, nd, Mi, msub, nsub, D,
+                                                       Dsel);
       select_big();
     }
     // 5. 6D FOF: all-pairs nodes over their compacted linkable particles
