@@ -274,6 +274,46 @@ def merger_report(H, cat, P, grid_min, prec, mp=0.3):
             "flags_lost": int((a["bound"].int() - b["bound"].int()).clamp(min=0).sum().item())}
 
 
+def subset_report(H, cat, P, grid_min, prec, m=10000, steps=3):
+    """The paper's subset linking length (ell_subset = 10^4, Section 3.2)
+    against the exact one: step time and stage times of each (same steps
+    and warm-up), node and halo counts, and the particles whose halo changed,
+    halos identified by their seed leaf's smallest particle index."""
+    import numpy as np
+    res = {}
+    for mm in (0, m):
+        ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=grid_min,
+                                          ell_subset=mm))
+        sec, out, stage = timed(ctx, P, steps, 1)
+        fof, nodes, halos, halo_of = out[:4]
+        canon = nodes["canon"].cpu().numpy().astype(np.int64)
+        seed = halos["seed_node"].cpu().numpy().astype(np.int64)
+        merged = halos["merged_into"].cpu().numpy().astype(np.int64)
+        key = canon[seed[merged]] if seed.size else seed
+        hof = halo_of.cpu().numpy().astype(np.int64)
+        res[mm] = dict(ms=sec * 1e3, stage=stage, nodes=int(canon.shape[0]),
+                       halos=int((merged == np.arange(merged.shape[0])).sum()),
+                       who=np.where(hof >= 0, key[np.maximum(hof, 0)] if key.size else -1, -1))
+    a, b = res[0], res[m]
+    # each exact halo is matched to the subset-form halo holding most of its
+    # particles; a particle changed when it is not in its halo's match
+    # (assigned in one form only counts as changed)
+    wa, wb = a["who"], b["who"]
+    both = (wa >= 0) & (wb >= 0)
+    pairs, cnt = np.unique(np.stack([wa[both], wb[both]], 1), axis=0, return_counts=True)
+    best = {}
+    for (x, _), c in zip(pairs.tolist(), cnt.tolist()):
+        best[x] = max(best.get(x, 0), c)
+    kept = int(sum(best.values()))
+    assigned = int(((wa >= 0) | (wb >= 0)).sum())
+    return {"ell_subset": m, "ms_per_step_exact": a["ms"], "ms_per_step_subset": b["ms"],
+            "refine_ms_exact": a["stage"]["refine6d"], "refine_ms_subset": b["stage"]["refine6d"],
+            "nodes_exact": a["nodes"], "nodes_subset": b["nodes"],
+            "halos_exact": a["halos"], "halos_subset": b["halos"],
+            "assigned": assigned, "changed_membership": assigned - kept,
+            "changed_fraction": (assigned - kept) / max(assigned, 1)}
+
+
 def cpu_baseline(cat, budget_s: float = 20.0):
     """The CPU oracle (serial FP64 C) on a sub-volume of the catalogue: the
     particles of the corner cube [0, L/k)^3, treated as a periodic box of side
@@ -322,6 +362,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other precision form and the mixed-vs-FP64 comparison")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-subset", action="store_true",
+                    help="skip the subset-linking-length comparison (not part of the step)")
     ap.add_argument("--no-merger", action="store_true",
                     help="skip timing the major-merger unbinding (not part of the step)")
     ap.add_argument("--no-extras", action="store_true",
@@ -424,6 +466,9 @@ def main():
     if extras is not None:
         progress("additional properties timed")
     merger = None if args.no_merger else merger_report(H, cat, P, args.grid_min, prec)
+    subset = None if args.no_subset else subset_report(H, cat, P, args.grid_min, prec)
+    if subset is not None:
+        progress("subset linking length timed")
     if merger is not None:
         progress("major-merger form timed")
     passes = pass_report(cat.n, out, stage)
@@ -455,6 +500,7 @@ def main():
         "precision": precision,
         "extras": extras,
         "merger": merger,
+        "subset": subset,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
