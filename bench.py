@@ -31,7 +31,7 @@ MEASURED_TRAFFIC = {
     "k_potential_f64": {"bytes": 440.7e6, "src": "paper_1110_4372_amd/csrc/unbind.hip",
                         "sha1": "ffe9c024d9e29573c1f2bf9cb9febd3ea7132fd4"},
     "k_nn": {"bytes": 88.8e6, "src": "paper_1110_4372_amd/csrc/refine6d.hip",
-             "sha1": "6972529ea7c1efa62d34388f33c5ae0d372542a9"},
+             "sha1": "6bd7a03261fa2ac406100f0bea80070a6d21f0f6"},
 }
 
 
@@ -392,7 +392,7 @@ def main():
     PROGRESS = args.progress
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "decomposition is a design, not part of this build", file=sys.stderr)
+              "decomposition is described, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

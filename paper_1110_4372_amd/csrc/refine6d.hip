@@ -900,7 +900,7 @@ __global__ void k_zero_node_scratch(NodeScratch sc, uint32_t K) {
   }
 }
 
-// ------------------------------------------------------------ driver -------
+// ------------------------------------------------------------ host side ----
 struct Rd {  // small read-back helper on the pinned host block
   Ctx& c;
   hipStream_t s;
