@@ -176,12 +176,108 @@ static int cmp_rad(const void* a, const void* b) {
 
 /* ------------------------------------------------------------- 3D FOF ---- */
 /*
+ * Friends of particle i within radius r (r2 = r^2): among the particles of
+ * the 27 cells around i's cell in a grid of nc2 >= 3 cells of side >= r
+ * (key sorted by cell, then index), or among all particles when key is NULL.
+ * mode 0 returns the count (j != i), stopping once it exceeds limit; mode 1
+ * unions i with each of them.
+ */
+static int64_t near_pass(const orc_params* p, int64_t n, int pos_f64, const void* x,
+                         const void* y, const void* z, const cellkey* key, int64_t nc2,
+                         int64_t i, double r2, int mode, int64_t limit, int64_t* par) {
+  const double L = p->box;
+  const double pc[3] = {pos_at(x, pos_f64, i), pos_at(y, pos_f64, i), pos_at(z, pos_f64, i)};
+  int64_t cnt = 0;
+  int64_t c[3] = {0, 0, 0};
+  if (key) {
+    const double inv = (double)nc2 / L;
+    for (int a = 0; a < 3; ++a) {
+      int64_t ci = (int64_t)floor(pc[a] * inv);
+      if (ci < 0) ci = 0;
+      if (ci >= nc2) ci = nc2 - 1;
+      c[a] = ci;
+    }
+  }
+  const int span = key ? 1 : 0;
+  for (int dz = -span; dz <= span; ++dz)
+    for (int dy = -span; dy <= span; ++dy)
+      for (int dx = -span; dx <= span; ++dx) {
+        int64_t lo = 0, hi = n;
+        uint64_t cell = 0;
+        if (key) {
+          int64_t nx = (c[0] + dx + nc2) % nc2, ny = (c[1] + dy + nc2) % nc2,
+                  nz = (c[2] + dz + nc2) % nc2;
+          cell = (uint64_t)((nz * nc2 + ny) * nc2 + nx);
+          while (lo < hi) {
+            int64_t mid = (lo + hi) / 2;
+            if (key[mid].cell < cell)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+        }
+        for (int64_t b = lo; b < n && (!key || key[b].cell == cell); ++b) {
+          int64_t j = key ? key[b].idx : b;
+          if (j == i) continue;
+          double ex = min_image(pos_at(x, pos_f64, j) - pc[0], L);
+          double ey = min_image(pos_at(y, pos_f64, j) - pc[1], L);
+          double ez = min_image(pos_at(z, pos_f64, j) - pc[2], L);
+          if (sq3(ex, ey, ez) <= r2) {
+            if (mode == 1)
+              uf_union(par, i, j);
+            else if (++cnt > limit)
+              return cnt;
+          }
+        }
+      }
+  return cnt;
+}
+
+/* The dense-particle links of the FOF variant (orc_fof3d). */
+static void dense_links(const orc_params* p, int64_t n, int pos_f64, const void* x,
+                        const void* y, const void* z, double ll, int64_t* par) {
+  const double L = p->box;
+  const int64_t nc2 = (int64_t)floor(L / (2.0 * ll * (1.0 + 1e-9)));
+  cellkey* key = NULL;
+  if (nc2 >= 3) {
+    key = (cellkey*)malloc(sizeof(cellkey) * n);
+    const double inv = (double)nc2 / L;
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t c[3];
+      const void* ax[3] = {x, y, z};
+      for (int a = 0; a < 3; ++a) {
+        int64_t ci = (int64_t)floor(pos_at(ax[a], pos_f64, i) * inv);
+        if (ci < 0) ci = 0;
+        if (ci >= nc2) ci = nc2 - 1;
+        c[a] = ci;
+      }
+      key[i].cell = (uint64_t)((c[2] * nc2 + c[1]) * nc2 + c[0]);
+      key[i].idx = i;
+    }
+    qsort(key, (size_t)n, sizeof(cellkey), cmp_cellkey);
+  }
+  const int64_t t = p->fof_dense;
+  for (int64_t i = 0; i < n; ++i)
+    if (near_pass(p, n, pos_f64, x, y, z, key, nc2, i, ll * ll, 0, t, par) > t)
+      near_pass(p, n, pos_f64, x, y, z, key, nc2, i, 4.0 * ll * ll, 1, 0, par);
+  free(key);
+}
+
+/*
  * Standard friends-of-friends (Section 3.1): two particles are friends when
  * their minimum-image separation is at most ll = b * (L^3/N)^(1/3); groups
  * are the connected components.  The paper's faster variant (skip the
  * neighbour search around particles with more than 16 friends, link groups
  * within 2 ll instead) links a superset that depends on visiting order; the
- * reading taken is the standard definition, the subset the paper guarantees.
+ * default reading is the standard definition, the subset the paper
+ * guarantees.  With fof_dense = t > 0 the variant is taken in an order-free
+ * form: every particle with more than t friends within ll (itself excluded)
+ * also links every particle within 2 ll.  Whatever the visiting order, the
+ * paper's groups lie between the standard ones and these (a skipped
+ * particle lies within ll of the dense particle that skipped it, so its
+ * standard links are implied by that particle's 2 ll links, and only
+ * visited dense particles add 2 ll links).  Pinned by brute force with and
+ * without the variant.
  * Label = smallest 0-based input index in the group.
  * Neighbour search: particles sorted by a uniform grid of cells no smaller
  * than ll, so that friends lie in the same or adjacent cells.
@@ -269,6 +365,7 @@ int orc_fof3d(const orc_params* p, int64_t n, int pos_f64, const void* x, const 
     }
     free(key);
   }
+  if (p->fof_dense > 0) dense_links(p, n, pos_f64, x, y, z, ll, par);
   for (int64_t i = 0; i < n; ++i) label[i] = (uint32_t)uf_find(par, i);
   free(par);
   return ORC_OK;

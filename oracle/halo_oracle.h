@@ -54,6 +54,9 @@ typedef struct {
                                this many (the paper's 10^4) */
   double major_merger;      /* MP: a subhalo with |S(h)| >= MP |S(host)| is unbound in
                                the merging system's potential; 0 = off */
+  int32_t fof_dense;        /* 0: standard FOF; t > 0: a particle with more than t
+                               friends within ll also links everything within 2 ll
+                               (the paper's dense-particle shortcut, t = 16) */
 } orc_params;
 
 typedef struct {            /* node table, structure of arrays, capacity cap */

@@ -37,7 +37,8 @@ class Params(C.Structure):
                 ("merge_q2", C.c_double), ("particle_mass", C.c_double),
                 ("G", C.c_double), ("rho_vir", C.c_double), ("softening", C.c_double),
                 ("core_frac", C.c_double), ("unbound_threshold", C.c_double),
-                ("ell_subset", C.c_int32), ("major_merger", C.c_double)]
+                ("ell_subset", C.c_int32), ("major_merger", C.c_double),
+                ("fof_dense", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -175,12 +176,13 @@ class Particles:
 
 def make_params(box, particle_mass, softening, *, b=0.28, f=0.7, min_members=10,
                 max_levels=200, merge_q2=200.0, G=None, rho_vir=None, core_frac=0.1,
-                unbound_threshold=0.5, major_merger=0.0, ell_subset=0) -> Params:
+                unbound_threshold=0.5, major_merger=0.0, ell_subset=0,
+                fof_dense=0) -> Params:
     from paper_1110_4372_amd import synth
     return Params(box, b, f, min_members, max_levels, merge_q2, particle_mass,
                   synth.G_NEWTON if G is None else G,
                   synth.RHO_VIR if rho_vir is None else rho_vir, softening, core_frac,
-                  unbound_threshold, ell_subset, major_merger)
+                  unbound_threshold, ell_subset, major_merger, fof_dense)
 
 
 def params_of(cat, **kw) -> Params:
