@@ -103,6 +103,12 @@ typedef struct {
                                with |S(h)| >= MP |S(host)| take their potential from the
                                merging system (the outermost halo reached through such
                                host links); 0 = off, the single-halo pass (paper: 0.3) */
+  int32_t fof_dense;        /* 0: standard FOF; t > 0: the dense-particle variant of
+                               Section 3.1 -- a particle with more than t friends within
+                               ll also links every particle within 2 ll (paper: 16);
+                               EINVAL when the box holds fewer than 2Q+1 cells of the
+                               2 ll stencil */
+  int32_t reserved2;        /* must be 0 */
 } libhalo_params;
 
 /* Node table (refine6d output), structure of arrays, capacity `cap` rows.

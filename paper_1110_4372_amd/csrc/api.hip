@@ -76,6 +76,8 @@ static std::string validate(const libhalo_params& p) {
     return "unbound_threshold must lie in [0, 1]";
   if (!(p.major_merger >= 0.0 && std::isfinite(p.major_merger)))
     return "major_merger must be finite and >= 0";
+  if (p.fof_dense < 0) return "fof_dense must be >= 0";
+  if (p.reserved2 != 0) return "reserved2 must be 0";
   if (!(p.e_recheck >= 0.0)) return "e_recheck must be >= 0";
   if (p.mode != LIBHALO_PLAIN && p.mode != LIBHALO_BATCHED) return "unknown mode";
   if (p.prec != LIBHALO_PREC_FP64 && p.prec != LIBHALO_PREC_MIXED) return "unknown prec";

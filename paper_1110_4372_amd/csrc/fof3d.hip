@@ -196,6 +196,132 @@ __global__ void k_link(const T* xs, const T* ys, const T* zs, const uint32_t* ce
   }
 }
 
+// ---------------------------------------------- dense-particle variant ----
+// Section 3.1's faster FOF, in an order-free form: a particle with more than
+// t friends within ll also links every particle within 2 ll.  (The paper
+// skips the searches of a dense particle's neighbours, which makes its result
+// depend on the visiting order; these links give a superset of any order's
+// groups, and like the paper's at least the standard ones.)
+
+// Visits the occupied cells within `reach` cells of cell (cx, cy, cz), all
+// offsets but the cell itself, whose closest point can lie within r2 of
+// it; f(cell) returns true to stop.
+template <class F>
+__device__ __forceinline__ void for_stencil(const unsigned long long* cell_key,
+                                            const uint32_t* row_start, const Grid& g,
+                                            int64_t cx, int64_t cy, int64_t cz, int reach,
+                                            double r2, F&& f) {
+  const int64_t nc = g.nc;
+  const double side = g.box / (double)nc;
+  for (int dz = -reach; dz <= reach; ++dz) {
+    for (int dy = -reach; dy <= reach; ++dy) {
+      int64_t ny = cy + dy, nz = cz + dz;
+      ny = ny < 0 ? ny + nc : (ny >= nc ? ny - nc : ny);
+      nz = nz < 0 ? nz + nc : (nz >= nc ? nz - nc : nz);
+      const int64_t row = nz * nc + ny;
+      const uint32_t r0 = row_start[row], r1 = row_start[row + 1];
+      if (r0 == r1) continue;
+      const unsigned long long rbase = (unsigned long long)row * (unsigned long long)nc;
+      int64_t u0 = cx - reach, u1 = cx + reach;
+      int64_t iv[2][2];
+      int nv = 0;
+      if (u0 < 0) {
+        iv[nv][0] = u0 + nc; iv[nv][1] = nc - 1; ++nv;
+        u0 = 0;
+      }
+      if (u1 >= nc) {
+        iv[nv][0] = 0; iv[nv][1] = u1 - nc; ++nv;
+        u1 = nc - 1;
+      }
+      iv[nv][0] = u0; iv[nv][1] = u1; ++nv;
+      for (int q = 0; q < nv; ++q) {
+        uint32_t p = lower_cell(cell_key, r0, r1, rbase + (unsigned long long)iv[q][0]);
+        for (; p < r1; ++p) {
+          const int64_t x = (int64_t)(cell_key[p] - rbase);
+          if (x > iv[q][1]) break;
+          int64_t dx = x - cx;
+          dx = dx > reach ? dx - nc : (dx < -reach ? dx + nc : dx);
+          if (dx == 0 && dy == 0 && dz == 0) continue;
+          const double gx = (double)(dx < 0 ? -dx - 1 : (dx > 0 ? dx - 1 : 0));
+          const double gy = (double)(dy < 0 ? -dy - 1 : (dy > 0 ? dy - 1 : 0));
+          const double gz = (double)(dz < 0 ? -dz - 1 : (dz > 0 ? dz - 1 : 0));
+          if ((gx * gx + gy * gy + gz * gz) * side * side > r2 * (1.0 + 1e-9)) continue;
+          if (f(p)) return;
+        }
+      }
+    }
+  }
+}
+
+// dense[i] = 1 when sorted particle i has more than t friends within ll
+// (its own cell's others all are: the cell is a clique).
+template <class T>
+__global__ void k_dense_flags(const T* xs, const T* ys, const T* zs, const uint32_t* cell_of,
+                              const uint32_t* cell_start, const unsigned long long* cell_key,
+                              const uint32_t* row_start, int64_t ncell, int64_t n, Grid g,
+                              uint32_t t, uint32_t* dense) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t c = cell_of[i];
+  const uint32_t a0 = cell_start[c];
+  const uint32_t a1 = (c + 1 < ncell) ? cell_start[c + 1] : (uint32_t)n;
+  uint32_t cnt = a1 - a0 - 1;
+  if (cnt <= t) {
+    const unsigned long long kc = cell_key[c];
+    const int64_t nc = g.nc;
+    const int64_t cx = (int64_t)(kc % (unsigned long long)nc);
+    const int64_t cy = (int64_t)((kc / (unsigned long long)nc) % (unsigned long long)nc);
+    const int64_t cz = (int64_t)(kc / ((unsigned long long)nc * (unsigned long long)nc));
+    const double xi = (double)xs[i], yi = (double)ys[i], zi = (double)zs[i];
+    for_stencil(cell_key, row_start, g, cx, cy, cz, g.reach, g.ll2, [&](uint32_t d) {
+      const uint32_t b0 = cell_start[d];
+      const uint32_t b1 = (d + 1 < ncell) ? cell_start[d + 1] : (uint32_t)n;
+      for (uint32_t j = b0; j < b1; ++j) {
+        const double ex = min_image((double)xs[j] - xi, g.box);
+        const double ey = min_image((double)ys[j] - yi, g.box);
+        const double ez = min_image((double)zs[j] - zi, g.box);
+        if (sq3(ex, ey, ez) <= g.ll2 && ++cnt > t) return true;
+      }
+      return false;
+    });
+  }
+  dense[i] = cnt > t ? 1u : 0u;
+}
+
+// A dense particle joins its cell with every cell holding a particle within
+// 2 ll (cells are cliques, so one such particle per cell suffices).
+template <class T>
+__global__ void k_dense_links(const T* xs, const T* ys, const T* zs, const uint32_t* cell_of,
+                              const uint32_t* cell_start, const unsigned long long* cell_key,
+                              const uint32_t* row_start, int64_t ncell, int64_t n, Grid g,
+                              int reach2, const uint32_t* dense, uint32_t* par) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !dense[i]) return;
+  const uint32_t c = cell_of[i];
+  const unsigned long long kc = cell_key[c];
+  const int64_t nc = g.nc;
+  const int64_t cx = (int64_t)(kc % (unsigned long long)nc);
+  const int64_t cy = (int64_t)((kc / (unsigned long long)nc) % (unsigned long long)nc);
+  const int64_t cz = (int64_t)(kc / ((unsigned long long)nc * (unsigned long long)nc));
+  const double xi = (double)xs[i], yi = (double)ys[i], zi = (double)zs[i];
+  const double r2 = 4.0 * g.ll2;
+  for_stencil(cell_key, row_start, g, cx, cy, cz, reach2, r2, [&](uint32_t d) {
+    if (uf_find(par, c) == uf_find(par, d)) return false;
+    const uint32_t b0 = cell_start[d];
+    const uint32_t b1 = (d + 1 < ncell) ? cell_start[d + 1] : (uint32_t)n;
+    for (uint32_t j = b0; j < b1; ++j) {
+      const double ex = min_image((double)xs[j] - xi, g.box);
+      const double ey = min_image((double)ys[j] - yi, g.box);
+      const double ez = min_image((double)zs[j] - zi, g.box);
+      if (sq3(ex, ey, ez) <= r2) {
+        uf_union(par, c, d);
+        break;
+      }
+    }
+    return false;
+  });
+}
+
 // Every parent becomes its root.  Roots do not change during this pass (no
 // unions), so each thread may store the root it reads.
 __global__ void k_compress(uint32_t* par, int64_t n) {
@@ -307,6 +433,9 @@ void fof3d_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, uint32_
              "cell grid exceeds 64-bit keys");
   const int64_t nrow = g.nc * g.nc;
   HALO_CHECK(nrow < 0xFFFFFFFFll, LIBHALO_EINVAL, "cell rows exceed 32-bit table");
+  const int reach2 = (int)ceil(2.0 * ll / side);  // stencil of the 2 ll links
+  HALO_CHECK(P.fof_dense == 0 || g.nc >= 2 * reach2 + 1, LIBHALO_EINVAL,
+             "box too small for the dense-particle variant (fewer than 2Q+1 cells per side)");
 
   Arena& A = ctx.ws;
   A.reset();
@@ -326,6 +455,7 @@ void fof3d_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, uint32_
   auto* minidx = A.take<uint32_t>(n);
   auto* gsize = A.take<uint32_t>(n);
   auto* cnt = A.take<uint32_t>(8);
+  uint32_t* dense = P.fof_dense > 0 ? A.take<uint32_t>(n) : nullptr;
   void* rtmp = A.take<char>(radix_tmp_bytes(n));
   uint32_t* stmp = A.take<uint32_t>(scan_tmp_elems<uint32_t>(n + 1));
 
@@ -354,6 +484,14 @@ void fof3d_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, uint32_
   for (int phase = 0; phase < 2; ++phase) {
     HALO_PROF(ctx, "k_link", s, k_link<T><<<blocks_for(ncell, 128), 128, 0, s>>>(xs, ys, zs, cell_start, cell_key,
                                                        row_start, ncell, n, g, phase, par));
+    k_compress<<<blocks_for(ncell, TB), TB, 0, s>>>(par, ncell);
+  }
+  if (P.fof_dense > 0) {
+    k_dense_flags<T><<<nb, TB, 0, s>>>(xs, ys, zs, cell_of, cell_start, cell_key, row_start,
+                                       ncell, n, g, (uint32_t)P.fof_dense, dense);
+    HALO_PROF(ctx, "k_dense_links", s,
+              k_dense_links<T><<<nb, TB, 0, s>>>(xs, ys, zs, cell_of, cell_start, cell_key,
+                                                 row_start, ncell, n, g, reach2, dense, par));
     k_compress<<<blocks_for(ncell, TB), TB, 0, s>>>(par, ncell);
   }
   k_fill_u32<<<nb, TB, 0, s>>>(minidx, ncell, 0xFFFFFFFFu);
@@ -404,6 +542,7 @@ size_t fof3d_workspace(const libhalo_params& P, int64_t n, int pos_dtype) {
   add(4 * n); add(4 * (n + 1)); add(4 * n); add(8 * n);
   add(4 * ((size_t)nc * nc + 1));
   add(4 * n); add(4 * n); add(4 * n); add(32);
+  if (P.fof_dense > 0) add(4 * n);
   add(radix_tmp_bytes(n));
   add(4 * scan_tmp_elems<uint32_t>(n + 1));
   return b + 4096;

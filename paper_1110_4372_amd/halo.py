@@ -35,7 +35,8 @@ class CParams(C.Structure):
                 ("rho_vir", C.c_double), ("softening", C.c_double), ("core_frac", C.c_double),
                 ("unbound_threshold", C.c_double), ("e_recheck", C.c_double),
                 ("mode", C.c_int32), ("prec", C.c_int32), ("grid_min", C.c_int32),
-                ("ell_subset", C.c_int32), ("major_merger", C.c_double)]
+                ("ell_subset", C.c_int32), ("major_merger", C.c_double),
+                ("fof_dense", C.c_int32), ("reserved2", C.c_int32)]
 
 
 @dataclasses.dataclass
@@ -58,13 +59,14 @@ class Params:
     grid_min: int = 0
     major_merger: float = 0.0
     ell_subset: int = 0
+    fof_dense: int = 0
 
     def c(self) -> CParams:
         return CParams(self.box, self.b, self.f, self.min_members, self.max_levels,
                        self.merge_q2, self.particle_mass, self.G, self.rho_vir,
                        self.softening, self.core_frac, self.unbound_threshold,
                        self.e_recheck, self.mode, self.prec, self.grid_min,
-                       self.ell_subset, self.major_merger)
+                       self.ell_subset, self.major_merger, self.fof_dense, 0)
 
 
 NODE_FIELDS = [("parent", torch.int32), ("level", torch.int32), ("first_child", torch.int32),
