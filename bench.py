@@ -323,6 +323,29 @@ def subset_report(H, cat, P, grid_min, prec, m=10000, steps=3):
             "changed_fraction": changed / max(assigned, 1)}
 
 
+def dense_report(H, cat, P, grid_min, prec, t=16, steps=3):
+    """The paper's dense-particle FOF variant (fof_dense = 16, Section 3.1)
+    against standard FOF: step and fof3d times of each (same steps and
+    warm-up), FOF group counts, and the particles whose group grew (the
+    variant only merges standard groups)."""
+    import numpy as np
+    res = {}
+    for tt in (0, t):
+        ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=grid_min,
+                                          fof_dense=tt))
+        sec, out, stage = timed(ctx, P, steps, 1)
+        lab = out[0]["label"].cpu().numpy().astype(np.int64)
+        size = np.bincount(lab, minlength=lab.shape[0])[lab]
+        res[tt] = dict(ms=sec * 1e3, fof_ms=stage["fof3d"], groups=int(out[0]["n_groups"]),
+                       halos=int(out[2]["seed_node"].shape[0]), size=size)
+    a, b = res[0], res[t]
+    return {"fof_dense": t, "ms_per_step_standard": a["ms"], "ms_per_step_dense": b["ms"],
+            "fof3d_ms_standard": a["fof_ms"], "fof3d_ms_dense": b["fof_ms"],
+            "groups_standard": a["groups"], "groups_dense": b["groups"],
+            "halo_rows_standard": a["halos"], "halo_rows_dense": b["halos"],
+            "particles_in_grown_groups": int((b["size"] != a["size"]).sum())}
+
+
 def cpu_baseline(cat, budget_s: float = 20.0):
     """The CPU oracle (serial FP64 C) on a sub-volume of the catalogue: the
     particles of the corner cube [0, L/k)^3, treated as a periodic box of side
@@ -371,6 +394,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other precision form and the mixed-vs-FP64 comparison")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the dense-particle FOF variant comparison (not part of the step)")
     ap.add_argument("--no-subset", action="store_true",
                     help="skip the subset-linking-length comparison (not part of the step)")
     ap.add_argument("--no-merger", action="store_true",
@@ -476,6 +501,9 @@ def main():
         progress("additional properties timed")
     merger = None if args.no_merger else merger_report(H, cat, P, args.grid_min, prec)
     subset = None if args.no_subset else subset_report(H, cat, P, args.grid_min, prec)
+    dense = None if args.no_dense else dense_report(H, cat, P, args.grid_min, prec)
+    if dense is not None:
+        progress("dense-particle FOF variant timed")
     if subset is not None:
         progress("subset linking length timed")
     if merger is not None:
@@ -510,6 +538,7 @@ def main():
         "extras": extras,
         "merger": merger,
         "subset": subset,
+        "fof_dense": dense,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
