@@ -108,7 +108,11 @@ typedef struct {
                                ll also links every particle within 2 ll (paper: 16);
                                EINVAL when the box holds fewer than 2Q+1 cells of the
                                2 ll stencil */
-  int32_t reserved2;        /* must be 0 */
+  int32_t bh_min;           /* with bh_theta > 0: halos with |S(h)| >= bh_min (0 = 65536)
+                               take their particles' potential from a tree */
+  double bh_theta;          /* 0: exact direct sum; > 0: the tree potential of
+                               Appendix B, a cell's monopole accepted at distances
+                               d >= r_max/2 + sqrt((r_max/2)^2 + sigma^2/theta) */
 } libhalo_params;
 
 /* Node table (refine6d output), structure of arrays, capacity `cap` rows.

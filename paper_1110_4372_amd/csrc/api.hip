@@ -33,6 +33,25 @@ void Ctx::ensure_ws(size_t bytes) {
   ws.cap = want;
 }
 
+void Ctx::ensure_ws2(size_t bytes) {
+  if (bytes <= ws2.cap) return;
+  if (ws2.base) {
+    HALO_HIP(hipDeviceSynchronize());
+    HALO_HIP(hipFree(ws2.base));
+    ws2.base = nullptr;
+    ws2.cap = 0;
+  }
+  size_t want = bytes + bytes / 8;
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{LIBHALO_ENOMEM, "tree workspace allocation of " + std::to_string(want) +
+                                    " bytes failed"};
+  }
+  ws2.base = static_cast<char*>(p);
+  ws2.cap = want;
+}
+
 hipEvent_t Ctx::event() {
   if (!spare.empty()) {
     hipEvent_t e = spare.back();
@@ -53,6 +72,9 @@ void Ctx::release() {
   recs.clear();
   spare.clear();
   if (ws.base) (void)hipFree(ws.base);
+  if (ws2.base) (void)hipFree(ws2.base);
+  ws2.base = nullptr;
+  ws2.cap = 0;
   if (d_err) (void)hipFree(d_err);
   if (h_pinned) (void)hipHostFree(h_pinned);
   ws.base = nullptr;
@@ -77,7 +99,8 @@ static std::string validate(const libhalo_params& p) {
   if (!(p.major_merger >= 0.0 && std::isfinite(p.major_merger)))
     return "major_merger must be finite and >= 0";
   if (p.fof_dense < 0) return "fof_dense must be >= 0";
-  if (p.reserved2 != 0) return "reserved2 must be 0";
+  if (p.bh_min < 0) return "bh_min must be >= 0";
+  if (!(p.bh_theta >= 0.0 && std::isfinite(p.bh_theta))) return "bh_theta must be finite and >= 0";
   if (!(p.e_recheck >= 0.0)) return "e_recheck must be >= 0";
   if (p.mode != LIBHALO_PLAIN && p.mode != LIBHALO_BATCHED) return "unknown mode";
   if (p.prec != LIBHALO_PREC_FP64 && p.prec != LIBHALO_PREC_MIXED) return "unknown prec";

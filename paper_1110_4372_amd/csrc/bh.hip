@@ -1,0 +1,407 @@
+// Tree potential for the largest haloes on gfx950 (Appendix B of the paper:
+// a binary space-partitioning tree whose cells are accepted as monopoles
+// beyond the Salmon-Warren distance).
+//
+// Per halo the particles of S(h) are sorted along a 48-bit Morton curve over
+// their bounding box, and the tree is implicit over that order: heap node k
+// at level l covers the sorted range [floor(i n / 2^l), floor((i+1) n / 2^l))
+// with i = k - 2^l, down to leaves of at most 17 particles.  A cell's mass
+// centre x0, its dispersion sigma^2 about x0 and r_max (exact in the leaves,
+// an upper bound above, which keeps the criterion conservative) give the
+// acceptance distance d >= r_max / 2 + sqrt((r_max / 2)^2 + sigma^2 / theta),
+// beyond which the monopole's relative error is at most theta.  One thread
+// per own particle, in Morton order so that a wave's walks coincide, walks the
+// tree depth first: accepted cells add m / sqrt(d^2 + eps^2), opened leaves
+// their particles one by one.  Each walk sums in a fixed order, so the result
+// does not depend on scheduling.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "bh.hpp"
+#include "primitives.hpp"
+
+namespace halo {
+
+namespace {
+
+constexpr int TB = 256;
+constexpr uint32_t kLeaf = 16;
+constexpr int kStack = 64;
+constexpr int kFrac = 32;  // fractional bits of the potential accumulators
+
+__device__ __forceinline__ uint32_t seg_find(const uint32_t* off, uint32_t K, uint32_t w) {
+  uint32_t lo = 0, hi = K;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= w)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__host__ __device__ __forceinline__ uint32_t depth_for(uint32_t n) {
+  uint32_t d = 0;
+  while ((n >> d) > kLeaf) ++d;
+  return d;
+}
+
+// round(v 2^frac), 0 <= v 2^frac < 2^94, as a 128-bit integer.
+__device__ __forceinline__ I128 fixed128(double v, int frac) {
+  const double s = rint(ldexp(v, frac));
+  const double hi = floor(s * 0x1p-64);
+  const double lo = __fma_rn(-hi, 0x1p64, s);
+  const double l1 = floor(lo * 0x1p-32);
+  const double l0 = __fma_rn(-l1, 0x1p32, lo);
+  I128 r;
+  r.lo = ((unsigned long long)(uint32_t)l1 << 32) | (uint32_t)l0;
+  r.hi = (long long)hi;
+  return r;
+}
+
+// A coordinate of up to 21 bits spread to every third bit (bit i -> bit 3i).
+__host__ __device__ __forceinline__ unsigned long long spread3(uint32_t v) {
+  unsigned long long x = v & 0x1FFFFFull;
+  x = (x | (x << 32)) & 0x001F00000000FFFFull;
+  x = (x | (x << 16)) & 0x001F0000FF0000FFull;
+  x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+  x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__global__ void k_bh_flags(const libhalo_halos h, uint32_t S, const uint32_t* nS, double theta,
+                           uint32_t bh_min, uint32_t* flag) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  flag[s] = bh_takes(h.merged_into[s] == (int32_t)s, h.n_assigned[s], nS[s], theta, bh_min)
+                ? 1u : 0u;
+}
+
+struct BhList {
+  uint32_t *big, *nel, *nnode, *depth, *nown, *eoff, *noff;
+};
+
+__global__ void k_bh_list(const uint32_t* flag, const uint32_t* pos, uint32_t S,
+                          const libhalo_halos h, const uint32_t* nS, BhList L) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S || !flag[s]) return;
+  const uint32_t b = pos[s];
+  const uint32_t n = nS[s];
+  const uint32_t d = depth_for(n);
+  L.big[b] = s;
+  L.nel[b] = n;
+  L.depth[b] = d;
+  L.nnode[b] = 2u << d;
+  L.nown[b] = h.n_assigned[s];
+}
+
+__global__ void k_bh_bbox_init(unsigned long long* bb, uint32_t B) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  for (int c = 0; c < 3; ++c) {
+    bb[6 * (size_t)b + c] = 0xFFFFFFFFFFFFFFFFull;  // min
+    bb[6 * (size_t)b + 3 + c] = 0ull;                // max
+  }
+}
+
+// Bounding box per halo as ordered-integer min / max; a wave whose elements
+// all belong to one halo sends one set of atomics.
+__global__ void k_bh_bbox(const double* ux, const double* uy, const double* uz, BhList L,
+                          const uint32_t* slot, uint32_t B, uint32_t E,
+                          unsigned long long* bb) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = e < E;
+  uint32_t b = 0xFFFFFFFFu;
+  unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0ull, 0ull, 0ull};
+  if (ok) {
+    b = seg_find(L.eoff, B, e);
+    const uint32_t q = slot[L.big[b]] + (e - L.eoff[b]);
+    const double p[3] = {ux[q], uy[q], uz[q]};
+    for (int c = 0; c < 3; ++c) mn[c] = mx[c] = f64_ord(p[c]);
+  }
+  const uint32_t b0 = __shfl(b, 0);
+  if (__all(b == b0) && b0 != 0xFFFFFFFFu) {
+    for (int o = 32; o > 0; o >>= 1)
+      for (int c = 0; c < 3; ++c) {
+        const unsigned long long a = __shfl_xor(mn[c], o), z = __shfl_xor(mx[c], o);
+        mn[c] = a < mn[c] ? a : mn[c];
+        mx[c] = z > mx[c] ? z : mx[c];
+      }
+    if ((threadIdx.x & 63u) == 0)
+      for (int c = 0; c < 3; ++c) {
+        atomicMin(bb + 6 * (size_t)b0 + c, mn[c]);
+        atomicMax(bb + 6 * (size_t)b0 + 3 + c, mx[c]);
+      }
+  } else if (ok) {
+    for (int c = 0; c < 3; ++c) {
+      atomicMin(bb + 6 * (size_t)b + c, mn[c]);
+      atomicMax(bb + 6 * (size_t)b + 3 + c, mx[c]);
+    }
+  }
+}
+
+__global__ void k_bh_keys(const double* ux, const double* uy, const double* uz, BhList L,
+                          const uint32_t* slot, uint32_t B, uint32_t E,
+                          const unsigned long long* bb, unsigned long long* key,
+                          uint32_t* val) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const uint32_t b = seg_find(L.eoff, B, e);
+  const uint32_t q = slot[L.big[b]] + (e - L.eoff[b]);
+  const double p[3] = {ux[q], uy[q], uz[q]};
+  double ext = 0.0, lo[3];
+  for (int c = 0; c < 3; ++c) {
+    lo[c] = ord_f64(bb[6 * (size_t)b + c]);
+    ext = fmax(ext, ord_f64(bb[6 * (size_t)b + 3 + c]) - lo[c]);
+  }
+  const double scale = ext > 0.0 ? 65535.0 / ext : 0.0;
+  unsigned long long m = 0ull;
+  for (int c = 0; c < 3; ++c) {
+    double u = floor((p[c] - lo[c]) * scale);
+    u = u < 0.0 ? 0.0 : (u > 65535.0 ? 65535.0 : u);
+    m |= spread3((uint32_t)u) << c;
+  }
+  key[e] = ((unsigned long long)b << 48) | m;
+  val[e] = q;
+}
+
+__global__ void k_bh_gather(const double* ux, const double* uy, const double* uz,
+                            const uint32_t* sval, uint32_t E, double* px, double* py,
+                            double* pz, uint32_t* pidx) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const uint32_t q = sval[e];
+  px[e] = ux[q];
+  py[e] = uy[q];
+  pz[e] = uz[q];
+  pidx[e] = q;
+}
+
+struct BhNodes {
+  double *cx, *cy, *cz, *cm, *sig2, *rmax, *crit2;
+};
+
+__device__ __forceinline__ void node_range(uint32_t k, uint32_t n, uint32_t& lo, uint32_t& hi) {
+  const uint32_t l = 31u - (uint32_t)__builtin_clz(k);
+  const unsigned long long i = (unsigned long long)(k - (1u << l));
+  lo = (uint32_t)((i * n) >> l);
+  hi = (uint32_t)(((i + 1ull) * n) >> l);
+}
+
+// Cell statistics of every node at `level` (leaves directly, others from
+// their children, which the previous launch filled).
+__global__ void k_bh_level(BhList L, uint32_t B, uint32_t T, uint32_t level, double theta,
+                           const double* px, const double* py, const double* pz, BhNodes N) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const uint32_t b = seg_find(L.noff, B, t);
+  const uint32_t k = t - L.noff[b];
+  if (k == 0) return;
+  const uint32_t l = 31u - (uint32_t)__builtin_clz(k);
+  const uint32_t D = L.depth[b];
+  if (l != level || l > D) return;
+  double x0[3], m, s2, r;
+  if (l == D) {
+    uint32_t lo, hi;
+    node_range(k, L.nel[b], lo, hi);
+    const uint32_t base = L.eoff[b];
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (uint32_t e = base + lo; e < base + hi; ++e) {
+      sx += px[e];
+      sy += py[e];
+      sz += pz[e];
+    }
+    m = (double)(hi - lo);
+    x0[0] = sx / m;
+    x0[1] = sy / m;
+    x0[2] = sz / m;
+    s2 = 0.0;
+    r = 0.0;
+    for (uint32_t e = base + lo; e < base + hi; ++e) {
+      const double d2 = sq3(px[e] - x0[0], py[e] - x0[1], pz[e] - x0[2]);
+      s2 += d2;
+      r = fmax(r, d2);
+    }
+    s2 /= m;
+    r = sqrt(r);
+  } else {
+    const uint32_t g1 = L.noff[b] + 2u * k, g2 = g1 + 1u;
+    const double m1 = N.cm[g1], m2 = N.cm[g2];
+    m = m1 + m2;
+    x0[0] = (m1 * N.cx[g1] + m2 * N.cx[g2]) / m;
+    x0[1] = (m1 * N.cy[g1] + m2 * N.cy[g2]) / m;
+    x0[2] = (m1 * N.cz[g1] + m2 * N.cz[g2]) / m;
+    const double d1 = sq3(N.cx[g1] - x0[0], N.cy[g1] - x0[1], N.cz[g1] - x0[2]);
+    const double d2 = sq3(N.cx[g2] - x0[0], N.cy[g2] - x0[1], N.cz[g2] - x0[2]);
+    s2 = (m1 * (N.sig2[g1] + d1) + m2 * (N.sig2[g2] + d2)) / m;
+    r = fmax(sqrt(d1) + N.rmax[g1], sqrt(d2) + N.rmax[g2]);
+  }
+  const uint32_t g = t;
+  N.cx[g] = x0[0];
+  N.cy[g] = x0[1];
+  N.cz[g] = x0[2];
+  N.cm[g] = m;
+  N.sig2[g] = s2;
+  N.rmax[g] = r;
+  const double dc = 0.5 * r + sqrt(0.25 * r * r + s2 / theta);
+  N.crit2[g] = dc * dc;
+}
+
+// One own particle per thread (sorted order; other elements idle): the walk.
+__global__ void __launch_bounds__(TB)
+    k_bh_walk(BhList L, uint32_t B, uint32_t E, const uint32_t* slot, const double* px,
+              const double* py, const double* pz, const uint32_t* pidx, BhNodes N,
+              double eps2, I128* pacc, uint32_t* err) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const uint32_t b = seg_find(L.eoff, B, e);
+  const uint32_t q = pidx[e];
+  if (q - slot[L.big[b]] >= L.nown[b]) return;  // a subhalo particle: source only
+  const double x = px[e], y = py[e], z = pz[e];
+  const uint32_t n = L.nel[b], D = L.depth[b], nb = L.noff[b], base = L.eoff[b];
+  uint32_t stack[kStack];
+  int sp = 0;
+  stack[sp++] = 1u;
+  double acc = 0.0;
+  while (sp > 0) {
+    const uint32_t k = stack[--sp];
+    const uint32_t g = nb + k;
+    const double d2 = sq3(x - N.cx[g], y - N.cy[g], z - N.cz[g]);
+    if (d2 >= N.crit2[g]) {
+      acc += N.cm[g] * rsqrt_f64(d2 + eps2);
+      continue;
+    }
+    const uint32_t l = 31u - (uint32_t)__builtin_clz(k);
+    if (l == D) {
+      uint32_t lo, hi;
+      node_range(k, n, lo, hi);
+      for (uint32_t f = base + lo; f < base + hi; ++f) {
+        if (pidx[f] == q) continue;
+        acc += rsqrt_f64(sq3(x - px[f], y - py[f], z - pz[f]) + eps2);
+      }
+      continue;
+    }
+    if (sp + 2 > kStack) {  // cannot happen for depth <= 31; reported, not faulted
+      atomicOr(err, 1u);
+      break;
+    }
+    stack[sp++] = 2u * k + 1u;
+    stack[sp++] = 2u * k;
+  }
+  if (acc > 0.0) atomic_add_i128(pacc + q, fixed128(acc, kFrac));
+}
+
+template <class F>
+void carve2(Ctx& ctx, F&& carve) {
+  Arena dry;
+  dry.counting = true;
+  carve(dry);
+  ctx.ensure_ws2(dry.off + 4096);
+  ctx.ws2.reset();
+  carve(ctx.ws2);
+}
+
+}  // namespace
+
+void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* nS,
+                  const uint32_t* slot, const double* ux, const double* uy, const double* uz,
+                  double eps2, double theta, uint32_t bh_min, I128* pacc, hipStream_t s) {
+  uint32_t* hb = ctx.host_slot<uint32_t>(4);
+  struct W {
+    uint32_t *flag, *pos, *cnt, *stmp;
+    BhList L;
+    unsigned long long* bb;
+  } w;
+  auto take_list = [&](Arena& A) {
+    w.flag = A.take<uint32_t>(S + 2);
+    w.pos = A.take<uint32_t>(S + 2);
+    w.cnt = A.take<uint32_t>(16);
+    w.stmp = A.take<uint32_t>(scan_tmp_elems<uint32_t>(S + 2));
+    w.L.big = A.take<uint32_t>(S + 2);
+    w.L.nel = A.take<uint32_t>(S + 2);
+    w.L.nnode = A.take<uint32_t>(S + 2);
+    w.L.depth = A.take<uint32_t>(S + 2);
+    w.L.nown = A.take<uint32_t>(S + 2);
+    w.L.eoff = A.take<uint32_t>(S + 2);
+    w.L.noff = A.take<uint32_t>(S + 2);
+    w.bb = A.take<unsigned long long>(6ull * (S + 2));
+  };
+  auto build_list = [&]() {
+    k_bh_flags<<<blocks_for(S, TB), TB, 0, s>>>(h, S, nS, theta, bh_min, w.flag);
+    exclusive_scan<uint32_t>(w.flag, w.pos, S, w.cnt, w.stmp, s);
+    k_bh_list<<<blocks_for(S, TB), TB, 0, s>>>(w.flag, w.pos, S, h, nS, w.L);
+  };
+  carve2(ctx, take_list);
+  build_list();
+  HALO_HIP(hipMemcpyAsync(hb, w.cnt, 4, hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipStreamSynchronize(s));
+  const uint32_t B = hb[0];
+  if (B == 0) return;
+  HALO_CHECK(B < 65536u, LIBHALO_EINVAL, "more than 65535 haloes take the tree (raise bh_min)");
+  exclusive_scan<uint32_t>(w.L.nel, w.L.eoff, B, w.cnt + 1, w.stmp, s);
+  exclusive_scan<uint32_t>(w.L.nnode, w.L.noff, B, w.cnt + 2, w.stmp, s);
+  std::vector<uint32_t> dep(B), nel(B);
+  HALO_HIP(hipMemcpyAsync(hb + 1, w.cnt + 1, 8, hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipMemcpyAsync(dep.data(), w.L.depth, 4ull * B, hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipMemcpyAsync(nel.data(), w.L.nel, 4ull * B, hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipStreamSynchronize(s));
+  uint32_t Dmax = 0;
+  unsigned long long E64 = 0, T64 = 0;
+  for (uint32_t b = 0; b < B; ++b) {
+    Dmax = std::max(Dmax, dep[b]);
+    E64 += nel[b];
+    T64 += 2ull << dep[b];
+  }
+  HALO_CHECK(E64 < 0xFFFFFFFFull && T64 < 0xFFFFFFFFull, LIBHALO_EINVAL,
+             "tree elements exceed 32-bit indices (raise bh_min)");
+  const uint32_t E = hb[1], T = hb[2];
+  HALO_CHECK(Dmax <= 31u, LIBHALO_EINVAL, "tree deeper than 31 levels");
+  // second carve with the element and node arrays; the list is rebuilt in it
+  unsigned long long *k0, *k1;
+  uint32_t *v0, *v1, *pidx;
+  double *px, *py, *pz;
+  BhNodes N;
+  void* rtmp;
+  carve2(ctx, [&](Arena& A) {
+    take_list(A);
+    k0 = A.take<unsigned long long>(E + 1);
+    k1 = A.take<unsigned long long>(E + 1);
+    v0 = A.take<uint32_t>(E + 1);
+    v1 = A.take<uint32_t>(E + 1);
+    pidx = A.take<uint32_t>(E + 1);
+    px = A.take<double>(E + 1);
+    py = A.take<double>(E + 1);
+    pz = A.take<double>(E + 1);
+    N.cx = A.take<double>(T + 1);
+    N.cy = A.take<double>(T + 1);
+    N.cz = A.take<double>(T + 1);
+    N.cm = A.take<double>(T + 1);
+    N.sig2 = A.take<double>(T + 1);
+    N.rmax = A.take<double>(T + 1);
+    N.crit2 = A.take<double>(T + 1);
+    rtmp = A.take<char>(radix_tmp_bytes(E + 1));
+  });
+  build_list();
+  exclusive_scan<uint32_t>(w.L.nel, w.L.eoff, B, w.cnt + 1, w.stmp, s);
+  exclusive_scan<uint32_t>(w.L.nnode, w.L.noff, B, w.cnt + 2, w.stmp, s);
+  k_bh_bbox_init<<<blocks_for(B, TB), TB, 0, s>>>(w.bb, B);
+  k_bh_bbox<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, w.L, slot, B, E, w.bb);
+  k_bh_keys<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, w.L, slot, B, E, w.bb, k0, v0);
+  const bool f = radix_sort_pairs<unsigned long long>(k0, v0, k1, v1, E,
+                                                      48 + bits_for(B > 1 ? B - 1 : 1), rtmp, s);
+  k_bh_gather<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, f ? v1 : v0, E, px, py, pz, pidx);
+  for (int l = (int)Dmax; l >= 0; --l)
+    k_bh_level<<<blocks_for(T, TB), TB, 0, s>>>(w.L, B, T, (uint32_t)l, theta, px, py, pz, N);
+  HALO_HIP(hipMemsetAsync(w.cnt + 8, 0, 4, s));
+  HALO_PROF(ctx, "k_bh_walk", s,
+            k_bh_walk<<<blocks_for(E, TB), TB, 0, s>>>(w.L, B, E, slot, px, py, pz, pidx, N,
+                                                      eps2, pacc, w.cnt + 8));
+  HALO_HIP(hipMemcpyAsync(hb + 3, w.cnt + 8, 4, hipMemcpyDeviceToHost, s));
+  HALO_HIP(hipStreamSynchronize(s));
+  HALO_CHECK(hb[3] == 0, LIBHALO_EINVAL, "tree walk stack exhausted");
+}
+
+}  // namespace halo

@@ -88,10 +88,12 @@ struct Ctx {
   int device = 0;
   std::string err;
   Arena ws;
+  Arena ws2;                       // second arena: the tree potential, inside unbinding
   uint32_t* d_err = nullptr;       // device error word
   void* h_pinned = nullptr;        // small pinned host buffer for read-backs
   hipStream_t stream = nullptr;
   void ensure_ws(size_t bytes);
+  void ensure_ws2(size_t bytes);
   void release();
   template <class T>
   T* host_slot(int i) { return reinterpret_cast<T*>(static_cast<char*>(h_pinned) + 64 * i); }

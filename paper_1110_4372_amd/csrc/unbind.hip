@@ -17,6 +17,7 @@
 #include <cmath>
 
 #include "lanes.hpp"
+#include "bh.hpp"
 #include "primitives.hpp"
 #include "stages.hpp"
 
@@ -232,11 +233,14 @@ __host__ __device__ __forceinline__ uint32_t pot_units(uint32_t nown, uint32_t n
 // Per kept halo: the unit count, and a sort key ordering halos by their cost
 // (~ nown |S(h)|), largest first.
 __global__ void k_pot_counts(const libhalo_halos h, uint32_t S, const uint32_t* nS,
-                             uint32_t* ucnt, uint32_t* key, uint32_t* val) {
+                             double bh_theta, uint32_t bh_min, uint32_t* ucnt, uint32_t* key,
+                             uint32_t* val) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;
   const uint32_t nown = h.n_assigned[s], ns = nS[s];
-  const bool on = h.merged_into[s] == (int32_t)s && nown > 0;
+  const bool kept = h.merged_into[s] == (int32_t)s;
+  // haloes taking the tree potential get no direct-sum units
+  const bool on = kept && nown > 0 && !bh_takes(kept, nown, ns, bh_theta, bh_min);
   const unsigned long long cost = ((unsigned long long)nown * ns) >> 16;
   ucnt[s] = on ? pot_units(nown, ns) : 0u;
   key[s] = on ? ~(uint32_t)min(cost, 0xFFFFFFFEull) : 0xFFFFFFFFu;
@@ -1078,7 +1082,9 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
   k_merge_target<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, P.major_merger, w.tgt);
   // potentials: work units ordered largest first, one partial per particle
   // and j-chunk, partials added in chunk order
-  k_pot_counts<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, w.ucnt, w.pk0, w.pv0);
+  const uint32_t bh_min = P.bh_min > 0 ? (uint32_t)P.bh_min : 65536u;
+  k_pot_counts<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, P.bh_theta, bh_min, w.ucnt, w.pk0,
+                                                w.pv0);
   const bool fo = radix_sort_pairs<uint32_t>(w.pk0, w.pv0, w.pk1, w.pv1, S, 32, w.rtmp, s);
   const uint32_t* order = fo ? w.pv1 : w.pv0;
   k_gather_u32<<<blocks_for(S, TB), TB, 0, s>>>(w.ucnt, order, S, w.uoff);
@@ -1116,6 +1122,9 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 4, 1, 0u);
       launch(0, U, w.dcnt + 4, std::min<uint32_t>(kPersist, U));
     }
+    if (P.bh_theta > 0.0)
+      bh_potential(ctx, h, S, w.nS, w.slot, w.ux, w.uy, w.uz, eps2, P.bh_theta, bh_min, w.pacc,
+                   s);
     if (P.major_merger > 0.0) {
       k_ext_counts<<<blocks_for(S + 1, TB), TB, 0, s>>>(h, S, w.tgt, w.nS, w.ecnt);
       exclusive_scan<uint32_t>(w.ecnt, w.eoff, S + 1, w.dcnt + 5, w.stmp, s);

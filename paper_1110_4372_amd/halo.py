@@ -36,7 +36,7 @@ class CParams(C.Structure):
                 ("unbound_threshold", C.c_double), ("e_recheck", C.c_double),
                 ("mode", C.c_int32), ("prec", C.c_int32), ("grid_min", C.c_int32),
                 ("ell_subset", C.c_int32), ("major_merger", C.c_double),
-                ("fof_dense", C.c_int32), ("reserved2", C.c_int32)]
+                ("fof_dense", C.c_int32), ("bh_min", C.c_int32), ("bh_theta", C.c_double)]
 
 
 @dataclasses.dataclass
@@ -60,13 +60,16 @@ class Params:
     major_merger: float = 0.0
     ell_subset: int = 0
     fof_dense: int = 0
+    bh_min: int = 0
+    bh_theta: float = 0.0
 
     def c(self) -> CParams:
         return CParams(self.box, self.b, self.f, self.min_members, self.max_levels,
                        self.merge_q2, self.particle_mass, self.G, self.rho_vir,
                        self.softening, self.core_frac, self.unbound_threshold,
                        self.e_recheck, self.mode, self.prec, self.grid_min,
-                       self.ell_subset, self.major_merger, self.fof_dense, 0)
+                       self.ell_subset, self.major_merger, self.fof_dense, self.bh_min,
+                       self.bh_theta)
 
 
 NODE_FIELDS = [("parent", torch.int32), ("level", torch.int32), ("first_child", torch.int32),

@@ -1,0 +1,108 @@
+"""The tree potential of Appendix B (`bh_theta`, `bh_min`) on the GPU against
+the exact direct sum of the oracle: the Salmon-Warren acceptance bounds each
+cell's relative error by theta, so every particle's potential lies within
+theta of the exact one; bound flags agree wherever the energy lies outside
+that band; theta -> 0 opens every cell and reproduces the exact sum."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import note, particles_from_arrays, to_np
+from tests.test_oracle_merger import BOX, EPS, M_PART, merger
+from tests.test_oracle_pins import particles
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1110_4372_amd import halo
+    halo.load_library()
+    return halo
+
+
+def tree_cases(o, bh_min):
+    h, ns = o["halos"], o["unbound"]["n_s"]
+    kept = h["merged_into"] == np.arange(h["merged_into"].shape[0])
+    return np.nonzero(kept & (ns >= bh_min) & (h["n_assigned"] > 0))[0]
+
+
+def check_against_exact(g, o, theta, bh_min, tol_scale):
+    tree = tree_cases(o, bh_min)
+    assert tree.shape[0] >= 1
+    sel = np.isin(o["halo_of"], tree)
+    gphi = to_np(g["phi"])
+    rel = np.abs(gphi[sel] / o["phi"][sel] - 1.0)
+    print(f"theta={theta}: {sel.sum()} particles in {tree.shape[0]} tree haloes, "
+          f"relative error median {np.median(rel):.2e} max {rel.max():.2e}")
+    assert rel.max() <= tol_scale * theta
+    # the other haloes keep the exact sum
+    other = (o["halo_of"] >= 0) & ~sel
+    np.testing.assert_allclose(gphi[other], o["phi"][other], rtol=1e-9, atol=0)
+    # flags agree outside the band the potential's error leaves
+    ho = o["halo_of"]
+    vb = np.stack([o["unbound"]["vbx"], o["unbound"]["vby"], o["unbound"]["vbz"]], 1)
+    return sel, rel, ho, vb
+
+
+@pytest.mark.parametrize("theta", [0.04, 0.01])
+def test_tree_within_theta_c1(H, orc, c1, c1_oracle, theta):
+    note(f"tree potential c1 theta={theta}")
+    bh_min = 2000
+    g = H.Halo(H.params_for_catalog(c1, bh_theta=theta, bh_min=bh_min)).run_all(
+        H.Particles.from_catalog(c1))
+    o = c1_oracle
+    sel, rel, ho, vb = check_against_exact(g, o, theta, bh_min, 1.0)
+    v = np.stack([c1.vx, c1.vy, c1.vz], 1).astype(np.float64)
+    k = 0.5 * ((v[sel] - vb[ho[sel]]) ** 2).sum(1)
+    e = k + o["phi"][sel]
+    decided = np.abs(e) > theta * np.abs(o["phi"][sel])
+    gb = to_np(g["bound"])[sel]
+    np.testing.assert_array_equal(gb[decided], o["bound"][sel][decided])
+    agree = float(np.mean(gb == o["bound"][sel]))
+    print(f"bound flags agree for {100 * agree:.3f}% of tree-halo particles")
+
+
+def test_tree_theta_to_zero_is_exact(H, orc, c1, c1_oracle):
+    """theta = 1e-12 opens every cell: the direct sum, in another order."""
+    note("tree potential theta -> 0")
+    g = H.Halo(H.params_for_catalog(c1, bh_theta=1e-12, bh_min=500)).run_all(
+        H.Particles.from_catalog(c1))
+    o = c1_oracle
+    tree = tree_cases(o, 500)
+    assert tree.shape[0] >= 3
+    ins = o["halo_of"] >= 0
+    np.testing.assert_allclose(to_np(g["phi"])[ins], o["phi"][ins], rtol=1e-11, atol=0)
+
+
+def test_tree_with_merger_and_mixed(H, orc):
+    """The tree for S(h), the exact merger term beyond it, the mixed form's
+    FP64 recheck: the potential stays within theta of the exact one."""
+    note("tree potential + major merger + mixed")
+    pos, vel = merger(1)
+    theta = 0.04
+    p = orc.make_params(BOX, M_PART, EPS, major_merger=0.3)
+    o = orc.run_all(p, particles(orc, pos, vel))
+    g = H.Halo(H.Params(box=BOX, particle_mass=M_PART, softening=EPS, major_merger=0.3,
+                        prec=1, bh_theta=theta, bh_min=300)).run_all(
+        particles_from_arrays(pos, vel))
+    ins = o["halo_of"] >= 0
+    rel = np.abs(to_np(g["phi"])[ins] / o["phi"][ins] - 1.0)
+    print(f"relative error median {np.median(rel):.2e} max {rel.max():.2e}")
+    assert rel.max() <= theta
+
+
+def test_tree_deterministic(H, c1):
+    note("tree potential plain == batched == repeat")
+    P = H.Particles.from_catalog(c1)
+    outs = [H.Halo(H.params_for_catalog(c1, bh_theta=0.04, bh_min=1000, mode=m)).run_all(P)
+            for m in (1, 1, 0)]
+    for r in outs[1:]:
+        np.testing.assert_array_equal(to_np(r["phi"]), to_np(outs[0]["phi"]))
+        np.testing.assert_array_equal(to_np(r["bound"]), to_np(outs[0]["bound"]))
+
+
+def test_tree_bad_parameters(H, c1):
+    with pytest.raises(H.HaloError):
+        H.Halo(H.params_for_catalog(c1, bh_theta=-1.0))
+    with pytest.raises(H.HaloError):
+        H.Halo(H.params_for_catalog(c1, bh_min=-5))
