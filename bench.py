@@ -346,6 +346,51 @@ def dense_report(H, cat, P, grid_min, prec, t=16, steps=3):
             "particles_in_grown_groups": int((b["size"] != a["size"]).sum())}
 
 
+def tree_report(H, cat, P, grid_min, prec, theta=0.04, bh_min=65536):
+    """The tree potential of Appendix B (bh_theta = 0.04, haloes with |S(h)| >=
+    bh_min) against the exact direct sum, outside the timed steps, on the same
+    halo table: unbind device time of each, the relative error of the tree
+    haloes' potentials, and their bound flags that differ."""
+    import numpy as np
+    import torch
+    ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=grid_min))
+    fof = ctx.fof3d(P)
+    nodes, deep = ctx.refine6d(P, fof)
+    halos, hof = ctx.assign(P, nodes, deep)
+    out = {}
+    for th in (0.0, theta):
+        c = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=grid_min,
+                                        bh_theta=th, bh_min=bh_min))
+        c.unbind(P, halos, hof)  # warm-up
+        torch.cuda.synchronize()
+        c.profile(True)
+        c.profile_reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        unb, bound, phi = c.unbind(P, halos, hof)
+        e1.record()
+        torch.cuda.synchronize()
+        walk = c.profile_read("k_bh_walk")
+        c.profile(False)
+        out[th] = dict(ms=e0.elapsed_time(e1), walk_ms=walk[0], unb=unb, bound=bound, phi=phi)
+    a, b = out[0.0], out[theta]
+    h = {k: v.cpu().numpy() for k, v in halos.items()}
+    ns = a["unb"]["n_s"].cpu().numpy()
+    kept = h["merged_into"] == np.arange(h["merged_into"].shape[0])
+    tree = np.nonzero(kept & (ns >= bh_min) & (h["n_assigned"] > 0))[0]
+    hofn = hof.cpu().numpy()
+    sel = np.isin(hofn, tree)
+    pa, pb = a["phi"].cpu().numpy()[sel], b["phi"].cpu().numpy()[sel]
+    rel = np.abs(pb / pa - 1.0) if pa.size else np.zeros(1)
+    ba, bb = a["bound"].cpu().numpy()[sel], b["bound"].cpu().numpy()[sel]
+    return {"bh_theta": theta, "bh_min": bh_min, "tree_haloes": int(tree.shape[0]),
+            "tree_particles": int(sel.sum()), "unbind_ms_exact": a["ms"],
+            "unbind_ms_tree": b["ms"], "walk_ms": b["walk_ms"],
+            "rel_err_median": float(np.median(rel)), "rel_err_max": float(rel.max()),
+            "flags_differ": int((ba != bb).sum()),
+            "flags_agree_fraction": float(np.mean(ba == bb)) if ba.size else 1.0}
+
+
 def cpu_baseline(cat, budget_s: float = 20.0):
     """The CPU oracle (serial FP64 C) on a sub-volume of the catalogue: the
     particles of the corner cube [0, L/k)^3, treated as a periodic box of side
@@ -394,6 +439,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other precision form and the mixed-vs-FP64 comparison")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-tree", action="store_true",
+                    help="skip the tree-potential comparison (not part of the step)")
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense-particle FOF variant comparison (not part of the step)")
     ap.add_argument("--no-subset", action="store_true",
@@ -502,6 +549,9 @@ def main():
     merger = None if args.no_merger else merger_report(H, cat, P, args.grid_min, prec)
     subset = None if args.no_subset else subset_report(H, cat, P, args.grid_min, prec)
     dense = None if args.no_dense else dense_report(H, cat, P, args.grid_min, prec)
+    tree = None if args.no_tree else tree_report(H, cat, P, args.grid_min, prec)
+    if tree is not None:
+        progress("tree potential timed")
     if dense is not None:
         progress("dense-particle FOF variant timed")
     if subset is not None:
@@ -539,6 +589,7 @@ def main():
         "merger": merger,
         "subset": subset,
         "fof_dense": dense,
+        "tree": tree,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -250,28 +250,48 @@ __global__ void k_bh_level(BhList L, uint32_t B, uint32_t T, uint32_t level, dou
   N.crit2[g] = dc * dc;
 }
 
-// One own particle per thread (sorted order; other elements idle): the walk.
+// Wave units of each tree halo: its sorted elements in runs of 64.
+__global__ void k_bh_wave_counts(BhList L, uint32_t B, uint32_t* wcnt) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  wcnt[b] = (L.nel[b] + 63u) / 64u;
+}
+
+// The walk, one wavefront per 64 consecutive sorted elements of one halo
+// (spatially close along the curve); lanes holding an own particle are the
+// targets, the others only ride along.  The wave walks one tree: a cell is
+// taken as a monopole when it is acceptable for every target lane, else it
+// is opened for all (which only makes the others more exact).  Node data are
+// wave-uniform (scalar loads), the stack is wave-uniform, and each lane sums
+// its terms in the wave's fixed order.
 __global__ void __launch_bounds__(TB)
-    k_bh_walk(BhList L, uint32_t B, uint32_t E, const uint32_t* slot, const double* px,
-              const double* py, const double* pz, const uint32_t* pidx, BhNodes N,
-              double eps2, I128* pacc, uint32_t* err) {
-  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E) return;
-  const uint32_t b = seg_find(L.eoff, B, e);
-  const uint32_t q = pidx[e];
-  if (q - slot[L.big[b]] >= L.nown[b]) return;  // a subhalo particle: source only
-  const double x = px[e], y = py[e], z = pz[e];
+    k_bh_walk(BhList L, uint32_t B, const uint32_t* woff, uint32_t nwave, const uint32_t* slot,
+              const double* px, const double* py, const double* pz, const uint32_t* pidx,
+              BhNodes N, double eps2, I128* pacc, uint32_t* err) {
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (TB / 64) +
+                                                       (threadIdx.x >> 6));
+  if (wave >= nwave) return;  // wave-uniform
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t b = __builtin_amdgcn_readfirstlane(seg_find(woff, B, wave));
   const uint32_t n = L.nel[b], D = L.depth[b], nb = L.noff[b], base = L.eoff[b];
-  uint32_t stack[kStack];
+  const uint32_t s0 = slot[L.big[b]], nown = L.nown[b];
+  const uint32_t e = base + (wave - woff[b]) * 64u + lane;
+  const bool in = e < base + n;
+  const uint32_t q = in ? pidx[e] : 0xFFFFFFFFu;
+  const bool target = in && (q - s0) < nown;
+  if (__ballot(target) == 0ull) return;  // wave-uniform
+  const double x = in ? px[e] : 0.0, y = in ? py[e] : 0.0, z = in ? pz[e] : 0.0;
+  uint32_t stack[kStack];  // wave-uniform contents
   int sp = 0;
   stack[sp++] = 1u;
   double acc = 0.0;
   while (sp > 0) {
-    const uint32_t k = stack[--sp];
+    const uint32_t k = __builtin_amdgcn_readfirstlane(stack[--sp]);
     const uint32_t g = nb + k;
-    const double d2 = sq3(x - N.cx[g], y - N.cy[g], z - N.cz[g]);
-    if (d2 >= N.crit2[g]) {
-      acc += N.cm[g] * rsqrt_f64(d2 + eps2);
+    const double cx = N.cx[g], cy = N.cy[g], cz = N.cz[g], cm = N.cm[g], c2 = N.crit2[g];
+    const double d2 = sq3(x - cx, y - cy, z - cz);
+    if (__ballot(target && d2 < c2) == 0ull) {
+      if (target) acc += cm * rsqrt_f64(d2 + eps2);
       continue;
     }
     const uint32_t l = 31u - (uint32_t)__builtin_clz(k);
@@ -279,19 +299,20 @@ __global__ void __launch_bounds__(TB)
       uint32_t lo, hi;
       node_range(k, n, lo, hi);
       for (uint32_t f = base + lo; f < base + hi; ++f) {
-        if (pidx[f] == q) continue;
-        acc += rsqrt_f64(sq3(x - px[f], y - py[f], z - pz[f]) + eps2);
+        const double fx = px[f], fy = py[f], fz = pz[f];
+        const uint32_t qf = pidx[f];
+        if (target && qf != q) acc += rsqrt_f64(sq3(x - fx, y - fy, z - fz) + eps2);
       }
       continue;
     }
     if (sp + 2 > kStack) {  // cannot happen for depth <= 31; reported, not faulted
-      atomicOr(err, 1u);
+      if (lane == 0) atomicOr(err, 1u);
       break;
     }
     stack[sp++] = 2u * k + 1u;
     stack[sp++] = 2u * k;
   }
-  if (acc > 0.0) atomic_add_i128(pacc + q, fixed128(acc, kFrac));
+  if (target && acc > 0.0) atomic_add_i128(pacc + q, fixed128(acc, kFrac));
 }
 
 template <class F>
@@ -395,10 +416,16 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   k_bh_gather<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, f ? v1 : v0, E, px, py, pz, pidx);
   for (int l = (int)Dmax; l >= 0; --l)
     k_bh_level<<<blocks_for(T, TB), TB, 0, s>>>(w.L, B, T, (uint32_t)l, theta, px, py, pz, N);
+  // wave units: runs of 64 sorted elements within each halo
+  k_bh_wave_counts<<<blocks_for(B, TB), TB, 0, s>>>(w.L, B, w.flag);
+  exclusive_scan<uint32_t>(w.flag, w.pos, B, w.cnt + 3, w.stmp, s);
+  HALO_HIP(hipMemcpyAsync(hb + 4, w.cnt + 3, 4, hipMemcpyDeviceToHost, s));
   HALO_HIP(hipMemsetAsync(w.cnt + 8, 0, 4, s));
+  HALO_HIP(hipStreamSynchronize(s));
+  const uint32_t nwave = hb[4];
   HALO_PROF(ctx, "k_bh_walk", s,
-            k_bh_walk<<<blocks_for(E, TB), TB, 0, s>>>(w.L, B, E, slot, px, py, pz, pidx, N,
-                                                      eps2, pacc, w.cnt + 8));
+            k_bh_walk<<<blocks_for((int64_t)nwave * 64, TB), TB, 0, s>>>(
+                w.L, B, w.pos, nwave, slot, px, py, pz, pidx, N, eps2, pacc, w.cnt + 8));
   HALO_HIP(hipMemcpyAsync(hb + 3, w.cnt + 8, 4, hipMemcpyDeviceToHost, s));
   HALO_HIP(hipStreamSynchronize(s));
   HALO_CHECK(hb[3] == 0, LIBHALO_EINVAL, "tree walk stack exhausted");
