@@ -346,43 +346,48 @@ def dense_report(H, cat, P, grid_min, prec, t=16, steps=3):
             "particles_in_grown_groups": int((b["size"] != a["size"]).sum())}
 
 
-def tree_report(H, cat, P, grid_min, prec, theta=0.04, bh_min=65536):
+def tree_report(ctx, P, out, theta=0.04, bh_min=65536):
     """The tree potential of Appendix B (bh_theta = 0.04, haloes with |S(h)| >=
-    bh_min) against the exact direct sum, outside the timed steps, on the same
-    halo table: unbind device time of each, the relative error of the tree
-    haloes' potentials, and their bound flags that differ."""
+    bh_min) against the exact direct sum, outside the timed steps, on the
+    step's own halo table and context (no second workspace): unbind device
+    time of each, the relative error of the tree haloes' potentials, and their
+    bound flags that differ."""
+    import dataclasses
     import numpy as np
     import torch
-    ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=grid_min))
-    fof = ctx.fof3d(P)
-    nodes, deep = ctx.refine6d(P, fof)
-    halos, hof = ctx.assign(P, nodes, deep)
-    out = {}
+    fof, nodes, halos, hof = out[:4]
+    base = ctx.params
+    res = {}
     for th in (0.0, theta):
-        c = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=grid_min,
-                                        bh_theta=th, bh_min=bh_min))
-        c.unbind(P, halos, hof)  # warm-up
-        torch.cuda.synchronize()
-        c.profile(True)
-        c.profile_reset()
+        ctx.set_params(dataclasses.replace(base, bh_theta=th, bh_min=bh_min))
+        if th > 0.0:  # the exact form is warm from the timed steps
+            ctx.unbind(P, halos, hof, want_phi=False)  # warm-up: the tree's workspace
+            torch.cuda.synchronize()
+            progress("tree form warmed up")
+        ctx.profile(True)
+        ctx.profile_reset()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        unb, bound, phi = c.unbind(P, halos, hof)
+        unb, bound, phi = ctx.unbind(P, halos, hof)
         e1.record()
         torch.cuda.synchronize()
-        walk = c.profile_read("k_bh_walk")
-        c.profile(False)
-        out[th] = dict(ms=e0.elapsed_time(e1), walk_ms=walk[0], unb=unb, bound=bound, phi=phi)
-    a, b = out[0.0], out[theta]
+        walk = ctx.profile_read("k_bh_walk")
+        ctx.profile(False)
+        progress(f"unbind timed with bh_theta = {th}")
+        hofn = hof.cpu().numpy()
+        res[th] = dict(ms=e0.elapsed_time(e1), walk_ms=walk[0],
+                       ns=unb["n_s"].cpu().numpy(), bound=bound.cpu().numpy(),
+                       phi=phi.cpu().numpy())
+        del unb, bound, phi
+    ctx.set_params(base)
+    a, b = res[0.0], res[theta]
     h = {k: v.cpu().numpy() for k, v in halos.items()}
-    ns = a["unb"]["n_s"].cpu().numpy()
     kept = h["merged_into"] == np.arange(h["merged_into"].shape[0])
-    tree = np.nonzero(kept & (ns >= bh_min) & (h["n_assigned"] > 0))[0]
-    hofn = hof.cpu().numpy()
+    tree = np.nonzero(kept & (a["ns"] >= bh_min) & (h["n_assigned"] > 0))[0]
     sel = np.isin(hofn, tree)
-    pa, pb = a["phi"].cpu().numpy()[sel], b["phi"].cpu().numpy()[sel]
+    pa, pb = a["phi"][sel], b["phi"][sel]
     rel = np.abs(pb / pa - 1.0) if pa.size else np.zeros(1)
-    ba, bb = a["bound"].cpu().numpy()[sel], b["bound"].cpu().numpy()[sel]
+    ba, bb = a["bound"][sel], b["bound"][sel]
     return {"bh_theta": theta, "bh_min": bh_min, "tree_haloes": int(tree.shape[0]),
             "tree_particles": int(sel.sum()), "unbind_ms_exact": a["ms"],
             "unbind_ms_tree": b["ms"], "walk_ms": b["walk_ms"],
@@ -441,6 +446,8 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-tree", action="store_true",
                     help="skip the tree-potential comparison (not part of the step)")
+    ap.add_argument("--bh-min", type=int, default=65536,
+                    help="smallest |S(h)| that takes the tree in the tree comparison")
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense-particle FOF variant comparison (not part of the step)")
     ap.add_argument("--no-subset", action="store_true",
@@ -549,7 +556,7 @@ def main():
     merger = None if args.no_merger else merger_report(H, cat, P, args.grid_min, prec)
     subset = None if args.no_subset else subset_report(H, cat, P, args.grid_min, prec)
     dense = None if args.no_dense else dense_report(H, cat, P, args.grid_min, prec)
-    tree = None if args.no_tree else tree_report(H, cat, P, args.grid_min, prec)
+    tree = None if args.no_tree else tree_report(ctx, P, out, bh_min=args.bh_min)
     if tree is not None:
         progress("tree potential timed")
     if dense is not None:
