@@ -28,8 +28,8 @@ FP32_PEAK_TFLOPS = 157.3
 # copy of known size).  Reported only while the kernel's source file is the
 # one that was measured.
 MEASURED_TRAFFIC = {
-    "k_potential_f64": {"bytes": 440.7e6, "src": "paper_1110_4372_amd/csrc/unbind.hip",
-                        "sha1": "ffe9c024d9e29573c1f2bf9cb9febd3ea7132fd4"},
+    "k_potential_f64": {"bytes": 436.1e6, "src": "paper_1110_4372_amd/csrc/unbind.hip",
+                        "sha1": "f429ab878fea3c10a77487c3dd41803290c1dcab"},
     "k_nn": {"bytes": 88.8e6, "src": "paper_1110_4372_amd/csrc/refine6d.hip",
              "sha1": "6bd7a03261fa2ac406100f0bea80070a6d21f0f6"},
 }
