@@ -6,8 +6,8 @@
 // their bounding box, and the tree is implicit over that order: heap node k
 // at level l covers the sorted range [floor(i n / 2^l), floor((i+1) n / 2^l))
 // with i = k - 2^l, down to leaves of at most 17 particles.  A cell's mass
-// centre x0, its dispersion sigma^2 about x0 and r_max (exact in the leaves,
-// an upper bound above, which keeps the criterion conservative) give the
+// centre x0, its dispersion sigma^2 about x0 and r_max (the largest distance
+// of its particles from x0, found by a pass over the particles) give the
 // acceptance distance d >= r_max / 2 + sqrt((r_max / 2)^2 + sigma^2 / theta),
 // beyond which the monopole's relative error is at most theta.  One thread
 // per own particle, in Morton order so that a wave's walks coincide, walks the
@@ -250,6 +250,65 @@ __global__ void k_bh_level(BhList L, uint32_t B, uint32_t T, uint32_t level, dou
   N.crit2[g] = dc * dc;
 }
 
+// Node of level l holding sorted position p of a halo of n particles: the i
+// with floor(i n / 2^l) <= p < floor((i + 1) n / 2^l).
+__device__ __forceinline__ uint32_t node_at(uint32_t p, uint32_t n, uint32_t l) {
+  unsigned long long i = (((unsigned long long)p) << l) / n;
+  while (((i + 1ull) * n >> l) <= p) ++i;
+  while (i > 0 && ((i * n) >> l) > p) --i;
+  return (1u << l) + (uint32_t)i;
+}
+
+// Exact r_max of every cell: each particle raises the maximum of its cell on
+// every level (as ordered integers; a wave whose particles share a cell sends
+// one atomic for it).
+__global__ void k_bh_rmax_init(unsigned long long* rm, uint32_t T) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < T) rm[t] = 0ull;
+}
+
+__global__ void k_bh_rmax(BhList L, uint32_t B, uint32_t E, const double* px, const double* py,
+                          const double* pz, BhNodes N, unsigned long long* rm) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = e < E;
+  const uint32_t b = ok ? seg_find(L.eoff, B, e) : 0u;
+  const uint32_t D = ok ? L.depth[b] : 0u;
+  // every lane runs the same number of levels (the wave maximum) for the
+  // wave-wide exchanges; lanes past their own depth or range stay idle
+  uint32_t Dm = D;
+  for (int o = 32; o > 0; o >>= 1) Dm = max(Dm, (uint32_t)__shfl_xor((int)Dm, o));
+  for (uint32_t l = 0; l <= Dm; ++l) {
+    const bool act = ok && l <= D;
+    uint32_t g = 0xFFFFFFFFu;
+    unsigned long long v = 0ull;
+    if (act) {
+      const uint32_t k = node_at(e - L.eoff[b], L.nel[b], l);
+      g = L.noff[b] + k;
+      v = f64_ord(sqrt(sq3(px[e] - N.cx[g], py[e] - N.cy[g], pz[e] - N.cz[g])));
+    }
+    const uint32_t g0 = __shfl(g, 0);
+    if (__all(g == g0) && g0 != 0xFFFFFFFFu) {
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w2 = __shfl_xor(v, o);
+        v = w2 > v ? w2 : v;
+      }
+      if ((threadIdx.x & 63u) == 0) atomicMax(rm + g0, v);
+    } else if (act) {
+      atomicMax(rm + g, v);
+    }
+  }
+}
+
+// Acceptance distances from the exact r_max.
+__global__ void k_bh_crit(uint32_t T, double theta, const unsigned long long* rm, BhNodes N) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T || rm[t] == 0ull) return;  // index 0 of each heap is unused
+  const double r = ord_f64(rm[t]);
+  N.rmax[t] = r;
+  const double dc = 0.5 * r + sqrt(0.25 * r * r + N.sig2[t] / theta);
+  N.crit2[t] = dc * dc;
+}
+
 // Wave units of each tree halo: its sorted elements in runs of 64.
 __global__ void k_bh_wave_counts(BhList L, uint32_t B, uint32_t* wcnt) {
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -262,12 +321,13 @@ __global__ void k_bh_wave_counts(BhList L, uint32_t B, uint32_t* wcnt) {
 // targets, the others only ride along.  The wave walks one tree: a cell is
 // taken as a monopole when it is acceptable for every target lane, else it
 // is opened for all (which only makes the others more exact).  Node data are
-// wave-uniform (scalar loads), the stack is wave-uniform, and each lane sums
+// wave-uniform (scalar loads), the stack is the wave's own in LDS, and each lane sums
 // its terms in the wave's fixed order.
 __global__ void __launch_bounds__(TB)
     k_bh_walk(BhList L, uint32_t B, const uint32_t* woff, uint32_t nwave, const uint32_t* slot,
               const double* px, const double* py, const double* pz, const uint32_t* pidx,
               BhNodes N, double eps2, I128* pacc, uint32_t* err) {
+  __shared__ uint32_t wstack[TB / 64][kStack];
   const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (TB / 64) +
                                                        (threadIdx.x >> 6));
   if (wave >= nwave) return;  // wave-uniform
@@ -281,7 +341,7 @@ __global__ void __launch_bounds__(TB)
   const bool target = in && (q - s0) < nown;
   if (__ballot(target) == 0ull) return;  // wave-uniform
   const double x = in ? px[e] : 0.0, y = in ? py[e] : 0.0, z = in ? pz[e] : 0.0;
-  uint32_t stack[kStack];  // wave-uniform contents
+  uint32_t* stack = wstack[threadIdx.x >> 6];  // the wave's own LDS stack
   int sp = 0;
   stack[sp++] = 1u;
   double acc = 0.0;
@@ -385,6 +445,7 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   uint32_t *v0, *v1, *pidx;
   double *px, *py, *pz;
   BhNodes N;
+  unsigned long long* rmx;
   void* rtmp;
   carve2(ctx, [&](Arena& A) {
     take_list(A);
@@ -403,6 +464,7 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
     N.sig2 = A.take<double>(T + 1);
     N.rmax = A.take<double>(T + 1);
     N.crit2 = A.take<double>(T + 1);
+    rmx = A.take<unsigned long long>(T + 1);
     rtmp = A.take<char>(radix_tmp_bytes(E + 1));
   });
   build_list();
@@ -416,6 +478,10 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   k_bh_gather<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, f ? v1 : v0, E, px, py, pz, pidx);
   for (int l = (int)Dmax; l >= 0; --l)
     k_bh_level<<<blocks_for(T, TB), TB, 0, s>>>(w.L, B, T, (uint32_t)l, theta, px, py, pz, N);
+  // exact r_max in place of the children's bound: a tighter acceptance distance
+  k_bh_rmax_init<<<blocks_for(T, TB), TB, 0, s>>>(rmx, T);
+  k_bh_rmax<<<blocks_for(E, TB), TB, 0, s>>>(w.L, B, E, px, py, pz, N, rmx);
+  k_bh_crit<<<blocks_for(T, TB), TB, 0, s>>>(T, theta, rmx, N);
   // wave units: runs of 64 sorted elements within each halo
   k_bh_wave_counts<<<blocks_for(B, TB), TB, 0, s>>>(w.L, B, w.flag);
   exclusive_scan<uint32_t>(w.flag, w.pos, B, w.cnt + 3, w.stmp, s);
