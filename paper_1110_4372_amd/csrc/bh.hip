@@ -9,11 +9,12 @@
 // centre x0, its dispersion sigma^2 about x0 and r_max (the largest distance
 // of its particles from x0, found by a pass over the particles) give the
 // acceptance distance d >= r_max / 2 + sqrt((r_max / 2)^2 + sigma^2 / theta),
-// beyond which the monopole's relative error is at most theta.  One thread
-// per own particle, in Morton order so that a wave's walks coincide, walks the
-// tree depth first: accepted cells add m / sqrt(d^2 + eps^2), opened leaves
-// their particles one by one.  Each walk sums in a fixed order, so the result
-// does not depend on scheduling.
+// beyond which the monopole's relative error is at most theta.  One wavefront
+// per 64 Morton-consecutive particles walks the tree depth first: a cell
+// acceptable for every target lane adds m / sqrt(d^2 + eps^2) to each, any
+// other cell is opened for all, and opened leaves add their particles one by
+// one.  Each lane sums in the wave's fixed order, so the result does not
+// depend on scheduling.
 #include <algorithm>
 #include <cmath>
 #include <vector>
