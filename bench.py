@@ -361,6 +361,8 @@ def tree_report(ctx, P, out, theta=0.04, bh_min=65536):
     for th in (0.0, theta):
         ctx.set_params(dataclasses.replace(base, bh_theta=th, bh_min=bh_min))
         if th > 0.0:  # the exact form is warm from the timed steps
+            # the library allocates outside torch's cache: return torch's idle blocks first
+            torch.cuda.empty_cache()
             ctx.unbind(P, halos, hof, want_phi=False)  # warm-up: the tree's workspace
             torch.cuda.synchronize()
             progress("tree form warmed up")

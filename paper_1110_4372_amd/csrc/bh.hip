@@ -171,14 +171,13 @@ __global__ void k_bh_keys(const double* ux, const double* uy, const double* uz, 
 
 __global__ void k_bh_gather(const double* ux, const double* uy, const double* uz,
                             const uint32_t* sval, uint32_t E, double* px, double* py,
-                            double* pz, uint32_t* pidx) {
+                            double* pz) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
   const uint32_t q = sval[e];
   px[e] = ux[q];
   py[e] = uy[q];
   pz[e] = uz[q];
-  pidx[e] = q;
 }
 
 struct BhNodes {
@@ -376,12 +375,23 @@ __global__ void __launch_bounds__(TB)
   if (target && acc > 0.0) atomic_add_i128(pacc + q, fixed128(acc, kFrac));
 }
 
+// The step workspace past the unbinding's own carve is idle while the tree runs:
+// the tree takes it when it fits and its own workspace only when it does not.
 template <class F>
 void carve2(Ctx& ctx, F&& carve) {
   Arena dry;
   dry.counting = true;
   carve(dry);
-  ctx.ensure_ws2(dry.off + 4096);
+  const size_t need = dry.off + 4096;
+  const size_t start = (ctx.ws.off + 255) & ~size_t(255);
+  if (ctx.ws.base && start <= ctx.ws.cap && need <= ctx.ws.cap - start) {
+    Arena tail;
+    tail.base = ctx.ws.base + start;
+    tail.cap = ctx.ws.cap - start;
+    carve(tail);
+    return;
+  }
+  ctx.ensure_ws2(need);
   ctx.ws2.reset();
   carve(ctx.ws2);
 }
@@ -443,8 +453,8 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   HALO_CHECK(Dmax <= 31u, LIBHALO_EINVAL, "tree deeper than 31 levels");
   // second carve with the element and node arrays; the list is rebuilt in it
   unsigned long long *k0, *k1;
-  uint32_t *v0, *v1, *pidx;
-  double *px, *py, *pz;
+  uint32_t *v0, *v1;
+  double* pz;
   BhNodes N;
   unsigned long long* rmx;
   void* rtmp;
@@ -454,9 +464,6 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
     k1 = A.take<unsigned long long>(E + 1);
     v0 = A.take<uint32_t>(E + 1);
     v1 = A.take<uint32_t>(E + 1);
-    pidx = A.take<uint32_t>(E + 1);
-    px = A.take<double>(E + 1);
-    py = A.take<double>(E + 1);
     pz = A.take<double>(E + 1);
     N.cx = A.take<double>(T + 1);
     N.cy = A.take<double>(T + 1);
@@ -476,7 +483,12 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   k_bh_keys<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, w.L, slot, B, E, w.bb, k0, v0);
   const bool f = radix_sort_pairs<unsigned long long>(k0, v0, k1, v1, E,
                                                       48 + bits_for(B > 1 ? B - 1 : 1), rtmp, s);
-  k_bh_gather<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, f ? v1 : v0, E, px, py, pz, pidx);
+  // after the sort the keys are dead: x and y of the sorted positions take their place, and
+  // the sorted values are the particle slots
+  const uint32_t* pidx = f ? v1 : v0;
+  double* px = reinterpret_cast<double*>(k0);
+  double* py = reinterpret_cast<double*>(k1);
+  k_bh_gather<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, pidx, E, px, py, pz);
   for (int l = (int)Dmax; l >= 0; --l)
     k_bh_level<<<blocks_for(T, TB), TB, 0, s>>>(w.L, B, T, (uint32_t)l, theta, px, py, pz, N);
   // exact r_max in place of the children's bound: a tighter acceptance distance
