@@ -342,20 +342,19 @@ __global__ void __launch_bounds__(TB)
   if (__ballot(target) == 0ull) return;  // wave-uniform
   const double x = in ? px[e] : 0.0, y = in ? py[e] : 0.0, z = in ? pz[e] : 0.0;
   uint32_t* stack = wstack[threadIdx.x >> 6];  // the wave's own LDS stack
+  // Depth-first, left child first: an opened cell goes on to its left child at
+  // once and leaves only the right one on the stack (at most one entry per level).
   int sp = 0;
-  stack[sp++] = 1u;
+  uint32_t k = 1u;
   double acc = 0.0;
-  while (sp > 0) {
-    const uint32_t k = __builtin_amdgcn_readfirstlane(stack[--sp]);
+  for (;;) {
     const uint32_t g = nb + k;
     const double cx = N.cx[g], cy = N.cy[g], cz = N.cz[g], cm = N.cm[g], c2 = N.crit2[g];
     const double d2 = sq3(x - cx, y - cy, z - cz);
+    const uint32_t l = 31u - (uint32_t)__builtin_clz(k);
     if (__ballot(target && d2 < c2) == 0ull) {
       if (target) acc += cm * rsqrt_f64(d2 + eps2);
-      continue;
-    }
-    const uint32_t l = 31u - (uint32_t)__builtin_clz(k);
-    if (l == D) {
+    } else if (l == D) {
       uint32_t lo, hi;
       node_range(k, n, lo, hi);
       for (uint32_t f = base + lo; f < base + hi; ++f) {
@@ -363,14 +362,17 @@ __global__ void __launch_bounds__(TB)
         const uint32_t qf = pidx[f];
         if (target && qf != q) acc += rsqrt_f64(sq3(x - fx, y - fy, z - fz) + eps2);
       }
+    } else {
+      if (sp + 1 > kStack) {  // cannot happen for depth <= 31; reported, not faulted
+        if (lane == 0) atomicOr(err, 1u);
+        break;
+      }
+      stack[sp++] = 2u * k + 1u;
+      k = 2u * k;
       continue;
     }
-    if (sp + 2 > kStack) {  // cannot happen for depth <= 31; reported, not faulted
-      if (lane == 0) atomicOr(err, 1u);
-      break;
-    }
-    stack[sp++] = 2u * k + 1u;
-    stack[sp++] = 2u * k;
+    if (sp == 0) break;
+    k = __builtin_amdgcn_readfirstlane(stack[--sp]);
   }
   if (target && acc > 0.0) atomic_add_i128(pacc + q, fixed128(acc, kFrac));
 }

@@ -106,3 +106,21 @@ def test_tree_bad_parameters(H, c1):
         H.Halo(H.params_for_catalog(c1, bh_theta=-1.0))
     with pytest.raises(H.HaloError):
         H.Halo(H.params_for_catalog(c1, bh_min=-5))
+
+
+def test_tree_workspace_placement(H, c1):
+    """The tree carves the step workspace past the unbinding's arrays when that
+    tail is large enough and a workspace of its own otherwise.  A context that
+    has run the whole path (its workspace sized by the largest call) and a
+    fresh one that runs only the unbinding (a tail of about an eighth of the
+    unbinding's arrays) give identical bits."""
+    note("tree potential workspace placement")
+    P = H.Particles.from_catalog(c1)
+    prm = H.params_for_catalog(c1, bh_theta=0.04, bh_min=500)
+    a = H.Halo(prm).run_all(P)
+    fresh = H.Halo(prm)
+    for _ in range(2):  # the second call finds the workspaces in place
+        unb, bound, phi = fresh.unbind(P, a["halos"], a["halo_of"])
+        np.testing.assert_array_equal(to_np(phi), to_np(a["phi"]))
+        np.testing.assert_array_equal(to_np(bound), to_np(a["bound"]))
+        np.testing.assert_array_equal(to_np(unb["n_s"]), to_np(a["unbound"]["n_s"]))
