@@ -180,8 +180,21 @@ __global__ void k_bh_gather(const double* ux, const double* uy, const double* uz
   pz[e] = uz[q];
 }
 
+// Node records, one 64-byte line per node: the walk reads a node's centre,
+// mass and acceptance distance in one scalar fetch.
 struct BhNodes {
-  double *cx, *cy, *cz, *cm, *sig2, *rmax, *crit2;
+  double* r;
+  __device__ __forceinline__ double& cx(uint32_t g) const { return r[8ull * g + 0]; }
+  __device__ __forceinline__ double& cy(uint32_t g) const { return r[8ull * g + 1]; }
+  __device__ __forceinline__ double& cz(uint32_t g) const { return r[8ull * g + 2]; }
+  __device__ __forceinline__ double& cm(uint32_t g) const { return r[8ull * g + 3]; }
+  __device__ __forceinline__ double& crit2(uint32_t g) const { return r[8ull * g + 4]; }
+  __device__ __forceinline__ double& sig2(uint32_t g) const { return r[8ull * g + 5]; }
+  __device__ __forceinline__ double& rmax(uint32_t g) const { return r[8ull * g + 6]; }
+  // exact r_max as an ordered integer, raised by atomicMax
+  __device__ __forceinline__ unsigned long long* rmx(uint32_t g) const {
+    return reinterpret_cast<unsigned long long*>(r + 8ull * g + 7);
+  }
 };
 
 __device__ __forceinline__ void node_range(uint32_t k, uint32_t n, uint32_t& lo, uint32_t& hi) {
@@ -229,25 +242,25 @@ __global__ void k_bh_level(BhList L, uint32_t B, uint32_t T, uint32_t level, dou
     r = sqrt(r);
   } else {
     const uint32_t g1 = L.noff[b] + 2u * k, g2 = g1 + 1u;
-    const double m1 = N.cm[g1], m2 = N.cm[g2];
+    const double m1 = N.cm(g1), m2 = N.cm(g2);
     m = m1 + m2;
-    x0[0] = (m1 * N.cx[g1] + m2 * N.cx[g2]) / m;
-    x0[1] = (m1 * N.cy[g1] + m2 * N.cy[g2]) / m;
-    x0[2] = (m1 * N.cz[g1] + m2 * N.cz[g2]) / m;
-    const double d1 = sq3(N.cx[g1] - x0[0], N.cy[g1] - x0[1], N.cz[g1] - x0[2]);
-    const double d2 = sq3(N.cx[g2] - x0[0], N.cy[g2] - x0[1], N.cz[g2] - x0[2]);
-    s2 = (m1 * (N.sig2[g1] + d1) + m2 * (N.sig2[g2] + d2)) / m;
-    r = fmax(sqrt(d1) + N.rmax[g1], sqrt(d2) + N.rmax[g2]);
+    x0[0] = (m1 * N.cx(g1) + m2 * N.cx(g2)) / m;
+    x0[1] = (m1 * N.cy(g1) + m2 * N.cy(g2)) / m;
+    x0[2] = (m1 * N.cz(g1) + m2 * N.cz(g2)) / m;
+    const double d1 = sq3(N.cx(g1) - x0[0], N.cy(g1) - x0[1], N.cz(g1) - x0[2]);
+    const double d2 = sq3(N.cx(g2) - x0[0], N.cy(g2) - x0[1], N.cz(g2) - x0[2]);
+    s2 = (m1 * (N.sig2(g1) + d1) + m2 * (N.sig2(g2) + d2)) / m;
+    r = fmax(sqrt(d1) + N.rmax(g1), sqrt(d2) + N.rmax(g2));
   }
   const uint32_t g = t;
-  N.cx[g] = x0[0];
-  N.cy[g] = x0[1];
-  N.cz[g] = x0[2];
-  N.cm[g] = m;
-  N.sig2[g] = s2;
-  N.rmax[g] = r;
+  N.cx(g) = x0[0];
+  N.cy(g) = x0[1];
+  N.cz(g) = x0[2];
+  N.cm(g) = m;
+  N.sig2(g) = s2;
+  N.rmax(g) = r;
   const double dc = 0.5 * r + sqrt(0.25 * r * r + s2 / theta);
-  N.crit2[g] = dc * dc;
+  N.crit2(g) = dc * dc;
 }
 
 // Node of level l holding sorted position p of a halo of n particles: the i
@@ -262,13 +275,13 @@ __device__ __forceinline__ uint32_t node_at(uint32_t p, uint32_t n, uint32_t l) 
 // Exact r_max of every cell: each particle raises the maximum of its cell on
 // every level (as ordered integers; a wave whose particles share a cell sends
 // one atomic for it).
-__global__ void k_bh_rmax_init(unsigned long long* rm, uint32_t T) {
+__global__ void k_bh_rmax_init(BhNodes N, uint32_t T) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < T) rm[t] = 0ull;
+  if (t < T) *N.rmx(t) = 0ull;
 }
 
 __global__ void k_bh_rmax(BhList L, uint32_t B, uint32_t E, const double* px, const double* py,
-                          const double* pz, BhNodes N, unsigned long long* rm) {
+                          const double* pz, BhNodes N) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = e < E;
   const uint32_t b = ok ? seg_find(L.eoff, B, e) : 0u;
@@ -284,7 +297,7 @@ __global__ void k_bh_rmax(BhList L, uint32_t B, uint32_t E, const double* px, co
     if (act) {
       const uint32_t k = node_at(e - L.eoff[b], L.nel[b], l);
       g = L.noff[b] + k;
-      v = f64_ord(sqrt(sq3(px[e] - N.cx[g], py[e] - N.cy[g], pz[e] - N.cz[g])));
+      v = f64_ord(sqrt(sq3(px[e] - N.cx(g), py[e] - N.cy(g), pz[e] - N.cz(g))));
     }
     const uint32_t g0 = __shfl(g, 0);
     if (__all(g == g0) && g0 != 0xFFFFFFFFu) {
@@ -292,21 +305,21 @@ __global__ void k_bh_rmax(BhList L, uint32_t B, uint32_t E, const double* px, co
         const unsigned long long w2 = __shfl_xor(v, o);
         v = w2 > v ? w2 : v;
       }
-      if ((threadIdx.x & 63u) == 0) atomicMax(rm + g0, v);
+      if ((threadIdx.x & 63u) == 0) atomicMax(N.rmx(g0), v);
     } else if (act) {
-      atomicMax(rm + g, v);
+      atomicMax(N.rmx(g), v);
     }
   }
 }
 
 // Acceptance distances from the exact r_max.
-__global__ void k_bh_crit(uint32_t T, double theta, const unsigned long long* rm, BhNodes N) {
+__global__ void k_bh_crit(uint32_t T, double theta, BhNodes N) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= T || rm[t] == 0ull) return;  // index 0 of each heap is unused
-  const double r = ord_f64(rm[t]);
-  N.rmax[t] = r;
-  const double dc = 0.5 * r + sqrt(0.25 * r * r + N.sig2[t] / theta);
-  N.crit2[t] = dc * dc;
+  if (t >= T || *N.rmx(t) == 0ull) return;  // index 0 of each heap is unused
+  const double r = ord_f64(*N.rmx(t));
+  N.rmax(t) = r;
+  const double dc = 0.5 * r + sqrt(0.25 * r * r + N.sig2(t) / theta);
+  N.crit2(t) = dc * dc;
 }
 
 // Wave units of each tree halo: its sorted elements in runs of 64.
@@ -325,8 +338,13 @@ __global__ void k_bh_wave_counts(BhList L, uint32_t B, uint32_t* wcnt) {
 // its terms in the wave's fixed order.
 __global__ void __launch_bounds__(TB)
     k_bh_walk(BhList L, uint32_t B, const uint32_t* woff, uint32_t nwave, const uint32_t* slot,
-              const double* px, const double* py, const double* pz, const uint32_t* pidx,
-              BhNodes N, double eps2, I128* pacc, uint32_t* err) {
+              const double* __restrict__ px, const double* __restrict__ py,
+              const double* __restrict__ pz, const uint32_t* __restrict__ pidx,
+              const double* __restrict__ nrec, double eps2, I128* __restrict__ pacc,
+              uint32_t* __restrict__ err) {
+  // read-only inputs that no pointer of the kernel writes: wave-uniform reads of
+  // them can take the scalar data cache
+  const BhNodes N{const_cast<double*>(nrec)};
   __shared__ uint32_t wstack[TB / 64][kStack];
   const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (TB / 64) +
                                                        (threadIdx.x >> 6));
@@ -349,7 +367,7 @@ __global__ void __launch_bounds__(TB)
   double acc = 0.0;
   for (;;) {
     const uint32_t g = nb + k;
-    const double cx = N.cx[g], cy = N.cy[g], cz = N.cz[g], cm = N.cm[g], c2 = N.crit2[g];
+    const double cx = N.cx(g), cy = N.cy(g), cz = N.cz(g), cm = N.cm(g), c2 = N.crit2(g);
     const double d2 = sq3(x - cx, y - cy, z - cz);
     const uint32_t l = 31u - (uint32_t)__builtin_clz(k);
     if (__ballot(target && d2 < c2) == 0ull) {
@@ -357,10 +375,14 @@ __global__ void __launch_bounds__(TB)
     } else if (l == D) {
       uint32_t lo, hi;
       node_range(k, n, lo, hi);
+      // every lane evaluates each term and keeps it by a select, so the loads of a
+      // leaf particle are not behind a branch and several can be in flight at once
+#pragma unroll 4
       for (uint32_t f = base + lo; f < base + hi; ++f) {
         const double fx = px[f], fy = py[f], fz = pz[f];
         const uint32_t qf = pidx[f];
-        if (target && qf != q) acc += rsqrt_f64(sq3(x - fx, y - fy, z - fz) + eps2);
+        const double tf = rsqrt_f64(sq3(x - fx, y - fy, z - fz) + eps2);
+        acc = (target && qf != q) ? acc + tf : acc;
       }
     } else {
       if (sp + 1 > kStack) {  // cannot happen for depth <= 31; reported, not faulted
@@ -458,7 +480,6 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   uint32_t *v0, *v1;
   double* pz;
   BhNodes N;
-  unsigned long long* rmx;
   void* rtmp;
   carve2(ctx, [&](Arena& A) {
     take_list(A);
@@ -467,14 +488,7 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
     v0 = A.take<uint32_t>(E + 1);
     v1 = A.take<uint32_t>(E + 1);
     pz = A.take<double>(E + 1);
-    N.cx = A.take<double>(T + 1);
-    N.cy = A.take<double>(T + 1);
-    N.cz = A.take<double>(T + 1);
-    N.cm = A.take<double>(T + 1);
-    N.sig2 = A.take<double>(T + 1);
-    N.rmax = A.take<double>(T + 1);
-    N.crit2 = A.take<double>(T + 1);
-    rmx = A.take<unsigned long long>(T + 1);
+    N.r = A.take<double>(8ull * (T + 1));
     rtmp = A.take<char>(radix_tmp_bytes(E + 1));
   });
   build_list();
@@ -494,9 +508,9 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   for (int l = (int)Dmax; l >= 0; --l)
     k_bh_level<<<blocks_for(T, TB), TB, 0, s>>>(w.L, B, T, (uint32_t)l, theta, px, py, pz, N);
   // exact r_max in place of the children's bound: a tighter acceptance distance
-  k_bh_rmax_init<<<blocks_for(T, TB), TB, 0, s>>>(rmx, T);
-  k_bh_rmax<<<blocks_for(E, TB), TB, 0, s>>>(w.L, B, E, px, py, pz, N, rmx);
-  k_bh_crit<<<blocks_for(T, TB), TB, 0, s>>>(T, theta, rmx, N);
+  k_bh_rmax_init<<<blocks_for(T, TB), TB, 0, s>>>(N, T);
+  k_bh_rmax<<<blocks_for(E, TB), TB, 0, s>>>(w.L, B, E, px, py, pz, N);
+  k_bh_crit<<<blocks_for(T, TB), TB, 0, s>>>(T, theta, N);
   // wave units: runs of 64 sorted elements within each halo
   k_bh_wave_counts<<<blocks_for(B, TB), TB, 0, s>>>(w.L, B, w.flag);
   exclusive_scan<uint32_t>(w.flag, w.pos, B, w.cnt + 3, w.stmp, s);
@@ -506,7 +520,7 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   const uint32_t nwave = hb[4];
   HALO_PROF(ctx, "k_bh_walk", s,
             k_bh_walk<<<blocks_for((int64_t)nwave * 64, TB), TB, 0, s>>>(
-                w.L, B, w.pos, nwave, slot, px, py, pz, pidx, N, eps2, pacc, w.cnt + 8));
+                w.L, B, w.pos, nwave, slot, px, py, pz, pidx, N.r, eps2, pacc, w.cnt + 8));
   HALO_HIP(hipMemcpyAsync(hb + 3, w.cnt + 8, 4, hipMemcpyDeviceToHost, s));
   HALO_HIP(hipStreamSynchronize(s));
   HALO_CHECK(hb[3] == 0, LIBHALO_EINVAL, "tree walk stack exhausted");
