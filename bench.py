@@ -448,6 +448,9 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-tree", action="store_true",
                     help="skip the tree-potential comparison (not part of the step)")
+    ap.add_argument("--bh-theta", type=float, default=0.0,
+                    help="tree potential (Appendix B) in the timed steps, for haloes of at "
+                         "least --bh-min particles; 0 (default) keeps the exact direct sum")
     ap.add_argument("--bh-min", type=int, default=65536,
                     help="smallest |S(h)| that takes the tree in the tree comparison")
     ap.add_argument("--no-dense", action="store_true",
@@ -497,7 +500,8 @@ def main():
         args.grid_min = int(best)
         tuned = {"grid_min": int(best), "refine_ms": {str(k): v for k, v in t.items()}}
         progress(f"autotuned grid_min = {best}")
-    ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=args.grid_min))
+    ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=args.grid_min,
+                                      bh_theta=args.bh_theta, bh_min=args.bh_min))
     sec, out, stage = timed(ctx, P, args.steps, args.warmup)
 
     # dominant kernels, timed with HIP events on the library's launch stream
@@ -558,7 +562,8 @@ def main():
     merger = None if args.no_merger else merger_report(H, cat, P, args.grid_min, prec)
     subset = None if args.no_subset else subset_report(H, cat, P, args.grid_min, prec)
     dense = None if args.no_dense else dense_report(H, cat, P, args.grid_min, prec)
-    tree = None if args.no_tree else tree_report(ctx, P, out, bh_min=args.bh_min)
+    tree = None if args.no_tree else tree_report(ctx, P, out, theta=args.bh_theta or 0.04,
+                                                 bh_min=args.bh_min)
     if tree is not None:
         progress("tree potential timed")
     if dense is not None:
@@ -586,6 +591,8 @@ def main():
                                "power-law NFW hosts + subhaloes + 40% uniform, seed 0"
                                + (" (GPU-drawn)" if args.gen == "device" else ""),
                    "form": "batched", "potential": args.prec,
+                   "bh_theta": args.bh_theta,
+                   "bh_min": args.bh_min if args.bh_theta > 0 else None,
                    "grid_min": args.grid_min, "autotune": tuned,
                    "n_groups": int(out[0]["n_groups"]), "n_nodes": int(out[1]["parent"].shape[0]),
                    "n_halos": int(out[2]["seed_node"].shape[0])},
