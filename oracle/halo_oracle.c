@@ -1097,8 +1097,11 @@ int orc_assign(const orc_params* p, int64_t n, int pos_f64, const void* x, const
         int64_t s = ord[t];
         double bd = INFINITY;
         int64_t best = -1;
+        /* candidates: halos of the group with strictly more assigned
+           particles (Section 3.4); none -> the halo is a host itself */
         for (int64_t u = a0; u < t; ++u) {
           int64_t H = ord[u];
+          if (h->n_assigned[H] <= h->n_assigned[s]) break;
           double xh[3] = {h->xs[H], h->ys[H], h->zs[H]};
           double vh[3] = {h->vxs[H], h->vys[H], h->vzs[H]};
           double d = eq3_d2(p->box, xh, vh, cdyn / h->vmax2[H], 1.0 / fmax(h->sv2[H], 1e-300),

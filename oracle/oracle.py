@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
 benchmark's CPU-baseline leg, never by the product path.  It shares no code
-with the GPU library; the two meet only in the seeded catalogues of
-``paper_1110_4372_amd.synth``.
+with the GPU library and imports nothing from the product package; the two
+meet only in the seeded catalogues that the tests pass to both.
 """
 from __future__ import annotations
 
@@ -20,12 +20,27 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 _lib = None
 
+# ---- units and constants (Section 3.3 and Table 1; positions in Mpc/h,
+# velocities in km/s, masses in Msun/h) -- the oracle's own definitions.
+# G in (Mpc/h) (km/s)^2 / (Msun/h): G M_sun / (1 Mpc (1 km/s)^2); the h factors
+# cancel.  Pinned against the SI values in tests/test_oracle_pins.py.
+G_NEWTON = 4.30091e-9
+# critical density 3 H0^2 / (8 pi G) with H0 = 100 h km/s/Mpc, in
+# (Msun/h) / (Mpc/h)^3
+RHO_CRIT = 2.77536627e11
+# matter density of the Bolshoi cosmology (Table 1)
+OMEGA_M = 0.27
+RHO_M = OMEGA_M * RHO_CRIT
+# virial overdensity against the background density at z = 0 (Section 3.3)
+DELTA_VIR = 360.0
+RHO_VIR = DELTA_VIR * RHO_M
+
 
 def build(force: bool = True) -> str:
     """Compile the oracle (plain C, FP64, no fused contractions)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-mfma", "-ffp-contract=off", "-fPIC", "-shared",
                                "-Wall", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -178,10 +193,9 @@ def make_params(box, particle_mass, softening, *, b=0.28, f=0.7, min_members=10,
                 max_levels=200, merge_q2=200.0, G=None, rho_vir=None, core_frac=0.1,
                 unbound_threshold=0.5, major_merger=0.0, ell_subset=0,
                 fof_dense=0) -> Params:
-    from paper_1110_4372_amd import synth
     return Params(box, b, f, min_members, max_levels, merge_q2, particle_mass,
-                  synth.G_NEWTON if G is None else G,
-                  synth.RHO_VIR if rho_vir is None else rho_vir, softening, core_frac,
+                  G_NEWTON if G is None else G,
+                  RHO_VIR if rho_vir is None else rho_vir, softening, core_frac,
                   unbound_threshold, ell_subset, major_merger, fof_dense)
 
 

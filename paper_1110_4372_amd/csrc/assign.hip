@@ -556,10 +556,10 @@ __global__ void k_kept_keys(const libhalo_halos h, uint32_t S, const uint32_t* f
   val[p] = s;
 }
 
-// Host/sub relation, one wavefront per FOF group.
 // Host of each halo (Section 3.4): argmin of the Eq. 3 distance over the
-// larger halos of its FOF group (earlier in ord), in the candidate host's
-// metric; one wavefront per halo, its group located by binary search.
+// halos of its FOF group with strictly more assigned particles (a prefix of
+// the group in ord), in the candidate host's metric; -1 when there is none.
+// One wavefront per halo, its group located by binary search.
 __global__ void k_hostsub(const uint32_t* ord, const uint32_t* seg_start, const uint32_t* nseg,
                           uint32_t KH, double box, double cdyn, libhalo_halos h) {
   const uint32_t F = nseg[0];
@@ -575,12 +575,14 @@ __global__ void k_hostsub(const uint32_t* ord, const uint32_t* seg_start, const 
         hi = mid;
     }
     const uint32_t a0 = seg_start[lo];
-    if (t == a0) continue;  // the group's largest halo has no host
+    if (t == a0) continue;  // the group's first halo has no host
     const uint32_t s = ord[t];
+    const uint32_t ns = h.n_assigned[s];
     double bd = INFINITY;
     uint32_t best = 0xFFFFFFFFu;
     for (uint32_t u = a0 + lane; u < t; u += 64) {
       const uint32_t H = ord[u];
+      if (h.n_assigned[H] <= ns) continue;
       const double ird = cdyn / h.vmax2[H];
       const double isv = 1.0 / fmax(h.sv2[H], 1e-300);
       double dx = min_image(h.xs[s] - h.xs[H], box), dy = min_image(h.ys[s] - h.ys[H], box),

@@ -44,6 +44,8 @@ class Params:
     box: float
     particle_mass: float
     softening: float
+    # (Mpc/h)(km/s)^2/(Msun/h); 360 x the background density of Omega_m = 0.27
+    # (Table 1, Section 3.3) with rho_crit = 2.77536627e11 (Msun/h)/(Mpc/h)^3
     G: float = 4.30091e-9
     rho_vir: float = 360.0 * 0.27 * 2.77536627e11
     b: float = 0.28
@@ -381,7 +383,6 @@ class Halo:
 
 
 def params_for_catalog(cat, **kw) -> Params:
-    """Parameters of a synthetic catalogue (box, particle mass, softening)."""
-    from . import synth
-    return Params(box=cat.box, particle_mass=cat.particle_mass, softening=cat.softening,
-                  G=synth.G_NEWTON, rho_vir=synth.RHO_VIR, **kw)
+    """Parameters of a catalogue (box, particle mass, softening); G and the
+    virial density keep the defaults of Params."""
+    return Params(box=cat.box, particle_mass=cat.particle_mass, softening=cat.softening, **kw)

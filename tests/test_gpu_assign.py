@@ -7,6 +7,7 @@ import pytest
 from tests.gpu_util import note, particles_from_arrays, to_np
 from tests.test_gpu_refine6d import gpu_nodes, subset_nodes
 from tests.test_oracle_pins import clustered, particles
+from tests.test_oracle_readings import clump_lattice
 
 pytestmark = pytest.mark.gpu
 
@@ -111,21 +112,6 @@ def test_assign_repeat(H, c1):
     b = gpu_pipeline(H, H.Particles.from_catalog(c1), H.params_for_catalog(c1))
     assert_halos_equal(a[3], b[3])
     np.testing.assert_array_equal(a[4], b[4])
-
-
-def clump_lattice(seed=41, side=9, per=30, box=20.0):
-    """side^3 tight clumps of `per` particles on a lattice finer than the
-    linking length (one FOF group), each with its own bulk velocity, so each
-    clump becomes a seed of that group."""
-    rng = np.random.default_rng(seed)
-    g = np.arange(side) * 0.2
-    cx, cy, cz = np.meshgrid(g, g, g, indexing="ij")
-    c = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], 1) + 8.0
-    k = c.shape[0]
-    pos = np.repeat(c, per, 0) + 0.01 * rng.standard_normal((k * per, 3))
-    bulk = 300.0 * rng.standard_normal((k, 3))
-    vel = (np.repeat(bulk, per, 0) + 5.0 * rng.standard_normal((k * per, 3))).astype(np.float32)
-    return pos, vel, box
 
 
 def test_assign_many_seeds_one_group(H, orc):

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from tests.gpu_util import note, particles_from_arrays, to_np
-from tests.test_gpu_unbind_props import compare_props, compare_unbind
+from tests.test_gpu_unbind_props import compare_props_agreeing, compare_unbind
 from tests.test_oracle_merger import BOX, EPS, M_PART, merger
 from tests.test_oracle_pins import particles
 
@@ -44,10 +44,8 @@ def test_merger_matches_oracle(H, orc, seed, prec, f64):
     g = ctx.run_all(particles_from_arrays(pos, vel))
     tol, rtol = (1e-9, 1e-9) if prec == 0 else (1e-4, 2e-5)
     amb, changed = compare_unbind(g["unbound"], g["bound"], g["phi"], o, P, tol, rtol)
-    print(f"ambiguous={amb} changed={changed}")
-    kept = o["halos"]["merged_into"] == np.arange(o["halos"]["merged_into"].shape[0])
-    if changed == 0:
-        compare_props(g["props"], o["props"], kept)
+    rows = compare_props_agreeing(g, o)
+    print(f"ambiguous={amb} changed={changed} property rows={rows}")
 
 
 def test_merger_off_is_the_single_halo_pass(H, c1):
@@ -72,10 +70,9 @@ def test_merger_c1(H, orc, c1, prec):
             H.Particles.from_catalog(c1))
         tol, rtol = (1e-9, 1e-9) if prec == 0 else (1e-4, 2e-5)
         amb, changed = compare_unbind(g["unbound"], g["bound"], g["phi"], o, c1, tol, rtol)
-        print(f"mp={mp} majors={n_major(o, mp)} ambiguous={amb} changed={changed}")
-        kept = o["halos"]["merged_into"] == np.arange(o["halos"]["merged_into"].shape[0])
-        if changed == 0:
-            compare_props(g["props"], o["props"], kept)
+        rows = compare_props_agreeing(g, o)
+        print(f"mp={mp} majors={n_major(o, mp)} ambiguous={amb} changed={changed} "
+              f"property rows={rows}")
 
 
 def test_merger_bad_parameter(H, c1):

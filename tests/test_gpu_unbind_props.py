@@ -48,11 +48,30 @@ def compare_unbind(g_unb, g_bound, g_phi, o, P, tol, phi_rtol):
     for c in ("vbx", "vby", "vbz"):
         np.testing.assert_array_equal(gu[c], o["unbound"][c])
     changed = int(np.sum(gb[inside] != o["bound"][inside]))
-    if ambiguous == 0 or changed == 0:
-        for c in ("n_bound_own", "n_bound_s", "valid"):
-            np.testing.assert_array_equal(gu[c].astype(np.int64),
-                                          o["unbound"][c].astype(np.int64))
+    rows = agreeing_rows(gb, o)
+    for c in ("n_bound_own", "n_bound_s", "valid"):
+        np.testing.assert_array_equal(gu[c][rows].astype(np.int64),
+                                      o["unbound"][c][rows].astype(np.int64))
     return ambiguous, changed
+
+
+def agreeing_rows(gb, o):
+    """Halo rows of the FOF groups whose bound flags all agree with the
+    oracle's (a flag inside the rounding band may differ; the counts and
+    properties of its group then legitimately differ too)."""
+    lab = np.asarray(o["label"]).astype(np.int64)
+    bad = np.unique(lab[(o["halo_of"] >= 0) & (np.asarray(gb) != o["bound"])])
+    return ~np.isin(o["halos"]["fof"].astype(np.int64), bad)
+
+
+def compare_props_agreeing(g, o, min_frac=0.9):
+    """compare_props over the kept halos of the groups whose flags agree;
+    those must be at least min_frac of the kept halos."""
+    kept = o["halos"]["merged_into"] == np.arange(o["halos"]["merged_into"].shape[0])
+    rows = kept & agreeing_rows(to_np(g["bound"]), o)
+    assert rows.sum() >= min_frac * kept.sum(), (int(rows.sum()), int(kept.sum()))
+    compare_props(g["props"], o["props"], rows)
+    return int(rows.sum())
 
 
 def compare_props(g, o, kept):
@@ -90,10 +109,8 @@ def test_unbind_props_clustered(H, orc, n, seed, f64, prec):
                 H.Params(box=box, particle_mass=m, softening=eps, prec=prec))
     tol, rtol = (1e-9, 1e-9) if prec == 0 else (1e-4, 2e-5)
     amb, changed = compare_unbind(g["unbound"], g["bound"], g["phi"], o, P, tol, rtol)
-    print(f"ambiguous={amb} changed={changed}")
-    kept = o["halos"]["merged_into"] == np.arange(o["halos"]["merged_into"].shape[0])
-    if changed == 0:
-        compare_props(g["props"], o["props"], kept)
+    rows = compare_props_agreeing(g, o)
+    print(f"ambiguous={amb} changed={changed} property rows={rows}")
 
 
 def test_unbind_small_softening(H, orc):
@@ -111,7 +128,8 @@ def test_unbind_small_softening(H, orc):
     g = run_gpu(H, particles_from_arrays(pos, vel),
                 H.Params(box=box, particle_mass=m, softening=eps, prec=0))
     amb, changed = compare_unbind(g["unbound"], g["bound"], g["phi"], o, P, 1e-9, 1e-9)
-    print(f"ambiguous={amb} changed={changed}")
+    rows = compare_props_agreeing(g, o)
+    print(f"ambiguous={amb} changed={changed} property rows={rows}")
 
 
 @pytest.mark.parametrize("prec", [0, 1])
