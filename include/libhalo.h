@@ -21,8 +21,10 @@
  *     velocities vx, vy, vz as float32 (km/s).  Particle i is the i-th element.
  *   - Every array argument is a DEVICE pointer owned by the caller, unless
  *     documented as a host pointer (the n_* counts and the parameter block).
- *     The library never frees caller memory; it owns only its workspace,
- *     allocated on the context's device and released by libhalo_ctx_destroy.
+ *     The library never frees caller memory.  Its workspace (device memory
+ *     beyond the inputs and outputs) comes only from the allocator callback
+ *     given to libhalo_ctx_create, and goes back through the matching free
+ *     callback; the library itself allocates no device memory.
  *   - Work is enqueued on `stream` (a hipStream_t, NULL = default stream).  A
  *     call returns after its host-visible counts are known, which needs a
  *     few small synchronous read-backs on that stream; device outputs are
@@ -53,7 +55,7 @@ extern "C" {
 typedef enum {
   LIBHALO_OK = 0,
   LIBHALO_EINVAL = -1,     /* bad argument, parameter or input value */
-  LIBHALO_ENOMEM = -2,     /* device allocation of the workspace failed */
+  LIBHALO_ENOMEM = -2,     /* the allocator callback returned no workspace */
   LIBHALO_EHIP = -3,       /* a HIP runtime call failed */
   LIBHALO_ECAPACITY = -4,  /* an output table is too small; n_* holds the need */
   LIBHALO_EGEOMETRY = -5   /* a FOF group spans half the box or more */
@@ -93,7 +95,7 @@ typedef struct {
   int32_t mode;             /* libhalo_mode */
   int32_t prec;             /* libhalo_prec */
   int32_t grid_min;         /* nodes with more particles use the exact grid
-                               neighbour search instead of all pairs; 0 = 8192,
+                               neighbour search instead of all pairs; 0 = 131072,
                                else >= 64 (results are identical either way) */
   int32_t ell_subset;       /* 0: ell from every particle's nearest neighbour (exact);
                                m > 0: nodes of more than m particles take it from a
@@ -193,10 +195,34 @@ typedef struct {
 
 typedef struct libhalo_ctx libhalo_ctx;
 
-/* Create a context on HIP device `device` with parameters *p (host).
- * Validates the parameters (EINVAL).  Allocates nothing on the device. */
-int libhalo_ctx_create(const libhalo_params* p, int device, libhalo_ctx** out);
-/* Release the workspace and the context. */
+/* Device memory provider of the workspace (for example a caching allocator).
+ *   alloc_fn(bytes, user, stream): return `bytes` (> 0) of device memory on
+ *     the context's device (current when called), aligned to 256 bytes, for
+ *     use by work enqueued on `stream` (a hipStream_t, NULL = default
+ *     stream); return NULL when it cannot, and the calling entry point fails
+ *     with LIBHALO_ENOMEM.  Each entry point takes its main workspace before
+ *     it writes any output, so a refusal there leaves the outputs untouched
+ *     (the tree potential's own workspace, when it needs one, is taken later
+ *     inside libhalo_unbind).
+ *   free_fn(ptr, user, stream): take back a block from alloc_fn.  The library
+ *     calls it only once the work it enqueued on `stream` is complete (after
+ *     a stream synchronisation; at libhalo_ctx_destroy after a device
+ *     synchronisation), when a workspace grows and when the context ends.
+ * `user` is passed through unchanged.  The callbacks are called on the
+ * thread that calls the library, from inside its entry points. */
+typedef void* (*libhalo_alloc_fn)(size_t bytes, void* user, void* stream);
+typedef void (*libhalo_free_fn)(void* ptr, void* user, void* stream);
+
+/* Create a context on HIP device `device` with parameters *p (host) and the
+ * workspace allocator (alloc_fn, free_fn, user; both functions required).
+ * Takes a 256-byte error word from alloc_fn; every later workspace is sized
+ * by the entry point that needs it, grown only when a larger one is needed,
+ * and kept for reuse until libhalo_ctx_destroy.
+ * Errors: EINVAL (bad parameters or device, a null callback), ENOMEM
+ * (alloc_fn returned NULL), EHIP. */
+int libhalo_ctx_create(const libhalo_params* p, int device, libhalo_alloc_fn alloc_fn,
+                       libhalo_free_fn free_fn, void* user, libhalo_ctx** out);
+/* Return the workspace to free_fn and release the context. */
 int libhalo_ctx_destroy(libhalo_ctx* ctx);
 /* Message of the last error on this context (static storage of the ctx). */
 const char* libhalo_last_error(const libhalo_ctx* ctx);

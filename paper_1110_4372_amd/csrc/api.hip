@@ -14,43 +14,34 @@ struct libhalo_ctx {
 
 namespace halo {
 
-void Ctx::ensure_ws(size_t bytes) {
-  if (bytes <= ws.cap) return;
-  if (ws.base) {
-    HALO_HIP(hipDeviceSynchronize());
-    HALO_HIP(hipFree(ws.base));
-    ws.base = nullptr;
-    ws.cap = 0;
-  }
-  size_t want = bytes + bytes / 8;
-  void* p = nullptr;
-  if (hipMalloc(&p, want) != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error{LIBHALO_ENOMEM, "workspace allocation of " + std::to_string(want) +
-                                    " bytes failed"};
-  }
-  ws.base = static_cast<char*>(p);
-  ws.cap = want;
+void* Ctx::dev_alloc(size_t bytes, const char* what) {
+  void* p = alloc_fn(bytes, user, (void*)stream);
+  if (!p)
+    throw Error{LIBHALO_ENOMEM, std::string(what) + " of " + std::to_string(bytes) +
+                                    " bytes: the allocator returned NULL"};
+  HALO_CHECK((reinterpret_cast<uintptr_t>(p) & 255u) == 0, LIBHALO_EINVAL,
+             "the allocator returned memory not aligned to 256 bytes");
+  return p;
 }
 
-void Ctx::ensure_ws2(size_t bytes) {
-  if (bytes <= ws2.cap) return;
-  if (ws2.base) {
-    HALO_HIP(hipDeviceSynchronize());
-    HALO_HIP(hipFree(ws2.base));
-    ws2.base = nullptr;
-    ws2.cap = 0;
+// A workspace grows by returning the old block (once the stream's work on it
+// is done) and taking a larger one, with an eighth of slack.
+static void grow(Ctx& c, Arena& a, size_t bytes, const char* what) {
+  if (bytes <= a.cap) return;
+  if (a.base) {
+    HALO_HIP(hipStreamSynchronize(c.stream));
+    c.free_fn(a.base, c.user, (void*)c.stream);
+    a.base = nullptr;
+    a.cap = 0;
   }
-  size_t want = bytes + bytes / 8;
-  void* p = nullptr;
-  if (hipMalloc(&p, want) != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error{LIBHALO_ENOMEM, "tree workspace allocation of " + std::to_string(want) +
-                                    " bytes failed"};
-  }
-  ws2.base = static_cast<char*>(p);
-  ws2.cap = want;
+  const size_t want = bytes + bytes / 8;
+  a.base = static_cast<char*>(c.dev_alloc(want, what));
+  a.cap = want;
 }
+
+void Ctx::ensure_ws(size_t bytes) { grow(*this, ws, bytes, "workspace"); }
+
+void Ctx::ensure_ws2(size_t bytes) { grow(*this, ws2, bytes, "tree workspace"); }
 
 hipEvent_t Ctx::event() {
   if (!spare.empty()) {
@@ -71,13 +62,13 @@ void Ctx::release() {
   for (auto e : spare) (void)hipEventDestroy(e);
   recs.clear();
   spare.clear();
-  if (ws.base) (void)hipFree(ws.base);
-  if (ws2.base) (void)hipFree(ws2.base);
-  ws2.base = nullptr;
-  ws2.cap = 0;
-  if (d_err) (void)hipFree(d_err);
+  // the caller has synchronised the device: every block is idle
+  if (ws.base) free_fn(ws.base, user, (void*)stream);
+  if (ws2.base) free_fn(ws2.base, user, (void*)stream);
+  if (d_err) free_fn(d_err, user, nullptr);
   if (h_pinned) (void)hipHostFree(h_pinned);
-  ws.base = nullptr;
+  ws.base = ws2.base = nullptr;
+  ws.cap = ws2.cap = 0;
   d_err = nullptr;
   h_pinned = nullptr;
 }
@@ -112,9 +103,10 @@ static std::string validate(const libhalo_params& p) {
 }  // namespace halo
 
 template <class F>
-static int guarded(libhalo_ctx* ctx, F&& f) {
+static int guarded(libhalo_ctx* ctx, F&& f, void* stream = nullptr) {
   if (!ctx) return LIBHALO_EINVAL;
   try {
+    ctx->c.stream = (hipStream_t)stream;
     HALO_HIP(hipSetDevice(ctx->c.device));
     f(ctx->c);
     ctx->c.err.clear();
@@ -132,8 +124,9 @@ extern "C" {
 
 const char* libhalo_version(void) { return "libhalo 0.1 (gfx950)"; }
 
-int libhalo_ctx_create(const libhalo_params* p, int device, libhalo_ctx** out) {
-  if (!p || !out) return LIBHALO_EINVAL;
+int libhalo_ctx_create(const libhalo_params* p, int device, libhalo_alloc_fn alloc_fn,
+                       libhalo_free_fn free_fn, void* user, libhalo_ctx** out) {
+  if (!p || !out || !alloc_fn || !free_fn) return LIBHALO_EINVAL;
   *out = nullptr;
   if (!halo::validate(*p).empty()) return LIBHALO_EINVAL;
   int ndev = 0;
@@ -143,12 +136,21 @@ int libhalo_ctx_create(const libhalo_params* p, int device, libhalo_ctx** out) {
   if (!c) return LIBHALO_ENOMEM;
   c->c.p = *p;
   c->c.device = device;
+  c->c.alloc_fn = alloc_fn;
+  c->c.free_fn = free_fn;
+  c->c.user = user;
+  int rc = LIBHALO_OK;
   if (hipSetDevice(device) != hipSuccess ||
-      hipMalloc(&c->c.d_err, 256) != hipSuccess ||
       hipHostMalloc(&c->c.h_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    rc = LIBHALO_EHIP;
+  } else {
+    c->c.d_err = static_cast<uint32_t*>(alloc_fn(256, user, nullptr));
+    if (!c->c.d_err) rc = LIBHALO_ENOMEM;
+  }
+  if (rc != LIBHALO_OK) {
     c->c.release();
     delete c;
-    return LIBHALO_EHIP;
+    return rc;
   }
   *out = c;
   return LIBHALO_OK;
@@ -227,7 +229,7 @@ int libhalo_fof3d(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, con
     c.ensure_ws(halo::fof3d_workspace(c.p, n, pos_dtype));
     halo::fof3d(c, n, pos_dtype, x, y, z, fof_label, perm, grp_first, grp_count, grp_cap,
                 n_groups, n_members, (hipStream_t)stream);
-  });
+  }, stream);
 }
 
 int libhalo_refine6d(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
@@ -244,7 +246,7 @@ int libhalo_refine6d(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
                LIBHALO_EINVAL, "bad group table");
     halo::refine6d(c, n, pos_dtype, x, y, z, vx, vy, vz, perm, grp_first, grp_count,
                    n_groups, nodes, deepest, n_nodes, (hipStream_t)stream);
-  });
+  }, stream);
 }
 
 int libhalo_assign(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, const void* y,
@@ -260,7 +262,7 @@ int libhalo_assign(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, co
     HALO_CHECK(n_nodes >= 0, LIBHALO_EINVAL, "n_nodes must be >= 0");
     halo::assign(c, n, pos_dtype, x, y, z, vx, vy, vz, nodes, n_nodes, deepest, halos,
                  halo_of, n_halos, (hipStream_t)stream);
-  });
+  }, stream);
 }
 
 int libhalo_unbind(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, const void* y,
@@ -275,7 +277,7 @@ int libhalo_unbind(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, co
     HALO_CHECK(n_halos >= 0, LIBHALO_EINVAL, "n_halos must be >= 0");
     halo::unbind(c, n, pos_dtype, x, y, z, vx, vy, vz, halos, n_halos, halo_of, bound, phi,
                  out, (hipStream_t)stream);
-  });
+  }, stream);
 }
 
 int libhalo_props(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, const void* y,
@@ -291,7 +293,7 @@ int libhalo_props(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, con
     HALO_CHECK(n_nodes >= 0 && n_halos >= 0, LIBHALO_EINVAL, "negative table size");
     halo::props(c, n, pos_dtype, x, y, z, vx, vy, vz, nodes, n_nodes, halos, n_halos, halo_of,
                 bound, out, (hipStream_t)stream);
-  });
+  }, stream);
 }
 
 int libhalo_props_extra(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
@@ -325,7 +327,7 @@ int libhalo_props_extra(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* 
                LIBHALO_EINVAL, "null output array in ext");
     halo::props(c, n, pos_dtype, x, y, z, vx, vy, vz, nodes, n_nodes, halos, n_halos, halo_of,
                 bound, out, (hipStream_t)stream, &ea);
-  });
+  }, stream);
 }
 
 }  // extern "C"

@@ -629,9 +629,9 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
     HALO_HIP(hipStreamSynchronize(s));
     return hb[slot];
   };
-  k_fill_i32<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, n, -1);
   *n_halos = 0;
   if (NN == 0) {
+    k_fill_i32<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, n, -1);
     HALO_HIP(hipStreamSynchronize(s));
     return;
   }
@@ -713,6 +713,8 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
     w.na = A.take<uint32_t>(K2);
     w.rb = radial_take(A, n, K2);
   });
+  // outputs are written only once the workspace is in place
+  k_fill_i32<<<blocks_for(n, TB), TB, 0, s>>>(halo_of, n, -1);
   uint32_t *flag = w.flag, *pos = w.pos, *dcnt = w.dcnt, *stmp = w.stmp;
   int32_t* node_seed = w.node_seed;
   k_leaf_flags<<<blocks_for(NN, TB), TB, 0, s>>>(nd.n_children, (uint32_t)NN, flag);

@@ -41,7 +41,8 @@ enum : uint32_t {
 };
 
 // ------------------------------------------------------------ workspace --
-// Grow-only device arena.  Each entry point resets it and carves buffers.
+// Grow-only device arena over a block from the context's allocator callback.
+// Each entry point resets it and carves buffers.
 struct Arena {
   char* base = nullptr;
   size_t cap = 0, off = 0;
@@ -91,7 +92,11 @@ struct Ctx {
   Arena ws2;                       // second arena: the tree potential, inside unbinding
   uint32_t* d_err = nullptr;       // device error word
   void* h_pinned = nullptr;        // small pinned host buffer for read-backs
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;    // stream of the entry point being run
+  libhalo_alloc_fn alloc_fn = nullptr;  // workspace provider (caller's callbacks)
+  libhalo_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  void* dev_alloc(size_t bytes, const char* what);  // ENOMEM on NULL
   void ensure_ws(size_t bytes);
   void ensure_ws2(size_t bytes);
   void release();

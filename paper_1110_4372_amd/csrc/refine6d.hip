@@ -925,9 +925,9 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
   const bool plain = P.mode == LIBHALO_PLAIN;
   Rd rd{ctx, s, ctx.host_slot<uint32_t>(0)};
 
-  k_fill_i32<<<blocks_for(n, TB), TB, 0, s>>>(deepest, n, -1);
   *n_nodes = 0;
   if (G == 0) {
+    k_fill_i32<<<blocks_for(n, TB), TB, 0, s>>>(deepest, n, -1);
     HALO_HIP(hipStreamSynchronize(s));
     return;
   }
@@ -1003,6 +1003,8 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     dcnt = A.take<uint32_t>(16);
     grid_take(A, gb, M, Kmax);
   });
+  // outputs are written only once the workspace is in place
+  k_fill_i32<<<blocks_for(n, TB), TB, 0, s>>>(deepest, n, -1);
 
   HALO_HIP(hipMemsetAsync(ctx.d_err, 0, sizeof(uint32_t), s));
   k_level0<<<blocks_for(M, TB), TB, 0, s>>>(perm, grp_first, grp_count, (uint32_t)G, M, lidx,

@@ -967,8 +967,8 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     HALO_HIP(hipStreamSynchronize(s));
     return hb[slot];
   };
-  k_init_particles<<<blocks_for(n, TB), TB, 0, s>>>(bound, phi, (uint32_t)n);
   if (S == 0) {
+    k_init_particles<<<blocks_for(n, TB), TB, 0, s>>>(bound, phi, (uint32_t)n);
     HALO_HIP(hipStreamSynchronize(s));
     return;
   }
@@ -1032,6 +1032,8 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     w.pacc = A.take<I128>(N2);
     w.rtmp = A.take<char>(radix_tmp_bytes(std::max(S2, N2)));
   });
+  // outputs are written only once the workspace is in place
+  k_init_particles<<<blocks_for(n, TB), TB, 0, s>>>(bound, phi, (uint32_t)n);
   // children lists of the host/sub forest, ascending ids per host
   k_kept_host_keys<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.flag);
   exclusive_scan<uint32_t>(w.flag, w.pos, S, w.dcnt, w.stmp, s);

@@ -125,6 +125,25 @@ SYMBOLS = ["libhalo_ctx_create", "libhalo_ctx_destroy", "libhalo_last_error",
            "libhalo_profile_read", "libhalo_fof3d", "libhalo_refine6d", "libhalo_assign",
            "libhalo_unbind", "libhalo_props", "libhalo_props_extra"]
 
+# Workspace allocator callbacks of libhalo_ctx_create.
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+def torch_allocator(device: int):
+    """(alloc, free) callables serving the library's workspace from torch's
+    caching allocator on `device`, on the stream the library names."""
+    def alloc(nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(stream or 0))
+        except RuntimeError:  # out of memory: the library reports ENOMEM
+            return None
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+    return alloc, free
+
+
 _lib = None
 
 
@@ -138,7 +157,8 @@ def load_library(path: str = LIB_PATH):
     L = C.CDLL(path)
     i64, i32 = C.c_int64, C.c_int
     pi64 = C.POINTER(C.c_int64)
-    L.libhalo_ctx_create.argtypes = [C.POINTER(CParams), i32, C.POINTER(_P)]
+    L.libhalo_ctx_create.argtypes = [C.POINTER(CParams), i32, ALLOC_FN, FREE_FN, _P,
+                                     C.POINTER(_P)]
     L.libhalo_ctx_destroy.argtypes = [_P]
     L.libhalo_last_error.argtypes = [_P]
     L.libhalo_last_error.restype = C.c_char_p
@@ -219,15 +239,22 @@ class Particles:
 
 
 class Halo:
-    """A libhalo context on one device with its parameters."""
+    """A libhalo context on one device with its parameters.  The workspace
+    comes from torch's caching allocator unless `allocator` gives other
+    (alloc(nbytes, stream) -> int or None, free(ptr, stream)) callables."""
 
-    def __init__(self, params: Params, device: int = 0):
+    def __init__(self, params: Params, device: int = 0, allocator=None):
         self.L = load_library()
         self.params = params
         self.device = torch.device("cuda", device)
         self._cp = params.c()
+        alloc, free = allocator if allocator is not None else torch_allocator(device)
+        # the ctypes thunks must outlive the context
+        self._alloc = ALLOC_FN(lambda nbytes, user, stream: alloc(nbytes, stream))
+        self._free = FREE_FN(lambda ptr, user, stream: free(ptr, stream))
         h = C.c_void_p()
-        rc = self.L.libhalo_ctx_create(C.byref(self._cp), device, C.byref(h))
+        rc = self.L.libhalo_ctx_create(C.byref(self._cp), device, self._alloc, self._free,
+                                       None, C.byref(h))
         if rc != 0:
             raise HaloError(rc, "context creation failed")
         self.h = h

@@ -37,7 +37,7 @@ def test_version_and_bad_args_without_gpu(lib):
     lib.libhalo_version.restype = ctypes.c_char_p
     assert b"gfx950" in lib.libhalo_version()
     # null arguments are rejected before any device call
-    assert lib.libhalo_ctx_create(None, 0, None) == -1
+    assert lib.libhalo_ctx_create(None, 0, None, None, None, None) == -1
     assert lib.libhalo_ctx_destroy(None) == -1
     assert lib.libhalo_fof3d(None, 10, 0, None, None, None, None, None, None, None, 0,
                              None, None, None) == -1
@@ -57,3 +57,28 @@ def test_product_path_does_not_import_oracle():
     for f in ("halo.py", "build.py", "synth.py", "__init__.py"):
         src = open(os.path.join(ROOT, "paper_1110_4372_amd", f)).read()
         assert not re.search(r"^\s*(from|import)\s+oracle", src, re.M), f
+
+
+def test_library_allocates_no_device_memory():
+    """The workspace comes only from the caller's allocator callback: no HIP
+    source of the library calls the runtime's device allocators."""
+    import glob
+    pat = re.compile(r"\bhip(Malloc|MallocManaged|MallocAsync|ExtMallocWithFlags|Free|FreeAsync)"
+                     r"\s*\(")
+    srcs = glob.glob(os.path.join(ROOT, "paper_1110_4372_amd", "csrc", "*"))
+    assert srcs
+    for f in srcs:
+        code = re.sub(r"//[^\n]*|/\*.*?\*/", "", open(f).read(), flags=re.S)
+        assert not pat.search(code), f"{f} allocates device memory itself"
+
+
+def test_ctx_create_requires_allocator(lib):
+    """A null alloc or free callback is rejected before any device call."""
+    from paper_1110_4372_amd import halo
+    p = halo.Params(box=10.0, particle_mass=1.0, softening=0.01).c()
+    h = ctypes.c_void_p()
+    lib.libhalo_ctx_create.argtypes = [ctypes.POINTER(halo.CParams), ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+    assert lib.libhalo_ctx_create(ctypes.byref(p), 0, None, None, None, ctypes.byref(h)) == -1
+    assert not h.value

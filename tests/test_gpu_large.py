@@ -188,8 +188,6 @@ def test_c4_full_size_subcubes(H, orc):
     assert g >= 20 and h >= 20 and pr >= 20
 
 
-@pytest.mark.skipif(not os.environ.get("HALO_FULL_1024"),
-                    reason="1024^3 at full size takes minutes of GPU time: set HALO_FULL_1024=1")
 def test_c5_full_size_subcubes(H, orc):
     """The 1024^3 catalogue (1.07e9 particles) at full size on one GPU, mixed
     precision, against the oracle on sub-cubes."""
