@@ -534,6 +534,40 @@ static float ell2_subset(int64_t n, const float* xi6, const int64_t* mem, int32_
 }
 
 /* 6D FOF at ell^2: comp[i] = smallest local index of i's component. */
+/*
+ * The same two definitions for a range of particles, so that a caller can
+ * split one node's O(n^2) work over several threads: the nearest-neighbour
+ * d^2 of particles [i0, i1) among all n, and the friend pairs (i, j > i) with
+ * d^2 <= ell2 for i in [i0, i1), at most `cap` of them (returns the number
+ * found, which may exceed cap; only the first cap are written).
+ */
+void orc_nn6d_range(int64_t n, const float* xi6, int64_t i0, int64_t i1, float* dmin) {
+  for (int64_t i = i0; i < i1; ++i) {
+    float best = INFINITY;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      float d = d2_6d(xi6 + 6 * i, xi6 + 6 * j);
+      if (d < best) best = d;
+    }
+    dmin[i - i0] = best;
+  }
+}
+
+int64_t orc_friends6d_range(int64_t n, const float* xi6, float ell2, int64_t i0, int64_t i1,
+                            int64_t cap, int64_t* pairs) {
+  int64_t k = 0;
+  for (int64_t i = i0; i < i1; ++i)
+    for (int64_t j = i + 1; j < n; ++j)
+      if (d2_6d(xi6 + 6 * i, xi6 + 6 * j) <= ell2) {
+        if (k < cap) {
+          pairs[2 * k] = i;
+          pairs[2 * k + 1] = j;
+        }
+        ++k;
+      }
+  return k;
+}
+
 void orc_fof6d(int64_t n, const float* xi6, float ell2, int64_t* comp) {
   for (int64_t i = 0; i < n; ++i) comp[i] = i;
   for (int64_t i = 0; i < n; ++i)

@@ -145,6 +145,9 @@ int orc_node_normalise(const orc_params* p, int64_t n_members, int pos_f64,
 void orc_nn6d(int64_t n, const float* xi6, float* dmin);
 float orc_ell2(int64_t n, const float* dmin, double f);
 void orc_fof6d(int64_t n, const float* xi6, float ell2, int64_t* comp);
+void orc_nn6d_range(int64_t n, const float* xi6, int64_t i0, int64_t i1, float* dmin);
+int64_t orc_friends6d_range(int64_t n, const float* xi6, float ell2, int64_t i0, int64_t i1,
+                            int64_t cap, int64_t* pairs);
 void orc_phi_points(const orc_params* p, int pos_f64, const void* x, const void* y,
                     const void* z, const int64_t* src, int64_t nsrc, const int64_t* tgt,
                     int64_t ntgt, double* phi);

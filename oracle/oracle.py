@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import dataclasses
+import math
 import os
 import subprocess
 
@@ -145,6 +146,10 @@ def lib():
         L.orc_ell2.restype = C.c_float
         L.orc_fof6d.argtypes = [i64, _P, C.c_float, _P]
         L.orc_fof6d.restype = None
+        L.orc_nn6d_range.argtypes = [i64, _P, i64, i64, _P]
+        L.orc_nn6d_range.restype = None
+        L.orc_friends6d_range.argtypes = [i64, _P, C.c_float, i64, i64, i64, _P]
+        L.orc_friends6d_range.restype = C.c_int64
         L.orc_phi_points.argtypes = [C.POINTER(Params), i32, _P, _P, _P, _P, i64, _P, i64, _P]
         L.orc_phi_points.restype = None
         L.orc_in_subset.argtypes = [C.c_uint64, C.c_int64, C.c_int64]
@@ -454,6 +459,61 @@ def fof6d(xi: np.ndarray, l2: float) -> np.ndarray:
     comp = np.zeros(xi.shape[0], dtype=np.int64)
     lib().orc_fof6d(xi.shape[0], xi.ctypes.data, C.c_float(l2), comp.ctypes.data)
     return comp
+
+
+def _chunks(n, threads):
+    """Contiguous ranges of the particles, more of them than threads, the
+    early ones (longer rows in the pair loop) shorter."""
+    k = 4 * threads
+    edges = [int(round(n * (1.0 - math.sqrt(1.0 - t / k)))) for t in range(k + 1)]
+    return [(a, b) for a, b in zip(edges[:-1], edges[1:]) if b > a]
+
+
+def nn6d_threads(xi: np.ndarray, threads: int = 8) -> np.ndarray:
+    """nn6d with the particles split over threads (each range by the oracle's
+    plain loop; ctypes releases the GIL during the calls)."""
+    from concurrent.futures import ThreadPoolExecutor
+    xi = np.ascontiguousarray(xi, dtype=np.float32)
+    n = xi.shape[0]
+    d = np.zeros(n, dtype=np.float32)
+    even = [(n * t // (4 * threads), n * (t + 1) // (4 * threads)) for t in range(4 * threads)]
+
+    def run(r):
+        a, b = r
+        if b > a:
+            lib().orc_nn6d_range(n, xi.ctypes.data, a, b, d[a:].ctypes.data)
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(run, even))
+    return d
+
+
+def fof6d_threads(xi: np.ndarray, l2: float, threads: int = 8) -> np.ndarray:
+    """fof6d from the friend pairs (d^2 <= l2) found by the oracle's plain loop
+    over ranges of particles in threads; components by scipy.  Returns the
+    smallest member index of each particle's component."""
+    from concurrent.futures import ThreadPoolExecutor
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    xi = np.ascontiguousarray(xi, dtype=np.float32)
+    n = xi.shape[0]
+
+    def run(r):
+        a, b = r
+        cap = 1 << 20
+        while True:
+            buf = np.zeros(2 * cap, dtype=np.int64)
+            k = lib().orc_friends6d_range(n, xi.ctypes.data, C.c_float(l2), a, b, cap,
+                                          buf.ctypes.data)
+            if k <= cap:
+                return buf[:2 * k].reshape(-1, 2)
+            cap = int(k)
+    with ThreadPoolExecutor(threads) as ex:
+        pairs = np.concatenate(list(ex.map(run, _chunks(n, threads))) + [np.zeros((0, 2), np.int64)])
+    g = coo_matrix((np.ones(pairs.shape[0], np.int8), (pairs[:, 0], pairs[:, 1])), shape=(n, n))
+    _, lab = connected_components(g, directed=False)
+    mins = np.full(lab.max() + 1, n, dtype=np.int64)
+    np.minimum.at(mins, lab, np.arange(n))
+    return mins[lab]
 
 
 def phi_points(p: Params, P: Particles, src: np.ndarray, tgt: np.ndarray) -> np.ndarray:

@@ -245,17 +245,14 @@ __host__ __device__ __forceinline__ uint32_t nn_units(uint32_t n, uint32_t jmin)
   return ((n + 255u) / 256u) * ((n + J - 1) / J);
 }
 
-// Units of the nodes selected by `which`: 0 = all-pairs nodes, 1 = nodes whose
-// grid search fell back.
+// Units of the all-pairs nodes (those not searched by a tree).
 __global__ void k_pair_items(const uint32_t* count, const double* prm, const uint32_t* gstate,
-                             uint32_t K, int which, uint32_t jmin, uint32_t* items) {
+                             uint32_t K, uint32_t jmin, uint32_t* items) {
   uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   const uint32_t n = count[k];
   const bool active = prm[12 * (size_t)k + 11] != 0.0;
-  const uint32_t g = gstate[k];
-  const bool sel = which == 0 ? g == 0u : g == 2u;
-  items[k] = (active && sel) ? nn_units(n, jmin) : 0u;
+  items[k] = (active && gstate[k] == 0u) ? nn_units(n, jmin) : 0u;
 }
 
 
@@ -1060,13 +1057,13 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     // 2. normalised coordinates
     k_norm6<T><<<blocks_for(Mi, TB), TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, lnode, 0, Mi, box,
                                                  sc, xi, S);
-    // 3. nearest neighbours: grid search for large nodes, all-pairs for the rest
+    // 3. nearest neighbours: tree search for large nodes, all-pairs for the rest
     k_fill_u32<<<blocks_for(Mi, TB), TB, 0, s>>>(D, Mi, 0x7F800000u);
     k_iota<<<blocks_for(Mi, TB), TB, 0, s>>>(par, Mi);
     HALO_PROF(ctx, "grid_build", s,
-              grid_build(gb, xi, S, nd, K, lnode, Mi, M, sc, P.f, rd.h + 8, s, D,
+              grid_build(gb, xi, S, nd, K, lnode, Mi, M, sc, rd.h + 8, s, D,
                          P.grid_min > 0 ? (uint32_t)P.grid_min : kGridMin));
-    k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, 0, nnj,
+    k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, nnj,
                                                    sc.wpair);
     exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
     if (plain) {
@@ -1111,19 +1108,6 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       }
     };
     if (Mi > (uint32_t)kSelSmall) select_big();  // else no node is above kSelSmall
-    // grid nodes whose ell^2 exceeds their search radius: all-pairs again
-    if (grid_check(gb, sc, lnode, Mi, D, rd.h + 8, s) > 0) {
-      k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, 1, nnj,
-                                                     sc.wpair);
-      exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
-      k_fill_u32<<<1, 64, 0, s>>>(dcnt + 8, 1, 0u);
-      HALO_PROF(ctx, "k_nn", s,
-                k_nn<<<pgrid, TB, 0, s>>>(xi, S, nd, K, sc.wpair, 0, K, dcnt + 8, nnj, D));
-      if (msub > 0)
-        k_subset_sel<<<blocks_for(Mi, TB), TB, 0, s>>>(lidx, lnode, nd, Mi, msub, nsub, D,
-                                                       Dsel);
-      select_big();
-    }
     // 5. 6D FOF: all-pairs nodes over their compacted linkable particles
     k_link_flags<<<blocks_for(Mi, TB), TB, 0, s>>>(lnode, D, Mi, sc, cflag);
     exclusive_scan<uint32_t>(cflag, crank, Mi, crank + Mi, stmp, s);

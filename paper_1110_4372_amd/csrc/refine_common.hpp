@@ -29,7 +29,7 @@ struct LevelNodes {
 };
 
 struct NodeScratch {
-  uint32_t* gstate;          // 0 all-pairs, 1 grid search, 2 grid fell back to all-pairs
+  uint32_t* gstate;          // 0 all-pairs, 1 tree search
   I128* acc;                 // 8 per node: sum qx, qy, qz, q^2, sum wx, wy, wz, w^2
   unsigned long long* ext;   // 6 per node: ordered min/max of u per axis (level 0)
   double* prm;               // 12 per node: anchor xyz, ubar xyz, vbar xyz, isx, isv, active
@@ -60,39 +60,47 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint
 }
 
 
-// ---- exact fixed-radius tile search for large nodes (grid6d.hip) ----
-constexpr uint32_t kGridMin = 131072; // default: nodes above this size use the tile search
+// ---- exact tree search for large nodes (grid6d.hip) ----
+constexpr uint32_t kGridMin = 131072; // default: nodes above this size use the tree search
 constexpr uint32_t kGridFloor = 64;   // smallest accepted threshold
-constexpr int kSamples = 512;         // sample size of the radius estimate
-// Search radius: R^2 = kRadiusFactor x the sample's (f + kSampleMargin)
-// quantile of NN d^2; the result is exact whenever the node's l^2 <= R^2, else
-// the node is redone all-pairs.  A tighter radius (1.1 x the f + 0.05
-// quantile) measured no faster: in 6D a 64-particle tile spans ~1/5 of each
-// coordinate range, so the candidate tiles are its neighbours whatever R is.
-constexpr float kSampleMargin = 0.0f;
-constexpr float kRadiusFactor = 2.0f;
+constexpr uint32_t kKdLeaf = 16;      // a tree node of at most this many particles is a leaf
+constexpr int kKdMaxDepth = 47;       // nodes at this depth are leaves whatever their size
+
+// A tree node: the bounding box of its particles and their range in the
+// sorted order; `left` is the first of its two adjacent children, or
+// kKdNone for a leaf.  64 bytes, so a node's two children are one 128-byte
+// read.
+constexpr uint32_t kKdNone = 0xFFFFFFFFu;
+struct __align__(16) KdNode {
+  float mn[6], mx[6];
+  uint32_t lo, hi, left, depth;
+};
+// A particle of a tree node in the sorted order: the six normalised
+// coordinates, its position m in the level arrays and its grid node b.
+struct __align__(16) KdPoint {
+  float x[6];
+  uint32_t m, b;
+};
 
 struct GridBufs {
-  uint32_t *nb_rank, *gnode, *ncell, *cellbase, *pstart, *gcount, *gtile_node;
-  float *samp, *r2, *tbox;
-  float* sbox;  // 12 per super-tile of 64 tiles: the union of their boxes
-  uint32_t *flag, *pos, *v0, *v1, *gm, *cnt, *stmp;
+  uint32_t *nb_rank, *gnode, *pstart, *gcount;
+  uint32_t *flag, *pos, *v0, *v1, *cnt, *stmp, *split;
   unsigned long long *k0, *k1;
-  float* gx;  // six planes of stride MB, sorted order
+  KdPoint* pt;       // MB points in sorted order
+  KdNode* node;      // tree nodes, level by level; roots are 0 .. NB-1
   void* rtmp;
-  uint32_t MB = 0, NB = 0, NT = 0;
+  uint32_t node_cap = 0;
+  uint32_t MB = 0, NB = 0, NN = 0;  // sorted points, grid nodes, tree nodes
 };
 
 void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax);
-// Classifies the level's nodes (sc.gstate), builds the grid of the large ones
-// and writes their nearest-neighbour distances into D.  Returns their number.
+// Classifies the level's nodes (sc.gstate 1 for tree nodes), builds their
+// trees and writes their exact nearest-neighbour distances into D.  Returns
+// the number of tree nodes of the level.
 uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint32_t K,
-                    const uint32_t* lnode, uint32_t Mi, uint32_t M, NodeScratch sc, double f,
+                    const uint32_t* lnode, uint32_t Mi, uint32_t M, NodeScratch sc,
                     uint32_t* hb, hipStream_t s, uint32_t* D, uint32_t gmin);
-// After the selection: nodes whose ell^2 exceeds their search radius get
-// gstate 2 and their D reset; returns how many.
-uint32_t grid_check(GridBufs& g, NodeScratch sc, const uint32_t* lnode, uint32_t Mi,
-                    uint32_t* D, uint32_t* hb, hipStream_t s);
+// 6D FOF at each tree node's ell^2 over its particles with D <= ell^2.
 void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par, hipStream_t s);
 
 // min over j in [j0, j1) of d2(i, j) over six FP32 coordinate planes of stride

@@ -124,3 +124,52 @@ def test_tree_workspace_placement(H, c1):
         np.testing.assert_array_equal(to_np(phi), to_np(a["phi"]))
         np.testing.assert_array_equal(to_np(bound), to_np(a["bound"]))
         np.testing.assert_array_equal(to_np(unb["n_s"]), to_np(a["unbound"]["n_s"]))
+
+
+def test_tree_large_haloes_c3(H, orc):
+    """The 512^3 catalogue at full size with the tree potential (theta = 0.04,
+    haloes of |S(h)| >= 65536): for the three largest tree haloes (the largest
+    near 10^6 particles, trees far deeper than c1's), the potential of 1000
+    sampled own particles lies within theta of the exact direct sum over S(h)
+    that the oracle computes for those particles; the walk's stack never runs
+    out (the call would fail)."""
+    import torch
+    from paper_1110_4372_amd import synth
+    note("tree potential on the largest 512^3 haloes")
+    theta = 0.04
+    cat = synth.make_catalog_device("c3", seed=0)
+    P = H.Particles.from_catalog(cat)
+    g = H.Halo(H.params_for_catalog(cat, bh_theta=theta)).run_all(P)
+    torch.cuda.synchronize()
+    h = {k: to_np(v) for k, v in g["halos"].items()}
+    ns = to_np(g["unbound"]["n_s"]).astype(np.int64)
+    kept = h["merged_into"] == np.arange(ns.shape[0])
+    big = np.nonzero(kept & (ns >= 100000))[0]
+    assert big.shape[0] >= 3
+    big = big[np.argsort(-ns[big])][:3]
+    assert ns[big[0]] >= 300000
+    hof = to_np(g["halo_of"]).astype(np.int64)
+    host = h["host"].astype(np.int64)
+    phi = g["phi"]
+    p = orc.params_of(cat)
+    rng = np.random.default_rng(3)
+    for t in big:
+        # S(t): particles of t and of every halo below it in the host links
+        under = np.arange(host.shape[0]) == t
+        anc = host.copy()
+        while np.any(anc >= 0):
+            under |= anc == t
+            anc = np.where(anc >= 0, host[np.maximum(anc, 0)], -1)
+        src = np.nonzero((hof >= 0) & under[np.maximum(hof, 0)])[0]
+        assert src.shape[0] == ns[t]
+        own = np.nonzero(hof == t)[0]
+        tgt = np.sort(rng.choice(own, 1000, replace=False))
+        idx = torch.from_numpy(src).to(P.x.device)
+        sub = orc.Particles(*[np.ascontiguousarray(to_np(a[idx]))
+                              for a in (P.x, P.y, P.z, P.vx, P.vy, P.vz)])
+        exact = orc.phi_points(p, sub, np.arange(src.shape[0]), np.searchsorted(src, tgt))
+        got = to_np(phi[torch.from_numpy(tgt).to(P.x.device)])
+        rel = np.abs(got / exact - 1.0)
+        print(f"halo {t}: |S(h)| {ns[t]}, sampled relative error median {np.median(rel):.2e} "
+              f"max {rel.max():.2e}", flush=True)
+        assert rel.max() <= theta

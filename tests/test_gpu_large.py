@@ -8,7 +8,6 @@ random sub-cubes (the box and the linking length of the full catalogue), and
 the GPU's output for the interior groups -- labels, node table, deepest node,
 halo table, halo_of and bound flags -- must match it exactly, as at the
 smaller sizes; the basic and additional halo properties within 1e-5."""
-import os
 
 import numpy as np
 import pytest
@@ -241,3 +240,64 @@ def test_c4_mixed_matches_fp64(H):
     if changed.shape[0] == 0:
         for k in a["props"]:
             np.testing.assert_array_equal(to_np(a["props"][k]), to_np(b["props"][k]))
+
+
+def test_c3_single_large_group(H, orc):
+    """A FOF group of the 512^3 catalogue just above the tree threshold (the
+    nodes above it take the tree search of Section 3.2's nearest neighbours and
+    6D FOF), refined alone on the GPU at its real size; the oracle computes the
+    same group's level-0 node (moments, normalised coordinates, every
+    nearest-neighbour distance, ell^2) and its 6D FOF components in full, its
+    O(n^2) loops split over the host's cores.  The level-0 row, the children
+    and every particle's level-1 subgroup must match exactly."""
+    from paper_1110_4372_amd import synth
+    note("c3 single large group through the tree search")
+    cat = synth.make_catalog_device("c3", seed=0)
+    P = H.Particles.from_catalog(cat)
+    ctx = H.Halo(H.params_for_catalog(cat))
+    fof = ctx.fof3d(P)
+    cnt = to_np(fof["grp_count"]).astype(np.int64)
+    first = to_np(fof["grp_first"]).astype(np.int64)
+    big = np.nonzero((cnt > 131072) & (cnt <= 200000))[0]
+    assert big.shape[0] >= 1
+    g = int(big[np.argmin(cnt[big])])
+    n = int(cnt[g])
+    members = fof["perm"][int(first[g]):int(first[g]) + n].clone()
+    one = dict(perm=members, grp_first=torch.zeros(1, dtype=torch.int32, device=P.x.device),
+               grp_count=torch.full((1,), n, dtype=torch.int32, device=P.x.device),
+               n_groups=1, n_members=n)
+    nodes, deep = ctx.refine6d(P, one)
+    gn = gpu_nodes(nodes)
+    mem = to_np(members).astype(np.int64)
+    assert np.all(np.diff(mem) > 0)
+    sub = [to_np(a[members.long()]) for a in (P.x, P.y, P.z, P.vx, P.vy, P.vz)]
+    Ps = orc.Particles(*[np.ascontiguousarray(a) for a in sub])
+    p = orc.params_of(cat)
+    xi, mom = orc.node_normalise(p, Ps, np.arange(n))
+    # level-0 row: moments and the linking length from every particle's
+    # nearest neighbour
+    row0 = [gn[f][0] for f in ("cx", "cy", "cz", "vx", "vy", "vz", "sx2", "sv2")]
+    np.testing.assert_array_equal(np.array(row0), mom)
+    assert gn["count"][0] == n and gn["canon"][0] == mem[0] and gn["level"][0] == 0
+    D = orc.nn6d_threads(xi, threads=16)
+    l2 = float(orc.ell2(D, p.f))
+    assert np.float32(gn["ell2"][0]).view(np.uint32) == np.float32(l2).view(np.uint32)
+    comp = orc.fof6d_threads(xi, l2, threads=16)
+    size = np.bincount(comp, minlength=n)
+    kids = np.nonzero(size >= p.min_members)[0]
+    # children of row 0, in canonical order, and each particle's level-1 node
+    rows = np.nonzero(gn["parent"] == 0)[0]
+    assert np.array_equal(gn["canon"][rows].astype(np.int64), mem[kids])
+    assert np.array_equal(gn["count"][rows].astype(np.int64), size[kids])
+    cur = to_np(deep)[mem].astype(np.int64)
+    assert np.all(cur >= 0)
+    lev = gn["level"][cur]
+    while np.any(lev > 1):
+        cur = np.where(lev > 1, gn["parent"][cur], cur)
+        lev = gn["level"][cur]
+    lvl1 = np.where(lev == 1, cur, -1)
+    want = np.where(size[comp] >= p.min_members, mem[comp], -1)
+    got = np.where(lvl1 >= 0, gn["canon"][np.maximum(lvl1, 0)].astype(np.int64), -1)
+    np.testing.assert_array_equal(got, want)
+    print(f"group of {n} particles: ell^2 {l2:.6g}, {rows.shape[0]} children, "
+          f"{int(np.sum(D <= l2))} linkable", flush=True)

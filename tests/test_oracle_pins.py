@@ -648,3 +648,15 @@ def test_oracle_imports_nothing_from_the_product():
         for line in open(f):
             if line.lstrip().startswith("#include"):
                 assert "libhalo" not in line and "csrc" not in line, f"{f}: {line}"
+
+
+def test_threaded_node_loops_equal_the_serial_ones(orc):
+    """The range forms of the nearest-neighbour and 6D FOF loops, split over
+    threads, give the serial loops' results bit for bit."""
+    rng = np.random.default_rng(17)
+    xi = np.concatenate([rng.standard_normal((1500, 6)),
+                         0.05 * rng.standard_normal((500, 6)) + 1.0]).astype(np.float32)
+    d = orc.nn6d(xi)
+    np.testing.assert_array_equal(orc.nn6d_threads(xi, threads=3), d)
+    l2 = float(orc.ell2(d))
+    np.testing.assert_array_equal(orc.fof6d_threads(xi, l2, threads=3), orc.fof6d(xi, l2))
