@@ -3,23 +3,26 @@
 // beyond the Salmon-Warren distance).
 //
 // Per halo the particles of S(h) are sorted along a 48-bit Morton curve over
-// their bounding box, and the tree is implicit over that order: heap node k
-// at level l covers the sorted range [floor(i n / 2^l), floor((i+1) n / 2^l))
-// with i = k - 2^l, down to leaves of at most 17 particles.  A cell's mass
-// centre x0, its dispersion sigma^2 about x0 and r_max (the largest distance
-// of its particles from x0, found by a pass over the particles) give the
-// acceptance distance d >= r_max / 2 + sqrt((r_max / 2)^2 + sigma^2 / theta),
-// beyond which the monopole's relative error is at most theta.  One wavefront
-// per 64 Morton-consecutive particles walks the tree depth first: a cell
-// acceptable for every target lane adds m / sqrt(d^2 + eps^2) to each, any
-// other cell is opened for all, and opened leaves add their particles one by
-// one.  Each lane sums in the wave's fixed order, so the result does not
-// depend on scheduling.
+// their bounding box, and a binary tree is built over that order (mtree.hpp):
+// a cell holding more than kLeaf particles splits where the highest differing
+// Morton bit of its particles changes, so each child is one cell of the curve
+// (an octree cell, shrunk to its particles).  A cell's mass centre x0, its
+// dispersion sigma^2 about x0 and r_max (the largest distance of its
+// particles from x0, found by a pass over the particles) give the acceptance
+// distance d >= r_max / 2 + sqrt((r_max / 2)^2 + sigma^2 / theta), beyond
+// which the monopole's relative error is at most theta.  The cells are stored
+// in depth-first preorder with the index after each subtree, and one
+// wavefront per 64 Morton-consecutive particles walks them in order: a cell
+// acceptable for every target lane adds m / sqrt(d^2 + eps^2) to each and is
+// skipped, a leaf that is not adds its particles one by one, any other cell
+// is entered.  The walk needs no stack.  Each lane sums in the wave's fixed
+// order, so the result does not depend on scheduling.
 #include <algorithm>
 #include <cmath>
 #include <vector>
 
 #include "bh.hpp"
+#include "mtree.hpp"
 #include "primitives.hpp"
 
 namespace halo {
@@ -27,8 +30,8 @@ namespace halo {
 namespace {
 
 constexpr int TB = 256;
-constexpr uint32_t kLeaf = 16;
-constexpr int kStack = 64;
+constexpr uint32_t kLeaf = 16;     // a cell of at most this many particles is a leaf
+constexpr uint32_t kMaxDepth = 64; // cells at this depth are leaves whatever their size
 constexpr int kFrac = 32;  // fractional bits of the potential accumulators
 
 __device__ __forceinline__ uint32_t seg_find(const uint32_t* off, uint32_t K, uint32_t w) {
@@ -41,12 +44,6 @@ __device__ __forceinline__ uint32_t seg_find(const uint32_t* off, uint32_t K, ui
       hi = mid;
   }
   return lo;
-}
-
-__host__ __device__ __forceinline__ uint32_t depth_for(uint32_t n) {
-  uint32_t d = 0;
-  while ((n >> d) > kLeaf) ++d;
-  return d;
 }
 
 // round(v 2^frac), 0 <= v 2^frac < 2^94, as a 128-bit integer.
@@ -82,7 +79,7 @@ __global__ void k_bh_flags(const libhalo_halos h, uint32_t S, const uint32_t* nS
 }
 
 struct BhList {
-  uint32_t *big, *nel, *nnode, *depth, *nown, *eoff, *noff;
+  uint32_t *big, *nel, *nown, *eoff;
 };
 
 __global__ void k_bh_list(const uint32_t* flag, const uint32_t* pos, uint32_t S,
@@ -90,12 +87,8 @@ __global__ void k_bh_list(const uint32_t* flag, const uint32_t* pos, uint32_t S,
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S || !flag[s]) return;
   const uint32_t b = pos[s];
-  const uint32_t n = nS[s];
-  const uint32_t d = depth_for(n);
   L.big[b] = s;
-  L.nel[b] = n;
-  L.depth[b] = d;
-  L.nnode[b] = 2u << d;
+  L.nel[b] = nS[s];
   L.nown[b] = h.n_assigned[s];
 }
 
@@ -180,146 +173,110 @@ __global__ void k_bh_gather(const double* ux, const double* uy, const double* uz
   pz[e] = uz[q];
 }
 
-// Node records, one 64-byte line per node: the walk reads a node's centre,
-// mass and acceptance distance in one scalar fetch.
-struct BhNodes {
-  double* r;
-  __device__ __forceinline__ double& cx(uint32_t g) const { return r[8ull * g + 0]; }
-  __device__ __forceinline__ double& cy(uint32_t g) const { return r[8ull * g + 1]; }
-  __device__ __forceinline__ double& cz(uint32_t g) const { return r[8ull * g + 2]; }
-  __device__ __forceinline__ double& cm(uint32_t g) const { return r[8ull * g + 3]; }
-  __device__ __forceinline__ double& crit2(uint32_t g) const { return r[8ull * g + 4]; }
-  __device__ __forceinline__ double& sig2(uint32_t g) const { return r[8ull * g + 5]; }
-  __device__ __forceinline__ double& rmax(uint32_t g) const { return r[8ull * g + 6]; }
-  // exact r_max as an ordered integer, raised by atomicMax
-  __device__ __forceinline__ unsigned long long* rmx(uint32_t g) const {
-    return reinterpret_cast<unsigned long long*>(r + 8ull * g + 7);
-  }
+// A cell as the walk reads it (one 64-byte scalar fetch), in preorder: mass
+// centre, mass (particles), dispersion, squared acceptance distance, its range
+// of the sorted order, the index after its subtree, and whether it is a leaf.
+struct __align__(16) BhRec {
+  double cx, cy, cz, cm, sig2, crit2;
+  uint32_t lo, hi, skip, leaf;
 };
 
-__device__ __forceinline__ void node_range(uint32_t k, uint32_t n, uint32_t& lo, uint32_t& hi) {
-  const uint32_t l = 31u - (uint32_t)__builtin_clz(k);
-  const unsigned long long i = (unsigned long long)(k - (1u << l));
-  lo = (uint32_t)((i * n) >> l);
-  hi = (uint32_t)(((i + 1ull) * n) >> l);
-}
-
-// Cell statistics of every node at `level` (leaves directly, others from
-// their children, which the previous launch filled).
-__global__ void k_bh_level(BhList L, uint32_t B, uint32_t T, uint32_t level, double theta,
-                           const double* px, const double* py, const double* pz, BhNodes N) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= T) return;
-  const uint32_t b = seg_find(L.noff, B, t);
-  const uint32_t k = t - L.noff[b];
-  if (k == 0) return;
-  const uint32_t l = 31u - (uint32_t)__builtin_clz(k);
-  const uint32_t D = L.depth[b];
-  if (l != level || l > D) return;
-  double x0[3], m, s2, r;
-  if (l == D) {
-    uint32_t lo, hi;
-    node_range(k, L.nel[b], lo, hi);
-    const uint32_t base = L.eoff[b];
+// Cell statistics of the nodes [u0, u0 + nu) of one depth: leaves from their
+// particles, others from their children's records (one depth deeper, already
+// written); r_max follows from a pass over the particles.
+__global__ void k_bh_records(const MtNode* bnode, const uint32_t* pre, uint32_t u0, uint32_t nu,
+                             const double* px, const double* py, const double* pz, BhRec* R) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nu) return;
+  const MtNode u = bnode[u0 + i];
+  const uint32_t p = pre[u0 + i];
+  double x0[3], m, s2;
+  if (u.left == kMtNone) {
     double sx = 0.0, sy = 0.0, sz = 0.0;
-    for (uint32_t e = base + lo; e < base + hi; ++e) {
+    for (uint32_t e = u.lo; e < u.hi; ++e) {
       sx += px[e];
       sy += py[e];
       sz += pz[e];
     }
-    m = (double)(hi - lo);
+    m = (double)(u.hi - u.lo);
     x0[0] = sx / m;
     x0[1] = sy / m;
     x0[2] = sz / m;
     s2 = 0.0;
-    r = 0.0;
-    for (uint32_t e = base + lo; e < base + hi; ++e) {
-      const double d2 = sq3(px[e] - x0[0], py[e] - x0[1], pz[e] - x0[2]);
-      s2 += d2;
-      r = fmax(r, d2);
-    }
+    for (uint32_t e = u.lo; e < u.hi; ++e)
+      s2 += sq3(px[e] - x0[0], py[e] - x0[1], pz[e] - x0[2]);
     s2 /= m;
-    r = sqrt(r);
   } else {
-    const uint32_t g1 = L.noff[b] + 2u * k, g2 = g1 + 1u;
-    const double m1 = N.cm(g1), m2 = N.cm(g2);
+    const BhRec& a = R[pre[u.left]];
+    const BhRec& b = R[pre[u.left + 1]];
+    const double m1 = a.cm, m2 = b.cm;
     m = m1 + m2;
-    x0[0] = (m1 * N.cx(g1) + m2 * N.cx(g2)) / m;
-    x0[1] = (m1 * N.cy(g1) + m2 * N.cy(g2)) / m;
-    x0[2] = (m1 * N.cz(g1) + m2 * N.cz(g2)) / m;
-    const double d1 = sq3(N.cx(g1) - x0[0], N.cy(g1) - x0[1], N.cz(g1) - x0[2]);
-    const double d2 = sq3(N.cx(g2) - x0[0], N.cy(g2) - x0[1], N.cz(g2) - x0[2]);
-    s2 = (m1 * (N.sig2(g1) + d1) + m2 * (N.sig2(g2) + d2)) / m;
-    r = fmax(sqrt(d1) + N.rmax(g1), sqrt(d2) + N.rmax(g2));
+    x0[0] = (m1 * a.cx + m2 * b.cx) / m;
+    x0[1] = (m1 * a.cy + m2 * b.cy) / m;
+    x0[2] = (m1 * a.cz + m2 * b.cz) / m;
+    const double d1 = sq3(a.cx - x0[0], a.cy - x0[1], a.cz - x0[2]);
+    const double d2 = sq3(b.cx - x0[0], b.cy - x0[1], b.cz - x0[2]);
+    s2 = (m1 * (a.sig2 + d1) + m2 * (b.sig2 + d2)) / m;
   }
-  const uint32_t g = t;
-  N.cx(g) = x0[0];
-  N.cy(g) = x0[1];
-  N.cz(g) = x0[2];
-  N.cm(g) = m;
-  N.sig2(g) = s2;
-  N.rmax(g) = r;
-  const double dc = 0.5 * r + sqrt(0.25 * r * r + s2 / theta);
-  N.crit2(g) = dc * dc;
+  BhRec r;
+  r.cx = x0[0];
+  r.cy = x0[1];
+  r.cz = x0[2];
+  r.cm = m;
+  r.sig2 = s2;
+  r.crit2 = 0.0;
+  r.lo = u.lo;
+  r.hi = u.hi;
+  r.skip = p + u.aux;
+  r.leaf = u.left == kMtNone ? 1u : 0u;
+  R[p] = r;
 }
 
-// Node of level l holding sorted position p of a halo of n particles: the i
-// with floor(i n / 2^l) <= p < floor((i + 1) n / 2^l).
-__device__ __forceinline__ uint32_t node_at(uint32_t p, uint32_t n, uint32_t l) {
-  unsigned long long i = (((unsigned long long)p) << l) / n;
-  while (((i + 1ull) * n >> l) <= p) ++i;
-  while (i > 0 && ((i * n) >> l) > p) --i;
-  return (1u << l) + (uint32_t)i;
-}
-
-// Exact r_max of every cell: each particle raises the maximum of its cell on
-// every level (as ordered integers; a wave whose particles share a cell sends
-// one atomic for it).
-__global__ void k_bh_rmax_init(BhNodes N, uint32_t T) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < T) *N.rmx(t) = 0ull;
-}
-
-__global__ void k_bh_rmax(BhList L, uint32_t B, uint32_t E, const double* px, const double* py,
-                          const double* pz, BhNodes N) {
+// Exact r_max of every cell, one depth per launch: each particle follows its
+// cell down the tree (cur: level-order index of its cell at this depth, kMtNone
+// once past its leaf), and the particles of a wave, whose cells form runs
+// along the sorted order, reduce each run to one atomic maximum (ordered
+// integers) before moving to the child that holds them.
+__global__ void k_bh_rmax_depth(uint32_t E, const double* px, const double* py, const double* pz,
+                                const MtNode* bnode, const uint32_t* pre, const BhRec* R,
+                                uint32_t* cur, unsigned long long* rmx) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = e < E;
-  const uint32_t b = ok ? seg_find(L.eoff, B, e) : 0u;
-  const uint32_t D = ok ? L.depth[b] : 0u;
-  // every lane runs the same number of levels (the wave maximum) for the
-  // wave-wide exchanges; lanes past their own depth or range stay idle
-  uint32_t Dm = D;
-  for (int o = 32; o > 0; o >>= 1) Dm = max(Dm, (uint32_t)__shfl_xor((int)Dm, o));
-  for (uint32_t l = 0; l <= Dm; ++l) {
-    const bool act = ok && l <= D;
-    uint32_t g = 0xFFFFFFFFu;
-    unsigned long long v = 0ull;
-    if (act) {
-      const uint32_t k = node_at(e - L.eoff[b], L.nel[b], l);
-      g = L.noff[b] + k;
-      v = f64_ord(sqrt(sq3(px[e] - N.cx(g), py[e] - N.cy(g), pz[e] - N.cz(g))));
-    }
-    const uint32_t g0 = __shfl(g, 0);
-    if (__all(g == g0) && g0 != 0xFFFFFFFFu) {
-      for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long w2 = __shfl_xor(v, o);
-        v = w2 > v ? w2 : v;
-      }
-      if ((threadIdx.x & 63u) == 0) atomicMax(N.rmx(g0), v);
-    } else if (act) {
-      atomicMax(N.rmx(g), v);
-    }
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t u = e < E ? cur[e] : kMtNone;
+  unsigned long long v = 0ull;
+  uint32_t p = kMtNone;
+  if (u != kMtNone) {
+    p = pre[u];
+    v = f64_ord(sqrt(sq3(px[e] - R[p].cx, py[e] - R[p].cy, pz[e] - R[p].cz)));
   }
+  // maximum over the rest of this lane's run (runs of equal cells are
+  // contiguous): lane i ends with the maximum over [i, end of its run]
+  for (uint32_t o = 1; o < 64u; o <<= 1) {
+    const unsigned long long vo = __shfl_down(v, o);
+    const uint32_t po = __shfl_down(p, o);
+    if (lane + o < 64u && po == p && vo > v) v = vo;
+  }
+  const uint32_t pp = __shfl_up(p, 1);
+  if (p != kMtNone && (lane == 0u || pp != p)) atomicMax(rmx + p, v);
+  if (u != kMtNone) {
+    const MtNode n = bnode[u];
+    cur[e] = n.left == kMtNone ? kMtNone : (e < bnode[n.left].hi ? n.left : n.left + 1u);
+  }
+}
+
+// Each element starts at the root of its halo's tree (roots are 0 .. B-1).
+__global__ void k_bh_rmax_roots(BhList L, uint32_t B, uint32_t E, uint32_t* cur) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E) cur[e] = seg_find(L.eoff, B, e);
 }
 
 // Acceptance distances from the exact r_max.
-__global__ void k_bh_crit(uint32_t T, double theta, BhNodes N) {
+__global__ void k_bh_crit(uint32_t T, double theta, const unsigned long long* rmx, BhRec* R) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= T || *N.rmx(t) == 0ull) return;  // index 0 of each heap is unused
-  const double r = ord_f64(*N.rmx(t));
-  N.rmax(t) = r;
-  const double dc = 0.5 * r + sqrt(0.25 * r * r + N.sig2(t) / theta);
-  N.crit2(t) = dc * dc;
+  if (t >= T) return;
+  const double r = ord_f64(rmx[t]);
+  const double dc = 0.5 * r + sqrt(0.25 * r * r + R[t].sig2 / theta);
+  R[t].crit2 = dc * dc;
 }
 
 // Wave units of each tree halo: its sorted elements in runs of 64.
@@ -331,27 +288,25 @@ __global__ void k_bh_wave_counts(BhList L, uint32_t B, uint32_t* wcnt) {
 
 // The walk, one wavefront per 64 consecutive sorted elements of one halo
 // (spatially close along the curve); lanes holding an own particle are the
-// targets, the others only ride along.  The wave walks one tree: a cell is
-// taken as a monopole when it is acceptable for every target lane, else it
-// is opened for all (which only makes the others more exact).  Node data are
-// wave-uniform (scalar loads), the stack is the wave's own in LDS, and each lane sums
-// its terms in the wave's fixed order.
+// targets, the others only ride along.  The wave reads the halo's cells in
+// preorder: a cell acceptable for every target lane (it lies beyond the
+// acceptance distance and does not hold the target) is taken as a monopole and
+// skipped, a leaf that is not is searched particle by particle, any other cell
+// is entered (its first child is the next record).  Cell records and
+// leaf particles are read at wave-uniform addresses (scalar loads), and each
+// lane sums its terms in the wave's fixed order.
 __global__ void __launch_bounds__(TB)
     k_bh_walk(BhList L, uint32_t B, const uint32_t* woff, uint32_t nwave, const uint32_t* slot,
               const double* __restrict__ px, const double* __restrict__ py,
               const double* __restrict__ pz, const uint32_t* __restrict__ pidx,
-              const double* __restrict__ nrec, double eps2, I128* __restrict__ pacc,
-              uint32_t* __restrict__ err) {
-  // read-only inputs that no pointer of the kernel writes: wave-uniform reads of
-  // them can take the scalar data cache
-  const BhNodes N{const_cast<double*>(nrec)};
-  __shared__ uint32_t wstack[TB / 64][kStack];
+              const BhRec* __restrict__ R, const uint32_t* __restrict__ troot, double eps2,
+              I128* __restrict__ pacc) {
   const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (TB / 64) +
                                                        (threadIdx.x >> 6));
   if (wave >= nwave) return;  // wave-uniform
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t b = __builtin_amdgcn_readfirstlane(seg_find(woff, B, wave));
-  const uint32_t n = L.nel[b], D = L.depth[b], nb = L.noff[b], base = L.eoff[b];
+  const uint32_t n = L.nel[b], base = L.eoff[b];
   const uint32_t s0 = slot[L.big[b]], nown = L.nown[b];
   const uint32_t e = base + (wave - woff[b]) * 64u + lane;
   const bool in = e < base + n;
@@ -359,42 +314,33 @@ __global__ void __launch_bounds__(TB)
   const bool target = in && (q - s0) < nown;
   if (__ballot(target) == 0ull) return;  // wave-uniform
   const double x = in ? px[e] : 0.0, y = in ? py[e] : 0.0, z = in ? pz[e] : 0.0;
-  uint32_t* stack = wstack[threadIdx.x >> 6];  // the wave's own LDS stack
-  // Depth-first, left child first: an opened cell goes on to its left child at
-  // once and leaves only the right one on the stack (at most one entry per level).
-  int sp = 0;
-  uint32_t k = 1u;
+  uint32_t u = __builtin_amdgcn_readfirstlane(troot[b]);
+  const uint32_t end = __builtin_amdgcn_readfirstlane(troot[b + 1]);
   double acc = 0.0;
-  for (;;) {
-    const uint32_t g = nb + k;
-    const double cx = N.cx(g), cy = N.cy(g), cz = N.cz(g), cm = N.cm(g), c2 = N.crit2(g);
-    const double d2 = sq3(x - cx, y - cy, z - cz);
-    const uint32_t l = 31u - (uint32_t)__builtin_clz(k);
-    if (__ballot(target && d2 < c2) == 0ull) {
-      if (target) acc += cm * rsqrt_f64(d2 + eps2);
-    } else if (l == D) {
-      uint32_t lo, hi;
-      node_range(k, n, lo, hi);
+  while (u < end) {
+    const BhRec& c = R[u];
+    const double d2 = sq3(x - c.cx, y - c.cy, z - c.cz);
+    // a cell is a monopole for a target outside it beyond the acceptance
+    // distance; the cell holding the target itself is always opened (a cell of
+    // coincident particles has a zero acceptance distance)
+    const bool open = d2 <= c.crit2 || (e >= c.lo && e < c.hi);
+    if (__ballot(target && open) == 0ull) {
+      if (target) acc += c.cm * rsqrt_f64(d2 + eps2);
+      u = c.skip;
+    } else if (c.leaf) {
       // every lane evaluates each term and keeps it by a select, so the loads of a
       // leaf particle are not behind a branch and several can be in flight at once
 #pragma unroll 4
-      for (uint32_t f = base + lo; f < base + hi; ++f) {
+      for (uint32_t f = c.lo; f < c.hi; ++f) {
         const double fx = px[f], fy = py[f], fz = pz[f];
         const uint32_t qf = pidx[f];
         const double tf = rsqrt_f64(sq3(x - fx, y - fy, z - fz) + eps2);
         acc = (target && qf != q) ? acc + tf : acc;
       }
+      u = c.skip;
     } else {
-      if (sp + 1 > kStack) {  // cannot happen for depth <= 31; reported, not faulted
-        if (lane == 0) atomicOr(err, 1u);
-        break;
-      }
-      stack[sp++] = 2u * k + 1u;
-      k = 2u * k;
-      continue;
+      u = u + 1u;
     }
-    if (sp == 0) break;
-    k = __builtin_amdgcn_readfirstlane(stack[--sp]);
   }
   if (target && acc > 0.0) atomic_add_i128(pacc + q, fixed128(acc, kFrac));
 }
@@ -438,11 +384,8 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
     w.stmp = A.take<uint32_t>(scan_tmp_elems<uint32_t>(S + 2));
     w.L.big = A.take<uint32_t>(S + 2);
     w.L.nel = A.take<uint32_t>(S + 2);
-    w.L.nnode = A.take<uint32_t>(S + 2);
-    w.L.depth = A.take<uint32_t>(S + 2);
     w.L.nown = A.take<uint32_t>(S + 2);
     w.L.eoff = A.take<uint32_t>(S + 2);
-    w.L.noff = A.take<uint32_t>(S + 2);
     w.bb = A.take<unsigned long long>(6ull * (S + 2));
   };
   auto build_list = [&]() {
@@ -458,28 +401,25 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   if (B == 0) return;
   HALO_CHECK(B < 65536u, LIBHALO_EINVAL, "more than 65535 haloes take the tree (raise bh_min)");
   exclusive_scan<uint32_t>(w.L.nel, w.L.eoff, B, w.cnt + 1, w.stmp, s);
-  exclusive_scan<uint32_t>(w.L.nnode, w.L.noff, B, w.cnt + 2, w.stmp, s);
-  std::vector<uint32_t> dep(B), nel(B);
-  HALO_HIP(hipMemcpyAsync(hb + 1, w.cnt + 1, 8, hipMemcpyDeviceToHost, s));
-  HALO_HIP(hipMemcpyAsync(dep.data(), w.L.depth, 4ull * B, hipMemcpyDeviceToHost, s));
+  std::vector<uint32_t> nel(B);
+  HALO_HIP(hipMemcpyAsync(hb + 1, w.cnt + 1, 4, hipMemcpyDeviceToHost, s));
   HALO_HIP(hipMemcpyAsync(nel.data(), w.L.nel, 4ull * B, hipMemcpyDeviceToHost, s));
   HALO_HIP(hipStreamSynchronize(s));
-  uint32_t Dmax = 0;
-  unsigned long long E64 = 0, T64 = 0;
-  for (uint32_t b = 0; b < B; ++b) {
-    Dmax = std::max(Dmax, dep[b]);
-    E64 += nel[b];
-    T64 += 2ull << dep[b];
-  }
-  HALO_CHECK(E64 < 0xFFFFFFFFull && T64 < 0xFFFFFFFFull, LIBHALO_EINVAL,
-             "tree elements exceed 32-bit indices (raise bh_min)");
-  const uint32_t E = hb[1], T = hb[2];
-  HALO_CHECK(Dmax <= 31u, LIBHALO_EINVAL, "tree deeper than 31 levels");
-  // second carve with the element and node arrays; the list is rebuilt in it
-  unsigned long long *k0, *k1;
-  uint32_t *v0, *v1;
+  unsigned long long E64 = 0;
+  for (uint32_t b = 0; b < B; ++b) E64 += nel[b];
+  HALO_CHECK(E64 < 0x7FFFFFFFull, LIBHALO_EINVAL,
+             "tree elements exceed 31-bit indices (raise bh_min)");
+  const uint32_t E = hb[1];
+  // cells: leaves of at most kLeaf particles use about 0.2 cells per particle; the
+  // capacity bounds memory, not results (a cell without room for its children
+  // stays a leaf)
+  const uint32_t cap = E / 4 + B + 64;
+  // second carve with the element and cell arrays; the list is rebuilt in it
+  unsigned long long *k0, *k1, *rmx;
+  uint32_t *v0, *v1, *cell;  // cell: each element's cell at the current depth (r_max pass)
   double* pz;
-  BhNodes N;
+  BhRec* R;
+  MTree t;
   void* rtmp;
   carve2(ctx, [&](Arena& A) {
     take_list(A);
@@ -488,42 +428,48 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
     v0 = A.take<uint32_t>(E + 1);
     v1 = A.take<uint32_t>(E + 1);
     pz = A.take<double>(E + 1);
-    N.r = A.take<double>(8ull * (T + 1));
+    cell = A.take<uint32_t>(E + 1);
+    mtree_take(A, t, cap, B + 1);
+    R = A.take<BhRec>(cap);
+    rmx = A.take<unsigned long long>(cap);
     rtmp = A.take<char>(radix_tmp_bytes(E + 1));
   });
   build_list();
   exclusive_scan<uint32_t>(w.L.nel, w.L.eoff, B, w.cnt + 1, w.stmp, s);
-  exclusive_scan<uint32_t>(w.L.nnode, w.L.noff, B, w.cnt + 2, w.stmp, s);
   k_bh_bbox_init<<<blocks_for(B, TB), TB, 0, s>>>(w.bb, B);
   k_bh_bbox<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, w.L, slot, B, E, w.bb);
   k_bh_keys<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, w.L, slot, B, E, w.bb, k0, v0);
   const bool f = radix_sort_pairs<unsigned long long>(k0, v0, k1, v1, E,
                                                       48 + bits_for(B > 1 ? B - 1 : 1), rtmp, s);
-  // after the sort the keys are dead: x and y of the sorted positions take their place, and
-  // the sorted values are the particle slots
   const uint32_t* pidx = f ? v1 : v0;
+  // the cells over each halo's sorted range; the sorted keys are read by the build
+  // only, so afterwards x and y of the sorted positions take their place
+  mtree_build(t, f ? k1 : k0, w.L.eoff, w.L.nel, B, kLeaf, kMaxDepth, hb + 2, s);
   double* px = reinterpret_cast<double*>(k0);
   double* py = reinterpret_cast<double*>(k1);
   k_bh_gather<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, pidx, E, px, py, pz);
-  for (int l = (int)Dmax; l >= 0; --l)
-    k_bh_level<<<blocks_for(T, TB), TB, 0, s>>>(w.L, B, T, (uint32_t)l, theta, px, py, pz, N);
-  // exact r_max in place of the children's bound: a tighter acceptance distance
-  k_bh_rmax_init<<<blocks_for(T, TB), TB, 0, s>>>(N, T);
-  k_bh_rmax<<<blocks_for(E, TB), TB, 0, s>>>(w.L, B, E, px, py, pz, N);
-  k_bh_crit<<<blocks_for(T, TB), TB, 0, s>>>(T, theta, N);
+  const uint32_t T = t.NN;
+  for (int d = (int)t.lev.size() - 2; d >= 0; --d) {
+    const uint32_t nu = t.lev[d + 1] - t.lev[d];
+    k_bh_records<<<blocks_for(nu, TB), TB, 0, s>>>(t.bnode, t.pre, t.lev[d], nu, px, py, pz, R);
+  }
+  // exact r_max, then the acceptance distances
+  k_fill_u64<<<blocks_for(T, TB), TB, 0, s>>>(rmx, T, 0ull);
+  k_bh_rmax_roots<<<blocks_for(E, TB), TB, 0, s>>>(w.L, B, E, cell);
+  for (size_t d = 0; d + 1 < t.lev.size(); ++d)
+    k_bh_rmax_depth<<<blocks_for(E, TB), TB, 0, s>>>(E, px, py, pz, t.bnode, t.pre, R, cell,
+                                                     rmx);
+  k_bh_crit<<<blocks_for(T, TB), TB, 0, s>>>(T, theta, rmx, R);
   // wave units: runs of 64 sorted elements within each halo
   k_bh_wave_counts<<<blocks_for(B, TB), TB, 0, s>>>(w.L, B, w.flag);
   exclusive_scan<uint32_t>(w.flag, w.pos, B, w.cnt + 3, w.stmp, s);
   HALO_HIP(hipMemcpyAsync(hb + 4, w.cnt + 3, 4, hipMemcpyDeviceToHost, s));
-  HALO_HIP(hipMemsetAsync(w.cnt + 8, 0, 4, s));
   HALO_HIP(hipStreamSynchronize(s));
   const uint32_t nwave = hb[4];
   HALO_PROF(ctx, "k_bh_walk", s,
             k_bh_walk<<<blocks_for((int64_t)nwave * 64, TB), TB, 0, s>>>(
-                w.L, B, w.pos, nwave, slot, px, py, pz, pidx, N.r, eps2, pacc, w.cnt + 8));
-  HALO_HIP(hipMemcpyAsync(hb + 3, w.cnt + 8, 4, hipMemcpyDeviceToHost, s));
+                w.L, B, w.pos, nwave, slot, px, py, pz, pidx, R, t.troot, eps2, pacc));
   HALO_HIP(hipStreamSynchronize(s));
-  HALO_CHECK(hb[3] == 0, LIBHALO_EINVAL, "tree walk stack exhausted");
 }
 
 }  // namespace halo

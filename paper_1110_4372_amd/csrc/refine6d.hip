@@ -946,6 +946,8 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
   LevelNodes L[2];
   NodeScratch sc;
   GridBufs gb;
+  MTree gtree;  // topology of the large nodes' trees
+  gb.mt = &gtree;
   carve_workspace(ctx, [&](Arena& A) {
     lidx = A.take<uint32_t>(M);
     lnode = A.take<uint32_t>(M);

@@ -3,6 +3,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "mtree.hpp"
 
 namespace halo {
 namespace refine {
@@ -64,16 +65,15 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint
 constexpr uint32_t kGridMin = 131072; // default: nodes above this size use the tree search
 constexpr uint32_t kGridFloor = 64;   // smallest accepted threshold
 constexpr uint32_t kKdLeaf = 16;      // a tree node of at most this many particles is a leaf
-constexpr int kKdMaxDepth = 47;       // nodes at this depth are leaves whatever their size
+constexpr int kKdMaxDepth = 64;       // nodes at this depth are leaves whatever their size
 
-// A tree node: the bounding box of its particles and their range in the
-// sorted order; `left` is the first of its two adjacent children, or
-// kKdNone for a leaf.  64 bytes, so a node's two children are one 128-byte
-// read.
-constexpr uint32_t kKdNone = 0xFFFFFFFFu;
+// A tree node as the walks read it, in depth-first preorder (first child
+// first) so that a node's first child is the next record and `skip` is the
+// record after its subtree: the bounding box of its particles, their range in
+// the sorted order, `skip`, and whether it is a leaf.  64 bytes.
 struct __align__(16) KdNode {
   float mn[6], mx[6];
-  uint32_t lo, hi, left, depth;
+  uint32_t lo, hi, skip, leaf;
 };
 // A particle of a tree node in the sorted order: the six normalised
 // coordinates, its position m in the level arrays and its grid node b.
@@ -84,13 +84,14 @@ struct __align__(16) KdPoint {
 
 struct GridBufs {
   uint32_t *nb_rank, *gnode, *pstart, *gcount;
-  uint32_t *flag, *pos, *v0, *v1, *cnt, *stmp, *split;
+  uint32_t *flag, *pos, *v0, *v1, *cnt, *stmp, *leafof;
   unsigned long long *k0, *k1;
   KdPoint* pt;       // MB points in sorted order
-  KdNode* node;      // tree nodes, level by level; roots are 0 .. NB-1
+  KdNode* node;      // tree nodes in preorder; tree b is [troot[b], troot[b+1])
+  const uint32_t* troot;
   void* rtmp;
-  uint32_t node_cap = 0;
-  uint32_t MB = 0, NB = 0, NN = 0;  // sorted points, grid nodes, tree nodes
+  MTree* mt;         // host object: the trees' topology (mtree.hpp)
+  uint32_t MB = 0, NB = 0;  // sorted points, grid nodes
 };
 
 void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax);
