@@ -25,6 +25,8 @@
 // in the box: no particle that could change the result is skipped.  D is
 // exact for every particle and the FOF links every pair within ell^2, so the
 // results equal those of the all-pairs passes bit for bit.
+#include <hip/hip_fp16.h>
+
 #include "primitives.hpp"
 #include "refine_common.hpp"
 
@@ -97,22 +99,27 @@ __global__ void k_pstart(GridBufs g, uint32_t NB) {
   g.pstart[NB] = acc;
 }
 
-// Sorted points (AoS, 32 bytes) from the level's coordinate planes.
+// Sorted points (six coordinates, 24 bytes) from the level's coordinate planes.
 __global__ void k_kd_gather(const uint32_t* val, const float* xi, size_t S, uint32_t MB,
                             const uint32_t* lnode, GridBufs g) {
   uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= MB) return;
   const uint32_t m = val[q];
-  KdPoint p;
-  for (int c = 0; c < 6; ++c) p.x[c] = xi[(size_t)c * S + m];
-  p.m = m;
-  p.b = g.nb_rank[lnode[m]];
-  g.pt[q] = p;
+  for (int c = 0; c < 6; ++c) g.pt[6ull * q + c] = xi[(size_t)c * S + m];
+  g.pm[q] = m;
+  g.pb[q] = g.nb_rank[lnode[m]];
 }
+
+__device__ __forceinline__ uint16_t h_down(float v) {
+  return __half_as_ushort(__float2half_rd(v));
+}
+__device__ __forceinline__ uint16_t h_up(float v) { return __half_as_ushort(__float2half_ru(v)); }
+__device__ __forceinline__ float h_f(uint16_t b) { return __half2float(__ushort_as_half(b)); }
 
 // Preorder records of the nodes [u0, u0 + nu) of one depth: a leaf's box from
 // its particles (which also learn their leaf), an internal node's from its
-// children's records (one depth deeper, already written).
+// children's records (one depth deeper, already written; the union of
+// half-precision bounds is exact).
 __global__ void k_kd_records(GridBufs g, const MtNode* bnode, const uint32_t* pre, uint32_t u0,
                              uint32_t nu) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -120,46 +127,55 @@ __global__ void k_kd_records(GridBufs g, const MtNode* bnode, const uint32_t* pr
   const MtNode u = bnode[u0 + i];
   const uint32_t p = pre[u0 + i];
   KdNode r;
-  for (int c = 0; c < 6; ++c) {
-    r.mn[c] = __int_as_float(0x7F800000);
-    r.mx[c] = -__int_as_float(0x7F800000);
-  }
   if (u.left == kMtNone) {
+    float mn[6], mx[6];
+    for (int c = 0; c < 6; ++c) {
+      mn[c] = __int_as_float(0x7F800000);
+      mx[c] = -__int_as_float(0x7F800000);
+    }
     for (uint32_t q = u.lo; q < u.hi; ++q) {
-      const KdPoint pq = g.pt[q];
       for (int c = 0; c < 6; ++c) {
-        r.mn[c] = fminf(r.mn[c], pq.x[c]);
-        r.mx[c] = fmaxf(r.mx[c], pq.x[c]);
+        const float v = g.pt[6ull * q + c];
+        mn[c] = fminf(mn[c], v);
+        mx[c] = fmaxf(mx[c], v);
       }
       g.leafof[q] = p;
+    }
+    for (int c = 0; c < 6; ++c) {
+      r.mn[c] = h_down(mn[c]);
+      r.mx[c] = h_up(mx[c]);
     }
   } else {
     const KdNode& a = g.node[pre[u.left]];
     const KdNode& b = g.node[pre[u.left + 1]];
     for (int c = 0; c < 6; ++c) {
-      r.mn[c] = fminf(a.mn[c], b.mn[c]);
-      r.mx[c] = fmaxf(a.mx[c], b.mx[c]);
+      r.mn[c] = h_down(fminf(h_f(a.mn[c]), h_f(b.mn[c])));
+      r.mx[c] = h_up(fmaxf(h_f(a.mx[c]), h_f(b.mx[c])));
     }
   }
   r.lo = u.lo;
-  r.hi = u.hi;
   r.skip = p + u.aux;
-  r.leaf = u.left == kMtNone ? 1u : 0u;
   g.node[p] = r;
+}
+
+// The record after the last tree: its `lo` ends the last leaf's range.
+__global__ void k_kd_sentinel(KdNode* node, uint32_t NN, uint32_t MB) {
+  KdNode r;
+  for (int c = 0; c < 6; ++c) r.mn[c] = r.mx[c] = 0;
+  r.lo = MB;
+  r.skip = NN + 1u;
+  node[NN] = r;
 }
 
 // Squared gap between a point and a box, in the component order and FP32
 // operations of d2_6: each step is monotone and the per-axis gap is at most
 // |b_c - a_c| for every b in the box, so the result never exceeds d2_6 of the
 // point and any particle inside.
-__device__ __forceinline__ float point_gap2(const float* a, const float4* r) {
-  // r[0..2]: mn[0..5], mx[0..5]
-  const float mn[6] = {r[0].x, r[0].y, r[0].z, r[0].w, r[1].x, r[1].y};
-  const float mx[6] = {r[1].z, r[1].w, r[2].x, r[2].y, r[2].z, r[2].w};
+__device__ __forceinline__ float point_gap2(const float* a, const KdNode& r) {
   float s = 0.0f;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    const float gap = fmaxf(0.0f, fmaxf(mn[c] - a[c], a[c] - mx[c]));
+    const float gap = fmaxf(0.0f, fmaxf(h_f(r.mn[c]) - a[c], a[c] - h_f(r.mx[c])));
     s = c == 0 ? gap * gap : __fmaf_rn(gap, gap, s);
   }
   return s;
@@ -186,43 +202,44 @@ __device__ __forceinline__ uint32_t xcd_wave(uint32_t bid, uint32_t G) {
 // until each has a leaf to search, then search their leaves together.
 template <int MODE>
 __global__ void __launch_bounds__(kWalkTB)
-    k_kd_walk(const KdNode* __restrict__ T, const KdPoint* __restrict__ pt,
+    k_kd_walk(const KdNode* __restrict__ T, const float* __restrict__ pt,
+              const uint32_t* __restrict__ pm, const uint32_t* __restrict__ pb,
               const uint32_t* __restrict__ leafof, const uint32_t* __restrict__ troot,
               uint32_t MB, const uint32_t* __restrict__ gnode, NodeScratch sc, uint32_t* D,
               uint32_t* par) {
   const uint32_t q = xcd_wave(blockIdx.x, gridDim.x) * kWalkTB + threadIdx.x;
   const bool valid = q < MB;
-  const KdPoint P = pt[valid ? q : MB - 1];
-  const float a[6] = {P.x[0], P.x[1], P.x[2], P.x[3], P.x[4], P.x[5]};
+  const uint32_t qq = valid ? q : MB - 1;
+  float a[6];
+  for (int c = 0; c < 6; ++c) a[c] = pt[6ull * qq + c];
+  const uint32_t b = pb[qq], m = pm[qq];
   bool active = valid;
   float best = __int_as_float(0x7F800000);  // MODE 0: nearest so far
   float l2 = 0.0f;                          // MODE 1: ell^2 of the node
   uint32_t ri = 0;
   if (MODE == 1 && active) {
-    l2 = sc.ell2[gnode[P.b]];
-    if (!(__uint_as_float(D[P.m]) <= l2))
+    l2 = sc.ell2[gnode[b]];
+    if (!(__uint_as_float(D[m]) <= l2))
       active = false;
     else
-      ri = uf_find(par, P.m);
+      ri = uf_find(par, m);
   }
-  const uint32_t own = leafof[valid ? q : MB - 1];
-  const uint32_t end = troot[P.b + 1];  // the record after the point's tree
+  const uint32_t own = leafof[qq];
+  const uint32_t end = troot[b + 1];  // the record after the point's tree
   // the own leaf first: range [lo, hi), then the walk from u
-  const uint4 oh = reinterpret_cast<const uint4*>(T + own)[3];
-  uint32_t lo = MODE == 0 ? oh.x : q + 1u, hi = oh.y;
-  uint32_t u = MODE == 0 ? troot[P.b] : oh.z;
+  uint32_t lo = MODE == 0 ? T[own].lo : q + 1u, hi = T[own + 1].lo;
+  uint32_t u = MODE == 0 ? troot[b] : own + 1u;
   bool have = active;  // a leaf range waiting to be searched
   while (__any(active)) {
     if (have) {
       for (uint32_t j = lo; j < hi; ++j) {
-        const float4* pj = reinterpret_cast<const float4*>(pt + j);
-        const float4 x0 = pj[0], x1 = pj[1];
-        const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], x0.x, x0.y, x0.z, x0.w,
-                             x1.x, x1.y);
+        const float* pj = pt + 6ull * j;
+        const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], pj[0], pj[1], pj[2], pj[3],
+                             pj[4], pj[5]);
         if (MODE == 0) {
           best = j != q ? fminf(best, d) : best;
         } else if (d <= l2) {
-          const uint32_t rj = uf_find(par, __float_as_uint(x1.z));
+          const uint32_t rj = uf_find(par, pm[j]);
           if (rj != ri) ri = uf_union(par, ri, rj);
         }
       }
@@ -234,20 +251,18 @@ __global__ void __launch_bounds__(kWalkTB)
         if (u >= end) {
           active = false;
         } else if (MODE == 0 && u == own) {
-          u = oh.z;  // searched first
+          u = own + 1u;  // searched first
         } else {
-          const float4* r = reinterpret_cast<const float4*>(T + u);
-          const float4 box[3] = {r[0], r[1], r[2]};
-          const uint4 h = reinterpret_cast<const uint4*>(T + u)[3];
-          const float g = point_gap2(a, box);
+          const KdNode r = T[u];
+          const float g = point_gap2(a, r);
           const bool in = MODE == 0 ? g < best : g <= l2;
           if (!in) {
-            u = h.z;
-          } else if (h.w) {
-            lo = h.x;
-            hi = h.y;
+            u = r.skip;
+          } else if (r.skip == u + 1u) {  // a leaf
+            lo = r.lo;
+            hi = T[u + 1].lo;
             have = true;
-            u = h.z;
+            u = u + 1u;
           } else {
             u = u + 1u;
           }
@@ -255,7 +270,7 @@ __global__ void __launch_bounds__(kWalkTB)
       }
     }
   }
-  if (MODE == 0 && valid) D[P.m] = __float_as_uint(best);
+  if (MODE == 0 && valid) D[m] = __float_as_uint(best);
 }
 
 unsigned walk_grid(uint32_t MB) { return (MB + kWalkTB - 1) / kWalkTB; }
@@ -273,14 +288,16 @@ void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax) {
   // 16-particle leaves use about 0.2 nodes per particle
   const uint32_t cap = M / 4 + NBmax + 64;
   mtree_take(A, *g.mt, cap, NBmax);
-  g.node = A.take<KdNode>(cap);
+  g.node = A.take<KdNode>(cap + 1);
   g.flag = A.take<uint32_t>((size_t)M + 2);
   g.pos = A.take<uint32_t>((size_t)M + 2);
   g.k0 = A.take<unsigned long long>((size_t)M + 2);
   g.k1 = A.take<unsigned long long>((size_t)M + 2);
   g.v0 = A.take<uint32_t>((size_t)M + 2);
   g.v1 = A.take<uint32_t>((size_t)M + 2);
-  g.pt = A.take<KdPoint>((size_t)M + 2);
+  g.pt = A.take<float>(6ull * ((size_t)M + 2));
+  g.pm = A.take<uint32_t>((size_t)M + 2);
+  g.pb = A.take<uint32_t>((size_t)M + 2);
   g.leafof = A.take<uint32_t>((size_t)M + 2);
   g.cnt = A.take<uint32_t>(16);
   g.rtmp = A.take<char>(radix_tmp_bytes((int64_t)M + 2));
@@ -324,15 +341,17 @@ uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint3
     const uint32_t nu = t.lev[d + 1] - t.lev[d];
     k_kd_records<<<blocks_for(nu, TB), TB, 0, s>>>(g, t.bnode, t.pre, t.lev[d], nu);
   }
-  k_kd_walk<0><<<walk_grid(MB), kWalkTB, 0, s>>>(g.node, g.pt, g.leafof, g.troot, MB, g.gnode,
-                                                 sc, D, nullptr);
+  k_kd_sentinel<<<1, 1, 0, s>>>(g.node, t.NN, MB);
+  k_kd_walk<0><<<walk_grid(MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof, g.troot,
+                                                 MB, g.gnode, sc, D, nullptr);
   return NB;
 }
 
 void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par, hipStream_t s) {
   if (g.NB == 0 || g.MB == 0) return;
-  k_kd_walk<1><<<walk_grid(g.MB), kWalkTB, 0, s>>>(g.node, g.pt, g.leafof, g.troot, g.MB,
-                                                   g.gnode, sc, const_cast<uint32_t*>(D), par);
+  k_kd_walk<1><<<walk_grid(g.MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof,
+                                                   g.troot, g.MB, g.gnode, sc,
+                                                   const_cast<uint32_t*>(D), par);
 }
 
 }  // namespace refine

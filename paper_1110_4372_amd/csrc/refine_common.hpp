@@ -69,24 +69,24 @@ constexpr int kKdMaxDepth = 64;       // nodes at this depth are leaves whatever
 
 // A tree node as the walks read it, in depth-first preorder (first child
 // first) so that a node's first child is the next record and `skip` is the
-// record after its subtree: the bounding box of its particles, their range in
-// the sorted order, `skip`, and whether it is a leaf.  64 bytes.
+// record after its subtree: the bounding box of its particles in half
+// precision, each bound rounded outward (so the box holds every particle and
+// a gap computed from it never exceeds the FP32 one), and the first particle
+// of its range in the sorted order.  A node is a leaf when skip is the next
+// record; its range ends where the next record's begins (the preorder tiles
+// the sorted order from left to right; a sentinel record closes the last
+// tree).  32 bytes.
 struct __align__(16) KdNode {
-  float mn[6], mx[6];
-  uint32_t lo, hi, skip, leaf;
-};
-// A particle of a tree node in the sorted order: the six normalised
-// coordinates, its position m in the level arrays and its grid node b.
-struct __align__(16) KdPoint {
-  float x[6];
-  uint32_t m, b;
+  uint16_t mn[6], mx[6];  // binary16 bit patterns
+  uint32_t lo, skip;
 };
 
 struct GridBufs {
   uint32_t *nb_rank, *gnode, *pstart, *gcount;
   uint32_t *flag, *pos, *v0, *v1, *cnt, *stmp, *leafof;
   unsigned long long *k0, *k1;
-  KdPoint* pt;       // MB points in sorted order
+  float* pt;         // MB points in sorted order, six normalised coordinates each
+  uint32_t *pm, *pb; // their positions in the level arrays and their grid nodes
   KdNode* node;      // tree nodes in preorder; tree b is [troot[b], troot[b+1])
   const uint32_t* troot;
   void* rtmp;
