@@ -77,11 +77,14 @@ def one_step(ctx, P, ev=None):
 PROGRESS = False
 
 
+_T0 = time.perf_counter()
+
+
 def progress(msg):
     """A line on stderr after each long step (--progress): large catalogues take
-    minutes per step."""
+    minutes per step.  Prefixed with the seconds since the start."""
     if PROGRESS:
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+        print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def timed(ctx, P, steps, warmup):

@@ -466,56 +466,93 @@ __global__ void k_cand_compact(const uint32_t* own, uint32_t q0, uint32_t q1,
   pidx[pos[q - q0]] = i;
 }
 
-struct Metric {
-  const double* xs;
-  const double* ys;
-  const double* zs;
-  const double* vxs;
-  const double* vys;
-  const double* vzs;
-  const double* ird;  // cdyn / v_max^2 = 1 / r_dyn^2 of the seed's current particles
-  const double* isv;  // 1 / sigma_v^2 (floored at 1e-300)
+// Eq. 3 parameters of a seed, one 64-byte record: its position and velocity
+// (the leaf means) and the weights of its current particles, 1/r_dyn^2 =
+// cdyn / v_max^2 and 1/sigma_v^2 (floored at 1e-300).
+struct __align__(16) SeedM {
+  double xs, ys, zs, vxs, vys, vzs, ird, isv;
 };
 
-// The Eq. 3 weights of every seed from its current sigma_v^2 and v_max^2,
-// once per level (the same expressions the per-particle loop would evaluate).
-__global__ void k_metric_weights(const double* sv2, const double* vm2, uint32_t S, double cdyn,
-                                 double* ird, double* isv) {
-  uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= S) return;
-  ird[h] = cdyn / vm2[h];
-  isv[h] = 1.0 / fmax(sv2[h], 1e-300);
+__global__ void k_seed_metric_init(const libhalo_halos h, uint32_t S, SeedM* sm) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  sm[s].xs = h.xs[s];
+  sm[s].ys = h.ys[s];
+  sm[s].zs = h.zs[s];
+  sm[s].vxs = h.vxs[s];
+  sm[s].vys = h.vys[s];
+  sm[s].vzs = h.vzs[s];
 }
 
+__global__ void k_metric_weights(const double* sv2, const double* vm2, uint32_t S, double cdyn,
+                                 SeedM* sm) {
+  uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= S) return;
+  sm[h].ird = cdyn / vm2[h];
+  sm[h].isv = 1.0 / fmax(sv2[h], 1e-300);
+}
+
+// Eq. 3 argmin over the seeds of the particle's node: FP64, ties to the lower
+// row (the node's seed list is ascending).
+__device__ __forceinline__ void eq3_min(double px, double py, double pz, double ux0, double uy0,
+                                        double uz0, double box, const SeedM& m, uint32_t hid,
+                                        double& bd, uint32_t& best) {
+  double dx = min_image(px - m.xs, box), dy = min_image(py - m.ys, box),
+         dz = min_image(pz - m.zs, box);
+  double ux = ux0 - m.vxs, uy = uy0 - m.vys, uz = uz0 - m.vzs;
+  double d = __fma_rn(sq3(dx, dy, dz), m.ird, sq3(ux, uy, uz) * m.isv);
+  if (d < bd) {
+    bd = d;
+    best = hid;
+  }
+}
+
+// One thread per own particle of the level's nodes (sorted by node).  When the
+// whole wave belongs to one node its seed list and records are wave-uniform
+// (scalar loads); otherwise each lane reads its own.
 template <class T>
 __global__ void k_assign_level(const T* x, const T* y, const T* z, const float* vx,
                                const float* vy, const float* vz, double box,
                                const uint32_t* own, const uint32_t* okey, uint32_t q0,
-                               uint32_t q1, const uint32_t* soff, const uint32_t* ids,
-                               Metric mt, int32_t* halo_of) {
-  uint32_t q = q0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= q1) return;
-  const uint32_t i = own[q], k = okey[q];
-  const uint32_t s0 = soff[k], s1 = soff[k + 1];
-  uint32_t best = ids[s0];
-  if (s1 - s0 > 1) {
-    const double px = (double)x[i], py = (double)y[i], pz = (double)z[i];
-    const double ux0 = (double)vx[i], uy0 = (double)vy[i], uz0 = (double)vz[i];
-    double bd = INFINITY;
-    for (uint32_t t = s0; t < s1; ++t) {
-      const uint32_t h = ids[t];
-      const double ird = mt.ird[h], isv = mt.isv[h];
-      double dx = min_image(px - mt.xs[h], box), dy = min_image(py - mt.ys[h], box),
-             dz = min_image(pz - mt.zs[h], box);
-      double ux = ux0 - mt.vxs[h], uy = uy0 - mt.vys[h], uz = uz0 - mt.vzs[h];
-      double d = __fma_rn(sq3(dx, dy, dz), ird, sq3(ux, uy, uz) * isv);
-      if (d < bd) {  // ids ascending: ties keep the lower id
-        bd = d;
-        best = h;
+                               uint32_t q1, const uint32_t* __restrict__ soff,
+                               const uint32_t* __restrict__ ids, const SeedM* __restrict__ sm,
+                               int32_t* halo_of) {
+  const uint32_t q = q0 + blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = q < q1;
+  const uint32_t i = ok ? own[q] : 0u, k = ok ? okey[q] : okey[q0];
+  const uint32_t kw = __builtin_amdgcn_readfirstlane(k);
+  double px = 0.0, py = 0.0, pz = 0.0, ux0 = 0.0, uy0 = 0.0, uz0 = 0.0;
+  if (ok) {
+    px = (double)x[i];
+    py = (double)y[i];
+    pz = (double)z[i];
+    ux0 = (double)vx[i];
+    uy0 = (double)vy[i];
+    uz0 = (double)vz[i];
+  }
+  uint32_t best;
+  if (__all(k == kw)) {
+    const uint32_t s0 = soff[kw], s1 = soff[kw + 1];
+    best = ids[s0];
+    if (s1 - s0 > 1) {
+      double bd = INFINITY;
+      for (uint32_t t = s0; t < s1; ++t) {
+        const uint32_t hid = ids[t];
+        eq3_min(px, py, pz, ux0, uy0, uz0, box, sm[hid], hid, bd, best);
+      }
+    }
+  } else {
+    const uint32_t s0 = soff[k], s1 = soff[k + 1];
+    best = ids[s0];
+    if (s1 - s0 > 1) {
+      double bd = INFINITY;
+      for (uint32_t t = s0; t < s1; ++t) {
+        const uint32_t hid = ids[t];
+        eq3_min(px, py, pz, ux0, uy0, uz0, box, sm[hid], hid, bd, best);
       }
     }
   }
-  halo_of[i] = (int32_t)best;
+  if (ok) halo_of[i] = (int32_t)best;
 }
 
 __global__ void k_all_assigned(const int32_t* halo_of, uint32_t n, uint32_t* flag) {
@@ -644,7 +681,8 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
   struct W {
     uint32_t *flag, *pos, *dcnt, *stmp, *cnt, *seg_start, *kept, *pcnt, *poff;
     int32_t* node_seed;
-    double *sx2, *sv2, *cur_sv2, *cur_vm2, *ird, *isv;
+    double *sx2, *sv2, *cur_sv2, *cur_vm2;
+    SeedM* sm;
     unsigned long long *k64a, *k64b, *pk0, *pk1, *vm;
     uint32_t *va, *vb, *pv0, *pv1, *pflag, *ppos, *soff, *ids, *ocnt, *iflag, *ipos;
     uint32_t *ok0, *ov0, *ok1, *ov1, *ooff, *lstart, *lmulti, *cand, *na;
@@ -706,8 +744,7 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
     w.cand = A.take<uint32_t>(K2);
     w.cur_sv2 = A.take<double>(K2);
     w.cur_vm2 = A.take<double>(K2);
-    w.ird = A.take<double>(K2);
-    w.isv = A.take<double>(K2);
+    w.sm = A.take<SeedM>(K2);
     w.acc = A.take<I128>(4 * K2);
     w.vm = A.take<unsigned long long>(K2);
     w.na = A.take<uint32_t>(K2);
@@ -812,7 +849,7 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
   I128* acc = w.acc;
   unsigned long long* vm = w.vm;
   RadialBufs& rb = w.rb;
-  Metric cur{h.xs, h.ys, h.zs, h.vxs, h.vys, h.vzs, w.ird, w.isv};
+  k_seed_metric_init<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.sm);
   for (int lev = maxlev; lev >= 0; --lev) {
     const uint32_t k0 = hls[lev], k1 = hls[lev + 1];
     const uint32_t q0 = hoo[k0], q1 = hoo[k1];  // own particles of this level
@@ -831,12 +868,11 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
       }
       radial_sort(pos_dtype, x, y, z, box, h.xs, h.ys, h.zs, m, S, rb, s);
       radial_sigma_vmax(vx, vy, vz, m, S, rb, Gm, eps2, acc, vm, cur_sv2, cur_vm2, s);
-      k_metric_weights<<<blocks_for(S, TB), TB, 0, s>>>(cur_sv2, cur_vm2, S, cdyn, w.ird,
-                                                        w.isv);
+      k_metric_weights<<<blocks_for(S, TB), TB, 0, s>>>(cur_sv2, cur_vm2, S, cdyn, w.sm);
     }
     if (q1 > q0)
       k_assign_level<T><<<blocks_for(q1 - q0, TB), TB, 0, s>>>(
-          x, y, z, vx, vy, vz, box, own, okey, q0, q1, soff, ids, cur, halo_of);
+          x, y, z, vx, vy, vz, box, own, okey, q0, q1, soff, ids, w.sm, halo_of);
   }
 
   // ---- final metric of every halo from all its particles

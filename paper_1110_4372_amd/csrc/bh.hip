@@ -317,8 +317,12 @@ __global__ void __launch_bounds__(TB)
   uint32_t u = __builtin_amdgcn_readfirstlane(troot[b]);
   const uint32_t end = __builtin_amdgcn_readfirstlane(troot[b + 1]);
   double acc = 0.0;
+  // the next record is read while this one is processed: entering a cell (the
+  // next record) is the common step; a skip reads its target afresh
+  BhRec c = R[u];
   while (u < end) {
-    const BhRec& c = R[u];
+    const BhRec nx = R[u + 1];
+    uint32_t v;
     const double d2 = sq3(x - c.cx, y - c.cy, z - c.cz);
     // a cell is a monopole for a target outside it beyond the acceptance
     // distance; the cell holding the target itself is always opened (a cell of
@@ -326,7 +330,7 @@ __global__ void __launch_bounds__(TB)
     const bool open = d2 <= c.crit2 || (e >= c.lo && e < c.hi);
     if (__ballot(target && open) == 0ull) {
       if (target) acc += c.cm * rsqrt_f64(d2 + eps2);
-      u = c.skip;
+      v = c.skip;
     } else if (c.leaf) {
       // every lane evaluates each term and keeps it by a select, so the loads of a
       // leaf particle are not behind a branch and several can be in flight at once
@@ -337,10 +341,15 @@ __global__ void __launch_bounds__(TB)
         const double tf = rsqrt_f64(sq3(x - fx, y - fy, z - fz) + eps2);
         acc = (target && qf != q) ? acc + tf : acc;
       }
-      u = c.skip;
+      v = c.skip;
     } else {
-      u = u + 1u;
+      v = u + 1u;
     }
+    if (v == u + 1u)
+      c = nx;
+    else if (v < end)
+      c = R[v];
+    u = v;
   }
   if (target && acc > 0.0) atomic_add_i128(pacc + q, fixed128(acc, kFrac));
 }
@@ -430,7 +439,7 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
     pz = A.take<double>(E + 1);
     cell = A.take<uint32_t>(E + 1);
     mtree_take(A, t, cap, B + 1);
-    R = A.take<BhRec>(cap);
+    R = A.take<BhRec>(cap + 1);  // the walk reads one record ahead
     rmx = A.take<unsigned long long>(cap);
     rtmp = A.take<char>(radix_tmp_bytes(E + 1));
   });
