@@ -2,10 +2,14 @@
 FOF -> 6D refine -> assign -> unbind (-> properties), batched vs plain, 1 GPU.
 
 A step is one pass of the whole path (libhalo_fof3d, libhalo_refine6d,
-libhalo_assign, libhalo_unbind, libhalo_props) over the seeded synthetic
-128^3 catalogue (100 Mpc/h box, power-law NFW hosts of 20-2e5 particles with
-subhaloes, 40% uniform background, float32 positions), inputs resident in
-HBM.  Prints one JSON line.
+libhalo_assign, libhalo_unbind, libhalo_props) over a seeded synthetic
+catalogue held in HBM.  The default workload is the 1024^3 catalogue (1 Gpc/h
+box, power-law NFW hosts of 20-1e7 particles with subhaloes, 40% uniform
+background, float32 positions, drawn on the GPU) in the batched form with the
+mixed-precision potential and the tree potential of Appendix B (theta = 0.04)
+for haloes of >= 65536 particles.  The plain form (one launch sequence per node
+and halo) is timed beside the batched one on the 128^3 catalogue, where it fits
+the run time.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -87,10 +91,18 @@ def progress(msg):
         print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
-def timed(ctx, P, steps, warmup):
-    """Mean wall time per step over `steps` after `warmup`, and the mean device
-    time of each call (HIP events, read after the timed region).  With
-    --progress each step is synchronised to report it."""
+HOT = ("k_kd_walk_nn", "k_kd_walk_fof", "k_bh_walk", "k_nn", "k_fof6", "k_potential_f64",
+       "k_potential_f32", "k_link", "k_mom_accum", "k_select_small", "k_assign_level")
+WALKS = ("k_kd_walk_nn", "k_kd_walk_fof")
+
+
+def timed(ctx, P, steps, warmup, prof=False):
+    """Mean wall time per step over `steps` after `warmup`, the mean device
+    time of each call (HIP events on the launch stream, read after the timed
+    region), and with `prof` the library's own HIP-event timing of its hot
+    kernels over the same timed steps (total ms and launches per kernel) and
+    the tree searches' work counts.  With --progress each step is
+    synchronised to report it."""
     import torch
     for k in range(warmup):
         one_step(ctx, P)
@@ -99,6 +111,9 @@ def timed(ctx, P, steps, warmup):
             progress(f"warm-up step {k + 1}/{warmup} done")
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
     torch.cuda.synchronize()
+    if prof:
+        ctx.profile(True)
+        ctx.profile_reset()
     t0 = time.perf_counter()
     for k in range(steps):
         out = one_step(ctx, P, evs[k])
@@ -109,31 +124,92 @@ def timed(ctx, P, steps, warmup):
     sec = (time.perf_counter() - t0) / steps
     stage = {STAGES[i]: sum(e[i].elapsed_time(e[i + 1]) for e in evs) / steps
              for i in range(5)}
-    return sec, out, stage
+    kp = None
+    if prof:
+        kp = {"kern": {k: ctx.profile_read(k) for k in HOT},
+              "work": {k: ctx.profile_work(k) for k in WALKS}}
+        ctx.profile(False)
+    return sec, out, stage, kp
 
 
-def pair_work(ctx, P, out):
-    """Algorithmic FLOPs of the dominant kernels of one step.
+GRID_MIN_DEFAULT = 131072  # the library's tree threshold when grid_min = 0
+BH_MIN_DEFAULT = 65536     # the library's smallest tree halo when bh_min = 0
+# FLOP of one evaluation, as counted for the ALU roofline:
+NN_PAIR_FLOP = 17.0   # 6D distance: 6 sub, 1 mul, 5 fma
+BOX_TEST_FLOP = 23.0  # point-to-box gap: per axis 2 sub + fma, 6 axes, minus the first fma's add
 
-    Nearest neighbour: each distinct pair of a node once, 17 FLOP (6 sub, 1 mul,
-    5 fma).  Potential: a term 1/sqrt(r^2 + eps^2) is 12 FLOP (3 sub, r^2 as
-    1 mul + 2 fma, + eps^2, rsqrt counted as sqrt + div, accumulate); a pair of
-    two own particles of a halo is one term added to both particles' sums
-    (13 FLOP), a pair of an own particle and a subhalo particle of S(h) one
-    term added to the own particle's sum (12 FLOP)."""
+
+def pair_work(out, grid_min, bh_theta, bh_min):
+    """Algorithmic FLOPs of one step of the all-pairs kernels.
+
+    Nearest neighbour (k_nn): each distinct pair of a node handled by the
+    all-pairs pass (not degenerate, at most grid_min particles; larger nodes
+    take the tree search) once, 17 FLOP.  Potential (k_potential_*): a term
+    1/sqrt(r^2 + eps^2) is 12 FLOP (3 sub, r^2 as 1 mul + 2 fma, + eps^2,
+    rsqrt counted as sqrt + div, accumulate); a pair of two own particles of a
+    halo is one term added to both particles' sums (13 FLOP), a pair of an own
+    particle and a subhalo particle of S(h) one term added to the own
+    particle's sum (12 FLOP), over the halos the direct sum handles (with the
+    tree on, those with |S(h)| < bh_min)."""
     import numpy as np
     fof, nodes, halos, halo_of, unb = out[:5]
+    gmin = grid_min if grid_min > 0 else GRID_MIN_DEFAULT
     cnt = nodes["count"].cpu().numpy().astype(np.float64)
     flags = nodes["flags"].cpu().numpy()
-    active = (flags & 2) == 0
-    nn_flops = 17.0 * float(np.sum(cnt[active] * (cnt[active] - 1.0) / 2.0))
+    on = ((flags & 2) == 0) & (cnt <= gmin)
+    nn_flops = NN_PAIR_FLOP * float(np.sum(cnt[on] * (cnt[on] - 1.0) / 2.0))
     h = {k: v.cpu().numpy() for k, v in halos.items()}
     ns = unb["n_s"].cpu().numpy().astype(np.float64)
     kept = h["merged_into"] == np.arange(h["merged_into"].shape[0])
+    if bh_theta > 0:
+        kept &= ns < (bh_min if bh_min > 0 else BH_MIN_DEFAULT)
     nown = h["n_assigned"][kept].astype(np.float64)
     nsk = ns[kept]
     pot_flops = float(np.sum(13.0 * nown * (nown - 1.0) / 2.0 + 12.0 * nown * (nsk - nown)))
     return nn_flops, pot_flops
+
+
+def roofline_report(kp, out, steps, prec_fp64, grid_min, bh_theta, bh_min):
+    """The roofline object of the dominant kernel of the timed steps (the hot
+    kernel with the largest device time).  All-pairs kernels: algorithmic
+    FLOP (pair_work) per launch over the average launch time, against the
+    VALU peak of their arithmetic.  Tree searches of large nodes: the work
+    the exact pruned search performs, from its device counters (box tests x 23
+    + distances x 17 FLOP), against the FP32 VALU peak."""
+    kern, work = kp["kern"], kp["work"]
+    nn_flops, pot_flops = pair_work(out, grid_min, bh_theta, bh_min)
+    pot = "k_potential_f64" if prec_fp64 else "k_potential_f32"
+    figures = {
+        "k_nn": (nn_flops * steps, FP32_PEAK_TFLOPS,
+                 "distinct pairs of the all-pairs nodes x 17 FLOP"),
+        pot: (pot_flops * steps, FP64_PEAK_TFLOPS if prec_fp64 else FP32_PEAK_TFLOPS,
+              "direct-sum pairs x 12-13 FLOP"),
+    }
+    for w in WALKS:
+        tests, evals = work[w]
+        figures[w] = (BOX_TEST_FLOP * tests + NN_PAIR_FLOP * evals, FP32_PEAK_TFLOPS,
+                      f"counted work of the exact tree search: {tests:.4g} box tests x 23 + "
+                      f"{evals:.4g} distances x 17 FLOP")
+    dom = max(kern, key=lambda k: kern[k][0])
+    t_ms, launches = kern[dom]
+    rec = {"kernel": dom, "launches": launches, "avg_launch_ms": t_ms / max(launches, 1),
+           "per_step_ms": {k: v[0] / steps for k, v in kern.items()}}
+    if dom in figures and t_ms > 0:
+        flops, peak, what = figures[dom]
+        achieved = flops / (t_ms * 1e-3) / 1e12
+        rec.update({"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                    "frac": achieved / peak, "traffic": measured_traffic(dom),
+                    "work": what})
+    else:
+        rec.update({"bound": "alu", "achieved": None, "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": None, "traffic": None,
+                    "work": "no algorithmic count for this kernel"})
+    # every candidate with a figure, for the record
+    rec["others"] = {k: {"ms_per_step": kern[k][0] / steps,
+                         "frac": (v[0] / (kern[k][0] * 1e-3) / 1e12 / v[1])
+                         if kern[k][0] > 0 else None}
+                     for k, v in figures.items() if k in kern}
+    return rec
 
 
 RHO_CRIT = 2.77536627e11
@@ -306,7 +382,7 @@ def subset_report(H, cat, P, grid_min, prec, m=10000, steps=3):
     for mm in (0, m):
         ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=grid_min,
                                           ell_subset=mm))
-        sec, out, stage = timed(ctx, P, steps, 1)
+        sec, out, stage, _ = timed(ctx, P, steps, 1)
         fof, nodes, halos, halo_of = out[:4]
         canon = nodes["canon"].cpu().numpy().astype(np.int64)
         seed = halos["seed_node"].cpu().numpy().astype(np.int64)
@@ -336,7 +412,7 @@ def dense_report(H, cat, P, grid_min, prec, t=16, steps=3):
     for tt in (0, t):
         ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=grid_min,
                                           fof_dense=tt))
-        sec, out, stage = timed(ctx, P, steps, 1)
+        sec, out, stage, _ = timed(ctx, P, steps, 1)
         lab = out[0]["label"].cpu().numpy().astype(np.int64)
         size = np.bincount(lab, minlength=lab.shape[0])[lab]
         res[tt] = dict(ms=sec * 1e3, fof_ms=stage["fof3d"], groups=int(out[0]["n_groups"]),
@@ -401,39 +477,106 @@ def tree_report(ctx, P, out, theta=0.04, bh_min=65536):
             "flags_agree_fraction": float(np.mean(ba == bb)) if ba.size else 1.0}
 
 
-def cpu_baseline(cat, budget_s: float = 20.0):
-    """The CPU oracle (serial FP64 C) on a sub-volume of the catalogue: the
-    particles of the corner cube [0, L/k)^3, treated as a periodic box of side
-    L/k (the same linking length), k chosen so the run takes ~budget_s (at
-    least 4, and large enough that the cube holds ~65k particles)."""
+def _oracle_job(job):
+    """One serial oracle run (a worker process of cpu_baseline): the whole path
+    over the particles of one sub-cube, treated as a periodic box of its own
+    side with the full catalogue's linking length.  Returns (particles,
+    seconds)."""
     import numpy as np
     from oracle import oracle as O
-    from paper_1110_4372_amd import synth
+    side, ll, mass, soft, cols = job
+    n = int(cols[0].shape[0])
+    p = O.make_params(side, mass, soft, b=ll * n ** (1.0 / 3.0) / side)
+    t0 = time.perf_counter()
+    O.run_all(p, O.Particles(*[np.ascontiguousarray(c) for c in cols]))
+    return n, time.perf_counter() - t0
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu's "Model name")."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cat, workers: int = 16, target: int = 65536):
+    """The CPU oracle (serial FP64 C, as it stands) on the host's cores: one
+    worker process per core (at most `workers`), each running the whole path
+    over one sub-cube of the catalogue of side L/k (k so that a cube holds
+    about `target` particles on average) with the full catalogue's linking
+    length; the cubes sit on a coarse lattice through the box and one holding
+    more than twice the average is passed over (a cube through the core of one
+    of the largest haloes would need hours of direct-sum unbinding).  Reports
+    the particles of all cubes over the wall time of the pool."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import oracle as O
     O.build(force=False)
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    nw = max(1, min(workers, ncpu or 1))
+    k = max(4, int(round((cat.n / float(target)) ** (1.0 / 3.0))))
+    side = cat.box / k
+    ll = 0.28 * cat.box / round(cat.n ** (1.0 / 3.0))
+    mean = cat.n / float(k ** 3)
+    cols_all = (cat.x, cat.y, cat.z, cat.vx, cat.vy, cat.vz)
+    jobs = []
+    step = max(1, k // 5)
+    for ix in range(0, k, step):
+        for iy in range(0, k, step):
+            if len(jobs) == nw:
+                break
+            o = (ix * side, iy * side, 0.0)
+            sel = ((cat.x >= o[0]) & (cat.x < o[0] + side) & (cat.y >= o[1])
+                   & (cat.y < o[1] + side) & (cat.z < side))
+            cnt = int(sel.sum())
+            if cnt < 100 or cnt > 2 * mean:
+                continue
+            cols = []
+            for a, off in zip(cols_all, (o[0], o[1], 0.0, None, None, None)):
+                v = a[sel]
+                v = v.cpu().numpy() if hasattr(v, "cpu") else np.asarray(v)
+                if off is not None:
+                    v = (v - v.dtype.type(off)).astype(v.dtype)
+                    v = np.clip(v, 0, np.nextafter(v.dtype.type(side), v.dtype.type(0)))
+                cols.append(np.ascontiguousarray(v))
+            jobs.append((side, ll, cat.particle_mass, cat.softening, cols))
+    if not jobs:
+        return None
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(jobs)) as pool:
+        res = pool.map(_oracle_job, jobs)
+    wall = time.perf_counter() - t0
+    nsum = sum(r[0] for r in res)
+    return dict(value=nsum / wall, unit="particles/s", cores=len(jobs), kind="oracle",
+                cpu=cpu_model(), host_cpus=ncpu,
+                sample=f"{len(jobs)} sub-cubes of side L/{k} ({nsum} particles, "
+                       f"{min(r[0] for r in res)}-{max(r[0] for r in res)} per cube) of "
+                       f"the same catalogue on a lattice through the box, full path "
+                       f"fof3d..props, one serial oracle process per cube, "
+                       f"{wall:.1f} s wall (per-cube {min(r[1] for r in res):.1f}-"
+                       f"{max(r[1] for r in res):.1f} s)")
 
-    def host(a):
-        return a.cpu().numpy() if hasattr(a, "cpu") else a
 
-    k0 = max(4, int(round((cat.n / 65536.0) ** (1.0 / 3.0))))
-    fracs = list(range(k0, max(1, k0 // 3), -1))
-    for frac in fracs:
-        side = cat.box / frac
-        sel = (cat.x < side) & (cat.y < side) & (cat.z < side)
-        cols = [np.ascontiguousarray(host(a[sel])) for a in (cat.x, cat.y, cat.z, cat.vx,
-                                                            cat.vy, cat.vz)]
-        nsel = int(cols[0].shape[0])
-        sub = synth.Catalog(cat.spec_name, side, nsel, *cols, cat.particle_mass,
-                            cat.softening, np.full(nsel, -1, np.int64), {})
-        p = O.params_of(sub)
-        t0 = time.perf_counter()
-        O.run_all(p, O.Particles.of(sub))
-        dt = time.perf_counter() - t0
-        if dt > budget_s / 4 or frac == fracs[-1]:
-            return dict(value=sub.n / dt, unit="particles/s", cores=1, kind="oracle",
-                        sample=f"corner sub-box of side L/{frac} ({sub.n} particles) of the "
-                               f"same catalogue, full path fof3d..props, serial C, "
-                               f"{dt:.1f} s")
-    return None
+def make_cat(name, gen):
+    from paper_1110_4372_amd import synth
+    if gen == "auto":
+        gen = "device" if name in ("c3", "c5") else "host"
+    if gen == "device":
+        return synth.make_catalog_device(name, seed=0), gen
+    return synth.make_catalog(name, seed=0), gen
+
+
+def workload_name(name, cat, gen):
+    return (f"{name}: {cat.n} particles, box {cat.box} Mpc/h, "
+            + ("8 NFW hosts + subhaloes + 30% uniform" if name == "c1" else
+               "power-law NFW hosts + 5e6-particle cluster + 40% uniform" if name == "c4" else
+               "power-law NFW hosts + subhaloes + 40% uniform")
+            + ", seed 0" + (" (GPU-drawn)" if gen == "device" else ""))
 
 
 def main():
@@ -441,21 +584,29 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c5",
+                    help="workload of the timed steps (default c5, the 1024^3 catalogue)")
+    ap.add_argument("--side-config", default="c2",
+                    help="workload of the plain form and of the comparisons outside the "
+                         "timed steps (default c2, where the plain form fits the run time)")
+    ap.add_argument("--side-steps", type=int, default=3,
+                    help="timed steps of each form on the side workload")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip everything on the side workload")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--progress", action="store_true",
                     help="report each step and stage on stderr (synchronises after each)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other precision form and the mixed-vs-FP64 comparison")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--prec", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--no-tree", action="store_true",
                     help="skip the tree-potential comparison (not part of the step)")
-    ap.add_argument("--bh-theta", type=float, default=0.0,
+    ap.add_argument("--bh-theta", type=float, default=0.04,
                     help="tree potential (Appendix B) in the timed steps, for haloes of at "
-                         "least --bh-min particles; 0 (default) keeps the exact direct sum")
+                         "least --bh-min particles; 0 keeps the exact direct sum")
     ap.add_argument("--bh-min", type=int, default=65536,
-                    help="smallest |S(h)| that takes the tree in the tree comparison")
+                    help="smallest |S(h)| that takes the tree")
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense-particle FOF variant comparison (not part of the step)")
     ap.add_argument("--no-subset", action="store_true",
@@ -467,13 +618,13 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration)")
     ap.add_argument("--grid-min", type=int, default=0,
-                    help="nodes above this many particles use the 6D tile search "
+                    help="nodes above this many particles use the 6D tree search "
                          "(0: the library default, or the autotuner's pick with --autotune)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the grid_min candidates before the run and use the fastest")
-    ap.add_argument("--gen", default="host", choices=["host", "device"],
-                    help="catalogue generator: numpy (host) or torch on the GPU (device; "
-                         "power-law configs, for the 512^3 and 1024^3 catalogues)")
+    ap.add_argument("--gen", default="auto", choices=["auto", "host", "device"],
+                    help="catalogue generator: numpy (host) or torch on the GPU (device); "
+                         "auto draws the 512^3 and 1024^3 catalogues on the GPU")
     args = ap.parse_args()
     global PROGRESS
     PROGRESS = args.progress
@@ -484,12 +635,8 @@ def main():
 
     import torch
     from paper_1110_4372_amd import halo as H
-    from paper_1110_4372_amd import synth
 
-    if args.gen == "device":
-        cat = synth.make_catalog_device(args.config, seed=0)
-    else:
-        cat = synth.make_catalog(args.config, seed=0)
+    cat, gen = make_cat(args.config, args.gen)
     P = H.Particles.from_catalog(cat)
     progress(f"catalogue {args.config}: {cat.n} particles")
     prec = H.PREC_FP64 if args.prec == "fp64" else H.PREC_MIXED
@@ -505,77 +652,82 @@ def main():
         progress(f"autotuned grid_min = {best}")
     ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=args.grid_min,
                                       bh_theta=args.bh_theta, bh_min=args.bh_min))
-    sec, out, stage = timed(ctx, P, args.steps, args.warmup)
-
-    # dominant kernels, timed with HIP events on the library's launch stream
-    ctx.profile(True)
-    ctx.profile_reset()
-    one_step(ctx, P)
-    torch.cuda.synchronize()
-    progress("kernel-timed step done")
-    kern = {k: ctx.profile_read(k) for k in ("k_nn", "k_fof6", "k_potential_f64",
-                                             "k_potential_f32", "k_link", "k_mom_accum",
-                                             "k_select_small")}
-    ctx.profile(False)
-    nn_flops, pot_flops = pair_work(ctx, P, out)
-    pot_name = "k_potential_f64" if prec == H.PREC_FP64 else "k_potential_f32"
-    t_pot, l_pot = kern[pot_name]
-    t_nn, l_nn = kern["k_nn"]
-    cands = {
-        pot_name: (t_pot, l_pot, pot_flops,
-                   FP64_PEAK_TFLOPS if prec == H.PREC_FP64 else FP32_PEAK_TFLOPS),
-        "k_nn": (t_nn, l_nn, nn_flops, FP32_PEAK_TFLOPS),
-    }
-    dom = max(cands, key=lambda k: cands[k][0])
-    t_ms, launches, flops, peak = cands[dom]
-    achieved = flops / (t_ms * 1e-3) / 1e12 if t_ms > 0 else 0.0
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(dom),
-                "launches": launches, "avg_launch_ms": t_ms / max(launches, 1),
-                "per_step_ms": {k: v[0] for k, v in kern.items()}}
-
-    # the four forms: batched and plain, FP64 and mixed potential, per pass
-    names = {H.PREC_FP64: "fp64", H.PREC_MIXED: "mixed"}
-    forms = {f"batched_{names[prec]}": {"value": cat.n / sec, "ms_per_step": sec * 1e3,
-                                          "stage_ms": stage}}
-    other = H.PREC_MIXED if prec == H.PREC_FP64 else H.PREC_FP64
-    if not args.no_forms:
-        ctxo = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=other,
-                                           grid_min=args.grid_min))
-        so, _, sto = timed(ctxo, P, args.steps, 1)
-        forms[f"batched_{names[other]}"] = {"value": cat.n / so, "ms_per_step": so * 1e3,
-                                             "stage_ms": sto}
-        del ctxo
-    plain = None
-    if not args.no_plain:
-        for pr in ((prec,) if args.no_forms else (prec, other)):
-            ctxp = H.Halo(H.params_for_catalog(cat, mode=H.PLAIN, prec=pr,
-                                               grid_min=args.grid_min))
-            sp, _, stp = timed(ctxp, P, 1, 1)
-            forms[f"plain_{names[pr]}"] = {"value": cat.n / sp, "ms_per_step": sp * 1e3,
-                                            "stage_ms": stp}
-            if pr == prec:
-                plain = {"value": cat.n / sp, "ms_per_step": sp * 1e3}
-            del ctxp
-    precision = None if args.no_forms else precision_report(H, cat, P, args.grid_min)
-    extras = None if args.no_extras else extras_report(ctx, P, out, cat.particle_mass,
-                                                       H.params_for_catalog(cat).rho_vir)
-    if extras is not None:
-        progress("additional properties timed")
-    merger = None if args.no_merger else merger_report(H, cat, P, args.grid_min, prec)
-    subset = None if args.no_subset else subset_report(H, cat, P, args.grid_min, prec)
-    dense = None if args.no_dense else dense_report(H, cat, P, args.grid_min, prec)
-    tree = None if args.no_tree else tree_report(ctx, P, out, theta=args.bh_theta or 0.04,
-                                                 bh_min=args.bh_min)
-    if tree is not None:
-        progress("tree potential timed")
-    if dense is not None:
-        progress("dense-particle FOF variant timed")
-    if subset is not None:
-        progress("subset linking length timed")
-    if merger is not None:
-        progress("major-merger form timed")
+    sec, out, stage, kp = timed(ctx, P, args.steps, args.warmup, prof=True)
+    roofline = roofline_report(kp, out, args.steps, prec == H.PREC_FP64, args.grid_min,
+                               args.bh_theta, args.bh_min)
     passes = pass_report(cat.n, out, stage)
+    counts = {"n_groups": int(out[0]["n_groups"]), "n_nodes": int(out[1]["parent"].shape[0]),
+              "n_halos": int(out[2]["seed_node"].shape[0])}
+    del out
+    progress("timed steps done")
+
+    names = {H.PREC_FP64: "fp64", H.PREC_MIXED: "mixed"}
+    forms = {f"batched_{names[prec]}": {"workload": args.config, "value": cat.n / sec,
+                                          "ms_per_step": sec * 1e3, "stage_ms": stage}}
+    plain = precision = extras = merger = subset = dense = tree = None
+    side = None
+    if not args.no_side:
+        # the forms and comparisons outside the timed steps, on the side workload
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+        scat, sgen = make_cat(args.side_config, "auto")
+        SP = H.Particles.from_catalog(scat)
+        side = workload_name(args.side_config, scat, sgen)
+        ss = max(1, args.side_steps)
+        sctx = None
+        for pr in (prec, H.PREC_MIXED if prec == H.PREC_FP64 else H.PREC_FP64):
+            if args.no_forms and pr != prec:
+                continue
+            c2 = H.Halo(H.params_for_catalog(scat, mode=H.BATCHED, prec=pr,
+                                             grid_min=args.grid_min, bh_theta=args.bh_theta,
+                                             bh_min=args.bh_min))
+            s2, o2, st2, _ = timed(c2, SP, ss, 1)
+            forms[f"side_batched_{names[pr]}"] = {"workload": args.side_config,
+                                                  "value": scat.n / s2,
+                                                  "ms_per_step": s2 * 1e3, "stage_ms": st2}
+            if pr == prec:
+                sctx, sout = c2, o2
+            else:
+                del c2, o2
+        progress("side workload: batched forms timed")
+        if not args.no_plain:
+            for pr in ((prec,) if args.no_forms else (prec, H.PREC_MIXED if prec == H.PREC_FP64
+                                                      else H.PREC_FP64)):
+                ctxp = H.Halo(H.params_for_catalog(scat, mode=H.PLAIN, prec=pr,
+                                                   grid_min=args.grid_min,
+                                                   bh_theta=args.bh_theta, bh_min=args.bh_min))
+                sp, _, stp, _ = timed(ctxp, SP, 1, 1)
+                forms[f"side_plain_{names[pr]}"] = {"workload": args.side_config,
+                                                    "value": scat.n / sp,
+                                                    "ms_per_step": sp * 1e3, "stage_ms": stp}
+                if pr == prec:
+                    bt = forms[f"side_batched_{names[pr]}"]["ms_per_step"]
+                    plain = {"workload": args.side_config, "value": scat.n / sp,
+                             "ms_per_step": sp * 1e3, "batched_ms_per_step": bt,
+                             "batched_over_plain": sp * 1e3 / bt}
+                del ctxp
+            progress("side workload: plain forms timed")
+        if not args.no_forms:
+            precision = precision_report(H, scat, SP, args.grid_min)
+        if not args.no_extras:
+            extras = extras_report(sctx, SP, sout, scat.particle_mass,
+                                   H.params_for_catalog(scat).rho_vir)
+            progress("additional properties timed")
+        if not args.no_merger:
+            merger = merger_report(H, scat, SP, args.grid_min, prec)
+            progress("major-merger form timed")
+        if not args.no_subset:
+            subset = subset_report(H, scat, SP, args.grid_min, prec)
+            progress("subset linking length timed")
+        if not args.no_dense:
+            dense = dense_report(H, scat, SP, args.grid_min, prec)
+            progress("dense-particle FOF variant timed")
+        if not args.no_tree:
+            tree = tree_report(sctx, SP, sout, theta=args.bh_theta or 0.04,
+                               bh_min=args.bh_min)
+            progress("tree potential timed")
+        del sctx, sout, SP, scat
 
     if args.copy_probe:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -584,21 +736,20 @@ def main():
         torch.cuda.synchronize()
 
     cpu = None if args.no_cpu else cpu_baseline(cat)
+    if cpu is not None:
+        progress("CPU oracle baseline done")
     rec = {
         "metric": METRIC, "value": cat.n / sec, "unit": "particles/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32" if prec == H.PREC_FP64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {cat.n} particles, box {cat.box} Mpc/h, "
-                               "power-law NFW hosts + subhaloes + 40% uniform, seed 0"
-                               + (" (GPU-drawn)" if args.gen == "device" else ""),
+        "config": {"workload": workload_name(args.config, cat, gen),
                    "form": "batched", "potential": args.prec,
                    "bh_theta": args.bh_theta,
                    "bh_min": args.bh_min if args.bh_theta > 0 else None,
-                   "grid_min": args.grid_min, "autotune": tuned,
-                   "n_groups": int(out[0]["n_groups"]), "n_nodes": int(out[1]["parent"].shape[0]),
-                   "n_halos": int(out[2]["seed_node"].shape[0])},
+                   "grid_min": args.grid_min, "autotune": tuned, **counts,
+                   "side_workload": side},
         "stage_ms": stage,
         "passes": passes,
         "plain": plain,

@@ -240,6 +240,11 @@ int libhalo_profile(libhalo_ctx* ctx, int enable);
 int libhalo_profile_reset(libhalo_ctx* ctx);
 int libhalo_profile_read(libhalo_ctx* ctx, const char* kernel, double* total_ms,
                          int64_t* launches);
+/* Work counted by the tree searches of large hierarchy nodes while profiling
+ * is enabled, since the last reset: the node boxes tested and the particle
+ * distances evaluated by "k_kd_walk_nn" (nearest neighbours) or
+ * "k_kd_walk_fof" (6D FOF).  Errors: EINVAL (another kernel name), EHIP. */
+int libhalo_profile_work(libhalo_ctx* ctx, const char* kernel, double* tests, double* evals);
 
 /*
  * 3D friends-of-friends (Section 3.1), standard definition: particles i and

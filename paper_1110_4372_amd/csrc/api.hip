@@ -14,6 +14,7 @@ struct libhalo_ctx {
 
 namespace halo {
 
+
 void* Ctx::dev_alloc(size_t bytes, const char* what) {
   void* p = alloc_fn(bytes, user, (void*)stream);
   if (!p)
@@ -193,6 +194,24 @@ int libhalo_profile_reset(libhalo_ctx* ctx) {
       c.spare.push_back(r.e1);
     }
     c.recs.clear();
+    HALO_HIP(hipDeviceSynchronize());
+    HALO_HIP(hipMemset(reinterpret_cast<char*>(c.d_err) + 64, 0, 64));
+  });
+}
+
+int libhalo_profile_work(libhalo_ctx* ctx, const char* kernel, double* tests, double* evals) {
+  return guarded(ctx, [&](halo::Ctx& c) {
+    HALO_CHECK(kernel && tests && evals, LIBHALO_EINVAL, "null pointer argument");
+    int slot = -1;
+    if (std::strcmp(kernel, "k_kd_walk_nn") == 0) slot = 0;
+    if (std::strcmp(kernel, "k_kd_walk_fof") == 0) slot = 2;
+    HALO_CHECK(slot >= 0, LIBHALO_EINVAL, "no work counters for this kernel");
+    unsigned long long w[4];
+    HALO_HIP(hipDeviceSynchronize());
+    HALO_HIP(hipMemcpy(w, reinterpret_cast<char*>(c.d_err) + 64, sizeof w,
+                       hipMemcpyDeviceToHost));
+    *tests = (double)w[slot];
+    *evals = (double)w[slot + 1];
   });
 }
 

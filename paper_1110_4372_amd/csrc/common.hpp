@@ -90,13 +90,19 @@ struct Ctx {
   std::string err;
   Arena ws;
   Arena ws2;                       // second arena: the tree potential, inside unbinding
-  uint32_t* d_err = nullptr;       // device error word
+  uint32_t* d_err = nullptr;       // device error word; its block also holds the
+                                   // walks' work counters (8 u64 at byte 64)
   void* h_pinned = nullptr;        // small pinned host buffer for read-backs
   hipStream_t stream = nullptr;    // stream of the entry point being run
   libhalo_alloc_fn alloc_fn = nullptr;  // workspace provider (caller's callbacks)
   libhalo_free_fn free_fn = nullptr;
   void* user = nullptr;
   void* dev_alloc(size_t bytes, const char* what);  // ENOMEM on NULL
+  // device work counters of the tree walks while profiling, else null
+  unsigned long long* work_counters() {
+    return prof ? reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(d_err) + 64)
+                : nullptr;
+  }
   void ensure_ws(size_t bytes);
   void ensure_ws2(size_t bytes);
   void release();

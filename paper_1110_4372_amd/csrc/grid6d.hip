@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(kWalkTB)
               const uint32_t* __restrict__ pm, const uint32_t* __restrict__ pb,
               const uint32_t* __restrict__ leafof, const uint32_t* __restrict__ troot,
               uint32_t MB, const uint32_t* __restrict__ gnode, NodeScratch sc, uint32_t* D,
-              uint32_t* par) {
+              uint32_t* par, unsigned long long* work) {
   const uint32_t q = xcd_wave(blockIdx.x, gridDim.x) * kWalkTB + threadIdx.x;
   const bool valid = q < MB;
   const uint32_t qq = valid ? q : MB - 1;
@@ -230,8 +230,10 @@ __global__ void __launch_bounds__(kWalkTB)
   uint32_t lo = MODE == 0 ? T[own].lo : q + 1u, hi = T[own + 1].lo;
   uint32_t u = MODE == 0 ? troot[b] : own + 1u;
   bool have = active;  // a leaf range waiting to be searched
+  uint32_t ntest = 0, neval = 0;  // work counts (profiling)
   while (__any(active)) {
     if (have) {
+      neval += hi > lo ? hi - lo : 0u;
       for (uint32_t j = lo; j < hi; ++j) {
         const float* pj = pt + 6ull * j;
         const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], pj[0], pj[1], pj[2], pj[3],
@@ -255,6 +257,7 @@ __global__ void __launch_bounds__(kWalkTB)
         } else {
           const KdNode r = T[u];
           const float g = point_gap2(a, r);
+          ++ntest;
           const bool in = MODE == 0 ? g < best : g <= l2;
           if (!in) {
             u = r.skip;
@@ -271,6 +274,17 @@ __global__ void __launch_bounds__(kWalkTB)
     }
   }
   if (MODE == 0 && valid) D[m] = __float_as_uint(best);
+  if (work) {
+    unsigned long long t = ntest, e = neval;
+    for (int o = 32; o > 0; o >>= 1) {
+      t += __shfl_xor(t, o);
+      e += __shfl_xor(e, o);
+    }
+    if ((threadIdx.x & 63u) == 0) {
+      atomicAdd(work + 2 * MODE, t);
+      atomicAdd(work + 2 * MODE + 1, e);
+    }
+  }
 }
 
 unsigned walk_grid(uint32_t MB) { return (MB + kWalkTB - 1) / kWalkTB; }
@@ -306,7 +320,7 @@ void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax) {
 
 uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint32_t K,
                     const uint32_t* lnode, uint32_t Mi, uint32_t M, NodeScratch sc,
-                    uint32_t* hb, hipStream_t s, uint32_t* D, uint32_t gmin) {
+                    uint32_t* hb, hipStream_t s, uint32_t gmin) {
   g.NB = 0;
   g.MB = 0;
   if (Mi <= gmin) {  // no node of the level can exceed the threshold: no read-back needed
@@ -342,16 +356,23 @@ uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint3
     k_kd_records<<<blocks_for(nu, TB), TB, 0, s>>>(g, t.bnode, t.pre, t.lev[d], nu);
   }
   k_kd_sentinel<<<1, 1, 0, s>>>(g.node, t.NN, MB);
-  k_kd_walk<0><<<walk_grid(MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof, g.troot,
-                                                 MB, g.gnode, sc, D, nullptr);
   return NB;
 }
 
-void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par, hipStream_t s) {
+void grid_nn(GridBufs& g, NodeScratch sc, uint32_t* D, unsigned long long* work,
+             hipStream_t s) {
+  if (g.NB == 0 || g.MB == 0) return;
+  k_kd_walk<0><<<walk_grid(g.MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof,
+                                                   g.troot, g.MB, g.gnode, sc, D, nullptr,
+                                                   work);
+}
+
+void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par,
+              unsigned long long* work, hipStream_t s) {
   if (g.NB == 0 || g.MB == 0) return;
   k_kd_walk<1><<<walk_grid(g.MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof,
                                                    g.troot, g.MB, g.gnode, sc,
-                                                   const_cast<uint32_t*>(D), par);
+                                                   const_cast<uint32_t*>(D), par, work);
 }
 
 }  // namespace refine

@@ -1063,8 +1063,9 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     k_fill_u32<<<blocks_for(Mi, TB), TB, 0, s>>>(D, Mi, 0x7F800000u);
     k_iota<<<blocks_for(Mi, TB), TB, 0, s>>>(par, Mi);
     HALO_PROF(ctx, "grid_build", s,
-              grid_build(gb, xi, S, nd, K, lnode, Mi, M, sc, rd.h + 8, s, D,
+              grid_build(gb, xi, S, nd, K, lnode, Mi, M, sc, rd.h + 8, s,
                          P.grid_min > 0 ? (uint32_t)P.grid_min : kGridMin));
+    HALO_PROF(ctx, "k_kd_walk_nn", s, grid_nn(gb, sc, D, ctx.work_counters(), s));
     k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, nnj,
                                                    sc.wpair);
     exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
@@ -1131,7 +1132,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
                 k_fof6<<<pgrid, TB, 0, s>>>(cxi, S, cnodes, lpos, K, sc.wpair, 0, K,
                                                dcnt + 8, sc.ell2, pj, par));
     }
-    HALO_PROF(ctx, "grid_fof", s, grid_fof(gb, sc, D, par, s));
+    HALO_PROF(ctx, "k_kd_walk_fof", s, grid_fof(gb, sc, D, par, ctx.work_counters(), s));
     k_compress<<<blocks_for(Mi, TB), TB, 0, s>>>(par, Mi);
     // 6. children
     k_fill_u32<<<blocks_for(Mi, TB), TB, 0, s>>>(csize, Mi, 0u);

@@ -95,14 +95,18 @@ struct GridBufs {
 };
 
 void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax);
-// Classifies the level's nodes (sc.gstate 1 for tree nodes), builds their
-// trees and writes their exact nearest-neighbour distances into D.  Returns
-// the number of tree nodes of the level.
+// Classifies the level's nodes (sc.gstate 1 for tree nodes) and builds the
+// trees of those above gmin.  Returns their number.
 uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint32_t K,
                     const uint32_t* lnode, uint32_t Mi, uint32_t M, NodeScratch sc,
-                    uint32_t* hb, hipStream_t s, uint32_t* D, uint32_t gmin);
-// 6D FOF at each tree node's ell^2 over its particles with D <= ell^2.
-void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par, hipStream_t s);
+                    uint32_t* hb, hipStream_t s, uint32_t gmin);
+// Exact nearest-neighbour distances of the tree nodes' particles into D.
+// work (may be null): adds the walk's box tests and distances to work[0], [1].
+void grid_nn(GridBufs& g, NodeScratch sc, uint32_t* D, unsigned long long* work, hipStream_t s);
+// 6D FOF at each tree node's ell^2 over its particles with D <= ell^2; work
+// (may be null): box tests and distances added to work[2], [3].
+void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par,
+              unsigned long long* work, hipStream_t s);
 
 // min over j in [j0, j1) of d2(i, j) over six FP32 coordinate planes of stride
 // S; j is wave-uniform, so the j coordinates are scalar loads feeding the

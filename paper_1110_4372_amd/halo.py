@@ -122,8 +122,8 @@ ExtraS = _struct(EXTRA_FIELDS, True)
 # Exported symbols (the C ABI of include/libhalo.h).
 SYMBOLS = ["libhalo_ctx_create", "libhalo_ctx_destroy", "libhalo_last_error",
            "libhalo_set_params", "libhalo_version", "libhalo_profile", "libhalo_profile_reset",
-           "libhalo_profile_read", "libhalo_fof3d", "libhalo_refine6d", "libhalo_assign",
-           "libhalo_unbind", "libhalo_props", "libhalo_props_extra"]
+           "libhalo_profile_read", "libhalo_profile_work", "libhalo_fof3d", "libhalo_refine6d",
+           "libhalo_assign", "libhalo_unbind", "libhalo_props", "libhalo_props_extra"]
 
 # Workspace allocator callbacks of libhalo_ctx_create.
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -167,6 +167,8 @@ def load_library(path: str = LIB_PATH):
     L.libhalo_profile.argtypes = [_P, i32]
     L.libhalo_profile_reset.argtypes = [_P]
     L.libhalo_profile_read.argtypes = [_P, C.c_char_p, C.POINTER(C.c_double), pi64]
+    L.libhalo_profile_work.argtypes = [_P, C.c_char_p, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double)]
     L.libhalo_fof3d.argtypes = [_P, i64, i32, _P, _P, _P, _P, _P, _P, _P, i64, pi64, pi64, _P]
     L.libhalo_refine6d.argtypes = [_P, i64, i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, i64,
                                    C.POINTER(NodesS), _P, pi64, _P]
@@ -293,6 +295,13 @@ class Halo:
         t, k = C.c_double(0.0), C.c_int64(0)
         self._check(self.L.libhalo_profile_read(self.h, kernel.encode(), C.byref(t), C.byref(k)))
         return t.value, k.value
+
+    def profile_work(self, kernel: str):
+        """(box tests, distances) counted by a tree-search kernel since the last
+        reset ("k_kd_walk_nn" or "k_kd_walk_fof")."""
+        t, e = C.c_double(0.0), C.c_double(0.0)
+        self._check(self.L.libhalo_profile_work(self.h, kernel.encode(), C.byref(t), C.byref(e)))
+        return t.value, e.value
 
     # ------------------------------------------------------------ stages --
     def fof3d(self, P: Particles, grp_cap: int | None = None):
