@@ -265,6 +265,29 @@ int libhalo_fof3d(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
                   int64_t* n_groups, int64_t* n_members, void* stream);
 
 /*
+ * libhalo_fof3d for callers that cannot allocate device memory during the
+ * call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as libhalo_fof3d,
+ * but the workspace is a fixed device array of LIBHALO_NOALLOC_SCRATCH_BYTES
+ * inside the library (each device that loads the library holds one copy until
+ * the process ends; its address is looked up when a context is created on
+ * that device), never the context's allocator: the call allocates nothing.
+ * The caller still passes every input and output buffer.
+ * Limit: ENOMEM, before any work, when the particles need more scratch than
+ * the array holds (about 80 bytes per particle plus 4 per cell row of the
+ * linking grid: up to about 3 million particles).
+ * Concurrency: every call on a device shares that device's array, so calls
+ * that overlap on one device (other threads, other contexts, other streams)
+ * race and must be serialised by the caller; the call returns after its work
+ * on `stream` has finished.
+ */
+#define LIBHALO_NOALLOC_SCRATCH_BYTES (256u << 20)
+int libhalo_fof3d_noalloc(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
+                          const void* y, const void* z, uint32_t* fof_label, uint32_t* perm,
+                          uint32_t* grp_first, uint32_t* grp_count, int64_t grp_cap,
+                          int64_t* n_groups, int64_t* n_members, void* stream);
+
+/*
  * Recursive phase-space FOF hierarchy (Section 3.2) of every FOF group given
  * by (perm, grp_first, grp_count) as produced by libhalo_fof3d.  For each
  * (sub)group: Eq. 1 metric (positions and velocities divided by the group's

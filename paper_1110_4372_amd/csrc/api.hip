@@ -1,7 +1,9 @@
 // C ABI of libhalo: context, parameter validation, error capture, dispatch.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "common.hpp"
 #include "fof3d.hpp"
@@ -14,6 +16,29 @@ struct libhalo_ctx {
 
 namespace halo {
 
+// Fixed device scratch of the no-alloc entry point: one copy per device that
+// loads the library, held until the process ends.  Host code never uses the
+// array's name as an address: each device's copy is looked up once, with that
+// device current, and kept in scratch_dev.
+constexpr size_t kScratchBytes = size_t(LIBHALO_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+static std::mutex scratch_mu;
+static std::vector<void*> scratch_dev;  // per device, null until looked up
+
+// The calling thread's current device is `device`.
+static hipError_t scratch_setup(int device, void** out) {
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if ((int)scratch_dev.size() <= device) scratch_dev.resize(device + 1, nullptr);
+  if (!scratch_dev[device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_dev[device] = ptr;
+  }
+  *out = scratch_dev[device];
+  return hipSuccess;
+}
 
 void* Ctx::dev_alloc(size_t bytes, const char* what) {
   void* p = alloc_fn(bytes, user, (void*)stream);
@@ -144,6 +169,8 @@ int libhalo_ctx_create(const libhalo_params* p, int device, libhalo_alloc_fn all
   if (hipSetDevice(device) != hipSuccess ||
       hipHostMalloc(&c->c.h_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
     rc = LIBHALO_EHIP;
+  } else if (halo::scratch_setup(device, &c->c.scratch) != hipSuccess) {
+    rc = LIBHALO_EHIP;
   } else {
     c->c.d_err = static_cast<uint32_t*>(alloc_fn(256, user, nullptr));
     if (!c->c.d_err) rc = LIBHALO_ENOMEM;
@@ -248,6 +275,40 @@ int libhalo_fof3d(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x, con
     c.ensure_ws(halo::fof3d_workspace(c.p, n, pos_dtype));
     halo::fof3d(c, n, pos_dtype, x, y, z, fof_label, perm, grp_first, grp_count, grp_cap,
                 n_groups, n_members, (hipStream_t)stream);
+  }, stream);
+}
+
+int libhalo_fof3d_noalloc(libhalo_ctx* ctx, int64_t n, int pos_dtype, const void* x,
+                          const void* y, const void* z, uint32_t* fof_label, uint32_t* perm,
+                          uint32_t* grp_first, uint32_t* grp_count, int64_t grp_cap,
+                          int64_t* n_groups, int64_t* n_members, void* stream) {
+  return guarded(ctx, [&](halo::Ctx& c) {
+    HALO_CHECK(n >= 1 && n < 0xFFFFFFFFll, LIBHALO_EINVAL, "n must lie in [1, 2^32-1)");
+    HALO_CHECK(dtype_ok(pos_dtype), LIBHALO_EINVAL, "pos_dtype must be F32 or F64");
+    HALO_CHECK(x && y && z && fof_label && perm && n_groups && n_members, LIBHALO_EINVAL,
+               "null pointer argument");
+    HALO_CHECK(grp_cap == 0 || (grp_first && grp_count), LIBHALO_EINVAL,
+               "null group table");
+    HALO_CHECK(c.scratch != nullptr, LIBHALO_EHIP, "no scratch array on this device");
+    const size_t need = halo::fof3d_workspace(c.p, n, pos_dtype);
+    if (need > halo::kScratchBytes)
+      throw halo::Error{LIBHALO_ENOMEM,
+                        "libhalo_fof3d_noalloc: these particles need " + std::to_string(need) +
+                            " bytes of scratch; the fixed array holds " +
+                            std::to_string(halo::kScratchBytes)};
+    // the call's workspace is the device's scratch array, not the context's
+    halo::Arena own = c.ws;
+    c.ws = halo::Arena{};
+    c.ws.base = static_cast<char*>(c.scratch);
+    c.ws.cap = halo::kScratchBytes;
+    try {
+      halo::fof3d(c, n, pos_dtype, x, y, z, fof_label, perm, grp_first, grp_count, grp_cap,
+                  n_groups, n_members, (hipStream_t)stream);
+    } catch (...) {
+      c.ws = own;
+      throw;
+    }
+    c.ws = own;
   }, stream);
 }
 

@@ -97,6 +97,7 @@ struct Ctx {
   libhalo_alloc_fn alloc_fn = nullptr;  // workspace provider (caller's callbacks)
   libhalo_free_fn free_fn = nullptr;
   void* user = nullptr;
+  void* scratch = nullptr;         // this device's fixed scratch array (no-alloc entry)
   void* dev_alloc(size_t bytes, const char* what);  // ENOMEM on NULL
   // device work counters of the tree walks while profiling, else null
   unsigned long long* work_counters() {

@@ -122,7 +122,8 @@ ExtraS = _struct(EXTRA_FIELDS, True)
 # Exported symbols (the C ABI of include/libhalo.h).
 SYMBOLS = ["libhalo_ctx_create", "libhalo_ctx_destroy", "libhalo_last_error",
            "libhalo_set_params", "libhalo_version", "libhalo_profile", "libhalo_profile_reset",
-           "libhalo_profile_read", "libhalo_profile_work", "libhalo_fof3d", "libhalo_refine6d",
+           "libhalo_profile_read", "libhalo_profile_work", "libhalo_fof3d",
+           "libhalo_fof3d_noalloc", "libhalo_refine6d",
            "libhalo_assign", "libhalo_unbind", "libhalo_props", "libhalo_props_extra"]
 
 # Workspace allocator callbacks of libhalo_ctx_create.
@@ -170,6 +171,7 @@ def load_library(path: str = LIB_PATH):
     L.libhalo_profile_work.argtypes = [_P, C.c_char_p, C.POINTER(C.c_double),
                                        C.POINTER(C.c_double)]
     L.libhalo_fof3d.argtypes = [_P, i64, i32, _P, _P, _P, _P, _P, _P, _P, i64, pi64, pi64, _P]
+    L.libhalo_fof3d_noalloc.argtypes = L.libhalo_fof3d.argtypes
     L.libhalo_refine6d.argtypes = [_P, i64, i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, i64,
                                    C.POINTER(NodesS), _P, pi64, _P]
     L.libhalo_assign.argtypes = [_P, i64, i32, _P, _P, _P, _P, _P, _P, C.POINTER(NodesS), i64,
@@ -319,6 +321,19 @@ class Halo:
         g = ng.value
         return dict(label=label, perm=perm[: nm.value], grp_first=first[:g],
                     grp_count=count[:g], n_groups=g, n_members=nm.value)
+
+    def fof3d_noalloc(self, P: Particles, label, perm, grp_first, grp_count):
+        """libhalo_fof3d_noalloc into caller-allocated int32 tensors (label and
+        perm of P.n entries, grp_first and grp_count of the table's capacity):
+        the call allocates nothing.  Returns (n_groups, n_members)."""
+        assert grp_first.shape[0] == grp_count.shape[0]
+        assert label.shape[0] >= P.n and perm.shape[0] >= P.n
+        ng, nm = C.c_int64(0), C.c_int64(0)
+        self._check(self.L.libhalo_fof3d_noalloc(
+            self.h, P.n, P.dtype_code, *P.args(False), _ptr(label), _ptr(perm),
+            _ptr(grp_first), _ptr(grp_count), grp_first.shape[0], C.byref(ng), C.byref(nm),
+            _stream()))
+        return ng.value, nm.value
 
     def refine6d(self, P: Particles, fof: dict, node_cap: int | None = None):
         dev = self.device
