@@ -37,6 +37,7 @@ namespace {
 
 constexpr float kHalfRange = 4.0f;      // Morton quantisation range [-A, A]
 constexpr int kWalkTB = 256;            // threads per block of the walks
+constexpr uint32_t kWalkChunk = 64;     // points a wave takes from the queue at a time
 
 __global__ void k_grid_classify(LevelNodes nd, uint32_t K, NodeScratch sc, uint32_t gmin,
                                 uint32_t* flag) {
@@ -181,17 +182,7 @@ __device__ __forceinline__ float point_gap2(const float* a, const KdNode& r) {
   return s;
 }
 
-// Block -> share of the points: the blocks that run on one XCD (blockIdx mod
-// 8) take one contiguous run of waves, so walks of neighbouring particles
-// share that XCD's L2.
-__device__ __forceinline__ uint32_t xcd_wave(uint32_t bid, uint32_t G) {
-  const uint32_t x = bid & 7u;
-  uint32_t start = 0;
-  for (uint32_t y = 0; y < x; ++y) start += (G - y + 7u) >> 3;
-  return start + (bid >> 3);
-}
-
-// One thread per sorted point q, walking its tree's preorder records: a node
+// One lane per query point q, walking its tree's preorder records: a node
 // whose box is close enough is entered (next record), else skipped (its
 // `skip`).  MODE 0: nearest-neighbour distance within the point's tree node
 // (D[m] = min over j != q of d2_6), starting from its own leaf's particles,
@@ -200,38 +191,76 @@ __device__ __forceinline__ uint32_t xcd_wave(uint32_t bid, uint32_t G) {
 // order: the rest of its own leaf, then the records after that leaf (the
 // preorder visits index ranges in increasing order).  Lanes first test nodes
 // until each has a leaf to search, then search their leaves together.
+//
+// The walks differ in length by several times within a wave, so the grid is
+// persistent and a lane whose walk ends takes the next query at once: each
+// wave takes chunks of kWalkChunk consecutive points (neighbours on the Morton
+// curve) from a queue counter and hands them out in order to its idle lanes.
+// The kernel ends when the queue is drained and every lane is idle; every
+// walk ends because u only grows and is bounded by its tree's end.
 template <int MODE>
 __global__ void __launch_bounds__(kWalkTB)
     k_kd_walk(const KdNode* __restrict__ T, const float* __restrict__ pt,
               const uint32_t* __restrict__ pm, const uint32_t* __restrict__ pb,
               const uint32_t* __restrict__ leafof, const uint32_t* __restrict__ troot,
               uint32_t MB, const uint32_t* __restrict__ gnode, NodeScratch sc, uint32_t* D,
-              uint32_t* par, unsigned long long* work) {
-  const uint32_t q = xcd_wave(blockIdx.x, gridDim.x) * kWalkTB + threadIdx.x;
-  const bool valid = q < MB;
-  const uint32_t qq = valid ? q : MB - 1;
-  float a[6];
-  for (int c = 0; c < 6; ++c) a[c] = pt[6ull * qq + c];
-  const uint32_t b = pb[qq], m = pm[qq];
-  bool active = valid;
+              uint32_t* par, uint32_t* queue, unsigned long long* work) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  uint32_t cbase = 0, cnext = kWalkChunk;  // the wave's chunk and its next unissued point
+  bool drained = false;
+  // this lane's query
+  bool active = false, have = false;
+  uint32_t q = 0, m = 0, own = 0, end = 0, lo = 0, hi = 0, u = 0, ri = 0;
+  float a[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   float best = __int_as_float(0x7F800000);  // MODE 0: nearest so far
   float l2 = 0.0f;                          // MODE 1: ell^2 of the node
-  uint32_t ri = 0;
-  if (MODE == 1 && active) {
-    l2 = sc.ell2[gnode[b]];
-    if (!(__uint_as_float(D[m]) <= l2))
-      active = false;
-    else
-      ri = uf_find(par, m);
-  }
-  const uint32_t own = leafof[qq];
-  const uint32_t end = troot[b + 1];  // the record after the point's tree
-  // the own leaf first: range [lo, hi), then the walk from u
-  uint32_t lo = MODE == 0 ? T[own].lo : q + 1u, hi = T[own + 1].lo;
-  uint32_t u = MODE == 0 ? troot[b] : own + 1u;
-  bool have = active;  // a leaf range waiting to be searched
-  uint32_t ntest = 0, neval = 0;  // work counts (profiling)
-  while (__any(active)) {
+  uint32_t ntest = 0, neval = 0;            // work counts (profiling)
+  while (true) {
+    // idle lanes take the next points of the wave's chunk
+    while (!drained) {
+      const unsigned long long idle = __ballot(!active);
+      if (idle == 0) break;
+      if (cnext >= kWalkChunk) {
+        uint32_t c = 0;
+        if (lane == 0) c = atomicAdd(queue, kWalkChunk);
+        c = __shfl(c, 0);
+        if (c >= MB) {
+          drained = true;
+          break;
+        }
+        cbase = c;
+        cnext = 0;
+      }
+      const uint32_t left = MB - cbase > cnext ? MB - cbase - cnext : 0u;
+      const uint32_t avail = min(kWalkChunk - cnext, left);
+      const uint32_t rank = (uint32_t)__popcll(idle & below);
+      if (!active && rank < avail) {
+        q = cbase + cnext + rank;
+        for (int c = 0; c < 6; ++c) a[c] = pt[6ull * q + c];
+        const uint32_t b = pb[q];
+        m = pm[q];
+        own = leafof[q];
+        end = troot[b + 1];  // the record after the point's tree
+        hi = T[own + 1].lo;
+        if (MODE == 0) {
+          lo = T[own].lo;
+          u = troot[b];
+          best = __int_as_float(0x7F800000);
+          active = true;
+        } else {
+          l2 = sc.ell2[gnode[b]];
+          lo = q + 1u;
+          u = own + 1u;
+          active = __uint_as_float(D[m]) <= l2;
+          if (active) ri = uf_find(par, m);
+        }
+        have = active;  // the own leaf first
+      }
+      const uint32_t took = min((uint32_t)__popcll(idle), avail);
+      cnext = avail == 0 ? kWalkChunk : cnext + took;
+    }
+    if (!__any(active)) break;
     if (have) {
       neval += hi > lo ? hi - lo : 0u;
       for (uint32_t j = lo; j < hi; ++j) {
@@ -251,6 +280,7 @@ __global__ void __launch_bounds__(kWalkTB)
     while (__any(active && !have)) {
       if (active && !have) {
         if (u >= end) {
+          if (MODE == 0) D[m] = __float_as_uint(best);
           active = false;
         } else if (MODE == 0 && u == own) {
           u = own + 1u;  // searched first
@@ -273,21 +303,26 @@ __global__ void __launch_bounds__(kWalkTB)
       }
     }
   }
-  if (MODE == 0 && valid) D[m] = __float_as_uint(best);
   if (work) {
     unsigned long long t = ntest, e = neval;
     for (int o = 32; o > 0; o >>= 1) {
       t += __shfl_xor(t, o);
       e += __shfl_xor(e, o);
     }
-    if ((threadIdx.x & 63u) == 0) {
+    if (lane == 0) {
       atomicAdd(work + 2 * MODE, t);
       atomicAdd(work + 2 * MODE + 1, e);
     }
   }
 }
 
-unsigned walk_grid(uint32_t MB) { return (MB + kWalkTB - 1) / kWalkTB; }
+// Persistent grid of the walks: as many waves as the chip holds at the
+// kernel's occupancy (8 per SIMD), fewer when there are fewer chunks.
+unsigned walk_grid(uint32_t MB) {
+  const uint32_t chunks = (MB + kWalkChunk - 1) / kWalkChunk;
+  const uint32_t waves = min(chunks, 256u * 4u * 8u);
+  return (waves + kWalkTB / 64 - 1) / (kWalkTB / 64);
+}
 
 }  // namespace
 
@@ -314,6 +349,7 @@ void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax) {
   g.pb = A.take<uint32_t>((size_t)M + 2);
   g.leafof = A.take<uint32_t>((size_t)M + 2);
   g.cnt = A.take<uint32_t>(16);
+  g.queue = A.take<uint32_t>(64);
   g.rtmp = A.take<char>(radix_tmp_bytes((int64_t)M + 2));
   g.stmp = A.take<uint32_t>(scan_tmp_elems<uint32_t>((int64_t)M + Kmax + 4));
 }
@@ -362,17 +398,20 @@ uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint3
 void grid_nn(GridBufs& g, NodeScratch sc, uint32_t* D, unsigned long long* work,
              hipStream_t s) {
   if (g.NB == 0 || g.MB == 0) return;
+  k_fill_u32<<<1, 64, 0, s>>>(g.queue, 2, 0u);
   k_kd_walk<0><<<walk_grid(g.MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof,
                                                    g.troot, g.MB, g.gnode, sc, D, nullptr,
-                                                   work);
+                                                   g.queue, work);
 }
 
 void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par,
               unsigned long long* work, hipStream_t s) {
   if (g.NB == 0 || g.MB == 0) return;
+  k_fill_u32<<<1, 64, 0, s>>>(g.queue, 2, 0u);
   k_kd_walk<1><<<walk_grid(g.MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof,
                                                    g.troot, g.MB, g.gnode, sc,
-                                                   const_cast<uint32_t*>(D), par, work);
+                                                   const_cast<uint32_t*>(D), par, g.queue,
+                                                   work);
 }
 
 }  // namespace refine
