@@ -162,15 +162,23 @@ __global__ void k_bh_keys(const double* ux, const double* uy, const double* uz, 
   val[e] = q;
 }
 
+// Sorted positions (FP64); with f non-null also their FP32 roundings, which
+// the mixed form's walk reads.
 __global__ void k_bh_gather(const double* ux, const double* uy, const double* uz,
                             const uint32_t* sval, uint32_t E, double* px, double* py,
-                            double* pz) {
+                            double* pz, float* f) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
   const uint32_t q = sval[e];
-  px[e] = ux[q];
-  py[e] = uy[q];
-  pz[e] = uz[q];
+  const double x = ux[q], y = uy[q], z = uz[q];
+  px[e] = x;
+  py[e] = y;
+  pz[e] = z;
+  if (f) {
+    f[3ull * e] = (float)x;
+    f[3ull * e + 1] = (float)y;
+    f[3ull * e + 2] = (float)z;
+  }
 }
 
 // A cell as the walk reads it (one 64-byte scalar fetch), in preorder: mass
@@ -295,12 +303,19 @@ __global__ void k_bh_wave_counts(BhList L, uint32_t B, uint32_t* wcnt) {
 // is entered (its first child is the next record).  Cell records and
 // leaf particles are read at wave-uniform addresses (scalar loads), and each
 // lane sums its terms in the wave's fixed order.
+//
+// F32 (the mixed form): distances and reciprocal square roots in FP32 from the
+// halo-local positions rounded to FP32 (their rounding, about 1e-7 of a halo's
+// extent, is far below the monopole error the acceptance distance allows); a
+// leaf's terms are summed in FP32 and each leaf's and monopole's sum is added
+// to the lane's FP64 total.
+template <bool F32>
 __global__ void __launch_bounds__(TB)
     k_bh_walk(BhList L, uint32_t B, const uint32_t* woff, uint32_t nwave, const uint32_t* slot,
               const double* __restrict__ px, const double* __restrict__ py,
-              const double* __restrict__ pz, const uint32_t* __restrict__ pidx,
-              const BhRec* __restrict__ R, const uint32_t* __restrict__ troot, double eps2,
-              I128* __restrict__ pacc) {
+              const double* __restrict__ pz, const float* __restrict__ pf,
+              const uint32_t* __restrict__ pidx, const BhRec* __restrict__ R,
+              const uint32_t* __restrict__ troot, double eps2, I128* __restrict__ pacc) {
   const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (TB / 64) +
                                                        (threadIdx.x >> 6));
   if (wave >= nwave) return;  // wave-uniform
@@ -314,6 +329,7 @@ __global__ void __launch_bounds__(TB)
   const bool target = in && (q - s0) < nown;
   if (__ballot(target) == 0ull) return;  // wave-uniform
   const double x = in ? px[e] : 0.0, y = in ? py[e] : 0.0, z = in ? pz[e] : 0.0;
+  const float xf = (float)x, yf = (float)y, zf = (float)z, eps2f = (float)eps2;
   uint32_t u = __builtin_amdgcn_readfirstlane(troot[b]);
   const uint32_t end = __builtin_amdgcn_readfirstlane(troot[b + 1]);
   double acc = 0.0;
@@ -323,23 +339,50 @@ __global__ void __launch_bounds__(TB)
   while (u < end) {
     const BhRec nx = R[u + 1];
     uint32_t v;
-    const double d2 = sq3(x - c.cx, y - c.cy, z - c.cz);
+    double d2;
+    float d2f = 0.0f;
+    if constexpr (F32) {
+      const float dx = xf - (float)c.cx, dy = yf - (float)c.cy, dz = zf - (float)c.cz;
+      d2f = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+      d2 = (double)d2f;
+    } else {
+      d2 = sq3(x - c.cx, y - c.cy, z - c.cz);
+    }
     // a cell is a monopole for a target outside it beyond the acceptance
     // distance; the cell holding the target itself is always opened (a cell of
     // coincident particles has a zero acceptance distance)
     const bool open = d2 <= c.crit2 || (e >= c.lo && e < c.hi);
     if (__ballot(target && open) == 0ull) {
-      if (target) acc += c.cm * rsqrt_f64(d2 + eps2);
+      if (target) {
+        if constexpr (F32)
+          acc += c.cm * (double)__builtin_amdgcn_rsqf(d2f + eps2f);
+        else
+          acc += c.cm * rsqrt_f64(d2 + eps2);
+      }
       v = c.skip;
     } else if (c.leaf) {
       // every lane evaluates each term and keeps it by a select, so the loads of a
       // leaf particle are not behind a branch and several can be in flight at once
+      if constexpr (F32) {
+        float sf = 0.0f;
 #pragma unroll 4
-      for (uint32_t f = c.lo; f < c.hi; ++f) {
-        const double fx = px[f], fy = py[f], fz = pz[f];
-        const uint32_t qf = pidx[f];
-        const double tf = rsqrt_f64(sq3(x - fx, y - fy, z - fz) + eps2);
-        acc = (target && qf != q) ? acc + tf : acc;
+        for (uint32_t f = c.lo; f < c.hi; ++f) {
+          const float fx = pf[3ull * f], fy = pf[3ull * f + 1], fz = pf[3ull * f + 2];
+          const uint32_t qf = pidx[f];
+          const float dx = xf - fx, dy = yf - fy, dz = zf - fz;
+          const float tf = __builtin_amdgcn_rsqf(
+              __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2f))));
+          sf = (target && qf != q) ? sf + tf : sf;
+        }
+        acc += (double)sf;
+      } else {
+#pragma unroll 4
+        for (uint32_t f = c.lo; f < c.hi; ++f) {
+          const double fx = px[f], fy = py[f], fz = pz[f];
+          const uint32_t qf = pidx[f];
+          const double tf = rsqrt_f64(sq3(x - fx, y - fy, z - fz) + eps2);
+          acc = (target && qf != q) ? acc + tf : acc;
+        }
       }
       v = c.skip;
     } else {
@@ -428,6 +471,8 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   uint32_t *v0, *v1, *cell;  // cell: each element's cell at the current depth (r_max pass)
   double* pz;
   BhRec* R;
+  float* pf;  // FP32 sorted positions (mixed form)
+  const bool f32 = ctx.p.prec == LIBHALO_PREC_MIXED;
   MTree t;
   void* rtmp;
   carve2(ctx, [&](Arena& A) {
@@ -440,6 +485,7 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
     cell = A.take<uint32_t>(E + 1);
     mtree_take(A, t, cap, B + 1);
     R = A.take<BhRec>(cap + 1);  // the walk reads one record ahead
+    pf = f32 ? A.take<float>(3ull * (E + 1)) : nullptr;
     rmx = A.take<unsigned long long>(cap);
     rtmp = A.take<char>(radix_tmp_bytes(E + 1));
   });
@@ -456,7 +502,7 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   mtree_build(t, f ? k1 : k0, w.L.eoff, w.L.nel, B, kLeaf, kMaxDepth, hb + 2, s);
   double* px = reinterpret_cast<double*>(k0);
   double* py = reinterpret_cast<double*>(k1);
-  k_bh_gather<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, pidx, E, px, py, pz);
+  k_bh_gather<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, pidx, E, px, py, pz, pf);
   const uint32_t T = t.NN;
   for (int d = (int)t.lev.size() - 2; d >= 0; --d) {
     const uint32_t nu = t.lev[d + 1] - t.lev[d];
@@ -475,9 +521,15 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   HALO_HIP(hipMemcpyAsync(hb + 4, w.cnt + 3, 4, hipMemcpyDeviceToHost, s));
   HALO_HIP(hipStreamSynchronize(s));
   const uint32_t nwave = hb[4];
-  HALO_PROF(ctx, "k_bh_walk", s,
-            k_bh_walk<<<blocks_for((int64_t)nwave * 64, TB), TB, 0, s>>>(
-                w.L, B, w.pos, nwave, slot, px, py, pz, pidx, R, t.troot, eps2, pacc));
+  const unsigned wg = blocks_for((int64_t)nwave * 64, TB);
+  if (f32)
+    HALO_PROF(ctx, "k_bh_walk", s,
+              k_bh_walk<true><<<wg, TB, 0, s>>>(w.L, B, w.pos, nwave, slot, px, py, pz, pf,
+                                                pidx, R, t.troot, eps2, pacc));
+  else
+    HALO_PROF(ctx, "k_bh_walk", s,
+              k_bh_walk<false><<<wg, TB, 0, s>>>(w.L, B, w.pos, nwave, slot, px, py, pz,
+                                                 nullptr, pidx, R, t.troot, eps2, pacc));
   HALO_HIP(hipStreamSynchronize(s));
 }
 

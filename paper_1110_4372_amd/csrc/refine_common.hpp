@@ -62,7 +62,7 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint
 
 
 // ---- exact tree search for large nodes (grid6d.hip) ----
-constexpr uint32_t kGridMin = 131072; // default: nodes above this size use the tree search
+constexpr uint32_t kGridMin = 32768;  // default: nodes above this size use the tree search
 constexpr uint32_t kGridFloor = 64;   // smallest accepted threshold
 constexpr uint32_t kKdLeaf = 16;      // a tree node of at most this many particles is a leaf
 constexpr int kKdMaxDepth = 64;       // nodes at this depth are leaves whatever their size

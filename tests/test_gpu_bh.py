@@ -74,6 +74,19 @@ def test_tree_theta_to_zero_is_exact(H, orc, c1, c1_oracle):
     np.testing.assert_allclose(to_np(g["phi"])[ins], o["phi"][ins], rtol=1e-11, atol=0)
 
 
+def test_tree_theta_to_zero_mixed(H, orc, c1, c1_oracle):
+    """The mixed form's walk (FP32 distances and reciprocal square roots of the
+    halo-local positions rounded to FP32, FP32 sums per leaf added in FP64)
+    with theta = 1e-12 opens every cell: the direct sum within the FP32 bound
+    of the mixed form's direct-sum tiles."""
+    note("tree potential theta -> 0, mixed form")
+    g = H.Halo(H.params_for_catalog(c1, bh_theta=1e-12, bh_min=500, prec=1)).run_all(
+        H.Particles.from_catalog(c1))
+    o = c1_oracle
+    ins = o["halo_of"] >= 0
+    np.testing.assert_allclose(to_np(g["phi"])[ins], o["phi"][ins], rtol=2e-5, atol=0)
+
+
 def test_tree_with_merger_and_mixed(H, orc):
     """The tree for S(h), the exact merger term beyond it, the mixed form's
     FP64 recheck: the potential stays within theta of the exact one."""
@@ -126,20 +139,21 @@ def test_tree_workspace_placement(H, c1):
         np.testing.assert_array_equal(to_np(unb["n_s"]), to_np(a["unbound"]["n_s"]))
 
 
-def test_tree_large_haloes_c3(H, orc):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tree_large_haloes_c3(H, orc, prec):
     """The 512^3 catalogue at full size with the tree potential (theta = 0.04,
-    haloes of |S(h)| >= 65536): for the three largest tree haloes (the largest
-    near 10^6 particles, trees far deeper than c1's), the potential of 1000
-    sampled own particles lies within theta of the exact direct sum over S(h)
-    that the oracle computes for those particles; the walk's stack never runs
-    out (the call would fail)."""
+    haloes of |S(h)| >= 65536), in the FP64 and the mixed form: for the three
+    largest tree haloes (the largest near 10^6 particles, trees far deeper
+    than c1's), the potential of 1000 sampled own particles lies within theta
+    of the exact direct sum over S(h) that the oracle computes for those
+    particles."""
     import torch
     from paper_1110_4372_amd import synth
-    note("tree potential on the largest 512^3 haloes")
+    note(f"tree potential on the largest 512^3 haloes prec={prec}")
     theta = 0.04
     cat = synth.make_catalog_device("c3", seed=0)
     P = H.Particles.from_catalog(cat)
-    g = H.Halo(H.params_for_catalog(cat, bh_theta=theta)).run_all(P)
+    g = H.Halo(H.params_for_catalog(cat, bh_theta=theta, prec=prec)).run_all(P)
     torch.cuda.synchronize()
     h = {k: to_np(v) for k, v in g["halos"].items()}
     ns = to_np(g["unbound"]["n_s"]).astype(np.int64)

@@ -243,9 +243,9 @@ def test_c4_mixed_matches_fp64(H):
 
 
 def test_c3_single_large_group(H, orc):
-    """A FOF group of the 512^3 catalogue just above the tree threshold (the
-    nodes above it take the tree search of Section 3.2's nearest neighbours and
-    6D FOF), refined alone on the GPU at its real size; the oracle computes the
+    """A FOF group of the 512^3 catalogue of 131072-200000 particles, above the
+    tree threshold (the nodes above it take the tree search of Section 3.2's
+    nearest neighbours and 6D FOF), refined alone on the GPU at its real size; the oracle computes the
     same group's level-0 node (moments, normalised coordinates, every
     nearest-neighbour distance, ell^2) and its 6D FOF components in full, its
     O(n^2) loops split over the host's cores.  The level-0 row, the children
