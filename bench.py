@@ -132,7 +132,7 @@ def timed(ctx, P, steps, warmup, prof=False):
     return sec, out, stage, kp
 
 
-GRID_MIN_DEFAULT = 131072  # the library's tree threshold when grid_min = 0
+GRID_MIN_DEFAULT = 32768   # the library's tree threshold when grid_min = 0
 BH_MIN_DEFAULT = 65536     # the library's smallest tree halo when bh_min = 0
 # FLOP of one evaluation, as counted for the ALU roofline:
 NN_PAIR_FLOP = 17.0   # 6D distance: 6 sub, 1 mul, 5 fma
@@ -621,7 +621,8 @@ def main():
                     help="nodes above this many particles use the 6D tree search "
                          "(0: the library default, or the autotuner's pick with --autotune)")
     ap.add_argument("--autotune", action="store_true",
-                    help="time the grid_min candidates before the run and use the fastest")
+                    help="before the timed steps, pick grid_min (unless given), the pair-unit "
+                         "chunks and the potential unit by timing (paper_1110_4372_amd.autotune)")
     ap.add_argument("--gen", default="auto", choices=["auto", "host", "device"],
                     help="catalogue generator: numpy (host) or torch on the GPU (device); "
                          "auto draws the 512^3 and 1024^3 catalogues on the GPU")
@@ -641,17 +642,17 @@ def main():
     progress(f"catalogue {args.config}: {cat.n} particles")
     prec = H.PREC_FP64 if args.prec == "fp64" else H.PREC_MIXED
     tuned = None
-    if args.grid_min == 0 and args.autotune:
+    base = H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=args.grid_min,
+                                bh_theta=args.bh_theta, bh_min=args.bh_min)
+    if args.autotune:
         # the framework's own tuning step, before (and outside) the timed steps:
-        # refine6d timed at each candidate size bin; results do not depend on it
+        # grid_min, the pair-unit chunks and the potential unit, each timed in turn
         from paper_1110_4372_amd import autotune
-        best, t = autotune.tune_grid_min(
-            H, H.params_for_catalog(cat, mode=H.BATCHED, prec=prec), P, repeats=2)
-        args.grid_min = int(best)
-        tuned = {"grid_min": int(best), "refine_ms": {str(k): v for k, v in t.items()}}
-        progress(f"autotuned grid_min = {best}")
-    ctx = H.Halo(H.params_for_catalog(cat, mode=H.BATCHED, prec=prec, grid_min=args.grid_min,
-                                      bh_theta=args.bh_theta, bh_min=args.bh_min))
+        grid = (args.grid_min,) if args.grid_min > 0 else autotune.CANDIDATES
+        base, tuned = autotune.tune(H, base, P, repeats=2, grid=grid)
+        args.grid_min = base.grid_min
+        progress(f"autotuned: {json.dumps({k: v['pick'] for k, v in tuned.items()})}")
+    ctx = H.Halo(base)
     sec, out, stage, kp = timed(ctx, P, args.steps, args.warmup, prof=True)
     roofline = roofline_report(kp, out, args.steps, prec == H.PREC_FP64, args.grid_min,
                                args.bh_theta, args.bh_min)

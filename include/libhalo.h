@@ -94,8 +94,8 @@ typedef struct {
                                e_recheck (|K| + |phi|) (1e-4) */
   int32_t mode;             /* libhalo_mode */
   int32_t prec;             /* libhalo_prec */
-  int32_t grid_min;         /* nodes with more particles use the exact grid
-                               neighbour search instead of all pairs; 0 = 131072,
+  int32_t grid_min;         /* nodes with more particles use the exact tree
+                               search instead of all pairs; 0 = 32768,
                                else >= 64 (results are identical either way) */
   int32_t ell_subset;       /* 0: ell from every particle's nearest neighbour (exact);
                                m > 0: nodes of more than m particles take it from a
@@ -115,6 +115,17 @@ typedef struct {
   double bh_theta;          /* 0: exact direct sum; > 0: the tree potential of
                                Appendix B, a cell's monopole accepted at distances
                                d >= r_max/2 + sqrt((r_max/2)^2 + sigma^2/theta) */
+  /* Work-unit sizes of the batched kernels, a speed choice (0 picks the
+   * default).  nn_chunk and fof_chunk change no result bit; pot_chunk groups
+   * the potential's partial sums differently, so phi changes at the rounding
+   * level (and a bound flag only inside that band). */
+  int32_t nn_chunk;         /* all-pairs nearest neighbours: smallest j-chunk of a
+                               unit on levels of >= 262144 particles; a multiple of
+                               256 in [256, 4096] (0 = 1024) */
+  int32_t fof_chunk;        /* all-pairs 6D FOF: j particles per unit on those
+                               levels; a multiple of 256 in [256, 16384] (0 = 2048) */
+  int32_t pot_chunk;        /* direct-sum potential: j particles per unit; 1024,
+                               2048 or 4096 (0 = 2048) */
 } libhalo_params;
 
 /* Node table (refine6d output), structure of arrays, capacity `cap` rows.

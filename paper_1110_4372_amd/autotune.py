@@ -1,13 +1,22 @@
-"""Autotuner for the size bin of the 6D neighbour search.
+"""Autotuner of the batched form's size bin and work-unit sizes.
 
-Nodes above `grid_min` particles take the exact tile search; the others the
-symmetric all-pairs pass.  Both give the same node table, so the threshold is
-purely a speed choice, and the best one depends on the catalogue (the share of
-particles in giant nodes).  `tune_grid_min` times the refinement call on the
-caller's particles at each candidate threshold (HIP events on the library's
-stream) and returns the fastest.
+Every knob here is a speed choice:
+  grid_min   nodes above it take the exact tree search of the 6D neighbours,
+             the others the symmetric all-pairs pass (same node table);
+  nn_chunk   smallest j-chunk of an all-pairs nearest-neighbour unit on large
+             levels (same distances);
+  fof_chunk  j particles of an all-pairs 6D FOF unit on large levels (same
+             components);
+  pot_chunk  j particles of a direct-sum potential unit, one of the compiled
+             instantiations (the partial sums are grouped differently: phi
+             agrees to rounding).
+The best values depend on the catalogue (the share of particles in giant
+nodes and haloes).  `tune` times the refinement call (HIP events on the
+library's stream) at each candidate of the first three knobs in turn, keeping
+the best of each, then the unbinding call at each pot_chunk, and returns the
+picks with every timing.
 
-    python -m paper_1110_4372_amd.autotune --config c3 --gen device
+    python -m paper_1110_4372_amd.autotune --config c3
 """
 from __future__ import annotations
 
@@ -15,53 +24,92 @@ import argparse
 import json
 import sys
 
-CANDIDATES = (32768, 65536, 131072, 262144, 524288)
+CANDIDATES = (8192, 16384, 32768, 65536, 131072)
+NN_CHUNKS = (512, 1024, 2048)
+FOF_CHUNKS = (1024, 2048, 4096)
+POT_CHUNKS = (1024, 2048, 4096)
 
 
 def choose(timings: dict) -> int:
-    """The candidate with the least time; ties go to the larger threshold (the
-    all-pairs pass, which needs no sample or sort)."""
+    """The candidate with the least time; ties go to the larger value (the
+    all-pairs pass, which needs no tree build; the fewer, larger units)."""
     if not timings:
         raise ValueError("no timings")
     return min(timings, key=lambda g: (timings[g], -g))
 
 
+def _time(call, repeats):
+    import torch
+    call()  # warm-up: workspace and code objects
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(repeats):
+        call()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / repeats
+
+
+def tune_knob(H, params, P, knob, candidates, stage_inputs, repeats: int = 2):
+    """Times one stage at each candidate value of `knob` (a Params field) and
+    returns (best value, {value: ms}).  stage_inputs(ctx) -> the stage call."""
+    from dataclasses import replace
+    timings = {}
+    for g in candidates:
+        ctx = H.Halo(replace(params, **{knob: int(g)}))
+        timings[int(g)] = _time(stage_inputs(ctx), repeats)
+    return choose(timings), timings
+
+
 def tune_grid_min(H, params, P, candidates=CANDIDATES, repeats: int = 2):
     """Times libhalo_refine6d at each candidate threshold (after one warm-up
     call per context) and returns (best threshold, {threshold: ms})."""
-    import torch
+    fof = H.Halo(params).fof3d(P)
+    return tune_knob(H, params, P, "grid_min", candidates,
+                     lambda ctx: (lambda: ctx.refine6d(P, fof)), repeats)
+
+
+def tune(H, params, P, repeats: int = 2, grid=CANDIDATES, nn=NN_CHUNKS, fof_c=FOF_CHUNKS,
+         pot=POT_CHUNKS):
+    """Coordinate search over grid_min, nn_chunk, fof_chunk (refinement time)
+    and pot_chunk (unbinding time).  Returns (tuned Params, report)."""
     from dataclasses import replace
     ctx0 = H.Halo(params)
     fof = ctx0.fof3d(P)
-    timings = {}
-    for g in candidates:
-        ctx = H.Halo(replace(params, grid_min=int(g)))
-        ctx.refine6d(P, fof)  # warm-up: workspace and code objects
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(repeats):
-            ctx.refine6d(P, fof)
-        ev1.record()
-        torch.cuda.synchronize()
-        timings[int(g)] = ev0.elapsed_time(ev1) / repeats
-    return choose(timings), timings
+    refine = lambda ctx: (lambda: ctx.refine6d(P, fof))  # noqa: E731
+    report = {}
+    p = params
+    for knob, cands in (("grid_min", grid), ("nn_chunk", nn), ("fof_chunk", fof_c)):
+        best, t = tune_knob(H, p, P, knob, cands, refine, repeats)
+        p = replace(p, **{knob: best})
+        report[knob] = {"pick": best, "refine_ms": {str(k): v for k, v in t.items()}}
+    nodes, deep = H.Halo(p).refine6d(P, fof)
+    halos, hof = H.Halo(p).assign(P, nodes, deep)
+    unbind = lambda ctx: (lambda: ctx.unbind(P, halos, hof, want_phi=False))  # noqa: E731
+    best, t = tune_knob(H, p, P, "pot_chunk", pot, unbind, repeats)
+    p = replace(p, pot_chunk=best)
+    report["pot_chunk"] = {"pick": best, "unbind_ms": {str(k): v for k, v in t.items()}}
+    return p, report
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--gen", default="host", choices=["host", "device"])
+    ap.add_argument("--gen", default="auto", choices=["auto", "host", "device"])
+    ap.add_argument("--prec", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--repeats", type=int, default=2)
     args = ap.parse_args()
     from paper_1110_4372_amd import halo as H
     from paper_1110_4372_amd import synth
-    cat = (synth.make_catalog_device(args.config, seed=0) if args.gen == "device"
+    gen = args.gen if args.gen != "auto" else ("device" if args.config in ("c3", "c5")
+                                               else "host")
+    cat = (synth.make_catalog_device(args.config, seed=0) if gen == "device"
            else synth.make_catalog(args.config, seed=0))
     P = H.Particles.from_catalog(cat)
-    best, t = tune_grid_min(H, H.params_for_catalog(cat), P, repeats=args.repeats)
-    print(json.dumps({"config": args.config, "grid_min": best,
-                      "refine_ms": {str(k): v for k, v in t.items()}}))
+    prec = H.PREC_FP64 if args.prec == "fp64" else H.PREC_MIXED
+    _, rep = tune(H, H.params_for_catalog(cat, prec=prec), P, repeats=args.repeats)
+    print(json.dumps({"config": args.config, **rep}))
     return 0
 
 

@@ -123,6 +123,13 @@ static std::string validate(const libhalo_params& p) {
   if (p.prec != LIBHALO_PREC_FP64 && p.prec != LIBHALO_PREC_MIXED) return "unknown prec";
   if (p.grid_min != 0 && p.grid_min < 64) return "grid_min must be 0 or >= 64";
   if (p.ell_subset < 0) return "ell_subset must be >= 0";
+  if (p.nn_chunk != 0 && (p.nn_chunk < 256 || p.nn_chunk > 4096 || p.nn_chunk % 256 != 0))
+    return "nn_chunk must be 0 or a multiple of 256 in [256, 4096]";
+  if (p.fof_chunk != 0 &&
+      (p.fof_chunk < 256 || p.fof_chunk > 16384 || p.fof_chunk % 256 != 0))
+    return "fof_chunk must be 0 or a multiple of 256 in [256, 16384]";
+  if (p.pot_chunk != 0 && p.pot_chunk != 1024 && p.pot_chunk != 2048 && p.pot_chunk != 4096)
+    return "pot_chunk must be 0, 1024, 2048 or 4096";
   return "";
 }
 

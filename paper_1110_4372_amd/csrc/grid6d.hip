@@ -196,8 +196,13 @@ __device__ __forceinline__ float point_gap2(const float* a, const KdNode& r) {
 // persistent and a lane whose walk ends takes the next query at once: each
 // wave takes chunks of kWalkChunk consecutive points (neighbours on the Morton
 // curve) from a queue counter and hands them out in order to its idle lanes.
-// The kernel ends when the queue is drained and every lane is idle; every
-// walk ends because u only grows and is bounded by its tree's end.
+// The points are split into eight contiguous ranges with a queue each, one
+// per XCD (blocks are dispatched to the XCDs round robin, so block b runs on
+// XCD b mod 8): an XCD's waves walk neighbouring points, whose tree records
+// and leaves its L2 then holds.  A wave whose range is drained takes chunks
+// from the next ranges in turn.  The kernel ends when all eight are drained
+// and every lane is idle; every walk ends because u only grows and is
+// bounded by its tree's end.
 template <int MODE>
 __global__ void __launch_bounds__(kWalkTB)
     k_kd_walk(const KdNode* __restrict__ T, const float* __restrict__ pt,
@@ -207,7 +212,8 @@ __global__ void __launch_bounds__(kWalkTB)
               uint32_t* par, uint32_t* queue, unsigned long long* work) {
   const uint32_t lane = threadIdx.x & 63u;
   const unsigned long long below = (1ull << lane) - 1ull;
-  uint32_t cbase = 0, cnext = kWalkChunk;  // the wave's chunk and its next unissued point
+  uint32_t cbase = 0, cend = 0, cnext = kWalkChunk;  // the wave's chunk [cbase, cend)
+  uint32_t qx = blockIdx.x & 7u, tried = 0;           // current range, ranges drained
   bool drained = false;
   // this lane's query
   bool active = false, have = false;
@@ -222,17 +228,22 @@ __global__ void __launch_bounds__(kWalkTB)
       const unsigned long long idle = __ballot(!active);
       if (idle == 0) break;
       if (cnext >= kWalkChunk) {
+        // range qx holds the points [MB qx / 8, MB (qx + 1) / 8)
+        const uint32_t r0 = (uint32_t)(((unsigned long long)MB * qx) >> 3);
+        const uint32_t r1 = (uint32_t)(((unsigned long long)MB * (qx + 1u)) >> 3);
         uint32_t c = 0;
-        if (lane == 0) c = atomicAdd(queue, kWalkChunk);
+        if (lane == 0) c = atomicAdd(queue + 16u * qx, kWalkChunk);
         c = __shfl(c, 0);
-        if (c >= MB) {
-          drained = true;
-          break;
+        if (c >= r1 - r0) {  // this range is drained: the next one
+          qx = (qx + 1u) & 7u;
+          if (++tried == 8u) drained = true;
+          continue;
         }
-        cbase = c;
+        cbase = r0 + c;
+        cend = min(cbase + kWalkChunk, r1);
         cnext = 0;
       }
-      const uint32_t left = MB - cbase > cnext ? MB - cbase - cnext : 0u;
+      const uint32_t left = cend - cbase > cnext ? cend - cbase - cnext : 0u;
       const uint32_t avail = min(kWalkChunk - cnext, left);
       const uint32_t rank = (uint32_t)__popcll(idle & below);
       if (!active && rank < avail) {
@@ -349,7 +360,7 @@ void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax) {
   g.pb = A.take<uint32_t>((size_t)M + 2);
   g.leafof = A.take<uint32_t>((size_t)M + 2);
   g.cnt = A.take<uint32_t>(16);
-  g.queue = A.take<uint32_t>(64);
+  g.queue = A.take<uint32_t>(128);
   g.rtmp = A.take<char>(radix_tmp_bytes((int64_t)M + 2));
   g.stmp = A.take<uint32_t>(scan_tmp_elems<uint32_t>((int64_t)M + Kmax + 4));
 }
@@ -398,7 +409,7 @@ uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint3
 void grid_nn(GridBufs& g, NodeScratch sc, uint32_t* D, unsigned long long* work,
              hipStream_t s) {
   if (g.NB == 0 || g.MB == 0) return;
-  k_fill_u32<<<1, 64, 0, s>>>(g.queue, 2, 0u);
+  k_fill_u32<<<1, 128, 0, s>>>(g.queue, 128, 0u);
   k_kd_walk<0><<<walk_grid(g.MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof,
                                                    g.troot, g.MB, g.gnode, sc, D, nullptr,
                                                    g.queue, work);
@@ -407,7 +418,7 @@ void grid_nn(GridBufs& g, NodeScratch sc, uint32_t* D, unsigned long long* work,
 void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par,
               unsigned long long* work, hipStream_t s) {
   if (g.NB == 0 || g.MB == 0) return;
-  k_fill_u32<<<1, 64, 0, s>>>(g.queue, 2, 0u);
+  k_fill_u32<<<1, 128, 0, s>>>(g.queue, 128, 0u);
   k_kd_walk<1><<<walk_grid(g.MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof,
                                                    g.troot, g.MB, g.gnode, sc,
                                                    const_cast<uint32_t*>(D), par, g.queue,

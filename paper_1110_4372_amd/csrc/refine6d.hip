@@ -1024,8 +1024,10 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
         kPersist, std::max<uint64_t>(256, 4 * (((uint64_t)Mi + 255) / 256)));
     // pair-unit chunks: shorter on small levels
     const bool small_level = Mi < kSmallLevel;
-    const uint32_t nnj = small_level ? kNNJSmall : (uint32_t)kNNJ;
-    const uint32_t pj = small_level ? kPairJSmall : (uint32_t)kPairJ;
+    const uint32_t nnj = small_level ? kNNJSmall
+                                     : (P.nn_chunk > 0 ? (uint32_t)P.nn_chunk : (uint32_t)kNNJ);
+    const uint32_t pj = small_level ? kPairJSmall
+                                    : (P.fof_chunk > 0 ? (uint32_t)P.fof_chunk : (uint32_t)kPairJ);
     const int level0 = level == 0;
     k_zero_node_scratch<<<blocks_for(K, TB), TB, 0, s>>>(sc, K);
     k_mom_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, K, sc.wmom);

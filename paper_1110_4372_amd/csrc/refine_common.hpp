@@ -84,7 +84,7 @@ struct __align__(16) KdNode {
 struct GridBufs {
   uint32_t *nb_rank, *gnode, *pstart, *gcount;
   uint32_t *flag, *pos, *v0, *v1, *cnt, *stmp, *leafof;
-  uint32_t* queue;   // work-queue counter of the walks (zeroed before each)
+  uint32_t* queue;   // the walks' eight work-queue counters, 64 B apart (zeroed before each)
   unsigned long long *k0, *k1;
   float* pt;         // MB points in sorted order, six normalised coordinates each
   uint32_t *pm, *pb; // their positions in the level arrays and their grid nodes

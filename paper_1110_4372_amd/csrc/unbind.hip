@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <type_traits>
+
 #include "lanes.hpp"
 #include "bh.hpp"
 #include "primitives.hpp"
@@ -194,7 +196,8 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint
 // ------------------------------------------------------------ potentials --
 // Work unit: kPotI own particles of a halo (a block of four wavefronts; each
 // lane holds kPotK particles i = t0 + lane + 64 k of its wave's tile of
-// kPotTile) against one j-chunk of kPotJ particles of its S(h).  S(h) starts
+// kPotTile) against one j-chunk of J particles of its S(h) (J one of the
+// instantiated chunk sizes, kPotJ by default; the libhalo_params pot_chunk).  S(h) starts
 // with the halo's own particles, followed by its subhaloes' S.  A pair of two
 // own particles is evaluated once: the wave owning the lower tile adds the
 // term to its particle's sum and, summed over the wave's kPotTile particles,
@@ -207,7 +210,7 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint
 constexpr uint32_t kPotK = 4;
 constexpr uint32_t kPotTile = 64 * kPotK;  // particles per wave
 constexpr uint32_t kPotI = 4 * kPotTile;   // particles per unit
-constexpr uint32_t kPotJ = 2048;           // a multiple of kPotTile
+constexpr uint32_t kPotJ = 2048;           // default j-chunk, a multiple of kPotTile
 constexpr int kPotFrac = 32;               // fractional bits of the accumulators
 constexpr double kFar = 1e150;             // coordinate of a lane slot without a particle
 
@@ -226,12 +229,25 @@ __device__ __forceinline__ I128 pot_fixed(double v) {
   return r;
 }
 
+template <uint32_t J>
 __host__ __device__ __forceinline__ uint32_t pot_units(uint32_t nown, uint32_t ns) {
-  return ((nown + kPotI - 1u) / kPotI) * ((ns + kPotJ - 1u) / kPotJ);
+  return ((nown + kPotI - 1u) / kPotI) * ((ns + J - 1u) / J);
+}
+
+// Calls f with the j-chunk size of pot_chunk (0: kPotJ) as a type.
+template <class F>
+void with_pot_chunk(int32_t pc, F&& f) {
+  if (pc == 1024)
+    f(std::integral_constant<uint32_t, 1024>{});
+  else if (pc == 4096)
+    f(std::integral_constant<uint32_t, 4096>{});
+  else
+    f(std::integral_constant<uint32_t, kPotJ>{});
 }
 
 // Per kept halo: the unit count, and a sort key ordering halos by their cost
 // (~ nown |S(h)|), largest first.
+template <uint32_t J>
 __global__ void k_pot_counts(const libhalo_halos h, uint32_t S, const uint32_t* nS,
                              double bh_theta, uint32_t bh_min, uint32_t* ucnt, uint32_t* key,
                              uint32_t* val) {
@@ -242,7 +258,7 @@ __global__ void k_pot_counts(const libhalo_halos h, uint32_t S, const uint32_t* 
   // haloes taking the tree potential get no direct-sum units
   const bool on = kept && nown > 0 && !bh_takes(kept, nown, ns, bh_theta, bh_min);
   const unsigned long long cost = ((unsigned long long)nown * ns) >> 16;
-  ucnt[s] = on ? pot_units(nown, ns) : 0u;
+  ucnt[s] = on ? pot_units<J>(nown, ns) : 0u;
   key[s] = on ? ~(uint32_t)min(cost, 0xFFFFFFFEull) : 0xFFFFFFFFu;
   val[s] = s;
 }
@@ -259,6 +275,7 @@ struct PotUnit {
 
 // Decodes unit u: the units of halo order[k] are [uoff[k], uoff[k+1]),
 // chunk-major so that concurrent blocks share a j-chunk.
+template <uint32_t J>
 __device__ __forceinline__ PotUnit pot_unit(const libhalo_halos& h, const uint32_t* order,
                                             const uint32_t* uoff, uint32_t K,
                                             const uint32_t* slot, const uint32_t* nS,
@@ -273,8 +290,8 @@ __device__ __forceinline__ PotUnit pot_unit(const libhalo_halos& h, const uint32
   const uint32_t nb = (r.nown + kPotI - 1u) / kPotI;
   const uint32_t c = local / nb;
   r.b = local - c * nb;
-  r.j0 = c * kPotJ;
-  r.j1 = min(r.j0 + kPotJ, r.ns);
+  r.j0 = c * J;
+  r.j1 = min(r.j0 + J, r.ns);
   return r;
 }
 
@@ -505,6 +522,7 @@ __device__ __forceinline__ void pot_sym_f64(const double* __restrict__ ux,
 }
 
 // FP64 form.
+template <uint32_t J>
 __global__ void __launch_bounds__(TB, 4)
     k_potential_f64(const double* __restrict__ ux, const double* __restrict__ uy,
                     const double* __restrict__ uz, const libhalo_halos h,
@@ -512,12 +530,12 @@ __global__ void __launch_bounds__(TB, 4)
                     uint32_t K, const uint32_t* __restrict__ slot,
                     const uint32_t* __restrict__ nS, uint32_t u0, uint32_t u1, uint32_t* ctr,
                     double eps2, I128* __restrict__ acc) {
-  __shared__ unsigned long long jlo[kPotJ], jhi[kPotJ];
+  __shared__ unsigned long long jlo[J], jhi[J];
   __shared__ uint32_t su;
   for (uint32_t t = 0;; ++t) {
     const uint32_t u = pot_next(ctr, u0, t, &su);
     if (u >= u1) break;
-    const PotUnit w = pot_unit(h, order, uoff, K, slot, nS, u);
+    const PotUnit w = pot_unit<J>(h, order, uoff, K, slot, nS, u);
     const uint32_t ib = w.b * kPotI;
     const uint32_t je = min(w.j1, w.nown);  // end of the chunk's own part
     if (w.j1 <= ib && w.j1 <= w.nown) continue;  // pairs taken from the other side
@@ -697,6 +715,7 @@ __global__ void k_rel_f32(const double* ux, const double* uy, const double* uz,
   fz[q] = (float)(uz[q] - uz[o]);
 }
 
+template <uint32_t J>
 __global__ void __launch_bounds__(TB, 4)
     k_potential_f32(const float* __restrict__ fx, const float* __restrict__ fy,
                     const float* __restrict__ fz, const libhalo_halos h,
@@ -704,12 +723,12 @@ __global__ void __launch_bounds__(TB, 4)
                     uint32_t K, const uint32_t* __restrict__ slot,
                     const uint32_t* __restrict__ nS, uint32_t u0, uint32_t u1, uint32_t* ctr,
                     float eps2, I128* __restrict__ acc) {
-  __shared__ unsigned long long jlo[kPotJ], jhi[kPotJ];
+  __shared__ unsigned long long jlo[J], jhi[J];
   __shared__ uint32_t su;
   for (uint32_t t = 0;; ++t) {
     const uint32_t u = pot_next(ctr, u0, t, &su);
     if (u >= u1) break;
-    const PotUnit w = pot_unit(h, order, uoff, K, slot, nS, u);
+    const PotUnit w = pot_unit<J>(h, order, uoff, K, slot, nS, u);
     const uint32_t ib = w.b * kPotI;
     const uint32_t je = min(w.j1, w.nown);
     if (w.j1 <= ib && w.j1 <= w.nown) continue;
@@ -1085,8 +1104,10 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
   // potentials: work units ordered largest first, one partial per particle
   // and j-chunk, partials added in chunk order
   const uint32_t bh_min = P.bh_min > 0 ? (uint32_t)P.bh_min : 65536u;
-  k_pot_counts<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, P.bh_theta, bh_min, w.ucnt, w.pk0,
-                                                w.pv0);
+  with_pot_chunk(P.pot_chunk, [&](auto Jc) {
+    k_pot_counts<decltype(Jc)::value><<<blocks_for(S, TB), TB, 0, s>>>(
+        h, S, w.nS, P.bh_theta, bh_min, w.ucnt, w.pk0, w.pv0);
+  });
   const bool fo = radix_sort_pairs<uint32_t>(w.pk0, w.pv0, w.pk1, w.pv1, S, 32, w.rtmp, s);
   const uint32_t* order = fo ? w.pv1 : w.pv0;
   k_gather_u32<<<blocks_for(S, TB), TB, 0, s>>>(w.ucnt, order, S, w.uoff);
@@ -1098,15 +1119,19 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       k_rel_f32<<<blocks_for(m, TB), TB, 0, s>>>(w.ux, w.uy, w.uz, h, w.slot, w.lhalo, m, w.fx,
                                                  w.fy, w.fz);
     auto launch = [&](uint32_t u0, uint32_t u1, uint32_t* ctr, unsigned grid) {
-      if (mixed)
-        HALO_PROF(ctx, "k_potential_f32", s,
-                  k_potential_f32<<<grid, TB, 0, s>>>(w.fx, w.fy, w.fz, h, order, w.uoff, S,
-                                                      w.slot, w.nS, u0, u1, ctr, (float)eps2,
-                                                      w.pacc));
-      else
-        HALO_PROF(ctx, "k_potential_f64", s,
-                  k_potential_f64<<<grid, TB, 0, s>>>(w.ux, w.uy, w.uz, h, order, w.uoff, S,
-                                                      w.slot, w.nS, u0, u1, ctr, eps2, w.pacc));
+      with_pot_chunk(P.pot_chunk, [&](auto Jc) {
+        constexpr uint32_t J = decltype(Jc)::value;
+        if (mixed)
+          HALO_PROF(ctx, "k_potential_f32", s,
+                    k_potential_f32<J><<<grid, TB, 0, s>>>(w.fx, w.fy, w.fz, h, order, w.uoff,
+                                                           S, w.slot, w.nS, u0, u1, ctr,
+                                                           (float)eps2, w.pacc));
+        else
+          HALO_PROF(ctx, "k_potential_f64", s,
+                    k_potential_f64<J><<<grid, TB, 0, s>>>(w.ux, w.uy, w.uz, h, order, w.uoff,
+                                                           S, w.slot, w.nS, u0, u1, ctr, eps2,
+                                                           w.pacc));
+      });
     };
     if (plain) {
       // one launch per halo, in halo order, each over that halo's units

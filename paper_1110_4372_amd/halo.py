@@ -36,7 +36,8 @@ class CParams(C.Structure):
                 ("unbound_threshold", C.c_double), ("e_recheck", C.c_double),
                 ("mode", C.c_int32), ("prec", C.c_int32), ("grid_min", C.c_int32),
                 ("ell_subset", C.c_int32), ("major_merger", C.c_double),
-                ("fof_dense", C.c_int32), ("bh_min", C.c_int32), ("bh_theta", C.c_double)]
+                ("fof_dense", C.c_int32), ("bh_min", C.c_int32), ("bh_theta", C.c_double),
+                ("nn_chunk", C.c_int32), ("fof_chunk", C.c_int32), ("pot_chunk", C.c_int32)]
 
 
 @dataclasses.dataclass
@@ -64,6 +65,10 @@ class Params:
     fof_dense: int = 0
     bh_min: int = 0
     bh_theta: float = 0.0
+    # work-unit sizes of the batched kernels (0 = library default; speed only)
+    nn_chunk: int = 0
+    fof_chunk: int = 0
+    pot_chunk: int = 0
 
     def c(self) -> CParams:
         return CParams(self.box, self.b, self.f, self.min_members, self.max_levels,
@@ -71,7 +76,7 @@ class Params:
                        self.softening, self.core_frac, self.unbound_threshold,
                        self.e_recheck, self.mode, self.prec, self.grid_min,
                        self.ell_subset, self.major_merger, self.fof_dense, self.bh_min,
-                       self.bh_theta)
+                       self.bh_theta, self.nn_chunk, self.fof_chunk, self.pot_chunk)
 
 
 NODE_FIELDS = [("parent", torch.int32), ("level", torch.int32), ("first_child", torch.int32),
