@@ -132,7 +132,9 @@ def timed(ctx, P, steps, warmup, prof=False):
     return sec, out, stage, kp
 
 
-GRID_MIN_DEFAULT = 32768   # the library's tree threshold when grid_min = 0
+# the library's tree threshold when grid_min = 0: 32768 on levels of at least
+# 2^23 particles, 131072 on smaller ones
+GRID_MIN_LARGE, GRID_MIN_SMALL, GRID_LEVEL = 32768, 131072, 1 << 23
 BH_MIN_DEFAULT = 65536     # the library's smallest tree halo when bh_min = 0
 # FLOP of one evaluation, as counted for the ALU roofline:
 NN_PAIR_FLOP = 17.0   # 6D distance: 6 sub, 1 mul, 5 fma
@@ -153,9 +155,14 @@ def pair_work(out, grid_min, bh_theta, bh_min):
     tree on, those with |S(h)| < bh_min)."""
     import numpy as np
     fof, nodes, halos, halo_of, unb = out[:5]
-    gmin = grid_min if grid_min > 0 else GRID_MIN_DEFAULT
     cnt = nodes["count"].cpu().numpy().astype(np.float64)
     flags = nodes["flags"].cpu().numpy()
+    if grid_min > 0:
+        gmin = grid_min
+    else:  # per node, from its level's particle count
+        lev = nodes["level"].cpu().numpy().astype(np.int64)
+        tot = np.bincount(lev, weights=cnt)
+        gmin = np.where(tot[lev] >= GRID_LEVEL, GRID_MIN_LARGE, GRID_MIN_SMALL)
     on = ((flags & 2) == 0) & (cnt <= gmin)
     nn_flops = NN_PAIR_FLOP * float(np.sum(cnt[on] * (cnt[on] - 1.0) / 2.0))
     h = {k: v.cpu().numpy() for k, v in halos.items()}

@@ -95,8 +95,9 @@ typedef struct {
   int32_t mode;             /* libhalo_mode */
   int32_t prec;             /* libhalo_prec */
   int32_t grid_min;         /* nodes with more particles use the exact tree
-                               search instead of all pairs; 0 = 32768,
-                               else >= 64 (results are identical either way) */
+                               search instead of all pairs; 0 = 32768 on levels of
+                               >= 2^23 particles and 131072 on smaller ones, else
+                               >= 64 (results are identical either way) */
   int32_t ell_subset;       /* 0: ell from every particle's nearest neighbour (exact);
                                m > 0: nodes of more than m particles take it from a
                                subset drawn with probability m / n per particle

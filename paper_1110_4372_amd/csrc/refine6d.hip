@@ -1066,7 +1066,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     k_iota<<<blocks_for(Mi, TB), TB, 0, s>>>(par, Mi);
     HALO_PROF(ctx, "grid_build", s,
               grid_build(gb, xi, S, nd, K, lnode, Mi, M, sc, rd.h + 8, s,
-                         P.grid_min > 0 ? (uint32_t)P.grid_min : kGridMin));
+                         P.grid_min > 0 ? (uint32_t)P.grid_min : default_grid_min(Mi)));
     HALO_PROF(ctx, "k_kd_walk_nn", s, grid_nn(gb, sc, D, ctx.work_counters(), s));
     k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, nnj,
                                                    sc.wpair);
