@@ -27,22 +27,29 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
-# HBM bytes per dispatch of the dominant kernels, from the committed rocprofv3
-# FETCH_SIZE / WRITE_SIZE runs (profiles/c2_hbm_traffic.md, scaled by a plain
-# copy of known size).  Reported only while the kernel's source file is the
-# one that was measured.
+# Fabric bytes per dispatch of the hot kernels on the 1024^3 workload, from the
+# committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (profiles/c5_hbm_traffic.md,
+# scaled by a plain copy of known size: fetch x2, write x1).  Reported only for
+# that workload and while the kernel's source file is the one that was measured.
+TRAFFIC_WORKLOAD = "c5"
 MEASURED_TRAFFIC = {
-    "k_potential_f64": {"bytes": 436.1e6, "src": "paper_1110_4372_amd/csrc/unbind.hip",
-                        "sha1": "f429ab878fea3c10a77487c3dd41803290c1dcab"},
-    "k_nn": {"bytes": 88.8e6, "src": "paper_1110_4372_amd/csrc/refine6d.hip",
-             "sha1": "6bd7a03261fa2ac406100f0bea80070a6d21f0f6"},
+    "k_kd_walk_nn": {"bytes": 834.96e9, "src": "paper_1110_4372_amd/csrc/grid6d.hip",
+                     "sha1": "de973f44a14e221b464ec6426ead62ea464d6851"},
+    "k_kd_walk_fof": {"bytes": 847.89e9, "src": "paper_1110_4372_amd/csrc/grid6d.hip",
+                      "sha1": "de973f44a14e221b464ec6426ead62ea464d6851"},
+    "k_bh_walk": {"bytes": 1197.01e9, "src": "paper_1110_4372_amd/csrc/bh.hip",
+                  "sha1": "7bb5498ec9e5e22ab06838879807dacf5838cc9c"},
+    "k_nn": {"bytes": 12.08e9, "src": "paper_1110_4372_amd/csrc/refine6d.hip",
+             "sha1": "7a5e971ed55d71692fce27afab6d5a05f91294d8"},
+    "k_potential_f32": {"bytes": 79.05e9, "src": "paper_1110_4372_amd/csrc/unbind.hip",
+                        "sha1": "6b882e5ae109c187bb5620ac38b6ce24a9d6d9c7"},
 }
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     import hashlib
     rec = MEASURED_TRAFFIC.get(kernel)
-    if rec is None:
+    if rec is None or workload != TRAFFIC_WORKLOAD:
         return None
     path = os.path.join(ROOT, rec["src"])
     if not os.path.exists(path):
@@ -176,7 +183,7 @@ def pair_work(out, grid_min, bh_theta, bh_min):
     return nn_flops, pot_flops
 
 
-def roofline_report(kp, out, steps, prec_fp64, grid_min, bh_theta, bh_min):
+def roofline_report(kp, out, steps, prec_fp64, grid_min, bh_theta, bh_min, workload):
     """The roofline object of the dominant kernel of the timed steps (the hot
     kernel with the largest device time).  All-pairs kernels: algorithmic
     FLOP (pair_work) per launch over the average launch time, against the
@@ -205,7 +212,7 @@ def roofline_report(kp, out, steps, prec_fp64, grid_min, bh_theta, bh_min):
         flops, peak, what = figures[dom]
         achieved = flops / (t_ms * 1e-3) / 1e12
         rec.update({"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                    "frac": achieved / peak, "traffic": measured_traffic(dom),
+                    "frac": achieved / peak, "traffic": measured_traffic(dom, workload),
                     "work": what})
     else:
         rec.update({"bound": "alu", "achieved": None, "peak": FP32_PEAK_TFLOPS,
@@ -662,7 +669,7 @@ def main():
     ctx = H.Halo(base)
     sec, out, stage, kp = timed(ctx, P, args.steps, args.warmup, prof=True)
     roofline = roofline_report(kp, out, args.steps, prec == H.PREC_FP64, args.grid_min,
-                               args.bh_theta, args.bh_min)
+                               args.bh_theta, args.bh_min, args.config)
     passes = pass_report(cat.n, out, stage)
     counts = {"n_groups": int(out[0]["n_groups"]), "n_nodes": int(out[1]["parent"].shape[0]),
               "n_halos": int(out[2]["seed_node"].shape[0])}
