@@ -274,6 +274,8 @@ __global__ void __launch_bounds__(kWalkTB)
     if (!__any(active)) break;
     if (have) {
       neval += hi > lo ? hi - lo : 0u;
+      // unrolled so that several points' loads are in flight together
+#pragma unroll 4
       for (uint32_t j = lo; j < hi; ++j) {
         const float* pj = pt + 6ull * j;
         const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], pj[0], pj[1], pj[2], pj[3],

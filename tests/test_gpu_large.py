@@ -199,6 +199,35 @@ def test_c5_full_size_subcubes(H, orc):
     assert g >= 20 and h >= 20 and pr >= 20
 
 
+def test_c3_plain_equals_batched(H):
+    """The 512^3 catalogue at full size in the plain form (one launch sequence
+    per node and per halo) and the batched form (every node of a level and
+    every halo per launch, persistent grids, work queues): every output of the
+    whole path -- labels, node table, deepest node, halo table, halo_of, bound
+    flags, phi and the properties -- is the same bit for bit (the sums are
+    exact fixed-point, so the schedule cannot change them)."""
+    from paper_1110_4372_amd import synth
+    note("c3 full size, plain == batched")
+    cat = synth.make_catalog_device("c3", seed=0)
+    P = H.Particles.from_catalog(cat)
+    out = {}
+    for mode in (H.BATCHED, H.PLAIN):
+        r = H.Halo(H.params_for_catalog(cat, mode=mode)).run_all(P)
+        torch.cuda.synchronize()
+        out[mode] = {"label": to_np(r["fof"]["label"]), "deepest": to_np(r["deepest"]),
+                     "halo_of": to_np(r["halo_of"]), "bound": to_np(r["bound"]),
+                     "phi": to_np(r["phi"]),
+                     **{"node_" + k: to_np(v) for k, v in r["nodes"].items()},
+                     **{"halo_" + k: to_np(v) for k, v in r["halos"].items()},
+                     **{"prop_" + k: to_np(v) for k, v in r["props"].items()}}
+        del r
+    a, b = out[H.BATCHED], out[H.PLAIN]
+    assert a.keys() == b.keys()
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    print(f"{a['node_count'].shape[0]} nodes, {a['halo_seed_node'].shape[0]} halo rows identical")
+
+
 def test_c4_mixed_matches_fp64(H):
     """256^3 plus a 5e6-particle cluster at full size: the mixed-precision form
     (FP32 potential tiles, FP64 recheck of energies within 1e-4 of zero) against
