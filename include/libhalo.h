@@ -127,6 +127,11 @@ typedef struct {
                                levels; a multiple of 256 in [256, 16384] (0 = 2048) */
   int32_t pot_chunk;        /* direct-sum potential: j particles per unit; 1024,
                                2048 or 4096 (0 = 2048) */
+  int32_t kd_leaf;          /* most particles of a leaf of the 6D search trees,
+                               in [4, 64] (0 = 16); no result bit depends on it */
+  int32_t bh_leaf;          /* most particles of a leaf of the tree potential's
+                               trees, in [4, 64] (0 = 16); changes which cells are
+                               accepted, so phi changes within the theta bound */
 } libhalo_params;
 
 /* Node table (refine6d output), structure of arrays, capacity `cap` rows.

@@ -9,12 +9,15 @@ Every knob here is a speed choice:
              components);
   pot_chunk  j particles of a direct-sum potential unit, one of the compiled
              instantiations (the partial sums are grouped differently: phi
-             agrees to rounding).
+             agrees to rounding);
+  kd_leaf    most points of a leaf of the 6D search trees (same node table);
+  bh_leaf    most particles of a leaf of the tree potential (with bh_theta > 0;
+             other cells are accepted, phi stays within the theta bound).
 The best values depend on the catalogue (the share of particles in giant
 nodes and haloes).  `tune` times the refinement call (HIP events on the
-library's stream) at each candidate of the first three knobs in turn, keeping
-the best of each, then the unbinding call at each pot_chunk, and returns the
-picks with every timing.
+library's stream) at each candidate of the refinement knobs in turn, keeping
+the best of each, then the unbinding call at each potential knob, and returns
+the picks with every timing.
 
     python -m paper_1110_4372_amd.autotune --config c3
 """
@@ -28,6 +31,8 @@ CANDIDATES = (8192, 16384, 32768, 65536, 131072)
 NN_CHUNKS = (512, 1024, 2048)
 FOF_CHUNKS = (1024, 2048, 4096)
 POT_CHUNKS = (1024, 2048, 4096)
+KD_LEAVES = (8, 16, 32)
+BH_LEAVES = (8, 16, 32)
 
 
 def choose(timings: dict) -> int:
@@ -71,25 +76,29 @@ def tune_grid_min(H, params, P, candidates=CANDIDATES, repeats: int = 2):
 
 
 def tune(H, params, P, repeats: int = 2, grid=CANDIDATES, nn=NN_CHUNKS, fof_c=FOF_CHUNKS,
-         pot=POT_CHUNKS):
-    """Coordinate search over grid_min, nn_chunk, fof_chunk (refinement time)
-    and pot_chunk (unbinding time).  Returns (tuned Params, report)."""
+         pot=POT_CHUNKS, kd_leaf=KD_LEAVES, bh_leaf=BH_LEAVES):
+    """Coordinate search over grid_min, nn_chunk, fof_chunk, kd_leaf
+    (refinement time), pot_chunk and, with the tree potential on, bh_leaf
+    (unbinding time).  Returns (tuned Params, report)."""
     from dataclasses import replace
     ctx0 = H.Halo(params)
     fof = ctx0.fof3d(P)
     refine = lambda ctx: (lambda: ctx.refine6d(P, fof))  # noqa: E731
     report = {}
     p = params
-    for knob, cands in (("grid_min", grid), ("nn_chunk", nn), ("fof_chunk", fof_c)):
+    for knob, cands in (("grid_min", grid), ("nn_chunk", nn), ("fof_chunk", fof_c),
+                        ("kd_leaf", kd_leaf)):
         best, t = tune_knob(H, p, P, knob, cands, refine, repeats)
         p = replace(p, **{knob: best})
         report[knob] = {"pick": best, "refine_ms": {str(k): v for k, v in t.items()}}
     nodes, deep = H.Halo(p).refine6d(P, fof)
     halos, hof = H.Halo(p).assign(P, nodes, deep)
     unbind = lambda ctx: (lambda: ctx.unbind(P, halos, hof, want_phi=False))  # noqa: E731
-    best, t = tune_knob(H, p, P, "pot_chunk", pot, unbind, repeats)
-    p = replace(p, pot_chunk=best)
-    report["pot_chunk"] = {"pick": best, "unbind_ms": {str(k): v for k, v in t.items()}}
+    knobs = [("pot_chunk", pot)] + ([("bh_leaf", bh_leaf)] if p.bh_theta > 0 else [])
+    for knob, cands in knobs:
+        best, t = tune_knob(H, p, P, knob, cands, unbind, repeats)
+        p = replace(p, **{knob: best})
+        report[knob] = {"pick": best, "unbind_ms": {str(k): v for k, v in t.items()}}
     return p, report
 
 

@@ -130,6 +130,8 @@ static std::string validate(const libhalo_params& p) {
     return "fof_chunk must be 0 or a multiple of 256 in [256, 16384]";
   if (p.pot_chunk != 0 && p.pot_chunk != 1024 && p.pot_chunk != 2048 && p.pot_chunk != 4096)
     return "pot_chunk must be 0, 1024, 2048 or 4096";
+  if (p.kd_leaf != 0 && (p.kd_leaf < 4 || p.kd_leaf > 64)) return "kd_leaf must be 0 or in [4, 64]";
+  if (p.bh_leaf != 0 && (p.bh_leaf < 4 || p.bh_leaf > 64)) return "bh_leaf must be 0 or in [4, 64]";
   return "";
 }
 

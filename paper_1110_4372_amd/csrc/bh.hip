@@ -30,7 +30,7 @@ namespace halo {
 namespace {
 
 constexpr int TB = 256;
-constexpr uint32_t kLeaf = 16;     // a cell of at most this many particles is a leaf
+constexpr uint32_t kLeaf = 16;     // default: a cell of at most this many particles is a leaf
 constexpr uint32_t kMaxDepth = 64; // cells at this depth are leaves whatever their size
 constexpr int kFrac = 32;  // fractional bits of the potential accumulators
 
@@ -462,10 +462,11 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   HALO_CHECK(E64 < 0x7FFFFFFFull, LIBHALO_EINVAL,
              "tree elements exceed 31-bit indices (raise bh_min)");
   const uint32_t E = hb[1];
-  // cells: leaves of at most kLeaf particles use about 0.2 cells per particle; the
+  // cells: leaves of at most L particles use about 3.2 / L cells per particle; the
   // capacity bounds memory, not results (a cell without room for its children
   // stays a leaf)
-  const uint32_t cap = E / 4 + B + 64;
+  const uint32_t leaf = ctx.p.bh_leaf > 0 ? (uint32_t)ctx.p.bh_leaf : kLeaf;
+  const uint32_t cap = (uint32_t)((4ull * E) / leaf) + B + 64;
   // second carve with the element and cell arrays; the list is rebuilt in it
   unsigned long long *k0, *k1, *rmx;
   uint32_t *v0, *v1, *cell;  // cell: each element's cell at the current depth (r_max pass)
@@ -499,7 +500,7 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   const uint32_t* pidx = f ? v1 : v0;
   // the cells over each halo's sorted range; the sorted keys are read by the build
   // only, so afterwards x and y of the sorted positions take their place
-  mtree_build(t, f ? k1 : k0, w.L.eoff, w.L.nel, B, kLeaf, kMaxDepth, hb + 2, s);
+  mtree_build(t, f ? k1 : k0, w.L.eoff, w.L.nel, B, leaf, kMaxDepth, hb + 2, s);
   double* px = reinterpret_cast<double*>(k0);
   double* py = reinterpret_cast<double*>(k1);
   k_bh_gather<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, pidx, E, px, py, pz, pf);

@@ -5,7 +5,7 @@
 //   1. its particles are sorted along a 6D Morton curve (8 bits per
 //      normalised coordinate over [-A, A], clamped), keyed by node first;
 //   2. a binary tree is built top down over the sorted order: a node whose
-//      range holds more than kKdLeaf particles splits where the highest Morton
+//      range holds more than kd_leaf particles (16 by default) splits where the highest Morton
 //      bit that differs across its range changes (at the middle of the range
 //      when every key is equal), so each child covers one cell of the curve;
 //      its box is the exact bounding box of its particles.  The split is the
@@ -339,7 +339,7 @@ unsigned walk_grid(uint32_t MB) {
 
 }  // namespace
 
-void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax) {
+void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax, uint32_t leaf) {
   const uint32_t NBmax = M / kGridFloor + 2;
   g.nb_rank = A.take<uint32_t>(Kmax + 2);
   g.gnode = A.take<uint32_t>(NBmax);
@@ -347,8 +347,9 @@ void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax) {
   g.gcount = A.take<uint32_t>(NBmax + 1);
   // tree nodes: the capacity bounds memory, not results (a node that finds no
   // room for its children stays a leaf and is searched in full); trees of
-  // 16-particle leaves use about 0.2 nodes per particle
-  const uint32_t cap = M / 4 + NBmax + 64;
+  // leaves of at most L particles use about 3.2 / L nodes per particle
+  g.leaf = leaf;
+  const uint32_t cap = (uint32_t)((4ull * M) / leaf) + NBmax + 64;
   mtree_take(A, *g.mt, cap, NBmax);
   g.node = A.take<KdNode>(cap + 1);
   g.flag = A.take<uint32_t>((size_t)M + 2);
@@ -398,7 +399,7 @@ uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint3
   const unsigned long long* key = fl ? g.k1 : g.k0;
   k_kd_gather<<<blocks_for(MB, TB), TB, 0, s>>>(fl ? g.v1 : g.v0, xi, S, MB, lnode, g);
   MTree& t = *g.mt;
-  mtree_build(t, key, g.pstart, g.gcount, NB, kKdLeaf, kKdMaxDepth, hb + 2, s);
+  mtree_build(t, key, g.pstart, g.gcount, NB, g.leaf, kKdMaxDepth, hb + 2, s);
   g.troot = t.troot;
   for (int d = (int)t.lev.size() - 2; d >= 0; --d) {
     const uint32_t nu = t.lev[d + 1] - t.lev[d];

@@ -1000,7 +1000,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     sc.selp = A.take<uint32_t>(2ull * (M / kSelSmall + 2));
     sc.ghist = A.take<uint32_t>(256ull * (M / kSelSmall + 2));
     dcnt = A.take<uint32_t>(16);
-    grid_take(A, gb, M, Kmax);
+    grid_take(A, gb, M, Kmax, P.kd_leaf > 0 ? (uint32_t)P.kd_leaf : kKdLeaf);
   });
   // outputs are written only once the workspace is in place
   k_fill_i32<<<blocks_for(n, TB), TB, 0, s>>>(deepest, n, -1);

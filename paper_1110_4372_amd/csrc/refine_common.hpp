@@ -72,7 +72,7 @@ __host__ __device__ inline uint32_t default_grid_min(uint32_t level_particles) {
   return level_particles >= kGridLevel ? kGridMin : kGridMinSmall;
 }
 constexpr uint32_t kGridFloor = 64;   // smallest accepted threshold
-constexpr uint32_t kKdLeaf = 16;      // a tree node of at most this many particles is a leaf
+constexpr uint32_t kKdLeaf = 16;      // default: a tree node of at most this many particles is a leaf
 constexpr int kKdMaxDepth = 64;       // nodes at this depth are leaves whatever their size
 
 // A tree node as the walks read it, in depth-first preorder (first child
@@ -101,9 +101,10 @@ struct GridBufs {
   void* rtmp;
   MTree* mt;         // host object: the trees' topology (mtree.hpp)
   uint32_t MB = 0, NB = 0;  // sorted points, grid nodes
+  uint32_t leaf = kKdLeaf;  // most points of a leaf
 };
 
-void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax);
+void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax, uint32_t leaf);
 // Classifies the level's nodes (sc.gstate 1 for tree nodes) and builds the
 // trees of those above gmin.  Returns their number.
 uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint32_t K,

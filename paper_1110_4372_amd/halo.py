@@ -37,7 +37,8 @@ class CParams(C.Structure):
                 ("mode", C.c_int32), ("prec", C.c_int32), ("grid_min", C.c_int32),
                 ("ell_subset", C.c_int32), ("major_merger", C.c_double),
                 ("fof_dense", C.c_int32), ("bh_min", C.c_int32), ("bh_theta", C.c_double),
-                ("nn_chunk", C.c_int32), ("fof_chunk", C.c_int32), ("pot_chunk", C.c_int32)]
+                ("nn_chunk", C.c_int32), ("fof_chunk", C.c_int32), ("pot_chunk", C.c_int32),
+                ("kd_leaf", C.c_int32), ("bh_leaf", C.c_int32)]
 
 
 @dataclasses.dataclass
@@ -69,6 +70,9 @@ class Params:
     nn_chunk: int = 0
     fof_chunk: int = 0
     pot_chunk: int = 0
+    # leaf sizes of the 6D search trees and of the tree potential (0 = 16)
+    kd_leaf: int = 0
+    bh_leaf: int = 0
 
     def c(self) -> CParams:
         return CParams(self.box, self.b, self.f, self.min_members, self.max_levels,
@@ -76,7 +80,8 @@ class Params:
                        self.softening, self.core_frac, self.unbound_threshold,
                        self.e_recheck, self.mode, self.prec, self.grid_min,
                        self.ell_subset, self.major_merger, self.fof_dense, self.bh_min,
-                       self.bh_theta, self.nn_chunk, self.fof_chunk, self.pot_chunk)
+                       self.bh_theta, self.nn_chunk, self.fof_chunk, self.pot_chunk,
+                       self.kd_leaf, self.bh_leaf)
 
 
 NODE_FIELDS = [("parent", torch.int32), ("level", torch.int32), ("first_child", torch.int32),

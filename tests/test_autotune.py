@@ -65,7 +65,8 @@ def test_unit_chunks_same_results():
     ref = H.Halo(base).run_all(P)
     torch.cuda.synchronize()
     for kw in ({"nn_chunk": 256, "fof_chunk": 16384}, {"nn_chunk": 4096, "fof_chunk": 256},
-               {"pot_chunk": 1024}, {"pot_chunk": 4096}):
+               {"pot_chunk": 1024}, {"pot_chunk": 4096},
+               {"grid_min": 2048, "kd_leaf": 4}, {"grid_min": 2048, "kd_leaf": 64}):
         out = H.Halo(replace(base, **kw)).run_all(P)
         torch.cuda.synchronize()
         for k in ref["nodes"]:
@@ -93,8 +94,9 @@ def test_tune_picks_candidates():
     P = particles_from_arrays(pos, vel)
     params = H.Params(box=20.0, particle_mass=1e10, softening=0.01)
     p, rep = autotune.tune(H, params, P, repeats=1, grid=(64, 1 << 30), nn=(512, 1024),
-                           fof_c=(1024, 2048), pot=(1024, 2048))
+                           fof_c=(1024, 2048), pot=(1024, 2048), kd_leaf=(8, 16))
     torch.cuda.synchronize()
     assert p.grid_min in (64, 1 << 30) and p.nn_chunk in (512, 1024)
     assert p.fof_chunk in (1024, 2048) and p.pot_chunk in (1024, 2048)
-    assert set(rep) == {"grid_min", "nn_chunk", "fof_chunk", "pot_chunk"}
+    assert p.kd_leaf in (8, 16)
+    assert set(rep) == {"grid_min", "nn_chunk", "fof_chunk", "kd_leaf", "pot_chunk"}

@@ -62,6 +62,21 @@ def test_tree_within_theta_c1(H, orc, c1, c1_oracle, theta):
     print(f"bound flags agree for {100 * agree:.3f}% of tree-halo particles")
 
 
+@pytest.mark.parametrize("leaf,prec", [(4, 0), (64, 1)])
+def test_tree_leaf_sizes_within_theta(H, orc, c1, c1_oracle, leaf, prec):
+    """Other leaf sizes of the potential's trees accept other cells; every
+    tree-halo potential still lies within theta of the exact sum."""
+    note(f"tree potential c1 bh_leaf={leaf} prec={prec}")
+    theta, bh_min = 0.04, 2000
+    g = H.Halo(H.params_for_catalog(c1, bh_theta=theta, bh_min=bh_min, bh_leaf=leaf,
+                                    prec=prec)).run_all(H.Particles.from_catalog(c1))
+    tree = tree_cases(c1_oracle, bh_min)
+    sel = np.isin(c1_oracle["halo_of"], tree)
+    rel = np.abs(to_np(g["phi"])[sel] / c1_oracle["phi"][sel] - 1.0)
+    print(f"relative error median {np.median(rel):.2e} max {rel.max():.2e}")
+    assert sel.sum() > 0 and rel.max() <= theta
+
+
 def test_tree_theta_to_zero_is_exact(H, orc, c1, c1_oracle):
     """theta = 1e-12 opens every cell: the direct sum, in another order."""
     note("tree potential theta -> 0")
