@@ -147,12 +147,16 @@ __global__ void k_kd_records(GridBufs g, const MtNode* bnode, const uint32_t* pr
       r.mx[c] = h_up(mx[c]);
     }
   } else {
-    const KdNode& a = g.node[pre[u.left]];
-    const KdNode& b = g.node[pre[u.left + 1]];
+    const uint32_t pl = pre[u.left], pr = pre[u.left + 1];
+    const KdNode& a = g.node[pl];
+    const KdNode& b = g.node[pr];
     for (int c = 0; c < 6; ++c) {
       r.mn[c] = h_down(fminf(h_f(a.mn[c]), h_f(b.mn[c])));
       r.mx[c] = h_up(fmaxf(h_f(a.mx[c]), h_f(b.mx[c])));
     }
+    // each child's parent, its sibling and the record after the sibling's subtree
+    g.up[pl] = make_uint4(p, pr, p + u.aux, 0u);
+    g.up[pr] = make_uint4(p, pl, pr, 0u);
   }
   r.lo = u.lo;
   r.skip = p + u.aux;
@@ -186,7 +190,11 @@ __device__ __forceinline__ float point_gap2(const float* a, const KdNode& r) {
 // whose box is close enough is entered (next record), else skipped (its
 // `skip`).  MODE 0: nearest-neighbour distance within the point's tree node
 // (D[m] = min over j != q of d2_6), starting from its own leaf's particles,
-// then every other leaf no farther than the best so far.  MODE 1: 6D FOF at
+// then, from the own leaf upwards, the sibling subtree of each ancestor in
+// turn, every leaf no farther than the best so far: the nearest subtrees come
+// first, so the best distance shrinks early and prunes the far ones (a CPU
+// count on a 3e5-point NFW halo: 12% fewer box tests, 15% fewer distances
+// than one walk from the root).  MODE 1: 6D FOF at
 // the node's ell^2 for points with D <= ell^2, over the points after q in the
 // order: the rest of its own leaf, then the records after that leaf (the
 // preorder visits index ranges in increasing order).  Lanes first test nodes
@@ -209,7 +217,8 @@ __global__ void __launch_bounds__(kWalkTB)
               const uint32_t* __restrict__ pm, const uint32_t* __restrict__ pb,
               const uint32_t* __restrict__ leafof, const uint32_t* __restrict__ troot,
               uint32_t MB, const uint32_t* __restrict__ gnode, NodeScratch sc, uint32_t* D,
-              uint32_t* par, uint32_t* queue, unsigned long long* work) {
+              uint32_t* par, uint32_t* queue, const uint4* __restrict__ UP,
+              unsigned long long* work) {
   const uint32_t lane = threadIdx.x & 63u;
   const unsigned long long below = (1ull << lane) - 1ull;
   uint32_t cbase = 0, cend = 0, cnext = kWalkChunk;  // the wave's chunk [cbase, cend)
@@ -218,6 +227,7 @@ __global__ void __launch_bounds__(kWalkTB)
   // this lane's query
   bool active = false, have = false;
   uint32_t q = 0, m = 0, own = 0, end = 0, lo = 0, hi = 0, u = 0, ri = 0;
+  uint32_t anc = 0, root = 0;  // MODE 0: the node whose sibling subtree is walked
   float a[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   float best = __int_as_float(0x7F800000);  // MODE 0: nearest so far
   float l2 = 0.0f;                          // MODE 1: ell^2 of the node
@@ -252,14 +262,16 @@ __global__ void __launch_bounds__(kWalkTB)
         const uint32_t b = pb[q];
         m = pm[q];
         own = leafof[q];
-        end = troot[b + 1];  // the record after the point's tree
         hi = T[own + 1].lo;
         if (MODE == 0) {
           lo = T[own].lo;
-          u = troot[b];
+          root = troot[b];
+          anc = own;
+          u = end = 0u;  // no subtree yet: the first step goes up from the own leaf
           best = __int_as_float(0x7F800000);
           active = true;
         } else {
+          end = troot[b + 1];  // the record after the point's tree
           l2 = sc.ell2[gnode[b]];
           lo = q + 1u;
           u = own + 1u;
@@ -293,10 +305,15 @@ __global__ void __launch_bounds__(kWalkTB)
     while (__any(active && !have)) {
       if (active && !have) {
         if (u >= end) {
-          if (MODE == 0) D[m] = __float_as_uint(best);
-          active = false;
-        } else if (MODE == 0 && u == own) {
-          u = own + 1u;  // searched first
+          if (MODE == 1 || anc == root) {
+            if (MODE == 0) D[m] = __float_as_uint(best);
+            active = false;
+          } else {  // the next subtree: the sibling of anc, whose parent is next
+            const uint4 up = UP[anc];
+            anc = up.x;
+            u = up.y;
+            end = up.z;
+          }
         } else {
           const KdNode r = T[u];
           const float g = point_gap2(a, r);
@@ -352,6 +369,7 @@ void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax, uint32_t leaf) 
   const uint32_t cap = (uint32_t)((4ull * M) / leaf) + NBmax + 64;
   mtree_take(A, *g.mt, cap, NBmax);
   g.node = A.take<KdNode>(cap + 1);
+  g.up = A.take<uint4>(cap + 1);
   g.flag = A.take<uint32_t>((size_t)M + 2);
   g.pos = A.take<uint32_t>((size_t)M + 2);
   g.k0 = A.take<unsigned long long>((size_t)M + 2);
@@ -415,7 +433,7 @@ void grid_nn(GridBufs& g, NodeScratch sc, uint32_t* D, unsigned long long* work,
   k_fill_u32<<<1, 128, 0, s>>>(g.queue, 128, 0u);
   k_kd_walk<0><<<walk_grid(g.MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof,
                                                    g.troot, g.MB, g.gnode, sc, D, nullptr,
-                                                   g.queue, work);
+                                                   g.queue, g.up, work);
 }
 
 void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par,
@@ -425,7 +443,7 @@ void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par,
   k_kd_walk<1><<<walk_grid(g.MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof,
                                                    g.troot, g.MB, g.gnode, sc,
                                                    const_cast<uint32_t*>(D), par, g.queue,
-                                                   work);
+                                                   g.up, work);
 }
 
 }  // namespace refine

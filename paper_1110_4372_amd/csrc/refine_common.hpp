@@ -97,6 +97,7 @@ struct GridBufs {
   float* pt;         // MB points in sorted order, six normalised coordinates each
   uint32_t *pm, *pb; // their positions in the level arrays and their grid nodes
   KdNode* node;      // tree nodes in preorder; tree b is [troot[b], troot[b+1])
+  uint4* up;         // per node: parent, sibling, the record after the sibling's subtree
   const uint32_t* troot;
   void* rtmp;
   MTree* mt;         // host object: the trees' topology (mtree.hpp)
