@@ -307,8 +307,9 @@ __global__ void k_bh_wave_counts(BhList L, uint32_t B, uint32_t* wcnt) {
 // F32 (the mixed form): distances and reciprocal square roots in FP32 from the
 // halo-local positions rounded to FP32 (their rounding, about 1e-7 of a halo's
 // extent, is far below the monopole error the acceptance distance allows); a
-// leaf's terms are summed in FP32 and each leaf's and monopole's sum is added
-// to the lane's FP64 total.
+// leaf's terms are summed in FP32, the target's own term subtracted once
+// afterwards instead of masked per term, and each leaf's and monopole's sum is
+// added to the lane's FP64 total.
 template <bool F32>
 __global__ void __launch_bounds__(TB)
     k_bh_walk(BhList L, uint32_t B, const uint32_t* woff, uint32_t nwave, const uint32_t* slot,
@@ -330,6 +331,9 @@ __global__ void __launch_bounds__(TB)
   if (__ballot(target) == 0ull) return;  // wave-uniform
   const double x = in ? px[e] : 0.0, y = in ? py[e] : 0.0, z = in ? pz[e] : 0.0;
   const float xf = (float)x, yf = (float)y, zf = (float)z, eps2f = (float)eps2;
+  // the F32 leaf sum's term of the target itself (the same expression at d = 0)
+  const float self_f = __builtin_amdgcn_rsqf(
+      __fmaf_rn(0.0f, 0.0f, __fmaf_rn(0.0f, 0.0f, __fmaf_rn(0.0f, 0.0f, eps2f))));
   uint32_t u = __builtin_amdgcn_readfirstlane(troot[b]);
   const uint32_t end = __builtin_amdgcn_readfirstlane(troot[b + 1]);
   double acc = 0.0;
@@ -364,16 +368,18 @@ __global__ void __launch_bounds__(TB)
       // every lane evaluates each term and keeps it by a select, so the loads of a
       // leaf particle are not behind a branch and several can be in flight at once
       if constexpr (F32) {
+        // every term is summed, the target's own (distance zero: the softening
+        // alone) included, and that one is taken back after the leaf; lanes
+        // without a target discard their sums
         float sf = 0.0f;
 #pragma unroll 4
         for (uint32_t f = c.lo; f < c.hi; ++f) {
           const float fx = pf[3ull * f], fy = pf[3ull * f + 1], fz = pf[3ull * f + 2];
-          const uint32_t qf = pidx[f];
           const float dx = xf - fx, dy = yf - fy, dz = zf - fz;
-          const float tf = __builtin_amdgcn_rsqf(
+          sf += __builtin_amdgcn_rsqf(
               __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2f))));
-          sf = (target && qf != q) ? sf + tf : sf;
         }
+        if (e >= c.lo && e < c.hi) sf -= self_f;
         acc += (double)sf;
       } else {
 #pragma unroll 4

@@ -38,6 +38,7 @@ namespace {
 constexpr float kHalfRange = 4.0f;      // Morton quantisation range [-A, A]
 constexpr int kWalkTB = 256;            // threads per block of the walks
 constexpr uint32_t kWalkChunk = 64;     // points a wave takes from the queue at a time
+constexpr uint32_t kLeafStep = 4;       // leaf points a walk evaluates per step
 
 __global__ void k_grid_classify(LevelNodes nd, uint32_t K, NodeScratch sc, uint32_t gmin,
                                 uint32_t* flag) {
@@ -197,8 +198,11 @@ __device__ __forceinline__ float point_gap2(const float* a, const KdNode& r) {
 // than one walk from the root).  MODE 1: 6D FOF at
 // the node's ell^2 for points with D <= ell^2, over the points after q in the
 // order: the rest of its own leaf, then the records after that leaf (the
-// preorder visits index ranges in increasing order).  Lanes first test nodes
-// until each has a leaf to search, then search their leaves together.
+// preorder visits index ranges in increasing order).  Each lane advances its
+// own walk by one step per iteration, a record test or up to kLeafStep leaf
+// points: the walks diverge at every record, and lanes that waited for the
+// others to reach a leaf left four in five lanes of the issued instructions
+// idle.
 //
 // The walks differ in length by several times within a wave, so the grid is
 // persistent and a lane whose walk ends takes the next query at once: each
@@ -284,51 +288,54 @@ __global__ void __launch_bounds__(kWalkTB)
       cnext = avail == 0 ? kWalkChunk : cnext + took;
     }
     if (!__any(active)) break;
-    if (have) {
-      neval += hi > lo ? hi - lo : 0u;
-      // unrolled so that several points' loads are in flight together
-#pragma unroll 4
-      for (uint32_t j = lo; j < hi; ++j) {
-        const float* pj = pt + 6ull * j;
-        const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], pj[0], pj[1], pj[2], pj[3],
-                             pj[4], pj[5]);
-        if (MODE == 0) {
-          best = j != q ? fminf(best, d) : best;
-        } else if (d <= l2) {
-          const uint32_t rj = uf_find(par, pm[j]);
-          if (rj != ri) ri = uf_union(par, ri, rj);
-        }
-      }
-      have = false;
-    }
-    // test records until this lane has a leaf to search or its walk ends
-    while (__any(active && !have)) {
-      if (active && !have) {
-        if (u >= end) {
-          if (MODE == 1 || anc == root) {
-            if (MODE == 0) D[m] = __float_as_uint(best);
-            active = false;
-          } else {  // the next subtree: the sibling of anc, whose parent is next
-            const uint4 up = UP[anc];
-            anc = up.x;
-            u = up.y;
-            end = up.z;
+    // one step of this lane's walk: up to kLeafStep points of the leaf it is
+    // searching, else one record.  Lanes in either kind of step run together,
+    // so no lane waits for the others to reach a leaf.
+    if (active) {
+      if (have) {
+        const uint32_t jn = lo < hi ? min(hi, lo + kLeafStep) : lo;
+        neval += jn - lo;
+#pragma unroll
+        for (uint32_t k = 0; k < kLeafStep; ++k) {
+          const uint32_t j = lo + k;
+          if (j < jn) {
+            const float* pj = pt + 6ull * j;
+            const float d = d2_6(a[0], a[1], a[2], a[3], a[4], a[5], pj[0], pj[1], pj[2],
+                                 pj[3], pj[4], pj[5]);
+            if (MODE == 0) {
+              best = j != q ? fminf(best, d) : best;
+            } else if (d <= l2) {
+              const uint32_t rj = uf_find(par, pm[j]);
+              if (rj != ri) ri = uf_union(par, ri, rj);
+            }
           }
+        }
+        lo = jn;
+        have = jn < hi;
+      } else if (u >= end) {
+        if (MODE == 1 || anc == root) {
+          if (MODE == 0) D[m] = __float_as_uint(best);
+          active = false;
+        } else {  // the next subtree: the sibling of anc, whose parent is next
+          const uint4 up = UP[anc];
+          anc = up.x;
+          u = up.y;
+          end = up.z;
+        }
+      } else {
+        const KdNode r = T[u];
+        const float g = point_gap2(a, r);
+        ++ntest;
+        const bool in = MODE == 0 ? g < best : g <= l2;
+        if (!in) {
+          u = r.skip;
         } else {
-          const KdNode r = T[u];
-          const float g = point_gap2(a, r);
-          ++ntest;
-          const bool in = MODE == 0 ? g < best : g <= l2;
-          if (!in) {
-            u = r.skip;
-          } else if (r.skip == u + 1u) {  // a leaf
+          if (r.skip == u + 1u) {  // a leaf
             lo = r.lo;
             hi = T[u + 1].lo;
             have = true;
-            u = u + 1u;
-          } else {
-            u = u + 1u;
           }
+          u = u + 1u;
         }
       }
     }
