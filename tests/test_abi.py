@@ -82,3 +82,25 @@ def test_ctx_create_requires_allocator(lib):
                                        ctypes.POINTER(ctypes.c_void_p)]
     assert lib.libhalo_ctx_create(ctypes.byref(p), 0, None, None, None, ctypes.byref(h)) == -1
     assert not h.value
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nn_chunk", 100), ("nn_chunk", 8192), ("fof_chunk", 300), ("fof_chunk", 32768),
+    ("pot_chunk", 3000), ("kd_leaf", 2), ("kd_leaf", 65), ("bh_leaf", 3), ("bh_leaf", 100),
+    ("grid_min", 32), ("bh_theta", -1.0), ("f", 1.5)])
+def test_ctx_create_rejects_bad_parameters(lib, field, value):
+    """Out-of-range parameters are EINVAL before any device call (a counting
+    allocator sees no request)."""
+    import dataclasses
+    from paper_1110_4372_amd import halo
+    calls = []
+    alloc = halo.ALLOC_FN(lambda n, user, stream: calls.append(n) or None)
+    free = halo.FREE_FN(lambda ptr, user, stream: None)
+    p = dataclasses.replace(halo.Params(box=10.0, particle_mass=1.0, softening=0.01),
+                            **{field: value}).c()
+    h = ctypes.c_void_p()
+    lib.libhalo_ctx_create.argtypes = [ctypes.POINTER(halo.CParams), ctypes.c_int,
+                                       halo.ALLOC_FN, halo.FREE_FN, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+    assert lib.libhalo_ctx_create(ctypes.byref(p), 0, alloc, free, None, ctypes.byref(h)) == -1
+    assert not h.value and calls == []
