@@ -240,49 +240,48 @@ __global__ void k_bh_records(const MtNode* bnode, const uint32_t* pre, uint32_t 
   R[p] = r;
 }
 
-// Exact r_max of every cell, one depth per launch: each particle follows its
-// cell down the tree (cur: level-order index of its cell at this depth, kMtNone
-// once past its leaf), and the particles of a wave, whose cells form runs
-// along the sorted order, reduce each run to one atomic maximum (ordered
-// integers) before moving to the child that holds them.
-__global__ void k_bh_rmax_depth(uint32_t E, const double* px, const double* py, const double* pz,
-                                const MtNode* bnode, const uint32_t* pre, const BhRec* R,
-                                uint32_t* cur, unsigned long long* rmx) {
+// Exact r_max of every cell in one launch: each particle starts at the root of
+// its halo's tree (roots are 0 .. B-1, level order) and follows its cell down
+// to its leaf, one depth per iteration; at each depth the particles of a wave,
+// whose cells form runs along the sorted order, reduce each run to one atomic
+// maximum (ordered integers) of the squared distance to the cell's centre.
+// sqrt is monotone, so the root of the largest square is the largest
+// distance, taken once per cell in k_bh_crit.
+__global__ void k_bh_rmax(BhList L, uint32_t B, uint32_t E, const double* px, const double* py,
+                          const double* pz, const MtNode* bnode, const uint32_t* pre,
+                          const BhRec* R, unsigned long long* rmx) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t u = e < E ? cur[e] : kMtNone;
-  unsigned long long v = 0ull;
-  uint32_t p = kMtNone;
-  if (u != kMtNone) {
-    p = pre[u];
-    v = f64_ord(sqrt(sq3(px[e] - R[p].cx, py[e] - R[p].cy, pz[e] - R[p].cz)));
+  uint32_t u = e < E ? seg_find(L.eoff, B, e) : kMtNone;
+  const double x = e < E ? px[e] : 0.0, y = e < E ? py[e] : 0.0, z = e < E ? pz[e] : 0.0;
+  while (__any(u != kMtNone)) {
+    unsigned long long v = 0ull;
+    uint32_t p = kMtNone;
+    if (u != kMtNone) {
+      p = pre[u];
+      v = f64_ord(sq3(x - R[p].cx, y - R[p].cy, z - R[p].cz));
+    }
+    // maximum over the rest of this lane's run (runs of equal cells are
+    // contiguous): lane i ends with the maximum over [i, end of its run]
+    for (uint32_t o = 1; o < 64u; o <<= 1) {
+      const unsigned long long vo = __shfl_down(v, o);
+      const uint32_t po = __shfl_down(p, o);
+      if (lane + o < 64u && po == p && vo > v) v = vo;
+    }
+    const uint32_t pp = __shfl_up(p, 1);
+    if (p != kMtNone && (lane == 0u || pp != p)) atomicMax(rmx + p, v);
+    if (u != kMtNone) {
+      const MtNode n = bnode[u];
+      u = n.left == kMtNone ? kMtNone : (e < bnode[n.left].hi ? n.left : n.left + 1u);
+    }
   }
-  // maximum over the rest of this lane's run (runs of equal cells are
-  // contiguous): lane i ends with the maximum over [i, end of its run]
-  for (uint32_t o = 1; o < 64u; o <<= 1) {
-    const unsigned long long vo = __shfl_down(v, o);
-    const uint32_t po = __shfl_down(p, o);
-    if (lane + o < 64u && po == p && vo > v) v = vo;
-  }
-  const uint32_t pp = __shfl_up(p, 1);
-  if (p != kMtNone && (lane == 0u || pp != p)) atomicMax(rmx + p, v);
-  if (u != kMtNone) {
-    const MtNode n = bnode[u];
-    cur[e] = n.left == kMtNone ? kMtNone : (e < bnode[n.left].hi ? n.left : n.left + 1u);
-  }
-}
-
-// Each element starts at the root of its halo's tree (roots are 0 .. B-1).
-__global__ void k_bh_rmax_roots(BhList L, uint32_t B, uint32_t E, uint32_t* cur) {
-  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < E) cur[e] = seg_find(L.eoff, B, e);
 }
 
 // Acceptance distances from the exact r_max.
 __global__ void k_bh_crit(uint32_t T, double theta, const unsigned long long* rmx, BhRec* R) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T) return;
-  const double r = ord_f64(rmx[t]);
+  const double r = sqrt(ord_f64(rmx[t]));  // r_max from the largest squared distance
   const double dc = 0.5 * r + sqrt(0.25 * r * r + R[t].sig2 / theta);
   R[t].crit2 = dc * dc;
 }
@@ -475,7 +474,7 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   const uint32_t cap = (uint32_t)((4ull * E) / leaf) + B + 64;
   // second carve with the element and cell arrays; the list is rebuilt in it
   unsigned long long *k0, *k1, *rmx;
-  uint32_t *v0, *v1, *cell;  // cell: each element's cell at the current depth (r_max pass)
+  uint32_t *v0, *v1;
   double* pz;
   BhRec* R;
   float* pf;  // FP32 sorted positions (mixed form)
@@ -489,7 +488,6 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
     v0 = A.take<uint32_t>(E + 1);
     v1 = A.take<uint32_t>(E + 1);
     pz = A.take<double>(E + 1);
-    cell = A.take<uint32_t>(E + 1);
     mtree_take(A, t, cap, B + 1);
     R = A.take<BhRec>(cap + 1);  // the walk reads one record ahead
     pf = f32 ? A.take<float>(3ull * (E + 1)) : nullptr;
@@ -517,10 +515,7 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   }
   // exact r_max, then the acceptance distances
   k_fill_u64<<<blocks_for(T, TB), TB, 0, s>>>(rmx, T, 0ull);
-  k_bh_rmax_roots<<<blocks_for(E, TB), TB, 0, s>>>(w.L, B, E, cell);
-  for (size_t d = 0; d + 1 < t.lev.size(); ++d)
-    k_bh_rmax_depth<<<blocks_for(E, TB), TB, 0, s>>>(E, px, py, pz, t.bnode, t.pre, R, cell,
-                                                     rmx);
+  k_bh_rmax<<<blocks_for(E, TB), TB, 0, s>>>(w.L, B, E, px, py, pz, t.bnode, t.pre, R, rmx);
   k_bh_crit<<<blocks_for(T, TB), TB, 0, s>>>(T, theta, rmx, R);
   // wave units: runs of 64 sorted elements within each halo
   k_bh_wave_counts<<<blocks_for(B, TB), TB, 0, s>>>(w.L, B, w.flag);

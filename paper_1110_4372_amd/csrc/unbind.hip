@@ -874,7 +874,7 @@ __global__ void __launch_bounds__(TB)
     for (uint32_t j = threadIdx.x; j < ns; j += TB) {
       if (base + j == qi) continue;
       double dx = ux[base + j] - xi, dy = uy[base + j] - yi, dz = uz[base + j] - zi;
-      acc += 1.0 / sqrt(sq3(dx, dy, dz) + eps2);
+      acc += rsqrt_f64(sq3(dx, dy, dz) + eps2);  // hardware estimate + one Newton step
     }
     red[threadIdx.x] = acc;
     __syncthreads();
