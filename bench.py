@@ -100,7 +100,7 @@ def progress(msg):
 
 HOT = ("k_kd_walk_nn", "k_kd_walk_fof", "k_bh_walk", "k_nn", "k_fof6", "k_potential_f64",
        "k_potential_f32", "k_link", "k_mom_accum", "k_select_small", "k_assign_level")
-WALKS = ("k_kd_walk_nn", "k_kd_walk_fof")
+WALKS = ("k_kd_walk_nn", "k_kd_walk_fof", "k_bh_walk")
 
 
 def timed(ctx, P, steps, warmup, prof=False):
@@ -108,8 +108,9 @@ def timed(ctx, P, steps, warmup, prof=False):
     time of each call (HIP events on the launch stream, read after the timed
     region), and with `prof` the library's own HIP-event timing of its hot
     kernels over the same timed steps (total ms and launches per kernel) and
-    the tree searches' work counts.  With --progress each step is
-    synchronised to report it."""
+    the tree walks' work counts per step (from one more, untimed step in the
+    walks' counting form).  With --progress each step is synchronised to
+    report it."""
     import torch
     for k in range(warmup):
         one_step(ctx, P)
@@ -133,9 +134,16 @@ def timed(ctx, P, steps, warmup, prof=False):
              for i in range(5)}
     kp = None
     if prof:
-        kp = {"kern": {k: ctx.profile_read(k) for k in HOT},
-              "work": {k: ctx.profile_work(k) for k in WALKS}}
+        kp = {"kern": {k: ctx.profile_read(k) for k in HOT}}
+        # the walks' work counts come from one more step in their counting form
+        # (slower, so it is not one of the timed steps); counts are per step
+        ctx.profile(False, count=True)
+        ctx.profile_reset()
+        one_step(ctx, P)
+        torch.cuda.synchronize()
+        kp["work"] = {k: ctx.profile_work(k) for k in WALKS}
         ctx.profile(False)
+        progress("work-counting step done")
     return sec, out, stage, kp
 
 
@@ -146,6 +154,8 @@ BH_MIN_DEFAULT = 65536     # the library's smallest tree halo when bh_min = 0
 # FLOP of one evaluation, as counted for the ALU roofline:
 NN_PAIR_FLOP = 17.0   # 6D distance: 6 sub, 1 mul, 5 fma
 BOX_TEST_FLOP = 23.0  # point-to-box gap: per axis 2 sub + fma, 6 axes, minus the first fma's add
+CELL_TEST_FLOP = 9.0  # tree-potential cell test: 3 sub, squared distance (1 mul, 2 fma), compare
+TERM_FLOP = 12.0      # a term 1/sqrt(r^2 + eps^2), as counted for the direct sum
 
 
 def pair_work(out, grid_min, bh_theta, bh_min):
@@ -199,11 +209,18 @@ def roofline_report(kp, out, steps, prec_fp64, grid_min, bh_theta, bh_min, workl
         pot: (pot_flops * steps, FP64_PEAK_TFLOPS if prec_fp64 else FP32_PEAK_TFLOPS,
               "direct-sum pairs x 12-13 FLOP"),
     }
-    for w in WALKS:
+    # work counts are per step; the kernel times cover `steps` steps
+    for w in WALKS[:2]:
         tests, evals = work[w]
-        figures[w] = (BOX_TEST_FLOP * tests + NN_PAIR_FLOP * evals, FP32_PEAK_TFLOPS,
-                      f"counted work of the exact tree search: {tests:.4g} box tests x 23 + "
-                      f"{evals:.4g} distances x 17 FLOP")
+        figures[w] = (steps * (BOX_TEST_FLOP * tests + NN_PAIR_FLOP * evals), FP32_PEAK_TFLOPS,
+                      f"counted work of the exact tree search per step: {tests:.4g} box "
+                      f"tests x 23 + {evals:.4g} distances x 17 FLOP")
+    cells, terms = work["k_bh_walk"]
+    figures["k_bh_walk"] = (steps * (CELL_TEST_FLOP * cells + TERM_FLOP * terms),
+                            FP64_PEAK_TFLOPS if prec_fp64 else FP32_PEAK_TFLOPS,
+                            f"counted work of the tree potential per step, summed over "
+                            f"targets: {cells:.4g} cell tests x 9 + {terms:.4g} terms x 12 "
+                            f"FLOP")
     dom = max(kern, key=lambda k: kern[k][0])
     t_ms, launches = kern[dom]
     rec = {"kernel": dom, "launches": launches, "avg_launch_ms": t_ms / max(launches, 1),

@@ -248,8 +248,10 @@ int libhalo_set_params(libhalo_ctx* ctx, const libhalo_params* p);
 /* Version string of the library. */
 const char* libhalo_version(void);
 
-/* Kernel timing (tracing aid).  With profiling enabled, the library brackets
- * its hot kernel launches with HIP events on the launch stream.
+/* Kernel timing (tracing aid).  enable bit 0: the library brackets its hot
+ * kernel launches with HIP events on the launch stream; bit 1: the tree walks
+ * run in a form that counts their work (libhalo_profile_work), which costs
+ * them time, so timing and counting belong in separate runs.
  * libhalo_profile_read waits for those events and returns the summed device
  * time (ms) and the number of launches of `kernel` (a kernel name such as
  * "k_potential_f64") recorded since the last reset.  Errors: EINVAL, EHIP. */
@@ -257,10 +259,12 @@ int libhalo_profile(libhalo_ctx* ctx, int enable);
 int libhalo_profile_reset(libhalo_ctx* ctx);
 int libhalo_profile_read(libhalo_ctx* ctx, const char* kernel, double* total_ms,
                          int64_t* launches);
-/* Work counted by the tree searches of large hierarchy nodes while profiling
- * is enabled, since the last reset: the node boxes tested and the particle
- * distances evaluated by "k_kd_walk_nn" (nearest neighbours) or
- * "k_kd_walk_fof" (6D FOF).  Errors: EINVAL (another kernel name), EHIP. */
+/* Work counted by the tree walks while counting is enabled, since the last
+ * reset: for "k_kd_walk_nn" (nearest neighbours) and "k_kd_walk_fof" (6D FOF)
+ * of large hierarchy nodes, the node boxes tested and the particle distances
+ * evaluated; for "k_bh_walk" (tree potential), summed over target particles,
+ * the cells tested and the terms added (monopoles and leaf particles).
+ * Errors: EINVAL (another kernel name), EHIP. */
 int libhalo_profile_work(libhalo_ctx* ctx, const char* kernel, double* tests, double* evals);
 
 /*

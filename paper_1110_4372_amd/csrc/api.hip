@@ -181,7 +181,7 @@ int libhalo_ctx_create(const libhalo_params* p, int device, libhalo_alloc_fn all
   } else if (halo::scratch_setup(device, &c->c.scratch) != hipSuccess) {
     rc = LIBHALO_EHIP;
   } else {
-    c->c.d_err = static_cast<uint32_t*>(alloc_fn(256, user, nullptr));
+    c->c.d_err = static_cast<uint32_t*>(alloc_fn(halo::kErrBlockBytes, user, nullptr));
     if (!c->c.d_err) rc = LIBHALO_ENOMEM;
   }
   if (rc != LIBHALO_OK) {
@@ -220,7 +220,10 @@ int libhalo_set_params(libhalo_ctx* ctx, const libhalo_params* p) {
 static bool dtype_ok(int d) { return d == LIBHALO_F32 || d == LIBHALO_F64; }
 
 int libhalo_profile(libhalo_ctx* ctx, int enable) {
-  return guarded(ctx, [&](halo::Ctx& c) { c.prof = enable != 0; });
+  return guarded(ctx, [&](halo::Ctx& c) {
+    c.prof = (enable & 1) != 0;
+    c.count = (enable & 2) != 0;
+  });
 }
 
 int libhalo_profile_reset(libhalo_ctx* ctx) {
@@ -231,7 +234,7 @@ int libhalo_profile_reset(libhalo_ctx* ctx) {
     }
     c.recs.clear();
     HALO_HIP(hipDeviceSynchronize());
-    HALO_HIP(hipMemset(reinterpret_cast<char*>(c.d_err) + 64, 0, 64));
+    HALO_HIP(hipMemset(reinterpret_cast<char*>(c.d_err) + 64, 0, halo::kErrBlockBytes - 64));
   });
 }
 
@@ -241,13 +244,26 @@ int libhalo_profile_work(libhalo_ctx* ctx, const char* kernel, double* tests, do
     int slot = -1;
     if (std::strcmp(kernel, "k_kd_walk_nn") == 0) slot = 0;
     if (std::strcmp(kernel, "k_kd_walk_fof") == 0) slot = 2;
+    if (std::strcmp(kernel, "k_bh_walk") == 0) slot = 4;
     HALO_CHECK(slot >= 0, LIBHALO_EINVAL, "no work counters for this kernel");
-    unsigned long long w[4];
     HALO_HIP(hipDeviceSynchronize());
-    HALO_HIP(hipMemcpy(w, reinterpret_cast<char*>(c.d_err) + 64, sizeof w,
-                       hipMemcpyDeviceToHost));
-    *tests = (double)w[slot];
-    *evals = (double)w[slot + 1];
+    if (slot < 4) {
+      unsigned long long w[4];
+      HALO_HIP(hipMemcpy(w, reinterpret_cast<char*>(c.d_err) + 64, sizeof w,
+                         hipMemcpyDeviceToHost));
+      *tests = (double)w[slot];
+      *evals = (double)w[slot + 1];
+    } else {  // the tree potential's counters, spread over kBhSlots cache lines
+      unsigned long long w[8 * halo::kBhSlots];
+      HALO_HIP(hipMemcpy(w, c.bh_counters(), sizeof w, hipMemcpyDeviceToHost));
+      double t = 0.0, e = 0.0;
+      for (int k = 0; k < halo::kBhSlots; ++k) {
+        t += (double)w[8 * k];
+        e += (double)w[8 * k + 1];
+      }
+      *tests = t;
+      *evals = e;
+    }
   });
 }
 

@@ -19,6 +19,7 @@
 // order, so the result does not depend on scheduling.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "bh.hpp"
@@ -309,13 +310,14 @@ __global__ void k_bh_wave_counts(BhList L, uint32_t B, uint32_t* wcnt) {
 // leaf's terms are summed in FP32, the target's own term subtracted once
 // afterwards instead of masked per term, and each leaf's and monopole's sum is
 // added to the lane's FP64 total.
-template <bool F32>
+template <bool F32, bool COUNT>
 __global__ void __launch_bounds__(TB)
     k_bh_walk(BhList L, uint32_t B, const uint32_t* woff, uint32_t nwave, const uint32_t* slot,
               const double* __restrict__ px, const double* __restrict__ py,
               const double* __restrict__ pz, const float* __restrict__ pf,
               const uint32_t* __restrict__ pidx, const BhRec* __restrict__ R,
-              const uint32_t* __restrict__ troot, double eps2, I128* __restrict__ pacc) {
+              const uint32_t* __restrict__ troot, double eps2, I128* __restrict__ pacc,
+              unsigned long long* work) {
   const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (TB / 64) +
                                                        (threadIdx.x >> 6));
   if (wave >= nwave) return;  // wave-uniform
@@ -336,6 +338,7 @@ __global__ void __launch_bounds__(TB)
   uint32_t u = __builtin_amdgcn_readfirstlane(troot[b]);
   const uint32_t end = __builtin_amdgcn_readfirstlane(troot[b + 1]);
   double acc = 0.0;
+  uint32_t ncell = 0, nterm = 0;  // work counts (profiling), the same in every lane
   // the next record is read while this one is processed: entering a cell (the
   // next record) is the common step; a skip reads its target afresh
   BhRec c = R[u];
@@ -355,7 +358,9 @@ __global__ void __launch_bounds__(TB)
     // distance; the cell holding the target itself is always opened (a cell of
     // coincident particles has a zero acceptance distance)
     const bool open = d2 <= c.crit2 || (e >= c.lo && e < c.hi);
+    if (COUNT) ++ncell;
     if (__ballot(target && open) == 0ull) {
+      if (COUNT) ++nterm;
       if (target) {
         if constexpr (F32)
           acc += c.cm * (double)__builtin_amdgcn_rsqf(d2f + eps2f);
@@ -364,6 +369,7 @@ __global__ void __launch_bounds__(TB)
       }
       v = c.skip;
     } else if (c.leaf) {
+      if (COUNT) nterm += c.hi - c.lo;
       // every lane evaluates each term and keeps it by a select, so the loads of a
       // leaf particle are not behind a branch and several can be in flight at once
       if constexpr (F32) {
@@ -400,6 +406,14 @@ __global__ void __launch_bounds__(TB)
     u = v;
   }
   if (target && acc > 0.0) atomic_add_i128(pacc + q, fixed128(acc, kFrac));
+  if (COUNT) {  // per target particle: cells tested, terms added
+    const unsigned long long nt = (unsigned long long)__popcll(__ballot(target));
+    if (lane == 0) {  // the waves spread their adds over kBhSlots lines
+      unsigned long long* w = work + 8u * (wave % (uint32_t)kBhSlots);
+      atomicAdd(w, nt * ncell);
+      atomicAdd(w + 1, nt * nterm);
+    }
+  }
 }
 
 // The step workspace past the unbinding's own carve is idle while the tree runs:
@@ -524,14 +538,17 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   HALO_HIP(hipStreamSynchronize(s));
   const uint32_t nwave = hb[4];
   const unsigned wg = blocks_for((int64_t)nwave * 64, TB);
-  if (f32)
-    HALO_PROF(ctx, "k_bh_walk", s,
-              k_bh_walk<true><<<wg, TB, 0, s>>>(w.L, B, w.pos, nwave, slot, px, py, pz, pf,
-                                                pidx, R, t.troot, eps2, pacc));
-  else
-    HALO_PROF(ctx, "k_bh_walk", s,
-              k_bh_walk<false><<<wg, TB, 0, s>>>(w.L, B, w.pos, nwave, slot, px, py, pz,
-                                                 nullptr, pidx, R, t.troot, eps2, pacc));
+  unsigned long long* work = ctx.count ? ctx.bh_counters() : nullptr;
+  auto walk = [&](auto f32c, auto countc) {
+    k_bh_walk<decltype(f32c)::value, decltype(countc)::value><<<wg, TB, 0, s>>>(
+        w.L, B, w.pos, nwave, slot, px, py, pz, f32 ? pf : nullptr, pidx, R, t.troot, eps2,
+        pacc, work);
+  };
+  using T1 = std::true_type;
+  using F0 = std::false_type;
+  HALO_PROF(ctx, "k_bh_walk", s,
+            f32 ? (work ? walk(T1{}, T1{}) : walk(T1{}, F0{}))
+                : (work ? walk(F0{}, T1{}) : walk(F0{}, F0{})));
   HALO_HIP(hipStreamSynchronize(s));
 }
 

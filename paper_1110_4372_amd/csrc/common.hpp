@@ -40,6 +40,10 @@ enum : uint32_t {
   kErrVelRange = 4u,   // |v| >= 2^16 km/s or NaN
 };
 
+// The device error block: error words, then the walks' work counters.
+constexpr size_t kErrBlockBytes = 4096;
+constexpr int kBhSlots = 32;  // tree-potential counter pairs (one per 64-byte line)
+
 // ------------------------------------------------------------ workspace --
 // Grow-only device arena over a block from the context's allocator callback.
 // Each entry point resets it and carves buffers.
@@ -90,8 +94,10 @@ struct Ctx {
   std::string err;
   Arena ws;
   Arena ws2;                       // second arena: the tree potential, inside unbinding
-  uint32_t* d_err = nullptr;       // device error word; its block also holds the
-                                   // walks' work counters (8 u64 at byte 64)
+  uint32_t* d_err = nullptr;       // device error word; its block (kErrBlockBytes)
+                                   // also holds the walks' work counters: the 6D
+                                   // walks' 4 u64 at byte 64, the tree potential's
+                                   // kBhSlots pairs at byte 1024, 64 bytes apart
   void* h_pinned = nullptr;        // small pinned host buffer for read-backs
   hipStream_t stream = nullptr;    // stream of the entry point being run
   libhalo_alloc_fn alloc_fn = nullptr;  // workspace provider (caller's callbacks)
@@ -99,10 +105,14 @@ struct Ctx {
   void* user = nullptr;
   void* scratch = nullptr;         // this device's fixed scratch array (no-alloc entry)
   void* dev_alloc(size_t bytes, const char* what);  // ENOMEM on NULL
-  // device work counters of the tree walks while profiling, else null
+  bool count = false;  // the tree walks count their work (a slower form of them)
+  // device work counters of the 6D tree walks while counting, else null
   unsigned long long* work_counters() {
-    return prof ? reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(d_err) + 64)
-                : nullptr;
+    return count ? reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(d_err) + 64)
+                 : nullptr;
+  }
+  unsigned long long* bh_counters() {
+    return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(d_err) + 1024);
   }
   void ensure_ws(size_t bytes);
   void ensure_ws2(size_t bytes);

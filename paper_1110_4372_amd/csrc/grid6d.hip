@@ -215,7 +215,7 @@ __device__ __forceinline__ float point_gap2(const float* a, const KdNode& r) {
 // from the next ranges in turn.  The kernel ends when all eight are drained
 // and every lane is idle; every walk ends because u only grows and is
 // bounded by its tree's end.
-template <int MODE>
+template <int MODE, bool COUNT>
 __global__ void __launch_bounds__(kWalkTB)
     k_kd_walk(const KdNode* __restrict__ T, const float* __restrict__ pt,
               const uint32_t* __restrict__ pm, const uint32_t* __restrict__ pb,
@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(kWalkTB)
     if (active) {
       if (have) {
         const uint32_t jn = lo < hi ? min(hi, lo + kLeafStep) : lo;
-        neval += jn - lo;
+        if (COUNT) neval += jn - lo;
 #pragma unroll
         for (uint32_t k = 0; k < kLeafStep; ++k) {
           const uint32_t j = lo + k;
@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(kWalkTB)
       } else {
         const KdNode r = T[u];
         const float g = point_gap2(a, r);
-        ++ntest;
+        if (COUNT) ++ntest;
         const bool in = MODE == 0 ? g < best : g <= l2;
         if (!in) {
           u = r.skip;
@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(kWalkTB)
       }
     }
   }
-  if (work) {
+  if (COUNT) {
     unsigned long long t = ntest, e = neval;
     for (int o = 32; o > 0; o >>= 1) {
       t += __shfl_xor(t, o);
@@ -438,19 +438,29 @@ void grid_nn(GridBufs& g, NodeScratch sc, uint32_t* D, unsigned long long* work,
              hipStream_t s) {
   if (g.NB == 0 || g.MB == 0) return;
   k_fill_u32<<<1, 128, 0, s>>>(g.queue, 128, 0u);
-  k_kd_walk<0><<<walk_grid(g.MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof,
-                                                   g.troot, g.MB, g.gnode, sc, D, nullptr,
-                                                   g.queue, g.up, work);
+  if (work)
+    k_kd_walk<0, true><<<walk_grid(g.MB), kWalkTB, 0, s>>>(
+        g.node, g.pt, g.pm, g.pb, g.leafof, g.troot, g.MB, g.gnode, sc, D, nullptr, g.queue,
+        g.up, work);
+  else
+    k_kd_walk<0, false><<<walk_grid(g.MB), kWalkTB, 0, s>>>(
+        g.node, g.pt, g.pm, g.pb, g.leafof, g.troot, g.MB, g.gnode, sc, D, nullptr, g.queue,
+        g.up, nullptr);
 }
 
 void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par,
               unsigned long long* work, hipStream_t s) {
   if (g.NB == 0 || g.MB == 0) return;
   k_fill_u32<<<1, 128, 0, s>>>(g.queue, 128, 0u);
-  k_kd_walk<1><<<walk_grid(g.MB), kWalkTB, 0, s>>>(g.node, g.pt, g.pm, g.pb, g.leafof,
-                                                   g.troot, g.MB, g.gnode, sc,
-                                                   const_cast<uint32_t*>(D), par, g.queue,
-                                                   g.up, work);
+  uint32_t* Dm = const_cast<uint32_t*>(D);
+  if (work)
+    k_kd_walk<1, true><<<walk_grid(g.MB), kWalkTB, 0, s>>>(
+        g.node, g.pt, g.pm, g.pb, g.leafof, g.troot, g.MB, g.gnode, sc, Dm, par, g.queue, g.up,
+        work);
+  else
+    k_kd_walk<1, false><<<walk_grid(g.MB), kWalkTB, 0, s>>>(
+        g.node, g.pt, g.pm, g.pb, g.leafof, g.troot, g.MB, g.gnode, sc, Dm, par, g.queue, g.up,
+        nullptr);
 }
 
 }  // namespace refine

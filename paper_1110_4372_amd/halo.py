@@ -295,9 +295,10 @@ class Halo:
             raise HaloError(rc, msg)
 
     # ------------------------------------------------------------ timing --
-    def profile(self, enable: bool = True):
-        """Bracket the library's hot kernel launches with HIP events."""
-        self._check(self.L.libhalo_profile(self.h, int(enable)))
+    def profile(self, enable: bool = True, count: bool = False):
+        """Bracket the library's hot kernel launches with HIP events (enable),
+        and run the tree walks in their work-counting form (count)."""
+        self._check(self.L.libhalo_profile(self.h, (1 if enable else 0) | (2 if count else 0)))
 
     def profile_reset(self):
         self._check(self.L.libhalo_profile_reset(self.h))
@@ -309,8 +310,9 @@ class Halo:
         return t.value, k.value
 
     def profile_work(self, kernel: str):
-        """(box tests, distances) counted by a tree-search kernel since the last
-        reset ("k_kd_walk_nn" or "k_kd_walk_fof")."""
+        """(box tests, distances) counted by a tree walk since the last reset:
+        "k_kd_walk_nn" or "k_kd_walk_fof"; for "k_bh_walk" (cells tested,
+        terms added), summed over target particles."""
         t, e = C.c_double(0.0), C.c_double(0.0)
         self._check(self.L.libhalo_profile_work(self.h, kernel.encode(), C.byref(t), C.byref(e)))
         return t.value, e.value

@@ -72,7 +72,7 @@ def test_counting_allocator_sees_every_block(H, c1):
 
 @pytest.mark.parametrize("stage", ["fof3d", "refine6d", "assign", "unbind", "props"])
 def test_refused_workspace_is_enomem(H, c1, stage):
-    """An allocator that refuses every block above 4 KiB (the 256-byte error word
+    """An allocator that refuses every block above 4 KiB (the 4 KiB error block
     of the context passes): the stage fails with ENOMEM and its outputs keep the
     values they had."""
     note(f"allocator: refused workspace in {stage}")
