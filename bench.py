@@ -33,16 +33,16 @@ FP32_PEAK_TFLOPS = 157.3
 # that workload and while the kernel's source file is the one that was measured.
 TRAFFIC_WORKLOAD = "c5"
 MEASURED_TRAFFIC = {
-    "k_kd_walk_nn": {"bytes": 834.96e9, "src": "paper_1110_4372_amd/csrc/grid6d.hip",
-                     "sha1": "de973f44a14e221b464ec6426ead62ea464d6851"},
-    "k_kd_walk_fof": {"bytes": 847.89e9, "src": "paper_1110_4372_amd/csrc/grid6d.hip",
-                      "sha1": "de973f44a14e221b464ec6426ead62ea464d6851"},
-    "k_bh_walk": {"bytes": 1197.01e9, "src": "paper_1110_4372_amd/csrc/bh.hip",
-                  "sha1": "7bb5498ec9e5e22ab06838879807dacf5838cc9c"},
+    "k_kd_walk_nn": {"bytes": 813.18e9, "src": "paper_1110_4372_amd/csrc/grid6d.hip",
+                     "sha1": "5b23b1a594377e6efa724163babf38e2498f041a"},
+    "k_kd_walk_fof": {"bytes": 1031.75e9, "src": "paper_1110_4372_amd/csrc/grid6d.hip",
+                      "sha1": "5b23b1a594377e6efa724163babf38e2498f041a"},
+    "k_bh_walk": {"bytes": 893.13e9, "src": "paper_1110_4372_amd/csrc/bh.hip",
+                  "sha1": "ea0600a2a6c3c83837bed5b3df67f19653826d25"},
     "k_nn": {"bytes": 12.08e9, "src": "paper_1110_4372_amd/csrc/refine6d.hip",
-             "sha1": "7a5e971ed55d71692fce27afab6d5a05f91294d8"},
-    "k_potential_f32": {"bytes": 79.05e9, "src": "paper_1110_4372_amd/csrc/unbind.hip",
-                        "sha1": "6b882e5ae109c187bb5620ac38b6ce24a9d6d9c7"},
+             "sha1": "0c055acd8163a6a20f1e64b21ae4ebd8b3ee9759"},
+    "k_potential_f32": {"bytes": 79.06e9, "src": "paper_1110_4372_amd/csrc/unbind.hip",
+                        "sha1": "dbdba7d8c4184fb3855f03c259eb61334f9fd199"},
 }
 
 
