@@ -42,7 +42,7 @@ MEASURED_TRAFFIC = {
     "k_nn": {"bytes": 12.08e9, "src": "paper_1110_4372_amd/csrc/refine6d.hip",
              "sha1": "0c055acd8163a6a20f1e64b21ae4ebd8b3ee9759"},
     "k_potential_f32": {"bytes": 79.06e9, "src": "paper_1110_4372_amd/csrc/unbind.hip",
-                        "sha1": "dbdba7d8c4184fb3855f03c259eb61334f9fd199"},
+                        "sha1": "66a78c9204fb5c49b7dd21c0ecfe8abb099d467a"},
 }
 
 

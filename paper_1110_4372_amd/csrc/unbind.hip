@@ -887,11 +887,16 @@ __global__ void __launch_bounds__(TB)
   }
 }
 
+// Energies and bound flags.  Mixed form: a particle whose energy lies within
+// e_rel of zero is listed for the FP64 recheck instead, unless its halo took
+// the tree potential, whose error (set by theta) dwarfs FP32 rounding: its
+// flag is the tree's, as in the FP64 form with the tree.
 __global__ void k_energy(const double* sum, const float* lvx, const float* lvy,
                          const float* lvz, const uint32_t* lhalo, const uint32_t* lp,
                          const double* vb, uint32_t m, double mGm, double e_rel, int mixed,
-                         uint8_t* bound, double* phi, uint32_t* nb_own, uint32_t* rlist,
-                         uint32_t* nr) {
+                         const libhalo_halos h, const uint32_t* nS, double bh_theta,
+                         uint32_t bh_min, uint8_t* bound, double* phi, uint32_t* nb_own,
+                         uint32_t* rlist, uint32_t* nr) {
   const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = q < m;
   uint32_t hh = 0;
@@ -905,7 +910,9 @@ __global__ void k_energy(const double* sum, const float* lvx, const float* lvy,
                  uz = (double)lvz[q] - vb[3 * (size_t)hh + 2];
     const double k = 0.5 * sq3(ux, uy, uz);
     const double e = k + ph;
-    if (mixed && fabs(e) < e_rel * (k + fabs(ph))) {
+    const bool tree = bh_takes(h.merged_into[hh] == (int32_t)hh, h.n_assigned[hh], nS[hh],
+                               bh_theta, bh_min);
+    if (mixed && !tree && fabs(e) < e_rel * (k + fabs(ph))) {
       rlist[atomicAdd(nr, 1u)] = q;  // decided after the FP64 recheck
     } else {
       b = e < 0.0;
@@ -1162,8 +1169,9 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     k_pot_finish<<<blocks_for(m, TB), TB, 0, s>>>(w.pacc, m, w.sum);
     k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 3, 1, 0u);
     k_energy<<<blocks_for(m, TB), TB, 0, s>>>(w.sum, w.lvx, w.lvy, w.lvz, w.lhalo, w.lp, w.vb, m,
-                                             mGm, P.e_recheck, mixed ? 1 : 0, bound, phi,
-                                             w.nb_own, w.rlist, w.dcnt + 3);
+                                             mGm, P.e_recheck, mixed ? 1 : 0, h, w.nS,
+                                             P.bh_theta, bh_min, bound, phi, w.nb_own,
+                                             w.rlist, w.dcnt + 3);
     if (mixed) {
       k_recheck<<<1024, TB, 0, s>>>(w.ux, w.uy, w.uz, w.lhalo, w.tgt, w.slot, w.nS, w.rlist,
                                     w.dcnt + 3, eps2, w.sum);
