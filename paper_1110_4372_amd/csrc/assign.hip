@@ -871,8 +871,9 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
       k_metric_weights<<<blocks_for(S, TB), TB, 0, s>>>(cur_sv2, cur_vm2, S, cdyn, w.sm);
     }
     if (q1 > q0)
-      k_assign_level<T><<<blocks_for(q1 - q0, TB), TB, 0, s>>>(
-          x, y, z, vx, vy, vz, box, own, okey, q0, q1, soff, ids, w.sm, halo_of);
+      HALO_PROF(ctx, "k_assign_level", s,
+                (k_assign_level<T><<<blocks_for(q1 - q0, TB), TB, 0, s>>>(
+                    x, y, z, vx, vy, vz, box, own, okey, q0, q1, soff, ids, w.sm, halo_of)));
   }
 
   // ---- final metric of every halo from all its particles
