@@ -98,8 +98,9 @@ def progress(msg):
         print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
-HOT = ("k_kd_walk_nn", "k_kd_walk_fof", "k_bh_walk", "k_nn", "k_fof6", "k_potential_f64",
-       "k_potential_f32", "k_link", "k_mom_accum", "k_select_small", "k_assign_level")
+HOT = ("k_kd_walk_nn", "k_kd_walk_fof", "k_kd_group_fof", "k_bh_walk", "k_nn", "k_fof6",
+       "k_potential_f64", "k_potential_f32", "k_link", "k_mom_accum", "k_select_small",
+       "k_assign_level")
 WALKS = ("k_kd_walk_nn", "k_kd_walk_fof", "k_bh_walk")
 
 

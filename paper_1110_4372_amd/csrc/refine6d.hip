@@ -1134,6 +1134,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
                 k_fof6<<<pgrid, TB, 0, s>>>(cxi, S, cnodes, lpos, K, sc.wpair, 0, K,
                                                dcnt + 8, sc.ell2, pj, par));
     }
+    HALO_PROF(ctx, "k_kd_group_fof", s, grid_fof_groups(gb, sc, D, par, s));
     HALO_PROF(ctx, "k_kd_walk_fof", s, grid_fof(gb, sc, D, par, ctx.work_counters(), s));
     k_compress<<<blocks_for(Mi, TB), TB, 0, s>>>(par, Mi);
     // 6. children

@@ -74,6 +74,7 @@ __host__ __device__ inline uint32_t default_grid_min(uint32_t level_particles) {
 constexpr uint32_t kGridFloor = 64;   // smallest accepted threshold
 constexpr uint32_t kKdLeaf = 16;      // default: a tree node of at most this many particles is a leaf
 constexpr int kKdMaxDepth = 64;       // nodes at this depth are leaves whatever their size
+constexpr uint32_t kFofGroup = 64;    // most points of a group of the FOF search's first pass
 
 // A tree node as the walks read it, in depth-first preorder (first child
 // first) so that a node's first child is the next record and `skip` is the
@@ -98,6 +99,8 @@ struct GridBufs {
   uint32_t *pm, *pb; // their positions in the level arrays and their grid nodes
   KdNode* node;      // tree nodes in preorder; tree b is [troot[b], troot[b+1])
   uint4* up;         // per node: parent, sibling, the record after the sibling's subtree
+  uint32_t* gskip;   // per sorted point: the record after its first-pass group's subtree
+  uint32_t* uroot;   // per node of at most kFofGroup points: the root all its points share
   const uint32_t* troot;
   void* rtmp;
   MTree* mt;         // host object: the trees' topology (mtree.hpp)
@@ -118,6 +121,12 @@ void grid_nn(GridBufs& g, NodeScratch sc, uint32_t* D, unsigned long long* work,
 // (may be null): box tests and distances added to work[2], [3].
 void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par,
               unsigned long long* work, hipStream_t s);
+// First pass of that FOF: links the pairs within each group (the largest
+// subtree of at most kFofGroup points holding a point's leaf), then records
+// the nodes of at most kFofGroup points whose points share one root.  Runs
+// before grid_fof, which then skips each point's own group.
+void grid_fof_groups(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par,
+                     hipStream_t s);
 
 // min over j in [j0, j1) of d2(i, j) over six FP32 coordinate planes of stride
 // S; j is wave-uniform, so the j coordinates are scalar loads feeding the
