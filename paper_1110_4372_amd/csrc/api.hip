@@ -93,6 +93,11 @@ void Ctx::release() {
   if (ws2.base) free_fn(ws2.base, user, (void*)stream);
   if (d_err) free_fn(d_err, user, nullptr);
   if (h_pinned) (void)hipHostFree(h_pinned);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (side) (void)hipStreamDestroy(side);
+  ev_fork = ev_join = nullptr;
+  side = nullptr;
   ws.base = ws2.base = nullptr;
   ws.cap = ws2.cap = 0;
   d_err = nullptr;
@@ -148,9 +153,13 @@ static int guarded(libhalo_ctx* ctx, F&& f, void* stream = nullptr) {
     return LIBHALO_OK;
   } catch (const halo::Error& e) {
     ctx->c.err = e.msg;
+    // an error between a fork and its join leaves side work queued: let it end
+    // before anything can grow or free the workspace it uses
+    (void)hipStreamSynchronize(ctx->c.side);
     return e.code;
   } catch (const std::bad_alloc&) {
     ctx->c.err = "host allocation failed";
+    (void)hipStreamSynchronize(ctx->c.side);
     return LIBHALO_ENOMEM;
   }
 }
@@ -179,6 +188,10 @@ int libhalo_ctx_create(const libhalo_params* p, int device, libhalo_alloc_fn all
       hipHostMalloc(&c->c.h_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
     rc = LIBHALO_EHIP;
   } else if (halo::scratch_setup(device, &c->c.scratch) != hipSuccess) {
+    rc = LIBHALO_EHIP;
+  } else if (hipStreamCreateWithFlags(&c->c.side, hipStreamNonBlocking) != hipSuccess ||
+             hipEventCreateWithFlags(&c->c.ev_fork, hipEventDisableTiming) != hipSuccess ||
+             hipEventCreateWithFlags(&c->c.ev_join, hipEventDisableTiming) != hipSuccess) {
     rc = LIBHALO_EHIP;
   } else {
     c->c.d_err = static_cast<uint32_t*>(alloc_fn(halo::kErrBlockBytes, user, nullptr));

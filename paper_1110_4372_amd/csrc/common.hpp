@@ -100,6 +100,21 @@ struct Ctx {
                                    // kBhSlots pairs at byte 1024, 64 bytes apart
   void* h_pinned = nullptr;        // small pinned host buffer for read-backs
   hipStream_t stream = nullptr;    // stream of the entry point being run
+  // A second stream of the context (default priority) for work that is
+  // independent of what runs meanwhile on the entry point's stream: fork()
+  // starts it after the work queued so far on s, join() makes s wait for it.
+  // Every fork is joined before the entry point returns.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t fork(hipStream_t s) {
+    HALO_HIP(hipEventRecord(ev_fork, s));
+    HALO_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+    return side;
+  }
+  void join(hipStream_t s) {
+    HALO_HIP(hipEventRecord(ev_join, side));
+    HALO_HIP(hipStreamWaitEvent(s, ev_join, 0));
+  }
   libhalo_alloc_fn alloc_fn = nullptr;  // workspace provider (caller's callbacks)
   libhalo_free_fn free_fn = nullptr;
   void* user = nullptr;

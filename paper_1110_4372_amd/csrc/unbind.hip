@@ -1125,19 +1125,24 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     if (mixed)
       k_rel_f32<<<blocks_for(m, TB), TB, 0, s>>>(w.ux, w.uy, w.uz, h, w.slot, w.lhalo, m, w.fx,
                                                  w.fy, w.fz);
+    // With the tree potential on, the direct sums of the other haloes run on
+    // the side stream beside it: both add into the fixed-point sums of
+    // disjoint particles.
+    const bool tree = P.bh_theta > 0.0;
+    hipStream_t sp = s;  // stream of the direct sums
     auto launch = [&](uint32_t u0, uint32_t u1, uint32_t* ctr, unsigned grid) {
       with_pot_chunk(P.pot_chunk, [&](auto Jc) {
         constexpr uint32_t J = decltype(Jc)::value;
         if (mixed)
-          HALO_PROF(ctx, "k_potential_f32", s,
-                    k_potential_f32<J><<<grid, TB, 0, s>>>(w.fx, w.fy, w.fz, h, order, w.uoff,
-                                                           S, w.slot, w.nS, u0, u1, ctr,
-                                                           (float)eps2, w.pacc));
+          HALO_PROF(ctx, "k_potential_f32", sp,
+                    k_potential_f32<J><<<grid, TB, 0, sp>>>(w.fx, w.fy, w.fz, h, order, w.uoff,
+                                                            S, w.slot, w.nS, u0, u1, ctr,
+                                                            (float)eps2, w.pacc));
         else
-          HALO_PROF(ctx, "k_potential_f64", s,
-                    k_potential_f64<J><<<grid, TB, 0, s>>>(w.ux, w.uy, w.uz, h, order, w.uoff,
-                                                           S, w.slot, w.nS, u0, u1, ctr, eps2,
-                                                           w.pacc));
+          HALO_PROF(ctx, "k_potential_f64", sp,
+                    k_potential_f64<J><<<grid, TB, 0, sp>>>(w.ux, w.uy, w.uz, h, order, w.uoff,
+                                                            S, w.slot, w.nS, u0, u1, ctr, eps2,
+                                                            w.pacc));
       });
     };
     if (plain) {
@@ -1148,17 +1153,20 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       HALO_HIP(hipStreamSynchronize(s));
       std::vector<uint32_t> pos(S);
       for (uint32_t k = 0; k < S; ++k) pos[ord[k]] = k;
+      if (tree) sp = ctx.fork(s);
       for (uint32_t hh = 0; hh < S; ++hh) {
         const uint32_t k = pos[hh], nu = ho[k + 1] - ho[k];
         if (nu) launch(ho[k], ho[k + 1], nullptr, nu);
       }
     } else if (U > 0) {
       k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 4, 1, 0u);
+      if (tree) sp = ctx.fork(s);
       launch(0, U, w.dcnt + 4, std::min<uint32_t>(kPersist, U));
     }
-    if (P.bh_theta > 0.0)
+    if (tree)
       bh_potential(ctx, h, S, w.nS, w.slot, w.ux, w.uy, w.uz, eps2, P.bh_theta, bh_min, w.pacc,
                    s);
+    if (sp != s) ctx.join(s);
     if (P.major_merger > 0.0) {
       k_ext_counts<<<blocks_for(S + 1, TB), TB, 0, s>>>(h, S, w.tgt, w.nS, w.ecnt);
       exclusive_scan<uint32_t>(w.ecnt, w.eoff, S + 1, w.dcnt + 5, w.stmp, s);
