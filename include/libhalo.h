@@ -132,6 +132,14 @@ typedef struct {
   int32_t bh_leaf;          /* most particles of a leaf of the tree potential's
                                trees, in [4, 64] (0 = 16); changes which cells are
                                accepted, so phi changes within the theta bound */
+  double nn_bracket;        /* exact ell (ell_subset = 0), tree-searched nodes of more
+                               than 4096 particles: the nearest-neighbour walks stop
+                               once a point's distance is certainly below or above a
+                               bracket of ell^2 taken from every 32nd point's exact
+                               distance, nn_bracket binomial standard deviations of
+                               the sample rank either side (0 = 4); a node whose
+                               ell^2 falls outside its bracket walks again without
+                               one.  < 0: no bracket.  No result bit depends on it */
 } libhalo_params;
 
 /* Node table (refine6d output), structure of arrays, capacity `cap` rows.

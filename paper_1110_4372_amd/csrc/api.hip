@@ -137,6 +137,7 @@ static std::string validate(const libhalo_params& p) {
     return "pot_chunk must be 0, 1024, 2048 or 4096";
   if (p.kd_leaf != 0 && (p.kd_leaf < 4 || p.kd_leaf > 64)) return "kd_leaf must be 0 or in [4, 64]";
   if (p.bh_leaf != 0 && (p.bh_leaf < 4 || p.bh_leaf > 64)) return "bh_leaf must be 0 or in [4, 64]";
+  if (!std::isfinite(p.nn_bracket)) return "nn_bracket must be finite";
   return "";
 }
 

@@ -232,6 +232,8 @@ __global__ void __launch_bounds__(kWalkTB)
               uint32_t MB, const uint32_t* __restrict__ gnode, NodeScratch sc, uint32_t* D,
               uint32_t* par, uint32_t* queue, const uint4* __restrict__ UP,
               const uint32_t* __restrict__ GS, const uint32_t* __restrict__ UR,
+              uint32_t MQ, uint32_t stride, const float* __restrict__ TL,
+              const float* __restrict__ TH, const uint32_t* __restrict__ ONLY,
               unsigned long long* work) {
   const uint32_t lane = threadIdx.x & 63u;
   const unsigned long long below = (1ull << lane) - 1ull;
@@ -244,6 +246,7 @@ __global__ void __launch_bounds__(kWalkTB)
   uint32_t anc = 0, root = 0;  // MODE 0: the node whose sibling subtree is walked
   float a[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   float best = __int_as_float(0x7F800000);  // MODE 0: nearest so far
+  float tlo = 0.0f;                         // MODE 0: the walk ends once best < tlo
   float l2 = 0.0f;                          // MODE 1: ell^2 of the node
   uint32_t ntest = 0, neval = 0;            // work counts (profiling)
   while (true) {
@@ -252,9 +255,9 @@ __global__ void __launch_bounds__(kWalkTB)
       const unsigned long long idle = __ballot(!active);
       if (idle == 0) break;
       if (cnext >= kWalkChunk) {
-        // range qx holds the points [MB qx / 8, MB (qx + 1) / 8)
-        const uint32_t r0 = (uint32_t)(((unsigned long long)MB * qx) >> 3);
-        const uint32_t r1 = (uint32_t)(((unsigned long long)MB * (qx + 1u)) >> 3);
+        // range qx holds the queries [MQ qx / 8, MQ (qx + 1) / 8)
+        const uint32_t r0 = (uint32_t)(((unsigned long long)MQ * qx) >> 3);
+        const uint32_t r1 = (uint32_t)(((unsigned long long)MQ * (qx + 1u)) >> 3);
         uint32_t c = 0;
         if (lane == 0) c = atomicAdd(queue + 16u * qx, kWalkChunk);
         c = __shfl(c, 0);
@@ -271,7 +274,7 @@ __global__ void __launch_bounds__(kWalkTB)
       const uint32_t avail = min(kWalkChunk - cnext, left);
       const uint32_t rank = (uint32_t)__popcll(idle & below);
       if (!active && rank < avail) {
-        q = cbase + cnext + rank;
+        q = (cbase + cnext + rank) * stride;  // query -> sorted point
         for (int c = 0; c < 6; ++c) a[c] = pt[6ull * q + c];
         const uint32_t b = pb[q];
         m = pm[q];
@@ -282,8 +285,9 @@ __global__ void __launch_bounds__(kWalkTB)
           root = troot[b];
           anc = own;
           u = end = 0u;  // no subtree yet: the first step goes up from the own leaf
-          best = __int_as_float(0x7F800000);
-          active = true;
+          best = TH ? TH[b] : __int_as_float(0x7F800000);
+          tlo = TL ? TL[b] : 0.0f;
+          active = ONLY == nullptr || ONLY[b] != 0u;
         } else {
           end = troot[b + 1];  // the record after the point's tree
           l2 = sc.ell2[gnode[b]];
@@ -321,6 +325,10 @@ __global__ void __launch_bounds__(kWalkTB)
         }
         lo = jn;
         have = jn < hi;
+        if (MODE == 0 && best < tlo) {  // certainly below the bracket: done
+          D[m] = __float_as_uint(best);
+          active = false;
+        }
       } else if (u >= end) {
         if (MODE == 1 || anc == root) {
           if (MODE == 0) D[m] = __float_as_uint(best);
@@ -447,6 +455,10 @@ void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax, uint32_t leaf) 
   g.gnode = A.take<uint32_t>(NBmax);
   g.pstart = A.take<uint32_t>(NBmax + 1);
   g.gcount = A.take<uint32_t>(NBmax + 1);
+  g.tl = A.take<float>(NBmax + 1);
+  g.th = A.take<float>(NBmax + 1);
+  g.tmap = A.take<uint32_t>(NBmax + 1);
+  g.redo = A.take<uint32_t>(NBmax + 1);
   // tree nodes: the capacity bounds memory, not results (a node that finds no
   // room for its children stays a leaf and is searched in full); trees of
   // leaves of at most L particles use about 3.2 / L nodes per particle
@@ -514,18 +526,19 @@ uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint3
   return NB;
 }
 
-void grid_nn(GridBufs& g, NodeScratch sc, uint32_t* D, unsigned long long* work,
-             hipStream_t s) {
+void grid_nn(GridBufs& g, NodeScratch sc, uint32_t* D, uint32_t stride, const float* tl,
+             const float* th, const uint32_t* only, unsigned long long* work, hipStream_t s) {
   if (g.NB == 0 || g.MB == 0) return;
+  const uint32_t MQ = (g.MB + stride - 1) / stride;
   k_fill_u32<<<1, 128, 0, s>>>(g.queue, 128, 0u);
   if (work)
-    k_kd_walk<0, true><<<walk_grid(g.MB), kWalkTB, 0, s>>>(
+    k_kd_walk<0, true><<<walk_grid(MQ), kWalkTB, 0, s>>>(
         g.node, g.pt, g.pm, g.pb, g.leafof, g.troot, g.MB, g.gnode, sc, D, nullptr, g.queue,
-        g.up, nullptr, nullptr, work);
+        g.up, nullptr, nullptr, MQ, stride, tl, th, only, work);
   else
-    k_kd_walk<0, false><<<walk_grid(g.MB), kWalkTB, 0, s>>>(
+    k_kd_walk<0, false><<<walk_grid(MQ), kWalkTB, 0, s>>>(
         g.node, g.pt, g.pm, g.pb, g.leafof, g.troot, g.MB, g.gnode, sc, D, nullptr, g.queue,
-        g.up, nullptr, nullptr, nullptr);
+        g.up, nullptr, nullptr, MQ, stride, tl, th, only, nullptr);
 }
 
 void grid_fof_groups(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par,
@@ -545,11 +558,11 @@ void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par,
   if (work)
     k_kd_walk<1, true><<<walk_grid(g.MB), kWalkTB, 0, s>>>(
         g.node, g.pt, g.pm, g.pb, g.leafof, g.troot, g.MB, g.gnode, sc, Dm, par, g.queue, g.up,
-        g.gskip, g.uroot, work);
+        g.gskip, g.uroot, g.MB, 1u, nullptr, nullptr, nullptr, work);
   else
     k_kd_walk<1, false><<<walk_grid(g.MB), kWalkTB, 0, s>>>(
         g.node, g.pt, g.pm, g.pb, g.leafof, g.troot, g.MB, g.gnode, sc, Dm, par, g.queue, g.up,
-        g.gskip, g.uroot, nullptr);
+        g.gskip, g.uroot, g.MB, 1u, nullptr, nullptr, nullptr, nullptr);
 }
 
 }  // namespace refine

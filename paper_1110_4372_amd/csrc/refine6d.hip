@@ -739,8 +739,10 @@ __global__ void __launch_bounds__(TB)
 }
 
 // One wave per big node: reads and clears its histogram, then narrows the
-// prefix and the rank to the selected bin.
-__global__ void k_select_big_resolve(NodeScratch sc, const uint32_t* nbig, int pass) {
+// prefix and the rank to the selected bin.  The value goes to the node's
+// ell^2, or, with out, to out[omap[b]].
+__global__ void k_select_big_resolve(NodeScratch sc, const uint32_t* nbig, int pass, float* out,
+                                     const uint32_t* omap) {
   const uint32_t B = nbig[0];
   const int shift = 24 - 8 * pass;
   const uint32_t lane = threadIdx.x & 63u;
@@ -762,9 +764,95 @@ __global__ void k_select_big_resolve(NodeScratch sc, const uint32_t* nbig, int p
         sc.selp[2 * b] = pre;
         sc.selp[2 * b + 1] = rest;
       }
-      if (pass == 3) sc.ell2[sc.big[b]] = __uint_as_float(pre);
+      if (pass == 3) (out ? out[omap[b]] : sc.ell2[sc.big[b]]) = __uint_as_float(pre);
     }
   }
+}
+
+// ------------------------------------------- nearest-neighbour bracket ----
+// ell^2 is the kth smallest D of a node, and only the points whose D lies
+// near it need their exact distance: a point with D < ell^2 is linkable
+// whatever its D, one with D > ell^2 is not.  For a tree node of more than
+// kSelSmall points, the exact D of every kNNSample-th sorted point brackets
+// the kth value by two sample order statistics [tl, th), kBracketSigma
+// binomial standard deviations of the sample rank either side; the walks of
+// all points then start with th as their best distance and end once it is
+// below tl.  The stored D is exact inside [tl, th), below tl where the true
+// one is, and th where the true one is th or more, so the kth smallest stored
+// value is the exact ell^2 whenever it lies inside [tl, th); otherwise the
+// node's walks are run again without a bracket.
+constexpr uint32_t kNNSample = 32;
+constexpr double kBracketSigma = 4.0;
+
+// Sample count and 1-based sample ranks [rlo, rhi] bracketing the node's kth
+// value; rlo < 1: no lower bound, rhi > ms: no upper bound.
+__device__ __forceinline__ void bracket_ranks(uint32_t n, uint32_t kth, uint32_t p0, double z,
+                                              uint32_t& ms, int64_t& rlo, int64_t& rhi) {
+  ms = (p0 + n + kNNSample - 1) / kNNSample - (p0 + kNNSample - 1) / kNNSample;
+  const double rho = ((double)kth - 0.5) / (double)n;
+  const double c = rho * (double)ms;
+  const double sig = sqrt((double)ms * rho * (1.0 - rho)) + 1.0;
+  rlo = (int64_t)floor(c - z * sig);
+  rhi = (int64_t)ceil(c + z * sig) + 1;
+}
+
+__global__ void k_bracket_flags(GridBufs g, LevelNodes nd, uint32_t NB, uint32_t* flag) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB) return;
+  flag[b] = nd.count[g.gnode[b]] > (uint32_t)kSelSmall ? 1u : 0u;
+  g.tl[b] = 0.0f;
+  g.th[b] = __int_as_float(0x7F800000);
+}
+
+// The selection list of the bracketed trees for sample rank rlo (hi = 0) or
+// rhi (hi = 1); a rank outside the sample selects nothing (kth 0).
+__global__ void k_bracket_list(GridBufs g, LevelNodes nd, NodeScratch sc, uint32_t NB,
+                               const uint32_t* flag, const uint32_t* pos, double z, int hi) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB || !flag[b]) return;
+  const uint32_t k = g.gnode[b], n = nd.count[k], i = pos[b];
+  uint32_t ms;
+  int64_t rlo, rhi;
+  bracket_ranks(n, sc.kth[k], g.pstart[b], z, ms, rlo, rhi);
+  const int64_t r = hi ? rhi : rlo;
+  sc.big[i] = k;
+  sc.wbig[i] = (n + kSelTile - 1) / kSelTile;
+  sc.selp[2 * i] = 0;
+  sc.selp[2 * i + 1] = (r >= 1 && r <= (int64_t)ms) ? (uint32_t)r : 0u;
+  g.tmap[i] = b;
+}
+
+// Ranks outside the sample: no bound on that side.  An empty bracket (equal
+// sample values) would always fail, so such a tree walks without one.
+__global__ void k_bracket_final(GridBufs g, LevelNodes nd, NodeScratch sc, uint32_t NB,
+                                const uint32_t* flag, double z) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB || !flag[b]) return;
+  const uint32_t k = g.gnode[b];
+  uint32_t ms;
+  int64_t rlo, rhi;
+  bracket_ranks(nd.count[k], sc.kth[k], g.pstart[b], z, ms, rlo, rhi);
+  float lo = g.tl[b], hi = g.th[b];
+  if (rlo < 1) lo = 0.0f;
+  if (rhi > (int64_t)ms) hi = __int_as_float(0x7F800000);
+  if (!(lo < hi)) {
+    lo = 0.0f;
+    hi = __int_as_float(0x7F800000);
+  }
+  g.tl[b] = lo;
+  g.th[b] = hi;
+}
+
+// A tree whose ell^2 fell outside its bracket walks again without one.
+__global__ void k_bracket_check(GridBufs g, NodeScratch sc, uint32_t NB, uint32_t* nredo) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB) return;
+  const float lo = g.tl[b], hi = g.th[b];
+  const bool bracketed = lo > 0.0f || hi < __int_as_float(0x7F800000);
+  const float l2 = sc.ell2[g.gnode[b]];
+  const bool redo = bracketed && !(l2 >= lo && l2 < hi);
+  g.redo[b] = redo ? 1u : 0u;
+  if (redo) atomicAdd(nredo, 1u);
 }
 
 // ------------------------------------------------------------ children -----
@@ -1067,7 +1155,34 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     HALO_PROF(ctx, "grid_build", s,
               grid_build(gb, xi, S, nd, K, lnode, Mi, M, sc, rd.h + 8, s,
                          P.grid_min > 0 ? (uint32_t)P.grid_min : default_grid_min(Mi)));
-    HALO_PROF(ctx, "k_kd_walk_nn", s, grid_nn(gb, sc, D, ctx.work_counters(), s));
+    // a bracket of ell^2 from sampled walks, then every point's walk within it
+    const bool bracket = msub == 0 && gb.NB > 0 && P.nn_bracket >= 0.0;
+    const double zb = P.nn_bracket > 0.0 ? P.nn_bracket : kBracketSigma;
+    if (bracket) {
+      const uint32_t NB = gb.NB;
+      HALO_PROF(ctx, "k_kd_walk_nn", s,
+                grid_nn(gb, sc, D, kNNSample, nullptr, nullptr, nullptr, ctx.work_counters(),
+                        s));
+      k_bracket_flags<<<blocks_for(NB, TB), TB, 0, s>>>(gb, nd, NB, cflag);
+      exclusive_scan<uint32_t>(cflag, head, NB, dcnt + 10, stmp, s);
+      for (int hi = 0; hi < 2; ++hi) {
+        k_fill_u32<<<blocks_for(NB + 1, TB), TB, 0, s>>>(sc.wbig, NB + 1, 0u);
+        k_bracket_list<<<blocks_for(NB, TB), TB, 0, s>>>(gb, nd, sc, NB, cflag, head, zb, hi);
+        exclusive_scan<uint32_t>(sc.wbig, sc.wbig, NB, sc.wbig + NB, stmp, s);
+        k_zero_hist<<<64, TB, 0, s>>>(sc, dcnt + 10);
+        for (int pass = 0; pass < 4; ++pass) {
+          k_select_big_hist<<<pgrid, TB, 0, s>>>(D, nd, sc, dcnt + 10, pass);
+          k_select_big_resolve<<<blocks_for(NB, TB / 64), TB, 0, s>>>(
+              sc, dcnt + 10, pass, hi ? gb.th : gb.tl, gb.tmap);
+        }
+      }
+      k_bracket_final<<<blocks_for(NB, TB), TB, 0, s>>>(gb, nd, sc, NB, cflag, zb);
+      HALO_PROF(ctx, "k_kd_walk_nn", s,
+                grid_nn(gb, sc, D, 1, gb.tl, gb.th, nullptr, ctx.work_counters(), s));
+    } else {
+      HALO_PROF(ctx, "k_kd_walk_nn", s,
+                grid_nn(gb, sc, D, 1, nullptr, nullptr, nullptr, ctx.work_counters(), s));
+    }
     k_pair_items<<<blocks_for(K, TB), TB, 0, s>>>(nd.count, sc.prm, sc.gstate, K, nnj,
                                                    sc.wpair);
     exclusive_scan<uint32_t>(sc.wpair, sc.wpair, K, sc.wpair + K, stmp, s);
@@ -1108,11 +1223,21 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
         k_zero_hist<<<64, TB, 0, s>>>(sc, dcnt);
         for (int pass = 0; pass < 4; ++pass) {
           k_select_big_hist<<<pgrid, TB, 0, s>>>(Dsl, nd, sc, dcnt, pass);
-          k_select_big_resolve<<<blocks_for(nbig, TB / 64), TB, 0, s>>>(sc, dcnt, pass);
+          k_select_big_resolve<<<blocks_for(nbig, TB / 64), TB, 0, s>>>(sc, dcnt, pass,
+                                                                        nullptr, nullptr);
         }
       }
     };
     if (Mi > (uint32_t)kSelSmall) select_big();  // else no node is above kSelSmall
+    if (bracket) {  // ell^2 outside a tree's bracket: its exact walks, then select again
+      k_fill_u32<<<1, 64, 0, s>>>(dcnt + 11, 1, 0u);
+      k_bracket_check<<<blocks_for(gb.NB, TB), TB, 0, s>>>(gb, sc, gb.NB, dcnt + 11);
+      if (rd.get(dcnt + 11, 16) > 0) {
+        HALO_PROF(ctx, "k_kd_walk_nn", s,
+                  grid_nn(gb, sc, D, 1, nullptr, nullptr, gb.redo, ctx.work_counters(), s));
+        select_big();
+      }
+    }
     // 5. 6D FOF: all-pairs nodes over their compacted linkable particles
     k_link_flags<<<blocks_for(Mi, TB), TB, 0, s>>>(lnode, D, Mi, sc, cflag);
     exclusive_scan<uint32_t>(cflag, crank, Mi, crank + Mi, stmp, s);

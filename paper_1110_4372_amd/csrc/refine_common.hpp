@@ -103,6 +103,11 @@ struct GridBufs {
   uint32_t* uroot;   // per node of at most kFofGroup points: the root all its points share
   const uint32_t* troot;
   void* rtmp;
+  // nearest-neighbour bracket of each tree node b: walks start at best = th[b]
+  // and end once best < tl[b]; tmap lists the bracketed trees, redo flags a
+  // tree whose ell^2 fell outside its bracket
+  float *tl, *th;
+  uint32_t *tmap, *redo;
   MTree* mt;         // host object: the trees' topology (mtree.hpp)
   uint32_t MB = 0, NB = 0;  // sorted points, grid nodes
   uint32_t leaf = kKdLeaf;  // most points of a leaf
@@ -114,9 +119,16 @@ void grid_take(Arena& A, GridBufs& g, uint32_t M, uint32_t Kmax, uint32_t leaf);
 uint32_t grid_build(GridBufs& g, const float* xi, size_t S, LevelNodes nd, uint32_t K,
                     const uint32_t* lnode, uint32_t Mi, uint32_t M, NodeScratch sc,
                     uint32_t* hb, hipStream_t s, uint32_t gmin);
-// Exact nearest-neighbour distances of the tree nodes' particles into D.
-// work (may be null): adds the walk's box tests and distances to work[0], [1].
-void grid_nn(GridBufs& g, NodeScratch sc, uint32_t* D, unsigned long long* work, hipStream_t s);
+// Nearest-neighbour walks of the tree nodes' particles, one per stride-th
+// sorted point (1: every point).  tl, th (may be null: 0 and +inf): the walk
+// of a point of tree b starts with th[b] as its best distance and ends as
+// soon as its best is below tl[b], so D[m] is exact when it lies in
+// [tl[b], th[b]), below tl[b] (an upper bound) when the true distance is, and
+// th[b] when the true distance is at least th[b].  only (may be null): walk
+// just the trees b with only[b] != 0.  work (may be null): adds the walk's
+// box tests and distances to work[0], [1].
+void grid_nn(GridBufs& g, NodeScratch sc, uint32_t* D, uint32_t stride, const float* tl,
+             const float* th, const uint32_t* only, unsigned long long* work, hipStream_t s);
 // 6D FOF at each tree node's ell^2 over its particles with D <= ell^2; work
 // (may be null): box tests and distances added to work[2], [3].
 void grid_fof(GridBufs& g, NodeScratch sc, const uint32_t* D, uint32_t* par,

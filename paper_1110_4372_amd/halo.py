@@ -38,7 +38,7 @@ class CParams(C.Structure):
                 ("ell_subset", C.c_int32), ("major_merger", C.c_double),
                 ("fof_dense", C.c_int32), ("bh_min", C.c_int32), ("bh_theta", C.c_double),
                 ("nn_chunk", C.c_int32), ("fof_chunk", C.c_int32), ("pot_chunk", C.c_int32),
-                ("kd_leaf", C.c_int32), ("bh_leaf", C.c_int32)]
+                ("kd_leaf", C.c_int32), ("bh_leaf", C.c_int32), ("nn_bracket", C.c_double)]
 
 
 @dataclasses.dataclass
@@ -73,6 +73,9 @@ class Params:
     # leaf sizes of the 6D search trees and of the tree potential (0 = 16)
     kd_leaf: int = 0
     bh_leaf: int = 0
+    # nearest-neighbour bracket of ell^2 in sample standard deviations (0 = 4;
+    # < 0: every walk exact; speed only)
+    nn_bracket: float = 0.0
 
     def c(self) -> CParams:
         return CParams(self.box, self.b, self.f, self.min_members, self.max_levels,
@@ -81,7 +84,7 @@ class Params:
                        self.e_recheck, self.mode, self.prec, self.grid_min,
                        self.ell_subset, self.major_merger, self.fof_dense, self.bh_min,
                        self.bh_theta, self.nn_chunk, self.fof_chunk, self.pot_chunk,
-                       self.kd_leaf, self.bh_leaf)
+                       self.kd_leaf, self.bh_leaf, self.nn_bracket)
 
 
 NODE_FIELDS = [("parent", torch.int32), ("level", torch.int32), ("first_child", torch.int32),

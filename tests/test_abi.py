@@ -87,7 +87,8 @@ def test_ctx_create_requires_allocator(lib):
 @pytest.mark.parametrize("field,value", [
     ("nn_chunk", 100), ("nn_chunk", 8192), ("fof_chunk", 300), ("fof_chunk", 32768),
     ("pot_chunk", 3000), ("kd_leaf", 2), ("kd_leaf", 65), ("bh_leaf", 3), ("bh_leaf", 100),
-    ("grid_min", 32), ("bh_theta", -1.0), ("f", 1.5)])
+    ("grid_min", 32), ("bh_theta", -1.0), ("f", 1.5), ("nn_bracket", float("nan")),
+    ("nn_bracket", float("inf"))])
 def test_ctx_create_rejects_bad_parameters(lib, field, value):
     """Out-of-range parameters are EINVAL before any device call (a counting
     allocator sees no request)."""

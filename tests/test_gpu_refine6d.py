@@ -185,3 +185,24 @@ def test_refine_duplicate_clumps(H, orc, mode):
     assert np.any((on["flags"] & 2) != 0), "expected degenerate nodes"
     assert_nodes_equal(gn, on)
     np.testing.assert_array_equal(gd, od)
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+def test_refine_nn_bracket_agrees(H, c2, mode):
+    """The bracket of ell^2 in the tree nodes' nearest-neighbour walks changes
+    no bit of the hierarchy: without it (nn_bracket < 0, every walk exact), at
+    the default width, and at widths so narrow that most bracketed nodes find
+    ell^2 outside their bracket and walk again without one.  grid_min = 64
+    puts every node of more than 64 particles on the tree search, so each
+    node of more than 4096 takes a bracket."""
+    note(f"refine6d nn_bracket variants on c2, mode {mode}")
+    P = H.Particles.from_catalog(c2)
+    outs = []
+    for nb in (-1.0, 0.0, 1e-3, 0.5, 8.0):
+        ctx = H.Halo(H.params_for_catalog(c2, mode=mode, grid_min=64, nn_bracket=nb))
+        gn, gd = ctx.refine6d(P, ctx.fof3d(P))
+        outs.append((gpu_nodes(gn), to_np(gd)))
+    assert outs[0][0]["parent"].shape[0] > 100
+    for gn, gd in outs[1:]:
+        assert_nodes_equal(gn, outs[0][0])
+        np.testing.assert_array_equal(gd, outs[0][1])
