@@ -7,7 +7,7 @@ catalogue held in HBM.  The default workload is the 1024^3 catalogue (1 Gpc/h
 box, power-law NFW hosts of 20-1e7 particles with subhaloes, 40% uniform
 background, float32 positions, drawn on the GPU) in the batched form with the
 mixed-precision potential and the tree potential of Appendix B (theta = 0.04)
-for haloes of >= 65536 particles.  The plain form (one launch sequence per node
+for haloes of >= 32768 particles.  The plain form (one launch sequence per node
 and halo) is timed beside the batched one on the 128^3 catalogue, where it fits
 the run time.  Prints one JSON line.
 """
@@ -148,10 +148,10 @@ def timed(ctx, P, steps, warmup, prof=False):
     return sec, out, stage, kp
 
 
-# the library's tree threshold when grid_min = 0: 32768 on levels of at least
+# the library's tree threshold when grid_min = 0: 16384 on levels of at least
 # 2^23 particles, 131072 on smaller ones
-GRID_MIN_LARGE, GRID_MIN_SMALL, GRID_LEVEL = 32768, 131072, 1 << 23
-BH_MIN_DEFAULT = 65536     # the library's smallest tree halo when bh_min = 0
+GRID_MIN_LARGE, GRID_MIN_SMALL, GRID_LEVEL = 16384, 131072, 1 << 23
+BH_MIN_DEFAULT = 32768     # the library's smallest tree halo when bh_min = 0
 # FLOP of one evaluation, as counted for the ALU roofline:
 NN_PAIR_FLOP = 17.0   # 6D distance: 6 sub, 1 mul, 5 fma
 BOX_TEST_FLOP = 23.0  # point-to-box gap: per axis 2 sub + fma, 6 axes, minus the first fma's add
@@ -457,7 +457,7 @@ def dense_report(H, cat, P, grid_min, prec, t=16, steps=3):
             "particles_in_grown_groups": int((b["size"] != a["size"]).sum())}
 
 
-def tree_report(ctx, P, out, theta=0.04, bh_min=65536):
+def tree_report(ctx, P, out, theta=0.04, bh_min=BH_MIN_DEFAULT):
     """The tree potential of Appendix B (bh_theta = 0.04, haloes with |S(h)| >=
     bh_min) against the exact direct sum, outside the timed steps, on the
     step's own halo table and context (no second workspace): unbind device
@@ -637,7 +637,7 @@ def main():
     ap.add_argument("--bh-theta", type=float, default=0.04,
                     help="tree potential (Appendix B) in the timed steps, for haloes of at "
                          "least --bh-min particles; 0 keeps the exact direct sum")
-    ap.add_argument("--bh-min", type=int, default=65536,
+    ap.add_argument("--bh-min", type=int, default=BH_MIN_DEFAULT,
                     help="smallest |S(h)| that takes the tree")
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense-particle FOF variant comparison (not part of the step)")

@@ -95,7 +95,7 @@ typedef struct {
   int32_t mode;             /* libhalo_mode */
   int32_t prec;             /* libhalo_prec */
   int32_t grid_min;         /* nodes with more particles use the exact tree
-                               search instead of all pairs; 0 = 32768 on levels of
+                               search instead of all pairs; 0 = 16384 on levels of
                                >= 2^23 particles and 131072 on smaller ones, else
                                >= 64 (results are identical either way) */
   int32_t ell_subset;       /* 0: ell from every particle's nearest neighbour (exact);
@@ -111,7 +111,7 @@ typedef struct {
                                ll also links every particle within 2 ll (paper: 16);
                                EINVAL when the box holds fewer than 2Q+1 cells of the
                                2 ll stencil */
-  int32_t bh_min;           /* with bh_theta > 0: halos with |S(h)| >= bh_min (0 = 65536)
+  int32_t bh_min;           /* with bh_theta > 0: halos with |S(h)| >= bh_min (0 = 32768)
                                take their particles' potential from a tree */
   double bh_theta;          /* 0: exact direct sum; > 0: the tree potential of
                                Appendix B, a cell's monopole accepted at distances

@@ -65,7 +65,7 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t K, uint
 // Default tree threshold: nodes above it use the tree search.  The walks need
 // many points to fill the chip (a launch's slowest walks set its tail), so the
 // low threshold applies only on levels of at least kGridLevel particles.
-constexpr uint32_t kGridMin = 32768;
+constexpr uint32_t kGridMin = 16384;
 constexpr uint32_t kGridMinSmall = 131072;
 constexpr uint32_t kGridLevel = 1u << 23;
 __host__ __device__ inline uint32_t default_grid_min(uint32_t level_particles) {

@@ -1110,7 +1110,7 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
   k_merge_target<<<blocks_for(S, TB), TB, 0, s>>>(h, S, w.nS, P.major_merger, w.tgt);
   // potentials: work units ordered largest first, one partial per particle
   // and j-chunk, partials added in chunk order
-  const uint32_t bh_min = P.bh_min > 0 ? (uint32_t)P.bh_min : 65536u;
+  const uint32_t bh_min = P.bh_min > 0 ? (uint32_t)P.bh_min : 32768u;
   with_pot_chunk(P.pot_chunk, [&](auto Jc) {
     k_pot_counts<decltype(Jc)::value><<<blocks_for(S, TB), TB, 0, s>>>(
         h, S, w.nS, P.bh_theta, bh_min, w.ucnt, w.pk0, w.pv0);

@@ -157,7 +157,7 @@ def test_tree_workspace_placement(H, c1):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_tree_large_haloes_c3(H, orc, prec):
     """The 512^3 catalogue at full size with the tree potential (theta = 0.04,
-    haloes of |S(h)| >= 65536), in the FP64 and the mixed form: for the three
+    haloes of |S(h)| >= 32768), in the FP64 and the mixed form: for the three
     largest tree haloes (the largest near 10^6 particles, trees far deeper
     than c1's), the potential of 1000 sampled own particles lies within theta
     of the exact direct sum over S(h) that the oracle computes for those
