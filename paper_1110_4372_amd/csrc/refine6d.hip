@@ -26,12 +26,31 @@ namespace {
 using namespace refine;
 
 // ------------------------------------------------------------ level 0 ------
+template <class T>
+struct Members {  // the FOF members' positions and velocities in member order
+  T *x, *y, *z;
+  float *vx, *vy, *vz;
+};
+
+// The level arrays index the members in their FOF order (lidx holds member
+// positions; perm maps them to input indices), and the members' positions and
+// velocities are gathered once into that order: every level's particles are a
+// subsequence of it, so the later levels read them in increasing order.
+template <class T>
 __global__ void k_level0(const uint32_t* perm, const uint32_t* grp_first,
                          const uint32_t* grp_count, uint32_t G, uint32_t M, uint32_t* lidx,
-                         uint32_t* lnode) {
+                         uint32_t* lnode, const T* x, const T* y, const T* z, const float* vx,
+                         const float* vy, const float* vz, Members<T> g) {
   uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= M) return;
-  lidx[m] = perm[m];
+  lidx[m] = m;
+  const uint32_t i = perm[m];
+  g.x[m] = x[i];
+  g.y[m] = y[i];
+  g.z[m] = z[i];
+  g.vx[m] = vx[i];
+  g.vy[m] = vy[i];
+  g.vz[m] = vz[i];
   // groups are contiguous and in order: last g with first[g] <= m
   uint32_t lo = 0, hi = G;
   while (hi - lo > 1) {
@@ -655,24 +674,24 @@ __device__ __forceinline__ bool in_subset(uint32_t index, uint32_t n, uint32_t m
 }
 
 // nsub[k] = subset size of each node above m (zero-initialised).
-__global__ void k_subset_count(const uint32_t* lidx, const uint32_t* lnode, LevelNodes nd,
-                               uint32_t Mi, uint32_t m, uint32_t* nsub) {
+__global__ void k_subset_count(const uint32_t* perm, const uint32_t* lidx, const uint32_t* lnode,
+                               LevelNodes nd, uint32_t Mi, uint32_t m, uint32_t* nsub) {
   const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = q < Mi;
   const uint32_t k = ok ? lnode[q] : 0u;
   const uint32_t n = ok ? nd.count[k] : 0u;
-  agg_add_u32(nsub, k, 1u, ok && n > m && in_subset(lidx[q], n, m));
+  agg_add_u32(nsub, k, 1u, ok && n > m && in_subset(perm[lidx[q]], n, m));
 }
 
 // Dsel = D on the subset, +inf elsewhere; a node whose draw came out empty
 // keeps every particle.
-__global__ void k_subset_sel(const uint32_t* lidx, const uint32_t* lnode, LevelNodes nd,
-                             uint32_t Mi, uint32_t m, const uint32_t* nsub, const uint32_t* D,
-                             uint32_t* Dsel) {
+__global__ void k_subset_sel(const uint32_t* perm, const uint32_t* lidx, const uint32_t* lnode,
+                             LevelNodes nd, uint32_t Mi, uint32_t m, const uint32_t* nsub,
+                             const uint32_t* D, uint32_t* Dsel) {
   const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= Mi) return;
   const uint32_t k = lnode[q], n = nd.count[k];
-  const bool keep = n <= m || nsub[k] == 0u || in_subset(lidx[q], n, m);
+  const bool keep = n <= m || nsub[k] == 0u || in_subset(perm[lidx[q]], n, m);
   Dsel[q] = keep ? D[q] : 0x7F800000u;
 }
 
@@ -884,7 +903,7 @@ __global__ void k_child_flags(const uint32_t* par, const uint32_t* lnode,
 }
 
 __global__ void k_child_nodes(const uint32_t* par, const uint32_t* lnode,
-                              const uint32_t* csize, const uint32_t* lidx,
+                              const uint32_t* csize, const uint32_t* perm, const uint32_t* lidx,
                               const uint32_t* hrank, const uint32_t* head, uint32_t M,
                               LevelNodes nd, int32_t base, NodeScratch sc, LevelNodes nx,
                               uint32_t* cid) {
@@ -893,7 +912,7 @@ __global__ void k_child_nodes(const uint32_t* par, const uint32_t* lnode,
   const uint32_t k = lnode[m];
   const uint32_t c = hrank[m];
   nx.count[c] = csize[m];
-  nx.canon[c] = lidx[m];
+  nx.canon[c] = perm[lidx[m]];
   nx.parent[c] = base + (int32_t)k;
   nx.fof[c] = nd.fof[k];
   cid[m] = c;
@@ -924,11 +943,11 @@ __global__ void k_next_first(const uint32_t* skey, uint32_t M2, uint32_t* first2
   if (q == 0 || skey[q] != skey[q - 1]) first2[skey[q]] = q;
 }
 
-__global__ void k_deepest(const uint32_t* lidx, const uint32_t* lnode, uint32_t M,
-                          int32_t base, int32_t* deepest) {
+__global__ void k_deepest(const uint32_t* perm, const uint32_t* lidx, const uint32_t* lnode,
+                          uint32_t M, int32_t base, int32_t* deepest) {
   uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= M) return;
-  deepest[lidx[m]] = base + (int32_t)lnode[m];
+  deepest[perm[lidx[m]]] = base + (int32_t)lnode[m];
 }
 
 __global__ void k_node_out(LevelNodes nd, uint32_t K, int32_t base, int32_t level,
@@ -1028,6 +1047,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       *cid, *k0, *v0, *k1, *v1, *stmp, *dcnt, *lpos, *Dsel = nullptr, *nsub = nullptr;
   const uint32_t msub = (uint32_t)P.ell_subset;  // 0: exact ell
   float *xi, *cxi;
+  Members<T> mem;
   LevelNodes cnodes;
   void* rtmp;
   double* mom;
@@ -1042,6 +1062,12 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     lidx2 = A.take<uint32_t>(M);
     lnode2 = A.take<uint32_t>(M);
     xi = A.take<float>(6ull * M);
+    mem.x = A.take<T>(M);
+    mem.y = A.take<T>(M);
+    mem.z = A.take<T>(M);
+    mem.vx = A.take<float>(M);
+    mem.vy = A.take<float>(M);
+    mem.vz = A.take<float>(M);
     cxi = A.take<float>(6ull * M);
     lpos = A.take<uint32_t>(M + 1);
     cnodes.first = A.take<uint32_t>(Kmax + 1);
@@ -1094,8 +1120,8 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
   k_fill_i32<<<blocks_for(n, TB), TB, 0, s>>>(deepest, n, -1);
 
   HALO_HIP(hipMemsetAsync(ctx.d_err, 0, sizeof(uint32_t), s));
-  k_level0<<<blocks_for(M, TB), TB, 0, s>>>(perm, grp_first, grp_count, (uint32_t)G, M, lidx,
-                                            lnode);
+  k_level0<T><<<blocks_for(M, TB), TB, 0, s>>>(perm, grp_first, grp_count, (uint32_t)G, M,
+                                               lidx, lnode, x, y, z, vx, vy, vz, mem);
   k_level0_nodes<<<blocks_for(G, TB), TB, 0, s>>>(perm, grp_first, grp_count, (uint32_t)G,
                                                   L[0]);
   uint32_t K = (uint32_t)G, Mi = M;
@@ -1129,15 +1155,15 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     if (plain) {
       for (uint32_t k = 0; k < K; ++k) {
         unsigned g = (hcount[k] + kMomTile - 1) / kMomTile;
-        HALO_PROF(ctx, "k_mom_accum", s, k_mom_accum<T><<<g, TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, nd, K, sc.wmom, k, k + 1,
+        HALO_PROF(ctx, "k_mom_accum", s, k_mom_accum<T><<<g, TB, 0, s>>>(mem.x, mem.y, mem.z, mem.vx, mem.vy, mem.vz, lidx, nd, K, sc.wmom, k, k + 1,
                                         box, sx, level0, sc, ctx.d_err));
-        k_mom_final<T><<<1, 64, 0, s>>>(x, y, z, lidx, nd, k, k + 1, box, sx, level0, P.f, sc,
+        k_mom_final<T><<<1, 64, 0, s>>>(mem.x, mem.y, mem.z, lidx, nd, k, k + 1, box, sx, level0, P.f, sc,
                                         mom, ctx.d_err);
       }
     } else {
-      HALO_PROF(ctx, "k_mom_accum", s, k_mom_accum<T><<<pgrid, TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, nd, K, sc.wmom, 0, K,
+      HALO_PROF(ctx, "k_mom_accum", s, k_mom_accum<T><<<pgrid, TB, 0, s>>>(mem.x, mem.y, mem.z, mem.vx, mem.vy, mem.vz, lidx, nd, K, sc.wmom, 0, K,
                                              box, sx, level0, sc, ctx.d_err));
-      k_mom_final<T><<<blocks_for(K, 128), 128, 0, s>>>(x, y, z, lidx, nd, 0, K, box, sx,
+      k_mom_final<T><<<blocks_for(K, 128), 128, 0, s>>>(mem.x, mem.y, mem.z, lidx, nd, 0, K, box, sx,
                                                         level0, P.f, sc, mom, ctx.d_err);
     }
     if (level0) {
@@ -1147,7 +1173,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       HALO_CHECK((e & kErrVelRange) == 0, LIBHALO_EINVAL, "a velocity is >= 2^16 km/s or NaN");
     }
     // 2. normalised coordinates
-    k_norm6<T><<<blocks_for(Mi, TB), TB, 0, s>>>(x, y, z, vx, vy, vz, lidx, lnode, 0, Mi, box,
+    k_norm6<T><<<blocks_for(Mi, TB), TB, 0, s>>>(mem.x, mem.y, mem.z, mem.vx, mem.vy, mem.vz, lidx, lnode, 0, Mi, box,
                                                  sc, xi, S);
     // 3. nearest neighbours: tree search for large nodes, all-pairs for the rest
     k_fill_u32<<<blocks_for(Mi, TB), TB, 0, s>>>(D, Mi, 0x7F800000u);
@@ -1207,8 +1233,9 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     const uint32_t* Dsl = msub > 0 ? Dsel : D;
     if (msub > 0) {
       k_fill_u32<<<blocks_for(K, TB), TB, 0, s>>>(nsub, K, 0u);
-      k_subset_count<<<blocks_for(Mi, TB), TB, 0, s>>>(lidx, lnode, nd, Mi, msub, nsub);
-      k_subset_sel<<<blocks_for(Mi, TB), TB, 0, s>>>(lidx, lnode, nd, Mi, msub, nsub, D, Dsel);
+      k_subset_count<<<blocks_for(Mi, TB), TB, 0, s>>>(perm, lidx, lnode, nd, Mi, msub, nsub);
+      k_subset_sel<<<blocks_for(Mi, TB), TB, 0, s>>>(perm, lidx, lnode, nd, Mi, msub, nsub, D,
+                                                      Dsel);
       k_subset_kth<<<blocks_for(K, TB), TB, 0, s>>>(nd, K, msub, P.f, nsub, sc);
       HALO_PROF(ctx, "k_select_small", s, k_select_small<<<K, TB, 0, s>>>(Dsel, nd, 0, K, sc));
     }
@@ -1275,7 +1302,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     const uint32_t K2 = rd.h[4], M2 = rd.h[5];
     const int32_t next_base = base + (int32_t)K;
     if (K2 > 0) {
-      k_child_nodes<<<blocks_for(Mi, TB), TB, 0, s>>>(par, lnode, csize, lidx, hrank, head, Mi,
+      k_child_nodes<<<blocks_for(Mi, TB), TB, 0, s>>>(par, lnode, csize, perm, lidx, hrank, head, Mi,
                                                       nd, base, sc, nx, cid);
       k_child_keys<<<blocks_for(Mi, TB), TB, 0, s>>>(par, cflag, crank, cid, Mi, k0, v0);
       bool f = radix_sort_pairs<uint32_t>(k0, v0, k1, v1, M2, bits_for(K2), rtmp, s);
@@ -1284,7 +1311,7 @@ void refine_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
       k_next_level<<<blocks_for(M2, TB), TB, 0, s>>>(sk, sv, lidx, M2, lidx2, lnode2);
       k_next_first<<<blocks_for(M2, TB), TB, 0, s>>>(sk, M2, nx.first);
     }
-    k_deepest<<<blocks_for(Mi, TB), TB, 0, s>>>(lidx, lnode, Mi, base, deepest);
+    k_deepest<<<blocks_for(Mi, TB), TB, 0, s>>>(perm, lidx, lnode, Mi, base, deepest);
     k_node_out<<<blocks_for(K, TB), TB, 0, s>>>(nd, K, base, level, next_base, mom, sc, *out);
     base = next_base;
     K = K2;
