@@ -164,7 +164,8 @@ __global__ void k_bh_keys(const double* ux, const double* uy, const double* uz, 
 }
 
 // Sorted positions (FP64); with f non-null also their FP32 roundings, which
-// the mixed form's walk reads.
+// the mixed form's walk reads, 16 bytes per particle (x, y, z, 0) so that a
+// leaf's particles are whole scalar loads.
 __global__ void k_bh_gather(const double* ux, const double* uy, const double* uz,
                             const uint32_t* sval, uint32_t E, double* px, double* py,
                             double* pz, float* f) {
@@ -176,19 +177,43 @@ __global__ void k_bh_gather(const double* ux, const double* uy, const double* uz
   py[e] = y;
   pz[e] = z;
   if (f) {
-    f[3ull * e] = (float)x;
-    f[3ull * e + 1] = (float)y;
-    f[3ull * e + 2] = (float)z;
+    f[4ull * e] = (float)x;
+    f[4ull * e + 1] = (float)y;
+    f[4ull * e + 2] = (float)z;
+    f[4ull * e + 3] = 0.0f;
   }
 }
 
 // A cell as the walk reads it (one 64-byte scalar fetch), in preorder: mass
 // centre, mass (particles), dispersion, squared acceptance distance, its range
 // of the sorted order, the index after its subtree, and whether it is a leaf.
+// Once the acceptance distance is set, the mixed form's walk takes the centre
+// rounded to FP32 and the squared acceptance distance rounded down to FP32
+// from the 16 bytes of the dispersion and that distance: for an FP32 squared
+// distance d, d <= crit2 exactly when d <= crit2 rounded down.
 struct __align__(16) BhRec {
-  double cx, cy, cz, cm, sig2, crit2;
+  double cx, cy, cz, cm;
+  union {
+    struct {
+      double sig2, crit2;
+    } d;
+    struct {
+      float cx, cy, cz, crit2;
+    } f;
+  } a;
   uint32_t lo, hi, skip, leaf;
 };
+
+// The lanes l of a wave whose element e0 + l lies in [lo, hi) (32-bit
+// arithmetic on wave-uniform values, so it stays on the scalar unit).
+__device__ __forceinline__ unsigned long long lane_span(uint32_t lo, uint32_t hi, uint32_t e0) {
+  // element indices stay below 2^31, so the differences fit a signed int
+  const int32_t a = max((int32_t)(lo - e0), 0);
+  const int32_t b = min(max((int32_t)(hi - e0), 0), 64);
+  if (a >= b) return 0ull;
+  const unsigned long long upto = b == 64 ? ~0ull : ((1ull << b) - 1ull);
+  return upto & ~((1ull << a) - 1ull);
+}
 
 // Cell statistics of the nodes [u0, u0 + nu) of one depth: leaves from their
 // particles, others from their children's records (one depth deeper, already
@@ -225,15 +250,15 @@ __global__ void k_bh_records(const MtNode* bnode, const uint32_t* pre, uint32_t 
     x0[2] = (m1 * a.cz + m2 * b.cz) / m;
     const double d1 = sq3(a.cx - x0[0], a.cy - x0[1], a.cz - x0[2]);
     const double d2 = sq3(b.cx - x0[0], b.cy - x0[1], b.cz - x0[2]);
-    s2 = (m1 * (a.sig2 + d1) + m2 * (b.sig2 + d2)) / m;
+    s2 = (m1 * (a.a.d.sig2 + d1) + m2 * (b.a.d.sig2 + d2)) / m;
   }
   BhRec r;
   r.cx = x0[0];
   r.cy = x0[1];
   r.cz = x0[2];
   r.cm = m;
-  r.sig2 = s2;
-  r.crit2 = 0.0;
+  r.a.d.sig2 = s2;
+  r.a.d.crit2 = 0.0;
   r.lo = u.lo;
   r.hi = u.hi;
   r.skip = p + u.aux;
@@ -279,12 +304,21 @@ __global__ void k_bh_rmax(BhList L, uint32_t B, uint32_t E, const double* px, co
 }
 
 // Acceptance distances from the exact r_max.
-__global__ void k_bh_crit(uint32_t T, double theta, const unsigned long long* rmx, BhRec* R) {
+__global__ void k_bh_crit(uint32_t T, double theta, const unsigned long long* rmx, int f32,
+                          BhRec* R) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T) return;
   const double r = sqrt(ord_f64(rmx[t]));  // r_max from the largest squared distance
-  const double dc = 0.5 * r + sqrt(0.25 * r * r + R[t].sig2 / theta);
-  R[t].crit2 = dc * dc;
+  const double dc = 0.5 * r + sqrt(0.25 * r * r + R[t].a.d.sig2 / theta);
+  if (f32) {
+    BhRec& c = R[t];
+    c.a.f.cx = (float)c.cx;
+    c.a.f.cy = (float)c.cy;
+    c.a.f.cz = (float)c.cz;
+    c.a.f.crit2 = __double2float_rd(dc * dc);
+  } else {
+    R[t].a.d.crit2 = dc * dc;
+  }
 }
 
 // Wave units of each tree halo: its sorted elements in runs of 64.
@@ -332,6 +366,10 @@ __global__ void __launch_bounds__(TB)
   if (__ballot(target) == 0ull) return;  // wave-uniform
   const double x = in ? px[e] : 0.0, y = in ? py[e] : 0.0, z = in ? pz[e] : 0.0;
   const float xf = (float)x, yf = (float)y, zf = (float)z, eps2f = (float)eps2;
+  // the wave's first element and its target lanes: the lanes a cell holds
+  // follow from its range alone
+  const uint32_t e0 = __builtin_amdgcn_readfirstlane(base + (wave - woff[b]) * 64u);
+  const unsigned long long tmask = __ballot(target);
   // the F32 leaf sum's term of the target itself (the same expression at d = 0)
   const float self_f = __builtin_amdgcn_rsqf(
       __fmaf_rn(0.0f, 0.0f, __fmaf_rn(0.0f, 0.0f, __fmaf_rn(0.0f, 0.0f, eps2f))));
@@ -345,21 +383,23 @@ __global__ void __launch_bounds__(TB)
   while (u < end) {
     const BhRec nx = R[u + 1];
     uint32_t v;
-    double d2;
+    double d2 = 0.0;
     float d2f = 0.0f;
+    bool near;
     if constexpr (F32) {
-      const float dx = xf - (float)c.cx, dy = yf - (float)c.cy, dz = zf - (float)c.cz;
+      const float dx = xf - c.a.f.cx, dy = yf - c.a.f.cy, dz = zf - c.a.f.cz;
       d2f = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
-      d2 = (double)d2f;
+      near = d2f <= c.a.f.crit2;
     } else {
       d2 = sq3(x - c.cx, y - c.cy, z - c.cz);
+      near = d2 <= c.a.d.crit2;
     }
     // a cell is a monopole for a target outside it beyond the acceptance
     // distance; the cell holding the target itself is always opened (a cell of
     // coincident particles has a zero acceptance distance)
-    const bool open = d2 <= c.crit2 || (e >= c.lo && e < c.hi);
+    const unsigned long long inside = lane_span(c.lo, c.hi, e0);
     if (COUNT) ++ncell;
-    if (__ballot(target && open) == 0ull) {
+    if (((__builtin_amdgcn_ballot_w64(near) | inside) & tmask) == 0ull) {
       if (COUNT) ++nterm;
       if (target) {
         if constexpr (F32)
@@ -379,12 +419,13 @@ __global__ void __launch_bounds__(TB)
         float sf = 0.0f;
 #pragma unroll 4
         for (uint32_t f = c.lo; f < c.hi; ++f) {
-          const float fx = pf[3ull * f], fy = pf[3ull * f + 1], fz = pf[3ull * f + 2];
+          const float4 p4 = reinterpret_cast<const float4*>(pf)[f];
+          const float fx = p4.x, fy = p4.y, fz = p4.z;
           const float dx = xf - fx, dy = yf - fy, dz = zf - fz;
           sf += __builtin_amdgcn_rsqf(
               __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmaf_rn(dx, dx, eps2f))));
         }
-        if (e >= c.lo && e < c.hi) sf -= self_f;
+        if ((inside >> lane) & 1ull) sf -= self_f;
         acc += (double)sf;
       } else {
 #pragma unroll 4
@@ -504,7 +545,7 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
     pz = A.take<double>(E + 1);
     mtree_take(A, t, cap, B + 1);
     R = A.take<BhRec>(cap + 1);  // the walk reads one record ahead
-    pf = f32 ? A.take<float>(3ull * (E + 1)) : nullptr;
+    pf = f32 ? A.take<float>(4ull * (E + 1)) : nullptr;
     rmx = A.take<unsigned long long>(cap);
     rtmp = A.take<char>(radix_tmp_bytes(E + 1));
   });
@@ -530,7 +571,7 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   // exact r_max, then the acceptance distances
   k_fill_u64<<<blocks_for(T, TB), TB, 0, s>>>(rmx, T, 0ull);
   k_bh_rmax<<<blocks_for(E, TB), TB, 0, s>>>(w.L, B, E, px, py, pz, t.bnode, t.pre, R, rmx);
-  k_bh_crit<<<blocks_for(T, TB), TB, 0, s>>>(T, theta, rmx, R);
+  k_bh_crit<<<blocks_for(T, TB), TB, 0, s>>>(T, theta, rmx, f32 ? 1 : 0, R);
   // wave units: runs of 64 sorted elements within each halo
   k_bh_wave_counts<<<blocks_for(B, TB), TB, 0, s>>>(w.L, B, w.flag);
   exclusive_scan<uint32_t>(w.flag, w.pos, B, w.cnt + 3, w.stmp, s);
