@@ -8,7 +8,9 @@
 //  - seed sets: every (ancestor, merged seed) pair of every leaf, sorted and
 //    made unique, gives the distinct halos below each node;
 //  - assignment, deepest level first: the particles a node holds outside its
-//    subgroups go to its only halo or to the Eq. 3 argmin, with sigma_v and
+//    subgroups go to its only halo or to the Eq. 3 argmin (a wave of
+//    spatially close particles first drops the seeds that cannot be nearest
+//    to any of them), with sigma_v and
 //    vmax of each candidate halo recomputed from its current particles by a
 //    segmented radial sort (exact, order-independent reductions);
 //  - host/sub: one wavefront per FOF group over halos by decreasing size.
@@ -418,12 +420,44 @@ __global__ void k_own_offsets(const uint32_t* okey, uint32_t M, uint32_t NN, uin
   off[k] = lo;
 }
 
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {  // bit b -> bit 3b
+  v &= 0x3FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// Own particles in compacted order with a 30-bit Morton key of the position
+// relative to the node's centre, 64 cells per sigma_x over +-8 sigma_x
+// (clamped): sorted by node, then by this key, the particles of a wave lie
+// close together.  The order changes no result.
+template <class T>
 __global__ void k_own_compact(const int32_t* deepest, const uint32_t* flag, const uint32_t* pos,
-                              uint32_t n, uint32_t* key, uint32_t* val) {
+                              uint32_t n, const T* x, const T* y, const T* z, double box,
+                              libhalo_nodes nd, uint32_t* key, uint32_t* val) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !flag[i]) return;
-  key[pos[i]] = (uint32_t)deepest[i];
+  const uint32_t k = (uint32_t)deepest[i];
+  const double sx = sqrt(nd.sx2[k]);
+  const double sc = sx > 0.0 ? 64.0 / sx : 0.0;
+  const double p[3] = {(double)x[i], (double)y[i], (double)z[i]};
+  const double c[3] = {nd.cx[k], nd.cy[k], nd.cz[k]};
+  uint32_t m = 0;
+  for (int a = 0; a < 3; ++a) {
+    double t = min_image(p[a] - c[a], box) * sc + 512.0;
+    t = fmin(fmax(t, 0.0), 1023.0);
+    m |= spread10((uint32_t)t) << a;
+  }
+  key[pos[i]] = m;
   val[pos[i]] = i;
+}
+
+__global__ void k_own_node_keys(const int32_t* deepest, const uint32_t* val, uint32_t m,
+                                uint32_t* key) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) key[q] = (uint32_t)deepest[val[q]];
 }
 
 __global__ void k_level_start(const int32_t* level, uint32_t NN, uint32_t* lstart) {
@@ -507,18 +541,56 @@ __device__ __forceinline__ void eq3_min(double px, double py, double pz, double 
   }
 }
 
-// One thread per own particle of the level's nodes (sorted by node).  When the
-// whole wave belongs to one node its seed list and records are wave-uniform
-// (scalar loads); otherwise each lane reads its own.
+__device__ __forceinline__ double wave_min_f64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_max_f64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Box bounds of one coordinate (the wave's interval [lo, hi], widened by w)
+// against a seed's value c: the smallest and the largest distance, squared,
+// added to g2 and f2.
+__device__ __forceinline__ void box_axis(double c, double lo, double hi, double w, double& g2,
+                                         double& f2) {
+  const double l = lo - w, h = hi + w;
+  const double g = fmax(0.0, fmax(l - c, c - h));
+  const double f = fmax(fabs(c - l), fabs(h - c));
+  g2 = __fma_rn(g, g, g2);
+  f2 = __fma_rn(f, f, f2);
+}
+
+// Seeds of a node above which a wave first bounds them against its box.
+constexpr uint32_t kPruneSeeds = 32;
+
+// One thread per own particle of the level's nodes (sorted by node, then
+// spatially).  When the whole wave belongs to one node its seed list and
+// records are wave-uniform (scalar loads); otherwise each lane reads its own.
+//
+// A wave in one node with more than kPruneSeeds seeds first bounds every
+// seed s against the box of its particles' positions (relative to the node's
+// centre, where the node's extent, below half the box, makes the difference
+// of two such offsets the minimum image) and velocities: the Eq. 3 distance
+// of any of its particles to s lies between lo(s) and hi(s).  With T the
+// least hi(s), a seed with lo(s) > T is farther than that seed from every
+// particle of the wave and cannot be its argmin or tie with it; the others
+// are evaluated exactly, in the node's order.  The box is widened by 1e-9 of
+// the box side (positions) and 1e-4 km/s (velocities), far above the
+// rounding of the offsets, and T by a factor 1 + 1e-9 above that of the sums,
+// so the argmin is the one of the full scan bit for bit.
 template <class T>
 __global__ void k_assign_level(const T* x, const T* y, const T* z, const float* vx,
                                const float* vy, const float* vz, double box,
                                const uint32_t* own, const uint32_t* okey, uint32_t q0,
                                uint32_t q1, const uint32_t* __restrict__ soff,
                                const uint32_t* __restrict__ ids, const SeedM* __restrict__ sm,
-                               int32_t* halo_of) {
+                               const double* __restrict__ ncx, const double* __restrict__ ncy,
+                               const double* __restrict__ ncz, int32_t* halo_of) {
   const uint32_t q = q0 + blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = q < q1;
+  if (!__any(ok)) return;  // wave-uniform
   const uint32_t i = ok ? own[q] : 0u, k = ok ? okey[q] : okey[q0];
   const uint32_t kw = __builtin_amdgcn_readfirstlane(k);
   double px = 0.0, py = 0.0, pz = 0.0, ux0 = 0.0, uy0 = 0.0, uz0 = 0.0;
@@ -534,7 +606,61 @@ __global__ void k_assign_level(const T* x, const T* y, const T* z, const float* 
   if (__all(k == kw)) {
     const uint32_t s0 = soff[kw], s1 = soff[kw + 1];
     best = ids[s0];
-    if (s1 - s0 > 1) {
+    if (s1 - s0 > kPruneSeeds) {
+      // the wave's box: positions relative to the node's centre, velocities
+      const double cx = ncx[kw], cy = ncy[kw], cz = ncz[kw];
+      const double inf = INFINITY;
+      const double rx = min_image(px - cx, box), ry = min_image(py - cy, box),
+                   rz = min_image(pz - cz, box);
+      const double lx = wave_min_f64(ok ? rx : inf), hx = wave_max_f64(ok ? rx : -inf);
+      const double ly = wave_min_f64(ok ? ry : inf), hy = wave_max_f64(ok ? ry : -inf);
+      const double lz = wave_min_f64(ok ? rz : inf), hz = wave_max_f64(ok ? rz : -inf);
+      const double lu = wave_min_f64(ok ? ux0 : inf), hu = wave_max_f64(ok ? ux0 : -inf);
+      const double lv = wave_min_f64(ok ? uy0 : inf), hv = wave_max_f64(ok ? uy0 : -inf);
+      const double lw = wave_min_f64(ok ? uz0 : inf), hw = wave_max_f64(ok ? uz0 : -inf);
+      const double wx = 1e-9 * box, wv = 1e-4;
+      const uint32_t lane = threadIdx.x & 63u;
+      // lane j bounds seed t = c0 + j of each run of 64
+      auto bounds = [&](uint32_t t, double& lo, double& hi) {
+        const SeedM m = sm[ids[t]];
+        double gx = 0.0, fx = 0.0, gv = 0.0, fv = 0.0;
+        box_axis(min_image(m.xs - cx, box), lx, hx, wx, gx, fx);
+        box_axis(min_image(m.ys - cy, box), ly, hy, wx, gx, fx);
+        box_axis(min_image(m.zs - cz, box), lz, hz, wx, gx, fx);
+        box_axis(m.vxs, lu, hu, wv, gv, fv);
+        box_axis(m.vys, lv, hv, wv, gv, fv);
+        box_axis(m.vzs, lw, hw, wv, gv, fv);
+        lo = __fma_rn(gx, m.ird, gv * m.isv);
+        hi = __fma_rn(fx, m.ird, fv * m.isv);
+      };
+      double tl = inf;
+      for (uint32_t c0 = s0; c0 < s1; c0 += 64u) {
+        const uint32_t t = c0 + lane;
+        if (t < s1) {
+          double lo, hi;
+          bounds(t, lo, hi);
+          tl = fmin(tl, hi);
+        }
+      }
+      const double lim = wave_min_f64(tl) * (1.0 + 1e-9);
+      double bd = INFINITY;
+      for (uint32_t c0 = s0; c0 < s1; c0 += 64u) {
+        const uint32_t t = c0 + lane;
+        bool keep = false;
+        if (t < s1) {
+          double lo, hi;
+          bounds(t, lo, hi);
+          keep = lo <= lim;
+        }
+        unsigned long long left = __ballot(keep);
+        while (left) {  // wave-uniform: the surviving seeds in order
+          const uint32_t j = (uint32_t)__builtin_ctzll(left);
+          left &= left - 1ull;
+          const uint32_t hid = ids[c0 + j];
+          eq3_min(px, py, pz, ux0, uy0, uz0, box, sm[hid], hid, bd, best);
+        }
+      }
+    } else if (s1 - s0 > 1) {
       double bd = INFINITY;
       for (uint32_t t = s0; t < s1; ++t) {
         const uint32_t hid = ids[t];
@@ -824,11 +950,20 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
   void* rtmp2 = w.rtmp2;
   k_own_flags<<<blocks_for(n, TB), TB, 0, s>>>(deepest, (uint32_t)n, iflag);
   exclusive_scan<uint32_t>(iflag, ipos, n, dcnt + 3, stmp, s);
-  k_own_compact<<<blocks_for(n, TB), TB, 0, s>>>(deepest, iflag, ipos, (uint32_t)n, ok0, ov0);
+  k_own_compact<T><<<blocks_for(n, TB), TB, 0, s>>>(deepest, iflag, ipos, (uint32_t)n, x, y, z,
+                                                    box, nd, ok0, ov0);
   const uint32_t M = readu(dcnt + 3, 4);
-  bool fo = radix_sort_pairs<uint32_t>(ok0, ov0, ok1, ov1, M, bits_for((uint64_t)NN), rtmp2, s);
-  uint32_t* okey = fo ? ok1 : ok0;
-  uint32_t* own = fo ? ov1 : ov0;
+  // by the spatial key, then stably by node
+  const bool f1 = radix_sort_pairs<uint32_t>(ok0, ov0, ok1, ov1, M, 30, rtmp2, s);
+  uint32_t* vsp = f1 ? ov1 : ov0;  // values in key order
+  uint32_t* kfree = f1 ? ok0 : ok1;
+  uint32_t* kold = f1 ? ok1 : ok0;
+  uint32_t* vfree = f1 ? ov0 : ov1;
+  k_own_node_keys<<<blocks_for(M, TB), TB, 0, s>>>(deepest, vsp, M, kfree);
+  const bool fo =
+      radix_sort_pairs<uint32_t>(kfree, vsp, kold, vfree, M, bits_for((uint64_t)NN), rtmp2, s);
+  uint32_t* okey = fo ? kold : kfree;
+  uint32_t* own = fo ? vfree : vsp;
   uint32_t* ooff = w.ooff;
   k_own_offsets<<<blocks_for(NN + 1, TB), TB, 0, s>>>(okey, M, (uint32_t)NN, ooff);
 
@@ -873,7 +1008,8 @@ void assign_impl(Ctx& ctx, int64_t n, int pos_dtype, const T* x, const T* y, con
     if (q1 > q0)
       HALO_PROF(ctx, "k_assign_level", s,
                 (k_assign_level<T><<<blocks_for(q1 - q0, TB), TB, 0, s>>>(
-                    x, y, z, vx, vy, vz, box, own, okey, q0, q1, soff, ids, w.sm, halo_of)));
+                    x, y, z, vx, vy, vz, box, own, okey, q0, q1, soff, ids, w.sm, nd.cx, nd.cy,
+                    nd.cz, halo_of)));
   }
 
   // ---- final metric of every halo from all its particles
