@@ -102,38 +102,51 @@ __global__ void k_bh_bbox_init(unsigned long long* bb, uint32_t B) {
   }
 }
 
-// Bounding box per halo as ordered-integer min / max; a wave whose elements
-// all belong to one halo sends one set of atomics.
+// Bounding box per halo as ordered-integer min / max.  A wave takes a tile of
+// kBoxTile consecutive elements (coalesced, 64 apart per lane); a tile inside
+// one halo sends one set of atomics, a tile across a halo boundary (at most
+// two per halo) sends each element's own.
+constexpr uint32_t kBoxTile = 1024;
+
 __global__ void k_bh_bbox(const double* ux, const double* uy, const double* uz, BhList L,
                           const uint32_t* slot, uint32_t B, uint32_t E,
                           unsigned long long* bb) {
-  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = e < E;
-  uint32_t b = 0xFFFFFFFFu;
-  unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0ull, 0ull, 0ull};
-  if (ok) {
-    b = seg_find(L.eoff, B, e);
-    const uint32_t q = slot[L.big[b]] + (e - L.eoff[b]);
-    const double p[3] = {ux[q], uy[q], uz[q]};
-    for (int c = 0; c < 3; ++c) mn[c] = mx[c] = f64_ord(p[c]);
-  }
-  const uint32_t b0 = __shfl(b, 0);
-  if (__all(b == b0) && b0 != 0xFFFFFFFFu) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t t0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * kBoxTile;
+  if (t0 >= E) return;  // wave-uniform
+  const uint32_t t1 = min(t0 + kBoxTile, E);
+  const uint32_t b0 = seg_find(L.eoff, B, t0), b1 = seg_find(L.eoff, B, t1 - 1u);
+  if (b0 == b1) {
+    const uint32_t q0 = slot[L.big[b0]] + (t0 - L.eoff[b0]);
+    unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0ull, 0ull, 0ull};
+    for (uint32_t e = t0 + lane; e < t1; e += 64u) {
+      const uint32_t q = q0 + (e - t0);
+      const unsigned long long v[3] = {f64_ord(ux[q]), f64_ord(uy[q]), f64_ord(uz[q])};
+      for (int c = 0; c < 3; ++c) {
+        mn[c] = v[c] < mn[c] ? v[c] : mn[c];
+        mx[c] = v[c] > mx[c] ? v[c] : mx[c];
+      }
+    }
     for (int o = 32; o > 0; o >>= 1)
       for (int c = 0; c < 3; ++c) {
         const unsigned long long a = __shfl_xor(mn[c], o), z = __shfl_xor(mx[c], o);
         mn[c] = a < mn[c] ? a : mn[c];
         mx[c] = z > mx[c] ? z : mx[c];
       }
-    if ((threadIdx.x & 63u) == 0)
+    if (lane == 0)
       for (int c = 0; c < 3; ++c) {
         atomicMin(bb + 6 * (size_t)b0 + c, mn[c]);
         atomicMax(bb + 6 * (size_t)b0 + 3 + c, mx[c]);
       }
-  } else if (ok) {
-    for (int c = 0; c < 3; ++c) {
-      atomicMin(bb + 6 * (size_t)b + c, mn[c]);
-      atomicMax(bb + 6 * (size_t)b + 3 + c, mx[c]);
+  } else {
+    for (uint32_t e = t0 + lane; e < t1; e += 64u) {
+      const uint32_t b = seg_find(L.eoff, B, e);
+      const uint32_t q = slot[L.big[b]] + (e - L.eoff[b]);
+      const double p[3] = {ux[q], uy[q], uz[q]};
+      for (int c = 0; c < 3; ++c) {
+        atomicMin(bb + 6 * (size_t)b + c, f64_ord(p[c]));
+        atomicMax(bb + 6 * (size_t)b + 3 + c, f64_ord(p[c]));
+      }
     }
   }
 }
@@ -295,7 +308,9 @@ __global__ void k_bh_rmax(BhList L, uint32_t B, uint32_t E, const double* px, co
       if (lane + o < 64u && po == p && vo > v) v = vo;
     }
     const uint32_t pp = __shfl_up(p, 1);
-    if (p != kMtNone && (lane == 0u || pp != p)) atomicMax(rmx + p, v);
+    // the maximum only grows: a run below the value already there sends no atomic
+    if (p != kMtNone && (lane == 0u || pp != p) && v > __atomic_load_n(rmx + p, __ATOMIC_RELAXED))
+      atomicMax(rmx + p, v);
     if (u != kMtNone) {
       const MtNode n = bnode[u];
       u = n.left == kMtNone ? kMtNone : (e < bnode[n.left].hi ? n.left : n.left + 1u);
@@ -552,7 +567,8 @@ void bh_potential(Ctx& ctx, const libhalo_halos& h, uint32_t S, const uint32_t* 
   build_list();
   exclusive_scan<uint32_t>(w.L.nel, w.L.eoff, B, w.cnt + 1, w.stmp, s);
   k_bh_bbox_init<<<blocks_for(B, TB), TB, 0, s>>>(w.bb, B);
-  k_bh_bbox<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, w.L, slot, B, E, w.bb);
+  k_bh_bbox<<<blocks_for((E + kBoxTile - 1) / kBoxTile, TB / 64), TB, 0, s>>>(ux, uy, uz, w.L,
+                                                                               slot, B, E, w.bb);
   k_bh_keys<<<blocks_for(E, TB), TB, 0, s>>>(ux, uy, uz, w.L, slot, B, E, w.bb, k0, v0);
   const bool f = radix_sort_pairs<unsigned long long>(k0, v0, k1, v1, E,
                                                       48 + bits_for(B > 1 ? B - 1 : 1), rtmp, s);

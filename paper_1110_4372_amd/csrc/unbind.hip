@@ -29,6 +29,7 @@ namespace {
 
 constexpr int TB = 256;
 constexpr unsigned kPersist = 4096;
+constexpr unsigned kSideGrid = 3 * 256;  // three blocks of 256 on each of 256 CUs
 
 __global__ void k_kept_host_keys(const libhalo_halos h, uint32_t S, uint32_t* flag) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1161,7 +1162,10 @@ void unbind_impl(Ctx& ctx, int64_t n, const T* x, const T* y, const T* z, const 
     } else if (U > 0) {
       k_fill_u32<<<1, 64, 0, s>>>(w.dcnt + 4, 1, 0u);
       if (tree) sp = ctx.fork(s);
-      launch(0, U, w.dcnt + 4, std::min<uint32_t>(kPersist, U));
+      // beside the tree, the persistent grid leaves one block slot per CU
+      // (of the four its registers allow) to the tree's build kernels, which
+      // would otherwise wait for it to drain
+      launch(0, U, w.dcnt + 4, std::min<uint32_t>(tree ? kSideGrid : kPersist, U));
     }
     if (tree)
       bh_potential(ctx, h, S, w.nS, w.slot, w.ux, w.uy, w.uz, eps2, P.bh_theta, bh_min, w.pacc,
