@@ -416,12 +416,11 @@ __global__ void __launch_bounds__(TB)
     if (COUNT) ++ncell;
     if (((__builtin_amdgcn_ballot_w64(near) | inside) & tmask) == 0ull) {
       if (COUNT) ++nterm;
-      if (target) {
-        if constexpr (F32)
-          acc += c.cm * (double)__builtin_amdgcn_rsqf(d2f + eps2f);
-        else
-          acc += c.cm * rsqrt_f64(d2 + eps2);
-      }
+      // every lane adds the monopole; lanes without a target discard their sums
+      if constexpr (F32)
+        acc += c.cm * (double)__builtin_amdgcn_rsqf(d2f + eps2f);
+      else
+        acc += c.cm * rsqrt_f64(d2 + eps2);
       v = c.skip;
     } else if (c.leaf) {
       if (COUNT) nterm += c.hi - c.lo;
