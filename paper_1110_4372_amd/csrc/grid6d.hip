@@ -28,8 +28,10 @@
 // The box test computes the point-to-box gap in the component order and FP32
 // operations of the distance, so it never exceeds the distance to any particle
 // in the box: no particle that could change the result is skipped.  D is
-// exact for every particle and the FOF links every pair within ell^2, so the
-// results equal those of the all-pairs passes bit for bit.
+// exact for every particle (or, when the walks are given a bracket of ell^2,
+// exact inside it and on the right side of it elsewhere, which fixes ell^2 and
+// every linkable flag; refine6d.hip) and the FOF links every pair within
+// ell^2, so the results equal those of the all-pairs passes bit for bit.
 #include <hip/hip_fp16.h>
 
 #include "primitives.hpp"
