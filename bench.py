@@ -33,16 +33,16 @@ FP32_PEAK_TFLOPS = 157.3
 # that workload and while the kernel's source file is the one that was measured.
 TRAFFIC_WORKLOAD = "c5"
 MEASURED_TRAFFIC = {
-    "k_kd_walk_nn": {"bytes": 813.18e9, "src": "paper_1110_4372_amd/csrc/grid6d.hip",
-                     "sha1": "5b23b1a594377e6efa724163babf38e2498f041a"},
-    "k_kd_walk_fof": {"bytes": 1031.75e9, "src": "paper_1110_4372_amd/csrc/grid6d.hip",
-                      "sha1": "5b23b1a594377e6efa724163babf38e2498f041a"},
-    "k_bh_walk": {"bytes": 893.13e9, "src": "paper_1110_4372_amd/csrc/bh.hip",
-                  "sha1": "ea0600a2a6c3c83837bed5b3df67f19653826d25"},
-    "k_nn": {"bytes": 12.08e9, "src": "paper_1110_4372_amd/csrc/refine6d.hip",
-             "sha1": "0c055acd8163a6a20f1e64b21ae4ebd8b3ee9759"},
-    "k_potential_f32": {"bytes": 79.06e9, "src": "paper_1110_4372_amd/csrc/unbind.hip",
-                        "sha1": "66a78c9204fb5c49b7dd21c0ecfe8abb099d467a"},
+    "k_bh_walk": {"bytes": 1019.05e9, "src": "paper_1110_4372_amd/csrc/bh.hip",
+                  "sha1": "d49593623d9edd3baf90f2d39e5a0d239e2beac3"},
+    "k_kd_walk_nn": {"bytes": 271.92e9, "src": "paper_1110_4372_amd/csrc/grid6d.hip",
+                     "sha1": "ccb54f0436f90b34eb21d5786f445995354a879e"},
+    "k_kd_walk_fof": {"bytes": 540.51e9, "src": "paper_1110_4372_amd/csrc/grid6d.hip",
+                      "sha1": "ccb54f0436f90b34eb21d5786f445995354a879e"},
+    "k_nn": {"bytes": 8.55e9, "src": "paper_1110_4372_amd/csrc/refine6d.hip",
+             "sha1": "7dc58ed32b0333b22208bd90f26e68544fe02440"},
+    "k_potential_f32": {"bytes": 45.63e9, "src": "paper_1110_4372_amd/csrc/unbind.hip",
+                        "sha1": "3a13952c28ac85b7e9fa4a58347e7c9c62140c4b"},
 }
 
 
