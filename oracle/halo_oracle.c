@@ -950,8 +950,10 @@ static double dyn_const(const orc_params* p) { return (4.0 * M_PI / 3.0) * p->G 
  *  - Host/sub: within a FOF group, kept halos by decreasing assigned count
  *    (ties: lower id); each halo after the first becomes a sub of the closest
  *    earlier halo by Eq. 3 with that halo's final metric (ties: lower id).
- * Parity: single-seed and two-seed pins; merge threshold pin; the readings of
- * merge order, "current" and host choice are parity unpinned.
+ * Parity: single-seed and two-seed pins; merge threshold pin; the merge
+ * visit and the host choice are checked against brute-force numpy forms of
+ * the same readings (tests/test_oracle_readings.py).  The readings of merge
+ * order, "current" and host choice themselves are not fixed by the paper.
  */
 int orc_assign(const orc_params* p, int64_t n, int pos_f64, const void* x, const void* y,
                const void* z, const float* vx, const float* vy, const float* vz,
@@ -1351,8 +1353,9 @@ int orc_unbind(const orc_params* p, int64_t n, int pos_f64, const void* x, const
  *    B(h) within core_frac R (the innermost particle if none);
  *  - V_off = |v_core - v_bulk|.
  * Merged seeds get zeros.  Pinned: NFW vmax, M_vir ~ n m, kicked-core V_off
- * (statistical); the reading of the centre chain and SO crossing is parity
- * unpinned.
+ * (statistical); the centre chain against a brute-force numpy form
+ * (tests/test_oracle_readings.py).  The readings of the centre chain and the
+ * SO crossing themselves are not fixed by the paper.
  */
 int orc_props(const orc_params* p, int64_t n, int pos_f64, const void* x, const void* y,
               const void* z, const float* vx, const float* vy, const float* vz,
