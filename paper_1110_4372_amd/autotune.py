@@ -63,7 +63,11 @@ def tune_knob(H, params, P, knob, candidates, stage_inputs, repeats: int = 2):
     timings = {}
     for g in candidates:
         ctx = H.Halo(replace(params, **{knob: int(g)}))
-        timings[int(g)] = _time(stage_inputs(ctx), repeats)
+        try:
+            timings[int(g)] = _time(stage_inputs(ctx), repeats)
+        finally:
+            ctx.close()  # one workspace at a time: at 1024^3 two do not fit
+        print(f"autotune {knob}={int(g)}: {timings[int(g)]:.1f} ms", file=sys.stderr, flush=True)
     return choose(timings), timings
 
 
@@ -83,6 +87,7 @@ def tune(H, params, P, repeats: int = 2, grid=CANDIDATES, nn=NN_CHUNKS, fof_c=FO
     from dataclasses import replace
     ctx0 = H.Halo(params)
     fof = ctx0.fof3d(P)
+    ctx0.close()  # the outputs are the caller's; its workspace is not needed
     refine = lambda ctx: (lambda: ctx.refine6d(P, fof))  # noqa: E731
     report = {}
     p = params
@@ -91,8 +96,10 @@ def tune(H, params, P, repeats: int = 2, grid=CANDIDATES, nn=NN_CHUNKS, fof_c=FO
         best, t = tune_knob(H, p, P, knob, cands, refine, repeats)
         p = replace(p, **{knob: best})
         report[knob] = {"pick": best, "refine_ms": {str(k): v for k, v in t.items()}}
-    nodes, deep = H.Halo(p).refine6d(P, fof)
-    halos, hof = H.Halo(p).assign(P, nodes, deep)
+    ctx1 = H.Halo(p)
+    nodes, deep = ctx1.refine6d(P, fof)
+    halos, hof = ctx1.assign(P, nodes, deep)
+    ctx1.close()
     unbind = lambda ctx: (lambda: ctx.unbind(P, halos, hof, want_phi=False))  # noqa: E731
     knobs = [("pot_chunk", pot)] + ([("bh_leaf", bh_leaf)] if p.bh_theta > 0 else [])
     for knob, cands in knobs:
