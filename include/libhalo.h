@@ -135,7 +135,7 @@ typedef struct {
   double nn_bracket;        /* exact ell (ell_subset = 0), tree-searched nodes of more
                                than 4096 particles: the nearest-neighbour walks stop
                                once a point's distance is certainly below or above a
-                               bracket of ell^2 taken from every 32nd point's exact
+                               bracket of ell^2 taken from every 64th point's exact
                                distance, nn_bracket binomial standard deviations of
                                the sample rank either side (0 = 4); a node whose
                                ell^2 falls outside its bracket walks again without

@@ -800,7 +800,7 @@ __global__ void k_select_big_resolve(NodeScratch sc, const uint32_t* nbig, int p
 // one is, and th where the true one is th or more, so the kth smallest stored
 // value is the exact ell^2 whenever it lies inside [tl, th); otherwise the
 // node's walks are run again without a bracket.
-constexpr uint32_t kNNSample = 32;
+constexpr uint32_t kNNSample = 64;
 constexpr double kBracketSigma = 4.0;
 
 // Sample count and 1-based sample ranks [rlo, rhi] bracketing the node's kth
