@@ -30,19 +30,22 @@ FP32_PEAK_TFLOPS = 157.3
 # Fabric bytes per dispatch of the hot kernels on the 1024^3 workload, from the
 # committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (profiles/c5_hbm_traffic.md,
 # scaled by a plain copy of known size: fetch x2, write x1).  Reported only for
-# that workload and while the kernel's source file is the one that was measured.
+# that workload and while the source files that set the kernel's work (its
+# own, and for the 6D walks the refinement that drives them) are the ones that
+# were measured.
 TRAFFIC_WORKLOAD = "c5"
+_GRID = ("paper_1110_4372_amd/csrc/grid6d.hip", "ccb54f0436f90b34eb21d5786f445995354a879e")
+_REFINE = ("paper_1110_4372_amd/csrc/refine6d.hip", "c8c946562558e02e125eed24496a815dbf149760")
 MEASURED_TRAFFIC = {
-    "k_bh_walk": {"bytes": 1019.05e9, "src": "paper_1110_4372_amd/csrc/bh.hip",
-                  "sha1": "d49593623d9edd3baf90f2d39e5a0d239e2beac3"},
-    "k_kd_walk_nn": {"bytes": 271.92e9, "src": "paper_1110_4372_amd/csrc/grid6d.hip",
-                     "sha1": "ccb54f0436f90b34eb21d5786f445995354a879e"},
-    "k_kd_walk_fof": {"bytes": 540.51e9, "src": "paper_1110_4372_amd/csrc/grid6d.hip",
-                      "sha1": "ccb54f0436f90b34eb21d5786f445995354a879e"},
-    "k_nn": {"bytes": 8.55e9, "src": "paper_1110_4372_amd/csrc/refine6d.hip",
-             "sha1": "7dc58ed32b0333b22208bd90f26e68544fe02440"},
-    "k_potential_f32": {"bytes": 45.63e9, "src": "paper_1110_4372_amd/csrc/unbind.hip",
-                        "sha1": "3a13952c28ac85b7e9fa4a58347e7c9c62140c4b"},
+    "k_bh_walk": {"bytes": 1019.25e9,
+                  "srcs": [("paper_1110_4372_amd/csrc/bh.hip",
+                            "d49593623d9edd3baf90f2d39e5a0d239e2beac3")]},
+    "k_kd_walk_nn": {"bytes": 243.76e9, "srcs": [_GRID, _REFINE]},
+    "k_kd_walk_fof": {"bytes": 541.46e9, "srcs": [_GRID, _REFINE]},
+    "k_nn": {"bytes": 8.55e9, "srcs": [_REFINE]},
+    "k_potential_f32": {"bytes": 45.63e9,
+                        "srcs": [("paper_1110_4372_amd/csrc/unbind.hip",
+                                  "3a13952c28ac85b7e9fa4a58347e7c9c62140c4b")]},
 }
 
 
@@ -51,11 +54,12 @@ def measured_traffic(kernel, workload):
     rec = MEASURED_TRAFFIC.get(kernel)
     if rec is None or workload != TRAFFIC_WORKLOAD:
         return None
-    path = os.path.join(ROOT, rec["src"])
-    if not os.path.exists(path):
-        return None
-    if hashlib.sha1(open(path, "rb").read()).hexdigest() != rec["sha1"]:
-        return None
+    for src, sha in rec["srcs"]:
+        path = os.path.join(ROOT, src)
+        if not os.path.exists(path):
+            return None
+        if hashlib.sha1(open(path, "rb").read()).hexdigest() != sha:
+            return None
     return rec["bytes"]
 
 
