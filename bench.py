@@ -34,14 +34,14 @@ FP32_PEAK_TFLOPS = 157.3
 # own, and for the 6D walks the refinement that drives them) are the ones that
 # were measured.
 TRAFFIC_WORKLOAD = "c5"
-_GRID = ("paper_1110_4372_amd/csrc/grid6d.hip", "ccb54f0436f90b34eb21d5786f445995354a879e")
+_GRID = ("paper_1110_4372_amd/csrc/grid6d.hip", "728bf98344d9e996b72ed78dec7ba90b521a0add")
 _REFINE = ("paper_1110_4372_amd/csrc/refine6d.hip", "c8c946562558e02e125eed24496a815dbf149760")
 MEASURED_TRAFFIC = {
-    "k_bh_walk": {"bytes": 1019.25e9,
+    "k_bh_walk": {"bytes": 1018.89e9,
                   "srcs": [("paper_1110_4372_amd/csrc/bh.hip",
                             "d49593623d9edd3baf90f2d39e5a0d239e2beac3")]},
-    "k_kd_walk_nn": {"bytes": 243.76e9, "srcs": [_GRID, _REFINE]},
-    "k_kd_walk_fof": {"bytes": 541.46e9, "srcs": [_GRID, _REFINE]},
+    "k_kd_walk_nn": {"bytes": 243.67e9, "srcs": [_GRID, _REFINE]},
+    "k_kd_walk_fof": {"bytes": 642.34e9, "srcs": [_GRID, _REFINE]},
     "k_nn": {"bytes": 8.55e9, "srcs": [_REFINE]},
     "k_potential_f32": {"bytes": 45.63e9,
                         "srcs": [("paper_1110_4372_amd/csrc/unbind.hip",
