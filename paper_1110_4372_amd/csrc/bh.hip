@@ -367,8 +367,14 @@ __global__ void __launch_bounds__(TB)
               const uint32_t* __restrict__ pidx, const BhRec* __restrict__ R,
               const uint32_t* __restrict__ troot, double eps2, I128* __restrict__ pacc,
               unsigned long long* work) {
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (TB / 64) +
-                                                       (threadIdx.x >> 6));
+  // blocks go to the eight XCDs in turn (block b to XCD b mod 8): the blocks
+  // of one XCD take a contiguous eighth of the waves, so the waves sharing an
+  // L2 walk neighbouring targets and read the same cells (a bijection; the
+  // last gridDim mod 8 blocks keep their own index)
+  const uint32_t g8 = gridDim.x >> 3;
+  const uint32_t blk = blockIdx.x < 8u * g8 ? (blockIdx.x & 7u) * g8 + (blockIdx.x >> 3)
+                                            : blockIdx.x;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(blk * (TB / 64) + (threadIdx.x >> 6));
   if (wave >= nwave) return;  // wave-uniform
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t b = __builtin_amdgcn_readfirstlane(seg_find(woff, B, wave));
