@@ -37,11 +37,11 @@ TRAFFIC_WORKLOAD = "c5"
 _GRID = ("paper_1110_4372_amd/csrc/grid6d.hip", "728bf98344d9e996b72ed78dec7ba90b521a0add")
 _REFINE = ("paper_1110_4372_amd/csrc/refine6d.hip", "c8c946562558e02e125eed24496a815dbf149760")
 MEASURED_TRAFFIC = {
-    "k_bh_walk": {"bytes": 1018.89e9,
+    "k_bh_walk": {"bytes": 75.13e9,
                   "srcs": [("paper_1110_4372_amd/csrc/bh.hip",
-                            "d49593623d9edd3baf90f2d39e5a0d239e2beac3")]},
-    "k_kd_walk_nn": {"bytes": 243.67e9, "srcs": [_GRID, _REFINE]},
-    "k_kd_walk_fof": {"bytes": 642.34e9, "srcs": [_GRID, _REFINE]},
+                            "e96751a07b9187a8bc6c9148c4179cbd1b725b9a")]},
+    "k_kd_walk_nn": {"bytes": 243.56e9, "srcs": [_GRID, _REFINE]},
+    "k_kd_walk_fof": {"bytes": 641.79e9, "srcs": [_GRID, _REFINE]},
     "k_nn": {"bytes": 8.55e9, "srcs": [_REFINE]},
     "k_potential_f32": {"bytes": 45.63e9,
                         "srcs": [("paper_1110_4372_amd/csrc/unbind.hip",
