@@ -151,6 +151,15 @@ struct Ctx {
   } while (0)
 
 // ------------------------------------------------------------ launch -----
+// Blocks are dispatched to the eight XCDs in turn (block b to XCD b mod 8).
+// This index gives the blocks of one XCD a contiguous eighth of the grid, so
+// neighbouring items, which read the same data, share an L2.  A bijection on
+// [0, gridDim.x); the last gridDim.x mod 8 blocks keep their own index.
+__device__ __forceinline__ uint32_t xcd_block() {
+  const uint32_t g8 = gridDim.x >> 3;
+  return blockIdx.x < 8u * g8 ? (blockIdx.x & 7u) * g8 + (blockIdx.x >> 3) : blockIdx.x;
+}
+
 inline unsigned blocks_for(int64_t n, int threads) {
   int64_t b = (n + threads - 1) / threads;
   return (unsigned)(b < 1 ? 1 : b);

@@ -138,7 +138,8 @@ template <class T>
 __global__ void k_link(const T* xs, const T* ys, const T* zs, const uint32_t* cell_start,
                        const unsigned long long* cell_key, const uint32_t* row_start,
                        int64_t ncell, int64_t n, Grid g, int phase, uint32_t* par) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // neighbouring cells, whose stencils read the same rows, on one XCD
+  int64_t c = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   const int64_t nc = g.nc;
   const unsigned long long kc = cell_key[c];
